@@ -1,0 +1,273 @@
+"""FP64 CPU oracle for the SBoTFlow LBM-IBM time step (arXiv 2402.04606).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the GPU library (``paper_2402_04606_amd``); both sides consume the
+same seeded inputs from ``workloads``.
+
+This module is argument marshalling around ``liborc.so`` (built from
+``oracle.c`` by ``oracle/build.py``); all arithmetic lives in the C file.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liborc.so")
+
+ORC_BODY_NONE, ORC_BODY_FIXED, ORC_BODY_FLAP = -1, 0, 1
+
+
+class _Case(C.Structure):
+    _fields_ = [
+        ("nx0", C.c_int32), ("ny0", C.c_int32), ("block_n", C.c_int32), ("n_levels", C.c_int32),
+        ("n_boxes", C.c_int32), ("boxes", C.POINTER(C.c_int32)),
+        ("tau0", C.c_double), ("rho0", C.c_double),
+        ("bc", C.c_int32 * 4), ("bc_u", C.c_double * 8), ("fext", C.c_double * 2),
+        ("cf_mode", C.c_int32), ("mdf_iters", C.c_int32), ("body_kind", C.c_int32),
+        ("n_markers", C.c_int32),
+        ("xb", C.POINTER(C.c_double)), ("yb", C.POINTER(C.c_double)), ("ds", C.POINTER(C.c_double)),
+        ("bp", C.c_double * 16),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = C.CDLL(LIB_PATH)
+        d = C.POINTER(C.c_double)
+        _lib.orc_create.argtypes = [C.POINTER(_Case), C.POINTER(C.c_void_p)]
+        _lib.orc_destroy.argtypes = [C.c_void_p]
+        _lib.orc_destroy.restype = None
+        _lib.orc_level_size.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        _lib.orc_level_kinds.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_uint8)]
+        _lib.orc_init_fields.argtypes = [C.c_void_p, C.c_int, d, d, d]
+        _lib.orc_step.argtypes = [C.c_void_p, C.c_int32]
+        _lib.orc_read_fields.argtypes = [C.c_void_p, C.c_int, d, d, d]
+        _lib.orc_read_populations.argtypes = [C.c_void_p, C.c_int, d]
+        _lib.orc_marker_forces.argtypes = [C.c_void_p, d, d]
+        _lib.orc_force_history.argtypes = [C.c_void_p, C.c_int32, d, d, C.POINTER(C.c_int32)]
+        _lib.orc_diagnostics.argtypes = [C.c_void_p, d]
+        _lib.orc_substeps.argtypes = [C.c_void_p]
+        _lib.orc_substeps.restype = C.c_int64
+        _lib.orc_velocity_set.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32), d]
+        _lib.orc_velocity_set.restype = None
+        _lib.orc_feq.argtypes = [C.c_double] * 3 + [d]
+        _lib.orc_feq.restype = None
+        _lib.orc_guo.argtypes = [C.c_double] * 5 + [d]
+        _lib.orc_guo.restype = None
+        _lib.orc_collide_cell.argtypes = [C.c_double, d, C.c_double, C.c_double, d]
+        _lib.orc_collide_cell.restype = None
+        _lib.orc_phi.argtypes = [C.c_double]
+        _lib.orc_phi.restype = C.c_double
+        _lib.orc_body_positions.argtypes = [C.POINTER(_Case), C.c_double, d, d]
+        _lib.orc_mdf.argtypes = [C.c_int32, C.c_int32, d, d, d, d, d, C.c_int32, d, d, d, d, d,
+                                 C.c_int32, d, d]
+        _lib.orc_interpolate.argtypes = [C.c_int32, C.c_int32, d, d, C.c_int32, d, d, d, d]
+        _lib.orc_spread.argtypes = [C.c_int32, C.c_int32, C.c_int32, d, d, d, d, d, d, d]
+        _lib.orc_num_threads.argtypes = []
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_case(wl):
+    """Marshal a ``workloads.Workload`` into the oracle's C struct.
+
+    Returns (struct, keepalive) -- keepalive holds the numpy buffers."""
+    c = _Case()
+    c.nx0, c.ny0, c.block_n, c.n_levels = wl.nx0, wl.ny0, wl.block_n, wl.n_levels
+    boxes = np.ascontiguousarray(np.array(wl.boxes, dtype=np.int32).reshape(-1, 5))
+    c.n_boxes = boxes.shape[0]
+    c.boxes = boxes.ctypes.data_as(C.POINTER(C.c_int32))
+    c.tau0, c.rho0 = wl.tau0, wl.rho0
+    for e in range(4):
+        c.bc[e] = wl.bc[e]
+        c.bc_u[2 * e], c.bc_u[2 * e + 1] = wl.bc_u[e]
+    c.fext[0], c.fext[1] = wl.fext
+    c.cf_mode, c.mdf_iters = wl.cf_mode, wl.mdf_iters
+    keep = [boxes]
+    if wl.body is None:
+        c.body_kind, c.n_markers = ORC_BODY_NONE, 0
+    else:
+        b = wl.body
+        xb, yb, ds = _f64(b.xb), _f64(b.yb), _f64(b.ds)
+        keep += [xb, yb, ds]
+        c.body_kind, c.n_markers = b.kind, len(xb)
+        c.xb, c.yb, c.ds = _dp(xb), _dp(yb), _dp(ds)
+        for i, v in enumerate(b.params):
+            c.bp[i] = v
+    return c, keep
+
+
+class OracleSim:
+    """One case on the oracle.  Fields are dense per-level arrays [ny, nx]."""
+
+    def __init__(self, wl):
+        self.wl = wl
+        self._case, self._keep = make_case(wl)
+        h = C.c_void_p()
+        rc = lib().orc_create(C.byref(self._case), C.byref(h))
+        if rc != 0:
+            raise RuntimeError(f"orc_create failed: {rc}")
+        self._h = h
+        self.n_levels = wl.n_levels
+        if wl.init is not None:
+            for l in range(wl.n_levels):
+                nx, ny = self.level_size(l)
+                rho, ux, uy = wl.init(l, nx, ny)
+                self.init_fields(l, rho, ux, uy)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc_destroy(h)
+            self._h = None
+
+    def level_size(self, l):
+        nx, ny = C.c_int32(), C.c_int32()
+        lib().orc_level_size(self._h, l, C.byref(nx), C.byref(ny))
+        return nx.value, ny.value
+
+    def kinds(self, l):
+        nx, ny = self.level_size(l)
+        k = np.zeros((ny, nx), dtype=np.uint8)
+        lib().orc_level_kinds(self._h, l, k.ctypes.data_as(C.POINTER(C.c_uint8)))
+        return k
+
+    def init_fields(self, l, rho, ux, uy):
+        nx, ny = self.level_size(l)
+        rho = _f64(np.broadcast_to(rho, (ny, nx)))
+        ux = _f64(np.broadcast_to(ux, (ny, nx)))
+        uy = _f64(np.broadcast_to(uy, (ny, nx)))
+        rc = lib().orc_init_fields(self._h, l, _dp(rho), _dp(ux), _dp(uy))
+        if rc:
+            raise RuntimeError(rc)
+
+    def step(self, n=1):
+        rc = lib().orc_step(self._h, int(n))
+        if rc:
+            raise RuntimeError(f"orc_step failed: {rc}")
+
+    def fields(self, l):
+        nx, ny = self.level_size(l)
+        r, u, v = (np.empty((ny, nx)) for _ in range(3))
+        lib().orc_read_fields(self._h, l, _dp(r), _dp(u), _dp(v))
+        return r, u, v
+
+    def populations(self, l):
+        nx, ny = self.level_size(l)
+        f = np.empty((ny, nx, 9))
+        lib().orc_read_populations(self._h, l, _dp(f))
+        return f
+
+    def marker_forces(self):
+        n = 0 if self.wl.body is None else len(self.wl.body.xb)
+        fx, fy = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        lib().orc_marker_forces(self._h, _dp(fx), _dp(fy))
+        return fx[:n], fy[:n]
+
+    def force_history(self, cap=1 << 20):
+        fx, fy = np.empty(cap), np.empty(cap)
+        n = C.c_int32()
+        lib().orc_force_history(self._h, cap, _dp(fx), _dp(fy), C.byref(n))
+        return fx[: n.value].copy(), fy[: n.value].copy()
+
+    def diagnostics(self):
+        out = np.zeros(3)
+        lib().orc_diagnostics(self._h, _dp(out))
+        return out
+
+    def substeps(self):
+        return int(lib().orc_substeps(self._h))
+
+
+# ---- building blocks ------------------------------------------------------
+
+def velocity_set():
+    cx, cy = (C.c_int32 * 9)(), (C.c_int32 * 9)()
+    w = np.zeros(9)
+    lib().orc_velocity_set(cx, cy, _dp(w))
+    return np.array(cx[:]), np.array(cy[:]), w
+
+
+def feq(rho, ux, uy):
+    out = np.zeros(9)
+    lib().orc_feq(rho, ux, uy, _dp(out))
+    return out
+
+
+def guo(tau, ux, uy, Fx, Fy):
+    out = np.zeros(9)
+    lib().orc_guo(tau, ux, uy, Fx, Fy, _dp(out))
+    return out
+
+
+def collide_cell(tau, f, Fx=0.0, Fy=0.0):
+    f = _f64(f)
+    out = np.zeros(9)
+    lib().orc_collide_cell(tau, _dp(f), Fx, Fy, _dp(out))
+    return out
+
+
+def phi(r):
+    return lib().orc_phi(float(r))
+
+
+def body_positions(wl, k):
+    c, keep = make_case(wl)
+    n = len(wl.body.xb)
+    X, Y = np.zeros(n), np.zeros(n)
+    rc = lib().orc_body_positions(C.byref(c), float(k), _dp(X), _dp(Y))
+    if rc:
+        raise RuntimeError(rc)
+    return X, Y
+
+
+def mdf(rho, ux, uy, X, Y, udx, udy, ds, iters):
+    """Run the MDF loop on a dense periodic grid; returns (ux, uy, Fx, Fy, ftx, fty)."""
+    ny, nx = rho.shape
+    rho = _f64(rho)
+    ux, uy = _f64(ux).copy(), _f64(uy).copy()
+    Fx, Fy = np.zeros((ny, nx)), np.zeros((ny, nx))
+    X, Y, udx, udy, ds = (_f64(a) for a in (X, Y, udx, udy, ds))
+    n = len(X)
+    ftx, fty = np.zeros(n), np.zeros(n)
+    lib().orc_mdf(nx, ny, _dp(rho), _dp(ux), _dp(uy), _dp(Fx), _dp(Fy), n, _dp(X), _dp(Y),
+                  _dp(udx), _dp(udy), _dp(ds), iters, _dp(ftx), _dp(fty))
+    return ux, uy, Fx, Fy, ftx, fty
+
+
+def interpolate(ux, uy, X, Y):
+    ny, nx = ux.shape
+    ux, uy, X, Y = (_f64(a) for a in (ux, uy, X, Y))
+    U, V = np.zeros(len(X)), np.zeros(len(X))
+    lib().orc_interpolate(nx, ny, _dp(ux), _dp(uy), len(X), _dp(X), _dp(Y), _dp(U), _dp(V))
+    return U, V
+
+
+def spread(shape, X, Y, Fjx, Fjy, ds):
+    ny, nx = shape
+    X, Y, Fjx, Fjy, ds = (_f64(a) for a in (X, Y, Fjx, Fjy, ds))
+    Fx, Fy = np.zeros((ny, nx)), np.zeros((ny, nx))
+    lib().orc_spread(nx, ny, len(X), _dp(X), _dp(Y), _dp(Fjx), _dp(Fjy), _dp(ds), _dp(Fx), _dp(Fy))
+    return Fx, Fy
+
+
+def num_threads():
+    return int(lib().orc_num_threads())

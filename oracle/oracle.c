@@ -1,0 +1,791 @@
+/*
+ * oracle.c -- plain FP64 CPU oracle for the SBoTFlow time step (arXiv 2402.04606).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test-suite, the package smoke check
+ * and the benchmark's CPU-baseline leg, never by the GPU library.  It is kept
+ * deliberately literal: dense per-level arrays, one loop per step of the
+ * paper's Algorithm 1, no blocking, no fusion.  OpenMP only splits the
+ * per-cell loops (each cell is written by exactly one thread), so results do
+ * not depend on the thread count; every reduction runs sequentially in index
+ * order.
+ *
+ * What each function follows in the paper:
+ *   velocity set ............ Sec. 2.1, Eq. (1)
+ *   collision + Guo forcing . Sec. 2.1, Eqs. (2)-(8)
+ *   streaming ............... Sec. 2.1, Eq. (10)
+ *   domain boundaries ....... Sec. 2.1 (kinds named only; formulas are the
+ *                             textbook readings listed in the design notes)
+ *   IBM, MDF loop ........... Sec. 2.2, Eqs. (11)-(16)
+ *   coarse/fine interface ... Sec. 2.4 (steps (1)-(6)), Algorithm 1
+ *   level recursion ......... Sec. 2.5, Algorithm 1
+ *
+ * Readings where the paper is silent (same list as the design notes):
+ *   - tau per level: tau_l - 1/2 = 2^l (tau_0 - 1/2) (same viscosity, dt ~ dx).
+ *   - body force per level: F_l = F_0 / 2^l.
+ *   - MDF: N_F iterations; rho_j interpolated with the delta kernel; the first
+ *     interpolation uses the uncorrected velocity, later ones the corrected one.
+ *   - halo ("ghost") cells are never collided; they are streamed in both fine
+ *     substeps; coarse-to-fine fills them only before the first substep; the
+ *     PreStreamingStep makes their post-stream values the sources of the
+ *     second stream.
+ *   - fine-to-coarse replaces f(X,i) exactly when X - c_i is covered by the
+ *     finer level, with the mean of the 4 children of X.
+ *   - RESCALE interface mode multiplies the non-equilibrium part by
+ *     (tau_f - 1)/(2 (tau_c - 1)) coarse->fine (post-collision) and
+ *     2 tau_c / tau_f fine->coarse (pre-collision).
+ *   - domain edges: half-way bounce-back with the moving-wall term (wall
+ *     density rho0), equilibrium inflow at rho0, zero-gradient outflow,
+ *     specular symmetry, periodic; corner diagonals follow the rule stated
+ *     at boundary().
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define MAXL 8
+#define Q 9
+
+/* Eq. (1): D2Q9 directions, and the weights of Eq. (7). */
+static const int CX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+static const int CY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+static const double WT[Q] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                             1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+
+enum { K_NONE = 0, K_OWN = 1, K_GHOST = 2, K_HIDDEN = 3 };
+
+typedef struct {
+    int nx, ny;
+    double tau, fx, fy;
+    uint8_t *kind;
+    double *f, *fs;           /* pre-collision / post-collision populations */
+    double *rho, *ux, *uy;    /* moments used by the last collision          */
+    double *Fx, *Fy;          /* IBM force density (finest level only)       */
+} olev;
+
+struct orc_sim {
+    orc_case c;
+    int32_t *boxes;
+    double *xb, *yb, *ds;
+    int m, per_x, per_y;
+    olev L[MAXL];
+    int64_t k;                /* finest-level substeps done */
+    double *hist;             /* 2 doubles per finest substep */
+    int64_t nhist, cap;
+    double *ftx, *fty;        /* per-marker total force of the last substep */
+    int err;
+};
+
+/* ------------------------------------------------------------------------ */
+/* Building blocks                                                           */
+/* ------------------------------------------------------------------------ */
+
+void orc_velocity_set(int32_t cx[9], int32_t cy[9], double w[9]) {
+    for (int i = 0; i < Q; ++i) { cx[i] = CX[i]; cy[i] = CY[i]; w[i] = WT[i]; }
+}
+
+/* Eq. (7), c_s^2 = 1/3. */
+void orc_feq(double rho, double ux, double uy, double out[9]) {
+    double usq = ux * ux + uy * uy;
+    for (int i = 0; i < Q; ++i) {
+        double cu = CX[i] * ux + CY[i] * uy;
+        out[i] = WT[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+    }
+}
+
+/* Eq. (3), Guo et al. forcing term. */
+void orc_guo(double tau, double ux, double uy, double Fx, double Fy, double out[9]) {
+    double uF = ux * Fx + uy * Fy;
+    double pre = 1.0 - 0.5 / tau;
+    for (int i = 0; i < Q; ++i) {
+        double cu = CX[i] * ux + CY[i] * uy;
+        double cF = CX[i] * Fx + CY[i] * Fy;
+        out[i] = WT[i] * pre * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
+    }
+}
+
+/* Eqs. (6), (8): moments with the half-force velocity, then BGK + forcing.
+ * Returns the moments through the last three slots of `mom` when non-NULL. */
+static void collide_cell(double tau, const double *f, double Fx, double Fy, double *out,
+                         double *mom) {
+    double rho = 0.0, jx = 0.0, jy = 0.0;
+    for (int i = 0; i < Q; ++i) { rho += f[i]; jx += CX[i] * f[i]; jy += CY[i] * f[i]; }
+    double ux = (jx + 0.5 * Fx) / rho;
+    double uy = (jy + 0.5 * Fy) / rho;
+    double feq[Q], fi[Q];
+    orc_feq(rho, ux, uy, feq);
+    orc_guo(tau, ux, uy, Fx, Fy, fi);
+    for (int i = 0; i < Q; ++i) out[i] = f[i] - (f[i] - feq[i]) / tau + fi[i];
+    if (mom) { mom[0] = rho; mom[1] = ux; mom[2] = uy; }
+}
+
+void orc_collide_cell(double tau, const double f[9], double Fx, double Fy, double out[9]) {
+    collide_cell(tau, f, Fx, Fy, out, NULL);
+}
+
+/* Eq. (14): Peskin's 4-point kernel (dx = 1). */
+double orc_phi(double r) {
+    double a = fabs(r);
+    if (a <= 1.0) return 0.125 * (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a));
+    if (a <= 2.0) return 0.125 * (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a));
+    return 0.0;
+}
+
+/* Kinematics.  FIXED: X = (x0 + xb, y0 + yb).  FLAP (Sec. 3.6 law, with the
+ * pitch amplitude and stroke angle as parameters):
+ *   t* = t U_ref / c,  theta = 2 pi t* / T
+ *   alpha = alpha0 - A_pitch sin(theta + phi)
+ *   (xc, yc) = (x0, y0) + (A0/2) cos(theta) (cos beta, sin beta)
+ *   X = xc + xb cos(alpha) + yb sin(alpha),  Y = yc - xb sin(alpha) + yb cos(alpha)
+ * bp = {x0, y0, alpha0, A_pitch, A0, beta, T, phi, U_ref, c}. */
+int orc_body_positions(const orc_case *c, double k, double *X, double *Y) {
+    const double *p = c->bp;
+    if (c->body_kind == ORC_BODY_FIXED) {
+        for (int j = 0; j < c->n_markers; ++j) { X[j] = p[0] + c->xb[j]; Y[j] = p[1] + c->yb[j]; }
+        return ORC_OK;
+    }
+    if (c->body_kind != ORC_BODY_FLAP) return ORC_ERR_ARG;
+    double tstar = k * p[8] / p[9];
+    double theta = 2.0 * M_PI * tstar / p[6];
+    double alpha = p[2] - p[3] * sin(theta + p[7]);
+    double h = 0.5 * p[4] * cos(theta);
+    double xc = p[0] + h * cos(p[5]);
+    double yc = p[1] + h * sin(p[5]);
+    double ca = cos(alpha), sa = sin(alpha);
+    for (int j = 0; j < c->n_markers; ++j) {
+        X[j] = xc + c->xb[j] * ca + c->yb[j] * sa;
+        Y[j] = yc - c->xb[j] * sa + c->yb[j] * ca;
+    }
+    return ORC_OK;
+}
+
+static inline int wrapi(int a, int n) { a %= n; return a < 0 ? a + n : a; }
+
+/* First of the 4 cells (centres at i + 1/2) within distance 2 of X. */
+static inline int tap0(double X) { return (int)floor(X - 1.5); }
+
+/* Eq. (12) on a dense periodic grid: sum over taps, y outer, x inner. */
+int orc_interpolate(int32_t nx, int32_t ny, const double *ux, const double *uy, int32_t n,
+                    const double *X, const double *Y, double *U, double *V) {
+    for (int j = 0; j < n; ++j) {
+        int i0 = tap0(X[j]), j0 = tap0(Y[j]);
+        double su = 0.0, sv = 0.0;
+        for (int b = 0; b < 4; ++b) {
+            double py = orc_phi(j0 + b + 0.5 - Y[j]);
+            int yy = wrapi(j0 + b, ny);
+            for (int a = 0; a < 4; ++a) {
+                double w = orc_phi(i0 + a + 0.5 - X[j]) * py;
+                int xx = wrapi(i0 + a, nx);
+                su += ux[(size_t)yy * nx + xx] * w;
+                sv += uy[(size_t)yy * nx + xx] * w;
+            }
+        }
+        U[j] = su; V[j] = sv;
+    }
+    return ORC_OK;
+}
+
+/* Eq. (15) on a dense periodic grid, markers in index order. */
+int orc_spread(int32_t nx, int32_t ny, int32_t n, const double *X, const double *Y,
+               const double *Fjx, const double *Fjy, const double *ds, double *Fx, double *Fy) {
+    for (int j = 0; j < n; ++j) {
+        int i0 = tap0(X[j]), j0 = tap0(Y[j]);
+        for (int b = 0; b < 4; ++b) {
+            double py = orc_phi(j0 + b + 0.5 - Y[j]);
+            int yy = wrapi(j0 + b, ny);
+            for (int a = 0; a < 4; ++a) {
+                double w = orc_phi(i0 + a + 0.5 - X[j]) * py;
+                int xx = wrapi(i0 + a, nx);
+                Fx[(size_t)yy * nx + xx] += Fjx[j] * w * ds[j];
+                Fy[(size_t)yy * nx + xx] += Fjy[j] * w * ds[j];
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* The multi-direct-forcing loop (Sec. 2.2, Eqs. (11)-(15), iterated N_F
+ * times): interpolate velocity and density at the markers, boundary force
+ * Eq. (11) with dt = 1, spread, correct the cell velocity by dF/(2 rho)
+ * (consistent with the half-force velocity of Eq. (8)) and accumulate. */
+int orc_mdf(int32_t nx, int32_t ny, const double *rho, double *ux, double *uy, double *Fx,
+            double *Fy, int32_t n, const double *X, const double *Y, const double *udx,
+            const double *udy, const double *ds, int32_t iters, double *ftx, double *fty) {
+    size_t ncell = (size_t)nx * ny;
+    double *U = malloc(sizeof(double) * n * 4);
+    double *dFx = calloc(ncell, sizeof(double)), *dFy = calloc(ncell, sizeof(double));
+    if (!U || !dFx || !dFy) { free(U); free(dFx); free(dFy); return ORC_ERR_ARG; }
+    double *V = U + n, *R = U + 2 * n, *Rv = U + 3 * n;
+    double *zero = calloc(ncell, sizeof(double));
+    for (int j = 0; j < n; ++j) { ftx[j] = 0.0; fty[j] = 0.0; }
+    for (int it = 0; it < iters; ++it) {
+        orc_interpolate(nx, ny, ux, uy, n, X, Y, U, V);
+        orc_interpolate(nx, ny, rho, zero, n, X, Y, R, Rv);
+        double *gx = malloc(sizeof(double) * n * 2), *gy = gx + n;
+        for (int j = 0; j < n; ++j) {
+            gx[j] = 2.0 * R[j] * (udx[j] - U[j]);
+            gy[j] = 2.0 * R[j] * (udy[j] - V[j]);
+            ftx[j] += gx[j];
+            fty[j] += gy[j];
+        }
+        memset(dFx, 0, sizeof(double) * ncell);
+        memset(dFy, 0, sizeof(double) * ncell);
+        orc_spread(nx, ny, n, X, Y, gx, gy, ds, dFx, dFy);
+        for (size_t c = 0; c < ncell; ++c) {
+            if (dFx[c] == 0.0 && dFy[c] == 0.0) continue;
+            Fx[c] += dFx[c];
+            Fy[c] += dFy[c];
+            ux[c] += dFx[c] / (2.0 * rho[c]);
+            uy[c] += dFy[c] / (2.0 * rho[c]);
+        }
+        free(gx);
+    }
+    free(U); free(dFx); free(dFy); free(zero);
+    return ORC_OK;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Topology                                                                  */
+/* ------------------------------------------------------------------------ */
+
+static int in_region(const orc_sim *s, int l, int x, int y) {
+    if (l == 0) return 1;
+    int B = s->c.block_n;
+    for (int b = 0; b < s->c.n_boxes; ++b) {
+        const int32_t *q = s->boxes + 5 * b;
+        if (q[0] != l) continue;
+        if (x >= q[1] * B && x < q[3] * B && y >= q[2] * B && y < q[4] * B) return 1;
+    }
+    return 0;
+}
+
+static inline size_t cid(const olev *L, int x, int y) { return (size_t)y * L->nx + x; }
+
+/* Wrap (x, y) on level L if the axis is periodic.  Returns 0 if outside. */
+static int wrap_level(const orc_sim *s, const olev *L, int *x, int *y) {
+    if (*x < 0 || *x >= L->nx) { if (!s->per_x) return 0; *x = wrapi(*x, L->nx); }
+    if (*y < 0 || *y >= L->ny) { if (!s->per_y) return 0; *y = wrapi(*y, L->ny); }
+    return 1;
+}
+
+static int build_topology(orc_sim *s) {
+    int m = s->m;
+    for (int l = 0; l < m; ++l) {
+        olev *L = &s->L[l];
+        for (int y = 0; y < L->ny; ++y)
+            for (int x = 0; x < L->nx; ++x) {
+                uint8_t kd = K_NONE;
+                if (in_region(s, l, x, y)) {
+                    kd = K_OWN;
+                    if (l + 1 < m && in_region(s, l + 1, 2 * x, 2 * y)) kd = K_HIDDEN;
+                }
+                L->kind[cid(L, x, y)] = kd;
+            }
+        /* nesting: every cell of region_l has its parent in region_{l-1} */
+        if (l > 0)
+            for (int y = 0; y < L->ny; ++y)
+                for (int x = 0; x < L->nx; ++x)
+                    if (L->kind[cid(L, x, y)] != K_NONE && !in_region(s, l - 1, x / 2, y / 2))
+                        return ORC_ERR_TOPOLOGY;
+    }
+    /* ghost (halo) cells: outside region_l, Chebyshev distance <= 2 from an
+     * owned cell of level l, parent owned on level l-1 (Sec. 2.4: two halo
+     * layers over faces, edges and vertices). */
+    for (int l = 1; l < m; ++l) {
+        olev *L = &s->L[l], *P = &s->L[l - 1];
+        uint8_t *mark = calloc((size_t)L->nx * L->ny, 1);
+        for (int y = 0; y < L->ny; ++y)
+            for (int x = 0; x < L->nx; ++x) {
+                if (L->kind[cid(L, x, y)] != K_OWN) continue;
+                for (int dy = -2; dy <= 2; ++dy)
+                    for (int dx = -2; dx <= 2; ++dx) {
+                        int xx = x + dx, yy = y + dy;
+                        if (!wrap_level(s, L, &xx, &yy)) { free(mark); return ORC_ERR_TOPOLOGY; }
+                        if (L->kind[cid(L, xx, yy)] == K_NONE) mark[cid(L, xx, yy)] = 1;
+                    }
+            }
+        for (int y = 0; y < L->ny; ++y)
+            for (int x = 0; x < L->nx; ++x) {
+                if (!mark[cid(L, x, y)]) continue;
+                if (P->kind[cid(P, x / 2, y / 2)] != K_OWN) { free(mark); return ORC_ERR_TOPOLOGY; }
+                L->kind[cid(L, x, y)] = K_GHOST;
+            }
+        free(mark);
+    }
+    /* refined levels may not reach a non-periodic domain edge */
+    for (int l = 1; l < m; ++l) {
+        olev *L = &s->L[l];
+        for (int y = 0; y < L->ny; ++y)
+            for (int x = 0; x < L->nx; ++x) {
+                if (L->kind[cid(L, x, y)] == K_NONE) continue;
+                if ((!s->per_x && (x == 0 || x == L->nx - 1)) ||
+                    (!s->per_y && (y == 0 || y == L->ny - 1)))
+                    return ORC_ERR_TOPOLOGY;
+            }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Life cycle                                                                */
+/* ------------------------------------------------------------------------ */
+
+void orc_destroy(orc_sim *s) {
+    if (!s) return;
+    for (int l = 0; l < MAXL; ++l) {
+        olev *L = &s->L[l];
+        free(L->kind); free(L->f); free(L->fs); free(L->rho); free(L->ux); free(L->uy);
+        free(L->Fx); free(L->Fy);
+    }
+    free(s->boxes); free(s->xb); free(s->yb); free(s->ds); free(s->hist);
+    free(s->ftx); free(s->fty);
+    free(s);
+}
+
+int orc_create(const orc_case *c, orc_sim **out) {
+    *out = NULL;
+    if (c->n_levels < 1 || c->n_levels > MAXL || c->nx0 <= 0 || c->ny0 <= 0 || c->block_n <= 0 ||
+        c->tau0 <= 0.5)
+        return ORC_ERR_ARG;
+    for (int e = 0; e < 4; ++e)
+        if (c->bc[e] < 0 || c->bc[e] > ORC_BC_SYMMETRY) return ORC_ERR_ARG;
+    if ((c->bc[ORC_W] == ORC_BC_PERIODIC) != (c->bc[ORC_E] == ORC_BC_PERIODIC) ||
+        (c->bc[ORC_S] == ORC_BC_PERIODIC) != (c->bc[ORC_N] == ORC_BC_PERIODIC))
+        return ORC_ERR_ARG;
+    orc_sim *s = calloc(1, sizeof(orc_sim));
+    s->c = *c;
+    s->m = c->n_levels;
+    s->per_x = c->bc[ORC_W] == ORC_BC_PERIODIC;
+    s->per_y = c->bc[ORC_S] == ORC_BC_PERIODIC;
+    s->boxes = malloc(sizeof(int32_t) * 5 * (c->n_boxes > 0 ? c->n_boxes : 1));
+    if (c->n_boxes > 0) memcpy(s->boxes, c->boxes, sizeof(int32_t) * 5 * c->n_boxes);
+    s->c.boxes = s->boxes;
+    int nm = c->body_kind == ORC_BODY_NONE ? 0 : c->n_markers;
+    s->c.n_markers = nm;
+    s->xb = malloc(sizeof(double) * (nm + 1));
+    s->yb = malloc(sizeof(double) * (nm + 1));
+    s->ds = malloc(sizeof(double) * (nm + 1));
+    s->ftx = calloc(nm + 1, sizeof(double));
+    s->fty = calloc(nm + 1, sizeof(double));
+    if (nm) {
+        memcpy(s->xb, c->xb, sizeof(double) * nm);
+        memcpy(s->yb, c->yb, sizeof(double) * nm);
+        memcpy(s->ds, c->ds, sizeof(double) * nm);
+    }
+    s->c.xb = s->xb; s->c.yb = s->yb; s->c.ds = s->ds;
+    for (int l = 0; l < s->m; ++l) {
+        olev *L = &s->L[l];
+        L->nx = c->nx0 << l;
+        L->ny = c->ny0 << l;
+        L->tau = 0.5 + (double)(1 << l) * (c->tau0 - 0.5);
+        L->fx = c->fext[0] / (double)(1 << l);
+        L->fy = c->fext[1] / (double)(1 << l);
+        size_t n = (size_t)L->nx * L->ny;
+        L->kind = calloc(n, 1);
+        L->f = malloc(sizeof(double) * n * Q);
+        L->fs = malloc(sizeof(double) * n * Q);
+        L->rho = malloc(sizeof(double) * n);
+        L->ux = malloc(sizeof(double) * n);
+        L->uy = malloc(sizeof(double) * n);
+        if (!L->kind || !L->f || !L->fs || !L->rho || !L->ux || !L->uy) {
+            orc_destroy(s);
+            return ORC_ERR_ARG;
+        }
+        for (size_t q = 0; q < n * Q; ++q) { L->f[q] = NAN; L->fs[q] = NAN; }
+        for (size_t q = 0; q < n; ++q) { L->rho[q] = NAN; L->ux[q] = NAN; L->uy[q] = NAN; }
+    }
+    olev *Lf = &s->L[s->m - 1];
+    size_t nf = (size_t)Lf->nx * Lf->ny;
+    Lf->Fx = calloc(nf, sizeof(double));
+    Lf->Fy = calloc(nf, sizeof(double));
+    int rc = build_topology(s);
+    if (rc) { orc_destroy(s); return rc; }
+    if (c->cf_mode == ORC_CF_RESCALE)
+        for (int l = 0; l + 1 < s->m; ++l)
+            if (fabs(s->L[l].tau - 1.0) < 1e-6) { orc_destroy(s); return ORC_ERR_ARG; }
+    /* default state: rest at rho0 */
+    for (int l = 0; l < s->m; ++l) {
+        olev *L = &s->L[l];
+        double feq[Q];
+        orc_feq(c->rho0, 0.0, 0.0, feq);
+        for (size_t q = 0; q < (size_t)L->nx * L->ny; ++q)
+            if (L->kind[q] == K_OWN) memcpy(L->f + q * Q, feq, sizeof feq);
+    }
+    s->cap = 1024;
+    s->hist = malloc(sizeof(double) * 2 * s->cap);
+    *out = s;
+    return ORC_OK;
+}
+
+int orc_level_size(const orc_sim *s, int level, int32_t *nx, int32_t *ny) {
+    if (level < 0 || level >= s->m) return ORC_ERR_ARG;
+    *nx = s->L[level].nx; *ny = s->L[level].ny;
+    return ORC_OK;
+}
+
+int orc_level_kinds(const orc_sim *s, int level, uint8_t *kind) {
+    if (level < 0 || level >= s->m) return ORC_ERR_ARG;
+    memcpy(kind, s->L[level].kind, (size_t)s->L[level].nx * s->L[level].ny);
+    return ORC_OK;
+}
+
+int orc_init_fields(orc_sim *s, int level, const double *rho, const double *ux, const double *uy) {
+    if (level < 0 || level >= s->m) return ORC_ERR_ARG;
+    olev *L = &s->L[level];
+    for (size_t q = 0; q < (size_t)L->nx * L->ny; ++q)
+        if (L->kind[q] == K_OWN) orc_feq(rho[q], ux[q], uy[q], L->f + q * Q);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The steps of Algorithm 1                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* UpdateVelocity: the IBM / MDF step on the finest level (Sec. 2.2). */
+static void update_velocity(orc_sim *s, int l) {
+    if (l != s->m - 1 || s->c.body_kind == ORC_BODY_NONE || s->c.n_markers == 0) return;
+    olev *L = &s->L[l];
+    int n = s->c.n_markers;
+    size_t ncell = (size_t)L->nx * L->ny;
+    double *X = malloc(sizeof(double) * n * 6);
+    double *Y = X + n, *X1 = X + 2 * n, *Y1 = X + 3 * n, *udx = X + 4 * n, *udy = X + 5 * n;
+    orc_body_positions(&s->c, (double)s->k, X, Y);
+    orc_body_positions(&s->c, (double)(s->k + 1), X1, Y1);
+    for (int j = 0; j < n; ++j) { udx[j] = X1[j] - X[j]; udy[j] = Y1[j] - Y[j]; }
+
+    /* Moments of the stencil cells: rho and the uncorrected velocity. */
+    double *rho = calloc(ncell, sizeof(double));
+    double *ux = calloc(ncell, sizeof(double)), *uy = calloc(ncell, sizeof(double));
+    memset(L->Fx, 0, sizeof(double) * ncell);
+    memset(L->Fy, 0, sizeof(double) * ncell);
+    for (int j = 0; j < n; ++j) {
+        int i0 = tap0(X[j]), j0 = tap0(Y[j]);
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) {
+                int x = i0 + a, y = j0 + b;
+                /* the stencil and its streaming sources must be owned cells */
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int xx = x + dx, yy = y + dy;
+                        if (!wrap_level(s, L, &xx, &yy) || L->kind[cid(L, xx, yy)] != K_OWN)
+                            s->err = ORC_ERR_MARKER;
+                    }
+                if (!wrap_level(s, L, &x, &y)) continue;
+                size_t q = cid(L, x, y);
+                const double *f = L->f + q * Q;
+                double r = 0.0, jx = 0.0, jy = 0.0;
+                for (int i = 0; i < Q; ++i) { r += f[i]; jx += CX[i] * f[i]; jy += CY[i] * f[i]; }
+                rho[q] = r;
+                ux[q] = (jx + 0.5 * L->fx) / r;
+                uy[q] = (jy + 0.5 * L->fy) / r;
+            }
+    }
+    if (!s->err)
+        orc_mdf(L->nx, L->ny, rho, ux, uy, L->Fx, L->Fy, n, X, Y, udx, udy, s->ds,
+                s->c.mdf_iters, s->ftx, s->fty);
+    /* Eq. (16): total force on the body */
+    double fsx = 0.0, fsy = 0.0;
+    for (int j = 0; j < n; ++j) { fsx -= s->ftx[j] * s->ds[j]; fsy -= s->fty[j] * s->ds[j]; }
+    if (s->nhist == s->cap) {
+        s->cap *= 2;
+        s->hist = realloc(s->hist, sizeof(double) * 2 * s->cap);
+    }
+    s->hist[2 * s->nhist] = fsx;
+    s->hist[2 * s->nhist + 1] = fsy;
+    s->nhist++;
+    free(X); free(rho); free(ux); free(uy);
+}
+
+/* CollisionStep: owned cells only; F = body force + IBM force (finest). */
+static void collision(orc_sim *s, int l) {
+    olev *L = &s->L[l];
+    int finest = (l == s->m - 1);
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < L->ny; ++y)
+        for (int x = 0; x < L->nx; ++x) {
+            size_t q = cid(L, x, y);
+            if (L->kind[q] != K_OWN) continue;
+            double Fx = L->fx, Fy = L->fy;
+            if (finest) { Fx += L->Fx[q]; Fy += L->Fy[q]; }
+            double mom[3];
+            collide_cell(L->tau, L->f + q * Q, Fx, Fy, L->fs + q * Q, mom);
+            L->rho[q] = mom[0]; L->ux[q] = mom[1]; L->uy[q] = mom[2];
+        }
+}
+
+/* CoarseToFineCommunication (step (2) of Sec. 2.4): each halo cell of the
+ * fine level takes the post-collision populations of its coarse parent. */
+static void coarse_to_fine(orc_sim *s, int lc, int lf) {
+    olev *C = &s->L[lc], *F = &s->L[lf];
+    double scf = (F->tau - 1.0) / (2.0 * (C->tau - 1.0));
+    int rescale = s->c.cf_mode == ORC_CF_RESCALE;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < F->ny; ++y)
+        for (int x = 0; x < F->nx; ++x) {
+            size_t q = cid(F, x, y);
+            if (F->kind[q] != K_GHOST) continue;
+            size_t p = cid(C, x / 2, y / 2);
+            const double *src = C->fs + p * Q;
+            double *dst = F->fs + q * Q;
+            if (!rescale) {
+                for (int i = 0; i < Q; ++i) dst[i] = src[i];
+            } else {
+                double feq[Q];
+                orc_feq(C->rho[p], C->ux[p], C->uy[p], feq);
+                for (int i = 0; i < Q; ++i) dst[i] = feq[i] + scf * (src[i] - feq[i]);
+            }
+        }
+}
+
+/* StreamingStep, Eq. (10), over owned and halo cells; same-level exchange is
+ * implicit in the dense arrays (with the periodic wrap).  Unknown incoming
+ * populations are left NaN for the boundary and fine-to-coarse steps. */
+static void streaming(orc_sim *s, int l) {
+    olev *L = &s->L[l];
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < L->ny; ++y)
+        for (int x = 0; x < L->nx; ++x) {
+            size_t q = cid(L, x, y);
+            uint8_t kd = L->kind[q];
+            if (kd != K_OWN && kd != K_GHOST) continue;
+            for (int i = 0; i < Q; ++i) {
+                int sx = x - CX[i], sy = y - CY[i];
+                double v = NAN;
+                if (wrap_level(s, L, &sx, &sy)) {
+                    size_t p = cid(L, sx, sy);
+                    if (L->kind[p] == K_OWN || L->kind[p] == K_GHOST) v = L->fs[p * Q + i];
+                }
+                L->f[q * Q + i] = v;
+            }
+        }
+}
+
+/* PreStreamingStep: before the second fine stream the halo cells' sources
+ * are their own post-stream values of the first substep. */
+static void pre_streaming(orc_sim *s, int l) {
+    olev *L = &s->L[l];
+    for (size_t q = 0; q < (size_t)L->nx * L->ny; ++q)
+        if (L->kind[q] == K_GHOST) memcpy(L->fs + q * Q, L->f + q * Q, sizeof(double) * Q);
+}
+
+static int opposite(int i) {
+    for (int k = 0; k < Q; ++k)
+        if (CX[k] == -CX[i] && CY[k] == -CY[i]) return k;
+    return -1;
+}
+
+static int mirror(int i, int normal_x) {
+    for (int k = 0; k < Q; ++k) {
+        if (normal_x && CX[k] == -CX[i] && CY[k] == CY[i]) return k;
+        if (!normal_x && CX[k] == CX[i] && CY[k] == -CY[i]) return k;
+    }
+    return -1;
+}
+
+/* Clamp a cell reference into the level (used only for corner populations). */
+static void clamp_level(const olev *L, int *x, int *y) {
+    if (*x < 0) *x = 0;
+    if (*x >= L->nx) *x = L->nx - 1;
+    if (*y < 0) *y = 0;
+    if (*y >= L->ny) *y = L->ny - 1;
+}
+
+static int local_kind(int k) { return k == ORC_BC_WALL || k == ORC_BC_INFLOW; }
+
+/* BoundaryConditionStep: fills the unknown populations of edge cells.  A
+ * population whose source lies beyond one non-periodic edge takes that
+ * edge's rule; one beyond two edges (a corner diagonal) takes the W/E edge's
+ * rule unless only the S/N edge is a wall or inflow, with any cell that rule
+ * refers to clamped into the domain. */
+static void boundary(orc_sim *s, int l) {
+    olev *L = &s->L[l];
+    if (s->per_x && s->per_y) return;
+    const int nrm[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+    double rho0 = s->c.rho0;
+    for (int y = 0; y < L->ny; ++y)
+        for (int x = 0; x < L->nx; ++x) {
+            size_t q = cid(L, x, y);
+            if (L->kind[q] != K_OWN) continue;
+            for (int i = 1; i < Q; ++i) {
+                int sx = x - CX[i], sy = y - CY[i];
+                int outx = (sx < 0 || sx >= L->nx) && !s->per_x;
+                int outy = (sy < 0 || sy >= L->ny) && !s->per_y;
+                if (!outx && !outy) continue;
+                int ex = sx < 0 ? ORC_W : ORC_E, ey = sy < 0 ? ORC_S : ORC_N;
+                int e = outx ? ex : ey;
+                if (outx && outy && !local_kind(s->c.bc[ex]) && local_kind(s->c.bc[ey])) e = ey;
+                double *fx = L->f + q * Q;
+                const double *fsx = L->fs + q * Q;
+                double uwx = s->c.bc_u[2 * e], uwy = s->c.bc_u[2 * e + 1];
+                switch (s->c.bc[e]) {
+                case ORC_BC_WALL:
+                    fx[i] = fsx[opposite(i)] + 6.0 * WT[i] * rho0 * (CX[i] * uwx + CY[i] * uwy);
+                    break;
+                case ORC_BC_INFLOW: {
+                    double feq[Q];
+                    orc_feq(rho0, uwx, uwy, feq);
+                    fx[i] = feq[i];
+                } break;
+                case ORC_BC_OUTFLOW: {
+                    int px = x - nrm[e][0] - CX[i], py = y - nrm[e][1] - CY[i];
+                    wrap_level(s, L, &px, &py);
+                    clamp_level(L, &px, &py);
+                    fx[i] = L->fs[cid(L, px, py) * Q + i];
+                } break;
+                case ORC_BC_SYMMETRY: {
+                    int nx_ = (e == ORC_W || e == ORC_E);
+                    int px = x - (nx_ ? 0 : CX[i]), py = y - (nx_ ? CY[i] : 0);
+                    wrap_level(s, L, &px, &py);
+                    clamp_level(L, &px, &py);
+                    fx[i] = L->fs[cid(L, px, py) * Q + mirror(i, nx_)];
+                } break;
+                default: break;
+                }
+            }
+        }
+}
+
+/* FineToCoarseCommunication (step (6) of Sec. 2.4). */
+static void fine_to_coarse(orc_sim *s, int lf, int lc) {
+    olev *F = &s->L[lf], *C = &s->L[lc];
+    double sfc = 2.0 * C->tau / F->tau;
+    int rescale = s->c.cf_mode == ORC_CF_RESCALE;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < C->ny; ++y)
+        for (int x = 0; x < C->nx; ++x) {
+            size_t q = cid(C, x, y);
+            if (C->kind[q] != K_OWN) continue;
+            int hid[Q];
+            int any = 0;
+            for (int i = 0; i < Q; ++i) {
+                int sx = x - CX[i], sy = y - CY[i];
+                hid[i] = wrap_level(s, C, &sx, &sy) && C->kind[cid(C, sx, sy)] == K_HIDDEN;
+                any |= hid[i];
+            }
+            if (!any) continue;
+            double avg[Q];
+            for (int i = 0; i < Q; ++i) {
+                if (!hid[i]) continue;
+                double sum = F->f[cid(F, 2 * x, 2 * y) * Q + i];
+                sum += F->f[cid(F, 2 * x + 1, 2 * y) * Q + i];
+                sum += F->f[cid(F, 2 * x, 2 * y + 1) * Q + i];
+                sum += F->f[cid(F, 2 * x + 1, 2 * y + 1) * Q + i];
+                avg[i] = 0.25 * sum;
+            }
+            double *dst = C->f + q * Q;
+            if (!rescale) {
+                for (int i = 0; i < Q; ++i) if (hid[i]) dst[i] = avg[i];
+            } else {
+                double g[Q], r = 0.0, jx = 0.0, jy = 0.0;
+                for (int i = 0; i < Q; ++i) g[i] = hid[i] ? avg[i] : dst[i];
+                for (int i = 0; i < Q; ++i) { r += g[i]; jx += CX[i] * g[i]; jy += CY[i] * g[i]; }
+                double feq[Q];
+                orc_feq(r, jx / r, jy / r, feq);
+                for (int i = 0; i < Q; ++i)
+                    if (hid[i]) dst[i] = feq[i] + sfc * (avg[i] - feq[i]);
+            }
+        }
+}
+
+/* Algorithm 1: SynchronousNonUniformTimeStep(l). */
+static void snuts(orc_sim *s, int l) {
+    int m = s->m;
+    update_velocity(s, l);
+    if (l == m - 1 && s->c.body_kind != ORC_BODY_NONE) s->k++;
+    collision(s, l);
+    if (l != m - 1) snuts(s, l + 1);
+    if (l != 0) coarse_to_fine(s, l - 1, l);
+    streaming(s, l);
+    boundary(s, l);
+    if (l != m - 1) fine_to_coarse(s, l + 1, l);
+    if (l == 0) return;
+    update_velocity(s, l);
+    if (l == m - 1 && s->c.body_kind != ORC_BODY_NONE) s->k++;
+    collision(s, l);
+    if (l != m - 1) snuts(s, l + 1);
+    pre_streaming(s, l);
+    streaming(s, l);
+    boundary(s, l);
+    if (l != m - 1) fine_to_coarse(s, l + 1, l);
+}
+
+int orc_step(orc_sim *s, int32_t n) {
+    for (int32_t t = 0; t < n && !s->err; ++t) {
+        if (s->c.body_kind == ORC_BODY_NONE) s->k += (int64_t)1 << (s->m - 1);
+        snuts(s, 0);
+    }
+    return s->err;
+}
+
+int64_t orc_substeps(const orc_sim *s) { return s->k; }
+
+/* ------------------------------------------------------------------------ */
+/* Outputs                                                                   */
+/* ------------------------------------------------------------------------ */
+
+int orc_read_fields(const orc_sim *s, int level, double *rho, double *ux, double *uy) {
+    if (level < 0 || level >= s->m) return ORC_ERR_ARG;
+    const olev *L = &s->L[level];
+    for (size_t q = 0; q < (size_t)L->nx * L->ny; ++q) {
+        if (L->kind[q] != K_OWN) { rho[q] = ux[q] = uy[q] = NAN; continue; }
+        const double *f = L->f + q * Q;
+        double r = 0.0, jx = 0.0, jy = 0.0;
+        for (int i = 0; i < Q; ++i) { r += f[i]; jx += CX[i] * f[i]; jy += CY[i] * f[i]; }
+        rho[q] = r;
+        ux[q] = (jx + 0.5 * L->fx) / r;
+        uy[q] = (jy + 0.5 * L->fy) / r;
+    }
+    return ORC_OK;
+}
+
+int orc_read_populations(const orc_sim *s, int level, double *f) {
+    if (level < 0 || level >= s->m) return ORC_ERR_ARG;
+    const olev *L = &s->L[level];
+    memcpy(f, L->f, sizeof(double) * Q * L->nx * L->ny);
+    return ORC_OK;
+}
+
+int orc_marker_forces(const orc_sim *s, double *fx, double *fy) {
+    for (int j = 0; j < s->c.n_markers; ++j) { fx[j] = s->ftx[j]; fy[j] = s->fty[j]; }
+    return ORC_OK;
+}
+
+int orc_force_history(const orc_sim *s, int32_t cap, double *fx, double *fy, int32_t *n_out) {
+    int64_t n = s->nhist < cap ? s->nhist : cap;
+    int64_t first = s->nhist - n;
+    for (int64_t t = 0; t < n; ++t) {
+        fx[t] = s->hist[2 * (first + t)];
+        fy[t] = s->hist[2 * (first + t) + 1];
+    }
+    *n_out = (int32_t)n;
+    return ORC_OK;
+}
+
+int orc_diagnostics(const orc_sim *s, double out[3]) {
+    double M = 0.0, Px = 0.0, Py = 0.0;
+    for (int l = 0; l < s->m; ++l) {
+        const olev *L = &s->L[l];
+        double vol = 1.0 / (double)(1 << (2 * l));
+        double m = 0.0, px = 0.0, py = 0.0;
+        for (size_t q = 0; q < (size_t)L->nx * L->ny; ++q) {
+            if (L->kind[q] != K_OWN) continue;
+            const double *f = L->f + q * Q;
+            for (int i = 0; i < Q; ++i) { m += f[i]; px += CX[i] * f[i]; py += CY[i] * f[i]; }
+        }
+        M += vol * m; Px += vol * px; Py += vol * py;
+    }
+    out[0] = M; out[1] = Px; out[2] = Py;
+    return ORC_OK;
+}

@@ -1,0 +1,104 @@
+/*
+ * oracle.h -- plain FP64 CPU oracle for the lattice-Boltzmann / multi-direct-
+ * forcing immersed-boundary time step of SBoTFlow (arXiv 2402.04606).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the package's smoke check
+ * and the CPU-baseline leg of the benchmark may load this library.  It shares
+ * no code, header, table or helper with the GPU library; the two meet only
+ * through the seeded workload generators in `workloads/`.
+ *
+ * Data layout: every refinement level l is held as a dense array covering the
+ * whole domain at that level's resolution (nx0*2^l x ny0*2^l cells), row-major,
+ * 9 populations per cell, direction order of Eq. (1).  Cells that are neither
+ * owned nor halo cells of the level hold NaN, so any read of an undefined
+ * population shows up in the results.
+ *
+ * All functions return 0 on success or a negative code (ORC_ERR_*).
+ */
+#ifndef SBT_ORACLE_H
+#define SBT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_TOPOLOGY = -2, ORC_ERR_MARKER = -7 };
+enum { ORC_BC_PERIODIC = 0, ORC_BC_WALL = 1, ORC_BC_INFLOW = 2, ORC_BC_OUTFLOW = 3,
+       ORC_BC_SYMMETRY = 4 };
+enum { ORC_CF_HOMOGENEOUS = 0, ORC_CF_RESCALE = 1 };
+enum { ORC_BODY_NONE = -1, ORC_BODY_FIXED = 0, ORC_BODY_FLAP = 1 };
+enum { ORC_W = 0, ORC_E = 1, ORC_S = 2, ORC_N = 3 };
+
+typedef struct {
+    int32_t nx0, ny0;        /* level-0 cells                                   */
+    int32_t block_n;         /* cells per block edge (boxes are in block units) */
+    int32_t n_levels;        /* m >= 1                                           */
+    int32_t n_boxes;         /* refinement boxes, 5 ints each:                   */
+    const int32_t *boxes;    /*   level, bx0, by0, bx1, by1 (half-open, level-l
+                                   block units); region_l = union of its boxes   */
+    double tau0, rho0;       /* level-0 relaxation time, reference density      */
+    int32_t bc[4];           /* edge kinds, order W, E, S, N                     */
+    double bc_u[8];          /* (ux, uy) per edge: wall / inflow velocity        */
+    double fext[2];          /* uniform body-force density, level-0 units        */
+    int32_t cf_mode;         /* ORC_CF_*                                         */
+    int32_t mdf_iters;       /* N_F                                              */
+    int32_t body_kind;       /* ORC_BODY_*                                       */
+    int32_t n_markers;
+    const double *xb, *yb;   /* body-frame marker coordinates, finest cells      */
+    const double *ds;        /* marker arc lengths, finest cells                 */
+    double bp[16];           /* kinematic parameters (see orc_body_positions)    */
+} orc_case;
+
+typedef struct orc_sim orc_sim;
+
+int  orc_create(const orc_case *c, orc_sim **out);
+void orc_destroy(orc_sim *s);
+int  orc_level_size(const orc_sim *s, int level, int32_t *nx, int32_t *ny);
+/* Kind map of a level: 0 none, 1 own, 2 ghost (halo), 3 hidden (covered by l+1). */
+int  orc_level_kinds(const orc_sim *s, int level, uint8_t *kind);
+/* f = f^eq(rho, u) with F = 0 on the owned cells of `level` (dense arrays). */
+int  orc_init_fields(orc_sim *s, int level, const double *rho, const double *ux,
+                     const double *uy);
+/* Advance n coarse (level-0) time steps. */
+int  orc_step(orc_sim *s, int32_t n);
+/* rho and u = (sum_i c_i f_i + F_ext/2)/rho on owned cells, NaN elsewhere. */
+int  orc_read_fields(const orc_sim *s, int level, double *rho, double *ux, double *uy);
+/* Raw populations of a level, dense [ny][nx][9]. */
+int  orc_read_populations(const orc_sim *s, int level, double *f);
+int  orc_marker_forces(const orc_sim *s, double *fx, double *fy);
+int  orc_force_history(const orc_sim *s, int32_t cap, double *fx, double *fy, int32_t *n_out);
+/* out = {mass, momentum x, momentum y}, each summed over owned cells with
+ * volume weight 4^-l; momentum is the bare first moment sum_i c_i f_i. */
+int  orc_diagnostics(const orc_sim *s, double out[3]);
+int64_t orc_substeps(const orc_sim *s);
+
+/* ---- building blocks, exposed so the test-suite can pin them ------------ */
+void   orc_velocity_set(int32_t cx[9], int32_t cy[9], double w[9]);
+void   orc_feq(double rho, double ux, double uy, double out[9]);
+void   orc_guo(double tau, double ux, double uy, double Fx, double Fy, double out[9]);
+void   orc_collide_cell(double tau, const double f[9], double Fx, double Fy, double out[9]);
+double orc_phi(double r);
+/* Marker positions of the body at finest substep k (time t_k = k). */
+int    orc_body_positions(const orc_case *c, double k, double *X, double *Y);
+/* The multi-direct-forcing loop on a dense periodic nx x ny grid of cell
+ * moments: rho (fixed), u (corrected in place), F (accumulated in place);
+ * markers X, Y, desired velocity ud, arc length ds; returns the per-marker
+ * total force ftot over all iterations. */
+int    orc_mdf(int32_t nx, int32_t ny, const double *rho, double *ux, double *uy,
+               double *Fx, double *Fy, int32_t n, const double *X, const double *Y,
+               const double *udx, const double *udy, const double *ds, int32_t iters,
+               double *ftx, double *fty);
+/* Velocity interpolation Eq. (12) at arbitrary points on a dense periodic grid. */
+int    orc_interpolate(int32_t nx, int32_t ny, const double *ux, const double *uy,
+                       int32_t n, const double *X, const double *Y, double *U, double *V);
+/* Force spreading Eq. (15) on a dense periodic grid (adds into Fx, Fy). */
+int    orc_spread(int32_t nx, int32_t ny, int32_t n, const double *X, const double *Y,
+                  const double *Fjx, const double *Fjy, const double *ds,
+                  double *Fx, double *Fy);
+int    orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

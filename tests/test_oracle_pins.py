@@ -1,0 +1,377 @@
+"""Pins for the FP64 oracle: each check is a property fixed by the paper or by
+the mathematics (an identity, a closed form, an invariant), never a re-typing
+of the oracle's own formula, and each is chosen so that a plausible slip in
+the oracle (a dropped term, a flipped sign, a transposed index) fails it."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+# ---- Sec. 2.1, Eq. (1): velocity set -------------------------------------
+
+def test_velocity_set_isotropy(orc):
+    cx, cy, w = orc.velocity_set()
+    assert list(cx) == [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    assert list(cy) == [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    assert abs(w.sum() - 1.0) < 1e-15
+    # lattice isotropy up to 4th order with c_s^2 = 1/3
+    assert abs((w * cx * cx).sum() - 1 / 3) < 1e-15
+    assert abs((w * cx * cy).sum()) < 1e-15
+    assert abs((w * cx ** 4).sum() - 3 * (1 / 3) ** 2) < 1e-15
+    assert abs((w * cx ** 2 * cy ** 2).sum() - (1 / 3) ** 2) < 1e-15
+
+
+# ---- Eq. (7): equilibrium moments (P2) -----------------------------------
+
+def test_equilibrium_moments(orc):
+    cx, cy, _ = orc.velocity_set()
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        rho = rng.uniform(0.5, 1.5)
+        ux, uy = rng.uniform(-0.2, 0.2, 2)
+        f = orc.feq(rho, ux, uy)
+        assert abs(f.sum() - rho) < 1e-14
+        assert abs((cx * f).sum() - rho * ux) < 1e-15
+        assert abs((cy * f).sum() - rho * uy) < 1e-15
+        assert abs((cx * cx * f).sum() - (rho / 3 + rho * ux * ux)) < 1e-14
+        assert abs((cx * cy * f).sum() - rho * ux * uy) < 1e-14
+        assert abs((cy * cy * f).sum() - (rho / 3 + rho * uy * uy)) < 1e-14
+
+
+# ---- Eqs. (3)-(5): Guo forcing moments (P1) ------------------------------
+
+def test_guo_moments(orc):
+    cx, cy, _ = orc.velocity_set()
+    rng = np.random.default_rng(2)
+    for _ in range(50):
+        tau = rng.uniform(0.51, 2.0)
+        ux, uy, Fx, Fy = rng.uniform(-0.1, 0.1, 4)
+        Fi = orc.guo(tau, ux, uy, Fx, Fy)
+        pre = 1 - 1 / (2 * tau)
+        assert abs(Fi.sum()) < 1e-15                                   # Eq. (4)
+        assert abs((cx * Fi).sum() - pre * Fx) < 1e-15                 # Eq. (5)
+        assert abs((cy * Fi).sum() - pre * Fy) < 1e-15
+        # second moment of Guo's term: (1 - 1/2tau)(uF + Fu)
+        assert abs((cx * cx * Fi).sum() - pre * 2 * ux * Fx) < 1e-15
+        assert abs((cx * cy * Fi).sum() - pre * (ux * Fy + uy * Fx)) < 1e-15
+
+
+def test_collision_conserves_mass_and_adds_force(orc):
+    """Eqs. (6), (8): a collision keeps rho and raises sum c f by exactly F."""
+    cx, cy, _ = orc.velocity_set()
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        tau = rng.uniform(0.51, 2.0)
+        f = orc.feq(1.0, 0.03, -0.02) + rng.uniform(-1e-3, 1e-3, 9)
+        Fx, Fy = rng.uniform(-1e-3, 1e-3, 2)
+        fs = orc.collide_cell(tau, f, Fx, Fy)
+        assert abs(fs.sum() - f.sum()) < 1e-15
+        assert abs((cx * fs).sum() - (cx * f).sum() - Fx) < 1e-16
+        assert abs((cy * fs).sum() - (cy * f).sum() - Fy) < 1e-16
+        # relaxation of the stress: sum c c (f* - f^eq) = (1 - 1/tau) sum c c (f - f^eq) + guo part
+        rho = f.sum()
+        u = ((cx * f).sum() + Fx / 2) / rho
+        v = ((cy * f).sum() + Fy / 2) / rho
+        fe = orc.feq(rho, u, v)
+        lhs = (cx * cy * (fs - fe)).sum()
+        rhs = (1 - 1 / tau) * (cx * cy * (f - fe)).sum() + (1 - 1 / (2 * tau)) * (u * Fy + v * Fx)
+        assert abs(lhs - rhs) < 1e-16
+
+
+# ---- Eq. (14): Peskin kernel (P3) ----------------------------------------
+
+def test_peskin_kernel_moments(orc):
+    rng = np.random.default_rng(4)
+    assert orc.phi(2.0) == 0.0 and orc.phi(-2.5) == 0.0 and orc.phi(7.0) == 0.0
+    assert abs(orc.phi(1.0) - 0.25) < 1e-16 and abs(orc.phi(1.0 - 1e-12) - 0.25) < 1e-11
+    assert abs(orc.phi(0.0) - 0.5) < 1e-16
+    for X in rng.uniform(-3, 3, 200):
+        i = np.arange(math.floor(X) - 3, math.floor(X) + 4)
+        r = i + 0.5 - X
+        p = np.array([orc.phi(v) for v in r])
+        assert (p > 0).sum() <= 4
+        assert abs(p.sum() - 1.0) < 1e-14                  # partition of unity
+        assert abs((r * p).sum()) < 1e-14                  # first moment
+        assert abs((p * p).sum() - 3.0 / 8.0) < 1e-14      # sum phi^2
+        assert abs(p[i % 2 == 0].sum() - 0.5) < 1e-14      # even/odd sums
+        assert abs(p[i % 2 == 1].sum() - 0.5) < 1e-14
+
+
+# ---- Eqs. (12), (15), (16): interpolation and spreading (P4) -------------
+
+def test_interpolation_exact_for_linear_fields(orc):
+    ny, nx = 32, 40
+    yy, xx = np.mgrid[0:ny, 0:nx] + 0.5
+    u = 0.3 + 0.01 * xx - 0.02 * yy
+    v = -0.1 + 0.005 * xx + 0.007 * yy
+    rng = np.random.default_rng(5)
+    X, Y = rng.uniform(8, nx - 8, 30), rng.uniform(8, ny - 8, 30)
+    U, V = orc.interpolate(u, v, X, Y)
+    assert np.abs(U - (0.3 + 0.01 * X - 0.02 * Y)).max() < 1e-14
+    assert np.abs(V - (-0.1 + 0.005 * X + 0.007 * Y)).max() < 1e-14
+
+
+def test_spread_total_equals_marker_total(orc):
+    rng = np.random.default_rng(6)
+    X, Y = rng.uniform(5, 45, 40), rng.uniform(5, 35, 40)
+    Fjx, Fjy, ds = rng.normal(size=40), rng.normal(size=40), rng.uniform(0.5, 1.5, 40)
+    Fx, Fy = orc.spread((40, 50), X, Y, Fjx, Fjy, ds)
+    assert abs(Fx.sum() - (Fjx * ds).sum()) < 1e-12
+    assert abs(Fy.sum() - (Fjy * ds).sum()) < 1e-12
+    # first moment of the spread force sits at the markers
+    yy, xx = np.mgrid[0:40, 0:50] + 0.5
+    assert abs((Fx * xx).sum() - (Fjx * ds * X).sum()) < 1e-10
+
+
+# ---- MDF closed form for one marker (P5) ---------------------------------
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_mdf_single_marker_closed_form(orc, k):
+    ny, nx = 24, 24
+    rho = np.ones((ny, nx))
+    u0 = np.zeros((ny, nx))
+    X, Y = np.array([11.37]), np.array([12.81])
+    ux, uy, Fx, Fy, ftx, fty = orc.mdf(rho, u0, u0, X, Y, np.array([1.0]), np.array([0.0]),
+                                       np.array([1.0]), k)
+    U, V = orc.interpolate(ux, uy, X, Y)
+    r = 55.0 / 64.0                        # 1 - ds (sum phi^2)^2 = 1 - 9/64
+    assert abs((1.0 - U[0]) - r ** k) < 1e-14
+    assert abs(V[0]) < 1e-15
+    assert abs(ftx[0] - 2.0 * sum(r ** i for i in range(k))) < 1e-13
+    assert abs(Fx.sum() - ftx[0]) < 1e-13   # Eq. (16) with ds = 1
+
+
+def test_mdf_slip_decreases_on_a_circle(orc):
+    """Reading 1: the iterated loop must reduce the boundary slip."""
+    ny, nx = 48, 48
+    rho = np.ones((ny, nx))
+    u = np.full((ny, nx), 0.05)
+    v = np.zeros((ny, nx))
+    xb, yb, ds = W.circle_markers(8.0, 50)
+    X, Y = 24.3 + xb, 23.9 + yb
+    slips = []
+    for k in (1, 2, 3, 4):
+        ux, uy, *_ = orc.mdf(rho, u, v, X, Y, np.zeros(50), np.zeros(50), ds, k)
+        U, V = orc.interpolate(ux, uy, X, Y)
+        slips.append(np.sqrt((U ** 2 + V ** 2).mean()))
+    assert all(slips[i + 1] < slips[i] for i in range(3))
+    assert slips[-1] < 0.2 * 0.05
+
+
+# ---- Kinematics (Sec. 3.6 law) -------------------------------------------
+
+def test_flap_kinematics_is_rigid_and_periodic(orc):
+    wl = W.flapping_ellipse()
+    X0, Y0 = orc.body_positions(wl, 0)
+    d0 = np.hypot(X0[:, None] - X0[None], Y0[:, None] - Y0[None])
+    p = wl.body.params
+    period_steps = p[6] * p[9] / p[8]
+    for k in (17, 333, 1234.5, period_steps / 4):
+        X, Y = orc.body_positions(wl, k)
+        d = np.hypot(X[:, None] - X[None], Y[:, None] - Y[None])
+        assert np.abs(d - d0).max() < 1e-10
+    X, Y = orc.body_positions(wl, period_steps)
+    assert np.abs(X - X0).max() < 1e-9 and np.abs(Y - Y0).max() < 1e-9
+    # at t = 0: pitch angle alpha0 - A sin(phi) = 0, heave at +A0/2 along beta = 90 deg
+    assert abs(Y0.mean() - (p[1] + p[4] / 2)) < 1e-9 and abs(X0.mean() - p[0]) < 1e-9
+    # a quarter period later the pitch angle is -A (nose down by A)
+    Xq, Yq = orc.body_positions(wl, period_steps / 4)
+    j = int(np.argmin(wl.body.xb))                      # leading-edge marker (xb = -c/2)
+    ang = math.atan2(Yq[j] - Yq.mean(), -(Xq[j] - Xq.mean()))
+    assert abs(ang + p[3]) < 1e-9      # positive alpha is nose-up
+
+
+def test_flap_with_zero_amplitudes_is_fixed(orc):
+    wl = W.flapping_ellipse()
+    b = wl.body
+    params = list(b.params)
+    params[3] = 0.0
+    params[4] = 0.0
+    moving = wl.replace(body=W.Body(W.BODY_FLAP, b.xb, b.yb, b.ds, params))
+    fixed = wl.replace(body=W.Body(W.BODY_FIXED, b.xb, b.yb, b.ds, params))
+    for k in (0, 10, 999):
+        Xm, Ym = orc.body_positions(moving, k)
+        Xf, Yf = orc.body_positions(fixed, k)
+        assert np.abs(Xm - Xf).max() < 1e-12 and np.abs(Ym - Yf).max() < 1e-12
+
+
+# ---- Whole-step invariants and closed forms ------------------------------
+
+def test_periodic_conservation_with_body_force(orc):
+    """P6: mass constant; total momentum grows by exactly N F per step."""
+    g = (2e-6, -1e-6)
+    wl = W.tgv(32).replace(fext=g)
+    s = orc.OracleSim(wl)
+    d0 = s.diagnostics()
+    s.step(50)
+    d1 = s.diagnostics()
+    n = 32 * 32
+    assert abs(d1[0] - d0[0]) < 1e-11 * n
+    assert abs((d1[1] - d0[1]) - 50 * n * g[0]) < 1e-12
+    assert abs((d1[2] - d0[2]) - 50 * n * g[1]) < 1e-12
+
+
+def _tgv_error(orc, wl, steps):
+    s = orc.OracleSim(wl)
+    s.step(steps)
+    fac = math.exp(-2 * wl.meta["nu"] * wl.meta["k"] ** 2 * steps)
+    num = den = 0.0
+    for l in range(wl.n_levels):
+        nx, ny = s.level_size(l)
+        _, u, _ = s.fields(l)
+        _, ua, _ = wl.init(l, nx, ny)
+        m = ~np.isnan(u)
+        num += ((u[m] - fac * ua[m]) ** 2).sum() / 4 ** l
+        den += ((fac * ua[m]) ** 2).sum() / 4 ** l
+    return math.sqrt(num / den), fac
+
+
+def test_tgv_closed_form_decay(orc):
+    """P7: 64x64, tau 0.8, u0 0.02, 1000 steps: u(t) = u(0) exp(-2 nu k^2 t)."""
+    err, fac = _tgv_error(orc, W.tgv(64), 1000)
+    assert abs(fac - 0.14549) < 1e-5
+    assert err < 1e-2
+
+
+def test_tgv_second_order_convergence(orc):
+    """Sec. 3.1: nu = 1/6, Re = 7.68, t* = 0.25; error falls as N^-2."""
+    ns = [32, 64, 96, 128]
+    errs = []
+    for n in ns:
+        wl = W.tgv_ladder(n)
+        errs.append(_tgv_error(orc, wl, wl.meta["steps"])[0])
+    order = -np.polyfit(np.log(ns), np.log(errs), 1)[0]
+    assert 1.8 < order < 2.3, (errs, order)
+
+
+def test_poiseuille_exact_profile(orc):
+    """P8: BGK + Guo + half-way bounce-back: parabolic profile, walls exactly
+    half-way at tau = 1/2 + sqrt(3)/4; constant 2nd difference -g/nu at any tau."""
+    for tau, exact in ((0.5 + math.sqrt(3) / 4, True), (0.8, False), (1.3, False)):
+        wl = W.poiseuille(nx=4, ny=16, tau=tau)
+        s = orc.OracleSim(wl)
+        s.step(30000 if tau < 1 else 12000)
+        _, u, v = s.fields(0)
+        g, nu = wl.meta["g"], wl.meta["nu"]
+        prof = u[:, 0]
+        d2 = prof[2:] - 2 * prof[1:-1] + prof[:-2]
+        assert np.abs(d2 * nu / g + 1.0).max() < 1e-6
+        assert np.abs(v).max() < 1e-13
+        if exact:
+            y = np.arange(16) + 0.5
+            ua = g / (2 * nu) * y * (16 - y)
+            assert np.abs(prof - ua).max() < 1e-9 * ua.max()
+
+
+def test_couette_linear_profile(orc):
+    """Moving-wall bounce-back: steady linear profile, walls half-way."""
+    U = 0.01
+    wl = W.Workload(name="couette", nx0=4, ny0=12, tau0=0.9, bc=(0, 0, W.WALL, W.WALL),
+                    bc_u=((0, 0), (0, 0), (0, 0), (U, 0.0)), init=W.uniform_init(1.0, 0, 0))
+    s = orc.OracleSim(wl)
+    s.step(20000)
+    _, u, _ = s.fields(0)
+    y = np.arange(12) + 0.5
+    assert np.abs(u[:, 0] - U * y / 12).max() < 1e-9 * U
+
+
+def test_closed_box_conserves_mass(orc):
+    wl = W.tgv(32).replace(bc=(W.WALL,) * 4)
+    s = orc.OracleSim(wl)
+    m0 = s.diagnostics()[0]
+    s.step(300)
+    assert abs(s.diagnostics()[0] - m0) < 1e-12 * m0
+
+
+def test_uniform_stream_is_fixed_point_of_open_boundaries(orc):
+    """Equilibrium inflow, zero-gradient outflow and symmetry edges keep a
+    uniform equilibrium stream exactly uniform; free-slip on all four edges
+    keeps a uniform x-stream uniform too."""
+    for bc in ((W.INFLOW, W.OUTFLOW, W.SYMMETRY, W.SYMMETRY),
+               (W.SYMMETRY, W.SYMMETRY, W.PERIODIC, W.PERIODIC)):
+        U = 0.05 if bc[0] == W.INFLOW else 0.0
+        V = 0.0 if bc[0] == W.INFLOW else 0.04
+        wl = W.Workload(name="stream", nx0=32, ny0=16, tau0=0.7, bc=bc,
+                        bc_u=((U, 0.0),) + ((0.0, 0.0),) * 3, init=W.uniform_init(1.0, U, V))
+        s = orc.OracleSim(wl)
+        s.step(100)
+        r, u, v = s.fields(0)
+        assert np.abs(r - 1).max() < 1e-14 and np.abs(u - U).max() < 1e-15
+        assert np.abs(v - V).max() < 1e-15
+
+
+def test_uniform_flow_on_refined_forest(orc):
+    """P9: f_neq = 0, so both interface operators are identities."""
+    for cf in (W.CF_HOMOGENEOUS, W.CF_RESCALE):
+        s = orc.OracleSim(W.uniform_refined(cf_mode=cf))
+        s.step(15)
+        for l in range(3):
+            r, u, v = s.fields(l)
+            m = ~np.isnan(r)
+            assert m.sum() > 0
+            assert np.abs(r[m] - 1).max() < 1e-13
+            assert np.abs(u[m] - 0.05).max() < 1e-14 and np.abs(v[m] - 0.02).max() < 1e-14
+
+
+def test_refined_band_conserves_mass(orc):
+    """P11: straight coarse-fine interfaces without corners, HOMOGENEOUS
+    operators: volume-weighted mass is conserved to roundoff."""
+    s = orc.OracleSim(W.tgv_band())
+    m0 = s.diagnostics()[0]
+    s.step(200)
+    assert abs(s.diagnostics()[0] - m0) < 1e-12 * m0
+
+
+def test_refined_patch_tgv_stays_close(orc):
+    """P12: a refined patch does not degrade TGV beyond an interface error
+    that shrinks with resolution."""
+    e_uni, _ = _tgv_error(orc, W.tgv(64), 500)
+    e_p2, _ = _tgv_error(orc, W.tgv_patch(m=2), 500)
+    e_p3, _ = _tgv_error(orc, W.tgv_patch(m=3), 500)
+    assert e_p2 < 1e-2 and e_p3 < 1e-2
+    wl128 = W.tgv(128, u0=0.01).replace(n_levels=2, boxes=[(1, 4, 4, 12, 12)])
+    e128, _ = _tgv_error(orc, wl128, 2000)
+    assert e128 < 0.5 * e_p2
+
+
+def test_symmetric_body_symmetric_flow(orc):
+    """P13: symmetric body in a symmetric channel: u_y odd about the centre line."""
+    wl = W.cylinder(128, 64, D=12.0, centre=(40.0, 32.0), n_markers=38, Re=40.0, perturb=False)
+    s = orc.OracleSim(wl)
+    s.step(300)
+    _, u, v = s.fields(0)
+    assert np.abs(v + v[::-1]).max() < 1e-12 * 0.05
+    assert np.abs(u - u[::-1]).max() < 1e-12 * 0.05
+    fx, fy = s.force_history()
+    assert len(fx) == 300 and np.abs(fy).max() < 1e-12
+
+
+def test_cylinder_drag_in_sane_range(orc):
+    """Sanity: steady drag of a cylinder at Re 40 in a channel is O(1)-O(few)."""
+    wl = W.cylinder(160, 80, D=16.0, centre=(48.0, 40.0), n_markers=50, Re=40.0, perturb=False)
+    s = orc.OracleSim(wl)
+    s.step(3000)
+    fx, _ = s.force_history()
+    cd = fx[-1] / (0.5 * 0.05 ** 2 * 16.0)      # Eq. (16): force on the body
+    assert 1.0 < cd < 4.0
+
+
+def test_marker_outside_finest_level_is_rejected(orc):
+    wl = W.small_cylinder()
+    b = wl.body
+    bad = wl.replace(body=W.Body(b.kind, b.xb, b.yb, b.ds, [2.0, 32.0] + [0.0] * 14))
+    s = orc.OracleSim(bad)
+    with pytest.raises(RuntimeError):
+        s.step(1)
+
+
+def test_invalid_topology_rejected(orc):
+    # level-1 box touching a non-periodic edge
+    wl = W.cavity().replace(boxes=[(1, 0, 0, 4, 4)], n_levels=2, body=None)
+    with pytest.raises(RuntimeError):
+        orc.OracleSim(wl)

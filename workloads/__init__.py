@@ -1,0 +1,285 @@
+"""Seeded, synthetic workload descriptions shared by the GPU path and the oracle.
+
+This module only *describes* inputs: domain sizes, refinement boxes, relaxation
+time, edge kinds, initial fields, marker geometry and kinematic parameters.  It
+holds none of the method's arithmetic (no collision, streaming, interpolation,
+kinematics or interface operator), so both sides can consume it without sharing
+any of the computation.
+
+Shapes follow the benchmarks of arXiv 2402.04606, Sec. 3, scaled to the five
+workloads this package is measured on:
+  tgv(...)            Sec. 3.1 Taylor-Green vortex (periodic, closed form)
+  cylinder(...)       Sec. 3.3 stationary cylinder, uniform 1024x512 grid
+  cavity(...)         Sec. 3.2 lid-driven cavity with a central cylinder,
+                      3 levels of 16x16-cell blocks
+  flapping_ellipse()  Sec. 3.5/3.6 pitching and plunging wing, 4 levels
+  batch_sweep()       64 uneven flapping cases drawn from a fixed seed
+Plus small cases used as pins (Poiseuille channel, uniform flow on a refined
+forest, refined periodic band).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Callable, Optional
+
+import numpy as np
+
+# Edge kinds, order of edges W, E, S, N.
+PERIODIC, WALL, INFLOW, OUTFLOW, SYMMETRY = 0, 1, 2, 3, 4
+W, E, S, N = 0, 1, 2, 3
+CF_HOMOGENEOUS, CF_RESCALE = 0, 1
+BODY_FIXED, BODY_FLAP = 0, 1
+
+
+@dataclasses.dataclass
+class Body:
+    kind: int                      # BODY_FIXED or BODY_FLAP
+    xb: np.ndarray                 # body-frame marker x (finest cells)
+    yb: np.ndarray
+    ds: np.ndarray                 # arc length per marker (finest cells)
+    params: list                   # 16 kinematic parameters
+    # FIXED: params[0:2] = (x0, y0)
+    # FLAP : (x0, y0, alpha0, A_pitch, A0, beta, T, phi, U_ref, chord)
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    nx0: int
+    ny0: int
+    n_levels: int = 1
+    block_n: int = 16
+    boxes: list = dataclasses.field(default_factory=list)   # (level, bx0, by0, bx1, by1)
+    tau0: float = 0.8
+    rho0: float = 1.0
+    bc: tuple = (PERIODIC, PERIODIC, PERIODIC, PERIODIC)
+    bc_u: tuple = ((0.0, 0.0),) * 4
+    fext: tuple = (0.0, 0.0)
+    cf_mode: int = CF_HOMOGENEOUS
+    mdf_iters: int = 3
+    body: Optional[Body] = None
+    init: Optional[Callable] = None   # init(level, nx, ny) -> (rho, ux, uy) dense [ny, nx]
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    def replace(self, **kw):
+        return dataclasses.replace(self, **kw)
+
+
+def level_tau(tau0, level):
+    """Input bookkeeping only: tau of a level under acoustic scaling, used to
+    derive tau0 from a target Reynolds number on the finest level."""
+    return 0.5 + (2 ** level) * (tau0 - 0.5)
+
+
+def _cell_centres(level, nx, ny):
+    h = 1.0 / (2 ** level)
+    x = (np.arange(nx) + 0.5) * h
+    y = (np.arange(ny) + 0.5) * h
+    return np.meshgrid(x, y)            # level-0 units, arrays [ny, nx]
+
+
+def uniform_init(rho0, ux, uy, perturb=None):
+    """Uniform flow; optional perturbation (x0, y0, size, duy) in level-0 cells."""
+    def init(level, nx, ny):
+        rho = np.full((ny, nx), rho0)
+        u = np.full((ny, nx), float(ux))
+        v = np.full((ny, nx), float(uy))
+        if perturb is not None:
+            x0, y0, size, duy = perturb
+            X, Y = _cell_centres(level, nx, ny)
+            m = (X >= x0) & (X < x0 + size) & (Y >= y0) & (Y < y0 + size)
+            v[m] += duy
+        return rho, u, v
+    return init
+
+
+def tgv_init(nx0, u0, rho0):
+    """Taylor-Green initial state (Sec. 3.1; pressure written with cos terms)."""
+    k = 2.0 * math.pi / nx0
+
+    def init(level, nx, ny):
+        X, Y = _cell_centres(level, nx, ny)
+        u = -u0 * np.cos(k * X) * np.sin(k * Y)
+        v = u0 * np.sin(k * X) * np.cos(k * Y)
+        p = -(rho0 * u0 * u0 / 4.0) * (np.cos(2 * k * X) + np.cos(2 * k * Y))
+        return rho0 + 3.0 * p, u, v
+    return init
+
+
+def tgv(n=64, tau=0.8, u0=0.02, rho0=1.0, n_levels=1, boxes=(), name=None):
+    return Workload(name=name or f"tgv{n}", nx0=n, ny0=n, n_levels=n_levels, boxes=list(boxes),
+                    tau0=tau, rho0=rho0, init=tgv_init(n, u0, rho0),
+                    meta=dict(u0=u0, k=2 * math.pi / n, nu=(tau - 0.5) / 3.0))
+
+
+def tgv_ladder(n):
+    """Resolution ladder of Sec. 3.1: nu = 1/6, Re = U0 N / nu = 7.68, t* = 0.25."""
+    nu = 1.0 / 6.0
+    u0 = 7.68 * nu / n
+    wl = tgv(n, tau=3 * nu + 0.5, u0=u0)
+    wl.meta["steps"] = int(round(0.25 * n / u0))
+    return wl
+
+
+def poiseuille(nx=16, ny=16, tau=0.5 + math.sqrt(3) / 4, g=1e-6):
+    return Workload(name="poiseuille", nx0=nx, ny0=ny, tau0=tau,
+                    bc=(PERIODIC, PERIODIC, WALL, WALL), fext=(g, 0.0),
+                    init=uniform_init(1.0, 0.0, 0.0), meta=dict(g=g, nu=(tau - 0.5) / 3.0))
+
+
+def circle_markers(radius, n):
+    th = 2.0 * math.pi * np.arange(n) / n
+    ds = np.full(n, 2.0 * math.pi * radius / n)
+    return radius * np.cos(th), radius * np.sin(th), ds
+
+
+def ellipse_markers(a, b, n, samples=200000):
+    """n markers at equal arc-length spacing on x = a cos s, y = b sin s."""
+    s = np.linspace(0.0, 2.0 * math.pi, samples + 1)
+    x, y = a * np.cos(s), b * np.sin(s)
+    seg = np.hypot(np.diff(x), np.diff(y))
+    arc = np.concatenate([[0.0], np.cumsum(seg)])
+    per = arc[-1]
+    target = per * np.arange(n) / n
+    sj = np.interp(target, arc, s)
+    return a * np.cos(sj), b * np.sin(sj), np.full(n, per / n)
+
+
+def cylinder(nx=1024, ny=512, D=40.0, centre=(256.0, 256.0), n_markers=126, U=0.05, Re=100.0,
+             mdf_iters=3, perturb=True):
+    nu = U * D / Re
+    xb, yb, ds = circle_markers(D / 2.0, n_markers)
+    body = Body(BODY_FIXED, xb, yb, ds, [centre[0], centre[1]] + [0.0] * 14)
+    pert = (centre[0] + D / 2 + 2.0, centre[1], 4.0, 1e-3 * U) if perturb else None
+    return Workload(name=f"cylinder{nx}x{ny}", nx0=nx, ny0=ny, tau0=3 * nu + 0.5,
+                    bc=(INFLOW, OUTFLOW, SYMMETRY, SYMMETRY), bc_u=((U, 0.0),) + ((0.0, 0.0),) * 3,
+                    mdf_iters=mdf_iters, body=body, init=uniform_init(1.0, U, 0.0, pert),
+                    meta=dict(U=U, D=D, Re=Re))
+
+
+def cavity(cf_mode=CF_RESCALE, U=0.1, Re=1000.0):
+    """256^2 base, 3 levels; L1 over base [96,160)^2, L2 over base [104,152)^2;
+    cylinder D = 32 base cells (128 finest) at the centre."""
+    n0 = 256
+    nu0 = U * n0 / Re
+    n_m = int(round(math.pi * 128))
+    xb, yb, ds = circle_markers(64.0, n_m)
+    body = Body(BODY_FIXED, xb, yb, ds, [512.0, 512.0] + [0.0] * 14)
+    return Workload(name="cavity256_3lvl", nx0=n0, ny0=n0, n_levels=3,
+                    boxes=[(1, 12, 12, 20, 20), (2, 26, 26, 38, 38)], tau0=3 * nu0 + 0.5,
+                    bc=(WALL, WALL, WALL, WALL), bc_u=((0, 0), (0, 0), (0, 0), (U, 0.0)),
+                    cf_mode=cf_mode, body=body, init=uniform_init(1.0, 0.0, 0.0),
+                    meta=dict(U=U, Re=Re, D_finest=128))
+
+
+def flap_params(x0, y0, chord, amp_deg, T, U, A0_over_c=2.5, beta_deg=90.0, alpha0=0.0, phi=0.0):
+    return [x0, y0, alpha0, math.radians(amp_deg), A0_over_c * chord, math.radians(beta_deg), T,
+            phi, U, chord] + [0.0] * 6
+
+
+def flapping_ellipse(Re=100.0, U=0.05, n_markers=200, chord=64.0, amp_deg=64.0,
+                     T=2.5 * math.pi):
+    """Coarse 512x256, 4 levels, chord 64 finest cells, thickness 0.125."""
+    m = 4
+    nu_f = U * chord / Re
+    tau0 = 0.5 + (3 * nu_f) / 2 ** (m - 1)
+    xb, yb, ds = ellipse_markers(chord / 2, chord / 16, n_markers)
+    body = Body(BODY_FLAP, xb, yb, ds, flap_params(1024.0, 1024.0, chord, amp_deg, T, U))
+    boxes = [(1, 13, 11, 19, 21), (2, 29, 26, 35, 38), (3, 61, 56, 67, 72)]
+    return Workload(name=f"flap_ellipse_re{int(Re)}", nx0=512, ny0=256, n_levels=m, boxes=boxes,
+                    tau0=tau0, bc=(INFLOW, OUTFLOW, SYMMETRY, SYMMETRY),
+                    bc_u=((U, 0.0),) + ((0.0, 0.0),) * 3, body=body,
+                    init=uniform_init(1.0, U, 0.0), meta=dict(U=U, Re=Re, chord=chord))
+
+
+def _nested_boxes(bbox_f, m, B, nx0, ny0):
+    """Block-aligned boxes for levels 1..m-1 around a finest-level bounding box
+    (x0, y0, x1, y1), each level containing the finer one plus a 1-cell margin.
+    Returns None if a refined level would come within one block of an edge."""
+    boxes = []
+    x0, y0, x1, y1 = bbox_f
+    bx0, by0 = math.floor(x0 / B), math.floor(y0 / B)
+    bx1, by1 = math.ceil(x1 / B), math.ceil(y1 / B)
+    for l in range(m - 1, 0, -1):
+        boxes.append((l, bx0, by0, bx1, by1))
+        # extent on level l-1 in cells, plus one cell, rounded out to blocks
+        cx0, cy0 = bx0 * B // 2 - 1, by0 * B // 2 - 1
+        cx1, cy1 = bx1 * B // 2 + 1, by1 * B // 2 + 1
+        bx0, by0 = math.floor(cx0 / B), math.floor(cy0 / B)
+        bx1, by1 = math.ceil(cx1 / B), math.ceil(cy1 / B)
+    # (bx0..bx1) is now the level-0 block box that must contain level 1
+    if bx0 < 1 or by0 < 1 or bx1 > nx0 // B - 1 or by1 > ny0 // B - 1:
+        return None
+    return sorted(boxes)
+
+
+def flapping_case(nx0, m, amp_deg, Re, n_markers, T, U=0.05, ds_target=0.65, name="flap"):
+    B = 16
+    per_over_c = 2.0453          # perimeter / chord of a 0.125-thick ellipse
+    chord = 2.0 * round(n_markers * ds_target / per_over_c / 2.0)
+    ny0 = nx0 // 2
+    f = 2 ** (m - 1)
+    xc, yc = nx0 / 4.0 * f, ny0 / 2.0 * f
+    half_x = 0.5 * chord + 6.0
+    half_y = 1.25 * chord + 0.5 * chord * math.sin(math.radians(amp_deg)) + chord / 16 + 6.0
+    bbox = (xc - half_x, yc - half_y, xc + half_x, yc + half_y)
+    boxes = _nested_boxes(bbox, m, B, nx0, ny0)
+    if boxes is None:
+        return None
+    nu_f = U * chord / Re
+    tau0 = 0.5 + 3 * nu_f / f
+    xb, yb, ds = ellipse_markers(chord / 2, chord / 16, n_markers)
+    body = Body(BODY_FLAP, xb, yb, ds, flap_params(xc, yc, chord, amp_deg, T, U))
+    return Workload(name=name, nx0=nx0, ny0=ny0, n_levels=m, boxes=boxes, tau0=tau0,
+                    bc=(INFLOW, OUTFLOW, SYMMETRY, SYMMETRY), bc_u=((U, 0.0),) + ((0.0, 0.0),) * 3,
+                    body=body, init=uniform_init(1.0, U, 0.0),
+                    meta=dict(U=U, Re=Re, chord=chord, amp_deg=amp_deg, T=T))
+
+
+def batch_sweep(n_cases=64, seed=4606):
+    """64 flapping cases of uneven size; a draw whose refined region would not
+    fit its domain is drawn again (same generator, so the list is fixed)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < n_cases:
+        nx0 = int(rng.integers(256 // 16, 1024 // 16 + 1)) * 16
+        m = int(rng.integers(2, 5))
+        amp = float(rng.uniform(10.0, 64.0))
+        Re = float(math.exp(rng.uniform(math.log(100.0), math.log(1000.0))))
+        nm = int(rng.integers(100, 301))
+        T = float(rng.uniform(2 * math.pi, 3 * math.pi))
+        wl = flapping_case(nx0, m, amp, Re, nm, T, name=f"sweep{len(out):02d}")
+        if wl is not None:
+            out.append(wl)
+    return out
+
+
+def uniform_refined(u=(0.05, 0.02), n0=64, boxes=((1, 2, 2, 6, 6), (2, 6, 6, 10, 10)), m=3,
+                    cf_mode=CF_RESCALE, tau0=0.6):
+    return Workload(name="uniform_refined", nx0=n0, ny0=n0, n_levels=m, boxes=list(boxes), tau0=tau0,
+                    cf_mode=cf_mode, init=uniform_init(1.0, u[0], u[1]))
+
+
+def tgv_band(n=64, u0=0.02, tau=0.8):
+    """Refined band spanning the periodic x axis (no corners)."""
+    wl = tgv(n, tau=tau, u0=u0, n_levels=2, boxes=[(1, 0, 3, 2 * n // 16, 5)], name="tgv_band")
+    return wl
+
+
+def tgv_patch(n=64, u0=0.02, tau=0.8, m=2, cf_mode=CF_HOMOGENEOUS):
+    boxes = [(1, 2, 2, 6, 6)] if m == 2 else [(1, 2, 2, 6, 6), (2, 6, 6, 10, 10)]
+    wl = tgv(n, tau=tau, u0=u0, n_levels=m, boxes=boxes, name=f"tgv_patch{m}")
+    wl.cf_mode = cf_mode
+    return wl
+
+
+def small_cylinder(nx=128, ny=64, D=12.0, n_markers=38, U=0.05, Re=40.0):
+    return cylinder(nx, ny, D=D, centre=(40.0, 32.0), n_markers=n_markers, U=U, Re=Re)
+
+
+def small_refined_flap(Re=100.0, m=3):
+    """A small moving-body case on a refined forest (parity-test size)."""
+    wl = flapping_case(128, m, 40.0, Re, 60, 2.5 * math.pi, name=f"small_flap{m}")
+    assert wl is not None
+    return wl
