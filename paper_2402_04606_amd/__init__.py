@@ -1,0 +1,299 @@
+"""MI355X (gfx950) hot path of SBoTFlow's LBM-IBM method (arXiv 2402.04606).
+
+Thin ctypes binding over ``libsbt.so`` (C ABI declared in ``include/sbt.h``).
+This module only marshals arguments: every step of the time step runs in the
+HIP kernels.  PyTorch provides the device buffer and the stream.  If the
+library is not built, every entry point raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsbt.so")
+
+F64, F32, F16S, BF16S = 0, 1, 2, 3
+STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S}
+STORAGE_BYTES = {F64: 8, F32: 4, F16S: 2, BF16S: 2}
+OPT_GRAPH, OPT_TILE, OPT_XCD_REMAP = 0, 1, 2
+
+ERRORS = {-1: "ARG", -2: "TOPOLOGY", -3: "DEVICE", -4: "NOMEM", -5: "STATE", -6: "NONFINITE",
+          -7: "MARKER_OUTSIDE", -8: "BUFSIZE"}
+
+# Every function include/sbt.h declares.
+ABI_SYMBOLS = [
+    "sbt_plan", "sbt_create", "sbt_destroy", "sbt_level_blocks", "sbt_level_info", "sbt_init_fields",
+    "sbt_set_body", "sbt_step", "sbt_synchronize", "sbt_read_fields", "sbt_read_marker_forces",
+    "sbt_read_force_history", "sbt_diagnostics", "sbt_state_bytes", "sbt_read_state",
+    "sbt_write_state", "sbt_set_option", "sbt_autotune", "sbt_profile", "sbt_updates_per_step",
+    "sbt_last_error",
+]
+
+
+class SbtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sbt error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class Box(C.Structure):
+    _fields_ = [("level", C.c_int32), ("bx0", C.c_int32), ("by0", C.c_int32), ("bx1", C.c_int32),
+                ("by1", C.c_int32)]
+
+
+class CaseDesc(C.Structure):
+    _fields_ = [
+        ("nx0", C.c_int32), ("ny0", C.c_int32), ("block_n", C.c_int32), ("n_levels", C.c_int32),
+        ("refine", C.POINTER(Box)), ("n_refine", C.c_int32),
+        ("tau0", C.c_double), ("rho0", C.c_double),
+        ("bc", C.c_int32 * 4), ("bc_u", (C.c_double * 2) * 4), ("fext", C.c_double * 2),
+        ("storage", C.c_int32), ("cf_mode", C.c_int32), ("mdf_iters", C.c_int32),
+        ("max_markers", C.c_int32), ("history_cap", C.c_int32),
+    ]
+
+
+class Body(C.Structure):
+    _fields_ = [("n", C.c_int32), ("xb", C.POINTER(C.c_double)), ("yb", C.POINTER(C.c_double)),
+                ("ds", C.POINTER(C.c_double)), ("kind", C.c_int32), ("p", C.c_double * 16)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsbt.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = C.CDLL(LIB_PATH)
+        d, i32, i64, vp = C.POINTER(C.c_double), C.c_int32, C.c_int64, C.c_void_p
+        sig = {
+            "sbt_plan": [C.POINTER(CaseDesc), i32, C.POINTER(C.c_size_t)],
+            "sbt_create": [C.POINTER(CaseDesc), i32, vp, C.c_size_t, vp, C.POINTER(vp)],
+            "sbt_destroy": [vp],
+            "sbt_level_blocks": [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
+            "sbt_level_info": [vp, i32, i32, C.POINTER(i64)],
+            "sbt_init_fields": [vp, i32, i32, d, d, d],
+            "sbt_set_body": [vp, i32, C.POINTER(Body)],
+            "sbt_step": [vp, i32],
+            "sbt_synchronize": [vp],
+            "sbt_read_fields": [vp, i32, i32, d, d, d],
+            "sbt_read_marker_forces": [vp, i32, d, d],
+            "sbt_read_force_history": [vp, i32, i32, d, d, C.POINTER(i32)],
+            "sbt_diagnostics": [vp, i32, d],
+            "sbt_state_bytes": [vp, C.POINTER(C.c_size_t)],
+            "sbt_read_state": [vp, vp, C.c_size_t],
+            "sbt_write_state": [vp, vp, C.c_size_t],
+            "sbt_set_option": [vp, i32, i32],
+            "sbt_autotune": [vp, i32, C.c_char_p],
+            "sbt_profile": [vp, i32, d],
+            "sbt_updates_per_step": [vp, C.POINTER(i64)],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int32
+        L.sbt_last_error.argtypes = []
+        L.sbt_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise SbtError(rc, lib().sbt_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_desc(wl, storage=F64, history_cap=1 << 16, max_markers=None):
+    """Marshal a ``workloads.Workload`` into an sbt_case_desc (+ keepalive)."""
+    d = CaseDesc()
+    d.nx0, d.ny0, d.block_n, d.n_levels = wl.nx0, wl.ny0, wl.block_n, wl.n_levels
+    boxes = (Box * max(1, len(wl.boxes)))()
+    for k, b in enumerate(wl.boxes):
+        boxes[k].level, boxes[k].bx0, boxes[k].by0, boxes[k].bx1, boxes[k].by1 = b
+    d.refine = C.cast(boxes, C.POINTER(Box))
+    d.n_refine = len(wl.boxes)
+    d.tau0, d.rho0 = wl.tau0, wl.rho0
+    for e in range(4):
+        d.bc[e] = wl.bc[e]
+        d.bc_u[e][0], d.bc_u[e][1] = wl.bc_u[e]
+    d.fext[0], d.fext[1] = wl.fext
+    d.storage = storage
+    d.cf_mode = wl.cf_mode
+    d.mdf_iters = wl.mdf_iters
+    nm = 0 if wl.body is None else len(wl.body.xb)
+    d.max_markers = nm if max_markers is None else max_markers
+    d.history_cap = history_cap
+    return d, boxes
+
+
+def plan(workloads, storage=F64):
+    descs, keep = _descs(workloads, storage)
+    n = C.c_size_t()
+    _check(lib().sbt_plan(descs, len(workloads), C.byref(n)))
+    return n.value
+
+
+def _descs(workloads, storage, history_cap=1 << 16):
+    arr = (CaseDesc * len(workloads))()
+    keep = []
+    for k, wl in enumerate(workloads):
+        d, b = make_desc(wl, storage, history_cap)
+        arr[k] = d
+        keep.append(b)
+    return arr, keep
+
+
+class Sim:
+    """One context on cuda:0 holding one or more cases (a batch).
+
+    Device memory is a torch uint8 buffer; the stream is torch's current
+    stream unless one is given."""
+
+    def __init__(self, workloads, storage="f64", stream=None, history_cap=1 << 16, init=True):
+        import torch
+        if not isinstance(workloads, (list, tuple)):
+            workloads = [workloads]
+        self.workloads = list(workloads)
+        self.storage = STORAGE[storage] if isinstance(storage, str) else storage
+        L = lib()
+        self._descs, self._keep = _descs(self.workloads, self.storage, history_cap)
+        n = C.c_size_t()
+        _check(L.sbt_plan(self._descs, len(self.workloads), C.byref(n)))
+        self.device_bytes = n.value
+        self._buf = torch.empty(self.device_bytes + 256, dtype=torch.uint8, device="cuda")
+        ptr = self._buf.data_ptr()
+        ptr = (ptr + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(L.sbt_create(self._descs, len(self.workloads), C.c_void_p(ptr), self.device_bytes,
+                            C.c_void_p(self._stream.cuda_stream), C.byref(h)))
+        self._h = h
+        if init:
+            for c, wl in enumerate(self.workloads):
+                if wl.init is not None:
+                    for l in range(wl.n_levels):
+                        nx, ny = self.level_size(c, l)
+                        r, u, v = wl.init(l, nx, ny)
+                        self.init_fields(c, l, r, u, v)
+                if wl.body is not None:
+                    self.set_body(c, wl.body)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().sbt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- geometry ---------------------------------------------------------
+    def level_size(self, c, l):
+        wl = self.workloads[c]
+        return wl.nx0 << l, wl.ny0 << l
+
+    def level_blocks(self, c, l):
+        n = C.c_int32()
+        _check(lib().sbt_level_blocks(self._h, c, l, C.byref(n), None, None))
+        ox, oy = np.zeros(n.value, np.int32), np.zeros(n.value, np.int32)
+        _check(lib().sbt_level_blocks(self._h, c, l, C.byref(n),
+                                      ox.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      oy.ctypes.data_as(C.POINTER(C.c_int32))))
+        return ox, oy
+
+    def level_info(self, c, l):
+        out = (C.c_int64 * 4)()
+        _check(lib().sbt_level_info(self._h, c, l, out))
+        return dict(owned_cells=out[0], blocks=out[1], halo_blocks=out[2], substeps=out[3])
+
+    def updates_per_step(self):
+        u = C.c_int64()
+        _check(lib().sbt_updates_per_step(self._h, C.byref(u)))
+        return u.value
+
+    # ---- state ------------------------------------------------------------
+    def init_fields(self, c, l, rho, ux, uy):
+        nx, ny = self.level_size(c, l)
+        r = np.ascontiguousarray(np.broadcast_to(rho, (ny, nx)), dtype=np.float64)
+        u = np.ascontiguousarray(np.broadcast_to(ux, (ny, nx)), dtype=np.float64)
+        v = np.ascontiguousarray(np.broadcast_to(uy, (ny, nx)), dtype=np.float64)
+        _check(lib().sbt_init_fields(self._h, c, l, _dp(r), _dp(u), _dp(v)))
+
+    def set_body(self, c, body):
+        xb, yb, ds = (np.ascontiguousarray(a, dtype=np.float64) for a in (body.xb, body.yb, body.ds))
+        b = Body()
+        b.n = len(xb)
+        b.xb, b.yb, b.ds = _dp(xb), _dp(yb), _dp(ds)
+        b.kind = body.kind
+        for k, v in enumerate(body.params):
+            b.p[k] = v
+        _check(lib().sbt_set_body(self._h, c, C.byref(b)))
+
+    def step(self, n=1):
+        _check(lib().sbt_step(self._h, int(n)))
+
+    def synchronize(self):
+        _check(lib().sbt_synchronize(self._h))
+
+    # ---- outputs ----------------------------------------------------------
+    def fields(self, c, l):
+        nx, ny = self.level_size(c, l)
+        r, u, v = (np.empty((ny, nx)) for _ in range(3))
+        _check(lib().sbt_read_fields(self._h, c, l, _dp(r), _dp(u), _dp(v)))
+        return r, u, v
+
+    def marker_forces(self, c=0):
+        n = len(self.workloads[c].body.xb)
+        fx, fy = np.empty(n), np.empty(n)
+        _check(lib().sbt_read_marker_forces(self._h, c, _dp(fx), _dp(fy)))
+        return fx, fy
+
+    def force_history(self, c=0, cap=1 << 16):
+        fx, fy = np.empty(cap), np.empty(cap)
+        n = C.c_int32()
+        _check(lib().sbt_read_force_history(self._h, c, cap, _dp(fx), _dp(fy), C.byref(n)))
+        return fx[: n.value].copy(), fy[: n.value].copy()
+
+    def diagnostics(self, c=0):
+        out = np.zeros(3)
+        _check(lib().sbt_diagnostics(self._h, c, _dp(out)))
+        return out
+
+    def state_bytes(self):
+        n = C.c_size_t()
+        _check(lib().sbt_state_bytes(self._h, C.byref(n)))
+        return n.value
+
+    def read_state(self):
+        buf = np.empty(self.state_bytes(), dtype=np.uint8)
+        _check(lib().sbt_read_state(self._h, buf.ctypes.data_as(C.c_void_p), buf.nbytes))
+        return buf
+
+    def write_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().sbt_write_state(self._h, buf.ctypes.data_as(C.c_void_p), buf.nbytes))
+
+    # ---- tuning / measurement ------------------------------------------------
+    def set_option(self, opt, value):
+        _check(lib().sbt_set_option(self._h, opt, int(value)))
+
+    def autotune(self, steps=3, cache_path=None):
+        _check(lib().sbt_autotune(self._h, steps, cache_path.encode() if cache_path else None))
+
+    def profile(self, n):
+        out = np.zeros(6)
+        _check(lib().sbt_profile(self._h, n, _dp(out)))
+        return dict(level_ms=out[0], level_launches=int(out[1]), mdf_ms=out[2],
+                    mdf_launches=int(out[3]), level_bytes=out[4], updates=out[5])

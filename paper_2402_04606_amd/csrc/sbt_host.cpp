@@ -1,0 +1,1317 @@
+// Host engine behind the sbt_* C ABI: block-forest builder and validator,
+// device memory plan, the level schedule of Algorithm 1 (unrolled into a
+// static phase list), HIP graph capture, readout, checkpoint and tuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "sbt.h"
+#include "sbt_internal.h"
+
+using namespace sbt;
+
+namespace {
+
+thread_local std::string g_err;
+
+sbt_status fail(sbt_status code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess) return fail(SBT_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t storage_bytes(int st) { return st == SBT_F64 ? 8 : (st == SBT_F32 ? 4 : 2); }
+
+uint32_t morton(uint32_t x, uint32_t y) {
+  auto spread = [](uint32_t v) {
+    v &= 0xffff;
+    v = (v | (v << 8)) & 0x00ff00ff;
+    v = (v | (v << 4)) & 0x0f0f0f0f;
+    v = (v | (v << 2)) & 0x33333333;
+    v = (v | (v << 1)) & 0x55555555;
+    return v;
+  };
+  return spread(x) | (spread(y) << 1);
+}
+
+const int DCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int DCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+// ---------------------------------------------------------------------------
+// Block forest of one case (Sec. 2.3): levels 0..m-1 of 16x16-cell blocks.
+// region_l = union of the level-l boxes (level 0: the whole domain);
+// own_l = region_l minus the cells covered by region_{l+1}.
+// ---------------------------------------------------------------------------
+struct Forest {
+  int m = 1;
+  bool per_x = false, per_y = false;
+  int nx[kMaxLevels], ny[kMaxLevels], nbx[kMaxLevels], nby[kMaxLevels];
+  std::vector<std::vector<uint8_t>> region;      // [l][by * nbx + bx]
+  std::vector<std::vector<int>> own, ghost;      // block ids (by * nbx + bx), Morton order
+
+  bool reg(int l, int bx, int by) const {
+    if (l >= m) return false;
+    if (bx < 0 || bx >= nbx[l]) {
+      if (!per_x) return false;
+      bx = ((bx % nbx[l]) + nbx[l]) % nbx[l];
+    }
+    if (by < 0 || by >= nby[l]) {
+      if (!per_y) return false;
+      by = ((by % nby[l]) + nby[l]) % nby[l];
+    }
+    return region[l][(size_t)by * nbx[l] + bx] != 0;
+  }
+  bool wrapc(int l, int &x, int &y) const {
+    if (x < 0 || x >= nx[l]) {
+      if (!per_x) return false;
+      x = ((x % nx[l]) + nx[l]) % nx[l];
+    }
+    if (y < 0 || y >= ny[l]) {
+      if (!per_y) return false;
+      y = ((y % ny[l]) + ny[l]) % ny[l];
+    }
+    return true;
+  }
+  bool cell_region(int l, int x, int y) const {
+    if (!wrapc(l, x, y)) return false;
+    return reg(l, x >> 4, y >> 4);
+  }
+  bool cell_hidden(int l, int x, int y) const {
+    if (!wrapc(l, x, y)) return false;
+    return l + 1 < m && reg(l, x >> 4, y >> 4) && reg(l + 1, (2 * x) >> 4, (2 * y) >> 4);
+  }
+  bool cell_own(int l, int x, int y) const {
+    if (!wrapc(l, x, y)) return false;
+    return reg(l, x >> 4, y >> 4) && !(l + 1 < m && reg(l + 1, (2 * x) >> 4, (2 * y) >> 4));
+  }
+  bool block_has_own(int l, int bx, int by) const {
+    if (!reg(l, bx, by)) return false;
+    if (l + 1 >= m) return true;
+    for (int q = 0; q < 4; ++q)
+      if (!reg(l + 1, 2 * bx + (q & 1), 2 * by + (q >> 1))) return true;
+    return false;
+  }
+  bool block_has_hidden(int l, int bx, int by) const {
+    if (!reg(l, bx, by) || l + 1 >= m) return false;
+    for (int q = 0; q < 4; ++q)
+      if (reg(l + 1, 2 * bx + (q & 1), 2 * by + (q >> 1))) return true;
+    return false;
+  }
+};
+
+sbt_status build_forest(const sbt_case_desc &d, Forest &F) {
+  if (d.block_n != kB) return fail(SBT_ERR_ARG, "block_n must be 16");
+  if (d.n_levels < 1 || d.n_levels > kMaxLevels) return fail(SBT_ERR_ARG, "n_levels must be 1..6");
+  if (d.nx0 <= 0 || d.ny0 <= 0 || d.nx0 % kB || d.ny0 % kB)
+    return fail(SBT_ERR_ARG, "nx0, ny0 must be positive multiples of 16");
+  if (!(d.tau0 > 0.5)) return fail(SBT_ERR_ARG, "tau0 must exceed 1/2");
+  if (!(d.rho0 > 0.0)) return fail(SBT_ERR_ARG, "rho0 must be positive");
+  for (int e = 0; e < 4; ++e)
+    if (d.bc[e] < 0 || d.bc[e] > SBT_BC_SYMMETRY) return fail(SBT_ERR_ARG, "bad edge kind");
+  if ((d.bc[0] == SBT_BC_PERIODIC) != (d.bc[1] == SBT_BC_PERIODIC) ||
+      (d.bc[2] == SBT_BC_PERIODIC) != (d.bc[3] == SBT_BC_PERIODIC))
+    return fail(SBT_ERR_ARG, "periodic edges must come in W/E or S/N pairs");
+  if (d.storage < SBT_F64 || d.storage > SBT_BF16S) return fail(SBT_ERR_ARG, "bad storage");
+  if (d.cf_mode != SBT_CF_HOMOGENEOUS && d.cf_mode != SBT_CF_RESCALE) return fail(SBT_ERR_ARG, "bad cf_mode");
+  if (d.max_markers < 0 || d.mdf_iters < 0) return fail(SBT_ERR_ARG, "negative marker count or N_F");
+  if (d.max_markers > 0 && d.history_cap <= 0) return fail(SBT_ERR_ARG, "history_cap must be positive");
+  if (d.n_refine < 0 || (d.n_refine > 0 && !d.refine)) return fail(SBT_ERR_ARG, "bad refine list");
+  F.m = d.n_levels;
+  F.per_x = d.bc[0] == SBT_BC_PERIODIC;
+  F.per_y = d.bc[2] == SBT_BC_PERIODIC;
+  F.region.assign(F.m, {});
+  for (int l = 0; l < F.m; ++l) {
+    F.nx[l] = d.nx0 << l;
+    F.ny[l] = d.ny0 << l;
+    F.nbx[l] = F.nx[l] / kB;
+    F.nby[l] = F.ny[l] / kB;
+    if ((size_t)F.nbx[l] * F.nby[l] > (size_t)1 << 28) return fail(SBT_ERR_ARG, "level too large");
+    F.region[l].assign((size_t)F.nbx[l] * F.nby[l], l == 0 ? 1 : 0);
+  }
+  for (int r = 0; r < d.n_refine; ++r) {
+    const sbt_box &b = d.refine[r];
+    if (b.level < 1 || b.level >= F.m) return fail(SBT_ERR_TOPOLOGY, "refine box level out of range");
+    int l = b.level;
+    if (b.bx0 < 0 || b.by0 < 0 || b.bx1 > F.nbx[l] || b.by1 > F.nby[l] || b.bx0 >= b.bx1 || b.by0 >= b.by1)
+      return fail(SBT_ERR_TOPOLOGY, "refine box outside its level");
+    for (int by = b.by0; by < b.by1; ++by)
+      for (int bx = b.bx0; bx < b.bx1; ++bx) F.region[l][(size_t)by * F.nbx[l] + bx] = 1;
+  }
+  // Nesting and 2:1 balance: every level-l block, widened by one cell of
+  // level l-1 (its two halo layers), lies inside region_{l-1} and inside the
+  // domain unless the axis is periodic.
+  for (int l = 1; l < F.m; ++l) {
+    bool any = false;
+    for (int by = 0; by < F.nby[l]; ++by)
+      for (int bx = 0; bx < F.nbx[l]; ++bx) {
+        if (!F.region[l][(size_t)by * F.nbx[l] + bx]) continue;
+        any = true;
+        int cx0 = bx * 8 - 1, cx1 = bx * 8 + 8, cy0 = by * 8 - 1, cy1 = by * 8 + 8;
+        for (int cy : {cy0, cy1})
+          for (int cx : {cx0, cx1}) {
+            int x = cx, y = cy;
+            if (!F.wrapc(l - 1, x, y))
+              return fail(SBT_ERR_TOPOLOGY, "refined level " + std::to_string(l) + " reaches a non-periodic edge");
+            if (!F.reg(l - 1, x >> 4, y >> 4))
+              return fail(SBT_ERR_TOPOLOGY, "level " + std::to_string(l) + " block not nested in level " +
+                                                std::to_string(l - 1) + " with a one-cell margin");
+          }
+      }
+    if (!any) return fail(SBT_ERR_TOPOLOGY, "level " + std::to_string(l) + " has no block");
+  }
+  // Blocks with owned cells, then halo blocks, Morton order per level.
+  F.own.assign(F.m, {});
+  F.ghost.assign(F.m, {});
+  for (int l = 0; l < F.m; ++l) {
+    std::vector<std::pair<uint32_t, int>> o, g;
+    for (int by = 0; by < F.nby[l]; ++by)
+      for (int bx = 0; bx < F.nbx[l]; ++bx) {
+        int id = by * F.nbx[l] + bx;
+        if (F.block_has_own(l, bx, by)) {
+          o.push_back({morton(bx, by), id});
+        } else if (l > 0 && !F.reg(l, bx, by)) {
+          bool adj = false;
+          for (int dy = -1; dy <= 1 && !adj; ++dy)
+            for (int dx = -1; dx <= 1 && !adj; ++dx)
+              if ((dx || dy) && F.block_has_own(l, bx + dx, by + dy)) adj = true;
+          if (adj) g.push_back({morton(bx, by), id});
+        }
+      }
+    std::sort(o.begin(), o.end());
+    std::sort(g.begin(), g.end());
+    for (auto &p : o) F.own[l].push_back(p.second);
+    for (auto &p : g) F.ghost[l].push_back(p.second);
+  }
+  return SBT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device memory plan (bump allocator, 256-byte aligned).
+// ---------------------------------------------------------------------------
+struct Carver {
+  char *base = nullptr;
+  size_t off = 0;
+  void *take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    void *p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+struct CaseLevelRange {
+  int v = -1;
+  int own0 = 0, own1 = 0, ghost0 = 0, ghost1 = 0;
+};
+
+struct Pool {
+  int n_own = 0, n_ghost = 0;
+  std::vector<BlockMeta> meta;
+  std::vector<uint16_t> codes;
+  BlockMeta *d_meta = nullptr;
+  uint16_t *d_codes = nullptr;
+  void *lat[2] = {nullptr, nullptr};
+  int cur = 0;
+  int total() const { return n_own + n_ghost; }
+};
+
+struct CaseHost {
+  sbt_case_desc d;
+  std::vector<sbt_box> boxes;
+  Forest F;
+  int vshift = 0;
+  std::vector<CaseLevelRange> lr;  // per true level
+  CaseDev dev;                     // host copy (pointers already device)
+  std::vector<int32_t> bmap;
+  bool has_body = false;
+  int n_markers = 0;
+  int win_cap = 0;
+  size_t hist_cap = 0;
+};
+
+enum PhaseType { PH_LEVEL = 0, PH_MDF = 1 };
+struct Phase {
+  int type, v, p;
+};
+
+}  // namespace
+
+struct sbt_ctx {
+  int n_cases = 0, V = 1, storage = 0;
+  std::vector<CaseHost> cs;
+  std::vector<Pool> pools;
+  CaseDev *d_cases = nullptr;
+  int32_t *d_body_cases = nullptr;
+  int n_bodies = 0;
+  int32_t *d_err = nullptr;
+  double *d_stage = nullptr, *d_partial = nullptr, *d_diag = nullptr;
+  size_t stage_blocks = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  bool post = false;               // false: lattices hold the initial pre-collision state
+  int tile = 0, xcd = 1, use_graph = 1;
+  std::vector<Phase> step_phases;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  bool graph_dirty = true;
+  size_t bytes_used = 0;
+  // profiling
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_level, ev_mdf;
+  double prof_bytes = 0.0, prof_updates = 0.0;
+};
+
+namespace {
+
+void build_tables(sbt_ctx &X);
+
+sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Carver &cv) {
+  if (!cases || n_cases <= 0) return fail(SBT_ERR_ARG, "no cases");
+  X.n_cases = n_cases;
+  X.cs.resize(n_cases);
+  X.V = 1;
+  X.storage = cases[0].storage;
+  for (int c = 0; c < n_cases; ++c) {
+    CaseHost &C = X.cs[c];
+    C.d = cases[c];
+    if (C.d.storage != X.storage) return fail(SBT_ERR_ARG, "all cases of a context share one storage");
+    C.boxes.assign(C.d.refine, C.d.refine + std::max(0, C.d.n_refine));
+    C.d.refine = C.boxes.data();
+    sbt_status st = build_forest(C.d, C.F);
+    if (st) return fail(st, "case " + std::to_string(c) + ": " + g_err);
+    if (C.d.cf_mode == SBT_CF_RESCALE)
+      for (int l = 0; l + 1 < C.F.m; ++l) {
+        double tau = 0.5 + (double)(1 << l) * (C.d.tau0 - 0.5);
+        if (std::fabs(tau - 1.0) < 1e-6) return fail(SBT_ERR_ARG, "RESCALE needs tau != 1 on coarse levels");
+      }
+    X.V = std::max(X.V, C.F.m);
+  }
+  const size_t s = storage_bytes(X.storage);
+  // Pools: per virtual level, own blocks of all cases, then halo blocks.
+  X.pools.assign(X.V, Pool());
+  for (int c = 0; c < n_cases; ++c) {
+    CaseHost &C = X.cs[c];
+    C.vshift = X.V - C.F.m;
+    C.lr.assign(C.F.m, CaseLevelRange());
+    for (int l = 0; l < C.F.m; ++l) {
+      int v = l + C.vshift;
+      C.lr[l].v = v;
+      C.lr[l].own0 = X.pools[v].n_own;
+      X.pools[v].n_own += (int)C.F.own[l].size();
+      C.lr[l].own1 = X.pools[v].n_own;
+    }
+  }
+  for (int c = 0; c < n_cases; ++c) {
+    CaseHost &C = X.cs[c];
+    for (int l = 0; l < C.F.m; ++l) {
+      Pool &P = X.pools[C.lr[l].v];
+      C.lr[l].ghost0 = P.n_own + P.n_ghost;
+      P.n_ghost += (int)C.F.ghost[l].size();
+      C.lr[l].ghost1 = P.n_own + P.n_ghost;
+    }
+  }
+  // Per-case IBM dimensions (host).
+  for (int c = 0; c < n_cases; ++c) {
+    CaseHost &C = X.cs[c];
+    CaseDev &D = C.dev;
+    std::memset(&D, 0, sizeof(D));
+    D.body_kind = -1;
+    C.has_body = C.d.max_markers > 0;
+    if (!C.has_body) continue;
+    const int lf = C.F.m - 1;
+    // finest-level block map over the bounding box of region_{m-1}
+    int x0 = C.F.nbx[lf], y0 = C.F.nby[lf], x1 = -1, y1 = -1;
+    for (int id : C.F.own[lf]) {
+      int bx = id % C.F.nbx[lf], by = id / C.F.nbx[lf];
+      x0 = std::min(x0, bx); y0 = std::min(y0, by); x1 = std::max(x1, bx); y1 = std::max(y1, by);
+    }
+    D.bm_x0 = x0; D.bm_y0 = y0; D.bm_w = x1 - x0 + 1; D.bm_h = y1 - y0 + 1;
+    size_t area = (size_t)D.bm_w * D.bm_h * kCells;
+    size_t side = (size_t)C.d.max_markers + 8;
+    C.win_cap = (int)std::min(area, side * side);
+    C.hist_cap = (size_t)C.d.history_cap;
+  }
+  build_tables(X);
+  // Device memory plan.
+  size_t max_blocks = 1;
+  for (auto &P : X.pools) {
+    P.d_meta = (BlockMeta *)cv.take(sizeof(BlockMeta) * P.total());
+    P.d_codes = (uint16_t *)cv.take(sizeof(uint16_t) * std::max<size_t>(1, P.codes.size()));
+    P.lat[0] = cv.take(s * kQ * kCells * (size_t)P.total());
+    P.lat[1] = cv.take(s * kQ * kCells * (size_t)P.total());
+  }
+  for (int c = 0; c < n_cases; ++c)
+    for (int l = 0; l < X.cs[c].F.m; ++l)
+      max_blocks = std::max(max_blocks, (size_t)(X.cs[c].lr[l].own1 - X.cs[c].lr[l].own0));
+  X.stage_blocks = max_blocks;
+  X.d_stage = (double *)cv.take(sizeof(double) * 3 * kCells * max_blocks);
+  X.d_partial = (double *)cv.take(sizeof(double) * 3 * max_blocks);
+  X.d_diag = (double *)cv.take(sizeof(double) * 4);
+  X.d_err = (int32_t *)cv.take(sizeof(int32_t) * 4);
+  X.d_cases = (CaseDev *)cv.take(sizeof(CaseDev) * n_cases);
+  X.d_body_cases = (int32_t *)cv.take(sizeof(int32_t) * n_cases);
+  for (int c = 0; c < n_cases; ++c) {
+    CaseHost &C = X.cs[c];
+    CaseDev &D = C.dev;
+    if (!C.has_body) continue;
+    const size_t N = (size_t)C.d.max_markers;
+    D.xb = (double *)cv.take(sizeof(double) * N);
+    D.yb = (double *)cv.take(sizeof(double) * N);
+    D.ds = (double *)cv.take(sizeof(double) * N);
+    D.X = (double *)cv.take(sizeof(double) * N);
+    D.Y = (double *)cv.take(sizeof(double) * N);
+    D.udx = (double *)cv.take(sizeof(double) * N);
+    D.udy = (double *)cv.take(sizeof(double) * N);
+    D.dFx = (double *)cv.take(sizeof(double) * N);
+    D.dFy = (double *)cv.take(sizeof(double) * N);
+    D.ftot = (double *)cv.take(sizeof(double) * 4 * N);
+    D.hist = (double *)cv.take(sizeof(double) * 2 * C.hist_cap);
+    D.kcount = (int64_t *)cv.take(sizeof(int64_t));
+    D.win = (IbmWindow *)cv.take(sizeof(IbmWindow));
+    D.wF = (double *)cv.take(sizeof(double) * 2 * C.win_cap);
+    D.wRho = (double *)cv.take(sizeof(double) * C.win_cap);
+    D.wU = (double *)cv.take(sizeof(double) * 2 * C.win_cap);
+    D.wCnt = (int32_t *)cv.take(sizeof(int32_t) * C.win_cap);
+    D.wList = (int32_t *)cv.take(sizeof(int32_t) * kMaxContrib * (size_t)C.win_cap);
+    D.bmap = (const int32_t *)cv.take(sizeof(int32_t) * (size_t)D.bm_w * D.bm_h);
+  }
+  return SBT_OK;
+}
+
+// Fill block metadata, cell codes and case parameters (host side).
+void build_tables(sbt_ctx &X) {
+  for (auto &P : X.pools) {
+    P.meta.assign(P.total(), BlockMeta());
+    P.codes.clear();
+  }
+  for (int c = 0; c < X.n_cases; ++c) {
+    CaseHost &C = X.cs[c];
+    const Forest &F = C.F;
+    // dense maps block id -> pool index, per level
+    std::vector<std::vector<int32_t>> map(F.m);
+    for (int l = 0; l < F.m; ++l) {
+      map[l].assign((size_t)F.nbx[l] * F.nby[l], -1);
+      for (size_t k = 0; k < F.own[l].size(); ++k) map[l][F.own[l][k]] = C.lr[l].own0 + (int)k;
+      for (size_t k = 0; k < F.ghost[l].size(); ++k) map[l][F.ghost[l][k]] = C.lr[l].ghost0 + (int)k;
+    }
+    auto lookup = [&](int l, int bx, int by) -> int32_t {
+      if (bx < 0 || bx >= F.nbx[l]) {
+        if (!F.per_x) return -1;
+        bx = ((bx % F.nbx[l]) + F.nbx[l]) % F.nbx[l];
+      }
+      if (by < 0 || by >= F.nby[l]) {
+        if (!F.per_y) return -1;
+        by = ((by % F.nby[l]) + F.nby[l]) % F.nby[l];
+      }
+      return map[l][(size_t)by * F.nbx[l] + bx];
+    };
+    for (int l = 0; l < F.m; ++l) {
+      Pool &P = X.pools[C.lr[l].v];
+      for (int pass = 0; pass < 2; ++pass) {
+        const std::vector<int> &ids = pass == 0 ? F.own[l] : F.ghost[l];
+        int base = pass == 0 ? C.lr[l].own0 : C.lr[l].ghost0;
+        for (size_t k = 0; k < ids.size(); ++k) {
+          int id = ids[k], bx = id % F.nbx[l], by = id / F.nbx[l];
+          BlockMeta &M = P.meta[base + k];
+          M.ox = bx * kB;
+          M.oy = by * kB;
+          for (int d = 1; d < 9; ++d) M.nbr[d - 1] = lookup(l, bx + DCX[d], by + DCY[d]);
+          for (int q = 0; q < 4; ++q)
+            M.child[q] = (pass == 0 && l + 1 < F.m) ? lookup(l + 1, 2 * bx + (q & 1), 2 * by + (q >> 1)) : -1;
+          M.case_id = c;
+          M.level = l;
+          M.flags = pass == 1 ? BF_GHOST : 0;
+          M.code = -1;
+          if (pass == 0 && l == 0) {
+            if ((!F.per_x && (bx == 0 || bx == F.nbx[0] - 1)) || (!F.per_y && (by == 0 || by == F.nby[0] - 1)))
+              M.flags |= BF_EDGE;
+          }
+          if (pass == 0 && l == F.m - 1 && C.has_body) M.flags |= BF_IBM;
+          // per-cell codes where a hidden cell is within reach, and in halo blocks
+          bool need = pass == 1;
+          if (pass == 0 && l + 1 < F.m)
+            for (int dy = -1; dy <= 1 && !need; ++dy)
+              for (int dx = -1; dx <= 1 && !need; ++dx)
+                if (F.block_has_hidden(l, bx + dx, by + dy)) need = true;
+          if (!need) continue;
+          std::vector<uint16_t> code(kCells, 0);
+          bool any = false;
+          for (int cell = 0; cell < kCells; ++cell) {
+            int gx = M.ox + (cell & 15), gy = M.oy + (cell >> 4);
+            uint16_t cc = 0;
+            if (pass == 0) {
+              if (F.cell_hidden(l, gx, gy)) cc |= CC_HIDDEN;
+              for (int i = 1; i < 9; ++i)
+                if (F.cell_hidden(l, gx - DCX[i], gy - DCY[i])) cc |= (uint16_t)(1u << i);
+              if (!(cc & CC_HIDDEN) && (cc & CC_HSRC)) cc |= CC_IFACE;
+            } else {
+              for (int dy = -2; dy <= 2 && !(cc & CC_BAND); ++dy)
+                for (int dx = -2; dx <= 2; ++dx)
+                  if (F.cell_own(l, gx + dx, gy + dy)) {
+                    cc |= CC_BAND;
+                    break;
+                  }
+            }
+            code[cell] = cc;
+            any |= cc != 0;
+          }
+          if (!any && pass == 0) continue;
+          M.flags |= BF_CODES;
+          M.code = (int32_t)(P.codes.size() / kCells);
+          P.codes.insert(P.codes.end(), code.begin(), code.end());
+        }
+      }
+    }
+    if (C.has_body) {
+      const int lf = F.m - 1;
+      C.bmap.assign((size_t)C.dev.bm_w * C.dev.bm_h, -1);
+      for (size_t k = 0; k < F.own[lf].size(); ++k) {
+        int id = F.own[lf][k], bx = id % F.nbx[lf] - C.dev.bm_x0, by = id / F.nbx[lf] - C.dev.bm_y0;
+        C.bmap[(size_t)by * C.dev.bm_w + bx] = C.lr[lf].own0 + (int)k;
+      }
+    }
+    // case parameters (the arithmetic below mirrors the relations stated in
+    // the header: tau_l, body force per level, interface factors)
+    CaseDev &D = C.dev;
+    const sbt_case_desc &d = C.d;
+    for (int l = 0; l < F.m; ++l) {
+      double tau = 0.5 + (double)(1 << l) * (d.tau0 - 0.5);
+      D.tau[l] = tau;
+      D.pre[l] = 1.0 - 0.5 / tau;
+      D.fx[l] = d.fext[0] / (double)(1 << l);
+      D.fy[l] = d.fext[1] / (double)(1 << l);
+      D.omega_f[l] = (float)(1.0 / tau);
+      D.pre_f[l] = (float)D.pre[l];
+      D.fx_f[l] = (float)D.fx[l];
+      D.fy_f[l] = (float)D.fy[l];
+      D.nx[l] = F.nx[l];
+      D.ny[l] = F.ny[l];
+    }
+    for (int l = 0; l < F.m; ++l) {
+      if (l > 0) D.s_cf[l] = (D.tau[l] - 1.0) / (2.0 * (D.tau[l - 1] - 1.0));
+      if (l + 1 < F.m) D.s_fc[l] = 2.0 * D.tau[l] / D.tau[l + 1];
+      D.s_cf_f[l] = (float)D.s_cf[l];
+      D.s_fc_f[l] = (float)D.s_fc[l];
+    }
+    D.rho0 = d.rho0;
+    for (int e = 0; e < 4; ++e) {
+      D.bc[e] = d.bc[e];
+      D.bcu[e][0] = d.bc_u[e][0];
+      D.bcu[e][1] = d.bc_u[e][1];
+    }
+    D.per_x = F.per_x;
+    D.per_y = F.per_y;
+    D.cf_mode = d.cf_mode;
+    D.n_levels = F.m;
+    D.mdf_iters = d.mdf_iters;
+    D.hist_cap = (int32_t)C.hist_cap;
+    D.win_cap = C.win_cap;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Schedule: the recursion of Algorithm 1 unrolled over virtual levels.  With
+// the pull scheme a level launch streams the previous collision's output and
+// performs the next collision, so the launches follow the order in which the
+// paper's StreamingStep calls occur: streams(v) = streams(v+1), S_v(first),
+// streams(v+1), S_v(second); the finest level's launches are each preceded by
+// the IBM (UpdateVelocity) launch.
+// ---------------------------------------------------------------------------
+void rec_phases(int v, int V, std::vector<Phase> &out) {
+  if (v == V - 1) {
+    for (int p = 1; p <= 2; ++p) {
+      out.push_back({PH_MDF, v, p});
+      out.push_back({PH_LEVEL, v, p});
+    }
+    return;
+  }
+  rec_phases(v + 1, V, out);
+  out.push_back({PH_LEVEL, v, 1});
+  rec_phases(v + 1, V, out);
+  out.push_back({PH_LEVEL, v, 2});
+}
+
+std::vector<Phase> step_phases(int V) {
+  std::vector<Phase> out;
+  if (V == 1) {
+    out.push_back({PH_MDF, 0, 1});
+    out.push_back({PH_LEVEL, 0, 1});
+    return out;
+  }
+  rec_phases(1, V, out);
+  out.push_back({PH_LEVEL, 0, 1});
+  return out;
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
+sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
+  Pool &P = X.pools[v];
+  LevelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.meta = P.d_meta;
+  a.codes = P.d_codes;
+  a.src = P.lat[P.cur];
+  a.dst = P.lat[1 - P.cur];
+  if (v + 1 < X.V) {
+    Pool &Q = X.pools[v + 1];
+    a.fmeta = Q.d_meta;
+    a.fcodes = Q.d_codes;
+    a.fprev = Q.lat[1 - Q.cur];
+    a.fcur = Q.lat[Q.cur];
+  }
+  a.cases = X.d_cases;
+  a.b0 = 0;
+  a.n_blocks = (mode == 0 && p == 1) ? P.total() : P.n_own;
+  a.mode = mode;
+  a.xcd_remap = X.xcd;
+  a.err = X.d_err;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (X.profiling) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+  }
+  HIPCHK(sbt_launch_level(X.storage, X.tile, &a, s));
+  if (X.profiling) {
+    HIPCHK(hipEventRecord(e1, s));
+    X.ev_level.push_back({e0, e1});
+  }
+  P.cur = 1 - P.cur;
+  return SBT_OK;
+}
+
+sbt_status launch_mdf(sbt_ctx &X, bool first, hipStream_t s) {
+  if (X.n_bodies == 0) return SBT_OK;
+  Pool &P = X.pools[X.V - 1];
+  MdfArgs a;
+  a.meta = P.d_meta;
+  a.src = P.lat[P.cur];
+  a.cases = X.d_cases;
+  a.body_cases = X.d_body_cases;
+  a.first = first ? 1 : 0;
+  a.err = X.d_err;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (X.profiling) {
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+  }
+  HIPCHK(sbt_launch_mdf(X.storage, &a, X.n_bodies, s));
+  if (X.profiling) {
+    HIPCHK(hipEventRecord(e1, s));
+    X.ev_mdf.push_back({e0, e1});
+  }
+  return SBT_OK;
+}
+
+// Collide once on every level from the initial pre-collision state (the
+// first CollisionStep of every level), finest first so that each coarse
+// level explodes into its finer level's current lattice.
+sbt_status run_prologue(sbt_ctx &X, hipStream_t s) {
+  for (int v = X.V - 1; v >= 0; --v) {
+    if (v == X.V - 1) {
+      sbt_status st = launch_mdf(X, true, s);
+      if (st) return st;
+    }
+    sbt_status st = launch_level(X, v, 1, MODE_LOCAL, s);
+    if (st) return st;
+  }
+  X.post = true;
+  return SBT_OK;
+}
+
+sbt_status run_step_eager(sbt_ctx &X, hipStream_t s) {
+  for (const Phase &ph : X.step_phases) {
+    sbt_status st = ph.type == PH_MDF ? launch_mdf(X, false, s) : launch_level(X, ph.v, ph.p, 0, s);
+    if (st) return st;
+  }
+  return SBT_OK;
+}
+
+void destroy_graphs(sbt_ctx &X) {
+  for (auto &g : X.graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
+  X.graph_dirty = true;
+}
+
+sbt_status capture_graph(sbt_ctx &X, int parity) {
+  if (!X.cap_stream) HIPCHK(hipStreamCreateWithFlags(&X.cap_stream, hipStreamNonBlocking));
+  std::vector<int> saved(X.V);
+  for (int v = 0; v < X.V; ++v) saved[v] = X.pools[v].cur;
+  hipGraph_t g = nullptr;
+  HIPCHK(hipStreamBeginCapture(X.cap_stream, hipStreamCaptureModeThreadLocal));
+  sbt_status st = run_step_eager(X, X.cap_stream);
+  hipError_t e = hipStreamEndCapture(X.cap_stream, &g);
+  for (int v = 0; v < X.V; ++v) X.pools[v].cur = saved[v];
+  if (st) return st;
+  if (e != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&X.graph[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return SBT_OK;
+}
+
+sbt_status check_case(sbt_ctx *ctx, int32_t c) {
+  if (!ctx) return fail(SBT_ERR_ARG, "null context");
+  if (c < 0 || c >= ctx->n_cases) return fail(SBT_ERR_ARG, "case index out of range");
+  return SBT_OK;
+}
+
+sbt_status check_level(sbt_ctx *ctx, int32_t c, int32_t l) {
+  sbt_status st = check_case(ctx, c);
+  if (st) return st;
+  if (l < 0 || l >= ctx->cs[c].F.m) return fail(SBT_ERR_ARG, "level out of range");
+  return SBT_OK;
+}
+
+// Gather a dense level field into per-block order [n][3][256] (host).
+void dense_to_blocks(const Forest &F, int l, const double *r, const double *u, const double *v,
+                     std::vector<double> &out) {
+  const auto &ids = F.own[l];
+  out.assign(ids.size() * 3 * kCells, 0.0);
+  for (size_t k = 0; k < ids.size(); ++k) {
+    int bx = ids[k] % F.nbx[l], by = ids[k] / F.nbx[l];
+    for (int cell = 0; cell < kCells; ++cell) {
+      size_t g = (size_t)(by * kB + (cell >> 4)) * F.nx[l] + bx * kB + (cell & 15);
+      out[(k * 3 + 0) * kCells + cell] = r[g];
+      out[(k * 3 + 1) * kCells + cell] = u[g];
+      out[(k * 3 + 2) * kCells + cell] = v[g];
+    }
+  }
+}
+
+sbt_status readout_level(sbt_ctx &X, int c, int l, hipStream_t s) {
+  CaseHost &C = X.cs[c];
+  int v = C.lr[l].v;
+  Pool &P = X.pools[v];
+  LevelArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.meta = P.d_meta;
+  a.codes = P.d_codes;
+  // after a step the state to read is the one the last launch streamed from
+  a.src = X.post ? P.lat[1 - P.cur] : P.lat[P.cur];
+  if (v + 1 < X.V) {
+    Pool &Q = X.pools[v + 1];
+    a.fmeta = Q.d_meta;
+    a.fcodes = Q.d_codes;
+    a.fprev = Q.lat[1 - Q.cur];
+    a.fcur = Q.lat[Q.cur];
+  }
+  a.cases = X.d_cases;
+  a.b0 = C.lr[l].own0;
+  a.n_blocks = C.lr[l].own1 - C.lr[l].own0;
+  a.mode = MODE_READOUT | (X.post ? 0 : MODE_LOCAL);
+  a.xcd_remap = 0;
+  a.out = X.d_stage;
+  a.partial = X.d_partial;
+  a.err = X.d_err;
+  HIPCHK(sbt_launch_level(X.storage, 0, &a, s));
+  return SBT_OK;
+}
+
+sbt_status upload_case(sbt_ctx &X, int c) {
+  HIPCHK(hipMemcpyAsync(X.d_cases + c, &X.cs[c].dev, sizeof(CaseDev), hipMemcpyHostToDevice, X.stream));
+  return SBT_OK;
+}
+
+// Reset counters and device IBM state; lattices keep their contents.
+sbt_status reset_counters(sbt_ctx &X) {
+  for (auto &C : X.cs) {
+    if (!C.has_body) continue;
+    HIPCHK(hipMemsetAsync(C.dev.kcount, 0, sizeof(int64_t), X.stream));
+    HIPCHK(hipMemsetAsync(C.dev.win, 0, sizeof(IbmWindow), X.stream));
+  }
+  X.post = false;
+  for (auto &P : X.pools) P.cur = 0;
+  destroy_graphs(X);
+  return SBT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *sbt_last_error(void) { return g_err.c_str(); }
+
+sbt_status sbt_plan(const sbt_case_desc *cases, int32_t n_cases, size_t *device_bytes) {
+  if (!device_bytes) return fail(SBT_ERR_ARG, "null output");
+  sbt_ctx X;
+  Carver cv;
+  sbt_status st = plan_ctx(cases, n_cases, X, cv);
+  if (st) return st;
+  *device_bytes = cv.off + 256;
+  return SBT_OK;
+}
+
+sbt_status sbt_create(const sbt_case_desc *cases, int32_t n_cases, void *device_buf, size_t bytes,
+                      void *hip_stream, sbt_ctx **out) {
+  if (!out) return fail(SBT_ERR_ARG, "null output");
+  *out = nullptr;
+  if (!device_buf) return fail(SBT_ERR_ARG, "null device buffer");
+  if (((uintptr_t)device_buf) & 255) return fail(SBT_ERR_ARG, "device buffer must be 256-byte aligned");
+  sbt_ctx *X = new sbt_ctx();
+  Carver cv;
+  cv.base = (char *)device_buf;
+  sbt_status st = plan_ctx(cases, n_cases, *X, cv);
+  if (st) {
+    delete X;
+    return st;
+  }
+  if (cv.off > bytes) {
+    delete X;
+    return fail(SBT_ERR_NOMEM, "device buffer smaller than sbt_plan reported");
+  }
+  X->bytes_used = cv.off;
+  X->stream = (hipStream_t)hip_stream;
+  auto cleanup_fail = [&](sbt_status s) {
+    delete X;
+    return s;
+  };
+  std::vector<int32_t> bodies;
+  for (int c = 0; c < X->n_cases; ++c)
+    if (X->cs[c].has_body) bodies.push_back(c);
+  X->n_bodies = 0;  // bodies become active with sbt_set_body
+  hipStream_t s = X->stream;
+  for (auto &P : X->pools) {
+    if (hipMemcpyAsync(P.d_meta, P.meta.data(), sizeof(BlockMeta) * P.meta.size(), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+      return cleanup_fail(fail(SBT_ERR_DEVICE, "meta upload"));
+    if (!P.codes.empty() &&
+        hipMemcpyAsync(P.d_codes, P.codes.data(), sizeof(uint16_t) * P.codes.size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+      return cleanup_fail(fail(SBT_ERR_DEVICE, "code upload"));
+    size_t n = (size_t)P.total() * kQ * kCells;
+    if (sbt_launch_fill_nan(P.lat[0], n, X->storage, s) != hipSuccess ||
+        sbt_launch_fill_nan(P.lat[1], n, X->storage, s) != hipSuccess)
+      return cleanup_fail(fail(SBT_ERR_DEVICE, "lattice fill"));
+  }
+  for (int c = 0; c < X->n_cases; ++c) {
+    CaseHost &C = X->cs[c];
+    if (C.has_body) {
+      if (hipMemcpyAsync((void *)C.dev.bmap, C.bmap.data(), sizeof(int32_t) * C.bmap.size(), hipMemcpyHostToDevice,
+                         s) != hipSuccess)
+        return cleanup_fail(fail(SBT_ERR_DEVICE, "block map upload"));
+    }
+    if (upload_case(*X, c)) return cleanup_fail(SBT_ERR_DEVICE);
+  }
+  if (hipMemsetAsync(X->d_err, 0, sizeof(int32_t) * 4, s) != hipSuccess)
+    return cleanup_fail(fail(SBT_ERR_DEVICE, "memset"));
+  if (reset_counters(*X)) return cleanup_fail(SBT_ERR_DEVICE);
+  for (auto &P : X->pools) {
+    if (sbt_launch_init(X->storage, P.d_meta, P.d_codes, X->d_cases, P.lat[0], 0, P.n_own, nullptr, s) !=
+        hipSuccess)
+      return cleanup_fail(fail(SBT_ERR_DEVICE, "init"));
+  }
+  X->step_phases = step_phases(X->V);
+  if (hipStreamSynchronize(s) != hipSuccess) return cleanup_fail(fail(SBT_ERR_DEVICE, "create sync"));
+  *out = X;
+  return SBT_OK;
+}
+
+sbt_status sbt_destroy(sbt_ctx *ctx) {
+  if (!ctx) return SBT_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  destroy_graphs(*ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  delete ctx;
+  return SBT_OK;
+}
+
+sbt_status sbt_level_blocks(sbt_ctx *ctx, int32_t c, int32_t level, int32_t *n_blocks, int32_t *ox,
+                            int32_t *oy) {
+  sbt_status st = check_level(ctx, c, level);
+  if (st) return st;
+  const Forest &F = ctx->cs[c].F;
+  const auto &ids = F.own[level];
+  if (n_blocks) *n_blocks = (int32_t)ids.size();
+  for (size_t k = 0; k < ids.size(); ++k) {
+    if (ox) ox[k] = (ids[k] % F.nbx[level]) * kB;
+    if (oy) oy[k] = (ids[k] / F.nbx[level]) * kB;
+  }
+  return SBT_OK;
+}
+
+sbt_status sbt_level_info(sbt_ctx *ctx, int32_t c, int32_t level, int64_t out[4]) {
+  sbt_status st = check_level(ctx, c, level);
+  if (st) return st;
+  const Forest &F = ctx->cs[c].F;
+  int64_t owned = 0;
+  for (int id : F.own[level]) {
+    int bx = id % F.nbx[level], by = id / F.nbx[level];
+    owned += kCells;
+    if (level + 1 < F.m)
+      for (int q = 0; q < 4; ++q)
+        if (F.reg(level + 1, 2 * bx + (q & 1), 2 * by + (q >> 1))) owned -= kCells / 4;
+  }
+  out[0] = owned;
+  out[1] = (int64_t)F.own[level].size();
+  out[2] = (int64_t)F.ghost[level].size();
+  out[3] = (int64_t)1 << (level + ctx->cs[c].vshift);
+  return SBT_OK;
+}
+
+sbt_status sbt_updates_per_step(sbt_ctx *ctx, int64_t *updates) {
+  if (!ctx || !updates) return fail(SBT_ERR_ARG, "null argument");
+  int64_t u = 0;
+  for (int c = 0; c < ctx->n_cases; ++c)
+    for (int l = 0; l < ctx->cs[c].F.m; ++l) {
+      int64_t info[4];
+      sbt_level_info(ctx, c, l, info);
+      u += info[0] * info[3];
+    }
+  *updates = u;
+  return SBT_OK;
+}
+
+sbt_status sbt_init_fields(sbt_ctx *ctx, int32_t c, int32_t level, const double *rho, const double *ux,
+                           const double *uy) {
+  sbt_status st = check_level(ctx, c, level);
+  if (st) return st;
+  if (!rho || !ux || !uy) return fail(SBT_ERR_ARG, "null field");
+  sbt_ctx &X = *ctx;
+  CaseHost &C = X.cs[c];
+  HIPCHK(hipStreamSynchronize(X.stream));
+  // Going back to the initial state: the pre-collision populations live in
+  // lattice 0 of every pool.  Other levels keep their initial values only if
+  // the context has not stepped; after stepping, re-initialise them too.
+  if (X.post) {  // back to the initial state: every level at rest, counters cleared
+    for (auto &P : X.pools) {
+      size_t n = (size_t)P.total() * kQ * kCells;
+      HIPCHK(sbt_launch_fill_nan(P.lat[0], n, X.storage, X.stream));
+      HIPCHK(sbt_launch_fill_nan(P.lat[1], n, X.storage, X.stream));
+      HIPCHK(sbt_launch_init(X.storage, P.d_meta, P.d_codes, X.d_cases, P.lat[0], 0, P.n_own, nullptr, X.stream));
+    }
+    if (reset_counters(X)) return SBT_ERR_DEVICE;
+  }
+  std::vector<double> host;
+  dense_to_blocks(C.F, level, rho, ux, uy, host);
+  size_t n = C.F.own[level].size();
+  for (size_t k0 = 0; k0 < n; k0 += X.stage_blocks) {
+    size_t k1 = std::min(n, k0 + X.stage_blocks);
+    HIPCHK(hipMemcpyAsync(X.d_stage, host.data() + k0 * 3 * kCells, sizeof(double) * 3 * kCells * (k1 - k0),
+                          hipMemcpyHostToDevice, X.stream));
+    Pool &P = X.pools[C.lr[level].v];
+    HIPCHK(sbt_launch_init(X.storage, P.d_meta, P.d_codes, X.d_cases, P.lat[0], C.lr[level].own0 + (int)k0,
+                           (int)(k1 - k0), X.d_stage, X.stream));
+    HIPCHK(hipStreamSynchronize(X.stream));
+  }
+  return SBT_OK;
+}
+
+sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
+  sbt_status st = check_case(ctx, c);
+  if (st) return st;
+  sbt_ctx &X = *ctx;
+  CaseHost &C = X.cs[c];
+  if (X.post) return fail(SBT_ERR_STATE, "bodies can only be set before the first step");
+  if (!C.has_body) return fail(SBT_ERR_ARG, "case was created with max_markers = 0");
+  if (!body || body->n <= 0 || body->n > C.d.max_markers) return fail(SBT_ERR_ARG, "marker count out of range");
+  if (!body->xb || !body->yb || !body->ds) return fail(SBT_ERR_ARG, "null marker arrays");
+  if (body->kind != SBT_BODY_FIXED && body->kind != SBT_BODY_FLAP) return fail(SBT_ERR_ARG, "bad body kind");
+  if (body->kind == SBT_BODY_FLAP && (body->p[6] == 0.0 || body->p[9] == 0.0))
+    return fail(SBT_ERR_ARG, "flap period and chord must be nonzero");
+  HIPCHK(hipStreamSynchronize(X.stream));
+  const size_t N = (size_t)body->n;
+  HIPCHK(hipMemcpy((void *)C.dev.xb, body->xb, sizeof(double) * N, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy((void *)C.dev.yb, body->yb, sizeof(double) * N, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy((void *)C.dev.ds, body->ds, sizeof(double) * N, hipMemcpyHostToDevice));
+  C.dev.body_kind = body->kind;
+  C.dev.n_markers = body->n;
+  std::memcpy(C.dev.bp, body->p, sizeof(body->p));
+  C.n_markers = body->n;
+  HIPCHK(hipMemcpy(X.d_cases + c, &C.dev, sizeof(CaseDev), hipMemcpyHostToDevice));
+  std::vector<int32_t> bc;
+  for (int k = 0; k < X.n_cases; ++k)
+    if (X.cs[k].has_body && X.cs[k].n_markers > 0) bc.push_back(k);
+  X.n_bodies = (int)bc.size();
+  if (!bc.empty()) HIPCHK(hipMemcpy(X.d_body_cases, bc.data(), sizeof(int32_t) * bc.size(), hipMemcpyHostToDevice));
+  destroy_graphs(X);
+  return SBT_OK;
+}
+
+sbt_status sbt_step(sbt_ctx *ctx, int32_t n) {
+  if (!ctx) return fail(SBT_ERR_ARG, "null context");
+  if (n < 0) return fail(SBT_ERR_ARG, "negative step count");
+  sbt_ctx &X = *ctx;
+  if (n == 0) return SBT_OK;
+  if (!X.post) {
+    sbt_status st = run_prologue(X, X.stream);
+    if (st) return st;
+  }
+  for (int t = 0; t < n; ++t) {
+    if (X.use_graph && !X.profiling) {
+      int par = X.pools[0].cur;
+      if (!X.graph[par]) {
+        sbt_status st = capture_graph(X, par);
+        if (st) return st;
+      }
+      HIPCHK(hipGraphLaunch(X.graph[par], X.stream));
+      // the graph performs the same lattice flips as the eager list
+      for (const Phase &ph : X.step_phases)
+        if (ph.type == PH_LEVEL) X.pools[ph.v].cur ^= 1;
+    } else {
+      sbt_status st = run_step_eager(X, X.stream);
+      if (st) return st;
+    }
+  }
+  return SBT_OK;
+}
+
+sbt_status sbt_synchronize(sbt_ctx *ctx) {
+  if (!ctx) return fail(SBT_ERR_ARG, "null context");
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  int32_t err[4];
+  HIPCHK(hipMemcpy(err, ctx->d_err, sizeof(err), hipMemcpyDeviceToHost));
+  if (err[0]) {
+    HIPCHK(hipMemset(ctx->d_err, 0, sizeof(err)));
+    if (err[0] & ERR_NONFINITE) return fail(SBT_ERR_NONFINITE, "a density became NaN or Inf");
+    if (err[0] & ERR_MARKER) return fail(SBT_ERR_MARKER_OUTSIDE, "a marker stencil left the finest owned cells");
+    if (err[0] & ERR_CONTRIB) return fail(SBT_ERR_MARKER_OUTSIDE, "more than 32 markers cover one cell");
+    if (err[0] & ERR_WINDOW) return fail(SBT_ERR_MARKER_OUTSIDE, "IBM window larger than planned");
+  }
+  return SBT_OK;
+}
+
+sbt_status sbt_read_fields(sbt_ctx *ctx, int32_t c, int32_t level, double *rho, double *ux, double *uy) {
+  sbt_status st = check_level(ctx, c, level);
+  if (st) return st;
+  if (!rho || !ux || !uy) return fail(SBT_ERR_ARG, "null field");
+  sbt_ctx &X = *ctx;
+  CaseHost &C = X.cs[c];
+  const Forest &F = C.F;
+  size_t ncell = (size_t)F.nx[level] * F.ny[level];
+  for (size_t q = 0; q < ncell; ++q) rho[q] = ux[q] = uy[q] = std::nan("");
+  st = readout_level(X, c, level, X.stream);
+  if (st) return st;
+  size_t n = F.own[level].size();
+  std::vector<double> host(n * 3 * kCells);
+  HIPCHK(hipMemcpyAsync(host.data(), X.d_stage, sizeof(double) * host.size(), hipMemcpyDeviceToHost, X.stream));
+  HIPCHK(hipStreamSynchronize(X.stream));
+  for (size_t k = 0; k < n; ++k) {
+    int bx = F.own[level][k] % F.nbx[level], by = F.own[level][k] / F.nbx[level];
+    for (int cell = 0; cell < kCells; ++cell) {
+      size_t g = (size_t)(by * kB + (cell >> 4)) * F.nx[level] + bx * kB + (cell & 15);
+      rho[g] = host[(k * 3 + 0) * kCells + cell];
+      ux[g] = host[(k * 3 + 1) * kCells + cell];
+      uy[g] = host[(k * 3 + 2) * kCells + cell];
+    }
+  }
+  return SBT_OK;
+}
+
+sbt_status sbt_diagnostics(sbt_ctx *ctx, int32_t c, double out[3]) {
+  sbt_status st = check_case(ctx, c);
+  if (st) return st;
+  sbt_ctx &X = *ctx;
+  CaseHost &C = X.cs[c];
+  for (int l = 0; l < C.F.m; ++l) {
+    st = readout_level(X, c, l, X.stream);
+    if (st) return st;
+    HIPCHK(sbt_launch_reduce(X.d_partial, C.lr[l].own1 - C.lr[l].own0, 1.0 / (double)(1 << (2 * l)), X.d_diag,
+                             l > 0 ? 1 : 0, X.stream));
+  }
+  HIPCHK(hipMemcpyAsync(out, X.d_diag, sizeof(double) * 3, hipMemcpyDeviceToHost, X.stream));
+  HIPCHK(hipStreamSynchronize(X.stream));
+  return SBT_OK;
+}
+
+static int64_t read_kcount(sbt_ctx &X, CaseHost &C) {
+  int64_t k = 0;
+  if (hipMemcpyAsync(&k, C.dev.kcount, sizeof(k), hipMemcpyDeviceToHost, X.stream) != hipSuccess) return -1;
+  if (hipStreamSynchronize(X.stream) != hipSuccess) return -1;
+  return k;
+}
+
+sbt_status sbt_read_marker_forces(sbt_ctx *ctx, int32_t c, double *fx, double *fy) {
+  sbt_status st = check_case(ctx, c);
+  if (st) return st;
+  sbt_ctx &X = *ctx;
+  CaseHost &C = X.cs[c];
+  if (!C.has_body || C.n_markers == 0) return fail(SBT_ERR_STATE, "case has no body");
+  int64_t k = read_kcount(X, C);
+  if (k < 0) return fail(SBT_ERR_DEVICE, "kcount read");
+  // the last launch computed the IBM of the next substep already
+  int64_t done = X.post ? k - 1 : 0;
+  if (done <= 0) return fail(SBT_ERR_STATE, "no completed substep yet");
+  size_t slot = (size_t)((done - 1) & 1);
+  const size_t N = C.n_markers;
+  HIPCHK(hipMemcpyAsync(fx, C.dev.ftot + slot * 2 * N, sizeof(double) * N, hipMemcpyDeviceToHost, X.stream));
+  HIPCHK(hipMemcpyAsync(fy, C.dev.ftot + slot * 2 * N + N, sizeof(double) * N, hipMemcpyDeviceToHost, X.stream));
+  HIPCHK(hipStreamSynchronize(X.stream));
+  return SBT_OK;
+}
+
+sbt_status sbt_read_force_history(sbt_ctx *ctx, int32_t c, int32_t cap, double *fx, double *fy, int32_t *n_out) {
+  sbt_status st = check_case(ctx, c);
+  if (st) return st;
+  if (!n_out || cap < 0) return fail(SBT_ERR_ARG, "bad output");
+  sbt_ctx &X = *ctx;
+  CaseHost &C = X.cs[c];
+  *n_out = 0;
+  if (!C.has_body || C.n_markers == 0) return SBT_OK;
+  int64_t k = read_kcount(X, C);
+  if (k < 0) return fail(SBT_ERR_DEVICE, "kcount read");
+  int64_t done = X.post ? k - 1 : 0;
+  int64_t n = std::min<int64_t>({done, (int64_t)cap, (int64_t)C.hist_cap});
+  if (n <= 0) return SBT_OK;
+  std::vector<double> h(2 * C.hist_cap);
+  HIPCHK(hipMemcpyAsync(h.data(), C.dev.hist, sizeof(double) * h.size(), hipMemcpyDeviceToHost, X.stream));
+  HIPCHK(hipStreamSynchronize(X.stream));
+  for (int64_t t = 0; t < n; ++t) {
+    int64_t sub = done - n + t;
+    size_t slot = (size_t)(sub % (int64_t)C.hist_cap);
+    fx[t] = h[2 * slot];
+    fy[t] = h[2 * slot + 1];
+  }
+  *n_out = (int32_t)n;
+  return SBT_OK;
+}
+
+// ---- checkpoint -----------------------------------------------------------
+struct StateHeader {
+  uint64_t magic, bytes;
+  int32_t post, V, n_cases, storage;
+  int32_t cur[kMaxLevels];
+};
+
+sbt_status sbt_state_bytes(sbt_ctx *ctx, size_t *bytes) {
+  if (!ctx || !bytes) return fail(SBT_ERR_ARG, "null argument");
+  size_t b = sizeof(StateHeader);
+  const size_t s = storage_bytes(ctx->storage);
+  for (auto &P : ctx->pools) b += 2 * s * kQ * kCells * (size_t)P.total();
+  for (auto &C : ctx->cs)
+    if (C.has_body) b += sizeof(int64_t) + sizeof(double) * (4 * (size_t)C.d.max_markers + 2 * C.hist_cap);
+  *bytes = b;
+  return SBT_OK;
+}
+
+sbt_status sbt_read_state(sbt_ctx *ctx, void *host, size_t bytes) {
+  size_t need = 0;
+  sbt_status st = sbt_state_bytes(ctx, &need);
+  if (st) return st;
+  if (!host || bytes != need) return fail(SBT_ERR_BUFSIZE, "state buffer size mismatch");
+  sbt_ctx &X = *ctx;
+  HIPCHK(hipStreamSynchronize(X.stream));
+  char *p = (char *)host;
+  StateHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.magic = 0x5342545354415445ull;
+  h.bytes = need;
+  h.post = X.post;
+  h.V = X.V;
+  h.n_cases = X.n_cases;
+  h.storage = X.storage;
+  for (int v = 0; v < X.V; ++v) h.cur[v] = X.pools[v].cur;
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  const size_t s = storage_bytes(X.storage);
+  for (auto &P : X.pools)
+    for (int k = 0; k < 2; ++k) {
+      size_t nb = s * kQ * kCells * (size_t)P.total();
+      HIPCHK(hipMemcpy(p, P.lat[k], nb, hipMemcpyDeviceToHost));
+      p += nb;
+    }
+  for (auto &C : X.cs) {
+    if (!C.has_body) continue;
+    HIPCHK(hipMemcpy(p, C.dev.kcount, sizeof(int64_t), hipMemcpyDeviceToHost));
+    p += sizeof(int64_t);
+    size_t nb = sizeof(double) * 4 * (size_t)C.d.max_markers;
+    HIPCHK(hipMemcpy(p, C.dev.ftot, nb, hipMemcpyDeviceToHost));
+    p += nb;
+    nb = sizeof(double) * 2 * C.hist_cap;
+    HIPCHK(hipMemcpy(p, C.dev.hist, nb, hipMemcpyDeviceToHost));
+    p += nb;
+  }
+  return SBT_OK;
+}
+
+sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes) {
+  size_t need = 0;
+  sbt_status st = sbt_state_bytes(ctx, &need);
+  if (st) return st;
+  if (!host || bytes != need) return fail(SBT_ERR_BUFSIZE, "state buffer size mismatch");
+  sbt_ctx &X = *ctx;
+  const char *p = (const char *)host;
+  StateHeader h;
+  std::memcpy(&h, p, sizeof(h));
+  if (h.magic != 0x5342545354415445ull || h.V != X.V || h.n_cases != X.n_cases || h.storage != X.storage)
+    return fail(SBT_ERR_ARG, "state does not match this context");
+  p += sizeof(h);
+  HIPCHK(hipStreamSynchronize(X.stream));
+  const size_t s = storage_bytes(X.storage);
+  for (auto &P : X.pools)
+    for (int k = 0; k < 2; ++k) {
+      size_t nb = s * kQ * kCells * (size_t)P.total();
+      HIPCHK(hipMemcpy(P.lat[k], p, nb, hipMemcpyHostToDevice));
+      p += nb;
+    }
+  for (auto &C : X.cs) {
+    if (!C.has_body) continue;
+    HIPCHK(hipMemcpy(C.dev.kcount, p, sizeof(int64_t), hipMemcpyHostToDevice));
+    p += sizeof(int64_t);
+    size_t nb = sizeof(double) * 4 * (size_t)C.d.max_markers;
+    HIPCHK(hipMemcpy(C.dev.ftot, p, nb, hipMemcpyHostToDevice));
+    p += nb;
+    nb = sizeof(double) * 2 * C.hist_cap;
+    HIPCHK(hipMemcpy(C.dev.hist, p, nb, hipMemcpyHostToDevice));
+    p += nb;
+  }
+  X.post = h.post != 0;
+  for (int v = 0; v < X.V; ++v) X.pools[v].cur = h.cur[v];
+  destroy_graphs(X);
+  return SBT_OK;
+}
+
+// ---- tuning and measurement -------------------------------------------------
+sbt_status sbt_set_option(sbt_ctx *ctx, int32_t option, int32_t value) {
+  if (!ctx) return fail(SBT_ERR_ARG, "null context");
+  switch (option) {
+    case SBT_OPT_GRAPH: ctx->use_graph = value != 0; break;
+    case SBT_OPT_TILE:
+      if (value < 0 || value > 2) return fail(SBT_ERR_ARG, "tile variant must be 0..2");
+      ctx->tile = value;
+      break;
+    case SBT_OPT_XCD_REMAP: ctx->xcd = value != 0; break;
+    default: return fail(SBT_ERR_ARG, "unknown option");
+  }
+  destroy_graphs(*ctx);
+  return SBT_OK;
+}
+
+sbt_status sbt_profile(sbt_ctx *ctx, int32_t n, double out[6]) {
+  if (!ctx || !out || n <= 0) return fail(SBT_ERR_ARG, "bad argument");
+  sbt_ctx &X = *ctx;
+  HIPCHK(hipStreamSynchronize(X.stream));
+  X.profiling = true;
+  X.ev_level.clear();
+  X.ev_mdf.clear();
+  sbt_status st = SBT_OK;
+  if (!X.post) st = run_prologue(X, X.stream);
+  for (int t = 0; t < n && !st; ++t) st = run_step_eager(X, X.stream);
+  X.profiling = false;
+  hipError_t e = hipStreamSynchronize(X.stream);
+  double tl = 0, tm = 0;
+  for (auto &p : X.ev_level) {
+    float ms = 0;
+    if (!st && e == hipSuccess) (void)hipEventElapsedTime(&ms, p.first, p.second);
+    tl += ms;
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  for (auto &p : X.ev_mdf) {
+    float ms = 0;
+    if (!st && e == hipSuccess) (void)hipEventElapsedTime(&ms, p.first, p.second);
+    tm += ms;
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  double nl = (double)X.ev_level.size(), nm = (double)X.ev_mdf.size();
+  X.ev_level.clear();
+  X.ev_mdf.clear();
+  if (st) return st;
+  if (e != hipSuccess) return fail(SBT_ERR_DEVICE, hipGetErrorString(e));
+  int64_t upd = 0;
+  sbt_updates_per_step(ctx, &upd);
+  out[0] = tl;
+  out[1] = nl;
+  out[2] = tm;
+  out[3] = nm;
+  out[5] = (double)upd * n;
+  out[4] = out[5] * 2.0 * kQ * (double)storage_bytes(X.storage);
+  return SBT_OK;
+}
+
+sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path) {
+  if (!ctx || steps <= 0) return fail(SBT_ERR_ARG, "bad argument");
+  sbt_ctx &X = *ctx;
+  // cache key: storage, pools and their block counts
+  std::ostringstream key;
+  key << "st" << X.storage;
+  for (auto &P : X.pools) key << "_" << P.n_own << "/" << P.n_ghost;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      size_t k = line.find("\"" + key.str() + "\"");
+      if (k == std::string::npos) continue;
+      size_t c = line.find(':', k);
+      if (c != std::string::npos) return sbt_set_option(ctx, SBT_OPT_TILE, std::atoi(line.c_str() + c + 1));
+    }
+  }
+  size_t sb = 0;
+  sbt_status st = sbt_state_bytes(ctx, &sb);
+  if (st) return st;
+  std::vector<char> saved(sb);
+  st = sbt_read_state(ctx, saved.data(), sb);
+  if (st) return st;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 1e30f;
+  for (int tile = 0; tile < 3; ++tile) {
+    sbt_set_option(ctx, SBT_OPT_TILE, tile);
+    st = sbt_step(ctx, 1);  // warm-up (captures the graph)
+    if (st) break;
+    HIPCHK(hipEventRecord(e0, X.stream));
+    st = sbt_step(ctx, steps);
+    if (st) break;
+    HIPCHK(hipEventRecord(e1, X.stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = tile;
+    }
+    st = sbt_write_state(ctx, saved.data(), sb);
+    if (st) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  st = sbt_set_option(ctx, SBT_OPT_TILE, best);
+  if (st) return st;
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::stringstream buf;
+    buf << in.rdbuf();
+    std::string body = buf.str();
+    std::vector<std::string> lines;
+    std::string line;
+    std::istringstream is(body);
+    while (std::getline(is, line))
+      if (line.find("\":") != std::string::npos && line.find("\"" + key.str() + "\"") == std::string::npos) {
+        while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+        lines.push_back(line);
+      }
+    lines.push_back("  \"" + key.str() + "\": " + std::to_string(best));
+    std::ofstream out(cache_path);
+    out << "{\n";
+    for (size_t k = 0; k < lines.size(); ++k) out << lines[k] << (k + 1 < lines.size() ? ",\n" : "\n");
+    out << "}\n";
+  }
+  return SBT_OK;
+}
+
+}  // extern "C"

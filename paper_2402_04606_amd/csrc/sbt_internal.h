@@ -1,0 +1,130 @@
+// Internal structures shared by the host engine and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sbt {
+
+constexpr int kQ = 9;
+constexpr int kB = 16;           // block edge in cells
+constexpr int kCells = kB * kB;  // cells per block
+constexpr int kMaxLevels = 6;
+constexpr int kMaxContrib = 32;  // markers whose 4x4 stencil may cover one cell
+
+// Block flags.
+enum : int32_t {
+  BF_GHOST = 1,    // halo block: holds the two halo layers of its level
+  BF_CODES = 2,    // block has a per-cell code array (hidden / interface / hidden sources)
+  BF_EDGE = 4,     // some source of this block lies outside a non-periodic domain edge
+  BF_IBM = 8,      // finest-level block of a case with a body
+};
+
+// Per-cell code bits (blocks with BF_CODES).
+enum : uint16_t {
+  CC_HSRC = 0x1FF,    // bit i: source of direction i is hidden (covered by level l+1)
+  CC_HIDDEN = 0x200,  // the cell itself is covered by level l+1
+  CC_IFACE = 0x400,   // coarse cell next to level l+1: coalesce-on-read and explode
+  CC_BAND = 0x800,    // halo block: cell belongs to the two halo layers
+};
+
+struct alignas(16) BlockMeta {
+  int32_t ox, oy;      // origin, in cells of the block's own level
+  int32_t nbr[8];      // same-pool neighbours, directions 1..8 of D2Q9; -1 if none
+  int32_t child[4];    // pool v+1 blocks under the quadrants (x>=8) + 2 (y>=8); -1 if none
+  int32_t case_id;
+  int32_t level;       // true level of the case
+  int32_t flags;
+  int32_t code;        // index into the cell-code array, or -1
+};
+
+// IBM window of one body for the current finest substep: a dense box of
+// finest cells covering every marker stencil.
+struct alignas(16) IbmWindow {
+  int32_t x0, y0, w, h;
+};
+
+struct alignas(16) CaseDev {
+  double tau[kMaxLevels];
+  double pre[kMaxLevels];      // 1 - 1/(2 tau)
+  double fx[kMaxLevels], fy[kMaxLevels];
+  double s_cf[kMaxLevels];     // (l-1 -> l) post-collision factor, index l
+  double s_fc[kMaxLevels];     // (l+1 -> l) pre-collision factor, index l
+  float omega_f[kMaxLevels];   // 1/tau
+  float pre_f[kMaxLevels];
+  float fx_f[kMaxLevels], fy_f[kMaxLevels];
+  float s_cf_f[kMaxLevels], s_fc_f[kMaxLevels];
+  double rho0;
+  double bcu[4][2];
+  int32_t bc[4];
+  int32_t nx[kMaxLevels], ny[kMaxLevels];
+  int32_t per_x, per_y, cf_mode, n_levels;
+  // ---- body ----
+  int32_t body_kind;           // -1: none
+  int32_t n_markers, mdf_iters, hist_cap;
+  int32_t win_cap;             // cells of the IBM window buffers
+  int32_t bm_x0, bm_y0, bm_w, bm_h;  // finest-level block map: origin and size (blocks)
+  double bp[16];
+  const double *xb, *yb, *ds;
+  double *X, *Y, *udx, *udy;   // marker state for the current substep
+  double *dFx, *dFy;           // marker force of the current MDF iteration
+  double *ftot;                // [2 slots][2][n]: total marker force, slot = substep parity
+  double *hist;                // [hist_cap][2]
+  int64_t *kcount;             // finest substeps done
+  IbmWindow *win;
+  double *wF;                  // [2][win_cap]  force density in the window
+  double *wRho, *wU;           // [win_cap], [2][win_cap]
+  int32_t *wCnt;               // [win_cap] contributing markers (-1: not a stencil cell)
+  int32_t *wList;              // [win_cap][kMaxContrib]
+  const int32_t *bmap;         // finest-level block map -> pool index (-1 outside)
+};
+
+// Arguments of one level (collide+stream) launch.
+struct LevelArgs {
+  const BlockMeta *meta;
+  const uint16_t *codes;
+  const void *src;             // lattice read (post-collision state of the pool)
+  void *dst;                   // lattice written
+  const BlockMeta *fmeta;      // pool v+1 (finer) or null
+  const uint16_t *fcodes;
+  const void *fprev;           // finer pool lattice read by its last substep
+  void *fcur;                  // finer pool current lattice (explosion target)
+  const CaseDev *cases;
+  int32_t b0;                  // first block of the launch
+  int32_t n_blocks;            // blocks launched: [b0, b0 + n_blocks)
+  int32_t mode;                // MODE_* bits
+  int32_t xcd_remap;
+  double *out;                 // readout: [block - b0][3][256] rho, ux, uy
+  double *partial;             // readout: [block - b0][3] mass, jx, jy partial sums
+  int32_t *err;                // device error flags
+};
+
+struct MdfArgs {
+  const BlockMeta *meta;       // finest pool
+  const void *src;             // finest pool lattice the next level launch reads
+  const CaseDev *cases;
+  const int32_t *body_cases;   // case index per workgroup
+  int32_t first;               // 1: local read (initial pre-collision state)
+  int32_t *err;
+};
+
+// Level launch modes: LOCAL = read the cell's own populations (initial
+// pre-collision state) instead of streaming; READOUT = moments only, no write.
+enum : int32_t { MODE_LOCAL = 1, MODE_READOUT = 2 };
+
+enum : int32_t { ERR_NONFINITE = 1, ERR_MARKER = 2, ERR_CONTRIB = 4, ERR_WINDOW = 8 };
+
+}  // namespace sbt
+
+// Launchers implemented in sbt_kernels.hip.
+extern "C" {
+hipError_t sbt_launch_level(int storage, int tile, const sbt::LevelArgs *a, hipStream_t s);
+hipError_t sbt_launch_mdf(int storage, const sbt::MdfArgs *a, int n_bodies, hipStream_t s);
+hipError_t sbt_launch_reduce(const double *partial, int n_blocks, double vol, double *out,
+                             int accumulate, hipStream_t s);
+hipError_t sbt_launch_fill_nan(void *p, size_t n_elems, int storage, hipStream_t s);
+// f = f^eq(rho, u) on the owned cells of blocks [b0, b0+n) from per-block FP64
+// fields [n][3][256] (or rest at rho0 when fields is null).
+hipError_t sbt_launch_init(int storage, const sbt::BlockMeta *meta, const uint16_t *codes,
+                           const sbt::CaseDev *cases, void *lat, int b0, int n, const double *fields,
+                           hipStream_t s);
+}

@@ -1,0 +1,909 @@
+// gfx950 kernels of the SBoTFlow LBM-IBM hot path (arXiv 2402.04606).
+//
+// level_kernel : one refinement level of one substep, fused.  Pull scheme: a
+//   lattice holds post-collision populations f*; a launch gathers
+//   f(x,i) = f*(x - c_i, i) (streaming, Eq. (10)) including the same-level
+//   exchange across block edges, domain-edge rules, halo cells and the
+//   fine-to-coarse coalescence, then collides (Eqs. (2)-(8), Guo forcing) and
+//   writes f* coalesced; coarse cells next to the finer level also explode
+//   their f* into the finer level's halo cells (coarse-to-fine, Sec. 2.4).
+//   Halo ("ghost") blocks of the level gather their two halo layers in the
+//   first fine substep and are never collided.
+// mdf_kernel   : one workgroup per body: kinematics, moments of the stencil
+//   cells, the multi-direct-forcing loop (Eqs. (11)-(15)) and the body force
+//   (Eq. (16)), all FP64, deterministic (no floating-point atomics).
+//
+// Layout in HBM: per virtual level a pool of 16x16-cell blocks, SoA
+// [block][q][256] in the storage type, two lattices (read / write).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sbt_internal.h"
+
+using namespace sbt;
+
+namespace {
+
+// ---- D2Q9 velocity set (Eq. (1)) and weights (Eq. (7)) -----------------
+__device__ constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__device__ constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__device__ constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+__device__ constexpr int MIRX[9] = {0, 3, 2, 1, 4, 6, 5, 8, 7};  // reflect about an x-normal edge
+__device__ constexpr int MIRY[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};  // reflect about a y-normal edge
+
+template <typename C>
+__device__ __forceinline__ C wgt(int i) {
+  return i == 0 ? C(4.0 / 9.0) : (i < 5 ? C(1.0 / 9.0) : C(1.0 / 36.0));
+}
+
+// ---- storage types ---------------------------------------------------------
+template <int ST> struct Store;
+template <> struct Store<0> {  // FP64: f itself, FP64 arithmetic
+  using T = double;
+  using C = double;
+  static constexpr bool kShift = false;
+  __device__ static C ld(T v) { return v; }
+  __device__ static T st(C v) { return v; }
+};
+template <> struct Store<1> {  // FP32 deviation
+  using T = float;
+  using C = float;
+  static constexpr bool kShift = true;
+  __device__ static C ld(T v) { return v; }
+  __device__ static T st(C v) { return v; }
+};
+template <> struct Store<2> {  // FP16 deviation, round to nearest even
+  using T = _Float16;
+  using C = float;
+  static constexpr bool kShift = true;
+  __device__ static C ld(T v) { return (float)v; }
+  __device__ static T st(C v) { return (_Float16)v; }
+};
+template <> struct Store<3> {  // BF16 deviation, round to nearest even
+  using T = uint16_t;
+  using C = float;
+  static constexpr bool kShift = true;
+  __device__ static C ld(T v) { return __uint_as_float(((uint32_t)v) << 16); }
+  __device__ static T st(C v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (T)(u >> 16);
+  }
+};
+
+__device__ __forceinline__ int wrap(int a, int n) {
+  a %= n;
+  return a < 0 ? a + n : a;
+}
+
+// Neighbour block holding local cell (x, y), x, y in [-1, 16].
+__device__ __forceinline__ int nbr_of(const BlockMeta &m, int self, int x, int y) {
+  int ox = x < 0 ? -1 : (x > 15 ? 1 : 0);
+  int oy = y < 0 ? -1 : (y > 15 ? 1 : 0);
+  if (ox == 0 && oy == 0) return self;
+  // D2Q9 direction with velocity (ox, oy): 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE
+  int d;
+  if (oy == 0) d = ox > 0 ? 1 : 3;
+  else if (ox == 0) d = oy > 0 ? 2 : 4;
+  else if (ox > 0) d = oy > 0 ? 5 : 8;
+  else d = oy > 0 ? 6 : 7;
+  return m.nbr[d - 1];
+}
+
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::T ldraw(const void *lat, int blk, int q, int cell) {
+  using T = typename Store<ST>::T;
+  return static_cast<const T *>(lat)[((size_t)blk * kQ + q) * kCells + cell];
+}
+
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::C ldv(const void *lat, int blk, int q, int cell) {
+  return Store<ST>::ld(ldraw<ST>(lat, blk, q, cell));
+}
+
+// Post-collision value of direction q at local cell (x, y) of block `self`
+// (x, y may be one cell outside the block).  NaN if no block holds the cell.
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::C fetch(const void *lat, const BlockMeta &m, int self,
+                                                     int x, int y, int q) {
+  using C = typename Store<ST>::C;
+  int nb = nbr_of(m, self, x, y);
+  if (nb < 0) return C(__builtin_nan(""));
+  return ldv<ST>(lat, nb, q, (y & 15) * 16 + (x & 15));
+}
+
+// ---- equilibrium in the storage frame --------------------------------------
+// FP64 path: f^eq exactly as Eq. (7) is written.  Deviation paths: f^eq - w rho0.
+__device__ __forceinline__ double feq64(int i, double rho, double ux, double uy, double usq) {
+#pragma clang fp contract(off)
+  double cu = CX[i] * ux + CY[i] * uy;
+  return wgt<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+}
+__device__ __forceinline__ float feqdev(int i, float drho, float rho, float ux, float uy, float usq) {
+  float cu = CX[i] * ux + CY[i] * uy;
+  return wgt<float>(i) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
+}
+
+// Moments in FP64 exactly in the order the paper's sums are written
+// (i = 0..8), so FP64 results are reproducible bit for bit.
+__device__ __forceinline__ void moments64(const double f[9], double &rho, double &jx, double &jy) {
+#pragma clang fp contract(off)
+  rho = 0.0;
+  jx = 0.0;
+  jy = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    rho += f[i];
+    jx += CX[i] * f[i];
+    jy += CY[i] * f[i];
+  }
+}
+
+// ---- collision (Eqs. (3), (6)-(8)) -----------------------------------------
+template <int ST>
+struct Collide;
+
+template <>
+struct Collide<0> {
+  __device__ static void run(const CaseDev &cp, int l, double f[9], double Fx, double Fy, double &rho,
+                             double &ux, double &uy) {
+#pragma clang fp contract(off)
+    double jx, jy;
+    moments64(f, rho, jx, jy);
+    ux = (jx + 0.5 * Fx) / rho;
+    uy = (jy + 0.5 * Fy) / rho;
+    double usq = ux * ux + uy * uy;
+    double tau = cp.tau[l];
+    bool forced = (Fx != 0.0) || (Fy != 0.0);
+    double uF = ux * Fx + uy * Fy;
+    double pre = cp.pre[l];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      double fe = feq64(i, rho, ux, uy, usq);
+      double v = f[i] - (f[i] - fe) / tau;
+      if (forced) {
+        double cu = CX[i] * ux + CY[i] * uy;
+        double cF = CX[i] * Fx + CY[i] * Fy;
+        v = v + wgt<double>(i) * pre * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
+      }
+      f[i] = v;
+    }
+  }
+};
+
+template <int ST>
+struct Collide {
+  // deviation form: f = w rho0 + d;  rho = rho0 + sum d;  sum c f = sum c d
+  __device__ static void run(const CaseDev &cp, int l, float d[9], float Fx, float Fy, float &rho,
+                             float &ux, float &uy) {
+    float drho = 0.f, jx = 0.f, jy = 0.f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      drho += d[i];
+      jx += CX[i] * d[i];
+      jy += CY[i] * d[i];
+    }
+    rho = (float)cp.rho0 + drho;
+    float ir = 1.0f / rho;
+    ux = (jx + 0.5f * Fx) * ir;
+    uy = (jy + 0.5f * Fy) * ir;
+    float usq = ux * ux + uy * uy;
+    float om = cp.omega_f[l];
+    float pre = cp.pre_f[l];
+    float uF = ux * Fx + uy * Fy;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      float cu = CX[i] * ux + CY[i] * uy;
+      float cF = CX[i] * Fx + CY[i] * Fy;
+      float fe = feqdev(i, drho, rho, ux, uy, usq);
+      d[i] = d[i] + om * (fe - d[i]) + wgt<float>(i) * pre * (3.f * cF + 9.f * cu * cF - 3.f * uF);
+    }
+  }
+};
+
+// Equilibrium in the storage frame for the interface / boundary operators.
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::C feq_frame(const CaseDev &cp, int i,
+                                                          typename Store<ST>::C rho,
+                                                          typename Store<ST>::C ux,
+                                                          typename Store<ST>::C uy) {
+  using C = typename Store<ST>::C;
+  if constexpr (!Store<ST>::kShift) {
+    return feq64(i, rho, ux, uy, ux * ux + uy * uy);
+  } else {
+    C r0 = (C)cp.rho0;
+    return feqdev(i, rho - r0, rho, ux, uy, ux * ux + uy * uy);
+  }
+}
+
+// Moments of a set of populations held in the storage frame.
+template <int ST>
+__device__ __forceinline__ void frame_moments(const CaseDev &cp, const typename Store<ST>::C f[9],
+                                              typename Store<ST>::C &rho, typename Store<ST>::C &jx,
+                                              typename Store<ST>::C &jy) {
+  if constexpr (!Store<ST>::kShift) {
+    moments64(f, rho, jx, jy);
+  } else {
+    float dr = 0.f, a = 0.f, b = 0.f;
+    for (int i = 0; i < 9; ++i) {
+      dr += f[i];
+      a += CX[i] * f[i];
+      b += CY[i] * f[i];
+    }
+    rho = (float)cp.rho0 + dr;
+    jx = a;
+    jy = b;
+  }
+}
+
+// ---- domain-edge rules -----------------------------------------------------
+// Unknown population q of cell (x, y) (local coordinates of block `self`,
+// level-0 global cell (gx, gy)); its source lies beyond a non-periodic edge.
+template <int ST>
+__device__ typename Store<ST>::C edge_value(const CaseDev &cp, const void *src, const BlockMeta &m,
+                                            int self, int x, int y, int gx, int gy, int q) {
+#pragma clang fp contract(off)
+  using C = typename Store<ST>::C;
+  const int nx = cp.nx[0], ny = cp.ny[0];
+  int sx = gx - CX[q], sy = gy - CY[q];
+  bool outx = (sx < 0 || sx >= nx) && !cp.per_x;
+  bool outy = (sy < 0 || sy >= ny) && !cp.per_y;
+  int ex = sx < 0 ? 0 : 1, ey = sy < 0 ? 2 : 3;
+  int e = outx ? ex : ey;
+  if (outx && outy) {
+    int kx = cp.bc[ex], ky = cp.bc[ey];
+    bool lx = kx == 1 || kx == 2, ly = ky == 1 || ky == 2;
+    if (!lx && ly) e = ey;
+  }
+  const double uwx = cp.bcu[e][0], uwy = cp.bcu[e][1];
+  switch (cp.bc[e]) {
+    case 1: {  // wall: half-way bounce-back with moving-wall term
+      C fs = ldv<ST>(src, self, OPP[q], y * 16 + x);
+      if constexpr (!Store<ST>::kShift) {
+        return fs + 6.0 * wgt<double>(q) * cp.rho0 * (CX[q] * uwx + CY[q] * uwy);
+      } else {
+        return fs + (float)(6.0 * wgt<double>(q) * cp.rho0 * (CX[q] * uwx + CY[q] * uwy));
+      }
+    }
+    case 2: {  // equilibrium inflow at (rho0, u_in)
+      if constexpr (!Store<ST>::kShift) {
+        return feq64(q, cp.rho0, uwx, uwy, uwx * uwx + uwy * uwy);
+      } else {
+        double cu = CX[q] * uwx + CY[q] * uwy;
+        return (float)(wgt<double>(q) * cp.rho0 *
+                       (3.0 * cu + 4.5 * cu * cu - 1.5 * (uwx * uwx + uwy * uwy)));
+      }
+    }
+    case 3:    // zero-gradient outflow: the value that streams into the interior neighbour
+    case 4: {  // specular symmetry: mirrored population from the tangential neighbour
+      const int nrm[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+      const bool xn = (e == 0 || e == 1);
+      int px, py, qq = q;
+      if (cp.bc[e] == 3) {
+        px = gx - nrm[e][0] - CX[q];
+        py = gy - nrm[e][1] - CY[q];
+      } else {
+        px = gx - (xn ? 0 : CX[q]);
+        py = gy - (xn ? CY[q] : 0);
+        qq = xn ? MIRX[q] : MIRY[q];
+      }
+      // periodic axes wrap through the neighbour table; others clamp (corners)
+      if (!cp.per_x) px = px < 0 ? 0 : (px >= nx ? nx - 1 : px);
+      if (!cp.per_y) py = py < 0 ? 0 : (py >= ny ? ny - 1 : py);
+      return fetch<ST>(src, m, self, x + (px - gx), y + (py - gy), qq);
+    }
+    default:
+      return C(__builtin_nan(""));
+  }
+}
+
+// ---- fine-to-coarse coalescence (step (6) of Sec. 2.4), on read ------------
+// Mean over the 4 children g of coarse cell (x, y) of the finer level's
+// post-stream value f(g, q) = f*(g - c_q, q), read from the finer lattice its
+// last substep streamed from.
+template <int ST>
+__device__ typename Store<ST>::C coalesce(const LevelArgs &a, const BlockMeta &m, int x, int y, int q) {
+#pragma clang fp contract(off)
+  using C = typename Store<ST>::C;
+  int quad = (x >= 8 ? 1 : 0) + (y >= 8 ? 2 : 0);
+  int cb = m.child[quad];
+  if (cb < 0) return C(__builtin_nan(""));
+  const BlockMeta &fm = a.fmeta[cb];
+  int fx0 = (2 * x) & 15, fy0 = (2 * y) & 15;
+  C v00 = fetch<ST>(a.fprev, fm, cb, fx0 - CX[q], fy0 - CY[q], q);
+  C v10 = fetch<ST>(a.fprev, fm, cb, fx0 + 1 - CX[q], fy0 - CY[q], q);
+  C v01 = fetch<ST>(a.fprev, fm, cb, fx0 - CX[q], fy0 + 1 - CY[q], q);
+  C v11 = fetch<ST>(a.fprev, fm, cb, fx0 + 1 - CX[q], fy0 + 1 - CY[q], q);
+  C sum = v00;
+  sum += v10;
+  sum += v01;
+  sum += v11;
+  return C(0.25) * sum;
+}
+
+// ---- one cell of a level launch --------------------------------------------
+template <int ST>
+__device__ __forceinline__ void level_cell(const LevelArgs &a, const BlockMeta &m, int b, int cell,
+                                           const CaseDev &cp, bool slow, double *part) {
+#pragma clang fp contract(off)
+  using S = Store<ST>;
+  using T = typename S::T;
+  using C = typename S::C;
+  const int x = cell & 15, y = cell >> 4;
+  const int l = m.level;
+  uint16_t code = (m.flags & BF_CODES) ? a.codes[(size_t)m.code * kCells + cell] : (uint16_t)0;
+
+  if (m.flags & BF_GHOST) {  // halo layers: streamed, never collided
+    if (!(code & CC_BAND)) return;
+    T g[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      int sx = x - CX[i], sy = y - CY[i];
+      int nb = nbr_of(m, b, sx, sy);
+      g[i] = nb < 0 ? S::st(C(__builtin_nan(""))) : ldraw<ST>(a.src, nb, i, (sy & 15) * 16 + (sx & 15));
+    }
+    T *dst = static_cast<T *>(a.dst);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dst[((size_t)b * kQ + i) * kCells + cell] = g[i];
+    return;
+  }
+
+  const size_t ob = (size_t)(b - a.b0);
+  if (code & CC_HIDDEN) {
+    if (a.mode & MODE_READOUT) {
+      for (int k = 0; k < 3; ++k) a.out[(ob * 3 + k) * kCells + cell] = __builtin_nan("");
+    }
+    return;
+  }
+
+  C f[9];
+  if (a.mode & MODE_LOCAL) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = ldv<ST>(a.src, b, i, cell);
+  } else if (!slow) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      int sx = x - CX[i], sy = y - CY[i];
+      int nb = nbr_of(m, b, sx, sy);
+      f[i] = nb < 0 ? C(__builtin_nan("")) : ldv<ST>(a.src, nb, i, (sy & 15) * 16 + (sx & 15));
+    }
+  } else {
+    const int gx = m.ox + x, gy = m.oy + y;
+    bool hid_any = false;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      int sx = x - CX[i], sy = y - CY[i];
+      int nb = nbr_of(m, b, sx, sy);
+      if (code & (1u << i)) {
+        f[i] = coalesce<ST>(a, m, x, y, i);
+        hid_any = true;
+      } else if (nb < 0) {
+        f[i] = edge_value<ST>(cp, a.src, m, b, x, y, gx, gy, i);
+      } else {
+        f[i] = ldv<ST>(a.src, nb, i, (sy & 15) * 16 + (sx & 15));
+      }
+    }
+    if (hid_any && cp.cf_mode == 1) {  // RESCALE the coalesced populations
+      C r, jx, jy;
+      frame_moments<ST>(cp, f, r, jx, jy);
+      C ux = jx / r, uy = jy / r;
+      C s = (C)(Store<ST>::kShift ? (C)cp.s_fc_f[l] : (C)cp.s_fc[l]);
+      if constexpr (!Store<ST>::kShift) s = cp.s_fc[l];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        if (!(code & (1u << i))) continue;
+        C fe = feq_frame<ST>(cp, i, r, ux, uy);
+        f[i] = fe + s * (f[i] - fe);
+      }
+    }
+  }
+
+  if (a.mode & MODE_READOUT) {  // readout: moments of the post-stream populations, FP64
+    double fd[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fd[i] = (double)f[i];
+    double rho, jx, jy;
+    moments64(fd, rho, jx, jy);
+    if constexpr (Store<ST>::kShift) rho = cp.rho0 + rho;
+    double ux = (jx + 0.5 * cp.fx[l]) / rho, uy = (jy + 0.5 * cp.fy[l]) / rho;
+    a.out[(ob * 3 + 0) * kCells + cell] = rho;
+    a.out[(ob * 3 + 1) * kCells + cell] = ux;
+    a.out[(ob * 3 + 2) * kCells + cell] = uy;
+    part[0] = rho;
+    part[1] = jx;
+    part[2] = jy;
+    return;
+  }
+
+  // Force density: uniform body force (+ IBM force on the finest level).
+  C Fx = Store<ST>::kShift ? (C)cp.fx_f[l] : (C)cp.fx[l];
+  C Fy = Store<ST>::kShift ? (C)cp.fy_f[l] : (C)cp.fy[l];
+  if constexpr (!Store<ST>::kShift) { Fx = cp.fx[l]; Fy = cp.fy[l]; }
+  if (m.flags & BF_IBM) {
+    IbmWindow w = *cp.win;
+    int wx = m.ox + x - w.x0, wy = m.oy + y - w.y0;
+    if (wx >= 0 && wx < w.w && wy >= 0 && wy < w.h) {
+      size_t wi = (size_t)wy * w.w + wx;
+      Fx = Fx + (C)cp.wF[wi];
+      Fy = Fy + (C)cp.wF[(size_t)cp.win_cap + wi];
+    }
+  }
+
+  C rho, ux, uy;
+  Collide<ST>::run(cp, l, f, Fx, Fy, rho, ux, uy);
+  if (!(rho == rho) || rho > C(1e30) || rho < C(-1e30)) atomicOr(a.err, ERR_NONFINITE);
+
+  T *dst = static_cast<T *>(a.dst);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) dst[((size_t)b * kQ + i) * kCells + cell] = S::st(f[i]);
+
+  if (code & CC_IFACE) {  // coarse-to-fine: explode f* into the 4 halo children
+    C e[9];
+    if (cp.cf_mode == 1) {
+      C s = Store<ST>::kShift ? (C)cp.s_cf_f[l + 1] : (C)cp.s_cf[l + 1];
+      if constexpr (!Store<ST>::kShift) s = cp.s_cf[l + 1];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        C fe = feq_frame<ST>(cp, i, rho, ux, uy);
+        e[i] = fe + s * (f[i] - fe);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) e[i] = f[i];
+    }
+    int quad = (x >= 8 ? 1 : 0) + (y >= 8 ? 2 : 0);
+    int cb = m.child[quad];
+    if (cb >= 0) {
+      T *fd = static_cast<T *>(a.fcur);
+      int fx0 = (2 * x) & 15, fy0 = (2 * y) & 15;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        T v = S::st(e[i]);
+        size_t base = ((size_t)cb * kQ + i) * kCells;
+        fd[base + fy0 * 16 + fx0] = v;
+        fd[base + fy0 * 16 + fx0 + 1] = v;
+        fd[base + (fy0 + 1) * 16 + fx0] = v;
+        fd[base + (fy0 + 1) * 16 + fx0 + 1] = v;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int remap_block(int bid, int nblk, int enable) {
+  if (!enable) return bid;
+  // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+  // contiguous run of (Morton-ordered) blocks so halo reads hit its own L2.
+  int xcd = bid & 7, k = bid >> 3;
+  int q = nblk >> 3, r = nblk & 7;
+  int start = xcd * q + (xcd < r ? xcd : r);
+  return start + k;
+}
+
+template <int ST, int CPT>
+__global__ __launch_bounds__(256 / CPT) void level_kernel(LevelArgs a) {
+  constexpr int NT = 256 / CPT;
+  const int bl = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  if (bl >= a.n_blocks) return;
+  const int b = a.b0 + bl;
+  const BlockMeta m = a.meta[b];
+  const CaseDev &cp = a.cases[m.case_id];
+  const bool slow = (m.flags & (BF_CODES | BF_EDGE)) != 0;
+  double part[3] = {0.0, 0.0, 0.0};
+  double acc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    int cell = threadIdx.x + k * NT;
+    level_cell<ST>(a, m, b, cell, cp, slow, part);
+    if (a.mode & MODE_READOUT) {
+      // fixed-order per-thread partials (hidden cells contribute nothing)
+      acc[0] += part[0];
+      acc[1] += part[1];
+      acc[2] += part[2];
+      part[0] = part[1] = part[2] = 0.0;
+    }
+  }
+  if (a.mode & MODE_READOUT) {
+    __shared__ double red[3][NT];
+    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+      if (threadIdx.x < s)
+        for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 3; ++k) a.partial[(size_t)bl * 3 + k] = red[k][0];
+  }
+}
+
+// ---- IBM: multi-direct forcing, one workgroup per body --------------------
+constexpr int MDF_THREADS = 1024;
+
+__device__ __forceinline__ double peskin(double r) {
+#pragma clang fp contract(off)
+  double a = fabs(r);
+  if (a <= 1.0) return 0.125 * (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a));
+  if (a <= 2.0) return 0.125 * (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a));
+  return 0.0;
+}
+
+__device__ __forceinline__ int tap0(double X) { return (int)floor(X - 1.5); }
+
+__device__ void body_positions(const CaseDev &cp, double k, int j, double &X, double &Y) {
+#pragma clang fp contract(off)
+  const double *p = cp.bp;
+  if (cp.body_kind == 0) {
+    X = p[0] + cp.xb[j];
+    Y = p[1] + cp.yb[j];
+    return;
+  }
+  double tstar = k * p[8] / p[9];
+  double theta = 2.0 * M_PI * tstar / p[6];
+  double alpha = p[2] - p[3] * sin(theta + p[7]);
+  double h = 0.5 * p[4] * cos(theta);
+  double xc = p[0] + h * cos(p[5]);
+  double yc = p[1] + h * sin(p[5]);
+  double ca = cos(alpha), sa = sin(alpha);
+  X = xc + cp.xb[j] * ca + cp.yb[j] * sa;
+  Y = yc - cp.xb[j] * sa + cp.yb[j] * ca;
+}
+
+template <int ST>
+__device__ void cell_moments(const MdfArgs &a, const CaseDev &cp, int gx, int gy, double &rho, double &ux,
+                             double &uy) {
+#pragma clang fp contract(off)
+  int bx = (gx >> 4) - cp.bm_x0, by = (gy >> 4) - cp.bm_y0;
+  int b = cp.bmap[(size_t)by * cp.bm_w + bx];
+  const BlockMeta &m = a.meta[b];
+  int x = gx & 15, y = gy & 15;
+  double f[9];
+  for (int i = 0; i < 9; ++i) {
+    if (a.first) f[i] = (double)ldv<ST>(a.src, b, i, y * 16 + x);
+    else f[i] = (double)fetch<ST>(a.src, m, b, x - CX[i], y - CY[i], i);
+  }
+  double jx, jy;
+  moments64(f, rho, jx, jy);
+  if constexpr (Store<ST>::kShift) rho = cp.rho0 + rho;
+  int l = cp.n_levels - 1;
+  ux = (jx + 0.5 * cp.fx[l]) / rho;
+  uy = (jy + 0.5 * cp.fy[l]) / rho;
+}
+
+// Is finest cell (gx, gy) with its 8 neighbours owned by a (non-halo) block?
+__device__ bool stencil_ok(const MdfArgs &a, const CaseDev &cp, int gx, int gy) {
+  int l = cp.n_levels - 1;
+  if (gx - 1 < 0 || gy - 1 < 0 || gx + 1 >= cp.nx[l] || gy + 1 >= cp.ny[l]) return false;
+  for (int by = (gy - 1) >> 4; by <= (gy + 1) >> 4; ++by)
+    for (int bx = (gx - 1) >> 4; bx <= (gx + 1) >> 4; ++bx) {
+      int rx = bx - cp.bm_x0, ry = by - cp.bm_y0;
+      if (rx < 0 || ry < 0 || rx >= cp.bm_w || ry >= cp.bm_h) return false;
+      int b = cp.bmap[(size_t)ry * cp.bm_w + rx];
+      if (b < 0 || (a.meta[b].flags & BF_GHOST)) return false;
+    }
+  return true;
+}
+
+template <int ST>
+__global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
+#pragma clang fp contract(off)
+  const int ci = a.body_cases[blockIdx.x];
+  const CaseDev &cp = a.cases[ci];
+  const int n = cp.n_markers;
+  const int tid = threadIdx.x;
+  __shared__ int s_box[4];
+  __shared__ int s_bad;
+  const int64_t k = *cp.kcount;
+
+  // 1. kinematics: r_j(t_k), desired velocity (r_j(t_k+1) - r_j(t_k)) / dt
+  int mnx = 1 << 30, mny = 1 << 30, mxx = -(1 << 30), mxy = -(1 << 30);
+  for (int j = tid; j < n; j += MDF_THREADS) {
+    double X, Y, X1, Y1;
+    body_positions(cp, (double)k, j, X, Y);
+    body_positions(cp, (double)(k + 1), j, X1, Y1);
+    cp.X[j] = X;
+    cp.Y[j] = Y;
+    cp.udx[j] = X1 - X;
+    cp.udy[j] = Y1 - Y;
+    int i0 = tap0(X), j0 = tap0(Y);
+    mnx = min(mnx, i0);
+    mny = min(mny, j0);
+    mxx = max(mxx, i0 + 4);
+    mxy = max(mxy, j0 + 4);
+  }
+  if (tid == 0) {
+    s_box[0] = 1 << 30; s_box[1] = 1 << 30; s_box[2] = -(1 << 30); s_box[3] = -(1 << 30);
+    s_bad = 0;
+  }
+  __syncthreads();
+  atomicMin(&s_box[0], mnx);
+  atomicMin(&s_box[1], mny);
+  atomicMax(&s_box[2], mxx);
+  atomicMax(&s_box[3], mxy);
+  __syncthreads();
+  const int wx0 = s_box[0], wy0 = s_box[1];
+  const int ww = s_box[2] - wx0, wh = s_box[3] - wy0;
+  const int ncell = ww * wh;
+  if (ncell > cp.win_cap || ww <= 0 || wh <= 0) {
+    if (tid == 0) {
+      atomicOr(a.err, ERR_WINDOW);
+      IbmWindow e = {0, 0, 0, 0};
+      *cp.win = e;
+      *cp.kcount = k + 1;
+    }
+    return;
+  }
+  if (tid == 0) {
+    IbmWindow w = {wx0, wy0, ww, wh};
+    *cp.win = w;
+  }
+  // 2. clear the window
+  for (int c = tid; c < ncell; c += MDF_THREADS) {
+    cp.wCnt[c] = -1;
+    cp.wF[c] = 0.0;
+    cp.wF[(size_t)cp.win_cap + c] = 0.0;
+  }
+  __syncthreads();
+  // 3. mark stencil cells, check they and their sources are owned finest cells
+  for (int p = tid; p < 16 * n; p += MDF_THREADS) {
+    int j = p >> 4, t = p & 15;
+    int gx = tap0(cp.X[j]) + (t & 3), gy = tap0(cp.Y[j]) + (t >> 2);
+    cp.wCnt[(gy - wy0) * ww + (gx - wx0)] = 0;
+    if (!stencil_ok(a, cp, gx, gy)) s_bad = 1;
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) {
+      atomicOr(a.err, ERR_MARKER);
+      IbmWindow e = {0, 0, 0, 0};
+      *cp.win = e;
+      *cp.kcount = k + 1;
+    }
+    return;
+  }
+  // 4. contributor lists: markers whose stencil covers each cell
+  for (int p = tid; p < 16 * n; p += MDF_THREADS) {
+    int j = p >> 4, t = p & 15;
+    int gx = tap0(cp.X[j]) + (t & 3), gy = tap0(cp.Y[j]) + (t >> 2);
+    int c = (gy - wy0) * ww + (gx - wx0);
+    int pos = atomicAdd(&cp.wCnt[c], 1);
+    if (pos < kMaxContrib) cp.wList[(size_t)c * kMaxContrib + pos] = j;
+    else s_bad = 2;
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) {
+      atomicOr(a.err, ERR_CONTRIB);
+      IbmWindow e = {0, 0, 0, 0};
+      *cp.win = e;
+      *cp.kcount = k + 1;
+    }
+    return;
+  }
+  // 5. sort each list by marker index (spreading sums in index order) and
+  //    compute rho and the uncorrected velocity of the stencil cells
+  for (int c = tid; c < ncell; c += MDF_THREADS) {
+    int cnt = cp.wCnt[c];
+    if (cnt < 0) continue;
+    int32_t *L = cp.wList + (size_t)c * kMaxContrib;
+    for (int i = 1; i < cnt; ++i) {
+      int v = L[i], q = i - 1;
+      while (q >= 0 && L[q] > v) {
+        L[q + 1] = L[q];
+        --q;
+      }
+      L[q + 1] = v;
+    }
+    double rho, ux, uy;
+    cell_moments<ST>(a, cp, wx0 + c % ww, wy0 + c / ww, rho, ux, uy);
+    cp.wRho[c] = rho;
+    cp.wU[c] = ux;
+    cp.wU[(size_t)cp.win_cap + c] = uy;
+  }
+  __syncthreads();
+  // 6. N_F iterations: interpolate (Eq. 12), boundary force (Eq. 11),
+  //    spread (Eq. 15), correct velocity and accumulate force
+  double *ftx = cp.ftot + (size_t)(k & 1) * 2 * n;
+  double *fty = ftx + n;
+  for (int it = 0; it < cp.mdf_iters; ++it) {
+    for (int j = tid; j < n; j += MDF_THREADS) {
+      double X = cp.X[j], Y = cp.Y[j];
+      int i0 = tap0(X), j0 = tap0(Y);
+      double su = 0.0, sv = 0.0, sr = 0.0;
+      for (int bb = 0; bb < 4; ++bb) {
+        double py = peskin(j0 + bb + 0.5 - Y);
+        int row = (j0 + bb - wy0) * ww;
+        for (int aa = 0; aa < 4; ++aa) {
+          double w = peskin(i0 + aa + 0.5 - X) * py;
+          int c = row + (i0 + aa - wx0);
+          su += cp.wU[c] * w;
+          sv += cp.wU[(size_t)cp.win_cap + c] * w;
+          sr += cp.wRho[c] * w;
+        }
+      }
+      double gx = 2.0 * sr * (cp.udx[j] - su);
+      double gy = 2.0 * sr * (cp.udy[j] - sv);
+      cp.dFx[j] = gx;
+      cp.dFy[j] = gy;
+      if (it == 0) {
+        ftx[j] = gx;
+        fty[j] = gy;
+      } else {
+        ftx[j] += gx;
+        fty[j] += gy;
+      }
+    }
+    __syncthreads();
+    for (int c = tid; c < ncell; c += MDF_THREADS) {
+      int cnt = cp.wCnt[c];
+      if (cnt < 0) continue;
+      const int32_t *L = cp.wList + (size_t)c * kMaxContrib;
+      int gx = wx0 + c % ww, gy = wy0 + c / ww;
+      double dfx = 0.0, dfy = 0.0;
+      for (int q = 0; q < cnt; ++q) {
+        int j = L[q];
+        double X = cp.X[j], Y = cp.Y[j];
+        double w = peskin(gx + 0.5 - X) * peskin(gy + 0.5 - Y);
+        dfx += cp.dFx[j] * w * cp.ds[j];
+        dfy += cp.dFy[j] * w * cp.ds[j];
+      }
+      cp.wF[c] += dfx;
+      cp.wF[(size_t)cp.win_cap + c] += dfy;
+      double r = cp.wRho[c];
+      cp.wU[c] += dfx / (2.0 * r);
+      cp.wU[(size_t)cp.win_cap + c] += dfy / (2.0 * r);
+    }
+    __syncthreads();
+  }
+  // 7. total force on the body, Eq. (16), summed in marker order
+  if (tid == 0) {
+    double fsx = 0.0, fsy = 0.0;
+    for (int j = 0; j < n; ++j) {
+      fsx -= ftx[j] * cp.ds[j];
+      fsy -= fty[j] * cp.ds[j];
+    }
+    int64_t slot = k % cp.hist_cap;
+    cp.hist[2 * slot] = fsx;
+    cp.hist[2 * slot + 1] = fsy;
+    *cp.kcount = k + 1;
+  }
+}
+
+// ---- small helpers ---------------------------------------------------------
+__global__ void reduce_kernel(const double *partial, int n, double vol, double *out, int accumulate) {
+  __shared__ double red[3][256];
+  double acc[3] = {0.0, 0.0, 0.0};
+  int per = (n + 255) / 256;
+  int b0 = threadIdx.x * per, b1 = min(n, b0 + per);
+  for (int b = b0; b < b1; ++b)
+    for (int k = 0; k < 3; ++k) acc[k] += partial[(size_t)b * 3 + k];
+  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) out[k] = (accumulate ? out[k] : 0.0) + vol * red[k][0];
+}
+
+// f = f^eq(rho, u) (Eq. (7)) on owned cells, in the storage frame.
+template <int ST>
+__global__ __launch_bounds__(256) void init_kernel(const BlockMeta *meta, const uint16_t *codes,
+                                                  const CaseDev *cases, void *lat, int b0,
+                                                  const double *fields) {
+#pragma clang fp contract(off)
+  using S = Store<ST>;
+  using T = typename S::T;
+  const int b = b0 + blockIdx.x, cell = threadIdx.x;
+  const BlockMeta m = meta[b];
+  const CaseDev &cp = cases[m.case_id];
+  uint16_t code = (m.flags & BF_CODES) ? codes[(size_t)m.code * kCells + cell] : (uint16_t)0;
+  if ((m.flags & BF_GHOST) || (code & CC_HIDDEN)) return;
+  double rho = cp.rho0, ux = 0.0, uy = 0.0;
+  if (fields) {
+    const double *f = fields + (size_t)blockIdx.x * 3 * kCells;
+    rho = f[cell];
+    ux = f[kCells + cell];
+    uy = f[2 * kCells + cell];
+  }
+  double usq = ux * ux + uy * uy;
+  T *d = static_cast<T *>(lat);
+  for (int i = 0; i < 9; ++i) {
+    double v = feq64(i, rho, ux, uy, usq);
+    if constexpr (S::kShift) v = v - wgt<double>(i) * cp.rho0;
+    d[((size_t)b * kQ + i) * kCells + cell] = S::st((typename S::C)v);
+  }
+}
+
+template <typename T>
+__global__ void fill_nan_kernel(T *p, size_t n, T v) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+template <int ST>
+hipError_t launch_level_st(int tile, const LevelArgs *a, hipStream_t s) {
+  if (a->n_blocks <= 0) return hipSuccess;
+  dim3 grid(a->n_blocks);
+  switch (tile) {
+    case 1:
+      hipLaunchKernelGGL((level_kernel<ST, 2>), grid, dim3(128), 0, s, *a);
+      break;
+    case 2:
+      hipLaunchKernelGGL((level_kernel<ST, 4>), grid, dim3(64), 0, s, *a);
+      break;
+    default:
+      hipLaunchKernelGGL((level_kernel<ST, 1>), grid, dim3(256), 0, s, *a);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+extern "C" hipError_t sbt_launch_level(int storage, int tile, const LevelArgs *a, hipStream_t s) {
+  switch (storage) {
+    case 0: return launch_level_st<0>(tile, a, s);
+    case 1: return launch_level_st<1>(tile, a, s);
+    case 2: return launch_level_st<2>(tile, a, s);
+    case 3: return launch_level_st<3>(tile, a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+extern "C" hipError_t sbt_launch_mdf(int storage, const MdfArgs *a, int n_bodies, hipStream_t s) {
+  if (n_bodies <= 0) return hipSuccess;
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(mdf_kernel<0>, dim3(n_bodies), dim3(MDF_THREADS), 0, s, *a); break;
+    case 1: hipLaunchKernelGGL(mdf_kernel<1>, dim3(n_bodies), dim3(MDF_THREADS), 0, s, *a); break;
+    case 2: hipLaunchKernelGGL(mdf_kernel<2>, dim3(n_bodies), dim3(MDF_THREADS), 0, s, *a); break;
+    case 3: hipLaunchKernelGGL(mdf_kernel<3>, dim3(n_bodies), dim3(MDF_THREADS), 0, s, *a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+extern "C" hipError_t sbt_launch_reduce(const double *partial, int n_blocks, double vol, double *out,
+                                        int accumulate, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(256), 0, s, partial, n_blocks, vol, out, accumulate);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t sbt_launch_init(int storage, const BlockMeta *meta, const uint16_t *codes,
+                                      const CaseDev *cases, void *lat, int b0, int n,
+                                      const double *fields, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  switch (storage) {
+    case 0: hipLaunchKernelGGL(init_kernel<0>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields); break;
+    case 1: hipLaunchKernelGGL(init_kernel<1>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields); break;
+    case 2: hipLaunchKernelGGL(init_kernel<2>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields); break;
+    case 3: hipLaunchKernelGGL(init_kernel<3>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+extern "C" hipError_t sbt_launch_fill_nan(void *p, size_t n, int storage, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  dim3 grid((unsigned)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536));
+  switch (storage) {
+    case 0:
+      hipLaunchKernelGGL(fill_nan_kernel<double>, grid, dim3(256), 0, s, (double *)p, n,
+                         (double)__builtin_nan(""));
+      break;
+    case 1:
+      hipLaunchKernelGGL(fill_nan_kernel<float>, grid, dim3(256), 0, s, (float *)p, n,
+                         (float)__builtin_nanf(""));
+      break;
+    case 2:
+    case 3:  // 0x7e00 is a quiet NaN in FP16; 0x7fc0 in BF16
+      hipLaunchKernelGGL(fill_nan_kernel<uint16_t>, grid, dim3(256), 0, s, (uint16_t *)p, n,
+                         (uint16_t)(storage == 2 ? 0x7e00 : 0x7fc0));
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}

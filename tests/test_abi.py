@@ -1,0 +1,79 @@
+"""CPU tests of the C-ABI library: it loads, exports every declared symbol,
+and its host-side forest builder validates descriptors (no GPU call)."""
+import os
+import re
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2402_04606_amd as P
+    P.lib()
+    return P
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "sbt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sbt_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree(pkg):
+    assert declared_symbols() == sorted(pkg.ABI_SYMBOLS)
+
+
+def test_library_exports_every_symbol(pkg):
+    L = pkg.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def test_plan_sizes(pkg):
+    small = pkg.plan([W.tgv(64)], pkg.F64)
+    assert small > 2 * 9 * 64 * 64 * 8
+    assert pkg.plan([W.tgv(64)], pkg.F16S) < small
+    big = pkg.plan(W.batch_sweep(), pkg.F16S)
+    assert big > 256 * 2 ** 20          # larger than the 256 MB Infinity Cache
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(boxes=[(1, 0, 0, 4, 4)], n_levels=2, body=None), -2),       # touches a wall
+    (dict(boxes=[(1, 12, 12, 20, 20), (2, 22, 22, 42, 42)]), -2),     # level 2 not nested
+    (dict(boxes=[(1, 12, 12, 20, 20), (2, 24, 24, 40, 40)]), -2),     # no 2:1 margin
+    (dict(boxes=[(3, 1, 1, 2, 2)]), -2),                              # level beyond n_levels
+    (dict(tau0=0.5), -1),
+    (dict(nx0=250), -1),
+    (dict(bc=(0, 1, 1, 1)), -1),                                      # unpaired periodic edge
+])
+def test_plan_rejects_invalid(pkg, bad, code):
+    wl = W.cavity().replace(**bad)
+    with pytest.raises(pkg.SbtError) as e:
+        pkg.plan([wl])
+    assert e.value.code == code
+
+
+def test_plan_rejects_mixed_storage(pkg):
+    import ctypes as C
+    arr = (pkg.CaseDesc * 2)()
+    d0, k0 = pkg.make_desc(W.tgv(32), pkg.F64)
+    d1, k1 = pkg.make_desc(W.tgv(32), pkg.F32)
+    arr[0], arr[1] = d0, d1
+    n = C.c_size_t()
+    assert pkg.lib().sbt_plan(arr, 2, C.byref(n)) == -1
+
+
+def test_rescale_rejects_unit_tau(pkg):
+    wl = W.tgv_patch(m=2, tau=1.0, cf_mode=W.CF_RESCALE)
+    with pytest.raises(pkg.SbtError):
+        pkg.plan([wl])
+
+
+def test_valid_configs_plan(pkg):
+    for wl in (W.cylinder(), W.cavity(), W.flapping_ellipse(), W.tgv_band(), W.tgv_patch(m=3),
+               W.small_refined_flap(), W.uniform_refined()):
+        assert pkg.plan([wl], pkg.F32) > 0

@@ -1,0 +1,297 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the
+same seeded inputs.  Tolerances: FP64 relative L2 of velocity <= 1e-12 (and
+bit-exact where the operation order is the paper's); reduced-precision
+storage forms have stated ceilings."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import oracle
+    import paper_2402_04606_amd as P
+    P.lib()
+    return P, oracle
+
+
+def rel_l2(ug, vg, uo, vo):
+    m = ~np.isnan(uo)
+    assert m.sum() > 0
+    assert not np.isnan(ug[m]).any(), "GPU field has NaN where the oracle has values"
+    assert np.isnan(ug[~m]).all(), "GPU field defined where the oracle has no owned cell"
+    num = np.sqrt(((ug[m] - uo[m]) ** 2 + (vg[m] - vo[m]) ** 2).sum())
+    den = np.sqrt((uo[m] ** 2 + vo[m] ** 2).sum())
+    # a level still at rest has |u| ~ roundoff; measure it against 1e-8 per cell
+    return num / max(den, 1e-8 * np.sqrt(m.sum()))
+
+
+def run_pair(env, wl, steps, storage="f64", **kw):
+    P, O = env
+    print(f"case {wl.name} storage {storage} steps {steps}", flush=True)
+    g = P.Sim(wl, storage, **kw)
+    o = O.OracleSim(wl)
+    g.step(steps)
+    g.synchronize()
+    o.step(steps)
+    return g, o
+
+
+def compare_levels(g, o, wl, tol, c=0):
+    errs = []
+    for l in range(wl.n_levels):
+        rg, ug, vg = g.fields(c, l)
+        ro, uo, vo = o.fields(l)
+        e = rel_l2(ug, vg, uo, vo)
+        m = ~np.isnan(ro)
+        er = np.abs(rg[m] - ro[m]).max()
+        print(f"  level {l}: rel L2 u {e:.3e}  max |drho| {er:.3e}", flush=True)
+        errs.append(e)
+        assert e <= tol, (l, e)
+        assert er <= max(tol, 1e-15) * 10, (l, er)
+    return errs
+
+
+# ---- uniform grids ---------------------------------------------------------
+
+def test_tgv_f64_matches_oracle(env):
+    wl = W.tgv(64)
+    g, o = run_pair(env, wl, 1000)
+    compare_levels(g, o, wl, TOL64)
+    # and the closed-form decay (P7) holds on the GPU as well
+    _, u, _ = g.fields(0, 0)
+    _, ua, _ = wl.init(0, 64, 64)
+    fac = math.exp(-2 * wl.meta["nu"] * wl.meta["k"] ** 2 * 1000)
+    assert np.sqrt(((u - fac * ua) ** 2).sum() / ((fac * ua) ** 2).sum()) < 1e-2
+
+
+def test_blocks_equal_monolithic_bitwise(env):
+    """P10: 16x16 blocks reproduce the dense grid bit for bit (FP64)."""
+    wl = W.tgv(48, tau=0.7)
+    g, o = run_pair(env, wl, 200)
+    rg, ug, vg = g.fields(0, 0)
+    ro, uo, vo = o.fields(0)
+    print("  max |du|", np.abs(ug - uo).max(), flush=True)
+    assert np.array_equal(ug, uo) and np.array_equal(vg, vo) and np.array_equal(rg, ro)
+
+
+def test_poiseuille_and_body_force(env):
+    wl = W.poiseuille(nx=32, ny=32)
+    g, o = run_pair(env, wl, 3000)
+    compare_levels(g, o, wl, TOL64)
+
+
+def test_couette_moving_wall(env):
+    wl = W.Workload(name="couette", nx0=32, ny0=48, tau0=0.9, bc=(0, 0, W.WALL, W.WALL),
+                    bc_u=((0, 0), (0, 0), (0, 0), (0.01, 0.0)), init=W.uniform_init(1.0, 0, 0))
+    g, o = run_pair(env, wl, 2000)
+    compare_levels(g, o, wl, TOL64)
+
+
+def test_open_boundaries_and_corners(env):
+    """Inflow, outflow, symmetry edges with a disturbance crossing them."""
+    wl = W.Workload(name="open", nx0=64, ny0=48, tau0=0.62,
+                    bc=(W.INFLOW, W.OUTFLOW, W.SYMMETRY, W.SYMMETRY),
+                    bc_u=((0.04, 0.0),) + ((0.0, 0.0),) * 3, init=W.tgv_init(64, 0.02, 1.0))
+    g, o = run_pair(env, wl, 400)
+    compare_levels(g, o, wl, TOL64)
+
+
+def test_cavity_walls_uniform(env):
+    wl = W.Workload(name="cavity_uniform", nx0=64, ny0=64, tau0=0.6, bc=(W.WALL,) * 4,
+                    bc_u=((0, 0), (0, 0), (0, 0), (0.1, 0.0)), init=W.uniform_init(1.0, 0, 0))
+    g, o = run_pair(env, wl, 500)
+    compare_levels(g, o, wl, TOL64)
+
+
+def test_cylinder_small_ibm(env):
+    wl = W.small_cylinder()
+    g, o = run_pair(env, wl, 300)
+    compare_levels(g, o, wl, TOL64)
+    fxg, fyg = g.force_history()
+    fxo, fyo = o.force_history()
+    assert len(fxg) == len(fxo) == 300
+    d = np.abs(fxg - fxo).max() / np.abs(fxo).max()
+    print("  force history rel diff", d, flush=True)
+    assert d <= TOL64
+    mg, mo = g.marker_forces(), o.marker_forces()
+    assert np.abs(mg[0] - mo[0]).max() <= TOL64 * np.abs(mo[0]).max()
+
+
+def test_cylinder_full_size_short_horizon(env):
+    """Workload C2 (1024x512, D 40, 126 markers) at a short horizon."""
+    wl = W.cylinder()
+    g, o = run_pair(env, wl, 60)
+    compare_levels(g, o, wl, TOL64)
+    fxg, _ = g.force_history()
+    fxo, _ = o.force_history()
+    assert np.abs(fxg - fxo).max() <= TOL64 * np.abs(fxo).max()
+
+
+# ---- refinement ------------------------------------------------------------
+
+@pytest.mark.parametrize("m,cf", [(2, 0), (3, 0), (2, 1), (3, 1)])
+def test_refined_patch_tgv(env, m, cf):
+    wl = W.tgv_patch(m=m, cf_mode=cf)
+    g, o = run_pair(env, wl, 40)
+    compare_levels(g, o, wl, TOL64)
+    dg, do = g.diagnostics(), o.diagnostics()
+    assert abs(dg[0] - do[0]) <= 1e-12 * do[0]
+
+
+def test_refined_band_mass(env):
+    wl = W.tgv_band()
+    g, o = run_pair(env, wl, 60)
+    compare_levels(g, o, wl, TOL64)
+
+
+def test_uniform_flow_refined_stays_uniform(env):
+    wl = W.uniform_refined()
+    g, o = run_pair(env, wl, 10)
+    compare_levels(g, o, wl, TOL64)
+
+
+def test_cavity_three_levels_ibm(env):
+    """Workload C3: 3 levels, lid, rescaled interfaces, cylinder D 128 finest."""
+    wl = W.cavity()
+    g, o = run_pair(env, wl, 6)
+    compare_levels(g, o, wl, TOL64)
+    fxg, _ = g.force_history()
+    fxo, _ = o.force_history()
+    assert len(fxg) == len(fxo) == 24
+    assert np.abs(fxg - fxo).max() <= 1e-11 * np.abs(fxo).max()
+
+
+def test_moving_body_refined(env):
+    wl = W.small_refined_flap()
+    g, o = run_pair(env, wl, 8)
+    compare_levels(g, o, wl, TOL64)
+    fxg, fyg = g.force_history()
+    fxo, fyo = o.force_history()
+    assert len(fxg) == len(fxo)
+    assert np.abs(fyg - fyo).max() <= 1e-11 * np.abs(fyo).max()
+
+
+def test_flapping_ellipse_four_levels(env):
+    """Workload C4 (4 levels, 200 moving markers) at a short horizon."""
+    wl = W.flapping_ellipse()
+    g, o = run_pair(env, wl, 2)
+    compare_levels(g, o, wl, TOL64)
+
+
+# ---- batch -------------------------------------------------------------------
+
+def test_batch_matches_cases_run_alone(env):
+    """Cases of 1, 2 and 3 levels in one context: each equals its own oracle
+    run over 2^(V-m) of its coarse steps per batch step."""
+    P, O = env
+    cases = [W.tgv_patch(m=3), W.tgv_patch(m=2, cf_mode=1), W.tgv(32, tau=0.7), W.small_cylinder()]
+    g = P.Sim(cases, "f64")
+    steps = 3
+    g.step(steps)
+    g.synchronize()
+    V = max(c.n_levels for c in cases)
+    for k, wl in enumerate(cases):
+        o = O.OracleSim(wl)
+        o.step(steps * 2 ** (V - wl.n_levels))
+        print(f"batch case {k} {wl.name}", flush=True)
+        compare_levels(g, o, wl, TOL64, c=k)
+
+
+# ---- precision forms ---------------------------------------------------------
+
+@pytest.mark.parametrize("storage,ceiling", [("f32", 2e-5), ("f16s", 3e-3), ("bf16s", 3e-2)])
+def test_reduced_precision_error_ceiling(env, storage, ceiling):
+    wl = W.tgv(64)
+    g, o = run_pair(env, wl, 500, storage)
+    compare_levels(g, o, wl, ceiling)
+
+
+@pytest.mark.parametrize("storage,ceiling", [("f32", 1e-4), ("f16s", 2e-2)])
+def test_reduced_precision_refined_ibm(env, storage, ceiling):
+    wl = W.cavity()
+    g, o = run_pair(env, wl, 30, storage)
+    compare_levels(g, o, wl, ceiling)
+
+
+# ---- engine behaviour ----------------------------------------------------------
+
+def test_determinism_graph_eager_and_tiles(env):
+    P, _ = env
+    wl = W.small_refined_flap()
+    outs = []
+    for graph, tile in ((1, 0), (1, 0), (0, 0), (1, 1), (1, 2)):
+        g = P.Sim(wl, "f64")
+        g.set_option(P.OPT_GRAPH, graph)
+        g.set_option(P.OPT_TILE, tile)
+        g.step(3)
+        g.synchronize()
+        outs.append([g.fields(0, l) for l in range(wl.n_levels)] + [g.force_history()])
+        g.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y, equal_nan=True)
+
+
+def test_checkpoint_resume_bitwise(env):
+    P, _ = env
+    wl = W.small_refined_flap()
+    a = P.Sim(wl, "f32")
+    a.step(2)
+    st = a.read_state()
+    a.step(3)
+    ref = [a.fields(0, l) for l in range(wl.n_levels)] + [a.force_history()]
+    b = P.Sim(wl, "f32")
+    b.write_state(st)
+    b.step(3)
+    got = [b.fields(0, l) for l in range(wl.n_levels)] + [b.force_history()]
+    for x, y in zip(ref, got):
+        for p, q in zip(x, y):
+            assert np.array_equal(p, q, equal_nan=True)
+
+
+def test_nonfinite_detected(env):
+    P, _ = env
+    wl = W.tgv(32)
+    g = P.Sim(wl, "f64")
+    rho, u, v = wl.init(0, 32, 32)
+    rho = rho.copy()
+    rho[5, 7] = np.nan
+    g.init_fields(0, 0, rho, u, v)
+    g.step(1)
+    with pytest.raises(P.SbtError) as e:
+        g.synchronize()
+    assert e.value.code == -6
+
+
+def test_marker_outside_finest_level(env):
+    P, _ = env
+    wl = W.small_refined_flap()
+    b = wl.body
+    params = list(b.params)
+    params[0] = 4.0        # pivot next to the domain edge, far outside the finest level
+    bad = wl.replace(body=W.Body(b.kind, b.xb, b.yb, b.ds, params))
+    g = P.Sim(bad, "f64")
+    g.step(1)
+    with pytest.raises(P.SbtError) as e:
+        g.synchronize()
+    assert e.value.code == -7
+
+
+def test_diagnostics_match_oracle(env):
+    wl = W.tgv_patch(m=3)
+    g, o = run_pair(env, wl, 20)
+    dg, do = g.diagnostics(), o.diagnostics()
+    assert abs(dg[0] - do[0]) <= 1e-12 * do[0]
+    assert np.abs(dg[1:] - do[1:]).max() <= 1e-12 * do[0]

@@ -243,7 +243,7 @@ def batch_sweep(n_cases=64, seed=4606):
     rng = np.random.default_rng(seed)
     out = []
     while len(out) < n_cases:
-        nx0 = int(rng.integers(256 // 16, 1024 // 16 + 1)) * 16
+        nx0 = int(rng.integers(256 // 32, 1024 // 32 + 1)) * 32    # ny0 = nx0/2 stays a block multiple
         m = int(rng.integers(2, 5))
         amp = float(rng.uniform(10.0, 64.0))
         Re = float(math.exp(rng.uniform(math.log(100.0), math.log(1000.0))))
@@ -280,6 +280,6 @@ def small_cylinder(nx=128, ny=64, D=12.0, n_markers=38, U=0.05, Re=40.0):
 
 def small_refined_flap(Re=100.0, m=3):
     """A small moving-body case on a refined forest (parity-test size)."""
-    wl = flapping_case(128, m, 40.0, Re, 60, 2.5 * math.pi, name=f"small_flap{m}")
+    wl = flapping_case(256, m, 40.0, Re, 60, 2.5 * math.pi, name=f"small_flap{m}")
     assert wl is not None
     return wl
