@@ -145,6 +145,9 @@ sbt_status sbt_level_info(sbt_ctx *ctx, int32_t c, int32_t level, int64_t out[4]
  * initial (pre-collision) state: force history and substep count restart. */
 sbt_status sbt_init_fields(sbt_ctx *ctx, int32_t c, int32_t level, const double *rho,
                            const double *ux, const double *uy);
+/* f = f^eq(rho, (ux, uy)) on every owned cell of every level of a case (a
+ * uniform initial state); same state semantics as sbt_init_fields. */
+sbt_status sbt_init_uniform(sbt_ctx *ctx, int32_t c, double rho, double ux, double uy);
 /* Attach a body to a case (copied in).  Only before the first sbt_step after
  * create/init.  n <= max_markers. */
 sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body);
@@ -161,6 +164,10 @@ sbt_status sbt_synchronize(sbt_ctx *ctx);
  * other cells.  Dense FP64 arrays.  Synchronises. */
 sbt_status sbt_read_fields(sbt_ctx *ctx, int32_t c, int32_t level, double *rho, double *ux,
                            double *uy);
+/* As sbt_read_fields, in block order: out[n_blocks][3][256] holds rho, ux,
+ * uy of the blocks sbt_level_blocks lists (NaN on cells covered by the finer
+ * level).  Synchronises. */
+sbt_status sbt_read_fields_blocks(sbt_ctx *ctx, int32_t c, int32_t level, double *out);
 /* Total MDF force F_j of every marker at the last completed finest substep
  * (sum over the N_F iterations of Eq. (11)). */
 sbt_status sbt_read_marker_forces(sbt_ctx *ctx, int32_t c, double *fx, double *fy);
@@ -194,9 +201,10 @@ sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path);
 /* Run n steps eagerly with HIP events around every launch, on the context's
  * stream.  out[0] = total ms of level (collide+stream) kernels, out[1] = their
  * launch count, out[2] = total ms of MDF kernels, out[3] = their count,
- * out[4] = algorithmic bytes moved by the level kernels (2 Q s per update),
- * out[5] = cell updates. */
-sbt_status sbt_profile(sbt_ctx *ctx, int32_t n, double out[6]);
+ * out[4] = algorithmic bytes moved by the level kernels (2 Q s per cell
+ * update), out[5] = cell updates, out[6] = ms of the interior-block kernel,
+ * out[7] = its launch count, out[8] = its algorithmic bytes. */
+sbt_status sbt_profile(sbt_ctx *ctx, int32_t n, double out[9]);
 /* Cell updates performed per sbt_step, summed over cases and levels. */
 sbt_status sbt_updates_per_step(sbt_ctx *ctx, int64_t *updates);
 

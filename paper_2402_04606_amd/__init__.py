@@ -26,7 +26,8 @@ ERRORS = {-1: "ARG", -2: "TOPOLOGY", -3: "DEVICE", -4: "NOMEM", -5: "STATE", -6:
 # Every function include/sbt.h declares.
 ABI_SYMBOLS = [
     "sbt_plan", "sbt_create", "sbt_destroy", "sbt_level_blocks", "sbt_level_info", "sbt_init_fields",
-    "sbt_set_body", "sbt_step", "sbt_synchronize", "sbt_read_fields", "sbt_read_marker_forces",
+    "sbt_init_uniform", "sbt_set_body", "sbt_step", "sbt_synchronize", "sbt_read_fields",
+    "sbt_read_fields_blocks", "sbt_read_marker_forces",
     "sbt_read_force_history", "sbt_diagnostics", "sbt_state_bytes", "sbt_read_state",
     "sbt_write_state", "sbt_set_option", "sbt_autotune", "sbt_profile", "sbt_updates_per_step",
     "sbt_last_error",
@@ -79,6 +80,8 @@ def lib():
             "sbt_level_blocks": [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
             "sbt_level_info": [vp, i32, i32, C.POINTER(i64)],
             "sbt_init_fields": [vp, i32, i32, d, d, d],
+            "sbt_init_uniform": [vp, i32, C.c_double, C.c_double, C.c_double],
+            "sbt_read_fields_blocks": [vp, i32, i32, d],
             "sbt_set_body": [vp, i32, C.POINTER(Body)],
             "sbt_step": [vp, i32],
             "sbt_synchronize": [vp],
@@ -180,7 +183,10 @@ class Sim:
         self._h = h
         if init:
             for c, wl in enumerate(self.workloads):
-                if wl.init is not None:
+                uni = getattr(wl.init, "uniform_state", None)
+                if uni is not None:
+                    self.init_uniform(c, *uni)
+                elif wl.init is not None:
                     for l in range(wl.n_levels):
                         nx, ny = self.level_size(c, l)
                         r, u, v = wl.init(l, nx, ny)
@@ -231,6 +237,9 @@ class Sim:
         v = np.ascontiguousarray(np.broadcast_to(uy, (ny, nx)), dtype=np.float64)
         _check(lib().sbt_init_fields(self._h, c, l, _dp(r), _dp(u), _dp(v)))
 
+    def init_uniform(self, c, rho, ux, uy):
+        _check(lib().sbt_init_uniform(self._h, c, float(rho), float(ux), float(uy)))
+
     def set_body(self, c, body):
         xb, yb, ds = (np.ascontiguousarray(a, dtype=np.float64) for a in (body.xb, body.yb, body.ds))
         b = Body()
@@ -253,6 +262,13 @@ class Sim:
         r, u, v = (np.empty((ny, nx)) for _ in range(3))
         _check(lib().sbt_read_fields(self._h, c, l, _dp(r), _dp(u), _dp(v)))
         return r, u, v
+
+    def fields_blocks(self, c, l):
+        """Fields in block order [n_blocks, 3, 16, 16] (rho, ux, uy)."""
+        n = self.level_info(c, l)["blocks"]
+        out = np.empty((n, 3, 16, 16))
+        _check(lib().sbt_read_fields_blocks(self._h, c, l, _dp(out)))
+        return out
 
     def marker_forces(self, c=0):
         n = len(self.workloads[c].body.xb)
@@ -293,7 +309,8 @@ class Sim:
         _check(lib().sbt_autotune(self._h, steps, cache_path.encode() if cache_path else None))
 
     def profile(self, n):
-        out = np.zeros(6)
+        out = np.zeros(9)
         _check(lib().sbt_profile(self._h, n, _dp(out)))
         return dict(level_ms=out[0], level_launches=int(out[1]), mdf_ms=out[2],
-                    mdf_launches=int(out[3]), level_bytes=out[4], updates=out[5])
+                    mdf_launches=int(out[3]), level_bytes=out[4], updates=out[5],
+                    fast_ms=out[6], fast_launches=int(out[7]), fast_bytes=out[8])

@@ -127,6 +127,7 @@ sbt_status build_forest(const sbt_case_desc &d, Forest &F) {
   if (d.cf_mode != SBT_CF_HOMOGENEOUS && d.cf_mode != SBT_CF_RESCALE) return fail(SBT_ERR_ARG, "bad cf_mode");
   if (d.max_markers < 0 || d.mdf_iters < 0) return fail(SBT_ERR_ARG, "negative marker count or N_F");
   if (d.max_markers > 0 && d.history_cap <= 0) return fail(SBT_ERR_ARG, "history_cap must be positive");
+  if (d.max_markers > kMaxMarkers) return fail(SBT_ERR_ARG, "at most 1024 markers per body");
   if (d.n_refine < 0 || (d.n_refine > 0 && !d.refine)) return fail(SBT_ERR_ARG, "bad refine list");
   F.m = d.n_levels;
   F.per_x = d.bc[0] == SBT_BC_PERIODIC;
@@ -220,8 +221,10 @@ struct Pool {
   int n_own = 0, n_ghost = 0;
   std::vector<BlockMeta> meta;
   std::vector<uint16_t> codes;
+  std::vector<int32_t> fast, slow, band;   // interior blocks, other owned blocks, halo-band cells
   BlockMeta *d_meta = nullptr;
   uint16_t *d_codes = nullptr;
+  int32_t *d_fast = nullptr, *d_slow = nullptr, *d_band = nullptr;
   void *lat[2] = {nullptr, nullptr};
   int cur = 0;
   int total() const { return n_own + n_ghost; }
@@ -268,7 +271,7 @@ struct sbt_ctx {
   size_t bytes_used = 0;
   // profiling
   bool profiling = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_level, ev_mdf;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_level, ev_fast, ev_mdf;
   double prof_bytes = 0.0, prof_updates = 0.0;
 };
 
@@ -348,6 +351,9 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
   for (auto &P : X.pools) {
     P.d_meta = (BlockMeta *)cv.take(sizeof(BlockMeta) * P.total());
     P.d_codes = (uint16_t *)cv.take(sizeof(uint16_t) * std::max<size_t>(1, P.codes.size()));
+    P.d_fast = (int32_t *)cv.take(sizeof(int32_t) * std::max<size_t>(1, P.fast.size()));
+    P.d_slow = (int32_t *)cv.take(sizeof(int32_t) * std::max<size_t>(1, P.slow.size()));
+    P.d_band = (int32_t *)cv.take(sizeof(int32_t) * std::max<size_t>(1, P.band.size()));
     P.lat[0] = cv.take(s * kQ * kCells * (size_t)P.total());
     P.lat[1] = cv.take(s * kQ * kCells * (size_t)P.total());
   }
@@ -369,12 +375,6 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     D.xb = (double *)cv.take(sizeof(double) * N);
     D.yb = (double *)cv.take(sizeof(double) * N);
     D.ds = (double *)cv.take(sizeof(double) * N);
-    D.X = (double *)cv.take(sizeof(double) * N);
-    D.Y = (double *)cv.take(sizeof(double) * N);
-    D.udx = (double *)cv.take(sizeof(double) * N);
-    D.udy = (double *)cv.take(sizeof(double) * N);
-    D.dFx = (double *)cv.take(sizeof(double) * N);
-    D.dFy = (double *)cv.take(sizeof(double) * N);
     D.ftot = (double *)cv.take(sizeof(double) * 4 * N);
     D.hist = (double *)cv.take(sizeof(double) * 2 * C.hist_cap);
     D.kcount = (int64_t *)cv.take(sizeof(int64_t));
@@ -384,6 +384,8 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     D.wU = (double *)cv.take(sizeof(double) * 2 * C.win_cap);
     D.wCnt = (int32_t *)cv.take(sizeof(int32_t) * C.win_cap);
     D.wList = (int32_t *)cv.take(sizeof(int32_t) * kMaxContrib * (size_t)C.win_cap);
+    D.sCells = (int32_t *)cv.take(sizeof(int32_t) * (size_t)C.win_cap);
+    D.sCount = (int32_t *)cv.take(sizeof(int32_t));
     D.bmap = (const int32_t *)cv.take(sizeof(int32_t) * (size_t)D.bm_w * D.bm_h);
   }
   return SBT_OK;
@@ -518,6 +520,25 @@ void build_tables(sbt_ctx &X) {
     D.hist_cap = (int32_t)C.hist_cap;
     D.win_cap = C.win_cap;
   }
+  // launch lists: interior blocks take the LDS-staged kernel
+  for (auto &P : X.pools) {
+    P.fast.clear();
+    P.slow.clear();
+    P.band.clear();
+    for (int b = 0; b < P.n_own; ++b) {
+      const BlockMeta &M = P.meta[b];
+      bool all_nbr = true;
+      for (int d = 0; d < 8; ++d) all_nbr &= M.nbr[d] >= 0;
+      if (!(M.flags & (BF_CODES | BF_EDGE)) && all_nbr) P.fast.push_back(b);
+      else P.slow.push_back(b);
+    }
+    for (int b = P.n_own; b < P.total(); ++b) {
+      const BlockMeta &M = P.meta[b];
+      if (!(M.flags & BF_CODES)) continue;
+      for (int cell = 0; cell < kCells; ++cell)
+        if (P.codes[(size_t)M.code * kCells + cell] & CC_BAND) P.band.push_back(b * kCells + cell);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -574,22 +595,54 @@ sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
     a.fcur = Q.lat[Q.cur];
   }
   a.cases = X.d_cases;
-  a.b0 = 0;
-  a.n_blocks = (mode == 0 && p == 1) ? P.total() : P.n_own;
   a.mode = mode;
   a.xcd_remap = X.xcd;
   a.err = X.d_err;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (X.profiling) {
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, s));
+  auto timed = [&](bool fast, auto &&launch) -> sbt_status {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (X.profiling) {
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventCreate(&e1));
+      HIPCHK(hipEventRecord(e0, s));
+    }
+    HIPCHK(launch());
+    if (X.profiling) {
+      HIPCHK(hipEventRecord(e1, s));
+      (fast ? X.ev_fast : X.ev_level).push_back({e0, e1});
+    }
+    return SBT_OK;
+  };
+  sbt_status st = SBT_OK;
+  if (mode == 0) {
+    if (!P.fast.empty()) {
+      LevelArgs f = a;
+      f.list = P.d_fast;
+      f.n_blocks = (int)P.fast.size();
+      st = timed(true, [&] { return sbt_launch_level_fast(X.storage, 0, &f, s); });
+      if (st) return st;
+    }
+    if (!P.slow.empty()) {
+      LevelArgs g = a;
+      g.list = P.d_slow;
+      g.n_blocks = (int)P.slow.size();
+      st = timed(false, [&] { return sbt_launch_level_fast(X.storage, 1, &g, s); });
+      if (st) return st;
+    }
+    if (p == 1 && !P.band.empty()) {
+      LevelArgs g = a;
+      g.list = nullptr;
+      g.n_blocks = 0;
+      g.band = P.d_band;
+      g.n_band = (int)P.band.size();
+      st = timed(false, [&] { return sbt_launch_level(X.storage, X.tile, &g, s); });
+    }
+  } else {
+    a.list = nullptr;
+    a.b0 = 0;
+    a.n_blocks = P.n_own;
+    st = timed(false, [&] { return sbt_launch_level(X.storage, X.tile, &a, s); });
   }
-  HIPCHK(sbt_launch_level(X.storage, X.tile, &a, s));
-  if (X.profiling) {
-    HIPCHK(hipEventRecord(e1, s));
-    X.ev_level.push_back({e0, e1});
-  }
+  if (st) return st;
   P.cur = 1 - P.cur;
   return SBT_OK;
 }
@@ -604,6 +657,8 @@ sbt_status launch_mdf(sbt_ctx &X, bool first, hipStream_t s) {
   a.body_cases = X.d_body_cases;
   a.first = first ? 1 : 0;
   a.err = X.d_err;
+  a.max_markers = 0;
+  for (auto &C : X.cs) a.max_markers = std::max(a.max_markers, C.n_markers);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (X.profiling) {
     HIPCHK(hipEventCreate(&e0));
@@ -715,6 +770,7 @@ sbt_status readout_level(sbt_ctx &X, int c, int l, hipStream_t s) {
     a.fcur = Q.lat[Q.cur];
   }
   a.cases = X.d_cases;
+  a.list = nullptr;
   a.b0 = C.lr[l].own0;
   a.n_blocks = C.lr[l].own1 - C.lr[l].own0;
   a.mode = MODE_READOUT | (X.post ? 0 : MODE_LOCAL);
@@ -800,6 +856,14 @@ sbt_status sbt_create(const sbt_case_desc *cases, int32_t n_cases, void *device_
         hipMemcpyAsync(P.d_codes, P.codes.data(), sizeof(uint16_t) * P.codes.size(), hipMemcpyHostToDevice, s) !=
             hipSuccess)
       return cleanup_fail(fail(SBT_ERR_DEVICE, "code upload"));
+    bool ok = true;
+    if (!P.fast.empty())
+      ok &= hipMemcpyAsync(P.d_fast, P.fast.data(), sizeof(int32_t) * P.fast.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    if (!P.slow.empty())
+      ok &= hipMemcpyAsync(P.d_slow, P.slow.data(), sizeof(int32_t) * P.slow.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    if (!P.band.empty())
+      ok &= hipMemcpyAsync(P.d_band, P.band.data(), sizeof(int32_t) * P.band.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    if (!ok) return cleanup_fail(fail(SBT_ERR_DEVICE, "list upload"));
     size_t n = (size_t)P.total() * kQ * kCells;
     if (sbt_launch_fill_nan(P.lat[0], n, X->storage, s) != hipSuccess ||
         sbt_launch_fill_nan(P.lat[1], n, X->storage, s) != hipSuccess)
@@ -818,7 +882,7 @@ sbt_status sbt_create(const sbt_case_desc *cases, int32_t n_cases, void *device_
     return cleanup_fail(fail(SBT_ERR_DEVICE, "memset"));
   if (reset_counters(*X)) return cleanup_fail(SBT_ERR_DEVICE);
   for (auto &P : X->pools) {
-    if (sbt_launch_init(X->storage, P.d_meta, P.d_codes, X->d_cases, P.lat[0], 0, P.n_own, nullptr, s) !=
+    if (sbt_launch_init(X->storage, P.d_meta, P.d_codes, X->d_cases, P.lat[0], 0, P.n_own, nullptr, nullptr, s) !=
         hipSuccess)
       return cleanup_fail(fail(SBT_ERR_DEVICE, "init"));
   }
@@ -899,7 +963,7 @@ sbt_status sbt_init_fields(sbt_ctx *ctx, int32_t c, int32_t level, const double 
       size_t n = (size_t)P.total() * kQ * kCells;
       HIPCHK(sbt_launch_fill_nan(P.lat[0], n, X.storage, X.stream));
       HIPCHK(sbt_launch_fill_nan(P.lat[1], n, X.storage, X.stream));
-      HIPCHK(sbt_launch_init(X.storage, P.d_meta, P.d_codes, X.d_cases, P.lat[0], 0, P.n_own, nullptr, X.stream));
+      HIPCHK(sbt_launch_init(X.storage, P.d_meta, P.d_codes, X.d_cases, P.lat[0], 0, P.n_own, nullptr, nullptr, X.stream));
     }
     if (reset_counters(X)) return SBT_ERR_DEVICE;
   }
@@ -912,9 +976,36 @@ sbt_status sbt_init_fields(sbt_ctx *ctx, int32_t c, int32_t level, const double 
                           hipMemcpyHostToDevice, X.stream));
     Pool &P = X.pools[C.lr[level].v];
     HIPCHK(sbt_launch_init(X.storage, P.d_meta, P.d_codes, X.d_cases, P.lat[0], C.lr[level].own0 + (int)k0,
-                           (int)(k1 - k0), X.d_stage, X.stream));
+                           (int)(k1 - k0), X.d_stage, nullptr, X.stream));
     HIPCHK(hipStreamSynchronize(X.stream));
   }
+  return SBT_OK;
+}
+
+sbt_status sbt_init_uniform(sbt_ctx *ctx, int32_t c, double rho, double ux, double uy) {
+  sbt_status st = check_case(ctx, c);
+  if (st) return st;
+  if (!(rho > 0.0)) return fail(SBT_ERR_ARG, "rho must be positive");
+  sbt_ctx &X = *ctx;
+  CaseHost &C = X.cs[c];
+  HIPCHK(hipStreamSynchronize(X.stream));
+  if (X.post) {
+    for (auto &P : X.pools) {
+      size_t n = (size_t)P.total() * kQ * kCells;
+      HIPCHK(sbt_launch_fill_nan(P.lat[0], n, X.storage, X.stream));
+      HIPCHK(sbt_launch_fill_nan(P.lat[1], n, X.storage, X.stream));
+      HIPCHK(sbt_launch_init(X.storage, P.d_meta, P.d_codes, X.d_cases, P.lat[0], 0, P.n_own, nullptr, nullptr,
+                             X.stream));
+    }
+    if (reset_counters(X)) return SBT_ERR_DEVICE;
+  }
+  double u0[3] = {rho, ux, uy};
+  for (int l = 0; l < C.F.m; ++l) {
+    Pool &P = X.pools[C.lr[l].v];
+    HIPCHK(sbt_launch_init(X.storage, P.d_meta, P.d_codes, X.d_cases, P.lat[0], C.lr[l].own0,
+                           C.lr[l].own1 - C.lr[l].own0, nullptr, u0, X.stream));
+  }
+  HIPCHK(hipStreamSynchronize(X.stream));
   return SBT_OK;
 }
 
@@ -1016,6 +1107,19 @@ sbt_status sbt_read_fields(sbt_ctx *ctx, int32_t c, int32_t level, double *rho, 
       uy[g] = host[(k * 3 + 2) * kCells + cell];
     }
   }
+  return SBT_OK;
+}
+
+sbt_status sbt_read_fields_blocks(sbt_ctx *ctx, int32_t c, int32_t level, double *out) {
+  sbt_status st = check_level(ctx, c, level);
+  if (st) return st;
+  if (!out) return fail(SBT_ERR_ARG, "null output");
+  sbt_ctx &X = *ctx;
+  st = readout_level(X, c, level, X.stream);
+  if (st) return st;
+  size_t n = X.cs[c].F.own[level].size();
+  HIPCHK(hipMemcpyAsync(out, X.d_stage, sizeof(double) * n * 3 * kCells, hipMemcpyDeviceToHost, X.stream));
+  HIPCHK(hipStreamSynchronize(X.stream));
   return SBT_OK;
 }
 
@@ -1198,46 +1302,56 @@ sbt_status sbt_set_option(sbt_ctx *ctx, int32_t option, int32_t value) {
   return SBT_OK;
 }
 
-sbt_status sbt_profile(sbt_ctx *ctx, int32_t n, double out[6]) {
+sbt_status sbt_profile(sbt_ctx *ctx, int32_t n, double out[9]) {
   if (!ctx || !out || n <= 0) return fail(SBT_ERR_ARG, "bad argument");
   sbt_ctx &X = *ctx;
   HIPCHK(hipStreamSynchronize(X.stream));
   X.profiling = true;
   X.ev_level.clear();
+  X.ev_fast.clear();
   X.ev_mdf.clear();
   sbt_status st = SBT_OK;
   if (!X.post) st = run_prologue(X, X.stream);
+  X.ev_level.clear();
+  X.ev_fast.clear();
+  X.ev_mdf.clear();
   for (int t = 0; t < n && !st; ++t) st = run_step_eager(X, X.stream);
   X.profiling = false;
   hipError_t e = hipStreamSynchronize(X.stream);
-  double tl = 0, tm = 0;
-  for (auto &p : X.ev_level) {
-    float ms = 0;
-    if (!st && e == hipSuccess) (void)hipEventElapsedTime(&ms, p.first, p.second);
-    tl += ms;
-    (void)hipEventDestroy(p.first);
-    (void)hipEventDestroy(p.second);
-  }
-  for (auto &p : X.ev_mdf) {
-    float ms = 0;
-    if (!st && e == hipSuccess) (void)hipEventElapsedTime(&ms, p.first, p.second);
-    tm += ms;
-    (void)hipEventDestroy(p.first);
-    (void)hipEventDestroy(p.second);
-  }
-  double nl = (double)X.ev_level.size(), nm = (double)X.ev_mdf.size();
-  X.ev_level.clear();
-  X.ev_mdf.clear();
+  auto total = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>> &ev) {
+    double t = 0;
+    for (auto &p : ev) {
+      float ms = 0;
+      if (!st && e == hipSuccess) (void)hipEventElapsedTime(&ms, p.first, p.second);
+      t += ms;
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+    double cnt = (double)ev.size();
+    ev.clear();
+    return std::make_pair(t, cnt);
+  };
+  auto fl = total(X.ev_fast), gl = total(X.ev_level), md = total(X.ev_mdf);
   if (st) return st;
   if (e != hipSuccess) return fail(SBT_ERR_DEVICE, hipGetErrorString(e));
   int64_t upd = 0;
   sbt_updates_per_step(ctx, &upd);
-  out[0] = tl;
-  out[1] = nl;
-  out[2] = tm;
-  out[3] = nm;
+  const double bpu = 2.0 * kQ * (double)storage_bytes(X.storage);
+  int64_t fast_cells = 0;
+  for (auto &P : X.pools) fast_cells += (int64_t)P.fast.size() * kCells;
+  // cell updates of the fast kernel per step: each pool runs 2^v times
+  double fast_upd = 0;
+  for (int v = 0; v < X.V; ++v) fast_upd += (double)X.pools[v].fast.size() * kCells * (double)(1 << v);
+  out[0] = fl.first + gl.first;
+  out[1] = fl.second + gl.second;
+  out[2] = md.first;
+  out[3] = md.second;
   out[5] = (double)upd * n;
-  out[4] = out[5] * 2.0 * kQ * (double)storage_bytes(X.storage);
+  out[4] = out[5] * bpu;
+  out[6] = fl.first;
+  out[7] = fl.second;
+  out[8] = fast_upd * n * bpu;
+  (void)fast_cells;
   return SBT_OK;
 }
 

@@ -10,6 +10,7 @@ constexpr int kB = 16;           // block edge in cells
 constexpr int kCells = kB * kB;  // cells per block
 constexpr int kMaxLevels = 6;
 constexpr int kMaxContrib = 32;  // markers whose 4x4 stencil may cover one cell
+constexpr int kMaxMarkers = 1024; // markers per body (one per lane of the MDF workgroup)
 
 // Block flags.
 enum : int32_t {
@@ -65,16 +66,16 @@ struct alignas(16) CaseDev {
   int32_t bm_x0, bm_y0, bm_w, bm_h;  // finest-level block map: origin and size (blocks)
   double bp[16];
   const double *xb, *yb, *ds;
-  double *X, *Y, *udx, *udy;   // marker state for the current substep
-  double *dFx, *dFy;           // marker force of the current MDF iteration
   double *ftot;                // [2 slots][2][n]: total marker force, slot = substep parity
   double *hist;                // [hist_cap][2]
   int64_t *kcount;             // finest substeps done
   IbmWindow *win;
   double *wF;                  // [2][win_cap]  force density in the window
   double *wRho, *wU;           // [win_cap], [2][win_cap]
-  int32_t *wCnt;               // [win_cap] contributing markers (-1: not a stencil cell)
-  int32_t *wList;              // [win_cap][kMaxContrib]
+  int32_t *wCnt;               // [win_cap] markers whose stencil covers the cell
+  int32_t *wList;              // [win_cap][kMaxContrib] those markers, ascending
+  int32_t *sCells;             // [win_cap] window index of each stencil cell (compact)
+  int32_t *sCount;             // number of stencil cells
   const int32_t *bmap;         // finest-level block map -> pool index (-1 outside)
 };
 
@@ -89,8 +90,11 @@ struct LevelArgs {
   const void *fprev;           // finer pool lattice read by its last substep
   void *fcur;                  // finer pool current lattice (explosion target)
   const CaseDev *cases;
-  int32_t b0;                  // first block of the launch
-  int32_t n_blocks;            // blocks launched: [b0, b0 + n_blocks)
+  const int32_t *list;         // blocks to process, or null for b0 .. b0 + n_blocks - 1
+  int32_t b0;
+  int32_t n_blocks;            // entries of list (or length of the range)
+  const int32_t *band;         // halo-band cells (block * 256 + cell), gathered after the blocks
+  int32_t n_band;
   int32_t mode;                // MODE_* bits
   int32_t xcd_remap;
   double *out;                 // readout: [block - b0][3][256] rho, ux, uy
@@ -104,6 +108,7 @@ struct MdfArgs {
   const CaseDev *cases;
   const int32_t *body_cases;   // case index per workgroup
   int32_t first;               // 1: local read (initial pre-collision state)
+  int32_t max_markers;         // sizes the workgroup's LDS marker tables
   int32_t *err;
 };
 
@@ -117,14 +122,22 @@ enum : int32_t { ERR_NONFINITE = 1, ERR_MARKER = 2, ERR_CONTRIB = 4, ERR_WINDOW 
 
 // Launchers implemented in sbt_kernels.hip.
 extern "C" {
+// Generic level kernel: any block (interfaces, domain edges, readout,
+// initial collision) and halo-band cells.
 hipError_t sbt_launch_level(int storage, int tile, const sbt::LevelArgs *a, hipStream_t s);
+// LDS-staged stream + collide for owned blocks.  slow = 0: interior blocks
+// (no cell codes, no domain edge, all eight neighbours present); slow = 1:
+// blocks next to a finer level or a domain edge.
+hipError_t sbt_launch_level_fast(int storage, int slow, const sbt::LevelArgs *a, hipStream_t s);
 hipError_t sbt_launch_mdf(int storage, const sbt::MdfArgs *a, int n_bodies, hipStream_t s);
+size_t sbt_mdf_lds_bytes(int max_markers);
 hipError_t sbt_launch_reduce(const double *partial, int n_blocks, double vol, double *out,
                              int accumulate, hipStream_t s);
 hipError_t sbt_launch_fill_nan(void *p, size_t n_elems, int storage, hipStream_t s);
 // f = f^eq(rho, u) on the owned cells of blocks [b0, b0+n) from per-block FP64
-// fields [n][3][256] (or rest at rho0 when fields is null).
+// fields [n][3][256], or from the constant state u0 = {rho, ux, uy} when
+// fields is null (u0 null: rest at rho0).
 hipError_t sbt_launch_init(int storage, const sbt::BlockMeta *meta, const uint16_t *codes,
                            const sbt::CaseDev *cases, void *lat, int b0, int n, const double *fields,
-                           hipStream_t s);
+                           const double *u0, hipStream_t s);
 }

@@ -72,23 +72,58 @@ template <> struct Store<3> {  // BF16 deviation, round to nearest even
   }
 };
 
-__device__ __forceinline__ int wrap(int a, int n) {
-  a %= n;
-  return a < 0 ? a + n : a;
+// Scalar (wave-uniform) context of one block: the workgroup's block id,
+// origin, level, flags and its 8 neighbours and 4 finer children, as named
+// scalars (no arrays, so a per-lane choice among them stays a value select
+// and never becomes an indexed load from private memory).
+struct Blk {
+  int self, ox, oy, level, flags, code, cid;
+  int nE, nN, nW, nS, nNE, nNW, nSW, nSE;
+  int c0, c1, c2, c3;
+};
+
+__device__ __forceinline__ Blk load_blk(const BlockMeta *meta, int b) {
+  Blk k;
+  const BlockMeta &m = meta[b];
+  k.self = b;
+  k.ox = m.ox;
+  k.oy = m.oy;
+  k.level = m.level;
+  k.flags = m.flags;
+  k.code = m.code;
+  k.cid = m.case_id;
+  k.nE = m.nbr[0]; k.nN = m.nbr[1]; k.nW = m.nbr[2]; k.nS = m.nbr[3];
+  k.nNE = m.nbr[4]; k.nNW = m.nbr[5]; k.nSW = m.nbr[6]; k.nSE = m.nbr[7];
+  k.c0 = m.child[0]; k.c1 = m.child[1]; k.c2 = m.child[2]; k.c3 = m.child[3];
+  return k;
 }
 
-// Neighbour block holding local cell (x, y), x, y in [-1, 16].
-__device__ __forceinline__ int nbr_of(const BlockMeta &m, int self, int x, int y) {
-  int ox = x < 0 ? -1 : (x > 15 ? 1 : 0);
-  int oy = y < 0 ? -1 : (y > 15 ? 1 : 0);
-  if (ox == 0 && oy == 0) return self;
-  // D2Q9 direction with velocity (ox, oy): 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE
+// Value select (both operands already loaded; a ?: on two fields would
+// select their address instead).
+__device__ __forceinline__ int vsel(bool c, int a, int b) { return c ? a : b; }
+
+// Block holding local cell (x, y), x, y in [-1, 16] (-1 if none).
+__device__ __forceinline__ int pick_nbr(const Blk &k, int x, int y) {
+  int w = vsel(y < 0, k.nSW, vsel(y > 15, k.nNW, k.nW));
+  int e = vsel(y < 0, k.nSE, vsel(y > 15, k.nNE, k.nE));
+  int c = vsel(y < 0, k.nS, vsel(y > 15, k.nN, k.self));
+  return vsel(x < 0, w, vsel(x > 15, e, c));
+}
+
+// Same, for a block known only per lane: the neighbour index is read from
+// the block table in memory.
+__device__ __forceinline__ int pick_nbr_mem(const BlockMeta *meta, int blk, int x, int y) {
   int d;
-  if (oy == 0) d = ox > 0 ? 1 : 3;
-  else if (ox == 0) d = oy > 0 ? 2 : 4;
-  else if (ox > 0) d = oy > 0 ? 5 : 8;
-  else d = oy > 0 ? 6 : 7;
-  return m.nbr[d - 1];
+  if (x < 0) d = y < 0 ? 6 : (y > 15 ? 5 : 2);
+  else if (x > 15) d = y < 0 ? 7 : (y > 15 ? 4 : 0);
+  else if (y < 0) d = 3;
+  else if (y > 15) d = 1;
+  else return blk;
+  return meta[blk].nbr[d];
+}
+
+__device__ __forceinline__ int pick_child(const Blk &k, int x, int y) {
+  return vsel(x < 8, vsel(y < 8, k.c0, k.c2), vsel(y < 8, k.c1, k.c3));
 }
 
 template <int ST>
@@ -102,13 +137,21 @@ __device__ __forceinline__ typename Store<ST>::C ldv(const void *lat, int blk, i
   return Store<ST>::ld(ldraw<ST>(lat, blk, q, cell));
 }
 
-// Post-collision value of direction q at local cell (x, y) of block `self`
-// (x, y may be one cell outside the block).  NaN if no block holds the cell.
+// Post-collision value of direction q at local cell (x, y) of the block in
+// context k (x, y may be one cell outside it).  NaN if no block holds it.
 template <int ST>
-__device__ __forceinline__ typename Store<ST>::C fetch(const void *lat, const BlockMeta &m, int self,
-                                                     int x, int y, int q) {
+__device__ __forceinline__ typename Store<ST>::C fetch(const void *lat, const Blk &k, int x, int y, int q) {
   using C = typename Store<ST>::C;
-  int nb = nbr_of(m, self, x, y);
+  int nb = pick_nbr(k, x, y);
+  if (nb < 0) return C(__builtin_nan(""));
+  return ldv<ST>(lat, nb, q, (y & 15) * 16 + (x & 15));
+}
+
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::C fetch_mem(const void *lat, const BlockMeta *meta, int blk,
+                                                         int x, int y, int q) {
+  using C = typename Store<ST>::C;
+  int nb = pick_nbr_mem(meta, blk, x, y);
   if (nb < 0) return C(__builtin_nan(""));
   return ldv<ST>(lat, nb, q, (y & 15) * 16 + (x & 15));
 }
@@ -145,7 +188,7 @@ struct Collide;
 
 template <>
 struct Collide<0> {
-  __device__ static void run(const CaseDev &cp, int l, double f[9], double Fx, double Fy, double &rho,
+  __device__ __forceinline__ static void run(const CaseDev &cp, int l, double f[9], double Fx, double Fy, double &rho,
                              double &ux, double &uy) {
 #pragma clang fp contract(off)
     double jx, jy;
@@ -174,7 +217,7 @@ struct Collide<0> {
 template <int ST>
 struct Collide {
   // deviation form: f = w rho0 + d;  rho = rho0 + sum d;  sum c f = sum c d
-  __device__ static void run(const CaseDev &cp, int l, float d[9], float Fx, float Fy, float &rho,
+  __device__ __forceinline__ static void run(const CaseDev &cp, int l, float d[9], float Fx, float Fy, float &rho,
                              float &ux, float &uy) {
     float drho = 0.f, jx = 0.f, jy = 0.f;
 #pragma unroll
@@ -240,8 +283,8 @@ __device__ __forceinline__ void frame_moments(const CaseDev &cp, const typename 
 // Unknown population q of cell (x, y) (local coordinates of block `self`,
 // level-0 global cell (gx, gy)); its source lies beyond a non-periodic edge.
 template <int ST>
-__device__ typename Store<ST>::C edge_value(const CaseDev &cp, const void *src, const BlockMeta &m,
-                                            int self, int x, int y, int gx, int gy, int q) {
+__device__ __forceinline__ typename Store<ST>::C edge_value(const CaseDev &cp, const void *src, const Blk &k, int x, int y,
+                                            int gx, int gy, int q) {
 #pragma clang fp contract(off)
   using C = typename Store<ST>::C;
   const int nx = cp.nx[0], ny = cp.ny[0];
@@ -258,7 +301,7 @@ __device__ typename Store<ST>::C edge_value(const CaseDev &cp, const void *src, 
   const double uwx = cp.bcu[e][0], uwy = cp.bcu[e][1];
   switch (cp.bc[e]) {
     case 1: {  // wall: half-way bounce-back with moving-wall term
-      C fs = ldv<ST>(src, self, OPP[q], y * 16 + x);
+      C fs = ldv<ST>(src, k.self, OPP[q], y * 16 + x);
       if constexpr (!Store<ST>::kShift) {
         return fs + 6.0 * wgt<double>(q) * cp.rho0 * (CX[q] * uwx + CY[q] * uwy);
       } else {
@@ -276,12 +319,12 @@ __device__ typename Store<ST>::C edge_value(const CaseDev &cp, const void *src, 
     }
     case 3:    // zero-gradient outflow: the value that streams into the interior neighbour
     case 4: {  // specular symmetry: mirrored population from the tangential neighbour
-      const int nrm[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+      const int nrx = e == 0 ? -1 : (e == 1 ? 1 : 0), nry = e == 2 ? -1 : (e == 3 ? 1 : 0);
       const bool xn = (e == 0 || e == 1);
       int px, py, qq = q;
       if (cp.bc[e] == 3) {
-        px = gx - nrm[e][0] - CX[q];
-        py = gy - nrm[e][1] - CY[q];
+        px = gx - nrx - CX[q];
+        py = gy - nry - CY[q];
       } else {
         px = gx - (xn ? 0 : CX[q]);
         py = gy - (xn ? CY[q] : 0);
@@ -290,7 +333,7 @@ __device__ typename Store<ST>::C edge_value(const CaseDev &cp, const void *src, 
       // periodic axes wrap through the neighbour table; others clamp (corners)
       if (!cp.per_x) px = px < 0 ? 0 : (px >= nx ? nx - 1 : px);
       if (!cp.per_y) py = py < 0 ? 0 : (py >= ny ? ny - 1 : py);
-      return fetch<ST>(src, m, self, x + (px - gx), y + (py - gy), qq);
+      return fetch<ST>(src, k, x + (px - gx), y + (py - gy), qq);
     }
     default:
       return C(__builtin_nan(""));
@@ -302,18 +345,16 @@ __device__ typename Store<ST>::C edge_value(const CaseDev &cp, const void *src, 
 // post-stream value f(g, q) = f*(g - c_q, q), read from the finer lattice its
 // last substep streamed from.
 template <int ST>
-__device__ typename Store<ST>::C coalesce(const LevelArgs &a, const BlockMeta &m, int x, int y, int q) {
+__device__ __forceinline__ typename Store<ST>::C coalesce(const LevelArgs &a, const Blk &k, int x, int y, int q) {
 #pragma clang fp contract(off)
   using C = typename Store<ST>::C;
-  int quad = (x >= 8 ? 1 : 0) + (y >= 8 ? 2 : 0);
-  int cb = m.child[quad];
+  int cb = pick_child(k, x, y);
   if (cb < 0) return C(__builtin_nan(""));
-  const BlockMeta &fm = a.fmeta[cb];
   int fx0 = (2 * x) & 15, fy0 = (2 * y) & 15;
-  C v00 = fetch<ST>(a.fprev, fm, cb, fx0 - CX[q], fy0 - CY[q], q);
-  C v10 = fetch<ST>(a.fprev, fm, cb, fx0 + 1 - CX[q], fy0 - CY[q], q);
-  C v01 = fetch<ST>(a.fprev, fm, cb, fx0 - CX[q], fy0 + 1 - CY[q], q);
-  C v11 = fetch<ST>(a.fprev, fm, cb, fx0 + 1 - CX[q], fy0 + 1 - CY[q], q);
+  C v00 = fetch_mem<ST>(a.fprev, a.fmeta, cb, fx0 - CX[q], fy0 - CY[q], q);
+  C v10 = fetch_mem<ST>(a.fprev, a.fmeta, cb, fx0 + 1 - CX[q], fy0 - CY[q], q);
+  C v01 = fetch_mem<ST>(a.fprev, a.fmeta, cb, fx0 - CX[q], fy0 + 1 - CY[q], q);
+  C v11 = fetch_mem<ST>(a.fprev, a.fmeta, cb, fx0 + 1 - CX[q], fy0 + 1 - CY[q], q);
   C sum = v00;
   sum += v10;
   sum += v01;
@@ -323,23 +364,24 @@ __device__ typename Store<ST>::C coalesce(const LevelArgs &a, const BlockMeta &m
 
 // ---- one cell of a level launch --------------------------------------------
 template <int ST>
-__device__ __forceinline__ void level_cell(const LevelArgs &a, const BlockMeta &m, int b, int cell,
-                                           const CaseDev &cp, bool slow, double *part) {
+__device__ __forceinline__ void level_cell(const LevelArgs &a, const Blk &k, int cell, const CaseDev &cp,
+                                           bool slow, double *part) {
 #pragma clang fp contract(off)
   using S = Store<ST>;
   using T = typename S::T;
   using C = typename S::C;
   const int x = cell & 15, y = cell >> 4;
-  const int l = m.level;
-  uint16_t code = (m.flags & BF_CODES) ? a.codes[(size_t)m.code * kCells + cell] : (uint16_t)0;
+  const int l = k.level;
+  const int b = k.self;
+  uint16_t code = (k.flags & BF_CODES) ? a.codes[(size_t)k.code * kCells + cell] : (uint16_t)0;
 
-  if (m.flags & BF_GHOST) {  // halo layers: streamed, never collided
+  if (k.flags & BF_GHOST) {  // halo layers: streamed, never collided
     if (!(code & CC_BAND)) return;
     T g[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       int sx = x - CX[i], sy = y - CY[i];
-      int nb = nbr_of(m, b, sx, sy);
+      int nb = pick_nbr(k, sx, sy);
       g[i] = nb < 0 ? S::st(C(__builtin_nan(""))) : ldraw<ST>(a.src, nb, i, (sy & 15) * 16 + (sx & 15));
     }
     T *dst = static_cast<T *>(a.dst);
@@ -351,7 +393,8 @@ __device__ __forceinline__ void level_cell(const LevelArgs &a, const BlockMeta &
   const size_t ob = (size_t)(b - a.b0);
   if (code & CC_HIDDEN) {
     if (a.mode & MODE_READOUT) {
-      for (int k = 0; k < 3; ++k) a.out[(ob * 3 + k) * kCells + cell] = __builtin_nan("");
+#pragma unroll
+      for (int q = 0; q < 3; ++q) a.out[(ob * 3 + q) * kCells + cell] = __builtin_nan("");
     }
     return;
   }
@@ -362,43 +405,38 @@ __device__ __forceinline__ void level_cell(const LevelArgs &a, const BlockMeta &
     for (int i = 0; i < 9; ++i) f[i] = ldv<ST>(a.src, b, i, cell);
   } else if (!slow) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      int sx = x - CX[i], sy = y - CY[i];
-      int nb = nbr_of(m, b, sx, sy);
-      f[i] = nb < 0 ? C(__builtin_nan("")) : ldv<ST>(a.src, nb, i, (sy & 15) * 16 + (sx & 15));
-    }
+    for (int i = 0; i < 9; ++i) f[i] = fetch<ST>(a.src, k, x - CX[i], y - CY[i], i);
   } else {
-    const int gx = m.ox + x, gy = m.oy + y;
-    bool hid_any = false;
+    const int gx = k.ox + x, gy = k.oy + y;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       int sx = x - CX[i], sy = y - CY[i];
-      int nb = nbr_of(m, b, sx, sy);
+      int nb = pick_nbr(k, sx, sy);
       if (code & (1u << i)) {
-        f[i] = coalesce<ST>(a, m, x, y, i);
-        hid_any = true;
+        f[i] = coalesce<ST>(a, k, x, y, i);
       } else if (nb < 0) {
-        f[i] = edge_value<ST>(cp, a.src, m, b, x, y, gx, gy, i);
+        f[i] = edge_value<ST>(cp, a.src, k, x, y, gx, gy, i);
       } else {
         f[i] = ldv<ST>(a.src, nb, i, (sy & 15) * 16 + (sx & 15));
       }
     }
-    if (hid_any && cp.cf_mode == 1) {  // RESCALE the coalesced populations
+    if ((code & CC_HSRC) && cp.cf_mode == 1) {  // RESCALE the coalesced populations
       C r, jx, jy;
       frame_moments<ST>(cp, f, r, jx, jy);
       C ux = jx / r, uy = jy / r;
-      C s = (C)(Store<ST>::kShift ? (C)cp.s_fc_f[l] : (C)cp.s_fc[l]);
+      C s;
       if constexpr (!Store<ST>::kShift) s = cp.s_fc[l];
+      else s = cp.s_fc_f[l];
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        if (!(code & (1u << i))) continue;
         C fe = feq_frame<ST>(cp, i, r, ux, uy);
-        f[i] = fe + s * (f[i] - fe);
+        C v = fe + s * (f[i] - fe);
+        f[i] = (code & (1u << i)) ? v : f[i];
       }
     }
   }
 
-  if (a.mode & MODE_READOUT) {  // readout: moments of the post-stream populations, FP64
+  if (a.mode & MODE_READOUT) {  // moments of the post-stream populations, FP64
     double fd[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) fd[i] = (double)f[i];
@@ -416,12 +454,17 @@ __device__ __forceinline__ void level_cell(const LevelArgs &a, const BlockMeta &
   }
 
   // Force density: uniform body force (+ IBM force on the finest level).
-  C Fx = Store<ST>::kShift ? (C)cp.fx_f[l] : (C)cp.fx[l];
-  C Fy = Store<ST>::kShift ? (C)cp.fy_f[l] : (C)cp.fy[l];
-  if constexpr (!Store<ST>::kShift) { Fx = cp.fx[l]; Fy = cp.fy[l]; }
-  if (m.flags & BF_IBM) {
-    IbmWindow w = *cp.win;
-    int wx = m.ox + x - w.x0, wy = m.oy + y - w.y0;
+  C Fx, Fy;
+  if constexpr (!Store<ST>::kShift) {
+    Fx = cp.fx[l];
+    Fy = cp.fy[l];
+  } else {
+    Fx = cp.fx_f[l];
+    Fy = cp.fy_f[l];
+  }
+  if (k.flags & BF_IBM) {
+    const IbmWindow w = *cp.win;
+    int wx = k.ox + x - w.x0, wy = k.oy + y - w.y0;
     if (wx >= 0 && wx < w.w && wy >= 0 && wy < w.h) {
       size_t wi = (size_t)wy * w.w + wx;
       Fx = Fx + (C)cp.wF[wi];
@@ -438,27 +481,22 @@ __device__ __forceinline__ void level_cell(const LevelArgs &a, const BlockMeta &
   for (int i = 0; i < 9; ++i) dst[((size_t)b * kQ + i) * kCells + cell] = S::st(f[i]);
 
   if (code & CC_IFACE) {  // coarse-to-fine: explode f* into the 4 halo children
-    C e[9];
-    if (cp.cf_mode == 1) {
-      C s = Store<ST>::kShift ? (C)cp.s_cf_f[l + 1] : (C)cp.s_cf[l + 1];
-      if constexpr (!Store<ST>::kShift) s = cp.s_cf[l + 1];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        C fe = feq_frame<ST>(cp, i, rho, ux, uy);
-        e[i] = fe + s * (f[i] - fe);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) e[i] = f[i];
-    }
-    int quad = (x >= 8 ? 1 : 0) + (y >= 8 ? 2 : 0);
-    int cb = m.child[quad];
+    int cb = pick_child(k, x, y);
     if (cb >= 0) {
+      C s = 1;
+      if constexpr (!Store<ST>::kShift) s = cp.s_cf[l + 1];
+      else s = cp.s_cf_f[l + 1];
+      const bool resc = cp.cf_mode == 1;
       T *fd = static_cast<T *>(a.fcur);
       int fx0 = (2 * x) & 15, fy0 = (2 * y) & 15;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        T v = S::st(e[i]);
+        C e = f[i];
+        if (resc) {
+          C fe = feq_frame<ST>(cp, i, rho, ux, uy);
+          e = fe + s * (f[i] - fe);
+        }
+        T v = S::st(e);
         size_t base = ((size_t)cb * kQ + i) * kCells;
         fd[base + fy0 * 16 + fx0] = v;
         fd[base + fy0 * 16 + fx0 + 1] = v;
@@ -479,21 +517,51 @@ __device__ __forceinline__ int remap_block(int bid, int nblk, int enable) {
   return start + k;
 }
 
+// Halo-band cell of a halo block: streamed in the first fine substep, never
+// collided.
+template <int ST>
+__device__ __forceinline__ void band_cell(const LevelArgs &a, int packed) {
+  using S = Store<ST>;
+  using T = typename S::T;
+  using C = typename S::C;
+  const int b = packed >> 8, cell = packed & 255;
+  const int x = cell & 15, y = cell >> 4;
+  const Blk k = load_blk(a.meta, b);
+  T g[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    int sx = x - CX[i], sy = y - CY[i];
+    int nb = pick_nbr(k, sx, sy);
+    g[i] = nb < 0 ? S::st(C(__builtin_nan(""))) : ldraw<ST>(a.src, nb, i, (sy & 15) * 16 + (sx & 15));
+  }
+  T *dst = static_cast<T *>(a.dst);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) dst[((size_t)b * kQ + i) * kCells + cell] = g[i];
+}
+
 template <int ST, int CPT>
 __global__ __launch_bounds__(256 / CPT) void level_kernel(LevelArgs a) {
   constexpr int NT = 256 / CPT;
-  const int bl = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  if (bl >= a.n_blocks) return;
-  const int b = a.b0 + bl;
-  const BlockMeta m = a.meta[b];
-  const CaseDev &cp = a.cases[m.case_id];
-  const bool slow = (m.flags & (BF_CODES | BF_EDGE)) != 0;
+  const int w = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  if (w >= a.n_blocks) {  // packed halo-band cells
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+      int idx = (w - a.n_blocks) * 256 + c * NT + threadIdx.x;
+      if (idx < a.n_band) band_cell<ST>(a, a.band[idx]);
+    }
+    return;
+  }
+  const int b = a.list ? a.list[w] : a.b0 + w;
+  const int bl = b - a.b0;
+  const Blk k = load_blk(a.meta, b);
+  const CaseDev &cp = a.cases[k.cid];
+  const bool slow = (k.flags & (BF_CODES | BF_EDGE)) != 0;
   double part[3] = {0.0, 0.0, 0.0};
   double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int k = 0; k < CPT; ++k) {
-    int cell = threadIdx.x + k * NT;
-    level_cell<ST>(a, m, b, cell, cp, slow, part);
+  for (int c = 0; c < CPT; ++c) {
+    int cell = threadIdx.x + c * NT;
+    level_cell<ST>(a, k, cell, cp, slow, part);
     if (a.mode & MODE_READOUT) {
       // fixed-order per-thread partials (hidden cells contribute nothing)
       acc[0] += part[0];
@@ -504,20 +572,176 @@ __global__ __launch_bounds__(256 / CPT) void level_kernel(LevelArgs a) {
   }
   if (a.mode & MODE_READOUT) {
     __shared__ double red[3][NT];
-    for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = acc[k];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) red[q][threadIdx.x] = acc[q];
     __syncthreads();
     for (int s = NT / 2; s > 0; s >>= 1) {
-      if (threadIdx.x < s)
-        for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+      if (threadIdx.x < s) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + s];
+      }
       __syncthreads();
     }
-    if (threadIdx.x == 0)
-      for (int k = 0; k < 3; ++k) a.partial[(size_t)bl * 3 + k] = red[k][0];
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) a.partial[(size_t)bl * 3 + q] = red[q][0];
+    }
+  }
+}
+
+// ---- interior blocks: LDS-staged stream + collide ---------------------------
+// The block's 9 planes are read with 16-byte vector loads into an LDS tile
+// that also holds the one-cell halo each direction needs (188 values from
+// the 8 neighbours); every lane then gathers its 9 incoming populations at
+// fixed offsets, collides and stores.
+template <int ST>
+struct Tile {
+  using T = typename Store<ST>::T;
+  static constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte vector
+  static constexpr int OFF = V;                  // column of x = 0 in a tile row
+  static constexpr int RS = 16 + 2 * V;          // row stride
+  static constexpr int PS = 18 * RS;             // plane stride
+};
+
+template <int ST, bool SLOW>
+__global__ __launch_bounds__(256) void level_fast_kernel(LevelArgs a) {
+#pragma clang fp contract(off)
+  using S = Store<ST>;
+  using T = typename S::T;
+  using C = typename S::C;
+  using TL = Tile<ST>;
+  __shared__ __attribute__((aligned(16))) T tile[9 * TL::PS];
+  const int w = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  if (w >= a.n_blocks) return;
+  const int b = a.list[w];
+  const Blk k = load_blk(a.meta, b);
+  const CaseDev &cp = a.cases[k.cid];
+  const int tid = threadIdx.x;
+  const T *src = static_cast<const T *>(a.src);
+
+  // interior of the 9 planes
+  constexpr int VPP = 256 / TL::V;      // vectors per plane
+  for (int v = tid; v < 9 * VPP; v += 256) {
+    int plane = v / VPP, e = (v % VPP) * TL::V;
+    int y = e >> 4, x = e & 15;
+    uint4 val = *reinterpret_cast<const uint4 *>(src + ((size_t)b * kQ + plane) * kCells + e);
+    *reinterpret_cast<uint4 *>(&tile[plane * TL::PS + (y + 1) * TL::RS + TL::OFF + x]) = val;
+  }
+  // halo: 16 cells for each axis direction, 31 for each diagonal
+  if (tid < 188) {
+    int plane, hx, hy;
+    if (tid < 64) {
+      int s = tid & 15;
+      plane = 1 + (tid >> 4);
+      hx = plane == 1 ? -1 : (plane == 3 ? 16 : s);
+      hy = plane == 2 ? -1 : (plane == 4 ? 16 : s);
+    } else {
+      int d = (tid - 64) / 31, s = (tid - 64) % 31;
+      plane = 5 + d;
+      bool col = s < 16;
+      if (plane == 5) { hx = col ? -1 : s - 16; hy = col ? s - 1 : -1; }
+      else if (plane == 6) { hx = col ? 16 : s - 15; hy = col ? s - 1 : -1; }
+      else if (plane == 7) { hx = col ? 16 : s - 15; hy = col ? s + 1 : 16; }
+      else { hx = col ? -1 : s - 16; hy = col ? s + 1 : 16; }
+    }
+    int nb = pick_nbr(k, hx, hy);
+    T v = nb < 0 ? S::st(C(__builtin_nan(""))) : src[((size_t)nb * kQ + plane) * kCells + (hy & 15) * 16 + (hx & 15)];
+    tile[plane * TL::PS + (hy + 1) * TL::RS + TL::OFF + hx] = v;
+  }
+  __syncthreads();
+
+  const int x = tid & 15, y = tid >> 4;
+  const int l = k.level;
+  uint16_t code = 0;
+  if (SLOW) {
+    code = (k.flags & BF_CODES) ? a.codes[(size_t)k.code * kCells + tid] : (uint16_t)0;
+    if (code & CC_HIDDEN) return;  // covered by the finer level
+  }
+  C f[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    f[i] = S::ld(tile[i * TL::PS + (y - CY[i] + 1) * TL::RS + TL::OFF + x - CX[i]]);
+  if (SLOW) {
+    const int gx = k.ox + x, gy = k.oy + y;
+    const bool edge = (k.flags & BF_EDGE) != 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      if (code & (1u << i)) {
+        f[i] = coalesce<ST>(a, k, x, y, i);
+      } else if (edge) {
+        int sx = gx - CX[i], sy = gy - CY[i];
+        bool out = (!cp.per_x && (sx < 0 || sx >= cp.nx[0])) || (!cp.per_y && (sy < 0 || sy >= cp.ny[0]));
+        if (out) f[i] = edge_value<ST>(cp, a.src, k, x, y, gx, gy, i);
+      }
+    }
+    if ((code & CC_HSRC) && cp.cf_mode == 1) {  // RESCALE the coalesced populations
+      C r, jx, jy;
+      frame_moments<ST>(cp, f, r, jx, jy);
+      C ux = jx / r, uy = jy / r;
+      C sf;
+      if constexpr (!S::kShift) sf = cp.s_fc[l];
+      else sf = cp.s_fc_f[l];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        C fe = feq_frame<ST>(cp, i, r, ux, uy);
+        C v = fe + sf * (f[i] - fe);
+        f[i] = (code & (1u << i)) ? v : f[i];
+      }
+    }
+  }
+
+  C Fx, Fy;
+  if constexpr (!S::kShift) {
+    Fx = cp.fx[l];
+    Fy = cp.fy[l];
+  } else {
+    Fx = cp.fx_f[l];
+    Fy = cp.fy_f[l];
+  }
+  if (k.flags & BF_IBM) {
+    const IbmWindow win = *cp.win;
+    int wx = k.ox + x - win.x0, wy = k.oy + y - win.y0;
+    if (wx >= 0 && wx < win.w && wy >= 0 && wy < win.h) {
+      size_t wi = (size_t)wy * win.w + wx;
+      Fx = Fx + (C)cp.wF[wi];
+      Fy = Fy + (C)cp.wF[(size_t)cp.win_cap + wi];
+    }
+  }
+  C rho, ux, uy;
+  Collide<ST>::run(cp, l, f, Fx, Fy, rho, ux, uy);
+  if (!(rho == rho) || rho > C(1e30) || rho < C(-1e30)) atomicOr(a.err, ERR_NONFINITE);
+  T *dst = static_cast<T *>(a.dst);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) dst[((size_t)b * kQ + i) * kCells + tid] = S::st(f[i]);
+  if (SLOW && (code & CC_IFACE)) {  // coarse-to-fine: explode f* into the 4 halo children
+    int cb = pick_child(k, x, y);
+    if (cb >= 0) {
+      C sc;
+      if constexpr (!S::kShift) sc = cp.s_cf[l + 1];
+      else sc = cp.s_cf_f[l + 1];
+      const bool resc = cp.cf_mode == 1;
+      T *fd = static_cast<T *>(a.fcur);
+      int fx0 = (2 * x) & 15, fy0 = (2 * y) & 15;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        C e = f[i];
+        if (resc) {
+          C fe = feq_frame<ST>(cp, i, rho, ux, uy);
+          e = fe + sc * (f[i] - fe);
+        }
+        T v = S::st(e);
+        size_t base = ((size_t)cb * kQ + i) * kCells;
+        fd[base + fy0 * 16 + fx0] = v;
+        fd[base + fy0 * 16 + fx0 + 1] = v;
+        fd[base + (fy0 + 1) * 16 + fx0] = v;
+        fd[base + (fy0 + 1) * 16 + fx0 + 1] = v;
+      }
+    }
   }
 }
 
 // ---- IBM: multi-direct forcing, one workgroup per body --------------------
-constexpr int MDF_THREADS = 1024;
+constexpr int MDF_THREADS = kMaxMarkers;
 
 __device__ __forceinline__ double peskin(double r) {
 #pragma clang fp contract(off)
@@ -529,37 +753,59 @@ __device__ __forceinline__ double peskin(double r) {
 
 __device__ __forceinline__ int tap0(double X) { return (int)floor(X - 1.5); }
 
-__device__ void body_positions(const CaseDev &cp, double k, int j, double &X, double &Y) {
+// Rigid motion of the body at finest substep k: centre and the rotation by
+// alpha (FIXED bodies: identity rotation about (p0, p1)).
+struct Pose {
+  double xc, yc, ca, sa;
+};
+
+__device__ Pose body_pose(const CaseDev &cp, double k) {
 #pragma clang fp contract(off)
   const double *p = cp.bp;
+  Pose r;
   if (cp.body_kind == 0) {
-    X = p[0] + cp.xb[j];
-    Y = p[1] + cp.yb[j];
-    return;
+    r.xc = p[0];
+    r.yc = p[1];
+    r.ca = 1.0;
+    r.sa = 0.0;
+    return r;
   }
   double tstar = k * p[8] / p[9];
   double theta = 2.0 * M_PI * tstar / p[6];
   double alpha = p[2] - p[3] * sin(theta + p[7]);
   double h = 0.5 * p[4] * cos(theta);
-  double xc = p[0] + h * cos(p[5]);
-  double yc = p[1] + h * sin(p[5]);
-  double ca = cos(alpha), sa = sin(alpha);
-  X = xc + cp.xb[j] * ca + cp.yb[j] * sa;
-  Y = yc - cp.xb[j] * sa + cp.yb[j] * ca;
+  r.xc = p[0] + h * cos(p[5]);
+  r.yc = p[1] + h * sin(p[5]);
+  r.ca = cos(alpha);
+  r.sa = sin(alpha);
+  return r;
 }
 
+__device__ __forceinline__ void marker_position(const CaseDev &cp, const Pose &q, int j, double &X, double &Y) {
+#pragma clang fp contract(off)
+  if (cp.body_kind == 0) {
+    X = q.xc + cp.xb[j];
+    Y = q.yc + cp.yb[j];
+    return;
+  }
+  X = q.xc + cp.xb[j] * q.ca + cp.yb[j] * q.sa;
+  Y = q.yc - cp.xb[j] * q.sa + cp.yb[j] * q.ca;
+}
+
+// rho and the uncorrected velocity of finest cell (gx, gy) from its
+// post-stream populations.
 template <int ST>
 __device__ void cell_moments(const MdfArgs &a, const CaseDev &cp, int gx, int gy, double &rho, double &ux,
                              double &uy) {
 #pragma clang fp contract(off)
   int bx = (gx >> 4) - cp.bm_x0, by = (gy >> 4) - cp.bm_y0;
   int b = cp.bmap[(size_t)by * cp.bm_w + bx];
-  const BlockMeta &m = a.meta[b];
   int x = gx & 15, y = gy & 15;
   double f[9];
+#pragma unroll
   for (int i = 0; i < 9; ++i) {
     if (a.first) f[i] = (double)ldv<ST>(a.src, b, i, y * 16 + x);
-    else f[i] = (double)fetch<ST>(a.src, m, b, x - CX[i], y - CY[i], i);
+    else f[i] = (double)fetch_mem<ST>(a.src, a.meta, b, x - CX[i], y - CY[i], i);
   }
   double jx, jy;
   moments64(f, rho, jx, jy);
@@ -583,6 +829,28 @@ __device__ bool stencil_ok(const MdfArgs &a, const CaseDev &cp, int gx, int gy) 
   return true;
 }
 
+// Ascending sort of up to N marker indices held in registers (bitonic
+// network; every index is a compile-time constant, so nothing spills).
+template <int N>
+__device__ __forceinline__ void sort_net(int (&v)[N]) {
+#pragma unroll
+  for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        int j = i ^ stride;
+        if (j > i) {
+          bool up = (i & size) == 0;
+          int lo = min(v[i], v[j]), hi = max(v[i], v[j]);
+          v[i] = up ? lo : hi;
+          v[j] = up ? hi : lo;
+        }
+      }
+    }
+  }
+}
+
 template <int ST>
 __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
 #pragma clang fp contract(off)
@@ -590,35 +858,54 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
   const CaseDev &cp = a.cases[ci];
   const int n = cp.n_markers;
   const int tid = threadIdx.x;
+  const int NM = a.max_markers;
+  // LDS marker tables: Peskin weights of the 4 x and 4 y taps, first tap,
+  // current force, arc length.
+  extern __shared__ double lds[];
+  double *s_wx = lds;               // [4][NM]
+  double *s_wy = s_wx + 4 * NM;     // [4][NM]
+  double *s_dFx = s_wy + 4 * NM;    // [NM]
+  double *s_dFy = s_dFx + NM;
+  double *s_ds = s_dFy + NM;
+  int *s_i0 = (int *)(s_ds + NM);   // [NM]
+  int *s_j0 = s_i0 + NM;
   __shared__ int s_box[4];
   __shared__ int s_bad;
+  __shared__ Pose s_pose[2];
   const int64_t k = *cp.kcount;
 
-  // 1. kinematics: r_j(t_k), desired velocity (r_j(t_k+1) - r_j(t_k)) / dt
-  int mnx = 1 << 30, mny = 1 << 30, mxx = -(1 << 30), mxy = -(1 << 30);
-  for (int j = tid; j < n; j += MDF_THREADS) {
-    double X, Y, X1, Y1;
-    body_positions(cp, (double)k, j, X, Y);
-    body_positions(cp, (double)(k + 1), j, X1, Y1);
-    cp.X[j] = X;
-    cp.Y[j] = Y;
-    cp.udx[j] = X1 - X;
-    cp.udy[j] = Y1 - Y;
-    int i0 = tap0(X), j0 = tap0(Y);
-    mnx = min(mnx, i0);
-    mny = min(mny, j0);
-    mxx = max(mxx, i0 + 4);
-    mxy = max(mxy, j0 + 4);
-  }
+  // 1. kinematics: r_j(t_k), desired velocity (r_j(t_k+1) - r_j(t_k)) / dt,
+  //    and the Peskin weights of the marker's 4x4 stencil (Eqs. (13), (14))
+  double udx = 0.0, udy = 0.0, ftx = 0.0, fty = 0.0;
+  const bool own = tid < n;
   if (tid == 0) {
     s_box[0] = 1 << 30; s_box[1] = 1 << 30; s_box[2] = -(1 << 30); s_box[3] = -(1 << 30);
     s_bad = 0;
+    s_pose[0] = body_pose(cp, (double)k);
+  } else if (tid == 64) {
+    s_pose[1] = body_pose(cp, (double)(k + 1));
   }
   __syncthreads();
-  atomicMin(&s_box[0], mnx);
-  atomicMin(&s_box[1], mny);
-  atomicMax(&s_box[2], mxx);
-  atomicMax(&s_box[3], mxy);
+  if (own) {
+    double X, Y, X1, Y1;
+    marker_position(cp, s_pose[0], tid, X, Y);
+    marker_position(cp, s_pose[1], tid, X1, Y1);
+    udx = X1 - X;
+    udy = Y1 - Y;
+    int i0 = tap0(X), j0 = tap0(Y);
+    s_i0[tid] = i0;
+    s_j0[tid] = j0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      s_wx[t * NM + tid] = peskin(i0 + t + 0.5 - X);
+      s_wy[t * NM + tid] = peskin(j0 + t + 0.5 - Y);
+    }
+    s_ds[tid] = cp.ds[tid];
+    atomicMin(&s_box[0], i0);
+    atomicMin(&s_box[1], j0);
+    atomicMax(&s_box[2], i0 + 4);
+    atomicMax(&s_box[3], j0 + 4);
+  }
   __syncthreads();
   const int wx0 = s_box[0], wy0 = s_box[1];
   const int ww = s_box[2] - wx0, wh = s_box[3] - wy0;
@@ -636,115 +923,111 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     IbmWindow w = {wx0, wy0, ww, wh};
     *cp.win = w;
   }
-  // 2. clear the window
+  // 2. clear the window (counts and force); the force is read by the level
+  //    kernel over the whole window
   for (int c = tid; c < ncell; c += MDF_THREADS) {
-    cp.wCnt[c] = -1;
+    cp.wCnt[c] = 0;
     cp.wF[c] = 0.0;
     cp.wF[(size_t)cp.win_cap + c] = 0.0;
   }
+  if (tid == 0) *cp.sCount = 0;
   __syncthreads();
-  // 3. mark stencil cells, check they and their sources are owned finest cells
+  // 3. one pass over (marker, tap): contributor lists of the cells, and a
+  //    compact list of the distinct stencil cells (the first toucher appends)
   for (int p = tid; p < 16 * n; p += MDF_THREADS) {
     int j = p >> 4, t = p & 15;
-    int gx = tap0(cp.X[j]) + (t & 3), gy = tap0(cp.Y[j]) + (t >> 2);
-    cp.wCnt[(gy - wy0) * ww + (gx - wx0)] = 0;
-    if (!stencil_ok(a, cp, gx, gy)) s_bad = 1;
-  }
-  __syncthreads();
-  if (s_bad) {
-    if (tid == 0) {
-      atomicOr(a.err, ERR_MARKER);
-      IbmWindow e = {0, 0, 0, 0};
-      *cp.win = e;
-      *cp.kcount = k + 1;
-    }
-    return;
-  }
-  // 4. contributor lists: markers whose stencil covers each cell
-  for (int p = tid; p < 16 * n; p += MDF_THREADS) {
-    int j = p >> 4, t = p & 15;
-    int gx = tap0(cp.X[j]) + (t & 3), gy = tap0(cp.Y[j]) + (t >> 2);
+    int gx = s_i0[j] + (t & 3), gy = s_j0[j] + (t >> 2);
     int c = (gy - wy0) * ww + (gx - wx0);
     int pos = atomicAdd(&cp.wCnt[c], 1);
+    if (pos == 0) cp.sCells[atomicAdd(cp.sCount, 1)] = c;
     if (pos < kMaxContrib) cp.wList[(size_t)c * kMaxContrib + pos] = j;
     else s_bad = 2;
   }
   __syncthreads();
-  if (s_bad) {
-    if (tid == 0) {
-      atomicOr(a.err, ERR_CONTRIB);
-      IbmWindow e = {0, 0, 0, 0};
-      *cp.win = e;
-      *cp.kcount = k + 1;
+  const int ns = *cp.sCount;
+  // 4. per stencil cell: check that it and its streaming sources are owned
+  //    finest cells, order its list by marker index (so spreading sums in
+  //    index order), and take rho and the uncorrected velocity
+  for (int q = tid; q < ns; q += MDF_THREADS) {
+    const int c = cp.sCells[q];
+    const int gx = wx0 + c % ww, gy = wy0 + c / ww;
+    if (!stencil_ok(a, cp, gx, gy)) {
+      s_bad = 1;
+      continue;
     }
-    return;
-  }
-  // 5. sort each list by marker index (spreading sums in index order) and
-  //    compute rho and the uncorrected velocity of the stencil cells
-  for (int c = tid; c < ncell; c += MDF_THREADS) {
-    int cnt = cp.wCnt[c];
-    if (cnt < 0) continue;
+    const int cnt = min(cp.wCnt[c], kMaxContrib);
     int32_t *L = cp.wList + (size_t)c * kMaxContrib;
-    for (int i = 1; i < cnt; ++i) {
-      int v = L[i], q = i - 1;
-      while (q >= 0 && L[q] > v) {
-        L[q + 1] = L[q];
-        --q;
-      }
-      L[q + 1] = v;
+    if (cnt <= 16) {
+      int v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = r < cnt ? L[r] : 0x7fffffff;
+      sort_net<16>(v);
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (r < cnt) L[r] = v[r];
+    } else {
+      int v[kMaxContrib];
+#pragma unroll
+      for (int r = 0; r < kMaxContrib; ++r) v[r] = r < cnt ? L[r] : 0x7fffffff;
+      sort_net<kMaxContrib>(v);
+#pragma unroll
+      for (int r = 0; r < kMaxContrib; ++r)
+        if (r < cnt) L[r] = v[r];
     }
     double rho, ux, uy;
-    cell_moments<ST>(a, cp, wx0 + c % ww, wy0 + c / ww, rho, ux, uy);
+    cell_moments<ST>(a, cp, gx, gy, rho, ux, uy);
     cp.wRho[c] = rho;
     cp.wU[c] = ux;
     cp.wU[(size_t)cp.win_cap + c] = uy;
   }
   __syncthreads();
+  if (s_bad) {
+    if (tid == 0) {
+      atomicOr(a.err, s_bad == 2 ? ERR_CONTRIB : ERR_MARKER);
+      IbmWindow e = {0, 0, 0, 0};
+      *cp.win = e;
+      *cp.kcount = k + 1;
+    }
+    return;
+  }
   // 6. N_F iterations: interpolate (Eq. 12), boundary force (Eq. 11),
   //    spread (Eq. 15), correct velocity and accumulate force
-  double *ftx = cp.ftot + (size_t)(k & 1) * 2 * n;
-  double *fty = ftx + n;
   for (int it = 0; it < cp.mdf_iters; ++it) {
-    for (int j = tid; j < n; j += MDF_THREADS) {
-      double X = cp.X[j], Y = cp.Y[j];
-      int i0 = tap0(X), j0 = tap0(Y);
+    if (own) {
+      const int i0 = s_i0[tid], j0 = s_j0[tid];
       double su = 0.0, sv = 0.0, sr = 0.0;
+#pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
-        double py = peskin(j0 + bb + 0.5 - Y);
-        int row = (j0 + bb - wy0) * ww;
+        double py = s_wy[bb * NM + tid];
+        int row = (j0 + bb - wy0) * ww + (i0 - wx0);
+#pragma unroll
         for (int aa = 0; aa < 4; ++aa) {
-          double w = peskin(i0 + aa + 0.5 - X) * py;
-          int c = row + (i0 + aa - wx0);
+          double w = s_wx[aa * NM + tid] * py;
+          int c = row + aa;
           su += cp.wU[c] * w;
           sv += cp.wU[(size_t)cp.win_cap + c] * w;
           sr += cp.wRho[c] * w;
         }
       }
-      double gx = 2.0 * sr * (cp.udx[j] - su);
-      double gy = 2.0 * sr * (cp.udy[j] - sv);
-      cp.dFx[j] = gx;
-      cp.dFy[j] = gy;
-      if (it == 0) {
-        ftx[j] = gx;
-        fty[j] = gy;
-      } else {
-        ftx[j] += gx;
-        fty[j] += gy;
-      }
+      double gx = 2.0 * sr * (udx - su);
+      double gy = 2.0 * sr * (udy - sv);
+      s_dFx[tid] = gx;
+      s_dFy[tid] = gy;
+      ftx += gx;
+      fty += gy;
     }
     __syncthreads();
-    for (int c = tid; c < ncell; c += MDF_THREADS) {
-      int cnt = cp.wCnt[c];
-      if (cnt < 0) continue;
+    for (int q = tid; q < ns; q += MDF_THREADS) {
+      const int c = cp.sCells[q];
+      const int cnt = cp.wCnt[c];
       const int32_t *L = cp.wList + (size_t)c * kMaxContrib;
       int gx = wx0 + c % ww, gy = wy0 + c / ww;
       double dfx = 0.0, dfy = 0.0;
       for (int q = 0; q < cnt; ++q) {
         int j = L[q];
-        double X = cp.X[j], Y = cp.Y[j];
-        double w = peskin(gx + 0.5 - X) * peskin(gy + 0.5 - Y);
-        dfx += cp.dFx[j] * w * cp.ds[j];
-        dfy += cp.dFy[j] * w * cp.ds[j];
+        double w = s_wx[(gx - s_i0[j]) * NM + j] * s_wy[(gy - s_j0[j]) * NM + j];
+        dfx += s_dFx[j] * w * s_ds[j];
+        dfy += s_dFy[j] * w * s_ds[j];
       }
       cp.wF[c] += dfx;
       cp.wF[(size_t)cp.win_cap + c] += dfy;
@@ -754,17 +1037,34 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     }
     __syncthreads();
   }
-  // 7. total force on the body, Eq. (16), summed in marker order
-  if (tid == 0) {
+  // 7. total marker forces, and the body force of Eq. (16) summed in marker
+  //    order: wave 0 loads 64 markers per round, lane 0 adds them in order
+  double *gtx = cp.ftot + (size_t)(k & 1) * 2 * n;
+  double *gty = gtx + n;
+  if (own) {
+    gtx[tid] = ftx;
+    gty[tid] = fty;
+    s_dFx[tid] = ftx * s_ds[tid];
+    s_dFy[tid] = fty * s_ds[tid];
+  }
+  __syncthreads();
+  if (tid < 64) {
     double fsx = 0.0, fsy = 0.0;
-    for (int j = 0; j < n; ++j) {
-      fsx -= ftx[j] * cp.ds[j];
-      fsy -= fty[j] * cp.ds[j];
+    for (int base = 0; base < n; base += 64) {
+      int j = base + tid;
+      double vx = j < n ? s_dFx[j] : 0.0, vy = j < n ? s_dFy[j] : 0.0;
+      int cnt = min(64, n - base);
+      for (int q = 0; q < cnt; ++q) {
+        fsx -= __shfl(vx, q, 64);
+        fsy -= __shfl(vy, q, 64);
+      }
     }
-    int64_t slot = k % cp.hist_cap;
-    cp.hist[2 * slot] = fsx;
-    cp.hist[2 * slot + 1] = fsy;
-    *cp.kcount = k + 1;
+    if (tid == 0) {
+      int64_t slot = k % cp.hist_cap;
+      cp.hist[2 * slot] = fsx;
+      cp.hist[2 * slot + 1] = fsy;
+      *cp.kcount = k + 1;
+    }
   }
 }
 
@@ -791,7 +1091,7 @@ __global__ void reduce_kernel(const double *partial, int n, double vol, double *
 template <int ST>
 __global__ __launch_bounds__(256) void init_kernel(const BlockMeta *meta, const uint16_t *codes,
                                                   const CaseDev *cases, void *lat, int b0,
-                                                  const double *fields) {
+                                                  const double *fields, double r0, double u0, double v0) {
 #pragma clang fp contract(off)
   using S = Store<ST>;
   using T = typename S::T;
@@ -800,7 +1100,7 @@ __global__ __launch_bounds__(256) void init_kernel(const BlockMeta *meta, const 
   const CaseDev &cp = cases[m.case_id];
   uint16_t code = (m.flags & BF_CODES) ? codes[(size_t)m.code * kCells + cell] : (uint16_t)0;
   if ((m.flags & BF_GHOST) || (code & CC_HIDDEN)) return;
-  double rho = cp.rho0, ux = 0.0, uy = 0.0;
+  double rho = r0 < 0.0 ? cp.rho0 : r0, ux = u0, uy = v0;
   if (fields) {
     const double *f = fields + (size_t)blockIdx.x * 3 * kCells;
     rho = f[cell];
@@ -825,8 +1125,9 @@ __global__ void fill_nan_kernel(T *p, size_t n, T v) {
 
 template <int ST>
 hipError_t launch_level_st(int tile, const LevelArgs *a, hipStream_t s) {
-  if (a->n_blocks <= 0) return hipSuccess;
-  dim3 grid(a->n_blocks);
+  int groups = a->n_blocks + (a->n_band + 255) / 256;
+  if (groups <= 0) return hipSuccess;
+  dim3 grid(groups);
   switch (tile) {
     case 1:
       hipLaunchKernelGGL((level_kernel<ST, 2>), grid, dim3(128), 0, s, *a);
@@ -843,6 +1144,23 @@ hipError_t launch_level_st(int tile, const LevelArgs *a, hipStream_t s) {
 
 }  // namespace
 
+extern "C" hipError_t sbt_launch_level_fast(int storage, int slow, const LevelArgs *a, hipStream_t s) {
+  if (a->n_blocks <= 0) return hipSuccess;
+  dim3 grid(a->n_blocks);
+#define SBT_TILE_LAUNCH(ST)                                                                          \
+  if (slow) hipLaunchKernelGGL((level_fast_kernel<ST, true>), grid, dim3(256), 0, s, *a);           \
+  else hipLaunchKernelGGL((level_fast_kernel<ST, false>), grid, dim3(256), 0, s, *a);
+  switch (storage) {
+    case 0: SBT_TILE_LAUNCH(0) break;
+    case 1: SBT_TILE_LAUNCH(1) break;
+    case 2: SBT_TILE_LAUNCH(2) break;
+    case 3: SBT_TILE_LAUNCH(3) break;
+    default: return hipErrorInvalidValue;
+  }
+#undef SBT_TILE_LAUNCH
+  return hipGetLastError();
+}
+
 extern "C" hipError_t sbt_launch_level(int storage, int tile, const LevelArgs *a, hipStream_t s) {
   switch (storage) {
     case 0: return launch_level_st<0>(tile, a, s);
@@ -853,13 +1171,18 @@ extern "C" hipError_t sbt_launch_level(int storage, int tile, const LevelArgs *a
   return hipErrorInvalidValue;
 }
 
+extern "C" size_t sbt_mdf_lds_bytes(int max_markers) {
+  return (size_t)max_markers * (11 * sizeof(double) + 2 * sizeof(int));
+}
+
 extern "C" hipError_t sbt_launch_mdf(int storage, const MdfArgs *a, int n_bodies, hipStream_t s) {
   if (n_bodies <= 0) return hipSuccess;
+  size_t lds = sbt_mdf_lds_bytes(a->max_markers);
   switch (storage) {
-    case 0: hipLaunchKernelGGL(mdf_kernel<0>, dim3(n_bodies), dim3(MDF_THREADS), 0, s, *a); break;
-    case 1: hipLaunchKernelGGL(mdf_kernel<1>, dim3(n_bodies), dim3(MDF_THREADS), 0, s, *a); break;
-    case 2: hipLaunchKernelGGL(mdf_kernel<2>, dim3(n_bodies), dim3(MDF_THREADS), 0, s, *a); break;
-    case 3: hipLaunchKernelGGL(mdf_kernel<3>, dim3(n_bodies), dim3(MDF_THREADS), 0, s, *a); break;
+    case 0: hipLaunchKernelGGL(mdf_kernel<0>, dim3(n_bodies), dim3(MDF_THREADS), lds, s, *a); break;
+    case 1: hipLaunchKernelGGL(mdf_kernel<1>, dim3(n_bodies), dim3(MDF_THREADS), lds, s, *a); break;
+    case 2: hipLaunchKernelGGL(mdf_kernel<2>, dim3(n_bodies), dim3(MDF_THREADS), lds, s, *a); break;
+    case 3: hipLaunchKernelGGL(mdf_kernel<3>, dim3(n_bodies), dim3(MDF_THREADS), lds, s, *a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -873,13 +1196,14 @@ extern "C" hipError_t sbt_launch_reduce(const double *partial, int n_blocks, dou
 
 extern "C" hipError_t sbt_launch_init(int storage, const BlockMeta *meta, const uint16_t *codes,
                                       const CaseDev *cases, void *lat, int b0, int n,
-                                      const double *fields, hipStream_t s) {
+                                      const double *fields, const double *u, hipStream_t s) {
   if (n <= 0) return hipSuccess;
+  double r0 = u ? u[0] : -1.0, u0 = u ? u[1] : 0.0, v0 = u ? u[2] : 0.0;
   switch (storage) {
-    case 0: hipLaunchKernelGGL(init_kernel<0>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields); break;
-    case 1: hipLaunchKernelGGL(init_kernel<1>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields); break;
-    case 2: hipLaunchKernelGGL(init_kernel<2>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields); break;
-    case 3: hipLaunchKernelGGL(init_kernel<3>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields); break;
+    case 0: hipLaunchKernelGGL(init_kernel<0>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields, r0, u0, v0); break;
+    case 1: hipLaunchKernelGGL(init_kernel<1>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields, r0, u0, v0); break;
+    case 2: hipLaunchKernelGGL(init_kernel<2>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields, r0, u0, v0); break;
+    case 3: hipLaunchKernelGGL(init_kernel<3>, dim3(n), dim3(256), 0, s, meta, codes, cases, lat, b0, fields, r0, u0, v0); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

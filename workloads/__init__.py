@@ -91,6 +91,8 @@ def uniform_init(rho0, ux, uy, perturb=None):
             m = (X >= x0) & (X < x0 + size) & (Y >= y0) & (Y < y0 + size)
             v[m] += duy
         return rho, u, v
+    if perturb is None:
+        init.uniform_state = (rho0, ux, uy)    # lets a consumer skip dense arrays
     return init
 
 
