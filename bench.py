@@ -160,17 +160,14 @@ def main():
     roofline = {
         "bound": "hbm", "achieved": round(fast_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(fast_gbs / HBM_PEAK_GBS, 4), "traffic": None,
-        "kernel": "level_fast_kernel (interior blocks, LDS-staged collide+stream)",
+        "kernel": "level_tile_kernel (LDS-staged stream+collide, all owned blocks)",
         "bytes_per_update": 2 * Q * sbytes,
         "launches": prof["fast_launches"],
         "avg_launch_us": round(prof["fast_ms"] * 1e3 / max(1, prof["fast_launches"]), 2),
         "time_share": {
-            "level_fast_kernel": round(prof["fast_ms"] / args.profile_steps, 4),
-            "level_kernel_generic": round(gen_ms / args.profile_steps, 4),
+            "level_tile_kernel": round(prof["fast_ms"] / args.profile_steps, 4),
             "mdf_kernel": round(prof["mdf_ms"] / args.profile_steps, 4),
             "unit": "ms per step (eager, events)"},
-        "generic_achieved_gbs": round(gen_bytes / max(gen_ms, 1e-9) / 1e6, 1),
-        "all_level_achieved_gbs": round(prof["level_bytes"] / (prof["level_ms"] * 1e-3) / 1e9, 1),
         "mdf_avg_launch_us": round(prof["mdf_ms"] * 1e3 / max(1, prof["mdf_launches"]), 2),
     }
 

@@ -202,8 +202,9 @@ sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path);
  * stream.  out[0] = total ms of level (collide+stream) kernels, out[1] = their
  * launch count, out[2] = total ms of MDF kernels, out[3] = their count,
  * out[4] = algorithmic bytes moved by the level kernels (2 Q s per cell
- * update), out[5] = cell updates, out[6] = ms of the interior-block kernel,
- * out[7] = its launch count, out[8] = its algorithmic bytes. */
+ * update), out[5] = cell updates, out[6] = ms of the per-substep tile kernel
+ * (all owned blocks and halo bands), out[7] = its launch count, out[8] = its
+ * algorithmic bytes. */
 sbt_status sbt_profile(sbt_ctx *ctx, int32_t n, double out[9]);
 /* Cell updates performed per sbt_step, summed over cases and levels. */
 sbt_status sbt_updates_per_step(sbt_ctx *ctx, int64_t *updates);

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <sstream>
@@ -224,13 +225,14 @@ struct Pool {
   std::vector<int32_t> fast, slow, band;   // interior blocks, other owned blocks, halo-band cells
   BlockMeta *d_meta = nullptr;
   uint16_t *d_codes = nullptr;
-  int32_t *d_fast = nullptr, *d_slow = nullptr, *d_band = nullptr;
+  int32_t *d_list = nullptr, *d_band = nullptr;   // d_list = fast blocks, then slow blocks
   void *lat[2] = {nullptr, nullptr};
   int cur = 0;
   int total() const { return n_own + n_ghost; }
 };
 
 struct CaseHost {
+  int group = 0;
   sbt_case_desc d;
   std::vector<sbt_box> boxes;
   Forest F;
@@ -251,12 +253,21 @@ struct Phase {
 
 }  // namespace
 
+struct GroupInfo {
+  std::vector<int> cases;          // case indices of the group
+  int32_t *d_body_cases = nullptr; // cases of the group that carry a body
+  int n_bodies = 0;
+};
+
 struct sbt_ctx {
   int n_cases = 0, V = 1, storage = 0;
+  int G = 1;                       // case groups: independent launch chains
   std::vector<CaseHost> cs;
-  std::vector<Pool> pools;
+  std::vector<Pool> pools;         // pool of group g, virtual level v at g * V + v
+  std::vector<GroupInfo> groups;
+  std::vector<hipStream_t> side_streams;
+  std::vector<hipEvent_t> fork_events;
   CaseDev *d_cases = nullptr;
-  int32_t *d_body_cases = nullptr;
   int n_bodies = 0;
   int32_t *d_err = nullptr;
   double *d_stage = nullptr, *d_partial = nullptr, *d_diag = nullptr;
@@ -265,8 +276,10 @@ struct sbt_ctx {
   hipStream_t cap_stream = nullptr;
   bool post = false;               // false: lattices hold the initial pre-collision state
   int tile = 0, xcd = 1, use_graph = 1;
+  int lds_window = 0;
   std::vector<Phase> step_phases;
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  std::vector<hipGraphExec_t> graph;   // [group * 2 + parity]
+  hipEvent_t step_event = nullptr;
   bool graph_dirty = true;
   size_t bytes_used = 0;
   // profiling
@@ -301,24 +314,50 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     X.V = std::max(X.V, C.F.m);
   }
   const size_t s = storage_bytes(X.storage);
-  // Pools: per virtual level, own blocks of all cases, then halo blocks.
-  X.pools.assign(X.V, Pool());
+  // Case groups: independent chains of launches that a step graph runs side
+  // by side, so one group's latency-bound IBM launches overlap another
+  // group's bandwidth-bound level launches.  Cases go to the least-loaded
+  // group (work = cell updates per step).
+  X.G = n_cases >= 16 ? std::min(4, n_cases / 16) : 1;
+  if (const char *e = std::getenv("SBT_GROUPS")) X.G = std::max(1, std::min(n_cases, std::atoi(e)));
+  {
+    std::vector<std::pair<double, int>> work;
+    for (int c = 0; c < n_cases; ++c) {
+      const CaseHost &C = X.cs[c];
+      double w = 0;
+      for (int l = 0; l < C.F.m; ++l) w += (double)C.F.own[l].size() * (double)(1 << (l + X.V - C.F.m));
+      work.push_back({-w, c});
+    }
+    std::sort(work.begin(), work.end());
+    std::vector<double> load(X.G, 0.0);
+    for (auto &wc : work) {
+      int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      X.cs[wc.second].group = g;
+      load[g] -= wc.first;
+    }
+    X.groups.assign(X.G, GroupInfo());
+    for (int c = 0; c < n_cases; ++c) X.groups[X.cs[c].group].cases.push_back(c);
+  }
+  // Pools: per group and virtual level, own blocks of the group's cases,
+  // then their halo blocks.
+  X.pools.assign((size_t)X.G * X.V, Pool());
   for (int c = 0; c < n_cases; ++c) {
     CaseHost &C = X.cs[c];
     C.vshift = X.V - C.F.m;
     C.lr.assign(C.F.m, CaseLevelRange());
     for (int l = 0; l < C.F.m; ++l) {
       int v = l + C.vshift;
+      Pool &P = X.pools[(size_t)C.group * X.V + v];
       C.lr[l].v = v;
-      C.lr[l].own0 = X.pools[v].n_own;
-      X.pools[v].n_own += (int)C.F.own[l].size();
-      C.lr[l].own1 = X.pools[v].n_own;
+      C.lr[l].own0 = P.n_own;
+      P.n_own += (int)C.F.own[l].size();
+      C.lr[l].own1 = P.n_own;
     }
   }
   for (int c = 0; c < n_cases; ++c) {
     CaseHost &C = X.cs[c];
     for (int l = 0; l < C.F.m; ++l) {
-      Pool &P = X.pools[C.lr[l].v];
+      Pool &P = X.pools[(size_t)C.group * X.V + C.lr[l].v];
       C.lr[l].ghost0 = P.n_own + P.n_ghost;
       P.n_ghost += (int)C.F.ghost[l].size();
       C.lr[l].ghost1 = P.n_own + P.n_ghost;
@@ -351,8 +390,7 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
   for (auto &P : X.pools) {
     P.d_meta = (BlockMeta *)cv.take(sizeof(BlockMeta) * P.total());
     P.d_codes = (uint16_t *)cv.take(sizeof(uint16_t) * std::max<size_t>(1, P.codes.size()));
-    P.d_fast = (int32_t *)cv.take(sizeof(int32_t) * std::max<size_t>(1, P.fast.size()));
-    P.d_slow = (int32_t *)cv.take(sizeof(int32_t) * std::max<size_t>(1, P.slow.size()));
+    P.d_list = (int32_t *)cv.take(sizeof(int32_t) * std::max<size_t>(1, P.fast.size() + P.slow.size()));
     P.d_band = (int32_t *)cv.take(sizeof(int32_t) * std::max<size_t>(1, P.band.size()));
     P.lat[0] = cv.take(s * kQ * kCells * (size_t)P.total());
     P.lat[1] = cv.take(s * kQ * kCells * (size_t)P.total());
@@ -366,7 +404,7 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
   X.d_diag = (double *)cv.take(sizeof(double) * 4);
   X.d_err = (int32_t *)cv.take(sizeof(int32_t) * 4);
   X.d_cases = (CaseDev *)cv.take(sizeof(CaseDev) * n_cases);
-  X.d_body_cases = (int32_t *)cv.take(sizeof(int32_t) * n_cases);
+  for (auto &Gr : X.groups) Gr.d_body_cases = (int32_t *)cv.take(sizeof(int32_t) * n_cases);
   for (int c = 0; c < n_cases; ++c) {
     CaseHost &C = X.cs[c];
     CaseDev &D = C.dev;
@@ -380,11 +418,17 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     D.kcount = (int64_t *)cv.take(sizeof(int64_t));
     D.win = (IbmWindow *)cv.take(sizeof(IbmWindow));
     D.wF = (double *)cv.take(sizeof(double) * 2 * C.win_cap);
-    D.wRho = (double *)cv.take(sizeof(double) * C.win_cap);
-    D.wU = (double *)cv.take(sizeof(double) * 2 * C.win_cap);
     D.wCnt = (int32_t *)cv.take(sizeof(int32_t) * C.win_cap);
+    D.wIdx = (int32_t *)cv.take(sizeof(int32_t) * C.win_cap);
     D.wList = (int32_t *)cv.take(sizeof(int32_t) * kMaxContrib * (size_t)C.win_cap);
     D.sCells = (int32_t *)cv.take(sizeof(int32_t) * (size_t)C.win_cap);
+    D.sList = (int32_t *)cv.take(sizeof(int32_t) * kMaxContrib * (size_t)C.win_cap);
+    D.sRho = (double *)cv.take(sizeof(double) * C.win_cap);
+    D.sU = (double *)cv.take(sizeof(double) * C.win_cap);
+    D.sV = (double *)cv.take(sizeof(double) * C.win_cap);
+    D.sFx = (double *)cv.take(sizeof(double) * C.win_cap);
+    D.sFy = (double *)cv.take(sizeof(double) * C.win_cap);
+    D.sMeta = (int32_t *)cv.take(sizeof(int32_t) * 4 * (size_t)C.win_cap);
     D.sCount = (int32_t *)cv.take(sizeof(int32_t));
     D.bmap = (const int32_t *)cv.take(sizeof(int32_t) * (size_t)D.bm_w * D.bm_h);
   }
@@ -419,7 +463,7 @@ void build_tables(sbt_ctx &X) {
       return map[l][(size_t)by * F.nbx[l] + bx];
     };
     for (int l = 0; l < F.m; ++l) {
-      Pool &P = X.pools[C.lr[l].v];
+      Pool &P = X.pools[(size_t)C.group * X.V + C.lr[l].v];
       for (int pass = 0; pass < 2; ++pass) {
         const std::vector<int> &ids = pass == 0 ? F.own[l] : F.ghost[l];
         int base = pass == 0 ? C.lr[l].own0 : C.lr[l].ghost0;
@@ -579,8 +623,8 @@ struct Timer {
   hipEvent_t a = nullptr, b = nullptr;
 };
 
-sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
-  Pool &P = X.pools[v];
+sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s) {
+  Pool &P = X.pools[(size_t)g * X.V + v];
   LevelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.meta = P.d_meta;
@@ -588,7 +632,7 @@ sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
   a.src = P.lat[P.cur];
   a.dst = P.lat[1 - P.cur];
   if (v + 1 < X.V) {
-    Pool &Q = X.pools[v + 1];
+    Pool &Q = X.pools[(size_t)g * X.V + v + 1];
     a.fmeta = Q.d_meta;
     a.fcodes = Q.d_codes;
     a.fprev = Q.lat[1 - Q.cur];
@@ -614,28 +658,15 @@ sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
   };
   sbt_status st = SBT_OK;
   if (mode == 0) {
-    if (!P.fast.empty()) {
-      LevelArgs f = a;
-      f.list = P.d_fast;
-      f.n_blocks = (int)P.fast.size();
-      st = timed(true, [&] { return sbt_launch_level_fast(X.storage, 0, &f, s); });
-      if (st) return st;
+    LevelArgs t = a;
+    t.list = P.d_list;
+    t.n_fast = (int)P.fast.size();
+    t.n_blocks = (int)(P.fast.size() + P.slow.size());
+    if (p == 1) {
+      t.band = P.d_band;
+      t.n_band = (int)P.band.size();
     }
-    if (!P.slow.empty()) {
-      LevelArgs g = a;
-      g.list = P.d_slow;
-      g.n_blocks = (int)P.slow.size();
-      st = timed(false, [&] { return sbt_launch_level_fast(X.storage, 1, &g, s); });
-      if (st) return st;
-    }
-    if (p == 1 && !P.band.empty()) {
-      LevelArgs g = a;
-      g.list = nullptr;
-      g.n_blocks = 0;
-      g.band = P.d_band;
-      g.n_band = (int)P.band.size();
-      st = timed(false, [&] { return sbt_launch_level(X.storage, X.tile, &g, s); });
-    }
+    if (t.n_blocks + t.n_band > 0) st = timed(true, [&] { return sbt_launch_level_tile(X.storage, &t, s); });
   } else {
     a.list = nullptr;
     a.b0 = 0;
@@ -647,25 +678,27 @@ sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
   return SBT_OK;
 }
 
-sbt_status launch_mdf(sbt_ctx &X, bool first, hipStream_t s) {
-  if (X.n_bodies == 0) return SBT_OK;
-  Pool &P = X.pools[X.V - 1];
+sbt_status launch_mdf(sbt_ctx &X, int g, bool first, hipStream_t s) {
+  GroupInfo &Gr = X.groups[g];
+  if (Gr.n_bodies == 0) return SBT_OK;
+  Pool &P = X.pools[(size_t)g * X.V + X.V - 1];
   MdfArgs a;
   a.meta = P.d_meta;
   a.src = P.lat[P.cur];
   a.cases = X.d_cases;
-  a.body_cases = X.d_body_cases;
+  a.body_cases = Gr.d_body_cases;
   a.first = first ? 1 : 0;
   a.err = X.d_err;
   a.max_markers = 0;
   for (auto &C : X.cs) a.max_markers = std::max(a.max_markers, C.n_markers);
+  a.lds_window = X.lds_window;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (X.profiling) {
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, s));
   }
-  HIPCHK(sbt_launch_mdf(X.storage, &a, X.n_bodies, s));
+  HIPCHK(sbt_launch_mdf(X.storage, &a, Gr.n_bodies, s));
   if (X.profiling) {
     HIPCHK(hipEventRecord(e1, s));
     X.ev_mdf.push_back({e0, e1});
@@ -677,21 +710,30 @@ sbt_status launch_mdf(sbt_ctx &X, bool first, hipStream_t s) {
 // first CollisionStep of every level), finest first so that each coarse
 // level explodes into its finer level's current lattice.
 sbt_status run_prologue(sbt_ctx &X, hipStream_t s) {
-  for (int v = X.V - 1; v >= 0; --v) {
-    if (v == X.V - 1) {
-      sbt_status st = launch_mdf(X, true, s);
+  for (int g = 0; g < X.G; ++g)
+    for (int v = X.V - 1; v >= 0; --v) {
+      if (v == X.V - 1) {
+        sbt_status st = launch_mdf(X, g, true, s);
+        if (st) return st;
+      }
+      sbt_status st = launch_level(X, g, v, 1, MODE_LOCAL, s);
       if (st) return st;
     }
-    sbt_status st = launch_level(X, v, 1, MODE_LOCAL, s);
-    if (st) return st;
-  }
   X.post = true;
   return SBT_OK;
 }
 
-sbt_status run_step_eager(sbt_ctx &X, hipStream_t s) {
+sbt_status run_group_step(sbt_ctx &X, int g, hipStream_t s) {
   for (const Phase &ph : X.step_phases) {
-    sbt_status st = ph.type == PH_MDF ? launch_mdf(X, false, s) : launch_level(X, ph.v, ph.p, 0, s);
+    sbt_status st = ph.type == PH_MDF ? launch_mdf(X, g, false, s) : launch_level(X, g, ph.v, ph.p, 0, s);
+    if (st) return st;
+  }
+  return SBT_OK;
+}
+
+sbt_status run_step_eager(sbt_ctx &X, hipStream_t s) {
+  for (int g = 0; g < X.G; ++g) {
+    sbt_status st = run_group_step(X, g, s);
     if (st) return st;
   }
   return SBT_OK;
@@ -706,17 +748,47 @@ void destroy_graphs(sbt_ctx &X) {
   X.graph_dirty = true;
 }
 
-sbt_status capture_graph(sbt_ctx &X, int parity) {
+sbt_status ensure_side_streams(sbt_ctx &X) {
   if (!X.cap_stream) HIPCHK(hipStreamCreateWithFlags(&X.cap_stream, hipStreamNonBlocking));
-  std::vector<int> saved(X.V);
-  for (int v = 0; v < X.V; ++v) saved[v] = X.pools[v].cur;
+  while ((int)X.side_streams.size() < X.G) {
+    hipStream_t st;
+    hipEvent_t ev;
+    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    X.side_streams.push_back(st);
+    X.fork_events.push_back(ev);
+  }
+  if (X.graph.size() != 2) X.graph.assign(2, nullptr);
+  return SBT_OK;
+}
+
+// One step as a graph: each case group's launch chain is a branch of its
+// own (forked from and joined back to the capture stream), so one group's
+// latency-bound IBM launches overlap other groups' level launches.
+sbt_status capture_graph(sbt_ctx &X, int parity) {
+  sbt_status st0 = ensure_side_streams(X);
+  if (st0) return st0;
+  std::vector<int> saved(X.pools.size());
+  for (size_t i = 0; i < X.pools.size(); ++i) saved[i] = X.pools[i].cur;
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(X.cap_stream, hipStreamCaptureModeThreadLocal));
-  sbt_status st = run_step_eager(X, X.cap_stream);
-  hipError_t e = hipStreamEndCapture(X.cap_stream, &g);
-  for (int v = 0; v < X.V; ++v) X.pools[v].cur = saved[v];
+  sbt_status st = SBT_OK;
+  hipError_t e = hipSuccess;
+  if (X.G > 1) {
+    e = hipEventRecord(X.fork_events[0], X.cap_stream);
+    for (int k = 1; k < X.G && e == hipSuccess; ++k) e = hipStreamWaitEvent(X.side_streams[k], X.fork_events[0], 0);
+  }
+  for (int k = 0; k < X.G && !st && e == hipSuccess; ++k)
+    st = run_group_step(X, k, k == 0 ? X.cap_stream : X.side_streams[k]);
+  for (int k = 1; k < X.G && !st && e == hipSuccess; ++k) {
+    e = hipEventRecord(X.fork_events[k], X.side_streams[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(X.cap_stream, X.fork_events[k], 0);
+  }
+  hipError_t e2 = hipStreamEndCapture(X.cap_stream, &g);
+  for (size_t i = 0; i < X.pools.size(); ++i) X.pools[i].cur = saved[i];
   if (st) return st;
-  if (e != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph fork/join: ") + hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e2));
   e = hipGraphInstantiate(&X.graph[parity], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
@@ -755,7 +827,7 @@ void dense_to_blocks(const Forest &F, int l, const double *r, const double *u, c
 sbt_status readout_level(sbt_ctx &X, int c, int l, hipStream_t s) {
   CaseHost &C = X.cs[c];
   int v = C.lr[l].v;
-  Pool &P = X.pools[v];
+  Pool &P = X.pools[(size_t)C.group * X.V + v];
   LevelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.meta = P.d_meta;
@@ -763,7 +835,7 @@ sbt_status readout_level(sbt_ctx &X, int c, int l, hipStream_t s) {
   // after a step the state to read is the one the last launch streamed from
   a.src = X.post ? P.lat[1 - P.cur] : P.lat[P.cur];
   if (v + 1 < X.V) {
-    Pool &Q = X.pools[v + 1];
+    Pool &Q = X.pools[(size_t)C.group * X.V + v + 1];
     a.fmeta = Q.d_meta;
     a.fcodes = Q.d_codes;
     a.fprev = Q.lat[1 - Q.cur];
@@ -858,9 +930,10 @@ sbt_status sbt_create(const sbt_case_desc *cases, int32_t n_cases, void *device_
       return cleanup_fail(fail(SBT_ERR_DEVICE, "code upload"));
     bool ok = true;
     if (!P.fast.empty())
-      ok &= hipMemcpyAsync(P.d_fast, P.fast.data(), sizeof(int32_t) * P.fast.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+      ok &= hipMemcpyAsync(P.d_list, P.fast.data(), sizeof(int32_t) * P.fast.size(), hipMemcpyHostToDevice, s) == hipSuccess;
     if (!P.slow.empty())
-      ok &= hipMemcpyAsync(P.d_slow, P.slow.data(), sizeof(int32_t) * P.slow.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+      ok &= hipMemcpyAsync(P.d_list + P.fast.size(), P.slow.data(), sizeof(int32_t) * P.slow.size(),
+                           hipMemcpyHostToDevice, s) == hipSuccess;
     if (!P.band.empty())
       ok &= hipMemcpyAsync(P.d_band, P.band.data(), sizeof(int32_t) * P.band.size(), hipMemcpyHostToDevice, s) == hipSuccess;
     if (!ok) return cleanup_fail(fail(SBT_ERR_DEVICE, "list upload"));
@@ -897,6 +970,9 @@ sbt_status sbt_destroy(sbt_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   destroy_graphs(*ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  for (auto st : ctx->side_streams) (void)hipStreamDestroy(st);
+  for (auto ev : ctx->fork_events) (void)hipEventDestroy(ev);
+  if (ctx->step_event) (void)hipEventDestroy(ctx->step_event);
   delete ctx;
   return SBT_OK;
 }
@@ -974,7 +1050,7 @@ sbt_status sbt_init_fields(sbt_ctx *ctx, int32_t c, int32_t level, const double 
     size_t k1 = std::min(n, k0 + X.stage_blocks);
     HIPCHK(hipMemcpyAsync(X.d_stage, host.data() + k0 * 3 * kCells, sizeof(double) * 3 * kCells * (k1 - k0),
                           hipMemcpyHostToDevice, X.stream));
-    Pool &P = X.pools[C.lr[level].v];
+    Pool &P = X.pools[(size_t)C.group * X.V + C.lr[level].v];
     HIPCHK(sbt_launch_init(X.storage, P.d_meta, P.d_codes, X.d_cases, P.lat[0], C.lr[level].own0 + (int)k0,
                            (int)(k1 - k0), X.d_stage, nullptr, X.stream));
     HIPCHK(hipStreamSynchronize(X.stream));
@@ -1001,7 +1077,7 @@ sbt_status sbt_init_uniform(sbt_ctx *ctx, int32_t c, double rho, double ux, doub
   }
   double u0[3] = {rho, ux, uy};
   for (int l = 0; l < C.F.m; ++l) {
-    Pool &P = X.pools[C.lr[l].v];
+    Pool &P = X.pools[(size_t)C.group * X.V + C.lr[l].v];
     HIPCHK(sbt_launch_init(X.storage, P.d_meta, P.d_codes, X.d_cases, P.lat[0], C.lr[l].own0,
                            C.lr[l].own1 - C.lr[l].own0, nullptr, u0, X.stream));
   }
@@ -1021,6 +1097,18 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
   if (body->kind != SBT_BODY_FIXED && body->kind != SBT_BODY_FLAP) return fail(SBT_ERR_ARG, "bad body kind");
   if (body->kind == SBT_BODY_FLAP && (body->p[6] == 0.0 || body->p[9] == 0.0))
     return fail(SBT_ERR_ARG, "flap period and chord must be nonzero");
+  {
+    int dev = 0, lds_max = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    int nmax = body->n;
+    for (auto &K : X.cs) nmax = std::max(nmax, K.n_markers);
+    if (sbt_mdf_lds_bytes(nmax, 0) + 1024 > (size_t)lds_max)
+      return fail(SBT_ERR_ARG, "too many markers for one workgroup's LDS (" + std::to_string(lds_max) + " bytes)");
+    // window counters in LDS with what is left (global atomics beyond that)
+    size_t left = (size_t)lds_max - 1024 - sbt_mdf_lds_bytes(nmax, 0);
+    X.lds_window = (int)std::min<size_t>(16384, left / sizeof(int32_t));
+  }
   HIPCHK(hipStreamSynchronize(X.stream));
   const size_t N = (size_t)body->n;
   HIPCHK(hipMemcpy((void *)C.dev.xb, body->xb, sizeof(double) * N, hipMemcpyHostToDevice));
@@ -1031,11 +1119,16 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
   std::memcpy(C.dev.bp, body->p, sizeof(body->p));
   C.n_markers = body->n;
   HIPCHK(hipMemcpy(X.d_cases + c, &C.dev, sizeof(CaseDev), hipMemcpyHostToDevice));
-  std::vector<int32_t> bc;
-  for (int k = 0; k < X.n_cases; ++k)
-    if (X.cs[k].has_body && X.cs[k].n_markers > 0) bc.push_back(k);
-  X.n_bodies = (int)bc.size();
-  if (!bc.empty()) HIPCHK(hipMemcpy(X.d_body_cases, bc.data(), sizeof(int32_t) * bc.size(), hipMemcpyHostToDevice));
+  X.n_bodies = 0;
+  for (auto &Gr : X.groups) {
+    std::vector<int32_t> bc;
+    for (int k : Gr.cases)
+      if (X.cs[k].has_body && X.cs[k].n_markers > 0) bc.push_back(k);
+    Gr.n_bodies = (int)bc.size();
+    X.n_bodies += Gr.n_bodies;
+    if (!bc.empty())
+      HIPCHK(hipMemcpy(Gr.d_body_cases, bc.data(), sizeof(int32_t) * bc.size(), hipMemcpyHostToDevice));
+  }
   destroy_graphs(X);
   return SBT_OK;
 }
@@ -1051,15 +1144,18 @@ sbt_status sbt_step(sbt_ctx *ctx, int32_t n) {
   }
   for (int t = 0; t < n; ++t) {
     if (X.use_graph && !X.profiling) {
+      sbt_status st = ensure_side_streams(X);
+      if (st) return st;
       int par = X.pools[0].cur;
       if (!X.graph[par]) {
-        sbt_status st = capture_graph(X, par);
+        st = capture_graph(X, par);
         if (st) return st;
       }
       HIPCHK(hipGraphLaunch(X.graph[par], X.stream));
       // the graph performs the same lattice flips as the eager list
-      for (const Phase &ph : X.step_phases)
-        if (ph.type == PH_LEVEL) X.pools[ph.v].cur ^= 1;
+      for (int g = 0; g < X.G; ++g)
+        for (const Phase &ph : X.step_phases)
+          if (ph.type == PH_LEVEL) X.pools[(size_t)g * X.V + ph.v].cur ^= 1;
     } else {
       sbt_status st = run_step_eager(X, X.stream);
       if (st) return st;
@@ -1194,13 +1290,12 @@ sbt_status sbt_read_force_history(sbt_ctx *ctx, int32_t c, int32_t cap, double *
 // ---- checkpoint -----------------------------------------------------------
 struct StateHeader {
   uint64_t magic, bytes;
-  int32_t post, V, n_cases, storage;
-  int32_t cur[kMaxLevels];
+  int32_t post, V, n_cases, storage, n_pools, pad;
 };
 
 sbt_status sbt_state_bytes(sbt_ctx *ctx, size_t *bytes) {
   if (!ctx || !bytes) return fail(SBT_ERR_ARG, "null argument");
-  size_t b = sizeof(StateHeader);
+  size_t b = sizeof(StateHeader) + sizeof(int32_t) * ctx->pools.size();
   const size_t s = storage_bytes(ctx->storage);
   for (auto &P : ctx->pools) b += 2 * s * kQ * kCells * (size_t)P.total();
   for (auto &C : ctx->cs)
@@ -1225,9 +1320,14 @@ sbt_status sbt_read_state(sbt_ctx *ctx, void *host, size_t bytes) {
   h.V = X.V;
   h.n_cases = X.n_cases;
   h.storage = X.storage;
-  for (int v = 0; v < X.V; ++v) h.cur[v] = X.pools[v].cur;
+  h.n_pools = (int32_t)X.pools.size();
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
+  for (auto &P : X.pools) {
+    int32_t cur = P.cur;
+    std::memcpy(p, &cur, sizeof(cur));
+    p += sizeof(cur);
+  }
   const size_t s = storage_bytes(X.storage);
   for (auto &P : X.pools)
     for (int k = 0; k < 2; ++k) {
@@ -1258,9 +1358,13 @@ sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes) {
   const char *p = (const char *)host;
   StateHeader h;
   std::memcpy(&h, p, sizeof(h));
-  if (h.magic != 0x5342545354415445ull || h.V != X.V || h.n_cases != X.n_cases || h.storage != X.storage)
+  if (h.magic != 0x5342545354415445ull || h.V != X.V || h.n_cases != X.n_cases || h.storage != X.storage ||
+      h.n_pools != (int32_t)X.pools.size())
     return fail(SBT_ERR_ARG, "state does not match this context");
   p += sizeof(h);
+  std::vector<int32_t> curs(X.pools.size());
+  std::memcpy(curs.data(), p, sizeof(int32_t) * curs.size());
+  p += sizeof(int32_t) * curs.size();
   HIPCHK(hipStreamSynchronize(X.stream));
   const size_t s = storage_bytes(X.storage);
   for (auto &P : X.pools)
@@ -1281,7 +1385,7 @@ sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes) {
     p += nb;
   }
   X.post = h.post != 0;
-  for (int v = 0; v < X.V; ++v) X.pools[v].cur = h.cur[v];
+  for (size_t i = 0; i < X.pools.size(); ++i) X.pools[i].cur = curs[i];
   destroy_graphs(X);
   return SBT_OK;
 }
@@ -1337,11 +1441,6 @@ sbt_status sbt_profile(sbt_ctx *ctx, int32_t n, double out[9]) {
   int64_t upd = 0;
   sbt_updates_per_step(ctx, &upd);
   const double bpu = 2.0 * kQ * (double)storage_bytes(X.storage);
-  int64_t fast_cells = 0;
-  for (auto &P : X.pools) fast_cells += (int64_t)P.fast.size() * kCells;
-  // cell updates of the fast kernel per step: each pool runs 2^v times
-  double fast_upd = 0;
-  for (int v = 0; v < X.V; ++v) fast_upd += (double)X.pools[v].fast.size() * kCells * (double)(1 << v);
   out[0] = fl.first + gl.first;
   out[1] = fl.second + gl.second;
   out[2] = md.first;
@@ -1350,8 +1449,7 @@ sbt_status sbt_profile(sbt_ctx *ctx, int32_t n, double out[9]) {
   out[4] = out[5] * bpu;
   out[6] = fl.first;
   out[7] = fl.second;
-  out[8] = fast_upd * n * bpu;
-  (void)fast_cells;
+  out[8] = out[4];  // the tile kernel performs every cell update of a step
   return SBT_OK;
 }
 

@@ -71,10 +71,14 @@ struct alignas(16) CaseDev {
   int64_t *kcount;             // finest substeps done
   IbmWindow *win;
   double *wF;                  // [2][win_cap]  force density in the window
-  double *wRho, *wU;           // [win_cap], [2][win_cap]
   int32_t *wCnt;               // [win_cap] markers whose stencil covers the cell
-  int32_t *wList;              // [win_cap][kMaxContrib] those markers, ascending
+  int32_t *wIdx;               // [win_cap] compact index of the cell (stencil cells)
+  int32_t *wList;              // [win_cap][kMaxContrib] those markers (unordered)
   int32_t *sCells;             // [win_cap] window index of each stencil cell (compact)
+  int32_t *sList;              // [win_cap][kMaxContrib] compact cell's markers, ascending
+  double *sRho, *sU, *sV;      // [win_cap] compact cell moments (u, v corrected in place)
+  double *sFx, *sFy;           // [win_cap] compact cell IBM force
+  int32_t *sMeta;              // [win_cap][4] compact cell: count, gx, gy, window index
   int32_t *sCount;             // number of stencil cells
   const int32_t *bmap;         // finest-level block map -> pool index (-1 outside)
 };
@@ -93,6 +97,7 @@ struct LevelArgs {
   const int32_t *list;         // blocks to process, or null for b0 .. b0 + n_blocks - 1
   int32_t b0;
   int32_t n_blocks;            // entries of list (or length of the range)
+  int32_t n_fast;              // leading list entries that are interior blocks
   const int32_t *band;         // halo-band cells (block * 256 + cell), gathered after the blocks
   int32_t n_band;
   int32_t mode;                // MODE_* bits
@@ -109,6 +114,7 @@ struct MdfArgs {
   const int32_t *body_cases;   // case index per workgroup
   int32_t first;               // 1: local read (initial pre-collision state)
   int32_t max_markers;         // sizes the workgroup's LDS marker tables
+  int32_t lds_window;          // window cells whose counters fit in LDS
   int32_t *err;
 };
 
@@ -125,12 +131,13 @@ extern "C" {
 // Generic level kernel: any block (interfaces, domain edges, readout,
 // initial collision) and halo-band cells.
 hipError_t sbt_launch_level(int storage, int tile, const sbt::LevelArgs *a, hipStream_t s);
-// LDS-staged stream + collide for owned blocks.  slow = 0: interior blocks
-// (no cell codes, no domain edge, all eight neighbours present); slow = 1:
-// blocks next to a finer level or a domain edge.
-hipError_t sbt_launch_level_fast(int storage, int slow, const sbt::LevelArgs *a, hipStream_t s);
+// One LDS-staged stream + collide launch for a level substep: list entries
+// [0, n_fast) are interior blocks (no cell codes, no domain edge, all eight
+// neighbours present), [n_fast, n_blocks) blocks next to a finer level or a
+// domain edge; then n_band packed halo-band cells.
+hipError_t sbt_launch_level_tile(int storage, const sbt::LevelArgs *a, hipStream_t s);
 hipError_t sbt_launch_mdf(int storage, const sbt::MdfArgs *a, int n_bodies, hipStream_t s);
-size_t sbt_mdf_lds_bytes(int max_markers);
+size_t sbt_mdf_lds_bytes(int max_markers, int lds_window);
 hipError_t sbt_launch_reduce(const double *partial, int n_blocks, double vol, double *out,
                              int accumulate, hipStream_t s);
 hipError_t sbt_launch_fill_nan(void *p, size_t n_elems, int storage, hipStream_t s);

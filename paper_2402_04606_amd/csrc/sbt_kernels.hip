@@ -604,16 +604,12 @@ struct Tile {
 };
 
 template <int ST, bool SLOW>
-__global__ __launch_bounds__(256) void level_fast_kernel(LevelArgs a) {
+__device__ __forceinline__ void tile_block(const LevelArgs &a, int b, typename Store<ST>::T *tile) {
 #pragma clang fp contract(off)
   using S = Store<ST>;
   using T = typename S::T;
   using C = typename S::C;
   using TL = Tile<ST>;
-  __shared__ __attribute__((aligned(16))) T tile[9 * TL::PS];
-  const int w = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  if (w >= a.n_blocks) return;
-  const int b = a.list[w];
   const Blk k = load_blk(a.meta, b);
   const CaseDev &cp = a.cases[k.cid];
   const int tid = threadIdx.x;
@@ -740,6 +736,24 @@ __global__ __launch_bounds__(256) void level_fast_kernel(LevelArgs a) {
   }
 }
 
+// One launch per level substep: the first n_fast list entries are interior
+// blocks, the rest of the list are blocks next to a finer level or a domain
+// edge, and workgroups past the list gather packed halo-band cells.
+template <int ST>
+__global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a) {
+  using T = typename Store<ST>::T;
+  __shared__ __attribute__((aligned(16))) T tile[9 * Tile<ST>::PS];
+  const int w = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
+  if (w < a.n_fast) {
+    tile_block<ST, false>(a, a.list[w], tile);
+  } else if (w < a.n_blocks) {
+    tile_block<ST, true>(a, a.list[w], tile);
+  } else {
+    int idx = (w - a.n_blocks) * 256 + threadIdx.x;
+    if (idx < a.n_band) band_cell<ST>(a, a.band[idx]);
+  }
+}
+
 // ---- IBM: multi-direct forcing, one workgroup per body --------------------
 constexpr int MDF_THREADS = kMaxMarkers;
 
@@ -792,20 +806,42 @@ __device__ __forceinline__ void marker_position(const CaseDev &cp, const Pose &q
   Y = q.yc - cp.xb[j] * q.sa + cp.yb[j] * q.ca;
 }
 
+// Owned finest-level block of the case holding cell (gx, gy), -1 if none.
+__device__ __forceinline__ int finest_block(const CaseDev &cp, int gx, int gy) {
+  const int l = cp.n_levels - 1;
+  if (gx < 0 || gy < 0 || gx >= cp.nx[l] || gy >= cp.ny[l]) return -1;
+  int rx = (gx >> 4) - cp.bm_x0, ry = (gy >> 4) - cp.bm_y0;
+  if (rx < 0 || ry < 0 || rx >= cp.bm_w || ry >= cp.bm_h) return -1;
+  return cp.bmap[(size_t)ry * cp.bm_w + rx];
+}
+
+// A stencil cell and its 8 streaming sources must be owned finest cells; the
+// 3x3 neighbourhood spans at most 2x2 blocks, all found at its corners.
+__device__ __forceinline__ bool stencil_ok(const CaseDev &cp, int gx, int gy) {
+  return finest_block(cp, gx - 1, gy - 1) >= 0 && finest_block(cp, gx + 1, gy - 1) >= 0 &&
+         finest_block(cp, gx - 1, gy + 1) >= 0 && finest_block(cp, gx + 1, gy + 1) >= 0;
+}
+
 // rho and the uncorrected velocity of finest cell (gx, gy) from its
-// post-stream populations.
+// post-stream populations (the initial state is read in place).
 template <int ST>
-__device__ void cell_moments(const MdfArgs &a, const CaseDev &cp, int gx, int gy, double &rho, double &ux,
-                             double &uy) {
+__device__ __forceinline__ void cell_moments(const MdfArgs &a, const CaseDev &cp, int gx, int gy, double &rho,
+                                             double &ux, double &uy) {
 #pragma clang fp contract(off)
-  int bx = (gx >> 4) - cp.bm_x0, by = (gy >> 4) - cp.bm_y0;
-  int b = cp.bmap[(size_t)by * cp.bm_w + bx];
-  int x = gx & 15, y = gy & 15;
   double f[9];
+  if (a.first) {
+    int b = finest_block(cp, gx, gy);
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    if (a.first) f[i] = (double)ldv<ST>(a.src, b, i, y * 16 + x);
-    else f[i] = (double)fetch_mem<ST>(a.src, a.meta, b, x - CX[i], y - CY[i], i);
+    for (int i = 0; i < 9; ++i) f[i] = (double)ldv<ST>(a.src, b, i, (gy & 15) * 16 + (gx & 15));
+  } else {
+    int nb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) nb[i] = finest_block(cp, gx - CX[i], gy - CY[i]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      int sx = gx - CX[i], sy = gy - CY[i];
+      f[i] = (double)ldv<ST>(a.src, nb[i], i, (sy & 15) * 16 + (sx & 15));
+    }
   }
   double jx, jy;
   moments64(f, rho, jx, jy);
@@ -813,20 +849,6 @@ __device__ void cell_moments(const MdfArgs &a, const CaseDev &cp, int gx, int gy
   int l = cp.n_levels - 1;
   ux = (jx + 0.5 * cp.fx[l]) / rho;
   uy = (jy + 0.5 * cp.fy[l]) / rho;
-}
-
-// Is finest cell (gx, gy) with its 8 neighbours owned by a (non-halo) block?
-__device__ bool stencil_ok(const MdfArgs &a, const CaseDev &cp, int gx, int gy) {
-  int l = cp.n_levels - 1;
-  if (gx - 1 < 0 || gy - 1 < 0 || gx + 1 >= cp.nx[l] || gy + 1 >= cp.ny[l]) return false;
-  for (int by = (gy - 1) >> 4; by <= (gy + 1) >> 4; ++by)
-    for (int bx = (gx - 1) >> 4; bx <= (gx + 1) >> 4; ++bx) {
-      int rx = bx - cp.bm_x0, ry = by - cp.bm_y0;
-      if (rx < 0 || ry < 0 || rx >= cp.bm_w || ry >= cp.bm_h) return false;
-      int b = cp.bmap[(size_t)ry * cp.bm_w + rx];
-      if (b < 0 || (a.meta[b].flags & BF_GHOST)) return false;
-    }
-  return true;
 }
 
 // Ascending sort of up to N marker indices held in registers (bitonic
@@ -851,16 +873,34 @@ __device__ __forceinline__ void sort_net(int (&v)[N]) {
   }
 }
 
+template <int N>
+__device__ __forceinline__ void sorted_copy(const int32_t *L, int cnt, int32_t *out) {
+  int v[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) v[r] = r < cnt ? L[r] : 0x7fffffff;
+  sort_net<N>(v);
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+    if (r < cnt) out[r] = v[r];
+}
+
+__device__ __forceinline__ void mdf_fail(const CaseDev &cp, int *err, int code, int64_t k) {
+  atomicOr(err, code);
+  IbmWindow e = {0, 0, 0, 0};
+  *cp.win = e;
+  *cp.kcount = k + 1;
+}
+
 template <int ST>
 __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
 #pragma clang fp contract(off)
   const int ci = a.body_cases[blockIdx.x];
   const CaseDev &cp = a.cases[ci];
   const int n = cp.n_markers;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int NM = a.max_markers;
-  // LDS marker tables: Peskin weights of the 4 x and 4 y taps, first tap,
-  // current force, arc length.
+  // LDS marker tables: Peskin weights of the 4 x and 4 y taps, current force,
+  // arc length, first tap, and the compact stencil-cell index of each tap.
   extern __shared__ double lds[];
   double *s_wx = lds;               // [4][NM]
   double *s_wy = s_wx + 4 * NM;     // [4][NM]
@@ -869,6 +909,8 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
   double *s_ds = s_dFy + NM;
   int *s_i0 = (int *)(s_ds + NM);   // [NM]
   int *s_j0 = s_i0 + NM;
+  int *s_tap = s_j0 + NM;           // [16][NM]
+  int *s_cnt = s_tap + 16 * NM;     // [lds_window] window counters
   __shared__ int s_box[4];
   __shared__ int s_bad;
   __shared__ Pose s_pose[2];
@@ -876,8 +918,6 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
 
   // 1. kinematics: r_j(t_k), desired velocity (r_j(t_k+1) - r_j(t_k)) / dt,
   //    and the Peskin weights of the marker's 4x4 stencil (Eqs. (13), (14))
-  double udx = 0.0, udy = 0.0, ftx = 0.0, fty = 0.0;
-  const bool own = tid < n;
   if (tid == 0) {
     s_box[0] = 1 << 30; s_box[1] = 1 << 30; s_box[2] = -(1 << 30); s_box[3] = -(1 << 30);
     s_bad = 0;
@@ -886,6 +926,9 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     s_pose[1] = body_pose(cp, (double)(k + 1));
   }
   __syncthreads();
+  double udx = 0.0, udy = 0.0, ftx = 0.0, fty = 0.0;
+  const bool own = tid < n;
+  int bx0 = 1 << 30, by0 = 1 << 30, bx1 = -(1 << 30), by1 = -(1 << 30);
   if (own) {
     double X, Y, X1, Y1;
     marker_position(cp, s_pose[0], tid, X, Y);
@@ -901,112 +944,160 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
       s_wy[t * NM + tid] = peskin(j0 + t + 0.5 - Y);
     }
     s_ds[tid] = cp.ds[tid];
-    atomicMin(&s_box[0], i0);
-    atomicMin(&s_box[1], j0);
-    atomicMax(&s_box[2], i0 + 4);
-    atomicMax(&s_box[3], j0 + 4);
+    bx0 = i0; by0 = j0; bx1 = i0 + 4; by1 = j0 + 4;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    bx0 = min(bx0, __shfl_xor(bx0, o, 64));
+    by0 = min(by0, __shfl_xor(by0, o, 64));
+    bx1 = max(bx1, __shfl_xor(bx1, o, 64));
+    by1 = max(by1, __shfl_xor(by1, o, 64));
+  }
+  if (lane == 0) {
+    atomicMin(&s_box[0], bx0);
+    atomicMin(&s_box[1], by0);
+    atomicMax(&s_box[2], bx1);
+    atomicMax(&s_box[3], by1);
   }
   __syncthreads();
   const int wx0 = s_box[0], wy0 = s_box[1];
   const int ww = s_box[2] - wx0, wh = s_box[3] - wy0;
   const int ncell = ww * wh;
   if (ncell > cp.win_cap || ww <= 0 || wh <= 0) {
-    if (tid == 0) {
-      atomicOr(a.err, ERR_WINDOW);
-      IbmWindow e = {0, 0, 0, 0};
-      *cp.win = e;
-      *cp.kcount = k + 1;
-    }
+    if (tid == 0) mdf_fail(cp, a.err, ERR_WINDOW, k);
     return;
   }
   if (tid == 0) {
     IbmWindow w = {wx0, wy0, ww, wh};
     *cp.win = w;
+    *cp.sCount = 0;
   }
-  // 2. clear the window (counts and force); the force is read by the level
-  //    kernel over the whole window
+  // 2. clear the window (counts and force; the level kernel reads the force
+  //    over the whole window).  Counters live in LDS when the window fits.
+  const bool lds_cnt = ncell <= a.lds_window;
+  int *wcnt = lds_cnt ? s_cnt : cp.wCnt;
   for (int c = tid; c < ncell; c += MDF_THREADS) {
-    cp.wCnt[c] = 0;
+    wcnt[c] = 0;
     cp.wF[c] = 0.0;
     cp.wF[(size_t)cp.win_cap + c] = 0.0;
   }
-  if (tid == 0) *cp.sCount = 0;
   __syncthreads();
-  // 3. one pass over (marker, tap): contributor lists of the cells, and a
-  //    compact list of the distinct stencil cells (the first toucher appends)
-  for (int p = tid; p < 16 * n; p += MDF_THREADS) {
-    int j = p >> 4, t = p & 15;
-    int gx = s_i0[j] + (t & 3), gy = s_j0[j] + (t >> 2);
-    int c = (gy - wy0) * ww + (gx - wx0);
-    int pos = atomicAdd(&cp.wCnt[c], 1);
-    if (pos == 0) cp.sCells[atomicAdd(cp.sCount, 1)] = c;
-    if (pos < kMaxContrib) cp.wList[(size_t)c * kMaxContrib + pos] = j;
-    else s_bad = 2;
+  // 3. each marker lane registers its 16 taps at once: contributor lists of
+  //    the cells, and a compact list of the distinct stencil cells (the first
+  //    toucher of a cell appends it; a wavefront prefix sum sizes the append)
+  {
+    int cidx[16], pos[16];
+    int nf = 0;
+    if (own) {
+      const int i0 = s_i0[tid], j0 = s_j0[tid];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) cidx[t] = (j0 + (t >> 2) - wy0) * ww + (i0 + (t & 3) - wx0);
+#pragma unroll
+      for (int t = 0; t < 16; ++t) pos[t] = atomicAdd(&wcnt[cidx[t]], 1);
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        if (pos[t] < kMaxContrib) cp.wList[(size_t)cidx[t] * kMaxContrib + pos[t]] = tid;
+        else s_bad = 2;
+        nf += pos[t] == 0;
+      }
+    }
+    int incl = nf;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    const int total = __shfl(incl, 63, 64);
+    int base = 0;
+    if (lane == 63 && total > 0) base = atomicAdd(cp.sCount, total);
+    base = __shfl(base, 63, 64);
+    if (own) {
+      int q = base + incl - nf;
+#pragma unroll
+      for (int t = 0; t < 16; ++t)
+        if (pos[t] == 0) {
+          cp.sCells[q] = cidx[t];
+          cp.wIdx[cidx[t]] = q;
+          ++q;
+        }
+    }
   }
   __syncthreads();
-  const int ns = *cp.sCount;
-  // 4. per stencil cell: check that it and its streaming sources are owned
-  //    finest cells, order its list by marker index (so spreading sums in
-  //    index order), and take rho and the uncorrected velocity
+  const int ns = atomicAdd(cp.sCount, 0);
+  // 4. taps -> compact cell index (LDS); per stencil cell: ownership check,
+  //    marker list in index order (spreading sums in index order), rho and
+  //    the uncorrected velocity
+  if (own) {
+    const int i0 = s_i0[tid], j0 = s_j0[tid];
+    int qi[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) qi[t] = cp.wIdx[(j0 + (t >> 2) - wy0) * ww + (i0 + (t & 3) - wx0)];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) s_tap[t * NM + tid] = qi[t];
+  }
   for (int q = tid; q < ns; q += MDF_THREADS) {
     const int c = cp.sCells[q];
     const int gx = wx0 + c % ww, gy = wy0 + c / ww;
-    if (!stencil_ok(a, cp, gx, gy)) {
+    const int cnt = min(wcnt[c], kMaxContrib);
+    if (!stencil_ok(cp, gx, gy)) {
       s_bad = 1;
       continue;
     }
-    const int cnt = min(cp.wCnt[c], kMaxContrib);
-    int32_t *L = cp.wList + (size_t)c * kMaxContrib;
+    const int32_t *L = cp.wList + (size_t)c * kMaxContrib;
+    int32_t *O = cp.sList + (size_t)q * kMaxContrib;
     if (cnt <= 16) {
-      int v[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) v[r] = r < cnt ? L[r] : 0x7fffffff;
-      sort_net<16>(v);
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        if (r < cnt) L[r] = v[r];
-    } else {
-      int v[kMaxContrib];
-#pragma unroll
-      for (int r = 0; r < kMaxContrib; ++r) v[r] = r < cnt ? L[r] : 0x7fffffff;
-      sort_net<kMaxContrib>(v);
-#pragma unroll
-      for (int r = 0; r < kMaxContrib; ++r)
-        if (r < cnt) L[r] = v[r];
+      sorted_copy<16>(L, cnt, O);
+    } else {  // rare: more than 16 markers over one cell
+      for (int r = 0; r < cnt; ++r) {
+        int v = L[r], w = r - 1;
+        while (w >= 0 && O[w] > v) {
+          O[w + 1] = O[w];
+          --w;
+        }
+        O[w + 1] = v;
+      }
     }
     double rho, ux, uy;
     cell_moments<ST>(a, cp, gx, gy, rho, ux, uy);
-    cp.wRho[c] = rho;
-    cp.wU[c] = ux;
-    cp.wU[(size_t)cp.win_cap + c] = uy;
+    cp.sRho[q] = rho;
+    cp.sU[q] = ux;
+    cp.sV[q] = uy;
+    cp.sFx[q] = 0.0;
+    cp.sFy[q] = 0.0;
+    int4 meta = {cnt, gx, gy, c};
+    *reinterpret_cast<int4 *>(cp.sMeta + 4 * (size_t)q) = meta;
   }
   __syncthreads();
   if (s_bad) {
-    if (tid == 0) {
-      atomicOr(a.err, s_bad == 2 ? ERR_CONTRIB : ERR_MARKER);
-      IbmWindow e = {0, 0, 0, 0};
-      *cp.win = e;
-      *cp.kcount = k + 1;
-    }
+    if (tid == 0) mdf_fail(cp, a.err, s_bad == 2 ? ERR_CONTRIB : ERR_MARKER, k);
     return;
   }
-  // 6. N_F iterations: interpolate (Eq. 12), boundary force (Eq. 11),
+  // 5. N_F iterations: interpolate (Eq. 12), boundary force (Eq. 11),
   //    spread (Eq. 15), correct velocity and accumulate force
   for (int it = 0; it < cp.mdf_iters; ++it) {
     if (own) {
-      const int i0 = s_i0[tid], j0 = s_j0[tid];
       double su = 0.0, sv = 0.0, sr = 0.0;
 #pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        double py = s_wy[bb * NM + tid];
-        int row = (j0 + bb - wy0) * ww + (i0 - wx0);
+      for (int half = 0; half < 2; ++half) {  // two rows of taps per round of loads
+        double uq[8], vq[8], rq[8];
 #pragma unroll
-        for (int aa = 0; aa < 4; ++aa) {
-          double w = s_wx[aa * NM + tid] * py;
-          int c = row + aa;
-          su += cp.wU[c] * w;
-          sv += cp.wU[(size_t)cp.win_cap + c] * w;
-          sr += cp.wRho[c] * w;
+        for (int t = 0; t < 8; ++t) {
+          int q = s_tap[(half * 8 + t) * NM + tid];
+          uq[t] = cp.sU[q];
+          vq[t] = cp.sV[q];
+          rq[t] = cp.sRho[q];
+        }
+#pragma unroll
+        for (int bh = 0; bh < 2; ++bh) {
+          const int bb = half * 2 + bh;
+          double py = s_wy[bb * NM + tid];
+#pragma unroll
+          for (int aa = 0; aa < 4; ++aa) {
+            double w = s_wx[aa * NM + tid] * py;
+            su += uq[bh * 4 + aa] * w;
+            sv += vq[bh * 4 + aa] * w;
+            sr += rq[bh * 4 + aa] * w;
+          }
         }
       }
       double gx = 2.0 * sr * (udx - su);
@@ -1018,27 +1109,39 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     }
     __syncthreads();
     for (int q = tid; q < ns; q += MDF_THREADS) {
-      const int c = cp.sCells[q];
-      const int cnt = cp.wCnt[c];
-      const int32_t *L = cp.wList + (size_t)c * kMaxContrib;
-      int gx = wx0 + c % ww, gy = wy0 + c / ww;
+      const int4 meta = *reinterpret_cast<const int4 *>(cp.sMeta + 4 * (size_t)q);
+      const int cnt = meta.x, gx = meta.y, gy = meta.z;
+      const int32_t *L = cp.sList + (size_t)q * kMaxContrib;
+      const double rho = cp.sRho[q], u0 = cp.sU[q], v0 = cp.sV[q], fx0 = cp.sFx[q], fy0 = cp.sFy[q];
       double dfx = 0.0, dfy = 0.0;
-      for (int q = 0; q < cnt; ++q) {
-        int j = L[q];
-        double w = s_wx[(gx - s_i0[j]) * NM + j] * s_wy[(gy - s_j0[j]) * NM + j];
-        dfx += s_dFx[j] * w * s_ds[j];
-        dfy += s_dFy[j] * w * s_ds[j];
+      for (int r0 = 0; r0 < cnt; r0 += 4) {
+        const int4 v4 = *reinterpret_cast<const int4 *>(L + r0);
+        const int js[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (r0 + r < cnt) {
+            int j = js[r];
+            double w = s_wx[(gx - s_i0[j]) * NM + j] * s_wy[(gy - s_j0[j]) * NM + j];
+            dfx += s_dFx[j] * w * s_ds[j];
+            dfy += s_dFy[j] * w * s_ds[j];
+          }
+        }
       }
-      cp.wF[c] += dfx;
-      cp.wF[(size_t)cp.win_cap + c] += dfy;
-      double r = cp.wRho[c];
-      cp.wU[c] += dfx / (2.0 * r);
-      cp.wU[(size_t)cp.win_cap + c] += dfy / (2.0 * r);
+      cp.sFx[q] = fx0 + dfx;
+      cp.sFy[q] = fy0 + dfy;
+      double r2 = 2.0 * rho;
+      cp.sU[q] = u0 + dfx / r2;
+      cp.sV[q] = v0 + dfy / r2;
     }
     __syncthreads();
   }
-  // 7. total marker forces, and the body force of Eq. (16) summed in marker
-  //    order: wave 0 loads 64 markers per round, lane 0 adds them in order
+  // 6. force density of the stencil cells for the collision, total marker
+  //    forces, and the body force of Eq. (16) summed in marker order
+  for (int q = tid; q < ns; q += MDF_THREADS) {
+    const int c = cp.sMeta[4 * (size_t)q + 3];
+    cp.wF[c] = cp.sFx[q];
+    cp.wF[(size_t)cp.win_cap + c] = cp.sFy[q];
+  }
   double *gtx = cp.ftot + (size_t)(k & 1) * 2 * n;
   double *gty = gtx + n;
   if (own) {
@@ -1048,23 +1151,30 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     s_dFy[tid] = fty * s_ds[tid];
   }
   __syncthreads();
-  if (tid < 64) {
+  if (tid == 0) {
     double fsx = 0.0, fsy = 0.0;
-    for (int base = 0; base < n; base += 64) {
-      int j = base + tid;
-      double vx = j < n ? s_dFx[j] : 0.0, vy = j < n ? s_dFy[j] : 0.0;
-      int cnt = min(64, n - base);
-      for (int q = 0; q < cnt; ++q) {
-        fsx -= __shfl(vx, q, 64);
-        fsy -= __shfl(vy, q, 64);
+    int j = 0;
+    for (; j + 8 <= n; j += 8) {
+      double vx[8], vy[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        vx[r] = s_dFx[j + r];
+        vy[r] = s_dFy[j + r];
+      }
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        fsx -= vx[r];
+        fsy -= vy[r];
       }
     }
-    if (tid == 0) {
-      int64_t slot = k % cp.hist_cap;
-      cp.hist[2 * slot] = fsx;
-      cp.hist[2 * slot + 1] = fsy;
-      *cp.kcount = k + 1;
+    for (; j < n; ++j) {
+      fsx -= s_dFx[j];
+      fsy -= s_dFy[j];
     }
+    int64_t slot = k % cp.hist_cap;
+    cp.hist[2 * slot] = fsx;
+    cp.hist[2 * slot + 1] = fsy;
+    *cp.kcount = k + 1;
   }
 }
 
@@ -1144,20 +1254,17 @@ hipError_t launch_level_st(int tile, const LevelArgs *a, hipStream_t s) {
 
 }  // namespace
 
-extern "C" hipError_t sbt_launch_level_fast(int storage, int slow, const LevelArgs *a, hipStream_t s) {
-  if (a->n_blocks <= 0) return hipSuccess;
-  dim3 grid(a->n_blocks);
-#define SBT_TILE_LAUNCH(ST)                                                                          \
-  if (slow) hipLaunchKernelGGL((level_fast_kernel<ST, true>), grid, dim3(256), 0, s, *a);           \
-  else hipLaunchKernelGGL((level_fast_kernel<ST, false>), grid, dim3(256), 0, s, *a);
+extern "C" hipError_t sbt_launch_level_tile(int storage, const LevelArgs *a, hipStream_t s) {
+  int groups = a->n_blocks + (a->n_band + 255) / 256;
+  if (groups <= 0) return hipSuccess;
+  dim3 grid(groups);
   switch (storage) {
-    case 0: SBT_TILE_LAUNCH(0) break;
-    case 1: SBT_TILE_LAUNCH(1) break;
-    case 2: SBT_TILE_LAUNCH(2) break;
-    case 3: SBT_TILE_LAUNCH(3) break;
+    case 0: hipLaunchKernelGGL(level_tile_kernel<0>, grid, dim3(256), 0, s, *a); break;
+    case 1: hipLaunchKernelGGL(level_tile_kernel<1>, grid, dim3(256), 0, s, *a); break;
+    case 2: hipLaunchKernelGGL(level_tile_kernel<2>, grid, dim3(256), 0, s, *a); break;
+    case 3: hipLaunchKernelGGL(level_tile_kernel<3>, grid, dim3(256), 0, s, *a); break;
     default: return hipErrorInvalidValue;
   }
-#undef SBT_TILE_LAUNCH
   return hipGetLastError();
 }
 
@@ -1171,13 +1278,13 @@ extern "C" hipError_t sbt_launch_level(int storage, int tile, const LevelArgs *a
   return hipErrorInvalidValue;
 }
 
-extern "C" size_t sbt_mdf_lds_bytes(int max_markers) {
-  return (size_t)max_markers * (11 * sizeof(double) + 2 * sizeof(int));
+extern "C" size_t sbt_mdf_lds_bytes(int max_markers, int lds_window) {
+  return (size_t)max_markers * (11 * sizeof(double) + 18 * sizeof(int)) + (size_t)lds_window * sizeof(int);
 }
 
 extern "C" hipError_t sbt_launch_mdf(int storage, const MdfArgs *a, int n_bodies, hipStream_t s) {
   if (n_bodies <= 0) return hipSuccess;
-  size_t lds = sbt_mdf_lds_bytes(a->max_markers);
+  size_t lds = sbt_mdf_lds_bytes(a->max_markers, a->lds_window);
   switch (storage) {
     case 0: hipLaunchKernelGGL(mdf_kernel<0>, dim3(n_bodies), dim3(MDF_THREADS), lds, s, *a); break;
     case 1: hipLaunchKernelGGL(mdf_kernel<1>, dim3(n_bodies), dim3(MDF_THREADS), lds, s, *a); break;
