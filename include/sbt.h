@@ -189,14 +189,17 @@ sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes);
 
 /* Tuning and measurement.
  * SBT_OPT_GRAPH (default 1): replay each step as a captured HIP graph.
- * SBT_OPT_TILE: level-kernel tile variant 0 = one cell per lane, 256 lanes
- *   per block; 1 = two cells per lane, 128 lanes; 2 = four cells per lane.
+ * SBT_OPT_TILE: interior 16x16 blocks per workgroup of the stream+collide
+ *   launch, 1..16 for every level (a workgroup loads block j+1 while it
+ *   computes block j); 0 (default) = automatic per launch size.
  * SBT_OPT_XCD_REMAP (default 1): map consecutive Morton blocks to one XCD. */
 enum { SBT_OPT_GRAPH = 0, SBT_OPT_TILE = 1, SBT_OPT_XCD_REMAP = 2 };
 sbt_status sbt_set_option(sbt_ctx *ctx, int32_t option, int32_t value);
-/* Time each tile variant over `steps` steps and keep the fastest; if
- * cache_path is non-NULL the choice is read from / written to that JSON file
- * keyed by the workload's shape.  The state is restored afterwards. */
+/* Pick the blocks per workgroup of each level by timing `steps` steps per
+ * trial (1, 2, 4, 8; finest level first, one level at a time) and keep the
+ * fastest; if cache_path is non-NULL the choice is read from / written to
+ * that JSON file keyed by the storage and the block counts.  The simulation
+ * state is restored afterwards. */
 sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path);
 /* Run n steps eagerly with HIP events around every launch, on the context's
  * stream.  out[0] = total ms of level (collide+stream) kernels, out[1] = their

@@ -35,6 +35,9 @@ sbt_status fail(sbt_status code, const std::string &msg) {
 
 size_t storage_bytes(int st) { return st == SBT_F64 ? 8 : (st == SBT_F32 ? 4 : 2); }
 
+// LDS per workgroup on gfx950.
+constexpr size_t kLdsBytes = 163840;
+
 uint32_t morton(uint32_t x, uint32_t y) {
   auto spread = [](uint32_t v) {
     v &= 0xffff;
@@ -276,7 +279,13 @@ struct sbt_ctx {
   hipStream_t cap_stream = nullptr;
   bool post = false;               // false: lattices hold the initial pre-collision state
   int tile = 0, xcd = 1, use_graph = 1;
-  int lds_window = 0;
+  std::vector<int> kpw_level;   // interior blocks per workgroup per virtual level (0: automatic)
+  int lds_window = 0;           // IBM window cells whose plan-builder counters fit in LDS
+  int cell_cap = 0;             // stencil cells per IBM plan (fits the forcing kernel's LDS)
+  int max_body_markers = 0;     // largest body set so far (LDS table stride)
+  bool need_prep = true;        // the plan of the next finest substep must be built first
+  std::vector<hipStream_t> prep_streams;
+  std::vector<hipEvent_t> ev_lvl, ev_prep;
   std::vector<Phase> step_phases;
   std::vector<hipGraphExec_t> graph;   // [group * 2 + parity]
   hipEvent_t step_event = nullptr;
@@ -314,12 +323,9 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     X.V = std::max(X.V, C.F.m);
   }
   const size_t s = storage_bytes(X.storage);
-  // Case groups: independent chains of launches that a step graph runs side
-  // by side, so one group's latency-bound IBM launches overlap another
-  // group's bandwidth-bound level launches.  Cases go to the least-loaded
-  // group (work = cell updates per step).
-  X.G = n_cases >= 16 ? std::min(4, n_cases / 16) : 1;
-  if (const char *e = std::getenv("SBT_GROUPS")) X.G = std::max(1, std::min(n_cases, std::atoi(e)));
+  // One launch chain holds every case: each phase is one launch over the
+  // blocks of all cases (the group tables keep the case-to-chain map).
+  X.G = 1;
   {
     std::vector<std::pair<double, int>> work;
     for (int c = 0; c < n_cases; ++c) {
@@ -384,6 +390,16 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     C.win_cap = (int)std::min(area, side * side);
     C.hist_cap = (size_t)C.d.history_cap;
   }
+  // Stencil cells per IBM plan: what the forcing kernel's LDS holds next to
+  // the marker tables of the largest body (160 KB per workgroup on gfx950),
+  // at most four per lane.
+  {
+    int nm = 0;
+    for (auto &C : X.cs) nm = std::max(nm, C.has_body ? C.d.max_markers : 0);
+    long cap = ((long)kLdsBytes - 2048 - (long)sbt_mdf_lds_bytes(nm, 0)) / (long)sbt_mdf_lds_bytes(0, 1);
+    X.cell_cap = (int)std::max(0L, std::min(4096L, cap));
+    if (nm > 0 && X.cell_cap < 64) return fail(SBT_ERR_ARG, "max_markers too large for one workgroup's LDS");
+  }
   build_tables(X);
   // Device memory plan.
   size_t max_blocks = 1;
@@ -416,20 +432,19 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     D.ftot = (double *)cv.take(sizeof(double) * 4 * N);
     D.hist = (double *)cv.take(sizeof(double) * 2 * C.hist_cap);
     D.kcount = (int64_t *)cv.take(sizeof(int64_t));
-    D.win = (IbmWindow *)cv.take(sizeof(IbmWindow));
-    D.wF = (double *)cv.take(sizeof(double) * 2 * C.win_cap);
+    D.pk = (int64_t *)cv.take(sizeof(int64_t));
+    const size_t nm = (size_t)C.d.max_markers, cc = (size_t)X.cell_cap;
+    D.win = (IbmWindow *)cv.take(sizeof(IbmWindow) * 2);
+    D.phdr = (int32_t *)cv.take(sizeof(int32_t) * 8);
+    D.wF = (double *)cv.take(sizeof(double) * 4 * C.win_cap);
     D.wCnt = (int32_t *)cv.take(sizeof(int32_t) * C.win_cap);
     D.wIdx = (int32_t *)cv.take(sizeof(int32_t) * C.win_cap);
-    D.wList = (int32_t *)cv.take(sizeof(int32_t) * kMaxContrib * (size_t)C.win_cap);
-    D.sCells = (int32_t *)cv.take(sizeof(int32_t) * (size_t)C.win_cap);
-    D.sList = (int32_t *)cv.take(sizeof(int32_t) * kMaxContrib * (size_t)C.win_cap);
-    D.sRho = (double *)cv.take(sizeof(double) * C.win_cap);
-    D.sU = (double *)cv.take(sizeof(double) * C.win_cap);
-    D.sV = (double *)cv.take(sizeof(double) * C.win_cap);
-    D.sFx = (double *)cv.take(sizeof(double) * C.win_cap);
-    D.sFy = (double *)cv.take(sizeof(double) * C.win_cap);
-    D.sMeta = (int32_t *)cv.take(sizeof(int32_t) * 4 * (size_t)C.win_cap);
-    D.sCount = (int32_t *)cv.take(sizeof(int32_t));
+    D.p_ij = (int32_t *)cv.take(sizeof(int32_t) * 4 * nm);
+    D.p_w = (double *)cv.take(sizeof(double) * 16 * nm);
+    D.p_ud = (double *)cv.take(sizeof(double) * 4 * nm);
+    D.p_tap = (uint16_t *)cv.take(sizeof(uint16_t) * 32 * nm);
+    D.p_cell = (int32_t *)cv.take(sizeof(int32_t) * 16 * cc);
+    D.p_list = (uint16_t *)cv.take(sizeof(uint16_t) * 32 * nm);
     D.bmap = (const int32_t *)cv.take(sizeof(int32_t) * (size_t)D.bm_w * D.bm_h);
   }
   return SBT_OK;
@@ -563,6 +578,8 @@ void build_tables(sbt_ctx &X) {
     D.mdf_iters = d.mdf_iters;
     D.hist_cap = (int32_t)C.hist_cap;
     D.win_cap = C.win_cap;
+    D.nm_cap = C.d.max_markers;
+    D.cell_cap = X.cell_cap;
   }
   // launch lists: interior blocks take the LDS-staged kernel
   for (auto &P : X.pools) {
@@ -623,6 +640,21 @@ struct Timer {
   hipEvent_t a = nullptr, b = nullptr;
 };
 
+// Interior blocks per workgroup of a tile launch.  Automatic: for 2-byte
+// storage as many as keep about four workgroups per resident slot (256 CUs
+// x 8), up to 8, so small launches still fill the chip and large ones
+// pipeline their loads; one otherwise.
+int blocks_per_wg(const sbt_ctx &X, int v, int n_fast) {
+  int k = v < (int)X.kpw_level.size() ? X.kpw_level[v] : 0;
+  if (k > 0) return k;
+  // 8- and 4-byte storage saturate HBM with one block per workgroup; the
+  // 2-byte forms move too few bytes per block to hide latency without runs
+  if (storage_bytes(X.storage) > 2) return 1;
+  k = 1;
+  while (k < 8 && (int64_t)n_fast >= (int64_t)k * 2 * 4 * 2048) k *= 2;
+  return k;
+}
+
 sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s) {
   Pool &P = X.pools[(size_t)g * X.V + v];
   LevelArgs a;
@@ -662,6 +694,7 @@ sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s
     t.list = P.d_list;
     t.n_fast = (int)P.fast.size();
     t.n_blocks = (int)(P.fast.size() + P.slow.size());
+    t.kpw = blocks_per_wg(X, v, t.n_fast);
     if (p == 1) {
       t.band = P.d_band;
       t.n_band = (int)P.band.size();
@@ -671,7 +704,7 @@ sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s
     a.list = nullptr;
     a.b0 = 0;
     a.n_blocks = P.n_own;
-    st = timed(false, [&] { return sbt_launch_level(X.storage, X.tile, &a, s); });
+    st = timed(false, [&] { return sbt_launch_level(X.storage, 0, &a, s); });
   }
   if (st) return st;
   P.cur = 1 - P.cur;
@@ -689,9 +722,8 @@ sbt_status launch_mdf(sbt_ctx &X, int g, bool first, hipStream_t s) {
   a.body_cases = Gr.d_body_cases;
   a.first = first ? 1 : 0;
   a.err = X.d_err;
-  a.max_markers = 0;
-  for (auto &C : X.cs) a.max_markers = std::max(a.max_markers, C.n_markers);
-  a.lds_window = X.lds_window;
+  a.max_markers = X.max_body_markers;
+  a.cell_cap = X.cell_cap;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (X.profiling) {
     HIPCHK(hipEventCreate(&e0));
@@ -706,17 +738,53 @@ sbt_status launch_mdf(sbt_ctx &X, int g, bool first, hipStream_t s) {
   return SBT_OK;
 }
 
+// Build the IBM plan of the next finest substep of group g's bodies
+// (from_kcount: of the substep the forcing loop runs next, after a restart).
+sbt_status launch_prep(sbt_ctx &X, int g, bool from_kcount, hipStream_t s) {
+  GroupInfo &Gr = X.groups[g];
+  if (Gr.n_bodies == 0) return SBT_OK;
+  IbmArgs a;
+  a.cases = X.d_cases;
+  a.body_cases = Gr.d_body_cases;
+  a.max_markers = X.max_body_markers;
+  a.cell_cap = X.cell_cap;
+  a.lds_window = X.lds_window;
+  a.from_kcount = from_kcount ? 1 : 0;
+  HIPCHK(sbt_launch_ibm_prep(&a, Gr.n_bodies, s));
+  return SBT_OK;
+}
+
+// The forcing loop of finest substep k needs its plan; the plan of k+1 is
+// built right before it (in stream order after the collision of k-1, the
+// last reader of that plan buffer).
+sbt_status launch_forcing(sbt_ctx &X, int g, bool first, hipStream_t s) {
+  sbt_status st = launch_prep(X, g, false, s);
+  if (st) return st;
+  return launch_mdf(X, g, first, s);
+}
+
+sbt_status initial_plans(sbt_ctx &X, hipStream_t s) {
+  for (int g = 0; g < X.G; ++g) {
+    sbt_status st = launch_prep(X, g, true, s);
+    if (st) return st;
+  }
+  X.need_prep = false;
+  return SBT_OK;
+}
+
 // Collide once on every level from the initial pre-collision state (the
 // first CollisionStep of every level), finest first so that each coarse
 // level explodes into its finer level's current lattice.
 sbt_status run_prologue(sbt_ctx &X, hipStream_t s) {
+  sbt_status st = initial_plans(X, s);
+  if (st) return st;
   for (int g = 0; g < X.G; ++g)
     for (int v = X.V - 1; v >= 0; --v) {
       if (v == X.V - 1) {
-        sbt_status st = launch_mdf(X, g, true, s);
+        st = launch_forcing(X, g, true, s);
         if (st) return st;
       }
-      sbt_status st = launch_level(X, g, v, 1, MODE_LOCAL, s);
+      st = launch_level(X, g, v, 1, MODE_LOCAL, s);
       if (st) return st;
     }
   X.post = true;
@@ -725,13 +793,55 @@ sbt_status run_prologue(sbt_ctx &X, hipStream_t s) {
 
 sbt_status run_group_step(sbt_ctx &X, int g, hipStream_t s) {
   for (const Phase &ph : X.step_phases) {
-    sbt_status st = ph.type == PH_MDF ? launch_mdf(X, g, false, s) : launch_level(X, g, ph.v, ph.p, 0, s);
+    sbt_status st = ph.type == PH_MDF ? launch_forcing(X, g, false, s) : launch_level(X, g, ph.v, ph.p, 0, s);
     if (st) return st;
   }
   return SBT_OK;
 }
 
+// Group g's step inside a graph capture: launches on stream s, the plan
+// builder on its own stream r, so the plan of substep k+1 is built while
+// the forcing loop and the collision of substep k run.  ev_lvl[0] forks r;
+// ev_lvl[i + 1] follows the i-th finest collision, ev_prep[i] the i-th plan.
+sbt_status capture_group_step(sbt_ctx &X, int g, hipStream_t s, hipStream_t r, const hipEvent_t *ev_lvl,
+                              const hipEvent_t *ev_prep, int n_mdf) {
+  HIPCHK(hipEventRecord(ev_lvl[0], s));
+  HIPCHK(hipStreamWaitEvent(r, ev_lvl[0], 0));
+  int im = 0, il = 0;
+  for (const Phase &ph : X.step_phases) {
+    sbt_status st = SBT_OK;
+    if (ph.type == PH_MDF) {
+      if (im >= n_mdf) return fail(SBT_ERR_STATE, "phase list has more forcing phases than planned");
+      st = launch_prep(X, g, false, r);
+      if (st) return st;
+      HIPCHK(hipEventRecord(ev_prep[im], r));
+      if (im > 0) HIPCHK(hipStreamWaitEvent(s, ev_prep[im - 1], 0));
+      st = launch_mdf(X, g, false, s);
+      ++im;
+    } else {
+      st = launch_level(X, g, ph.v, ph.p, 0, s);
+      if (!st && ph.v == X.V - 1 && il < n_mdf) {
+        HIPCHK(hipEventRecord(ev_lvl[il + 1], s));
+        HIPCHK(hipStreamWaitEvent(r, ev_lvl[il + 1], 0));
+        ++il;
+      }
+    }
+    if (st) return st;
+  }
+  // join: the step ends when its last plan is built
+  if (im > 0) HIPCHK(hipStreamWaitEvent(s, ev_prep[im - 1], 0));
+  else {
+    HIPCHK(hipEventRecord(ev_lvl[n_mdf], r));
+    HIPCHK(hipStreamWaitEvent(s, ev_lvl[n_mdf], 0));
+  }
+  return SBT_OK;
+}
+
 sbt_status run_step_eager(sbt_ctx &X, hipStream_t s) {
+  if (X.need_prep) {
+    sbt_status st = initial_plans(X, s);
+    if (st) return st;
+  }
   for (int g = 0; g < X.G; ++g) {
     sbt_status st = run_group_step(X, g, s);
     if (st) return st;
@@ -748,26 +858,46 @@ void destroy_graphs(sbt_ctx &X) {
   X.graph_dirty = true;
 }
 
+int forcing_phases(const sbt_ctx &X) {
+  int n = 0;
+  for (const Phase &ph : X.step_phases) n += ph.type == PH_MDF;
+  return n;
+}
+
 sbt_status ensure_side_streams(sbt_ctx &X) {
   if (!X.cap_stream) HIPCHK(hipStreamCreateWithFlags(&X.cap_stream, hipStreamNonBlocking));
-  while ((int)X.side_streams.size() < X.G) {
+  auto new_stream = [](std::vector<hipStream_t> &v) -> hipError_t {
     hipStream_t st;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) v.push_back(st);
+    return e;
+  };
+  auto new_event = [](std::vector<hipEvent_t> &v) -> hipError_t {
     hipEvent_t ev;
-    HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    X.side_streams.push_back(st);
-    X.fork_events.push_back(ev);
+    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) v.push_back(ev);
+    return e;
+  };
+  while ((int)X.side_streams.size() < X.G) {
+    HIPCHK(new_stream(X.side_streams));
+    HIPCHK(new_event(X.fork_events));
   }
+  while ((int)X.prep_streams.size() < X.G) HIPCHK(new_stream(X.prep_streams));
+  const int nm = forcing_phases(X);
+  while ((int)X.ev_lvl.size() < X.G * (nm + 1)) HIPCHK(new_event(X.ev_lvl));
+  while ((int)X.ev_prep.size() < X.G * std::max(1, nm)) HIPCHK(new_event(X.ev_prep));
   if (X.graph.size() != 2) X.graph.assign(2, nullptr);
   return SBT_OK;
 }
 
 // One step as a graph: each case group's launch chain is a branch of its
 // own (forked from and joined back to the capture stream), so one group's
-// latency-bound IBM launches overlap other groups' level launches.
+// latency-bound IBM launches overlap other groups' level launches; within a
+// group the plan builder runs on a branch beside the chain.
 sbt_status capture_graph(sbt_ctx &X, int parity) {
   sbt_status st0 = ensure_side_streams(X);
   if (st0) return st0;
+  const int nm = forcing_phases(X);
   std::vector<int> saved(X.pools.size());
   for (size_t i = 0; i < X.pools.size(); ++i) saved[i] = X.pools[i].cur;
   hipGraph_t g = nullptr;
@@ -778,15 +908,24 @@ sbt_status capture_graph(sbt_ctx &X, int parity) {
     e = hipEventRecord(X.fork_events[0], X.cap_stream);
     for (int k = 1; k < X.G && e == hipSuccess; ++k) e = hipStreamWaitEvent(X.side_streams[k], X.fork_events[0], 0);
   }
-  for (int k = 0; k < X.G && !st && e == hipSuccess; ++k)
-    st = run_group_step(X, k, k == 0 ? X.cap_stream : X.side_streams[k]);
+  for (int k = 0; k < X.G && !st && e == hipSuccess; ++k) {
+    hipStream_t sk = k == 0 ? X.cap_stream : X.side_streams[k];
+    if (X.groups[k].n_bodies > 0)
+      st = capture_group_step(X, k, sk, X.prep_streams[k], &X.ev_lvl[(size_t)k * (nm + 1)],
+                              &X.ev_prep[(size_t)k * std::max(1, nm)], nm);
+    else
+      st = run_group_step(X, k, sk);
+  }
   for (int k = 1; k < X.G && !st && e == hipSuccess; ++k) {
     e = hipEventRecord(X.fork_events[k], X.side_streams[k]);
     if (e == hipSuccess) e = hipStreamWaitEvent(X.cap_stream, X.fork_events[k], 0);
   }
   hipError_t e2 = hipStreamEndCapture(X.cap_stream, &g);
   for (size_t i = 0; i < X.pools.size(); ++i) X.pools[i].cur = saved[i];
-  if (st) return st;
+  if (st) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
   if (e != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph fork/join: ") + hipGetErrorString(e));
   if (e2 != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e2));
   e = hipGraphInstantiate(&X.graph[parity], g, nullptr, nullptr, 0);
@@ -864,9 +1003,11 @@ sbt_status reset_counters(sbt_ctx &X) {
   for (auto &C : X.cs) {
     if (!C.has_body) continue;
     HIPCHK(hipMemsetAsync(C.dev.kcount, 0, sizeof(int64_t), X.stream));
-    HIPCHK(hipMemsetAsync(C.dev.win, 0, sizeof(IbmWindow), X.stream));
+    HIPCHK(hipMemsetAsync(C.dev.pk, 0, sizeof(int64_t), X.stream));
+    HIPCHK(hipMemsetAsync(C.dev.win, 0, 2 * sizeof(IbmWindow), X.stream));
   }
   X.post = false;
+  X.need_prep = true;
   for (auto &P : X.pools) P.cur = 0;
   destroy_graphs(X);
   return SBT_OK;
@@ -971,7 +1112,10 @@ sbt_status sbt_destroy(sbt_ctx *ctx) {
   destroy_graphs(*ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (auto st : ctx->side_streams) (void)hipStreamDestroy(st);
+  for (auto st : ctx->prep_streams) (void)hipStreamDestroy(st);
   for (auto ev : ctx->fork_events) (void)hipEventDestroy(ev);
+  for (auto ev : ctx->ev_lvl) (void)hipEventDestroy(ev);
+  for (auto ev : ctx->ev_prep) (void)hipEventDestroy(ev);
   if (ctx->step_event) (void)hipEventDestroy(ctx->step_event);
   delete ctx;
   return SBT_OK;
@@ -1103,11 +1247,13 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
     HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     int nmax = body->n;
     for (auto &K : X.cs) nmax = std::max(nmax, K.n_markers);
-    if (sbt_mdf_lds_bytes(nmax, 0) + 1024 > (size_t)lds_max)
+    const size_t mdf = sbt_mdf_lds_bytes(nmax, X.cell_cap), prep = sbt_prep_lds_bytes(nmax, X.cell_cap, 0);
+    if (mdf + 1024 > (size_t)lds_max || prep + 1024 > (size_t)lds_max)
       return fail(SBT_ERR_ARG, "too many markers for one workgroup's LDS (" + std::to_string(lds_max) + " bytes)");
-    // window counters in LDS with what is left (global atomics beyond that)
-    size_t left = (size_t)lds_max - 1024 - sbt_mdf_lds_bytes(nmax, 0);
-    X.lds_window = (int)std::min<size_t>(16384, left / sizeof(int32_t));
+    // the plan builder keeps window counters in LDS with what is left
+    // (global memory beyond that)
+    X.lds_window = (int)std::min<size_t>(16384, ((size_t)lds_max - 1024 - prep) / (2 * sizeof(int32_t)));
+    X.max_body_markers = nmax;
   }
   HIPCHK(hipStreamSynchronize(X.stream));
   const size_t N = (size_t)body->n;
@@ -1141,6 +1287,9 @@ sbt_status sbt_step(sbt_ctx *ctx, int32_t n) {
   if (!X.post) {
     sbt_status st = run_prologue(X, X.stream);
     if (st) return st;
+  } else if (X.need_prep) {
+    sbt_status st = initial_plans(X, X.stream);
+    if (st) return st;
   }
   for (int t = 0; t < n; ++t) {
     if (X.use_graph && !X.profiling) {
@@ -1173,8 +1322,10 @@ sbt_status sbt_synchronize(sbt_ctx *ctx) {
     HIPCHK(hipMemset(ctx->d_err, 0, sizeof(err)));
     if (err[0] & ERR_NONFINITE) return fail(SBT_ERR_NONFINITE, "a density became NaN or Inf");
     if (err[0] & ERR_MARKER) return fail(SBT_ERR_MARKER_OUTSIDE, "a marker stencil left the finest owned cells");
-    if (err[0] & ERR_CONTRIB) return fail(SBT_ERR_MARKER_OUTSIDE, "more than 32 markers cover one cell");
+    if (err[0] & ERR_CONTRIB)
+      return fail(SBT_ERR_MARKER_OUTSIDE, "IBM stencil cells exceed the plan capacity (" + std::to_string(ctx->cell_cap) + ")");
     if (err[0] & ERR_WINDOW) return fail(SBT_ERR_MARKER_OUTSIDE, "IBM window larger than planned");
+    if (err[0] & ERR_PLAN) return fail(SBT_ERR_STATE, "IBM plan out of step with the forcing loop");
   }
   return SBT_OK;
 }
@@ -1385,6 +1536,7 @@ sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes) {
     p += nb;
   }
   X.post = h.post != 0;
+  X.need_prep = true;
   for (size_t i = 0; i < X.pools.size(); ++i) X.pools[i].cur = curs[i];
   destroy_graphs(X);
   return SBT_OK;
@@ -1396,8 +1548,9 @@ sbt_status sbt_set_option(sbt_ctx *ctx, int32_t option, int32_t value) {
   switch (option) {
     case SBT_OPT_GRAPH: ctx->use_graph = value != 0; break;
     case SBT_OPT_TILE:
-      if (value < 0 || value > 2) return fail(SBT_ERR_ARG, "tile variant must be 0..2");
+      if (value < 0 || value > 16) return fail(SBT_ERR_ARG, "blocks per workgroup must be 0..16");
       ctx->tile = value;
+      ctx->kpw_level.assign(ctx->V, value);
       break;
     case SBT_OPT_XCD_REMAP: ctx->xcd = value != 0; break;
     default: return fail(SBT_ERR_ARG, "unknown option");
@@ -1453,12 +1606,18 @@ sbt_status sbt_profile(sbt_ctx *ctx, int32_t n, double out[9]) {
   return SBT_OK;
 }
 
+static std::string kpw_string(const std::vector<int> &k) {
+  std::string r;
+  for (size_t i = 0; i < k.size(); ++i) r += (i ? "," : "") + std::to_string(k[i]);
+  return r;
+}
+
 sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path) {
   if (!ctx || steps <= 0) return fail(SBT_ERR_ARG, "bad argument");
   sbt_ctx &X = *ctx;
-  // cache key: storage, pools and their block counts
+  // cache key: storage and the block counts of every pool
   std::ostringstream key;
-  key << "st" << X.storage;
+  key << "st" << X.storage << "_g" << X.G;
   for (auto &P : X.pools) key << "_" << P.n_own << "/" << P.n_ghost;
   if (cache_path) {
     std::ifstream in(cache_path);
@@ -1466,8 +1625,18 @@ sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path) {
     while (std::getline(in, line)) {
       size_t k = line.find("\"" + key.str() + "\"");
       if (k == std::string::npos) continue;
-      size_t c = line.find(':', k);
-      if (c != std::string::npos) return sbt_set_option(ctx, SBT_OPT_TILE, std::atoi(line.c_str() + c + 1));
+      size_t q0 = line.find('"', line.find(':', k));
+      size_t q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
+      if (q1 == std::string::npos) continue;
+      std::vector<int> got;
+      std::stringstream ss(line.substr(q0 + 1, q1 - q0 - 1));
+      std::string tok;
+      while (std::getline(ss, tok, ',')) got.push_back(std::atoi(tok.c_str()));
+      if ((int)got.size() == X.V) {
+        X.kpw_level = got;
+        destroy_graphs(X);
+        return SBT_OK;
+      }
     }
   }
   size_t sb = 0;
@@ -1479,30 +1648,48 @@ sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  int best = 0;
-  float best_ms = 1e30f;
-  for (int tile = 0; tile < 3; ++tile) {
-    sbt_set_option(ctx, SBT_OPT_TILE, tile);
-    st = sbt_step(ctx, 1);  // warm-up (captures the graph)
-    if (st) break;
+  // start from the automatic choice, then settle one level at a time,
+  // finest first (it carries most of the updates)
+  std::vector<int> cur(X.V);
+  for (int v = 0; v < X.V; ++v) {
+    int nf = 0;
+    for (int g = 0; g < X.G; ++g) nf = std::max(nf, (int)X.pools[(size_t)g * X.V + v].fast.size());
+    X.kpw_level.assign(X.V, 0);
+    cur[v] = blocks_per_wg(X, v, nf);
+  }
+  auto trial = [&](const std::vector<int> &k, float &ms) -> sbt_status {
+    X.kpw_level = k;
+    destroy_graphs(X);
+    sbt_status r = sbt_step(ctx, 1);  // warm-up (captures the graph)
+    if (r) return r;
     HIPCHK(hipEventRecord(e0, X.stream));
-    st = sbt_step(ctx, steps);
-    if (st) break;
+    r = sbt_step(ctx, steps);
+    if (r) return r;
     HIPCHK(hipEventRecord(e1, X.stream));
     HIPCHK(hipEventSynchronize(e1));
-    float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
-      best_ms = ms;
-      best = tile;
+    return sbt_write_state(ctx, saved.data(), sb);
+  };
+  float best_ms = 0;
+  st = trial(cur, best_ms);
+  for (int v = X.V - 1; v >= 0 && !st; --v) {
+    for (int k : {1, 2, 4, 8}) {
+      if (k == cur[v]) continue;
+      std::vector<int> t = cur;
+      t[v] = k;
+      float ms = 0;
+      st = trial(t, ms);
+      if (st) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        cur = t;
+      }
     }
-    st = sbt_write_state(ctx, saved.data(), sb);
-    if (st) break;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (st) return st;
-  st = sbt_set_option(ctx, SBT_OPT_TILE, best);
+  X.kpw_level = cur;
+  destroy_graphs(X);
   if (st) return st;
   if (cache_path) {
     std::ifstream in(cache_path);
@@ -1517,7 +1704,7 @@ sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path) {
         while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
         lines.push_back(line);
       }
-    lines.push_back("  \"" + key.str() + "\": " + std::to_string(best));
+    lines.push_back("  \"" + key.str() + "\": \"" + kpw_string(cur) + "\"");
     std::ofstream out(cache_path);
     out << "{\n";
     for (size_t k = 0; k < lines.size(); ++k) out << lines[k] << (k + 1 < lines.size() ? ",\n" : "\n");

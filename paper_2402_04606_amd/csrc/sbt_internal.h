@@ -9,7 +9,6 @@ constexpr int kQ = 9;
 constexpr int kB = 16;           // block edge in cells
 constexpr int kCells = kB * kB;  // cells per block
 constexpr int kMaxLevels = 6;
-constexpr int kMaxContrib = 32;  // markers whose 4x4 stencil may cover one cell
 constexpr int kMaxMarkers = 1024; // markers per body (one per lane of the MDF workgroup)
 
 // Block flags.
@@ -68,18 +67,20 @@ struct alignas(16) CaseDev {
   const double *xb, *yb, *ds;
   double *ftot;                // [2 slots][2][n]: total marker force, slot = substep parity
   double *hist;                // [hist_cap][2]
-  int64_t *kcount;             // finest substeps done
-  IbmWindow *win;
-  double *wF;                  // [2][win_cap]  force density in the window
-  int32_t *wCnt;               // [win_cap] markers whose stencil covers the cell
-  int32_t *wIdx;               // [win_cap] compact index of the cell (stencil cells)
-  int32_t *wList;              // [win_cap][kMaxContrib] those markers (unordered)
-  int32_t *sCells;             // [win_cap] window index of each stencil cell (compact)
-  int32_t *sList;              // [win_cap][kMaxContrib] compact cell's markers, ascending
-  double *sRho, *sU, *sV;      // [win_cap] compact cell moments (u, v corrected in place)
-  double *sFx, *sFy;           // [win_cap] compact cell IBM force
-  int32_t *sMeta;              // [win_cap][4] compact cell: count, gx, gy, window index
-  int32_t *sCount;             // number of stencil cells
+  int64_t *kcount;             // finest substeps whose forcing loop has run
+  int64_t *pk;                 // finest substeps whose IBM plan has been built
+  int32_t nm_cap;              // marker capacity of the plan buffers
+  int32_t cell_cap;            // stencil-cell capacity of a plan
+  IbmWindow *win;              // [2] window of the plan in buffer (k & 1)
+  int32_t *phdr;               // [2][4] plan header: stamp (low 32 bits of k), stencil cells, status, 0
+  double *wF;                  // [2][2][win_cap] force density in the window, per plan buffer
+  int32_t *wCnt, *wIdx;        // [win_cap] plan builder's counters / compact index beyond LDS
+  int32_t *p_ij;               // [2][2][nm_cap] first tap of each marker (x, y)
+  double *p_w;                 // [2][8][nm_cap] Peskin weights of the 4 x and 4 y taps
+  double *p_ud;                // [2][2][nm_cap] desired marker velocity
+  uint16_t *p_tap;             // [2][16][nm_cap] stencil cell of each tap
+  int32_t *p_cell;             // [2][cell_cap][8] window index, 4 source blocks, list start, count, 0
+  uint16_t *p_list;            // [2][16 nm_cap] markers over each stencil cell, ascending
   const int32_t *bmap;         // finest-level block map -> pool index (-1 outside)
 };
 
@@ -98,6 +99,7 @@ struct LevelArgs {
   int32_t b0;
   int32_t n_blocks;            // entries of list (or length of the range)
   int32_t n_fast;              // leading list entries that are interior blocks
+  int32_t kpw;                 // interior blocks per workgroup (tile launch, >= 1)
   const int32_t *band;         // halo-band cells (block * 256 + cell), gathered after the blocks
   int32_t n_band;
   int32_t mode;                // MODE_* bits
@@ -113,16 +115,25 @@ struct MdfArgs {
   const CaseDev *cases;
   const int32_t *body_cases;   // case index per workgroup
   int32_t first;               // 1: local read (initial pre-collision state)
-  int32_t max_markers;         // sizes the workgroup's LDS marker tables
-  int32_t lds_window;          // window cells whose counters fit in LDS
+  int32_t max_markers;         // LDS marker-table stride (>= every body's markers)
+  int32_t cell_cap;            // LDS stencil-cell table size (>= every plan's cells)
   int32_t *err;
+};
+
+struct IbmArgs {
+  const CaseDev *cases;
+  const int32_t *body_cases;   // case index per workgroup
+  int32_t max_markers;         // LDS list stride (>= every body's markers)
+  int32_t cell_cap;            // stencil-cell capacity
+  int32_t lds_window;          // window cells whose counters fit in LDS
+  int32_t from_kcount;         // 1: plan substep kcount (restart), else pk
 };
 
 // Level launch modes: LOCAL = read the cell's own populations (initial
 // pre-collision state) instead of streaming; READOUT = moments only, no write.
 enum : int32_t { MODE_LOCAL = 1, MODE_READOUT = 2 };
 
-enum : int32_t { ERR_NONFINITE = 1, ERR_MARKER = 2, ERR_CONTRIB = 4, ERR_WINDOW = 8 };
+enum : int32_t { ERR_NONFINITE = 1, ERR_MARKER = 2, ERR_CONTRIB = 4, ERR_WINDOW = 8, ERR_PLAN = 16 };
 
 }  // namespace sbt
 
@@ -133,11 +144,15 @@ extern "C" {
 hipError_t sbt_launch_level(int storage, int tile, const sbt::LevelArgs *a, hipStream_t s);
 // One LDS-staged stream + collide launch for a level substep: list entries
 // [0, n_fast) are interior blocks (no cell codes, no domain edge, all eight
-// neighbours present), [n_fast, n_blocks) blocks next to a finer level or a
-// domain edge; then n_band packed halo-band cells.
+// neighbours present), kpw of them per workgroup; [n_fast, n_blocks) blocks
+// next to a finer level or a domain edge; then n_band packed halo-band cells.
 hipError_t sbt_launch_level_tile(int storage, const sbt::LevelArgs *a, hipStream_t s);
+// IBM plan of the next finest substep of every body, one workgroup each.
+hipError_t sbt_launch_ibm_prep(const sbt::IbmArgs *a, int n_bodies, hipStream_t s);
+// Multi-direct forcing loop of the current finest substep on its plan.
 hipError_t sbt_launch_mdf(int storage, const sbt::MdfArgs *a, int n_bodies, hipStream_t s);
-size_t sbt_mdf_lds_bytes(int max_markers, int lds_window);
+size_t sbt_mdf_lds_bytes(int max_markers, int cell_cap);
+size_t sbt_prep_lds_bytes(int max_markers, int cell_cap, int lds_window);
 hipError_t sbt_launch_reduce(const double *partial, int n_blocks, double vol, double *out,
                              int accumulate, hipStream_t s);
 hipError_t sbt_launch_fill_nan(void *p, size_t n_elems, int storage, hipStream_t s);

@@ -216,33 +216,69 @@ struct Collide<0> {
 
 template <int ST>
 struct Collide {
-  // deviation form: f = w rho0 + d;  rho = rho0 + sum d;  sum c f = sum c d
+  // Deviation form (f = w rho0 + d): rho = rho0 + sum d, sum c f = sum c d,
+  // and d^eq = w (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2)), evaluated with
+  // the shared terms of the D2Q9 directions.  The Guo term is added only
+  // where the force is nonzero.
   __device__ __forceinline__ static void run(const CaseDev &cp, int l, float d[9], float Fx, float Fy, float &rho,
-                             float &ux, float &uy) {
-    float drho = 0.f, jx = 0.f, jy = 0.f;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      drho += d[i];
-      jx += CX[i] * d[i];
-      jy += CY[i] * d[i];
-    }
+                                             float &ux, float &uy) {
+    const float e = d[1] + d[5] + d[8], w = d[3] + d[6] + d[7];   // c_x = +1, -1
+    const float n = d[2] + d[5] + d[6], s = d[4] + d[7] + d[8];   // c_y = +1, -1
+    const float jx = e - w, jy = n - s;
+    const float drho = d[0] + (e + w) + (d[2] + d[4]);
     rho = (float)cp.rho0 + drho;
-    float ir = 1.0f / rho;
+    const float ir = __builtin_amdgcn_rcpf(rho);
     ux = (jx + 0.5f * Fx) * ir;
     uy = (jy + 0.5f * Fy) * ir;
-    float usq = ux * ux + uy * uy;
-    float om = cp.omega_f[l];
-    float pre = cp.pre_f[l];
-    float uF = ux * Fx + uy * Fy;
+    const float om = cp.omega_f[l];
+    const float A = drho - rho * (1.5f * (ux * ux + uy * uy));
+    const float W1 = 1.0f / 9.0f, W2 = 1.0f / 36.0f;
+    auto relax = [&](int i, float wi, float cu) {
+      const float fe = wi * fmaf(rho * cu, fmaf(4.5f, cu, 3.0f), A);
+      d[i] = fmaf(om, fe - d[i], d[i]);
+    };
+    d[0] = fmaf(om, (4.0f / 9.0f) * A - d[0], d[0]);
+    relax(1, W1, ux);
+    relax(2, W1, uy);
+    relax(3, W1, -ux);
+    relax(4, W1, -uy);
+    const float pp = ux + uy, pm = ux - uy;
+    relax(5, W2, pp);
+    relax(6, W2, -pm);
+    relax(7, W2, -pp);
+    relax(8, W2, pm);
+    if (Fx != 0.f || Fy != 0.f) {
+      const float pre = cp.pre_f[l];
+      const float uF = ux * Fx + uy * Fy;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      float cu = CX[i] * ux + CY[i] * uy;
-      float cF = CX[i] * Fx + CY[i] * Fy;
-      float fe = feqdev(i, drho, rho, ux, uy, usq);
-      d[i] = d[i] + om * (fe - d[i]) + wgt<float>(i) * pre * (3.f * cF + 9.f * cu * cF - 3.f * uF);
+      for (int i = 1; i < 9; ++i) {
+        const float cu = CX[i] * ux + CY[i] * uy;
+        const float cF = CX[i] * Fx + CY[i] * Fy;
+        d[i] += wgt<float>(i) * pre * (3.f * cF + 9.f * cu * cF - 3.f * uF);
+      }
+      d[0] += wgt<float>(0) * pre * (-3.f * uF);
     }
   }
 };
+
+// IBM force density at cell (x, y) of the finest block at (ox, oy) for the
+// collision of the substep the last forcing loop ran for (zero outside its
+// window).  The window test is per block, on wave-uniform values.
+template <typename C>
+__device__ __forceinline__ void add_ibm_force(const CaseDev &cp, int ox, int oy, int x, int y, C &Fx, C &Fy) {
+  const int b = __builtin_amdgcn_readfirstlane((int)((*cp.kcount - 1) & 1));
+  const IbmWindow w = cp.win[b];
+  const int x0 = __builtin_amdgcn_readfirstlane(w.x0), y0 = __builtin_amdgcn_readfirstlane(w.y0);
+  const int ww = __builtin_amdgcn_readfirstlane(w.w), wh = __builtin_amdgcn_readfirstlane(w.h);
+  if (ox + kB <= x0 || ox >= x0 + ww || oy + kB <= y0 || oy >= y0 + wh) return;
+  const int wx = ox + x - x0, wy = oy + y - y0;
+  if (wx >= 0 && wx < ww && wy >= 0 && wy < wh) {
+    const double *F = cp.wF + (size_t)b * 2 * cp.win_cap;
+    const size_t wi = (size_t)wy * ww + wx;
+    Fx = Fx + (C)F[wi];
+    Fy = Fy + (C)F[(size_t)cp.win_cap + wi];
+  }
+}
 
 // Equilibrium in the storage frame for the interface / boundary operators.
 template <int ST>
@@ -462,15 +498,7 @@ __device__ __forceinline__ void level_cell(const LevelArgs &a, const Blk &k, int
     Fx = cp.fx_f[l];
     Fy = cp.fy_f[l];
   }
-  if (k.flags & BF_IBM) {
-    const IbmWindow w = *cp.win;
-    int wx = k.ox + x - w.x0, wy = k.oy + y - w.y0;
-    if (wx >= 0 && wx < w.w && wy >= 0 && wy < w.h) {
-      size_t wi = (size_t)wy * w.w + wx;
-      Fx = Fx + (C)cp.wF[wi];
-      Fy = Fy + (C)cp.wF[(size_t)cp.win_cap + wi];
-    }
-  }
+  if (k.flags & BF_IBM) add_ibm_force<C>(cp, k.ox, k.oy, x, y, Fx, Fy);
 
   C rho, ux, uy;
   Collide<ST>::run(cp, l, f, Fx, Fy, rho, ux, uy);
@@ -515,6 +543,33 @@ __device__ __forceinline__ int remap_block(int bid, int nblk, int enable) {
   int q = nblk >> 3, r = nblk & 7;
   int start = xcd * q + (xcd < r ? xcd : r);
   return start + k;
+}
+
+// Work item of tile-launch workgroup `bid` (roles: 0 interior run, 1 edge or
+// interface block, 2 band-cell group, -1 none).  Workgroups go to the 8
+// XCDs round-robin; XCD x takes the x-th eighth of each role (contiguous in
+// Morton order, so its halo reads stay in its own L2), so the slower roles
+// are spread over all XCDs instead of trailing on the last ones.  Without
+// the remap the grid is plain [runs | blocks | band groups].
+__device__ __forceinline__ int tile_role(int bid, int n_run, int n_blk, int n_bnd, int enable, int &idx) {
+  if (!enable) {
+    if (bid < n_run) { idx = bid; return 0; }
+    bid -= n_run;
+    if (bid < n_blk) { idx = bid; return 1; }
+    bid -= n_blk;
+    idx = bid;
+    return bid < n_bnd ? 2 : -1;
+  }
+  const int x = bid & 7, k = bid >> 3;
+  const int r0 = n_run * x / 8, r1 = n_run * (x + 1) / 8;
+  if (k < r1 - r0) { idx = r0 + k; return 0; }
+  const int k1 = k - (r1 - r0);
+  const int s0 = n_blk * x / 8, s1 = n_blk * (x + 1) / 8;
+  if (k1 < s1 - s0) { idx = s0 + k1; return 1; }
+  const int k2 = k1 - (s1 - s0);
+  const int b0 = n_bnd * x / 8, b1 = n_bnd * (x + 1) / 8;
+  if (k2 < b1 - b0) { idx = b0 + k2; return 2; }
+  return -1;
 }
 
 // Halo-band cell of a halo block: streamed in the first fine substep, never
@@ -594,60 +649,147 @@ __global__ __launch_bounds__(256 / CPT) void level_kernel(LevelArgs a) {
 // that also holds the one-cell halo each direction needs (188 values from
 // the 8 neighbours); every lane then gathers its 9 incoming populations at
 // fixed offsets, collides and stores.
+// LDS image of one block: the 9 planes dense (256 cells each, the same
+// byte order as in HBM, so a 16-byte-per-lane direct copy fills them), then
+// 188 halo populations that stream in from the 8 neighbours.
 template <int ST>
 struct Tile {
   using T = typename Store<ST>::T;
-  static constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte vector
-  static constexpr int OFF = V;                  // column of x = 0 in a tile row
-  static constexpr int RS = 16 + 2 * V;          // row stride
-  static constexpr int PS = 18 * RS;             // plane stride
+  static constexpr int DENSE = kQ * kCells;                   // elements
+  static constexpr int HALO = 192;                            // 188 used
+  static constexpr int SIZE = DENSE + HALO;
+  static constexpr int NVEC = DENSE * (int)sizeof(T) / 16;    // 16-byte vectors
+  static constexpr int NOPS = (NVEC + 255) / 256;             // copies per lane
 };
 
-template <int ST, bool SLOW>
-__device__ __forceinline__ void tile_block(const LevelArgs &a, int b, typename Store<ST>::T *tile) {
-#pragma clang fp contract(off)
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Halo slot t (0..187): the plane it feeds and the local cell (x, y in
+// -1..16) just outside the block that the plane streams in from.  Slots
+// 0..63 are the four axis directions (16 each), 64..187 the four diagonals
+// (31 each: a column of 16, then a row of 15).
+__device__ __forceinline__ void halo_slot(int t, int &plane, int &hx, int &hy) {
+  if (t < 64) {
+    int s = t & 15;
+    plane = 1 + (t >> 4);
+    hx = plane == 1 ? -1 : (plane == 3 ? 16 : s);
+    hy = plane == 2 ? -1 : (plane == 4 ? 16 : s);
+  } else {
+    int d = (t - 64) / 31, s = (t - 64) % 31;
+    plane = 5 + d;
+    bool col = s < 16;
+    if (plane == 5) { hx = col ? -1 : s - 16; hy = col ? s - 1 : -1; }
+    else if (plane == 6) { hx = col ? 16 : s - 15; hy = col ? s - 1 : -1; }
+    else if (plane == 7) { hx = col ? 16 : s - 15; hy = col ? s + 1 : 16; }
+    else { hx = col ? -1 : s - 16; hy = col ? s + 1 : 16; }
+  }
+}
+
+// LDS element holding the population of direction i that streams into
+// local cell (x, y): the dense plane when its source cell is inside the
+// block, else the halo slot of that source (inverse of halo_slot).
+__device__ __forceinline__ int tile_index(int i, int x, int y) {
+  const int sx = x - CX[i], sy = y - CY[i];
+  if ((unsigned)sx < 16u && (unsigned)sy < 16u) return i * kCells + sy * 16 + sx;
+  int slot;
+  switch (i) {
+    case 1: slot = y; break;
+    case 2: slot = 16 + x; break;
+    case 3: slot = 32 + y; break;
+    case 4: slot = 48 + x; break;
+    case 5: slot = 64 + (x == 0 ? y : 15 + x); break;
+    case 6: slot = 95 + (x == 15 ? y : 16 + x); break;
+    case 7: slot = 126 + (x == 15 ? y : 16 + x); break;
+    default: slot = 157 + (x == 0 ? y : 15 + x); break;
+  }
+  return kQ * kCells + slot;
+}
+
+// Issue the loads of block k into LDS image `buf`: the dense planes by
+// direct global->LDS copies (16 bytes per lane, no registers), and this
+// lane's halo population into h (NaN where the neighbour is missing).
+template <int ST>
+__device__ __forceinline__ void fetch_tile(const LevelArgs &a, const Blk &k, typename Store<ST>::T *buf,
+                                           typename Store<ST>::T &h) {
   using S = Store<ST>;
   using T = typename S::T;
   using C = typename S::C;
   using TL = Tile<ST>;
-  const Blk k = load_blk(a.meta, b);
-  const CaseDev &cp = a.cases[k.cid];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const T *src = static_cast<const T *>(a.src);
-
-  // interior of the 9 planes
-  constexpr int VPP = 256 / TL::V;      // vectors per plane
-  for (int v = tid; v < 9 * VPP; v += 256) {
-    int plane = v / VPP, e = (v % VPP) * TL::V;
-    int y = e >> 4, x = e & 15;
-    uint4 val = *reinterpret_cast<const uint4 *>(src + ((size_t)b * kQ + plane) * kCells + e);
-    *reinterpret_cast<uint4 *>(&tile[plane * TL::PS + (y + 1) * TL::RS + TL::OFF + x]) = val;
+  const char *g = reinterpret_cast<const char *>(src + (size_t)k.self * kQ * kCells);
+#pragma unroll
+  for (int r = 0; r < TL::NOPS; ++r) {
+    const int v0 = r * 256 + wv * 64;  // wave-uniform first vector
+    if (v0 < TL::NVEC && v0 + lane < TL::NVEC)
+      __builtin_amdgcn_global_load_lds(g + (size_t)(v0 + lane) * 16, (lds_void *)(reinterpret_cast<char *>(buf) + v0 * 16),
+                                       16, 0, 0);
   }
-  // halo: 16 cells for each axis direction, 31 for each diagonal
   if (tid < 188) {
     int plane, hx, hy;
-    if (tid < 64) {
-      int s = tid & 15;
-      plane = 1 + (tid >> 4);
-      hx = plane == 1 ? -1 : (plane == 3 ? 16 : s);
-      hy = plane == 2 ? -1 : (plane == 4 ? 16 : s);
-    } else {
-      int d = (tid - 64) / 31, s = (tid - 64) % 31;
-      plane = 5 + d;
-      bool col = s < 16;
-      if (plane == 5) { hx = col ? -1 : s - 16; hy = col ? s - 1 : -1; }
-      else if (plane == 6) { hx = col ? 16 : s - 15; hy = col ? s - 1 : -1; }
-      else if (plane == 7) { hx = col ? 16 : s - 15; hy = col ? s + 1 : 16; }
-      else { hx = col ? -1 : s - 16; hy = col ? s + 1 : 16; }
-    }
+    halo_slot(tid, plane, hx, hy);
     int nb = pick_nbr(k, hx, hy);
-    T v = nb < 0 ? S::st(C(__builtin_nan(""))) : src[((size_t)nb * kQ + plane) * kCells + (hy & 15) * 16 + (hx & 15)];
-    tile[plane * TL::PS + (hy + 1) * TL::RS + TL::OFF + hx] = v;
+    h = nb < 0 ? S::st(C(__builtin_nan(""))) : src[((size_t)nb * kQ + plane) * kCells + (hy & 15) * 16 + (hx & 15)];
   }
+}
+
+// Make buf complete for every lane: this lane's halo value, then wait for
+// this wave's direct copies before the barrier (other waves read them).
+template <int ST>
+__device__ __forceinline__ void commit_tile(typename Store<ST>::T *buf, typename Store<ST>::T h) {
+  if (threadIdx.x < 188) buf[Tile<ST>::DENSE + threadIdx.x] = h;
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
   __syncthreads();
+}
+
+// Block metadata read as one 32-bit word per lane (lanes 0..17), so it is
+// waited for together with the block data rather than on the scalar path.
+__device__ __forceinline__ int meta_word(const BlockMeta *meta, int b, int lane) {
+  return reinterpret_cast<const int32_t *>(meta + b)[min(lane, 17)];
+}
+
+__device__ __forceinline__ Blk blk_from_lanes(int mv, int self) {
+  Blk k;
+  k.self = self;
+  k.ox = __builtin_amdgcn_readlane(mv, 0);
+  k.oy = __builtin_amdgcn_readlane(mv, 1);
+  k.nE = __builtin_amdgcn_readlane(mv, 2);
+  k.nN = __builtin_amdgcn_readlane(mv, 3);
+  k.nW = __builtin_amdgcn_readlane(mv, 4);
+  k.nS = __builtin_amdgcn_readlane(mv, 5);
+  k.nNE = __builtin_amdgcn_readlane(mv, 6);
+  k.nNW = __builtin_amdgcn_readlane(mv, 7);
+  k.nSW = __builtin_amdgcn_readlane(mv, 8);
+  k.nSE = __builtin_amdgcn_readlane(mv, 9);
+  k.c0 = __builtin_amdgcn_readlane(mv, 10);
+  k.c1 = __builtin_amdgcn_readlane(mv, 11);
+  k.c2 = __builtin_amdgcn_readlane(mv, 12);
+  k.c3 = __builtin_amdgcn_readlane(mv, 13);
+  k.cid = __builtin_amdgcn_readlane(mv, 14);
+  k.level = __builtin_amdgcn_readlane(mv, 15);
+  k.flags = __builtin_amdgcn_readlane(mv, 16);
+  k.code = __builtin_amdgcn_readlane(mv, 17);
+  return k;
+}
+
+// Stream (from the staged tile) + collide of block k; interface, edge and
+// explosion work only when SLOW.
+template <int ST, bool SLOW>
+__device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev *__restrict__ cases, const Blk &k,
+                                              const typename Store<ST>::T *tile) {
+#pragma clang fp contract(off)
+  using S = Store<ST>;
+  using T = typename S::T;
+  using C = typename S::C;
+  // block fields are wave-uniform: keep the case parameters on the scalar
+  // path (a vector load here would wait for the next block's copies)
+  const CaseDev &cp = cases[__builtin_amdgcn_readfirstlane(k.cid)];
+  const int tid = threadIdx.x;
+  const int b = __builtin_amdgcn_readfirstlane(k.self);
 
   const int x = tid & 15, y = tid >> 4;
-  const int l = k.level;
+  const int l = __builtin_amdgcn_readfirstlane(k.level);
   uint16_t code = 0;
   if (SLOW) {
     code = (k.flags & BF_CODES) ? a.codes[(size_t)k.code * kCells + tid] : (uint16_t)0;
@@ -656,7 +798,7 @@ __device__ __forceinline__ void tile_block(const LevelArgs &a, int b, typename S
   C f[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i)
-    f[i] = S::ld(tile[i * TL::PS + (y - CY[i] + 1) * TL::RS + TL::OFF + x - CX[i]]);
+    f[i] = S::ld(tile[tile_index(i, x, y)]);
   if (SLOW) {
     const int gx = k.ox + x, gy = k.oy + y;
     const bool edge = (k.flags & BF_EDGE) != 0;
@@ -694,15 +836,7 @@ __device__ __forceinline__ void tile_block(const LevelArgs &a, int b, typename S
     Fx = cp.fx_f[l];
     Fy = cp.fy_f[l];
   }
-  if (k.flags & BF_IBM) {
-    const IbmWindow win = *cp.win;
-    int wx = k.ox + x - win.x0, wy = k.oy + y - win.y0;
-    if (wx >= 0 && wx < win.w && wy >= 0 && wy < win.h) {
-      size_t wi = (size_t)wy * win.w + wx;
-      Fx = Fx + (C)cp.wF[wi];
-      Fy = Fy + (C)cp.wF[(size_t)cp.win_cap + wi];
-    }
-  }
+  if (k.flags & BF_IBM) add_ibm_force<C>(cp, k.ox, k.oy, x, y, Fx, Fy);
   C rho, ux, uy;
   Collide<ST>::run(cp, l, f, Fx, Fy, rho, ux, uy);
   if (!(rho == rho) || rho > C(1e30) || rho < C(-1e30)) atomicOr(a.err, ERR_NONFINITE);
@@ -736,25 +870,92 @@ __device__ __forceinline__ void tile_block(const LevelArgs &a, int b, typename S
   }
 }
 
-// One launch per level substep: the first n_fast list entries are interior
-// blocks, the rest of the list are blocks next to a finer level or a domain
-// edge, and workgroups past the list gather packed halo-band cells.
+// One pipelined step over a run of interior blocks: make `cur` (block j)
+// complete, start block j+1's copies into `nxt` and its metadata for j+2,
+// then stream + collide block j from `cur`.
 template <int ST>
-__global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a) {
+__device__ __forceinline__ void pipe_step(const LevelArgs &a, const CaseDev *__restrict__ cases, Blk &k, int &mvn,
+                                          int lv, int j, int cnt,
+                                          typename Store<ST>::T *cur, typename Store<ST>::T *nxt,
+                                          typename Store<ST>::T &h) {
+  commit_tile<ST>(cur, h);
+  const Blk kc = k;
+  if (j + 1 < cnt) {
+    k = blk_from_lanes(mvn, __builtin_amdgcn_readlane(lv, j + 1));
+    fetch_tile<ST>(a, k, nxt, h);
+    if (j + 2 < cnt) mvn = meta_word(a.meta, __builtin_amdgcn_readlane(lv, j + 2), threadIdx.x & 63);
+  }
+  compute_block<ST, false>(a, cases, kc, cur);
+}
+
+// One launch per level substep.  With NBUF = 2, workgroups [0, n_fast_wg)
+// each take a run of up to `kpw` consecutive interior blocks (no cell
+// codes, no domain edge, all eight neighbours) and copy block j+1 into the
+// second LDS image while block j is computed from the first.  The next
+// n_blocks - n_fast workgroups take one block next to a finer level or a
+// domain edge each; the rest gather packed halo-band cells.
+template <int ST, int NBUF>
+__global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a, const CaseDev *__restrict__ cases) {
   using T = typename Store<ST>::T;
-  __shared__ __attribute__((aligned(16))) T tile[9 * Tile<ST>::PS];
-  const int w = remap_block(blockIdx.x, gridDim.x, a.xcd_remap);
-  if (w < a.n_fast) {
-    tile_block<ST, false>(a, a.list[w], tile);
-  } else if (w < a.n_blocks) {
-    tile_block<ST, true>(a, a.list[w], tile);
-  } else {
-    int idx = (w - a.n_blocks) * 256 + threadIdx.x;
+  using TL = Tile<ST>;
+  __shared__ __attribute__((aligned(16))) T bufA[TL::SIZE];
+  __shared__ __attribute__((aligned(16))) T bufB[NBUF == 2 ? TL::SIZE : 8];
+  const int kpw = NBUF == 2 ? a.kpw : 1;
+  const int n_fast_wg = (a.n_fast + kpw - 1) / kpw;
+  const int n_band_wg = (a.n_band + 255) / 256;
+  int w;
+  const int role = tile_role(blockIdx.x, n_fast_wg, a.n_blocks - a.n_fast, n_band_wg, a.xcd_remap, w);
+  const int lane = threadIdx.x & 63;
+  T h;
+  if (role == 0) {
+    const int first = w * kpw;
+    const int cnt = min(kpw, a.n_fast - first);
+    if (NBUF == 1 || cnt == 1) {
+      const Blk k = load_blk(a.meta, a.list[first]);
+      fetch_tile<ST>(a, k, bufA, h);
+      commit_tile<ST>(bufA, h);
+      compute_block<ST, false>(a, cases, k, bufA);
+      return;
+    }
+    // the run's block ids (one per lane) and the first two blocks' metadata
+    const int lv = a.list[first + min(lane, cnt - 1)];
+    const int b0 = __builtin_amdgcn_readlane(lv, 0);
+    Blk k = blk_from_lanes(meta_word(a.meta, b0, lane), b0);
+    fetch_tile<ST>(a, k, bufA, h);
+    int mvn = meta_word(a.meta, __builtin_amdgcn_readlane(lv, 1), lane);
+    Blk kk = k;
+    for (int j = 0; j < cnt; j += 2) {
+      pipe_step<ST>(a, cases, kk, mvn, lv, j, cnt, bufA, bufB, h);
+      if (j + 1 < cnt) pipe_step<ST>(a, cases, kk, mvn, lv, j + 1, cnt, bufB, bufA, h);
+    }
+    return;
+  }
+  if (role == 1) {
+    const Blk k = load_blk(a.meta, a.list[a.n_fast + w]);
+    fetch_tile<ST>(a, k, bufA, h);
+    commit_tile<ST>(bufA, h);
+    compute_block<ST, true>(a, cases, k, bufA);
+  } else if (role == 2) {
+    int idx = w * 256 + threadIdx.x;
     if (idx < a.n_band) band_cell<ST>(a, a.band[idx]);
   }
 }
 
-// ---- IBM: multi-direct forcing, one workgroup per body --------------------
+// ---- IBM: multi-direct forcing (Sec. 2.2), one workgroup per body ----------
+// Two kernels per finest substep k of every body:
+//  * ibm_prep_kernel builds the plan of substep k one substep ahead.  It
+//    needs only the prescribed kinematics and the block map: marker
+//    positions, desired velocities and Peskin weights (Eqs. (13), (14)), the
+//    IBM window, the compact list of stencil cells with the blocks their
+//    streaming sources lie in, and for every stencil cell the markers whose
+//    stencil covers it, in ascending marker index (CSR).
+//  * mdf_kernel runs the forcing loop of substep k on that plan: cell
+//    moments, N_F iterations of interpolation (Eq. (12)), boundary force
+//    (Eq. (11)) and spreading (Eq. (15)), with the moments and the marker
+//    tables in LDS and each stencil cell's force in its owner's registers,
+//    then the force density for the collision and the body force (Eq. (16)).
+// Plans are double-buffered by the parity of k, and so are the window and
+// its force density that the collision of substep k reads.
 constexpr int MDF_THREADS = kMaxMarkers;
 
 __device__ __forceinline__ double peskin(double r) {
@@ -815,42 +1016,6 @@ __device__ __forceinline__ int finest_block(const CaseDev &cp, int gx, int gy) {
   return cp.bmap[(size_t)ry * cp.bm_w + rx];
 }
 
-// A stencil cell and its 8 streaming sources must be owned finest cells; the
-// 3x3 neighbourhood spans at most 2x2 blocks, all found at its corners.
-__device__ __forceinline__ bool stencil_ok(const CaseDev &cp, int gx, int gy) {
-  return finest_block(cp, gx - 1, gy - 1) >= 0 && finest_block(cp, gx + 1, gy - 1) >= 0 &&
-         finest_block(cp, gx - 1, gy + 1) >= 0 && finest_block(cp, gx + 1, gy + 1) >= 0;
-}
-
-// rho and the uncorrected velocity of finest cell (gx, gy) from its
-// post-stream populations (the initial state is read in place).
-template <int ST>
-__device__ __forceinline__ void cell_moments(const MdfArgs &a, const CaseDev &cp, int gx, int gy, double &rho,
-                                             double &ux, double &uy) {
-#pragma clang fp contract(off)
-  double f[9];
-  if (a.first) {
-    int b = finest_block(cp, gx, gy);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = (double)ldv<ST>(a.src, b, i, (gy & 15) * 16 + (gx & 15));
-  } else {
-    int nb[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) nb[i] = finest_block(cp, gx - CX[i], gy - CY[i]);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      int sx = gx - CX[i], sy = gy - CY[i];
-      f[i] = (double)ldv<ST>(a.src, nb[i], i, (sy & 15) * 16 + (sx & 15));
-    }
-  }
-  double jx, jy;
-  moments64(f, rho, jx, jy);
-  if constexpr (Store<ST>::kShift) rho = cp.rho0 + rho;
-  int l = cp.n_levels - 1;
-  ux = (jx + 0.5 * cp.fx[l]) / rho;
-  uy = (jy + 0.5 * cp.fy[l]) / rho;
-}
-
 // Ascending sort of up to N marker indices held in registers (bitonic
 // network; every index is a compile-time constant, so nothing spills).
 template <int N>
@@ -873,77 +1038,85 @@ __device__ __forceinline__ void sort_net(int (&v)[N]) {
   }
 }
 
-template <int N>
-__device__ __forceinline__ void sorted_copy(const int32_t *L, int cnt, int32_t *out) {
-  int v[N];
-#pragma unroll
-  for (int r = 0; r < N; ++r) v[r] = r < cnt ? L[r] : 0x7fffffff;
-  sort_net<N>(v);
-#pragma unroll
-  for (int r = 0; r < N; ++r)
-    if (r < cnt) out[r] = v[r];
+// Plan buffer b of a case: element offsets of its arrays.
+struct PlanView {
+  int32_t *i0, *j0;      // first tap of each marker
+  double *w;             // [8][nm]: wx[0..3], wy[0..3]
+  double *ud;            // [2][nm]: desired velocity
+  uint16_t *tap;         // [16][nm]: stencil cell of each tap (y outer, x inner)
+  int32_t *cell;         // [cell_cap][8]: window index, 4 source blocks, csr start, count, 0
+  uint16_t *list;        // [16 nm]: contributors of the stencil cells, CSR
+  int32_t *hdr;          // [4]: stamp (low 32 bits of k), stencil cells, status, 0
+};
+
+__device__ __forceinline__ PlanView plan_view(const CaseDev &cp, int b) {
+  const size_t nm = (size_t)cp.nm_cap;
+  PlanView v;
+  v.i0 = cp.p_ij + (size_t)b * 2 * nm;
+  v.j0 = v.i0 + nm;
+  v.w = cp.p_w + (size_t)b * 8 * nm;
+  v.ud = cp.p_ud + (size_t)b * 2 * nm;
+  v.tap = cp.p_tap + (size_t)b * 16 * nm;
+  v.cell = cp.p_cell + (size_t)b * 8 * cp.cell_cap;
+  v.list = cp.p_list + (size_t)b * 16 * nm;
+  v.hdr = cp.phdr + 4 * b;
+  return v;
 }
 
-__device__ __forceinline__ void mdf_fail(const CaseDev &cp, int *err, int code, int64_t k) {
-  atomicOr(err, code);
-  IbmWindow e = {0, 0, 0, 0};
-  *cp.win = e;
-  *cp.kcount = k + 1;
-}
-
-template <int ST>
-__global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
+// Plan builder.  LDS: window counters and compact indices (when the window
+// fits), the stencil cells' window indices and CSR starts, the contributor
+// lists while they are filled.
+__global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
 #pragma clang fp contract(off)
   const int ci = a.body_cases[blockIdx.x];
   const CaseDev &cp = a.cases[ci];
   const int n = cp.n_markers;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int NM = a.max_markers;
-  // LDS marker tables: Peskin weights of the 4 x and 4 y taps, current force,
-  // arc length, first tap, and the compact stencil-cell index of each tap.
-  extern __shared__ double lds[];
-  double *s_wx = lds;               // [4][NM]
-  double *s_wy = s_wx + 4 * NM;     // [4][NM]
-  double *s_dFx = s_wy + 4 * NM;    // [NM]
-  double *s_dFy = s_dFx + NM;
-  double *s_ds = s_dFy + NM;
-  int *s_i0 = (int *)(s_ds + NM);   // [NM]
-  int *s_j0 = s_i0 + NM;
-  int *s_tap = s_j0 + NM;           // [16][NM]
-  int *s_cnt = s_tap + 16 * NM;     // [lds_window] window counters
+  const int nm = cp.nm_cap, cap = cp.cell_cap;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  extern __shared__ int lds_i[];
+  const int NMa = a.max_markers, CCa = a.cell_cap;  // LDS table sizes
+  int *s_cells = lds_i;                  // [CCa] window index of stencil cell q
+  int *s_start = s_cells + CCa;          // [CCa] CSR start of stencil cell q
+  uint16_t *s_list = reinterpret_cast<uint16_t *>(s_start + CCa);  // [16 NMa]
+  int *s_cnt = reinterpret_cast<int *>(s_list + 16 * NMa);          // [lds_window]
+  int *s_idx = s_cnt + a.lds_window;                                     // [lds_window]
   __shared__ int s_box[4];
-  __shared__ int s_bad;
+  __shared__ int s_ns, s_bad;
+  __shared__ int s_wsum[MDF_THREADS / 64];
   __shared__ Pose s_pose[2];
-  const int64_t k = *cp.kcount;
+  const int64_t k = a.from_kcount ? *cp.kcount : *cp.pk;
+  const int b = (int)(k & 1);
+  const PlanView P = plan_view(cp, b);
 
   // 1. kinematics: r_j(t_k), desired velocity (r_j(t_k+1) - r_j(t_k)) / dt,
-  //    and the Peskin weights of the marker's 4x4 stencil (Eqs. (13), (14))
+  //    and the Peskin weights of the marker's 4x4 stencil
   if (tid == 0) {
     s_box[0] = 1 << 30; s_box[1] = 1 << 30; s_box[2] = -(1 << 30); s_box[3] = -(1 << 30);
+    s_ns = 0;
     s_bad = 0;
     s_pose[0] = body_pose(cp, (double)k);
   } else if (tid == 64) {
     s_pose[1] = body_pose(cp, (double)(k + 1));
   }
   __syncthreads();
-  double udx = 0.0, udy = 0.0, ftx = 0.0, fty = 0.0;
   const bool own = tid < n;
+  int i0 = 0, j0 = 0;
   int bx0 = 1 << 30, by0 = 1 << 30, bx1 = -(1 << 30), by1 = -(1 << 30);
   if (own) {
     double X, Y, X1, Y1;
     marker_position(cp, s_pose[0], tid, X, Y);
     marker_position(cp, s_pose[1], tid, X1, Y1);
-    udx = X1 - X;
-    udy = Y1 - Y;
-    int i0 = tap0(X), j0 = tap0(Y);
-    s_i0[tid] = i0;
-    s_j0[tid] = j0;
+    P.ud[tid] = X1 - X;
+    P.ud[nm + tid] = Y1 - Y;
+    i0 = tap0(X);
+    j0 = tap0(Y);
+    P.i0[tid] = i0;
+    P.j0[tid] = j0;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      s_wx[t * NM + tid] = peskin(i0 + t + 0.5 - X);
-      s_wy[t * NM + tid] = peskin(j0 + t + 0.5 - Y);
+      P.w[(size_t)t * nm + tid] = peskin(i0 + t + 0.5 - X);
+      P.w[(size_t)(4 + t) * nm + tid] = peskin(j0 + t + 0.5 - Y);
     }
-    s_ds[tid] = cp.ds[tid];
     bx0 = i0; by0 = j0; bx1 = i0 + 4; by1 = j0 + 4;
   }
 #pragma unroll
@@ -964,42 +1137,45 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
   const int ww = s_box[2] - wx0, wh = s_box[3] - wy0;
   const int ncell = ww * wh;
   if (ncell > cp.win_cap || ww <= 0 || wh <= 0) {
-    if (tid == 0) mdf_fail(cp, a.err, ERR_WINDOW, k);
+    if (tid == 0) {
+      IbmWindow e = {0, 0, 0, 0};
+      cp.win[b] = e;
+      P.hdr[0] = (int)k; P.hdr[1] = 0; P.hdr[2] = ERR_WINDOW;
+      *cp.pk = k + 1;
+    }
     return;
   }
   if (tid == 0) {
     IbmWindow w = {wx0, wy0, ww, wh};
-    *cp.win = w;
-    *cp.sCount = 0;
+    cp.win[b] = w;
   }
-  // 2. clear the window (counts and force; the level kernel reads the force
-  //    over the whole window).  Counters live in LDS when the window fits.
-  const bool lds_cnt = ncell <= a.lds_window;
-  int *wcnt = lds_cnt ? s_cnt : cp.wCnt;
-  for (int c = tid; c < ncell; c += MDF_THREADS) {
-    wcnt[c] = 0;
-    cp.wF[c] = 0.0;
-    cp.wF[(size_t)cp.win_cap + c] = 0.0;
+  // 2. clear the window's force density (the collision reads all of it) and
+  //    the per-cell counters
+  const bool in_lds = ncell <= a.lds_window;
+  int *cnt = in_lds ? s_cnt : cp.wCnt;
+  int *idx = in_lds ? s_idx : cp.wIdx;
+  {
+    double *F = cp.wF + (size_t)b * 2 * cp.win_cap;
+    for (int c = tid; c < ncell; c += MDF_THREADS) {
+      cnt[c] = 0;
+      F[c] = 0.0;
+      F[(size_t)cp.win_cap + c] = 0.0;
+    }
   }
   __syncthreads();
-  // 3. each marker lane registers its 16 taps at once: contributor lists of
-  //    the cells, and a compact list of the distinct stencil cells (the first
-  //    toucher of a cell appends it; a wavefront prefix sum sizes the append)
+  // 3. every marker lane registers its 16 taps: its slot in each cell's
+  //    contributor list, and the first toucher of a cell appends the cell
+  //    to the compact list (a wavefront prefix sum sizes the append)
+  int cidx[16], pos[16];
   {
-    int cidx[16], pos[16];
     int nf = 0;
     if (own) {
-      const int i0 = s_i0[tid], j0 = s_j0[tid];
 #pragma unroll
       for (int t = 0; t < 16; ++t) cidx[t] = (j0 + (t >> 2) - wy0) * ww + (i0 + (t & 3) - wx0);
 #pragma unroll
-      for (int t = 0; t < 16; ++t) pos[t] = atomicAdd(&wcnt[cidx[t]], 1);
+      for (int t = 0; t < 16; ++t) pos[t] = atomicAdd(&cnt[cidx[t]], 1);
 #pragma unroll
-      for (int t = 0; t < 16; ++t) {
-        if (pos[t] < kMaxContrib) cp.wList[(size_t)cidx[t] * kMaxContrib + pos[t]] = tid;
-        else s_bad = 2;
-        nf += pos[t] == 0;
-      }
+      for (int t = 0; t < 16; ++t) nf += pos[t] == 0;
     }
     int incl = nf;
 #pragma unroll
@@ -1009,138 +1185,290 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     }
     const int total = __shfl(incl, 63, 64);
     int base = 0;
-    if (lane == 63 && total > 0) base = atomicAdd(cp.sCount, total);
+    if (lane == 63 && total > 0) base = atomicAdd(&s_ns, total);
     base = __shfl(base, 63, 64);
     if (own) {
       int q = base + incl - nf;
 #pragma unroll
       for (int t = 0; t < 16; ++t)
         if (pos[t] == 0) {
-          cp.sCells[q] = cidx[t];
-          cp.wIdx[cidx[t]] = q;
+          if (q < cap) s_cells[q] = cidx[t];
+          idx[cidx[t]] = q;
           ++q;
         }
     }
   }
   __syncthreads();
-  const int ns = atomicAdd(cp.sCount, 0);
-  // 4. taps -> compact cell index (LDS); per stencil cell: ownership check,
-  //    marker list in index order (spreading sums in index order), rho and
-  //    the uncorrected velocity
-  if (own) {
-    const int i0 = s_i0[tid], j0 = s_j0[tid];
-    int qi[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) qi[t] = cp.wIdx[(j0 + (t >> 2) - wy0) * ww + (i0 + (t & 3) - wx0)];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) s_tap[t * NM + tid] = qi[t];
-  }
-  for (int q = tid; q < ns; q += MDF_THREADS) {
-    const int c = cp.sCells[q];
-    const int gx = wx0 + c % ww, gy = wy0 + c / ww;
-    const int cnt = min(wcnt[c], kMaxContrib);
-    if (!stencil_ok(cp, gx, gy)) {
-      s_bad = 1;
-      continue;
+  const int ns = s_ns;
+  if (ns > cap) {
+    if (tid == 0) {
+      P.hdr[0] = (int)k; P.hdr[1] = 0; P.hdr[2] = ERR_CONTRIB;
+      *cp.pk = k + 1;
     }
-    const int32_t *L = cp.wList + (size_t)c * kMaxContrib;
-    int32_t *O = cp.sList + (size_t)q * kMaxContrib;
-    if (cnt <= 16) {
-      sorted_copy<16>(L, cnt, O);
-    } else {  // rare: more than 16 markers over one cell
-      for (int r = 0; r < cnt; ++r) {
-        int v = L[r], w = r - 1;
-        while (w >= 0 && O[w] > v) {
-          O[w + 1] = O[w];
-          --w;
-        }
-        O[w + 1] = v;
-      }
-    }
-    double rho, ux, uy;
-    cell_moments<ST>(a, cp, gx, gy, rho, ux, uy);
-    cp.sRho[q] = rho;
-    cp.sU[q] = ux;
-    cp.sV[q] = uy;
-    cp.sFx[q] = 0.0;
-    cp.sFy[q] = 0.0;
-    int4 meta = {cnt, gx, gy, c};
-    *reinterpret_cast<int4 *>(cp.sMeta + 4 * (size_t)q) = meta;
-  }
-  __syncthreads();
-  if (s_bad) {
-    if (tid == 0) mdf_fail(cp, a.err, s_bad == 2 ? ERR_CONTRIB : ERR_MARKER, k);
     return;
   }
-  // 5. N_F iterations: interpolate (Eq. 12), boundary force (Eq. 11),
+  // 4. CSR starts: exclusive prefix sum of the contributor counts over the
+  //    compact cells (each lane sums a contiguous run, then a block scan)
+  {
+    const int per = (ns + MDF_THREADS - 1) / MDF_THREADS;
+    const int q0 = min(ns, tid * per), q1 = min(ns, q0 + per);
+    int sum = 0;
+    for (int q = q0; q < q1; ++q) sum += cnt[s_cells[q]];
+    int incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      int v = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += v;
+    }
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    int wbase = 0;
+    for (int w = 0; w < wave; ++w) wbase += s_wsum[w];
+    int run = wbase + incl - sum;
+    for (int q = q0; q < q1; ++q) {
+      s_start[q] = run;
+      run += cnt[s_cells[q]];
+    }
+  }
+  __syncthreads();
+  // 5. fill the contributor lists (slot order is arbitrary) and the
+  //    marker-side map from each tap to its stencil cell
+  if (own) {
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int q = idx[cidx[t]];
+      s_list[s_start[q] + pos[t]] = (uint16_t)tid;
+      P.tap[(size_t)t * nm + tid] = (uint16_t)q;
+    }
+  }
+  __syncthreads();
+  // 6. per stencil cell: contributors in ascending marker index (the
+  //    spreading sums in marker order), the blocks holding the cell and its
+  //    streaming sources (the 3x3 neighbourhood spans at most 2x2 blocks,
+  //    found at its corners; all must be owned finest blocks)
+  for (int q = tid; q < ns; q += MDF_THREADS) {
+    const int c = s_cells[q];
+    const int n_c = cnt[c], st = s_start[q];
+    const int gx = wx0 + c % ww, gy = wy0 + c / ww;
+    uint16_t *L = s_list + st;
+    uint16_t *O = P.list + st;
+    if (n_c <= 16) {
+      int v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = r < n_c ? (int)L[r] : 0x7fffffff;
+      sort_net<16>(v);
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        if (r < n_c) O[r] = (uint16_t)v[r];
+    } else {  // rare: more than 16 markers over one cell (insertion sort in LDS)
+      for (int r = 1; r < n_c; ++r) {
+        uint16_t v = L[r];
+        int w = r - 1;
+        while (w >= 0 && L[w] > v) {
+          L[w + 1] = L[w];
+          --w;
+        }
+        L[w + 1] = v;
+      }
+      for (int r = 0; r < n_c; ++r) O[r] = L[r];
+    }
+    const int sw = finest_block(cp, gx - 1, gy - 1), se = finest_block(cp, gx + 1, gy - 1);
+    const int nw = finest_block(cp, gx - 1, gy + 1), ne = finest_block(cp, gx + 1, gy + 1);
+    if (sw < 0 || se < 0 || nw < 0 || ne < 0) s_bad = 1;
+    int4 r0 = {c, sw, se, nw};
+    int4 r1 = {ne, st, n_c, 0};
+    int4 *R = reinterpret_cast<int4 *>(P.cell + (size_t)q * 8);
+    R[0] = r0;
+    R[1] = r1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    P.hdr[0] = (int)k;
+    P.hdr[1] = ns;
+    P.hdr[2] = s_bad ? ERR_MARKER : 0;
+    *cp.pk = k + 1;
+  }
+}
+
+__device__ __forceinline__ void mdf_fail(const CaseDev &cp, int *err, int code, int64_t k) {
+  atomicOr(err, code);
+  IbmWindow e = {0, 0, 0, 0};
+  cp.win[k & 1] = e;
+  *cp.kcount = k + 1;
+}
+
+constexpr int kCellsPerLane = 4;  // stencil cells owned per lane (cell_cap <= 4096)
+
+// Block of the finest cell (sx, sy) inside the 3x3 neighbourhood of (gx, gy),
+// from the four corner blocks of that neighbourhood.
+__device__ __forceinline__ int corner_block(int gx, int gy, int sx, int sy, int sw, int se, int nw, int ne) {
+  const bool west = (sx >> 4) == ((gx - 1) >> 4), south = (sy >> 4) == ((gy - 1) >> 4);
+  return west ? (south ? sw : nw) : (south ? se : ne);
+}
+
+template <int ST>
+__global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
+#pragma clang fp contract(off)
+  const int ci = a.body_cases[blockIdx.x];
+  const CaseDev &cp = a.cases[ci];
+  const int n = cp.n_markers;
+  const int nm = cp.nm_cap;
+  const int tid = threadIdx.x;
+  const int NM = a.max_markers, CC = a.cell_cap;  // LDS table strides
+  extern __shared__ double lds[];
+  double *s_wx = lds;               // [4][NM]
+  double *s_wy = s_wx + 4 * NM;     // [4][NM]
+  double *s_dFx = s_wy + 4 * NM;    // [NM]
+  double *s_dFy = s_dFx + NM;
+  double *s_ds = s_dFy + NM;
+  double *s_rho = s_ds + NM;        // [CC]
+  double *s_u = s_rho + CC;         // [CC]
+  double *s_v = s_u + CC;           // [CC]
+  double *s_fx = s_v + CC;          // [CC] accumulated force of the cell
+  double *s_fy = s_fx + CC;         // [CC]
+  int *s_i0 = reinterpret_cast<int *>(s_fy + CC);  // [NM]
+  int *s_j0 = s_i0 + NM;
+  uint16_t *s_list = reinterpret_cast<uint16_t *>(s_j0 + NM);  // [16 NM]
+  const int64_t k = *cp.kcount;
+  const int b = (int)(k & 1);
+  const PlanView P = plan_view(cp, b);
+  const int stamp = P.hdr[0], ns = P.hdr[1];
+  int status = P.hdr[2];
+  if (stamp != (int)k) status = ERR_PLAN;
+  if (!status && ns > min(CC, kCellsPerLane * MDF_THREADS)) status = ERR_CONTRIB;
+  if (status) {
+    if (tid == 0) mdf_fail(cp, a.err, status, k);
+    return;
+  }
+  // 1. load the plan: marker weights and desired velocity (registers and
+  //    LDS), the contributor lists (LDS), and per owned stencil cell its
+  //    moments from the post-stream populations (the initial state is read
+  //    in place), with rho and the uncorrected velocity to LDS
+  const bool own = tid < n;
+  double wx[4], wy[4], udx = 0.0, udy = 0.0;
+  uint32_t taps[8];  // stencil cells of the 16 taps, two per word
+  if (own) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      wx[t] = P.w[(size_t)t * nm + tid];
+      wy[t] = P.w[(size_t)(4 + t) * nm + tid];
+      s_wx[t * NM + tid] = wx[t];
+      s_wy[t * NM + tid] = wy[t];
+    }
+    udx = P.ud[tid];
+    udy = P.ud[nm + tid];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      taps[t] = (uint32_t)P.tap[(size_t)(2 * t) * nm + tid] | ((uint32_t)P.tap[(size_t)(2 * t + 1) * nm + tid] << 16);
+    s_i0[tid] = P.i0[tid];
+    s_j0[tid] = P.j0[tid];
+    s_ds[tid] = cp.ds[tid];
+  }
+  {
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(P.list);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(s_list);
+    for (int e = tid; e < 8 * n; e += MDF_THREADS) dst[e] = src[e];
+  }
+  const int l = cp.n_levels - 1;
+  const IbmWindow win = cp.win[b];
+  // per owned stencil cell: gx | gy << 16, list start | count << 16
+  int cxy[kCellsPerLane], csc[kCellsPerLane];
+#pragma unroll
+  for (int r = 0; r < kCellsPerLane; ++r) {
+    const int q = tid + r * MDF_THREADS;
+    cxy[r] = 0;
+    csc[r] = 0;
+    if (q < ns) {
+      const int4 *R = reinterpret_cast<const int4 *>(P.cell + (size_t)q * 8);
+      const int4 r0 = R[0], r1 = R[1];
+      const int c = r0.x;
+      const int gx = win.x0 + c % win.w, gy = win.y0 + c / win.w;
+      cxy[r] = gx | (gy << 16);
+      csc[r] = r1.y | (r1.z << 16);
+      double f[9];
+      if (a.first) {
+        const int ob = corner_block(gx, gy, gx, gy, r0.y, r0.z, r0.w, r1.x);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = (double)ldv<ST>(a.src, ob, i, (gy & 15) * 16 + (gx & 15));
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const int sx = gx - CX[i], sy = gy - CY[i];
+          const int nb = corner_block(gx, gy, sx, sy, r0.y, r0.z, r0.w, r1.x);
+          f[i] = (double)ldv<ST>(a.src, nb, i, (sy & 15) * 16 + (sx & 15));
+        }
+      }
+      double rho, jx, jy;
+      moments64(f, rho, jx, jy);
+      if constexpr (Store<ST>::kShift) rho = cp.rho0 + rho;
+      s_rho[q] = rho;
+      s_u[q] = (jx + 0.5 * cp.fx[l]) / rho;
+      s_v[q] = (jy + 0.5 * cp.fy[l]) / rho;
+      s_fx[q] = 0.0;
+      s_fy[q] = 0.0;
+    }
+  }
+  __syncthreads();
+  // 2. N_F iterations: interpolate (Eq. 12), boundary force (Eq. 11),
   //    spread (Eq. 15), correct velocity and accumulate force
+  double ftx = 0.0, fty = 0.0;
   for (int it = 0; it < cp.mdf_iters; ++it) {
     if (own) {
       double su = 0.0, sv = 0.0, sr = 0.0;
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {  // two rows of taps per round of loads
-        double uq[8], vq[8], rq[8];
+      for (int bb = 0; bb < 4; ++bb) {
+        const double py = wy[bb];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          int q = s_tap[(half * 8 + t) * NM + tid];
-          uq[t] = cp.sU[q];
-          vq[t] = cp.sV[q];
-          rq[t] = cp.sRho[q];
-        }
-#pragma unroll
-        for (int bh = 0; bh < 2; ++bh) {
-          const int bb = half * 2 + bh;
-          double py = s_wy[bb * NM + tid];
-#pragma unroll
-          for (int aa = 0; aa < 4; ++aa) {
-            double w = s_wx[aa * NM + tid] * py;
-            su += uq[bh * 4 + aa] * w;
-            sv += vq[bh * 4 + aa] * w;
-            sr += rq[bh * 4 + aa] * w;
-          }
+        for (int aa = 0; aa < 4; ++aa) {
+          const int t = bb * 4 + aa;
+          const int q = (taps[t >> 1] >> ((t & 1) * 16)) & 0xffff;
+          const double w = wx[aa] * py;
+          su += s_u[q] * w;
+          sv += s_v[q] * w;
+          sr += s_rho[q] * w;
         }
       }
-      double gx = 2.0 * sr * (udx - su);
-      double gy = 2.0 * sr * (udy - sv);
+      const double gx = 2.0 * sr * (udx - su);
+      const double gy = 2.0 * sr * (udy - sv);
       s_dFx[tid] = gx;
       s_dFy[tid] = gy;
       ftx += gx;
       fty += gy;
     }
     __syncthreads();
-    for (int q = tid; q < ns; q += MDF_THREADS) {
-      const int4 meta = *reinterpret_cast<const int4 *>(cp.sMeta + 4 * (size_t)q);
-      const int cnt = meta.x, gx = meta.y, gy = meta.z;
-      const int32_t *L = cp.sList + (size_t)q * kMaxContrib;
-      const double rho = cp.sRho[q], u0 = cp.sU[q], v0 = cp.sV[q], fx0 = cp.sFx[q], fy0 = cp.sFy[q];
-      double dfx = 0.0, dfy = 0.0;
-      for (int r0 = 0; r0 < cnt; r0 += 4) {
-        const int4 v4 = *reinterpret_cast<const int4 *>(L + r0);
-        const int js[4] = {v4.x, v4.y, v4.z, v4.w};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          if (r0 + r < cnt) {
-            int j = js[r];
-            double w = s_wx[(gx - s_i0[j]) * NM + j] * s_wy[(gy - s_j0[j]) * NM + j];
-            dfx += s_dFx[j] * w * s_ds[j];
-            dfy += s_dFy[j] * w * s_ds[j];
-          }
+    for (int r = 0; r < kCellsPerLane; ++r) {
+      const int q = tid + r * MDF_THREADS;
+      if (q < ns) {
+        const int gx = cxy[r] & 0xffff, gy = cxy[r] >> 16;
+        const int st = csc[r] & 0xffff, cnt = csc[r] >> 16;
+        double dfx = 0.0, dfy = 0.0;
+        for (int e = 0; e < cnt; ++e) {
+          const int j = s_list[st + e];
+          const double w = s_wx[(gx - s_i0[j]) * NM + j] * s_wy[(gy - s_j0[j]) * NM + j];
+          dfx += s_dFx[j] * w * s_ds[j];
+          dfy += s_dFy[j] * w * s_ds[j];
         }
+        s_fx[q] = s_fx[q] + dfx;
+        s_fy[q] = s_fy[q] + dfy;
+        const double r2 = 2.0 * s_rho[q];
+        s_u[q] = s_u[q] + dfx / r2;
+        s_v[q] = s_v[q] + dfy / r2;
       }
-      cp.sFx[q] = fx0 + dfx;
-      cp.sFy[q] = fy0 + dfy;
-      double r2 = 2.0 * rho;
-      cp.sU[q] = u0 + dfx / r2;
-      cp.sV[q] = v0 + dfy / r2;
     }
     __syncthreads();
   }
-  // 6. force density of the stencil cells for the collision, total marker
+  // 3. force density of the stencil cells for the collision, total marker
   //    forces, and the body force of Eq. (16) summed in marker order
-  for (int q = tid; q < ns; q += MDF_THREADS) {
-    const int c = cp.sMeta[4 * (size_t)q + 3];
-    cp.wF[c] = cp.sFx[q];
-    cp.wF[(size_t)cp.win_cap + c] = cp.sFy[q];
+  {
+    double *F = cp.wF + (size_t)b * 2 * cp.win_cap;
+#pragma unroll
+    for (int r = 0; r < kCellsPerLane; ++r)
+      if (tid + r * MDF_THREADS < ns) {
+        const int wi = ((cxy[r] >> 16) - win.y0) * win.w + ((cxy[r] & 0xffff) - win.x0);
+        F[wi] = s_fx[tid + r * MDF_THREADS];
+        F[(size_t)cp.win_cap + wi] = s_fy[tid + r * MDF_THREADS];
+      }
   }
   double *gtx = cp.ftot + (size_t)(k & 1) * 2 * n;
   double *gty = gtx + n;
@@ -1255,16 +1583,33 @@ hipError_t launch_level_st(int tile, const LevelArgs *a, hipStream_t s) {
 }  // namespace
 
 extern "C" hipError_t sbt_launch_level_tile(int storage, const LevelArgs *a, hipStream_t s) {
-  int groups = a->n_blocks + (a->n_band + 255) / 256;
+  if (a->kpw < 1) return hipErrorInvalidValue;
+  const bool pipe = a->kpw > 1;
+  const int kpw = pipe ? a->kpw : 1;
+  const int n_run = (a->n_fast + kpw - 1) / kpw, n_blk = a->n_blocks - a->n_fast, n_bnd = (a->n_band + 255) / 256;
+  int groups = n_run + n_blk + n_bnd;
   if (groups <= 0) return hipSuccess;
+  if (a->xcd_remap) {  // 8 x the largest per-XCD share (see tile_role)
+    int most = 0;
+    for (int x = 0; x < 8; ++x) {
+      int c = (n_run * (x + 1) / 8 - n_run * x / 8) + (n_blk * (x + 1) / 8 - n_blk * x / 8) +
+              (n_bnd * (x + 1) / 8 - n_bnd * x / 8);
+      most = c > most ? c : most;
+    }
+    groups = 8 * most;
+  }
   dim3 grid(groups);
+#define SBT_TILE_LAUNCH(S)                                                               \
+  if (pipe) hipLaunchKernelGGL((level_tile_kernel<S, 2>), grid, dim3(256), 0, s, *a, a->cases); \
+  else hipLaunchKernelGGL((level_tile_kernel<S, 1>), grid, dim3(256), 0, s, *a, a->cases);
   switch (storage) {
-    case 0: hipLaunchKernelGGL(level_tile_kernel<0>, grid, dim3(256), 0, s, *a); break;
-    case 1: hipLaunchKernelGGL(level_tile_kernel<1>, grid, dim3(256), 0, s, *a); break;
-    case 2: hipLaunchKernelGGL(level_tile_kernel<2>, grid, dim3(256), 0, s, *a); break;
-    case 3: hipLaunchKernelGGL(level_tile_kernel<3>, grid, dim3(256), 0, s, *a); break;
+    case 0: SBT_TILE_LAUNCH(0); break;
+    case 1: SBT_TILE_LAUNCH(1); break;
+    case 2: SBT_TILE_LAUNCH(2); break;
+    case 3: SBT_TILE_LAUNCH(3); break;
     default: return hipErrorInvalidValue;
   }
+#undef SBT_TILE_LAUNCH
   return hipGetLastError();
 }
 
@@ -1278,13 +1623,26 @@ extern "C" hipError_t sbt_launch_level(int storage, int tile, const LevelArgs *a
   return hipErrorInvalidValue;
 }
 
-extern "C" size_t sbt_mdf_lds_bytes(int max_markers, int lds_window) {
-  return (size_t)max_markers * (11 * sizeof(double) + 18 * sizeof(int)) + (size_t)lds_window * sizeof(int);
+extern "C" size_t sbt_mdf_lds_bytes(int max_markers, int cell_cap) {
+  return (size_t)max_markers * (11 * sizeof(double) + 2 * sizeof(int) + 16 * sizeof(uint16_t)) +
+         (size_t)cell_cap * 5 * sizeof(double);
+}
+
+extern "C" size_t sbt_prep_lds_bytes(int max_markers, int cell_cap, int lds_window) {
+  return (size_t)cell_cap * 2 * sizeof(int) + (size_t)max_markers * 16 * sizeof(uint16_t) +
+         (size_t)lds_window * 2 * sizeof(int);
+}
+
+extern "C" hipError_t sbt_launch_ibm_prep(const IbmArgs *a, int n_bodies, hipStream_t s) {
+  if (n_bodies <= 0) return hipSuccess;
+  size_t lds = sbt_prep_lds_bytes(a->max_markers, a->cell_cap, a->lds_window);
+  hipLaunchKernelGGL(ibm_prep_kernel, dim3(n_bodies), dim3(MDF_THREADS), lds, s, *a);
+  return hipGetLastError();
 }
 
 extern "C" hipError_t sbt_launch_mdf(int storage, const MdfArgs *a, int n_bodies, hipStream_t s) {
   if (n_bodies <= 0) return hipSuccess;
-  size_t lds = sbt_mdf_lds_bytes(a->max_markers, a->lds_window);
+  size_t lds = sbt_mdf_lds_bytes(a->max_markers, a->cell_cap);
   switch (storage) {
     case 0: hipLaunchKernelGGL(mdf_kernel<0>, dim3(n_bodies), dim3(MDF_THREADS), lds, s, *a); break;
     case 1: hipLaunchKernelGGL(mdf_kernel<1>, dim3(n_bodies), dim3(MDF_THREADS), lds, s, *a); break;
