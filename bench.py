@@ -58,11 +58,13 @@ def rel_l2_vs(ref, sim, wls):
     return math.sqrt(num / max(den, 1e-300)), worst
 
 
-def time_form(P, wls, storage, steps, warmup, tile=None):
+def time_form(P, wls, storage, steps, warmup, tile=None, autotune=False):
     import torch
     sim = P.Sim(wls, storage)
     if tile is not None:
         sim.set_option(P.OPT_TILE, tile)
+    if autotune:
+        sim.autotune(steps=2, cache_path=os.path.join(ROOT, "paper_2402_04606_amd", "tune_cache.json"))
     sim.step(warmup)
     sim.synchronize()
     torch.cuda.synchronize()
@@ -145,9 +147,7 @@ def main():
     V = max(w.n_levels for w in wls)
 
     # ---- headline form, timed with graphs --------------------------------------
-    sim, dt, ups = time_form(P, wls, args.storage, args.steps, args.warmup, args.tile)
-    if args.autotune:
-        sim.autotune(steps=3, cache_path=os.path.join(ROOT, "paper_2402_04606_amd", "tune_cache.json"))
+    sim, dt, ups = time_form(P, wls, args.storage, args.steps, args.warmup, args.tile, args.autotune)
     mlups = ups * args.steps / dt / 1e6
     ms_per_step = dt * 1e3 / args.steps
 

@@ -284,6 +284,8 @@ struct sbt_ctx {
   int cell_cap = 0;             // stencil cells per IBM plan (fits the forcing kernel's LDS)
   int max_body_markers = 0;     // largest body set so far (LDS table stride)
   bool need_prep = true;        // the plan of the next finest substep must be built first
+  int64_t k_host = 0;           // finest substeps issued (every body's forcing-loop counter)
+
   std::vector<hipStream_t> prep_streams;
   std::vector<hipEvent_t> ev_lvl, ev_prep;
   std::vector<Phase> step_phases;
@@ -673,6 +675,8 @@ sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s
   a.cases = X.d_cases;
   a.mode = mode;
   a.xcd_remap = X.xcd;
+  // the finest level collides with the force of the forcing loop just run
+  a.ibm_parity = (v == X.V - 1 && X.n_bodies > 0 && X.k_host > 0) ? (int)((X.k_host - 1) & 1) : -1;
   a.err = X.d_err;
   auto timed = [&](bool fast, auto &&launch) -> sbt_status {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -724,6 +728,8 @@ sbt_status launch_mdf(sbt_ctx &X, int g, bool first, hipStream_t s) {
   a.err = X.d_err;
   a.max_markers = X.max_body_markers;
   a.cell_cap = X.cell_cap;
+  a.parity = (int)(X.k_host & 1);
+  ++X.k_host;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (X.profiling) {
     HIPCHK(hipEventCreate(&e0));
@@ -803,6 +809,8 @@ sbt_status run_group_step(sbt_ctx &X, int g, hipStream_t s) {
 // builder on its own stream r, so the plan of substep k+1 is built while
 // the forcing loop and the collision of substep k run.  ev_lvl[0] forks r;
 // ev_lvl[i + 1] follows the i-th finest collision, ev_prep[i] the i-th plan.
+// (The forcing loop itself stays on the chain: its workgroups each need a
+// whole CU, so it does not overlap the bandwidth-bound collision usefully.)
 sbt_status capture_group_step(sbt_ctx &X, int g, hipStream_t s, hipStream_t r, const hipEvent_t *ev_lvl,
                               const hipEvent_t *ev_prep, int n_mdf) {
   HIPCHK(hipEventRecord(ev_lvl[0], s));
@@ -886,7 +894,8 @@ sbt_status ensure_side_streams(sbt_ctx &X) {
   const int nm = forcing_phases(X);
   while ((int)X.ev_lvl.size() < X.G * (nm + 1)) HIPCHK(new_event(X.ev_lvl));
   while ((int)X.ev_prep.size() < X.G * std::max(1, nm)) HIPCHK(new_event(X.ev_prep));
-  if (X.graph.size() != 2) X.graph.assign(2, nullptr);
+
+  if (X.graph.size() != 4) X.graph.assign(4, nullptr);
   return SBT_OK;
 }
 
@@ -900,6 +909,7 @@ sbt_status capture_graph(sbt_ctx &X, int parity) {
   const int nm = forcing_phases(X);
   std::vector<int> saved(X.pools.size());
   for (size_t i = 0; i < X.pools.size(); ++i) saved[i] = X.pools[i].cur;
+  const int64_t saved_k = X.k_host;
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(X.cap_stream, hipStreamCaptureModeThreadLocal));
   sbt_status st = SBT_OK;
@@ -922,6 +932,7 @@ sbt_status capture_graph(sbt_ctx &X, int parity) {
   }
   hipError_t e2 = hipStreamEndCapture(X.cap_stream, &g);
   for (size_t i = 0; i < X.pools.size(); ++i) X.pools[i].cur = saved[i];
+  X.k_host = saved_k;
   if (st) {
     if (g) (void)hipGraphDestroy(g);
     return st;
@@ -969,6 +980,8 @@ sbt_status readout_level(sbt_ctx &X, int c, int l, hipStream_t s) {
   Pool &P = X.pools[(size_t)C.group * X.V + v];
   LevelArgs a;
   std::memset(&a, 0, sizeof(a));
+  a.ibm_parity = -1;
+  a.kpw = 1;
   a.meta = P.d_meta;
   a.codes = P.d_codes;
   // after a step the state to read is the one the last launch streamed from
@@ -1008,6 +1021,7 @@ sbt_status reset_counters(sbt_ctx &X) {
   }
   X.post = false;
   X.need_prep = true;
+  X.k_host = 0;
   for (auto &P : X.pools) P.cur = 0;
   destroy_graphs(X);
   return SBT_OK;
@@ -1113,6 +1127,7 @@ sbt_status sbt_destroy(sbt_ctx *ctx) {
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (auto st : ctx->side_streams) (void)hipStreamDestroy(st);
   for (auto st : ctx->prep_streams) (void)hipStreamDestroy(st);
+
   for (auto ev : ctx->fork_events) (void)hipEventDestroy(ev);
   for (auto ev : ctx->ev_lvl) (void)hipEventDestroy(ev);
   for (auto ev : ctx->ev_prep) (void)hipEventDestroy(ev);
@@ -1295,16 +1310,20 @@ sbt_status sbt_step(sbt_ctx *ctx, int32_t n) {
     if (X.use_graph && !X.profiling) {
       sbt_status st = ensure_side_streams(X);
       if (st) return st;
-      int par = X.pools[0].cur;
+      // a graph bakes in the lattice parities and the IBM plan parities of
+      // its substeps
+      const int par = X.pools[0].cur + 2 * (int)(X.k_host & 1);
       if (!X.graph[par]) {
         st = capture_graph(X, par);
         if (st) return st;
       }
       HIPCHK(hipGraphLaunch(X.graph[par], X.stream));
-      // the graph performs the same lattice flips as the eager list
+      // the graph performs the same lattice flips and forcing loops as the
+      // eager list
       for (int g = 0; g < X.G; ++g)
         for (const Phase &ph : X.step_phases)
           if (ph.type == PH_LEVEL) X.pools[(size_t)g * X.V + ph.v].cur ^= 1;
+      if (X.n_bodies > 0) X.k_host += forcing_phases(X);
     } else {
       sbt_status st = run_step_eager(X, X.stream);
       if (st) return st;
@@ -1527,6 +1546,7 @@ sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes) {
   for (auto &C : X.cs) {
     if (!C.has_body) continue;
     HIPCHK(hipMemcpy(C.dev.kcount, p, sizeof(int64_t), hipMemcpyHostToDevice));
+    std::memcpy(&X.k_host, p, sizeof(int64_t));  // every body shares the substep counter
     p += sizeof(int64_t);
     size_t nb = sizeof(double) * 4 * (size_t)C.d.max_markers;
     HIPCHK(hipMemcpy(C.dev.ftot, p, nb, hipMemcpyHostToDevice));

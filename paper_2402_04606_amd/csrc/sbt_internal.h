@@ -100,6 +100,7 @@ struct LevelArgs {
   int32_t n_blocks;            // entries of list (or length of the range)
   int32_t n_fast;              // leading list entries that are interior blocks
   int32_t kpw;                 // interior blocks per workgroup (tile launch, >= 1)
+  int32_t ibm_parity;          // IBM plan buffer of the substep (-1: from the forcing-loop counter)
   const int32_t *band;         // halo-band cells (block * 256 + cell), gathered after the blocks
   int32_t n_band;
   int32_t mode;                // MODE_* bits
@@ -117,6 +118,7 @@ struct MdfArgs {
   int32_t first;               // 1: local read (initial pre-collision state)
   int32_t max_markers;         // LDS marker-table stride (>= every body's markers)
   int32_t cell_cap;            // LDS stencil-cell table size (>= every plan's cells)
+  int32_t parity;              // plan buffer of this substep (its index & 1)
   int32_t *err;
 };
 

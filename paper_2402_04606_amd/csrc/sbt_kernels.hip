@@ -263,10 +263,13 @@ struct Collide {
 
 // IBM force density at cell (x, y) of the finest block at (ox, oy) for the
 // collision of the substep the last forcing loop ran for (zero outside its
-// window).  The window test is per block, on wave-uniform values.
+// window).  `parity` is that substep's plan buffer (negative: derived from
+// the forcing-loop counter).  The window test is per block, on wave-uniform
+// values.
 template <typename C>
-__device__ __forceinline__ void add_ibm_force(const CaseDev &cp, int ox, int oy, int x, int y, C &Fx, C &Fy) {
-  const int b = __builtin_amdgcn_readfirstlane((int)((*cp.kcount - 1) & 1));
+__device__ __forceinline__ void add_ibm_force(const CaseDev &cp, int parity, int ox, int oy, int x, int y, C &Fx,
+                                              C &Fy) {
+  const int b = parity >= 0 ? parity : __builtin_amdgcn_readfirstlane((int)((*cp.kcount - 1) & 1));
   const IbmWindow w = cp.win[b];
   const int x0 = __builtin_amdgcn_readfirstlane(w.x0), y0 = __builtin_amdgcn_readfirstlane(w.y0);
   const int ww = __builtin_amdgcn_readfirstlane(w.w), wh = __builtin_amdgcn_readfirstlane(w.h);
@@ -498,7 +501,7 @@ __device__ __forceinline__ void level_cell(const LevelArgs &a, const Blk &k, int
     Fx = cp.fx_f[l];
     Fy = cp.fy_f[l];
   }
-  if (k.flags & BF_IBM) add_ibm_force<C>(cp, k.ox, k.oy, x, y, Fx, Fy);
+  if (k.flags & BF_IBM) add_ibm_force<C>(cp, a.ibm_parity, k.ox, k.oy, x, y, Fx, Fy);
 
   C rho, ux, uy;
   Collide<ST>::run(cp, l, f, Fx, Fy, rho, ux, uy);
@@ -548,9 +551,11 @@ __device__ __forceinline__ int remap_block(int bid, int nblk, int enable) {
 // Work item of tile-launch workgroup `bid` (roles: 0 interior run, 1 edge or
 // interface block, 2 band-cell group, -1 none).  Workgroups go to the 8
 // XCDs round-robin; XCD x takes the x-th eighth of each role (contiguous in
-// Morton order, so its halo reads stay in its own L2), so the slower roles
-// are spread over all XCDs instead of trailing on the last ones.  Without
-// the remap the grid is plain [runs | blocks | band groups].
+// Morton order, so its halo reads stay in its own L2), band groups and
+// edge/interface blocks first: they are latency-bound and slower, so they
+// are spread over all XCDs and overlap the streaming runs instead of
+// trailing at the end.  Without the remap the grid is plain
+// [runs | blocks | band groups].
 __device__ __forceinline__ int tile_role(int bid, int n_run, int n_blk, int n_bnd, int enable, int &idx) {
   if (!enable) {
     if (bid < n_run) { idx = bid; return 0; }
@@ -561,14 +566,14 @@ __device__ __forceinline__ int tile_role(int bid, int n_run, int n_blk, int n_bn
     return bid < n_bnd ? 2 : -1;
   }
   const int x = bid & 7, k = bid >> 3;
-  const int r0 = n_run * x / 8, r1 = n_run * (x + 1) / 8;
-  if (k < r1 - r0) { idx = r0 + k; return 0; }
-  const int k1 = k - (r1 - r0);
+  const int b0 = n_bnd * x / 8, b1 = n_bnd * (x + 1) / 8;
+  if (k < b1 - b0) { idx = b0 + k; return 2; }
+  const int k1 = k - (b1 - b0);
   const int s0 = n_blk * x / 8, s1 = n_blk * (x + 1) / 8;
   if (k1 < s1 - s0) { idx = s0 + k1; return 1; }
   const int k2 = k1 - (s1 - s0);
-  const int b0 = n_bnd * x / 8, b1 = n_bnd * (x + 1) / 8;
-  if (k2 < b1 - b0) { idx = b0 + k2; return 2; }
+  const int r0 = n_run * x / 8, r1 = n_run * (x + 1) / 8;
+  if (k2 < r1 - r0) { idx = r0 + k2; return 0; }
   return -1;
 }
 
@@ -836,7 +841,7 @@ __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev 
     Fx = cp.fx_f[l];
     Fy = cp.fy_f[l];
   }
-  if (k.flags & BF_IBM) add_ibm_force<C>(cp, k.ox, k.oy, x, y, Fx, Fy);
+  if (k.flags & BF_IBM) add_ibm_force<C>(cp, a.ibm_parity, k.ox, k.oy, x, y, Fx, Fy);
   C rho, ux, uy;
   Collide<ST>::run(cp, l, f, Fx, Fy, rho, ux, uy);
   if (!(rho == rho) || rho > C(1e30) || rho < C(-1e30)) atomicOr(a.err, ERR_NONFINITE);
@@ -1329,58 +1334,53 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
   int *s_i0 = reinterpret_cast<int *>(s_fy + CC);  // [NM]
   int *s_j0 = s_i0 + NM;
   uint16_t *s_list = reinterpret_cast<uint16_t *>(s_j0 + NM);  // [16 NM]
-  const int64_t k = *cp.kcount;
-  const int b = (int)(k & 1);
+  // The plan buffer is the substep's parity (known to the launcher), so the
+  // plan loads below do not wait for the substep counter.
+  const int b = a.parity;
   const PlanView P = plan_view(cp, b);
-  const int stamp = P.hdr[0], ns = P.hdr[1];
-  int status = P.hdr[2];
-  if (stamp != (int)k) status = ERR_PLAN;
-  if (!status && ns > min(CC, kCellsPerLane * MDF_THREADS)) status = ERR_CONTRIB;
-  if (status) {
-    if (tid == 0) mdf_fail(cp, a.err, status, k);
-    return;
-  }
-  // 1. load the plan: marker weights and desired velocity (registers and
-  //    LDS), the contributor lists (LDS), and per owned stencil cell its
-  //    moments from the post-stream populations (the initial state is read
-  //    in place), with rho and the uncorrected velocity to LDS
-  const bool own = tid < n;
-  double wx[4], wy[4], udx = 0.0, udy = 0.0;
-  uint32_t taps[8];  // stencil cells of the 16 taps, two per word
-  if (own) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      wx[t] = P.w[(size_t)t * nm + tid];
-      wy[t] = P.w[(size_t)(4 + t) * nm + tid];
-      s_wx[t * NM + tid] = wx[t];
-      s_wy[t * NM + tid] = wy[t];
-    }
-    udx = P.ud[tid];
-    udy = P.ud[nm + tid];
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-      taps[t] = (uint32_t)P.tap[(size_t)(2 * t) * nm + tid] | ((uint32_t)P.tap[(size_t)(2 * t + 1) * nm + tid] << 16);
-    s_i0[tid] = P.i0[tid];
-    s_j0[tid] = P.j0[tid];
-    s_ds[tid] = cp.ds[tid];
+  const int64_t k = *cp.kcount;
+  const int4 hdr = *reinterpret_cast<const int4 *>(P.hdr);
+  const IbmWindow win = cp.win[b];
+  // 1. load the plan: this lane's stencil-cell records (up to the plan
+  //    capacity, so before the header is known) and the contributor lists
+  //    (LDS)
+  const int cap = min(cp.cell_cap, min(CC, kCellsPerLane * MDF_THREADS));
+  int4 rec0[kCellsPerLane], rec1[kCellsPerLane];
+  if (tid < cap) {  // first owned cell: before the header is known
+    const int4 *R = reinterpret_cast<const int4 *>(P.cell + (size_t)tid * 8);
+    rec0[0] = R[0];
+    rec1[0] = R[1];
   }
   {
     const uint32_t *src = reinterpret_cast<const uint32_t *>(P.list);
     uint32_t *dst = reinterpret_cast<uint32_t *>(s_list);
     for (int e = tid; e < 8 * n; e += MDF_THREADS) dst[e] = src[e];
   }
+  const int ns = hdr.y;
+  int status = hdr.z;
+  if (hdr.x != (int)k || (k & 1) != b) status = ERR_PLAN;
+  if (!status && ns > cap) status = ERR_CONTRIB;
+  if (status) {
+    if (tid == 0) mdf_fail(cp, a.err, status, k);
+    return;
+  }
+  // 2. moments of the owned stencil cells from the post-stream populations
+  //    (the initial state is read in place): rho and the uncorrected
+  //    velocity to LDS
   const int l = cp.n_levels - 1;
-  const IbmWindow win = cp.win[b];
-  // per owned stencil cell: gx | gy << 16, list start | count << 16
-  int cxy[kCellsPerLane], csc[kCellsPerLane];
+  int cxy[kCellsPerLane], csc[kCellsPerLane];  // gx | gy << 16, list start | count << 16
 #pragma unroll
   for (int r = 0; r < kCellsPerLane; ++r) {
     const int q = tid + r * MDF_THREADS;
     cxy[r] = 0;
     csc[r] = 0;
     if (q < ns) {
-      const int4 *R = reinterpret_cast<const int4 *>(P.cell + (size_t)q * 8);
-      const int4 r0 = R[0], r1 = R[1];
+      if (r > 0) {
+        const int4 *R = reinterpret_cast<const int4 *>(P.cell + (size_t)q * 8);
+        rec0[r] = R[0];
+        rec1[r] = R[1];
+      }
+      const int4 r0 = rec0[r], r1 = rec1[r];
       const int c = r0.x;
       const int gx = win.x0 + c % win.w, gy = win.y0 + c / win.w;
       cxy[r] = gx | (gy << 16);
@@ -1408,8 +1408,28 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
       s_fy[q] = 0.0;
     }
   }
+  // marker weights and desired velocity (registers and LDS), loaded while
+  // the gathers above are in flight
+  const bool own = tid < n;
+  double udx = 0.0, udy = 0.0;
+  uint32_t taps[8];  // stencil cells of the 16 taps, two per word
+  if (own) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      s_wx[t * NM + tid] = P.w[(size_t)t * nm + tid];
+      s_wy[t * NM + tid] = P.w[(size_t)(4 + t) * nm + tid];
+    }
+    udx = P.ud[tid];
+    udy = P.ud[nm + tid];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      taps[t] = (uint32_t)P.tap[(size_t)(2 * t) * nm + tid] | ((uint32_t)P.tap[(size_t)(2 * t + 1) * nm + tid] << 16);
+    s_i0[tid] = P.i0[tid];
+    s_j0[tid] = P.j0[tid];
+    s_ds[tid] = cp.ds[tid];
+  }
   __syncthreads();
-  // 2. N_F iterations: interpolate (Eq. 12), boundary force (Eq. 11),
+  // 3. N_F iterations: interpolate (Eq. 12), boundary force (Eq. 11),
   //    spread (Eq. 15), correct velocity and accumulate force
   double ftx = 0.0, fty = 0.0;
   for (int it = 0; it < cp.mdf_iters; ++it) {
@@ -1417,12 +1437,12 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
       double su = 0.0, sv = 0.0, sr = 0.0;
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
-        const double py = wy[bb];
+        const double py = s_wy[bb * NM + tid];
 #pragma unroll
         for (int aa = 0; aa < 4; ++aa) {
           const int t = bb * 4 + aa;
           const int q = (taps[t >> 1] >> ((t & 1) * 16)) & 0xffff;
-          const double w = wx[aa] * py;
+          const double w = s_wx[aa * NM + tid] * py;
           su += s_u[q] * w;
           sv += s_v[q] * w;
           sr += s_rho[q] * w;
@@ -1443,11 +1463,27 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
         const int gx = cxy[r] & 0xffff, gy = cxy[r] >> 16;
         const int st = csc[r] & 0xffff, cnt = csc[r] >> 16;
         double dfx = 0.0, dfy = 0.0;
-        for (int e = 0; e < cnt; ++e) {
-          const int j = s_list[st + e];
-          const double w = s_wx[(gx - s_i0[j]) * NM + j] * s_wy[(gy - s_j0[j]) * NM + j];
-          dfx += s_dFx[j] * w * s_ds[j];
-          dfy += s_dFy[j] * w * s_ds[j];
+        // contributors four at a time (their LDS reads overlap), summed in
+        // ascending marker order
+        for (int e0 = 0; e0 < cnt; e0 += 4) {
+          int js[4];
+          double wv[4], fxv[4], fyv[4], dsv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) js[u] = e0 + u < cnt ? (int)s_list[st + e0 + u] : -1;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int j = js[u] < 0 ? 0 : js[u];
+            wv[u] = s_wx[(gx - s_i0[j]) * NM + j] * s_wy[(gy - s_j0[j]) * NM + j];
+            fxv[u] = s_dFx[j];
+            fyv[u] = s_dFy[j];
+            dsv[u] = s_ds[j];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (js[u] >= 0) {
+              dfx += fxv[u] * wv[u] * dsv[u];
+              dfy += fyv[u] * wv[u] * dsv[u];
+            }
         }
         s_fx[q] = s_fx[q] + dfx;
         s_fy[q] = s_fy[q] + dfy;
@@ -1458,28 +1494,15 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     }
     __syncthreads();
   }
-  // 3. force density of the stencil cells for the collision, total marker
-  //    forces, and the body force of Eq. (16) summed in marker order
-  {
-    double *F = cp.wF + (size_t)b * 2 * cp.win_cap;
-#pragma unroll
-    for (int r = 0; r < kCellsPerLane; ++r)
-      if (tid + r * MDF_THREADS < ns) {
-        const int wi = ((cxy[r] >> 16) - win.y0) * win.w + ((cxy[r] & 0xffff) - win.x0);
-        F[wi] = s_fx[tid + r * MDF_THREADS];
-        F[(size_t)cp.win_cap + wi] = s_fy[tid + r * MDF_THREADS];
-      }
-  }
-  double *gtx = cp.ftot + (size_t)(k & 1) * 2 * n;
-  double *gty = gtx + n;
+  // 4. body force of Eq. (16) summed in marker order by the last lane (its
+  //    wave rarely owns markers or cells), while the other lanes write the
+  //    force density of the stencil cells and the total marker forces
   if (own) {
-    gtx[tid] = ftx;
-    gty[tid] = fty;
     s_dFx[tid] = ftx * s_ds[tid];
     s_dFy[tid] = fty * s_ds[tid];
   }
   __syncthreads();
-  if (tid == 0) {
+  if (tid == MDF_THREADS - 1) {
     double fsx = 0.0, fsy = 0.0;
     int j = 0;
     for (; j + 8 <= n; j += 8) {
@@ -1502,8 +1525,23 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     int64_t slot = k % cp.hist_cap;
     cp.hist[2 * slot] = fsx;
     cp.hist[2 * slot + 1] = fsy;
-    *cp.kcount = k + 1;
   }
+  {
+    double *F = cp.wF + (size_t)b * 2 * cp.win_cap;
+#pragma unroll
+    for (int r = 0; r < kCellsPerLane; ++r)
+      if (tid + r * MDF_THREADS < ns) {
+        const int wi = ((cxy[r] >> 16) - win.y0) * win.w + ((cxy[r] & 0xffff) - win.x0);
+        F[wi] = s_fx[tid + r * MDF_THREADS];
+        F[(size_t)cp.win_cap + wi] = s_fy[tid + r * MDF_THREADS];
+      }
+  }
+  if (own) {
+    double *gtx = cp.ftot + (size_t)(k & 1) * 2 * n;
+    gtx[tid] = ftx;
+    gtx[n + tid] = fty;
+  }
+  if (tid == 0) *cp.kcount = k + 1;
 }
 
 // ---- small helpers ---------------------------------------------------------
