@@ -9,6 +9,7 @@ storage forms with their error against FP64, and the FP64 CPU oracle timed on
 a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -35,6 +36,22 @@ def workload_list(name):
     if name == "tgv8192":
         return [W.tgv(8192, tau=0.8, u0=0.02)], "tgv_8192x8192_single_level"
     raise SystemExit(f"unknown workload {name}")
+
+
+def measured_traffic(workload, storage):
+    """HBM bytes per launch of the level kernel from the committed counter
+    summary of this workload and storage form (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, each scaled by the same counter's reading for a plain copy
+    of known size), or None when there is none or the kernel source changed
+    since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"level_tile_kernel_{workload}_{storage}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2402_04606_amd", "csrc", "sbt_kernels.hip")
+    if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def rel_l2_vs(ref, sim, wls):
@@ -159,9 +176,10 @@ def main():
     gen_bytes = prof["level_bytes"] - prof["fast_bytes"]
     roofline = {
         "bound": "hbm", "achieved": round(fast_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(fast_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+        "frac": round(fast_gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, args.storage),
         "kernel": "level_tile_kernel (LDS-staged stream+collide, all owned blocks)",
         "bytes_per_update": 2 * Q * sbytes,
+        "algorithmic_bytes_per_launch": round(prof["fast_bytes"] / max(1, prof["fast_launches"])),
         "launches": prof["fast_launches"],
         "avg_launch_us": round(prof["fast_ms"] * 1e3 / max(1, prof["fast_launches"]), 2),
         "time_share": {

@@ -295,3 +295,118 @@ def test_diagnostics_match_oracle(env):
     dg, do = g.diagnostics(), o.diagnostics()
     assert abs(dg[0] - do[0]) <= 1e-12 * do[0]
     assert np.abs(dg[1:] - do[1:]).max() <= 1e-12 * do[0]
+
+
+# ---- full-size batch (the benchmark workload, in its launch configuration) ------
+
+def _dense_cells(wl):
+    return sum(wl.nx0 * wl.ny0 * 4 ** l for l in range(wl.n_levels))
+
+
+@pytest.fixture(scope="module")
+def sweep_f64(env):
+    P, _ = env
+    wls = W.batch_sweep()
+    print(f"batch sweep: {len(wls)} cases, f64, graph", flush=True)
+    g = P.Sim(wls, "f64")
+    g.step(2)
+    g.synchronize()
+    return wls, g
+
+
+def test_sweep_cases_match_oracle(env, sweep_f64):
+    """The 64-case batch in FP64 through the graph-replayed launch chain the
+    benchmark times; the cases whose dense oracle arrays fit are compared
+    with the oracle run of that case alone (2 global steps = 2 * 2^(4-m)
+    coarse steps of a case with m levels)."""
+    P, O = env
+    wls, g = sweep_f64
+    V = max(w.n_levels for w in wls)
+    order = sorted(range(len(wls)), key=lambda c: _dense_cells(wls[c]))
+    picked = []
+    for m in (2, 3, 4):        # the smallest case of each level count
+        picked += [c for c in order if wls[c].n_levels == m][:1]
+    for c in picked:
+        wl = wls[c]
+        o = O.OracleSim(wl)
+        o.step(2 * 2 ** (V - wl.n_levels))
+        print(f"sweep case {c} ({wl.nx0}x{wl.ny0}, {wl.n_levels} levels)", flush=True)
+        compare_levels(g, o, wl, TOL64, c=c)
+        fg, _ = g.force_history(c)
+        fo, _ = o.force_history()
+        assert len(fg) == len(fo) and np.abs(fg - fo).max() <= TOL64 * np.abs(fo).max()
+
+
+def test_sweep_batch_equals_cases_alone(env, sweep_f64):
+    """Any size: every case of the batch equals, bit for bit, the same case
+    run in a context of its own (batching changes no arithmetic)."""
+    P, _ = env
+    wls, g = sweep_f64
+    V = max(w.n_levels for w in wls)
+    for c, wl in enumerate(wls):
+        a = P.Sim(wl, "f64")
+        a.step(2 * 2 ** (V - wl.n_levels))
+        a.synchronize()
+        for l in range(wl.n_levels):
+            x, y = g.fields_blocks(c, l), a.fields_blocks(0, l)
+            assert np.array_equal(x, y, equal_nan=True), (c, l)
+        assert np.array_equal(g.force_history(c)[0], a.force_history()[0]), c
+        a.close()
+
+
+def test_sweep_f16s_error_ceiling(env, sweep_f64):
+    """The benchmark's storage form on the full batch: relative L2 of
+    velocity against the FP64 batch after the same 2 global steps."""
+    P, _ = env
+    wls, g = sweep_f64
+    h = P.Sim(wls, "f16s")
+    h.step(2)
+    h.synchronize()
+    num = den = 0.0
+    for c, wl in enumerate(wls):
+        for l in range(wl.n_levels):
+            a, b = g.fields_blocks(c, l), h.fields_blocks(c, l)     # [block][rho, ux, uy][cell]
+            m = ~np.isnan(a[:, 0])
+            for k in (1, 2):
+                num += float(((b[:, k][m] - a[:, k][m]) ** 2).sum())
+                den += float((a[:, k][m] ** 2).sum())
+    e = math.sqrt(num / den)
+    print(f"  f16s vs f64 rel L2 u: {e:.3e}", flush=True)
+    assert e <= 5e-3
+
+
+# ---- physics against the paper's printed values ------------------------------------
+
+def test_cylinder_table1_full_size(env):
+    """Configuration C2 (1024x512, D 40, 126 markers, Re 100) run to a
+    periodic wake: mean drag, rms lift and Strouhal number against Sec. 3.3,
+    Table 1 (tests/golden/cylinder_table1.json).  C2's channel is 512 cells
+    high with symmetry edges (blockage D/H = 0.078), which raises drag and
+    shedding frequency above the paper's values, so C_D may sit up to 15 %
+    and St up to 10 % above them (measured: C_D 1.469, St 0.169, C_L' 0.294);
+    a lost factor 2, a wrong sign or a missing ds moves them far more."""
+    import json
+    import os
+    P, _ = env
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cylinder_table1.json")))["Re100"]
+    wl = W.cylinder()
+    g = P.Sim(wl, "f64")
+    n, chunk = 100000, 10000
+    for done in range(0, n, chunk):
+        g.step(chunk)
+        g.synchronize()
+        print(f"  cylinder steps {done + chunk}", flush=True)
+    fx, fy = g.force_history()
+    U, D = wl.meta["U"], wl.meta["D"]
+    cd, cl = fx / (0.5 * U * U * D), fy / (0.5 * U * U * D)
+    tail = slice(len(cl) - 30000, len(cl))
+    c = cl[tail] - cl[tail].mean()
+    up = np.nonzero((c[:-1] < 0) & (c[1:] >= 0))[0]
+    assert len(up) >= 4, "no periodic shedding"
+    st = D / (np.diff(up).mean() * U)
+    print(f"  C_D {cd[tail].mean():.4f}  C_L' {c.std():.4f}  St {st:.4f}", flush=True)
+    p = gold["present"]
+    assert p["St"] * 0.97 <= st <= p["St"] * 1.10, st
+    assert p["CD_mean"] * 0.97 <= cd[tail].mean() <= p["CD_mean"] * 1.15, cd[tail].mean()
+    lo, hi = gold["literature_range"]["CL_rms"]
+    assert lo <= c.std() <= 1.2 * hi, c.std()
