@@ -690,6 +690,52 @@ __device__ __forceinline__ void halo_slot(int t, int &plane, int &hx, int &hy) {
   }
 }
 
+// Halo slot t as (neighbour << 16) | element: the neighbour in BlockMeta.nbr
+// order (E, N, W, S, NE, NW, SW, SE) that holds the source cell, and the
+// element (plane * 256 + cell) of that population inside it.  A table
+// built at compile time from halo_slot, so a lane does one lookup instead
+// of the slot arithmetic.
+struct HaloTable {
+  uint32_t e[192];
+  constexpr HaloTable() : e() {
+    for (int t = 0; t < 192; ++t) {
+      int plane = 0, hx = 0, hy = 0, s = 0;
+      const int u = t < 188 ? t : 187;
+      if (u < 64) {
+        s = u & 15;
+        plane = 1 + (u >> 4);
+        hx = plane == 1 ? -1 : (plane == 3 ? 16 : s);
+        hy = plane == 2 ? -1 : (plane == 4 ? 16 : s);
+      } else {
+        const int d = (u - 64) / 31;
+        s = (u - 64) % 31;
+        plane = 5 + d;
+        const bool col = s < 16;
+        if (plane == 5) { hx = col ? -1 : s - 16; hy = col ? s - 1 : -1; }
+        else if (plane == 6) { hx = col ? 16 : s - 15; hy = col ? s - 1 : -1; }
+        else if (plane == 7) { hx = col ? 16 : s - 15; hy = col ? s + 1 : 16; }
+        else { hx = col ? -1 : s - 16; hy = col ? s + 1 : 16; }
+      }
+      int nb = 0;
+      if (hx < 0) nb = hy < 0 ? 6 : (hy > 15 ? 5 : 2);
+      else if (hx > 15) nb = hy < 0 ? 7 : (hy > 15 ? 4 : 0);
+      else nb = hy < 0 ? 3 : 1;
+      e[t] = ((uint32_t)nb << 16) | (uint32_t)(plane * kCells + (hy & 15) * 16 + (hx & 15));
+    }
+  }
+};
+__constant__ constexpr HaloTable kHalo{};
+
+__device__ __forceinline__ int halo_nbr(const Blk &k, int code) {
+  int v = vsel(code == 1, k.nN, k.nE);
+  v = vsel(code == 2, k.nW, v);
+  v = vsel(code == 3, k.nS, v);
+  v = vsel(code == 4, k.nNE, v);
+  v = vsel(code == 5, k.nNW, v);
+  v = vsel(code == 6, k.nSW, v);
+  return vsel(code == 7, k.nSE, v);
+}
+
 // LDS element holding the population of direction i that streams into
 // local cell (x, y): the dense plane when its source cell is inside the
 // block, else the halo slot of that source (inverse of halo_slot).
@@ -732,10 +778,9 @@ __device__ __forceinline__ void fetch_tile(const LevelArgs &a, const Blk &k, typ
                                        16, 0, 0);
   }
   if (tid < 188) {
-    int plane, hx, hy;
-    halo_slot(tid, plane, hx, hy);
-    int nb = pick_nbr(k, hx, hy);
-    h = nb < 0 ? S::st(C(__builtin_nan(""))) : src[((size_t)nb * kQ + plane) * kCells + (hy & 15) * 16 + (hx & 15)];
+    const uint32_t e = kHalo.e[tid];
+    const int nb = halo_nbr(k, (int)(e >> 16));
+    h = nb < 0 ? S::st(C(__builtin_nan(""))) : src[(size_t)nb * kQ * kCells + (e & 0xffff)];
   }
 }
 
@@ -879,8 +924,8 @@ __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev 
 // complete, start block j+1's copies into `nxt` and its metadata for j+2,
 // then stream + collide block j from `cur`.
 template <int ST>
-__device__ __forceinline__ void pipe_step(const LevelArgs &a, const CaseDev *__restrict__ cases, Blk &k, int &mvn,
-                                          int lv, int j, int cnt,
+__device__ __forceinline__ void pipe_step(const LevelArgs &a, const CaseDev *__restrict__ cases,
+                                          const BlockMeta *__restrict__ meta, Blk &k, int &mvn, int lv, int j, int cnt,
                                           typename Store<ST>::T *cur, typename Store<ST>::T *nxt,
                                           typename Store<ST>::T &h) {
   commit_tile<ST>(cur, h);
@@ -888,7 +933,7 @@ __device__ __forceinline__ void pipe_step(const LevelArgs &a, const CaseDev *__r
   if (j + 1 < cnt) {
     k = blk_from_lanes(mvn, __builtin_amdgcn_readlane(lv, j + 1));
     fetch_tile<ST>(a, k, nxt, h);
-    if (j + 2 < cnt) mvn = meta_word(a.meta, __builtin_amdgcn_readlane(lv, j + 2), threadIdx.x & 63);
+    if (j + 2 < cnt) mvn = meta_word(meta, __builtin_amdgcn_readlane(lv, j + 2), threadIdx.x & 63);
   }
   compute_block<ST, false>(a, cases, kc, cur);
 }
@@ -900,7 +945,8 @@ __device__ __forceinline__ void pipe_step(const LevelArgs &a, const CaseDev *__r
 // n_blocks - n_fast workgroups take one block next to a finer level or a
 // domain edge each; the rest gather packed halo-band cells.
 template <int ST, int NBUF>
-__global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a, const CaseDev *__restrict__ cases) {
+__global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a, const CaseDev *__restrict__ cases,
+                                                        const BlockMeta *__restrict__ meta, const int32_t *__restrict__ list) {
   using T = typename Store<ST>::T;
   using TL = Tile<ST>;
   __shared__ __attribute__((aligned(16))) T bufA[TL::SIZE];
@@ -908,35 +954,37 @@ __global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a, const Case
   const int kpw = NBUF == 2 ? a.kpw : 1;
   const int n_fast_wg = (a.n_fast + kpw - 1) / kpw;
   const int n_band_wg = (a.n_band + 255) / 256;
-  int w;
-  const int role = tile_role(blockIdx.x, n_fast_wg, a.n_blocks - a.n_fast, n_band_wg, a.xcd_remap, w);
+  int w0;
+  const int role = __builtin_amdgcn_readfirstlane(
+      tile_role(blockIdx.x, n_fast_wg, a.n_blocks - a.n_fast, n_band_wg, a.xcd_remap, w0));
+  const int w = __builtin_amdgcn_readfirstlane(w0);  // wave-uniform: keeps block metadata on the scalar path
   const int lane = threadIdx.x & 63;
   T h;
   if (role == 0) {
     const int first = w * kpw;
     const int cnt = min(kpw, a.n_fast - first);
     if (NBUF == 1 || cnt == 1) {
-      const Blk k = load_blk(a.meta, a.list[first]);
+      const Blk k = load_blk(meta, list[first]);
       fetch_tile<ST>(a, k, bufA, h);
       commit_tile<ST>(bufA, h);
       compute_block<ST, false>(a, cases, k, bufA);
       return;
     }
     // the run's block ids (one per lane) and the first two blocks' metadata
-    const int lv = a.list[first + min(lane, cnt - 1)];
+    const int lv = list[first + min(lane, cnt - 1)];
     const int b0 = __builtin_amdgcn_readlane(lv, 0);
-    Blk k = blk_from_lanes(meta_word(a.meta, b0, lane), b0);
+    Blk k = blk_from_lanes(meta_word(meta, b0, lane), b0);
     fetch_tile<ST>(a, k, bufA, h);
-    int mvn = meta_word(a.meta, __builtin_amdgcn_readlane(lv, 1), lane);
+    int mvn = meta_word(meta, __builtin_amdgcn_readlane(lv, 1), lane);
     Blk kk = k;
     for (int j = 0; j < cnt; j += 2) {
-      pipe_step<ST>(a, cases, kk, mvn, lv, j, cnt, bufA, bufB, h);
-      if (j + 1 < cnt) pipe_step<ST>(a, cases, kk, mvn, lv, j + 1, cnt, bufB, bufA, h);
+      pipe_step<ST>(a, cases, meta, kk, mvn, lv, j, cnt, bufA, bufB, h);
+      if (j + 1 < cnt) pipe_step<ST>(a, cases, meta, kk, mvn, lv, j + 1, cnt, bufB, bufA, h);
     }
     return;
   }
   if (role == 1) {
-    const Blk k = load_blk(a.meta, a.list[a.n_fast + w]);
+    const Blk k = load_blk(meta, list[a.n_fast + w]);
     fetch_tile<ST>(a, k, bufA, h);
     commit_tile<ST>(bufA, h);
     compute_block<ST, true>(a, cases, k, bufA);
@@ -1638,8 +1686,8 @@ extern "C" hipError_t sbt_launch_level_tile(int storage, const LevelArgs *a, hip
   }
   dim3 grid(groups);
 #define SBT_TILE_LAUNCH(S)                                                               \
-  if (pipe) hipLaunchKernelGGL((level_tile_kernel<S, 2>), grid, dim3(256), 0, s, *a, a->cases); \
-  else hipLaunchKernelGGL((level_tile_kernel<S, 1>), grid, dim3(256), 0, s, *a, a->cases);
+  if (pipe) hipLaunchKernelGGL((level_tile_kernel<S, 2>), grid, dim3(256), 0, s, *a, a->cases, a->meta, a->list); \
+  else hipLaunchKernelGGL((level_tile_kernel<S, 1>), grid, dim3(256), 0, s, *a, a->cases, a->meta, a->list);
   switch (storage) {
     case 0: SBT_TILE_LAUNCH(0); break;
     case 1: SBT_TILE_LAUNCH(1); break;
