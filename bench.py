@@ -81,6 +81,8 @@ def time_form(P, wls, storage, steps, warmup, tile=None, autotune=False):
     if tile is not None:
         sim.set_option(P.OPT_TILE, tile)
     if autotune:
+        # blocks per workgroup per level: the autotuner's cached choice for
+        # this workload shape, or timed trials when the shape is new
         sim.autotune(steps=2, cache_path=os.path.join(ROOT, "paper_2402_04606_amd", "tune_cache.json"))
     sim.step(warmup)
     sim.synchronize()
@@ -134,7 +136,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tile", type=int, default=None)
-    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="automatic blocks per workgroup instead of the autotuner's choice")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -199,7 +202,7 @@ def main():
         for st in want:
             if st == args.storage:
                 continue
-            s2, dt2, _ = time_form(P, wls, st, args.steps, args.warmup, args.tile)
+            s2, dt2, _ = time_form(P, wls, st, args.steps, args.warmup, args.tile, args.autotune)
             sims[st] = s2
             forms[st] = {"mlups": round(ups * args.steps / dt2 / 1e6, 1),
                          "ms_per_step": round(dt2 * 1e3 / args.steps, 3),

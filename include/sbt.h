@@ -89,7 +89,7 @@ enum { SBT_CF_HOMOGENEOUS = 0, SBT_CF_RESCALE = 1 };
  *        centre = (p[0], p[1]) + (p[4]/2) cos(theta) (cos p[5], sin p[5]),
  *        r_j = centre + (xb cos a + yb sin a, -xb sin a + yb cos a).
  *        p = {x0, y0, alpha0, A_pitch, A0, beta, T, phi, U_ref, chord}. */
-enum { SBT_BODY_FIXED = 0, SBT_BODY_FLAP = 1 };
+enum { SBT_BODY_FIXED = 0, SBT_BODY_FLAP = 1, SBT_BODY_HOST = 2 };
 
 typedef struct {
     int32_t level;                 /* >= 1                                        */
@@ -116,7 +116,10 @@ typedef struct {
 
 typedef struct {
     int32_t n;                     /* markers, <= max_markers                      */
-    const double *xb, *yb, *ds;    /* body-frame coordinates and arc length         */
+    const double *xb, *yb, *ds;    /* body-frame coordinates and arc length
+                                      (SBT_BODY_HOST: absolute marker positions in
+                                      finest-level cells, desired velocity 0 until
+                                      sbt_set_markers)                              */
     int32_t kind;                  /* SBT_BODY_*                                   */
     double p[16];                  /* kinematic parameters                         */
 } sbt_body;
@@ -151,6 +154,17 @@ sbt_status sbt_init_uniform(sbt_ctx *ctx, int32_t c, double rho, double ux, doub
 /* Attach a body to a case (copied in).  Only before the first sbt_step after
  * create/init.  n <= max_markers. */
 sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body);
+/* Markers placed by the caller (Sec. 2.2 takes the Lagrangian positions and
+ * their desired velocities as given): for a case whose body is
+ * SBT_BODY_HOST, every forcing loop that the following sbt_step calls run
+ * uses positions x, y (finest-level cells) and desired velocities udx, udy
+ * (finest-level lattice units), n = the body's marker count, until the next
+ * call.  A step collides one finest substep ahead of what the readouts
+ * show: after the readouts show finest substep s, the next forcing loop is
+ * that of substep s + 1 (the first sbt_step runs substeps 0 and 1).  Host
+ * arrays, copied in; waits for the context's stream. */
+sbt_status sbt_set_markers(sbt_ctx *ctx, int32_t c, int32_t n, const double *x, const double *y,
+                           const double *udx, const double *udy);
 
 /* Advance every case by n virtual-level-0 steps (Algorithm 1, each level
  * sub-cycled 2^l times).  Asynchronous, stream-ordered. */

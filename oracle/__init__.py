@@ -18,7 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liborc.so")
 
-ORC_BODY_NONE, ORC_BODY_FIXED, ORC_BODY_FLAP = -1, 0, 1
+ORC_BODY_NONE, ORC_BODY_FIXED, ORC_BODY_FLAP, ORC_BODY_HOST = -1, 0, 1, 2
 
 
 class _Case(C.Structure):
@@ -55,6 +55,7 @@ def lib():
         _lib.orc_read_fields.argtypes = [C.c_void_p, C.c_int, d, d, d]
         _lib.orc_read_populations.argtypes = [C.c_void_p, C.c_int, d]
         _lib.orc_marker_forces.argtypes = [C.c_void_p, d, d]
+        _lib.orc_set_markers.argtypes = [C.c_void_p, C.c_int32, d, d, d, d]
         _lib.orc_force_history.argtypes = [C.c_void_p, C.c_int32, d, d, C.POINTER(C.c_int32)]
         _lib.orc_diagnostics.argtypes = [C.c_void_p, d]
         _lib.orc_substeps.argtypes = [C.c_void_p]
@@ -181,6 +182,13 @@ class OracleSim:
         fx, fy = np.zeros(max(n, 1)), np.zeros(max(n, 1))
         lib().orc_marker_forces(self._h, _dp(fx), _dp(fy))
         return fx[:n], fy[:n]
+
+    def set_markers(self, X, Y, udx, udy):
+        """Caller-placed markers (body kind HOST) for the next steps."""
+        X, Y, udx, udy = (_f64(a) for a in (X, Y, udx, udy))
+        rc = lib().orc_set_markers(self._h, len(X), _dp(X), _dp(Y), _dp(udx), _dp(udy))
+        if rc:
+            raise RuntimeError(f"orc_set_markers failed: {rc}")
 
     def force_history(self, cap=1 << 20):
         fx, fy = np.empty(cap), np.empty(cap)

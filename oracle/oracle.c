@@ -77,6 +77,7 @@ struct orc_sim {
     double *hist;             /* 2 doubles per finest substep */
     int64_t nhist, cap;
     double *ftx, *fty;        /* per-marker total force of the last substep */
+    double *hud;              /* ORC_BODY_HOST: desired velocity, 2 x n       */
     int err;
 };
 
@@ -146,6 +147,10 @@ int orc_body_positions(const orc_case *c, double k, double *X, double *Y) {
     const double *p = c->bp;
     if (c->body_kind == ORC_BODY_FIXED) {
         for (int j = 0; j < c->n_markers; ++j) { X[j] = p[0] + c->xb[j]; Y[j] = p[1] + c->yb[j]; }
+        return ORC_OK;
+    }
+    if (c->body_kind == ORC_BODY_HOST) {      /* caller-placed markers */
+        for (int j = 0; j < c->n_markers; ++j) { X[j] = c->xb[j]; Y[j] = c->yb[j]; }
         return ORC_OK;
     }
     if (c->body_kind != ORC_BODY_FLAP) return ORC_ERR_ARG;
@@ -349,7 +354,7 @@ void orc_destroy(orc_sim *s) {
         free(L->kind); free(L->f); free(L->fs); free(L->rho); free(L->ux); free(L->uy);
         free(L->Fx); free(L->Fy);
     }
-    free(s->boxes); free(s->xb); free(s->yb); free(s->ds); free(s->hist);
+    free(s->boxes); free(s->xb); free(s->yb); free(s->ds); free(s->hist); free(s->hud);
     free(s->ftx); free(s->fty);
     free(s);
 }
@@ -379,6 +384,7 @@ int orc_create(const orc_case *c, orc_sim **out) {
     s->ds = malloc(sizeof(double) * (nm + 1));
     s->ftx = calloc(nm + 1, sizeof(double));
     s->fty = calloc(nm + 1, sizeof(double));
+    s->hud = calloc(2 * nm + 1, sizeof(double));
     if (nm) {
         memcpy(s->xb, c->xb, sizeof(double) * nm);
         memcpy(s->yb, c->yb, sizeof(double) * nm);
@@ -462,8 +468,12 @@ static void update_velocity(orc_sim *s, int l) {
     double *X = malloc(sizeof(double) * n * 6);
     double *Y = X + n, *X1 = X + 2 * n, *Y1 = X + 3 * n, *udx = X + 4 * n, *udy = X + 5 * n;
     orc_body_positions(&s->c, (double)s->k, X, Y);
-    orc_body_positions(&s->c, (double)(s->k + 1), X1, Y1);
-    for (int j = 0; j < n; ++j) { udx[j] = X1[j] - X[j]; udy[j] = Y1[j] - Y[j]; }
+    if (s->c.body_kind == ORC_BODY_HOST) {    /* desired velocity given with the markers */
+        for (int j = 0; j < n; ++j) { udx[j] = s->hud[j]; udy[j] = s->hud[n + j]; }
+    } else {
+        orc_body_positions(&s->c, (double)(s->k + 1), X1, Y1);
+        for (int j = 0; j < n; ++j) { udx[j] = X1[j] - X[j]; udy[j] = Y1[j] - Y[j]; }
+    }
 
     /* Moments of the stencil cells: rho and the uncorrected velocity. */
     double *rho = calloc(ncell, sizeof(double));
@@ -759,6 +769,18 @@ int orc_read_populations(const orc_sim *s, int level, double *f) {
 
 int orc_marker_forces(const orc_sim *s, double *fx, double *fy) {
     for (int j = 0; j < s->c.n_markers; ++j) { fx[j] = s->ftx[j]; fy[j] = s->fty[j]; }
+    return ORC_OK;
+}
+
+int orc_set_markers(orc_sim *s, int32_t n, const double *X, const double *Y, const double *udx,
+                    const double *udy) {
+    if (s->c.body_kind != ORC_BODY_HOST || n != s->c.n_markers) return ORC_ERR_ARG;
+    for (int j = 0; j < n; ++j) {
+        s->xb[j] = X[j];
+        s->yb[j] = Y[j];
+        s->hud[j] = udx[j];
+        s->hud[n + j] = udy[j];
+    }
     return ORC_OK;
 }
 

@@ -27,7 +27,7 @@ enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_TOPOLOGY = -2, ORC_ERR_MARKER = -7 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_WALL = 1, ORC_BC_INFLOW = 2, ORC_BC_OUTFLOW = 3,
        ORC_BC_SYMMETRY = 4 };
 enum { ORC_CF_HOMOGENEOUS = 0, ORC_CF_RESCALE = 1 };
-enum { ORC_BODY_NONE = -1, ORC_BODY_FIXED = 0, ORC_BODY_FLAP = 1 };
+enum { ORC_BODY_NONE = -1, ORC_BODY_FIXED = 0, ORC_BODY_FLAP = 1, ORC_BODY_HOST = 2 };
 enum { ORC_W = 0, ORC_E = 1, ORC_S = 2, ORC_N = 3 };
 
 typedef struct {
@@ -45,7 +45,8 @@ typedef struct {
     int32_t mdf_iters;       /* N_F                                              */
     int32_t body_kind;       /* ORC_BODY_*                                       */
     int32_t n_markers;
-    const double *xb, *yb;   /* body-frame marker coordinates, finest cells      */
+    const double *xb, *yb;   /* body-frame marker coordinates, finest cells
+                                (ORC_BODY_HOST: absolute positions)              */
     const double *ds;        /* marker arc lengths, finest cells                 */
     double bp[16];           /* kinematic parameters (see orc_body_positions)    */
 } orc_case;
@@ -67,6 +68,11 @@ int  orc_read_fields(const orc_sim *s, int level, double *rho, double *ux, doubl
 /* Raw populations of a level, dense [ny][nx][9]. */
 int  orc_read_populations(const orc_sim *s, int level, double *f);
 int  orc_marker_forces(const orc_sim *s, double *fx, double *fy);
+/* ORC_BODY_HOST: marker positions X, Y (finest cells) and desired velocities
+ * used by every finest substep from the next orc_step on (Sec. 2.2 takes
+ * both as given). */
+int  orc_set_markers(orc_sim *s, int32_t n, const double *X, const double *Y, const double *udx,
+                     const double *udy);
 int  orc_force_history(const orc_sim *s, int32_t cap, double *fx, double *fy, int32_t *n_out);
 /* out = {mass, momentum x, momentum y}, each summed over owned cells with
  * volume weight 4^-l; momentum is the bare first moment sum_i c_i f_i. */

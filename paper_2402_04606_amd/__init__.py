@@ -26,7 +26,7 @@ ERRORS = {-1: "ARG", -2: "TOPOLOGY", -3: "DEVICE", -4: "NOMEM", -5: "STATE", -6:
 # Every function include/sbt.h declares.
 ABI_SYMBOLS = [
     "sbt_plan", "sbt_create", "sbt_destroy", "sbt_level_blocks", "sbt_level_info", "sbt_init_fields",
-    "sbt_init_uniform", "sbt_set_body", "sbt_step", "sbt_synchronize", "sbt_read_fields",
+    "sbt_init_uniform", "sbt_set_body", "sbt_set_markers", "sbt_step", "sbt_synchronize", "sbt_read_fields",
     "sbt_read_fields_blocks", "sbt_read_marker_forces",
     "sbt_read_force_history", "sbt_diagnostics", "sbt_state_bytes", "sbt_read_state",
     "sbt_write_state", "sbt_set_option", "sbt_autotune", "sbt_profile", "sbt_updates_per_step",
@@ -83,6 +83,7 @@ def lib():
             "sbt_init_uniform": [vp, i32, C.c_double, C.c_double, C.c_double],
             "sbt_read_fields_blocks": [vp, i32, i32, d],
             "sbt_set_body": [vp, i32, C.POINTER(Body)],
+            "sbt_set_markers": [vp, i32, i32, d, d, d, d],
             "sbt_step": [vp, i32],
             "sbt_synchronize": [vp],
             "sbt_read_fields": [vp, i32, i32, d, d, d],
@@ -249,6 +250,12 @@ class Sim:
         for k, v in enumerate(body.params):
             b.p[k] = v
         _check(lib().sbt_set_body(self._h, c, C.byref(b)))
+
+    def set_markers(self, c, x, y, udx, udy):
+        """Caller-placed markers (body kind HOST): positions and desired
+        velocities for every finest substep from the next step on."""
+        x, y, udx, udy = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, udx, udy))
+        _check(lib().sbt_set_markers(self._h, c, len(x), _dp(x), _dp(y), _dp(udx), _dp(udy)))
 
     def step(self, n=1):
         _check(lib().sbt_step(self._h, int(n)))

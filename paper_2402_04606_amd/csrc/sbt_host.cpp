@@ -435,6 +435,7 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     D.hist = (double *)cv.take(sizeof(double) * 2 * C.hist_cap);
     D.kcount = (int64_t *)cv.take(sizeof(int64_t));
     D.pk = (int64_t *)cv.take(sizeof(int64_t));
+    D.hud = (double *)cv.take(sizeof(double) * 2 * (size_t)C.d.max_markers);
     const size_t nm = (size_t)C.d.max_markers, cc = (size_t)X.cell_cap;
     D.win = (IbmWindow *)cv.take(sizeof(IbmWindow) * 2);
     D.phdr = (int32_t *)cv.take(sizeof(int32_t) * 8);
@@ -1253,7 +1254,8 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
   if (!C.has_body) return fail(SBT_ERR_ARG, "case was created with max_markers = 0");
   if (!body || body->n <= 0 || body->n > C.d.max_markers) return fail(SBT_ERR_ARG, "marker count out of range");
   if (!body->xb || !body->yb || !body->ds) return fail(SBT_ERR_ARG, "null marker arrays");
-  if (body->kind != SBT_BODY_FIXED && body->kind != SBT_BODY_FLAP) return fail(SBT_ERR_ARG, "bad body kind");
+  if (body->kind != SBT_BODY_FIXED && body->kind != SBT_BODY_FLAP && body->kind != SBT_BODY_HOST)
+    return fail(SBT_ERR_ARG, "bad body kind");
   if (body->kind == SBT_BODY_FLAP && (body->p[6] == 0.0 || body->p[9] == 0.0))
     return fail(SBT_ERR_ARG, "flap period and chord must be nonzero");
   {
@@ -1275,6 +1277,7 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
   HIPCHK(hipMemcpy((void *)C.dev.xb, body->xb, sizeof(double) * N, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy((void *)C.dev.yb, body->yb, sizeof(double) * N, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy((void *)C.dev.ds, body->ds, sizeof(double) * N, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(C.dev.hud, 0, sizeof(double) * 2 * (size_t)C.d.max_markers));
   C.dev.body_kind = body->kind;
   C.dev.n_markers = body->n;
   std::memcpy(C.dev.bp, body->p, sizeof(body->p));
@@ -1291,6 +1294,25 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
       HIPCHK(hipMemcpy(Gr.d_body_cases, bc.data(), sizeof(int32_t) * bc.size(), hipMemcpyHostToDevice));
   }
   destroy_graphs(X);
+  return SBT_OK;
+}
+
+sbt_status sbt_set_markers(sbt_ctx *ctx, int32_t c, int32_t n, const double *x, const double *y,
+                           const double *udx, const double *udy) {
+  sbt_status st = check_case(ctx, c);
+  if (st) return st;
+  sbt_ctx &X = *ctx;
+  CaseHost &C = X.cs[c];
+  if (!C.has_body || C.dev.body_kind != SBT_BODY_HOST) return fail(SBT_ERR_ARG, "case has no caller-placed body");
+  if (n != C.n_markers) return fail(SBT_ERR_ARG, "marker count differs from the body's");
+  if (!x || !y || !udx || !udy) return fail(SBT_ERR_ARG, "null marker arrays");
+  HIPCHK(hipStreamSynchronize(X.stream));
+  const size_t N = (size_t)n, nm = (size_t)C.d.max_markers;
+  HIPCHK(hipMemcpy((void *)C.dev.xb, x, sizeof(double) * N, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy((void *)C.dev.yb, y, sizeof(double) * N, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(C.dev.hud, udx, sizeof(double) * N, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(C.dev.hud + nm, udy, sizeof(double) * N, hipMemcpyHostToDevice));
+  X.need_prep = true;  // the plan of the next substep was built from the old markers
   return SBT_OK;
 }
 

@@ -69,6 +69,7 @@ struct alignas(16) CaseDev {
   double *hist;                // [hist_cap][2]
   int64_t *kcount;             // finest substeps whose forcing loop has run
   int64_t *pk;                 // finest substeps whose IBM plan has been built
+  double *hud;                 // [2][nm_cap] desired velocity of caller-placed markers
   int32_t nm_cap;              // marker capacity of the plan buffers
   int32_t cell_cap;            // stencil-cell capacity of a plan
   IbmWindow *win;              // [2] window of the plan in buffer (k & 1)

@@ -673,7 +673,7 @@ typedef __attribute__((address_space(3))) void lds_void;
 // -1..16) just outside the block that the plane streams in from.  Slots
 // 0..63 are the four axis directions (16 each), 64..187 the four diagonals
 // (31 each: a column of 16, then a row of 15).
-__device__ __forceinline__ void halo_slot(int t, int &plane, int &hx, int &hy) {
+constexpr void halo_slot(int t, int &plane, int &hx, int &hy) {
   if (t < 64) {
     int s = t & 15;
     plane = 1 + (t >> 4);
@@ -699,23 +699,8 @@ struct HaloTable {
   uint32_t e[192];
   constexpr HaloTable() : e() {
     for (int t = 0; t < 192; ++t) {
-      int plane = 0, hx = 0, hy = 0, s = 0;
-      const int u = t < 188 ? t : 187;
-      if (u < 64) {
-        s = u & 15;
-        plane = 1 + (u >> 4);
-        hx = plane == 1 ? -1 : (plane == 3 ? 16 : s);
-        hy = plane == 2 ? -1 : (plane == 4 ? 16 : s);
-      } else {
-        const int d = (u - 64) / 31;
-        s = (u - 64) % 31;
-        plane = 5 + d;
-        const bool col = s < 16;
-        if (plane == 5) { hx = col ? -1 : s - 16; hy = col ? s - 1 : -1; }
-        else if (plane == 6) { hx = col ? 16 : s - 15; hy = col ? s - 1 : -1; }
-        else if (plane == 7) { hx = col ? 16 : s - 15; hy = col ? s + 1 : 16; }
-        else { hx = col ? -1 : s - 16; hy = col ? s + 1 : 16; }
-      }
+      int plane = 0, hx = 0, hy = 0;
+      halo_slot(t < 188 ? t : 187, plane, hx, hy);
       int nb = 0;
       if (hx < 0) nb = hy < 0 ? 6 : (hy > 15 ? 5 : 2);
       else if (hx > 15) nb = hy < 0 ? 7 : (hy > 15 ? 4 : 0);
@@ -1156,11 +1141,19 @@ __global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
   int i0 = 0, j0 = 0;
   int bx0 = 1 << 30, by0 = 1 << 30, bx1 = -(1 << 30), by1 = -(1 << 30);
   if (own) {
-    double X, Y, X1, Y1;
-    marker_position(cp, s_pose[0], tid, X, Y);
-    marker_position(cp, s_pose[1], tid, X1, Y1);
-    P.ud[tid] = X1 - X;
-    P.ud[nm + tid] = Y1 - Y;
+    double X, Y;
+    if (cp.body_kind == 2) {  // caller-placed markers with given desired velocity
+      X = cp.xb[tid];
+      Y = cp.yb[tid];
+      P.ud[tid] = cp.hud[tid];
+      P.ud[nm + tid] = cp.hud[nm + tid];
+    } else {
+      double X1, Y1;
+      marker_position(cp, s_pose[0], tid, X, Y);
+      marker_position(cp, s_pose[1], tid, X1, Y1);
+      P.ud[tid] = X1 - X;
+      P.ud[nm + tid] = Y1 - Y;
+    }
     i0 = tap0(X);
     j0 = tap0(Y);
     P.i0[tid] = i0;

@@ -410,3 +410,41 @@ def test_cylinder_table1_full_size(env):
     assert p["CD_mean"] * 0.97 <= cd[tail].mean() <= p["CD_mean"] * 1.15, cd[tail].mean()
     lo, hi = gold["literature_range"]["CL_rms"]
     assert lo <= c.std() <= 1.2 * hi, c.std()
+
+
+def test_host_markers_match_oracle(env):
+    """sbt_set_markers on the graph path against the oracle's caller-placed
+    body: the markers of a flapping motion (positions r(t_k), desired
+    velocity r(t_k+1) - r(t_k)) are set before every step.  The GPU's step n
+    runs the forcing loop of substep n (it collides one substep ahead; step
+    1 also runs substep 0), so the oracle is fed substep 0 with the markers
+    of substep 1 and substep k >= 1 with those of k; both must agree bit for
+    bit."""
+    P, O = env
+    U, chord = 0.05, 24.0
+    xb, yb, ds = W.ellipse_markers(chord / 2, chord / 16, 60)
+    flap = W.Body(W.BODY_FLAP, xb, yb, ds, W.flap_params(64.0, 64.0, chord, 30.0, 2.5 * np.pi, U))
+    wl = W.Workload(name="flap1", nx0=128, ny0=128, tau0=0.56, bc=(W.INFLOW, W.OUTFLOW, W.SYMMETRY, W.SYMMETRY),
+                    bc_u=((U, 0.0),) + ((0.0, 0.0),) * 3, body=flap, init=W.uniform_init(1.0, U, 0.0))
+
+    def markers(k):
+        X, Y = O.body_positions(wl, k)
+        X1, Y1 = O.body_positions(wl, k + 1)
+        return X, Y, X1 - X, Y1 - Y
+
+    n = 40
+    X0, Y0, _, _ = markers(0)
+    host = wl.replace(body=W.Body(W.BODY_HOST, X0, Y0, ds, [0.0] * 16))
+    o = O.OracleSim(host)
+    for k in range(n):
+        o.set_markers(*markers(max(k, 1)))
+        o.step(1)
+    g = P.Sim(host, "f64")
+    for k in range(1, n + 1):
+        g.set_markers(0, *markers(k))
+        g.step(1)
+    g.synchronize()
+    for a, b in zip(g.fields(0, 0), o.fields(0)):
+        assert np.array_equal(a, b, equal_nan=True)
+    fg, fo = g.force_history()[0], o.force_history()[0]
+    assert len(fg) == len(fo) == 40 and np.array_equal(fg, fo)

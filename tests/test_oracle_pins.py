@@ -405,3 +405,40 @@ def test_cylinder_shedding_matches_table1(orc):
     lo, hi = gold["literature_range"]["CL_rms"]
     assert lo <= c.std() <= hi, c.std()
     assert 0.9 * p["CD_mean"] <= cd[tail].mean() <= 1.25 * p["CD_mean"], cd[tail].mean()
+
+
+def _flap_single_level():
+    """A flapping ellipse on one uniform level (one finest substep per step)."""
+    U, chord = 0.05, 24.0
+    xb, yb, ds = W.ellipse_markers(chord / 2, chord / 16, 60)
+    body = W.Body(W.BODY_FLAP, xb, yb, ds, W.flap_params(64.0, 64.0, chord, 30.0, 2.5 * np.pi, U))
+    return W.Workload(name="flap1", nx0=128, ny0=128, tau0=0.56, bc=(W.INFLOW, W.OUTFLOW, W.SYMMETRY, W.SYMMETRY),
+                      bc_u=((U, 0.0),) + ((0.0, 0.0),) * 3, body=body, init=W.uniform_init(1.0, U, 0.0))
+
+
+def host_driven(wl, orc_sim, steps, positions):
+    """Drive a HOST body with the positions of wl's prescribed body: before
+    each step, markers at r(t_k) and desired velocity r(t_k+1) - r(t_k)."""
+    for k in range(steps):
+        X, Y = positions(k)
+        X1, Y1 = positions(k + 1)
+        orc_sim.set_markers(X, Y, X1 - X, Y1 - Y)
+        orc_sim.step(1)
+
+
+def test_host_markers_reproduce_prescribed_motion(orc):
+    """Sec. 2.2 takes marker positions and desired velocities as given: a
+    caller-placed body fed the positions of a prescribed flapping body, one
+    substep at a time, reproduces that body's run bit for bit."""
+    wl = _flap_single_level()
+    ref = orc.OracleSim(wl)
+    ref.step(40)
+    b = wl.body
+    host = wl.replace(body=W.Body(W.BODY_HOST, np.zeros(len(b.xb)), np.zeros(len(b.xb)), b.ds, [0.0] * 16))
+    h = orc.OracleSim(host)
+    pos = lambda k: orc.body_positions(wl, k)
+    host_driven(wl, h, 40, pos)
+    for l in range(wl.n_levels):
+        for a, c in zip(ref.fields(l), h.fields(l)):
+            assert np.array_equal(a, c, equal_nan=True)
+    assert np.array_equal(ref.force_history()[0], h.force_history()[0])

@@ -29,12 +29,12 @@ import numpy as np
 PERIODIC, WALL, INFLOW, OUTFLOW, SYMMETRY = 0, 1, 2, 3, 4
 W, E, S, N = 0, 1, 2, 3
 CF_HOMOGENEOUS, CF_RESCALE = 0, 1
-BODY_FIXED, BODY_FLAP = 0, 1
+BODY_FIXED, BODY_FLAP, BODY_HOST = 0, 1, 2
 
 
 @dataclasses.dataclass
 class Body:
-    kind: int                      # BODY_FIXED or BODY_FLAP
+    kind: int                      # BODY_FIXED, BODY_FLAP or BODY_HOST (xb, yb absolute)
     xb: np.ndarray                 # body-frame marker x (finest cells)
     yb: np.ndarray
     ds: np.ndarray                 # arc length per marker (finest cells)
