@@ -448,3 +448,48 @@ def test_host_markers_match_oracle(env):
         assert np.array_equal(a, b, equal_nan=True)
     fg, fo = g.force_history()[0], o.force_history()[0]
     assert len(fg) == len(fo) == 40 and np.array_equal(fg, fo)
+
+
+def test_autotune_keeps_state_and_results(env, tmp_path):
+    """sbt_autotune times block-run lengths on the live context and restores
+    its state: stepping after tuning gives the same bits as an untuned run."""
+    P, _ = env
+    wl = W.small_refined_flap()
+    a = P.Sim(wl, "f32")
+    a.step(2)
+    a.autotune(steps=1, cache_path=str(tmp_path / "tune.json"))
+    a.step(3)
+    b = P.Sim(wl, "f32")
+    b.step(5)
+    for l in range(wl.n_levels):
+        assert np.array_equal(a.fields_blocks(0, l), b.fields_blocks(0, l), equal_nan=True)
+    assert np.array_equal(a.force_history()[0], b.force_history()[0])
+    c = P.Sim(wl, "f32")              # the cached choice is read back, no trials
+    c.autotune(steps=1, cache_path=str(tmp_path / "tune.json"))
+    c.step(5)
+    for l in range(wl.n_levels):
+        assert np.array_equal(c.fields_blocks(0, l), b.fields_blocks(0, l), equal_nan=True)
+
+
+def test_single_marker_body(env):
+    """Degenerate body: one marker (one lane of the forcing workgroup, one
+    4x4 stencil) in a uniform stream, against the oracle."""
+    U = 0.05
+    body = W.Body(W.BODY_FIXED, np.array([0.0]), np.array([0.0]), np.array([1.0]), [40.3, 31.7] + [0.0] * 14)
+    wl = W.Workload(name="one_marker", nx0=96, ny0=64, tau0=0.6, bc=(W.INFLOW, W.OUTFLOW, W.SYMMETRY, W.SYMMETRY),
+                    bc_u=((U, 0.0),) + ((0.0, 0.0),) * 3, body=body, init=W.uniform_init(1.0, U, 0.0))
+    g, o = run_pair(env, wl, 50)
+    compare_levels(g, o, wl, TOL64)
+    fg, fo = g.force_history()[0], o.force_history()[0]
+    assert np.abs(fg - fo).max() <= TOL64 * np.abs(fo).max()
+    assert fo[-1] > 0          # the marker drags the stream
+
+
+def test_set_markers_rejects_other_bodies(env):
+    P, _ = env
+    wl = W.small_cylinder()
+    g = P.Sim(wl, "f64")
+    n = len(wl.body.xb)
+    with pytest.raises(P.SbtError) as e:
+        g.set_markers(0, np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n))
+    assert e.value.code == -1
