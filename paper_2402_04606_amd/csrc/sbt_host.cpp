@@ -268,8 +268,6 @@ struct sbt_ctx {
   std::vector<CaseHost> cs;
   std::vector<Pool> pools;         // pool of group g, virtual level v at g * V + v
   std::vector<GroupInfo> groups;
-  std::vector<hipStream_t> side_streams;
-  std::vector<hipEvent_t> fork_events;
   CaseDev *d_cases = nullptr;
   int n_bodies = 0;
   int32_t *d_err = nullptr;
@@ -282,14 +280,12 @@ struct sbt_ctx {
   std::vector<int> kpw_level;   // interior blocks per workgroup per virtual level (0: automatic)
   int lds_window = 0;           // IBM window cells whose plan-builder counters fit in LDS
   int cell_cap = 0;             // stencil cells per IBM plan (fits the forcing kernel's LDS)
+  int plan_bufs = 1;            // IBM plan buffers per body: the finest substeps of a step
   int max_body_markers = 0;     // largest body set so far (LDS table stride)
-  bool need_prep = true;        // the plan of the next finest substep must be built first
   int64_t k_host = 0;           // finest substeps issued (every body's forcing-loop counter)
 
-  std::vector<hipStream_t> prep_streams;
-  std::vector<hipEvent_t> ev_lvl, ev_prep;
   std::vector<Phase> step_phases;
-  std::vector<hipGraphExec_t> graph;   // [group * 2 + parity]
+  std::vector<hipGraphExec_t> graph;   // [lattice parity + 2 * plan buffer]
   hipEvent_t step_event = nullptr;
   bool graph_dirty = true;
   size_t bytes_used = 0;
@@ -324,6 +320,8 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
       }
     X.V = std::max(X.V, C.F.m);
   }
+  // one IBM plan buffer per finest substep of a step
+  X.plan_bufs = 1 << (X.V - 1);
   const size_t s = storage_bytes(X.storage);
   // One launch chain holds every case: each phase is one launch over the
   // blocks of all cases (the group tables keep the case-to-chain map).
@@ -434,20 +432,20 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     D.ftot = (double *)cv.take(sizeof(double) * 4 * N);
     D.hist = (double *)cv.take(sizeof(double) * 2 * C.hist_cap);
     D.kcount = (int64_t *)cv.take(sizeof(int64_t));
-    D.pk = (int64_t *)cv.take(sizeof(int64_t));
     D.hud = (double *)cv.take(sizeof(double) * 2 * (size_t)C.d.max_markers);
     const size_t nm = (size_t)C.d.max_markers, cc = (size_t)X.cell_cap;
-    D.win = (IbmWindow *)cv.take(sizeof(IbmWindow) * 2);
-    D.phdr = (int32_t *)cv.take(sizeof(int32_t) * 8);
-    D.wF = (double *)cv.take(sizeof(double) * 4 * C.win_cap);
-    D.wCnt = (int32_t *)cv.take(sizeof(int32_t) * C.win_cap);
-    D.wIdx = (int32_t *)cv.take(sizeof(int32_t) * C.win_cap);
-    D.p_ij = (int32_t *)cv.take(sizeof(int32_t) * 4 * nm);
-    D.p_w = (double *)cv.take(sizeof(double) * 16 * nm);
-    D.p_ud = (double *)cv.take(sizeof(double) * 4 * nm);
-    D.p_tap = (uint16_t *)cv.take(sizeof(uint16_t) * 32 * nm);
-    D.p_cell = (int32_t *)cv.take(sizeof(int32_t) * 16 * cc);
-    D.p_list = (uint16_t *)cv.take(sizeof(uint16_t) * 32 * nm);
+    const size_t B = (size_t)X.plan_bufs;
+    D.win = (IbmWindow *)cv.take(sizeof(IbmWindow) * B);
+    D.phdr = (int32_t *)cv.take(sizeof(int32_t) * 4 * B);
+    D.wF = (double *)cv.take(sizeof(double) * 2 * B * C.win_cap);
+    D.wCnt = (int32_t *)cv.take(sizeof(int32_t) * B * C.win_cap);
+    D.wIdx = (int32_t *)cv.take(sizeof(int32_t) * B * C.win_cap);
+    D.p_ij = (int32_t *)cv.take(sizeof(int32_t) * 2 * B * nm);
+    D.p_w = (double *)cv.take(sizeof(double) * 8 * B * nm);
+    D.p_ud = (double *)cv.take(sizeof(double) * 2 * B * nm);
+    D.p_tap = (uint16_t *)cv.take(sizeof(uint16_t) * 16 * B * nm);
+    D.p_cell = (int32_t *)cv.take(sizeof(int32_t) * 8 * B * cc);
+    D.p_list = (uint16_t *)cv.take(sizeof(uint16_t) * 16 * B * nm);
     D.bmap = (const int32_t *)cv.take(sizeof(int32_t) * (size_t)D.bm_w * D.bm_h);
   }
   return SBT_OK;
@@ -583,6 +581,7 @@ void build_tables(sbt_ctx &X) {
     D.win_cap = C.win_cap;
     D.nm_cap = C.d.max_markers;
     D.cell_cap = X.cell_cap;
+    D.plan_mask = X.plan_bufs - 1;
   }
   // launch lists: interior blocks take the LDS-staged kernel
   for (auto &P : X.pools) {
@@ -677,7 +676,7 @@ sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s
   a.mode = mode;
   a.xcd_remap = X.xcd;
   // the finest level collides with the force of the forcing loop just run
-  a.ibm_parity = (v == X.V - 1 && X.n_bodies > 0 && X.k_host > 0) ? (int)((X.k_host - 1) & 1) : -1;
+  a.ibm_parity = (v == X.V - 1 && X.n_bodies > 0 && X.k_host > 0) ? (int)((X.k_host - 1) & (X.plan_bufs - 1)) : -1;
   a.err = X.d_err;
   auto timed = [&](bool fast, auto &&launch) -> sbt_status {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -729,7 +728,7 @@ sbt_status launch_mdf(sbt_ctx &X, int g, bool first, hipStream_t s) {
   a.err = X.d_err;
   a.max_markers = X.max_body_markers;
   a.cell_cap = X.cell_cap;
-  a.parity = (int)(X.k_host & 1);
+  a.parity = (int)(X.k_host & (X.plan_bufs - 1));
   ++X.k_host;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (X.profiling) {
@@ -745,37 +744,29 @@ sbt_status launch_mdf(sbt_ctx &X, int g, bool first, hipStream_t s) {
   return SBT_OK;
 }
 
-// Build the IBM plan of the next finest substep of group g's bodies
-// (from_kcount: of the substep the forcing loop runs next, after a restart).
-sbt_status launch_prep(sbt_ctx &X, int g, bool from_kcount, hipStream_t s) {
+int forcing_phases(const sbt_ctx &X) {
+  int n = 0;
+  for (const Phase &ph : X.step_phases) n += ph.type == PH_MDF;
+  return n;
+}
+
+// Build the IBM plans of group g's bodies for the next n_plans finest
+// substeps (those of kcount .. kcount + n_plans - 1), one workgroup per body
+// and substep.  The plan of substep k goes to buffer k & (plan_bufs - 1);
+// every earlier reader of those buffers precedes this launch in stream order.
+sbt_status launch_prep(sbt_ctx &X, int g, int n_plans, hipStream_t s) {
   GroupInfo &Gr = X.groups[g];
   if (Gr.n_bodies == 0) return SBT_OK;
+  if (n_plans > X.plan_bufs) return fail(SBT_ERR_STATE, "more IBM plans than plan buffers");
   IbmArgs a;
   a.cases = X.d_cases;
   a.body_cases = Gr.d_body_cases;
   a.max_markers = X.max_body_markers;
   a.cell_cap = X.cell_cap;
   a.lds_window = X.lds_window;
-  a.from_kcount = from_kcount ? 1 : 0;
-  HIPCHK(sbt_launch_ibm_prep(&a, Gr.n_bodies, s));
-  return SBT_OK;
-}
-
-// The forcing loop of finest substep k needs its plan; the plan of k+1 is
-// built right before it (in stream order after the collision of k-1, the
-// last reader of that plan buffer).
-sbt_status launch_forcing(sbt_ctx &X, int g, bool first, hipStream_t s) {
-  sbt_status st = launch_prep(X, g, false, s);
-  if (st) return st;
-  return launch_mdf(X, g, first, s);
-}
-
-sbt_status initial_plans(sbt_ctx &X, hipStream_t s) {
-  for (int g = 0; g < X.G; ++g) {
-    sbt_status st = launch_prep(X, g, true, s);
-    if (st) return st;
-  }
-  X.need_prep = false;
+  a.n_bodies = Gr.n_bodies;
+  a.n_plans = n_plans;
+  HIPCHK(sbt_launch_ibm_prep(&a, s));
   return SBT_OK;
 }
 
@@ -783,12 +774,12 @@ sbt_status initial_plans(sbt_ctx &X, hipStream_t s) {
 // first CollisionStep of every level), finest first so that each coarse
 // level explodes into its finer level's current lattice.
 sbt_status run_prologue(sbt_ctx &X, hipStream_t s) {
-  sbt_status st = initial_plans(X, s);
-  if (st) return st;
+  sbt_status st = SBT_OK;
   for (int g = 0; g < X.G; ++g)
     for (int v = X.V - 1; v >= 0; --v) {
       if (v == X.V - 1) {
-        st = launch_forcing(X, g, true, s);
+        st = launch_prep(X, g, 1, s);
+        if (!st) st = launch_mdf(X, g, true, s);
         if (st) return st;
       }
       st = launch_level(X, g, v, 1, MODE_LOCAL, s);
@@ -798,59 +789,19 @@ sbt_status run_prologue(sbt_ctx &X, hipStream_t s) {
   return SBT_OK;
 }
 
+// One step of group g: the IBM plans of all its finest substeps (they depend
+// on the marker positions only), then the phases in order.
 sbt_status run_group_step(sbt_ctx &X, int g, hipStream_t s) {
+  sbt_status st = launch_prep(X, g, forcing_phases(X), s);
+  if (st) return st;
   for (const Phase &ph : X.step_phases) {
-    sbt_status st = ph.type == PH_MDF ? launch_forcing(X, g, false, s) : launch_level(X, g, ph.v, ph.p, 0, s);
+    st = ph.type == PH_MDF ? launch_mdf(X, g, false, s) : launch_level(X, g, ph.v, ph.p, 0, s);
     if (st) return st;
-  }
-  return SBT_OK;
-}
-
-// Group g's step inside a graph capture: launches on stream s, the plan
-// builder on its own stream r, so the plan of substep k+1 is built while
-// the forcing loop and the collision of substep k run.  ev_lvl[0] forks r;
-// ev_lvl[i + 1] follows the i-th finest collision, ev_prep[i] the i-th plan.
-// (The forcing loop itself stays on the chain: its workgroups each need a
-// whole CU, so it does not overlap the bandwidth-bound collision usefully.)
-sbt_status capture_group_step(sbt_ctx &X, int g, hipStream_t s, hipStream_t r, const hipEvent_t *ev_lvl,
-                              const hipEvent_t *ev_prep, int n_mdf) {
-  HIPCHK(hipEventRecord(ev_lvl[0], s));
-  HIPCHK(hipStreamWaitEvent(r, ev_lvl[0], 0));
-  int im = 0, il = 0;
-  for (const Phase &ph : X.step_phases) {
-    sbt_status st = SBT_OK;
-    if (ph.type == PH_MDF) {
-      if (im >= n_mdf) return fail(SBT_ERR_STATE, "phase list has more forcing phases than planned");
-      st = launch_prep(X, g, false, r);
-      if (st) return st;
-      HIPCHK(hipEventRecord(ev_prep[im], r));
-      if (im > 0) HIPCHK(hipStreamWaitEvent(s, ev_prep[im - 1], 0));
-      st = launch_mdf(X, g, false, s);
-      ++im;
-    } else {
-      st = launch_level(X, g, ph.v, ph.p, 0, s);
-      if (!st && ph.v == X.V - 1 && il < n_mdf) {
-        HIPCHK(hipEventRecord(ev_lvl[il + 1], s));
-        HIPCHK(hipStreamWaitEvent(r, ev_lvl[il + 1], 0));
-        ++il;
-      }
-    }
-    if (st) return st;
-  }
-  // join: the step ends when its last plan is built
-  if (im > 0) HIPCHK(hipStreamWaitEvent(s, ev_prep[im - 1], 0));
-  else {
-    HIPCHK(hipEventRecord(ev_lvl[n_mdf], r));
-    HIPCHK(hipStreamWaitEvent(s, ev_lvl[n_mdf], 0));
   }
   return SBT_OK;
 }
 
 sbt_status run_step_eager(sbt_ctx &X, hipStream_t s) {
-  if (X.need_prep) {
-    sbt_status st = initial_plans(X, s);
-    if (st) return st;
-  }
   for (int g = 0; g < X.G; ++g) {
     sbt_status st = run_group_step(X, g, s);
     if (st) return st;
@@ -867,80 +818,32 @@ void destroy_graphs(sbt_ctx &X) {
   X.graph_dirty = true;
 }
 
-int forcing_phases(const sbt_ctx &X) {
-  int n = 0;
-  for (const Phase &ph : X.step_phases) n += ph.type == PH_MDF;
-  return n;
-}
-
-sbt_status ensure_side_streams(sbt_ctx &X) {
+sbt_status ensure_capture_stream(sbt_ctx &X) {
   if (!X.cap_stream) HIPCHK(hipStreamCreateWithFlags(&X.cap_stream, hipStreamNonBlocking));
-  auto new_stream = [](std::vector<hipStream_t> &v) -> hipError_t {
-    hipStream_t st;
-    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-    if (e == hipSuccess) v.push_back(st);
-    return e;
-  };
-  auto new_event = [](std::vector<hipEvent_t> &v) -> hipError_t {
-    hipEvent_t ev;
-    hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-    if (e == hipSuccess) v.push_back(ev);
-    return e;
-  };
-  while ((int)X.side_streams.size() < X.G) {
-    HIPCHK(new_stream(X.side_streams));
-    HIPCHK(new_event(X.fork_events));
-  }
-  while ((int)X.prep_streams.size() < X.G) HIPCHK(new_stream(X.prep_streams));
-  const int nm = forcing_phases(X);
-  while ((int)X.ev_lvl.size() < X.G * (nm + 1)) HIPCHK(new_event(X.ev_lvl));
-  while ((int)X.ev_prep.size() < X.G * std::max(1, nm)) HIPCHK(new_event(X.ev_prep));
-
-  if (X.graph.size() != 4) X.graph.assign(4, nullptr);
+  if ((int)X.graph.size() != 2 * X.plan_bufs) X.graph.assign(2 * X.plan_bufs, nullptr);
   return SBT_OK;
 }
 
-// One step as a graph: each case group's launch chain is a branch of its
-// own (forked from and joined back to the capture stream), so one group's
-// latency-bound IBM launches overlap other groups' level launches; within a
-// group the plan builder runs on a branch beside the chain.
-sbt_status capture_graph(sbt_ctx &X, int parity) {
-  sbt_status st0 = ensure_side_streams(X);
-  if (st0) return st0;
-  const int nm = forcing_phases(X);
+// One step as a graph: the eager launch list captured on one stream (the
+// launches depend on each other in order, so the graph is a chain).
+sbt_status capture_graph(sbt_ctx &X, int key) {
+  sbt_status st = ensure_capture_stream(X);
+  if (st) return st;
   std::vector<int> saved(X.pools.size());
   for (size_t i = 0; i < X.pools.size(); ++i) saved[i] = X.pools[i].cur;
   const int64_t saved_k = X.k_host;
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(X.cap_stream, hipStreamCaptureModeThreadLocal));
-  sbt_status st = SBT_OK;
-  hipError_t e = hipSuccess;
-  if (X.G > 1) {
-    e = hipEventRecord(X.fork_events[0], X.cap_stream);
-    for (int k = 1; k < X.G && e == hipSuccess; ++k) e = hipStreamWaitEvent(X.side_streams[k], X.fork_events[0], 0);
-  }
-  for (int k = 0; k < X.G && !st && e == hipSuccess; ++k) {
-    hipStream_t sk = k == 0 ? X.cap_stream : X.side_streams[k];
-    if (X.groups[k].n_bodies > 0)
-      st = capture_group_step(X, k, sk, X.prep_streams[k], &X.ev_lvl[(size_t)k * (nm + 1)],
-                              &X.ev_prep[(size_t)k * std::max(1, nm)], nm);
-    else
-      st = run_group_step(X, k, sk);
-  }
-  for (int k = 1; k < X.G && !st && e == hipSuccess; ++k) {
-    e = hipEventRecord(X.fork_events[k], X.side_streams[k]);
-    if (e == hipSuccess) e = hipStreamWaitEvent(X.cap_stream, X.fork_events[k], 0);
-  }
-  hipError_t e2 = hipStreamEndCapture(X.cap_stream, &g);
+  for (int k = 0; k < X.G && !st; ++k) st = run_group_step(X, k, X.cap_stream);
+  hipError_t e = hipStreamEndCapture(X.cap_stream, &g);
   for (size_t i = 0; i < X.pools.size(); ++i) X.pools[i].cur = saved[i];
   X.k_host = saved_k;
   if (st) {
     if (g) (void)hipGraphDestroy(g);
     return st;
   }
-  if (e != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph fork/join: ") + hipGetErrorString(e));
-  if (e2 != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e2));
-  e = hipGraphInstantiate(&X.graph[parity], g, nullptr, nullptr, 0);
+  if (e != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&X.graph[key], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
   return SBT_OK;
@@ -1017,11 +920,9 @@ sbt_status reset_counters(sbt_ctx &X) {
   for (auto &C : X.cs) {
     if (!C.has_body) continue;
     HIPCHK(hipMemsetAsync(C.dev.kcount, 0, sizeof(int64_t), X.stream));
-    HIPCHK(hipMemsetAsync(C.dev.pk, 0, sizeof(int64_t), X.stream));
-    HIPCHK(hipMemsetAsync(C.dev.win, 0, 2 * sizeof(IbmWindow), X.stream));
+    HIPCHK(hipMemsetAsync(C.dev.win, 0, X.plan_bufs * sizeof(IbmWindow), X.stream));
   }
   X.post = false;
-  X.need_prep = true;
   X.k_host = 0;
   for (auto &P : X.pools) P.cur = 0;
   destroy_graphs(X);
@@ -1126,12 +1027,6 @@ sbt_status sbt_destroy(sbt_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   destroy_graphs(*ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-  for (auto st : ctx->side_streams) (void)hipStreamDestroy(st);
-  for (auto st : ctx->prep_streams) (void)hipStreamDestroy(st);
-
-  for (auto ev : ctx->fork_events) (void)hipEventDestroy(ev);
-  for (auto ev : ctx->ev_lvl) (void)hipEventDestroy(ev);
-  for (auto ev : ctx->ev_prep) (void)hipEventDestroy(ev);
   if (ctx->step_event) (void)hipEventDestroy(ctx->step_event);
   delete ctx;
   return SBT_OK;
@@ -1268,8 +1163,11 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
     if (mdf + 1024 > (size_t)lds_max || prep + 1024 > (size_t)lds_max)
       return fail(SBT_ERR_ARG, "too many markers for one workgroup's LDS (" + std::to_string(lds_max) + " bytes)");
     // the plan builder keeps window counters in LDS with what is left
-    // (global memory beyond that)
-    X.lds_window = (int)std::min<size_t>(16384, ((size_t)lds_max - 1024 - prep) / (2 * sizeof(int32_t)));
+    // (global memory beyond that), within half the CU's LDS when its tables
+    // leave room, so that two plan builders share a CU
+    const size_t half = (size_t)lds_max / 2 - 1024;
+    const size_t budget = prep + 4096 * 4 <= half ? half : (size_t)lds_max - 1024;
+    X.lds_window = (int)std::min<size_t>(32768, (budget - prep) / 4 - 1);
     X.max_body_markers = nmax;
   }
   HIPCHK(hipStreamSynchronize(X.stream));
@@ -1312,7 +1210,6 @@ sbt_status sbt_set_markers(sbt_ctx *ctx, int32_t c, int32_t n, const double *x, 
   HIPCHK(hipMemcpy((void *)C.dev.yb, y, sizeof(double) * N, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(C.dev.hud, udx, sizeof(double) * N, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(C.dev.hud + nm, udy, sizeof(double) * N, hipMemcpyHostToDevice));
-  X.need_prep = true;  // the plan of the next substep was built from the old markers
   return SBT_OK;
 }
 
@@ -1324,17 +1221,14 @@ sbt_status sbt_step(sbt_ctx *ctx, int32_t n) {
   if (!X.post) {
     sbt_status st = run_prologue(X, X.stream);
     if (st) return st;
-  } else if (X.need_prep) {
-    sbt_status st = initial_plans(X, X.stream);
-    if (st) return st;
   }
   for (int t = 0; t < n; ++t) {
     if (X.use_graph && !X.profiling) {
-      sbt_status st = ensure_side_streams(X);
+      sbt_status st = ensure_capture_stream(X);
       if (st) return st;
-      // a graph bakes in the lattice parities and the IBM plan parities of
+      // a graph bakes in the lattice parities and the IBM plan buffers of
       // its substeps
-      const int par = X.pools[0].cur + 2 * (int)(X.k_host & 1);
+      const int par = X.pools[0].cur + 2 * (int)(X.k_host & (X.plan_bufs - 1));
       if (!X.graph[par]) {
         st = capture_graph(X, par);
         if (st) return st;
@@ -1578,7 +1472,6 @@ sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes) {
     p += nb;
   }
   X.post = h.post != 0;
-  X.need_prep = true;
   for (size_t i = 0; i < X.pools.size(); ++i) X.pools[i].cur = curs[i];
   destroy_graphs(X);
   return SBT_OK;

@@ -68,20 +68,20 @@ struct alignas(16) CaseDev {
   double *ftot;                // [2 slots][2][n]: total marker force, slot = substep parity
   double *hist;                // [hist_cap][2]
   int64_t *kcount;             // finest substeps whose forcing loop has run
-  int64_t *pk;                 // finest substeps whose IBM plan has been built
   double *hud;                 // [2][nm_cap] desired velocity of caller-placed markers
   int32_t nm_cap;              // marker capacity of the plan buffers
   int32_t cell_cap;            // stencil-cell capacity of a plan
-  IbmWindow *win;              // [2] window of the plan in buffer (k & 1)
-  int32_t *phdr;               // [2][4] plan header: stamp (low 32 bits of k), stencil cells, status, 0
-  double *wF;                  // [2][2][win_cap] force density in the window, per plan buffer
-  int32_t *wCnt, *wIdx;        // [win_cap] plan builder's counters / compact index beyond LDS
-  int32_t *p_ij;               // [2][2][nm_cap] first tap of each marker (x, y)
-  double *p_w;                 // [2][8][nm_cap] Peskin weights of the 4 x and 4 y taps
-  double *p_ud;                // [2][2][nm_cap] desired marker velocity
-  uint16_t *p_tap;             // [2][16][nm_cap] stencil cell of each tap
-  int32_t *p_cell;             // [2][cell_cap][8] window index, 4 source blocks, list start, count, 0
-  uint16_t *p_list;            // [2][16 nm_cap] markers over each stencil cell, ascending
+  int32_t plan_mask;           // plan buffers - 1 (a power of two >= the finest substeps of a step)
+  IbmWindow *win;              // [plan_mask + 1] window of the plan in buffer k & plan_mask
+  int32_t *phdr;               // [plan_mask + 1][4] plan header: stamp (low 32 bits of k), stencil cells, status, 0
+  double *wF;                  // [plan_mask + 1][2][win_cap] force density in the window, per plan buffer
+  int32_t *wCnt, *wIdx;        // [plan_mask + 1][win_cap] plan builder's counters / compact index beyond LDS
+  int32_t *p_ij;               // [plan_mask + 1][2][nm_cap] first tap of each marker (x, y)
+  double *p_w;                 // [plan_mask + 1][8][nm_cap] Peskin weights of the 4 x and 4 y taps
+  double *p_ud;                // [plan_mask + 1][2][nm_cap] desired marker velocity
+  uint16_t *p_tap;             // [plan_mask + 1][16][nm_cap] stencil cell of each tap
+  int32_t *p_cell;             // [plan_mask + 1][cell_cap][8] window index, 4 source blocks, list start, count, 0
+  uint16_t *p_list;            // [plan_mask + 1][16 nm_cap] markers over each stencil cell, ascending
   const int32_t *bmap;         // finest-level block map -> pool index (-1 outside)
 };
 
@@ -119,7 +119,7 @@ struct MdfArgs {
   int32_t first;               // 1: local read (initial pre-collision state)
   int32_t max_markers;         // LDS marker-table stride (>= every body's markers)
   int32_t cell_cap;            // LDS stencil-cell table size (>= every plan's cells)
-  int32_t parity;              // plan buffer of this substep (its index & 1)
+  int32_t parity;              // plan buffer of this substep (its index & plan_mask)
   int32_t *err;
 };
 
@@ -129,7 +129,8 @@ struct IbmArgs {
   int32_t max_markers;         // LDS list stride (>= every body's markers)
   int32_t cell_cap;            // stencil-cell capacity
   int32_t lds_window;          // window cells whose counters fit in LDS
-  int32_t from_kcount;         // 1: plan substep kcount (restart), else pk
+  int32_t n_bodies;            // bodies per plan: workgroup w builds plan w / n_bodies of body w % n_bodies
+  int32_t n_plans;             // plans per body: substeps kcount .. kcount + n_plans - 1
 };
 
 // Level launch modes: LOCAL = read the cell's own populations (initial
@@ -151,7 +152,7 @@ hipError_t sbt_launch_level(int storage, int tile, const sbt::LevelArgs *a, hipS
 // next to a finer level or a domain edge; then n_band packed halo-band cells.
 hipError_t sbt_launch_level_tile(int storage, const sbt::LevelArgs *a, hipStream_t s);
 // IBM plan of the next finest substep of every body, one workgroup each.
-hipError_t sbt_launch_ibm_prep(const sbt::IbmArgs *a, int n_bodies, hipStream_t s);
+hipError_t sbt_launch_ibm_prep(const sbt::IbmArgs *a, hipStream_t s);
 // Multi-direct forcing loop of the current finest substep on its plan.
 hipError_t sbt_launch_mdf(int storage, const sbt::MdfArgs *a, int n_bodies, hipStream_t s);
 size_t sbt_mdf_lds_bytes(int max_markers, int cell_cap);

@@ -269,7 +269,7 @@ struct Collide {
 template <typename C>
 __device__ __forceinline__ void add_ibm_force(const CaseDev &cp, int parity, int ox, int oy, int x, int y, C &Fx,
                                               C &Fy) {
-  const int b = parity >= 0 ? parity : __builtin_amdgcn_readfirstlane((int)((*cp.kcount - 1) & 1));
+  const int b = parity >= 0 ? parity : __builtin_amdgcn_readfirstlane((int)((*cp.kcount - 1) & cp.plan_mask));
   const IbmWindow w = cp.win[b];
   const int x0 = __builtin_amdgcn_readfirstlane(w.x0), y0 = __builtin_amdgcn_readfirstlane(w.y0);
   const int ww = __builtin_amdgcn_readfirstlane(w.w), wh = __builtin_amdgcn_readfirstlane(w.h);
@@ -992,8 +992,9 @@ __global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a, const Case
 //    (Eq. (11)) and spreading (Eq. (15)), with the moments and the marker
 //    tables in LDS and each stencil cell's force in its owner's registers,
 //    then the force density for the collision and the body force (Eq. (16)).
-// Plans are double-buffered by the parity of k, and so are the window and
-// its force density that the collision of substep k reads.
+// Plans live in plan_mask + 1 buffers (index k & plan_mask), and so do the
+// window and its force density that the collision of substep k reads: one
+// launch builds the plans of all finest substeps of a coarse step.
 constexpr int MDF_THREADS = kMaxMarkers;
 
 __device__ __forceinline__ double peskin(double r) {
@@ -1080,7 +1081,7 @@ __device__ __forceinline__ void sort_net(int (&v)[N]) {
 struct PlanView {
   int32_t *i0, *j0;      // first tap of each marker
   double *w;             // [8][nm]: wx[0..3], wy[0..3]
-  double *ud;            // [2][nm]: desired velocity
+  double *ud;            // [2][nm]: desired velocity (x, y)
   uint16_t *tap;         // [16][nm]: stencil cell of each tap (y outer, x inner)
   int32_t *cell;         // [cell_cap][8]: window index, 4 source blocks, csr start, count, 0
   uint16_t *list;        // [16 nm]: contributors of the stencil cells, CSR
@@ -1104,9 +1105,10 @@ __device__ __forceinline__ PlanView plan_view(const CaseDev &cp, int b) {
 // Plan builder.  LDS: window counters and compact indices (when the window
 // fits), the stencil cells' window indices and CSR starts, the contributor
 // lists while they are filled.
-__global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
+__global__ __launch_bounds__(MDF_THREADS, 8) void ibm_prep_kernel(IbmArgs a) {
 #pragma clang fp contract(off)
-  const int ci = a.body_cases[blockIdx.x];
+  const int ci = a.body_cases[blockIdx.x % a.n_bodies];
+  const int64_t j = blockIdx.x / a.n_bodies;  // plan of the launch's j-th substep
   const CaseDev &cp = a.cases[ci];
   const int n = cp.n_markers;
   const int nm = cp.nm_cap, cap = cp.cell_cap;
@@ -1116,14 +1118,17 @@ __global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
   int *s_cells = lds_i;                  // [CCa] window index of stencil cell q
   int *s_start = s_cells + CCa;          // [CCa] CSR start of stencil cell q
   uint16_t *s_list = reinterpret_cast<uint16_t *>(s_start + CCa);  // [16 NMa]
-  int *s_cnt = reinterpret_cast<int *>(s_list + 16 * NMa);          // [lds_window]
-  int *s_idx = s_cnt + a.lds_window;                                     // [lds_window]
+  // window cells' contributor counters, two 16-bit counters per word, and
+  // their compact indices (16 bits)
+  uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_list + 16 * NMa);  // [(lds_window + 1) / 2]
+  uint16_t *s_idx = reinterpret_cast<uint16_t *>(s_cnt + (a.lds_window + 1) / 2);  // [lds_window]
   __shared__ int s_box[4];
   __shared__ int s_ns, s_bad;
   __shared__ int s_wsum[MDF_THREADS / 64];
   __shared__ Pose s_pose[2];
-  const int64_t k = a.from_kcount ? *cp.kcount : *cp.pk;
-  const int b = (int)(k & 1);
+  // the forcing loop of substep kcount runs next, in stream order after this
+  const int64_t k = *cp.kcount + j;
+  const int b = (int)(k & cp.plan_mask);
   const PlanView P = plan_view(cp, b);
 
   // 1. kinematics: r_j(t_k), desired velocity (r_j(t_k+1) - r_j(t_k)) / dt,
@@ -1187,7 +1192,6 @@ __global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
       IbmWindow e = {0, 0, 0, 0};
       cp.win[b] = e;
       P.hdr[0] = (int)k; P.hdr[1] = 0; P.hdr[2] = ERR_WINDOW;
-      *cp.pk = k + 1;
     }
     return;
   }
@@ -1198,30 +1202,38 @@ __global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
   // 2. clear the window's force density (the collision reads all of it) and
   //    the per-cell counters
   const bool in_lds = ncell <= a.lds_window;
-  int *cnt = in_lds ? s_cnt : cp.wCnt;
-  int *idx = in_lds ? s_idx : cp.wIdx;
+  uint32_t *cnt = in_lds ? s_cnt : reinterpret_cast<uint32_t *>(cp.wCnt + (size_t)b * cp.win_cap);
+  uint16_t *idx = in_lds ? s_idx : reinterpret_cast<uint16_t *>(cp.wIdx + (size_t)b * cp.win_cap);
+  auto count_of = [&](int c) -> int { return (int)((cnt[c >> 1] >> ((c & 1) << 4)) & 0xffffu); };
   {
     double *F = cp.wF + (size_t)b * 2 * cp.win_cap;
     for (int c = tid; c < ncell; c += MDF_THREADS) {
-      cnt[c] = 0;
       F[c] = 0.0;
       F[(size_t)cp.win_cap + c] = 0.0;
     }
+    for (int w = tid; w < (ncell + 1) / 2; w += MDF_THREADS) cnt[w] = 0u;
   }
   __syncthreads();
   // 3. every marker lane registers its 16 taps: its slot in each cell's
   //    contributor list, and the first toucher of a cell appends the cell
-  //    to the compact list (a wavefront prefix sum sizes the append)
-  int cidx[16], pos[16];
+  //    to the compact list (a wavefront prefix sum sizes the append).
+  //    cidx(t): window index of tap t; pos(t): its slot in that cell's
+  //    contributor list (16 bits, two per word)
+  auto cidx = [&](int t) { return (j0 + (t >> 2) - wy0) * ww + (i0 + (t & 3) - wx0); };
+  uint32_t pos2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  auto pos = [&](int t) { return (int)((pos2[t >> 1] >> ((t & 1) << 4)) & 0xffffu); };
   {
     int nf = 0;
     if (own) {
 #pragma unroll
-      for (int t = 0; t < 16; ++t) cidx[t] = (j0 + (t >> 2) - wy0) * ww + (i0 + (t & 3) - wx0);
+      for (int t = 0; t < 16; ++t) {
+        const int c = cidx(t), sh = (c & 1) << 4;  // counts stay below 2^16 (at most one per marker)
+        const uint32_t p = (atomicAdd(&cnt[c >> 1], 1u << sh) >> sh) & 0xffffu;
+        if (t & 1) pos2[t >> 1] |= p << 16;
+        else pos2[t >> 1] = p;
+      }
 #pragma unroll
-      for (int t = 0; t < 16; ++t) pos[t] = atomicAdd(&cnt[cidx[t]], 1);
-#pragma unroll
-      for (int t = 0; t < 16; ++t) nf += pos[t] == 0;
+      for (int t = 0; t < 16; ++t) nf += pos(t) == 0;
     }
     int incl = nf;
 #pragma unroll
@@ -1237,9 +1249,9 @@ __global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
       int q = base + incl - nf;
 #pragma unroll
       for (int t = 0; t < 16; ++t)
-        if (pos[t] == 0) {
-          if (q < cap) s_cells[q] = cidx[t];
-          idx[cidx[t]] = q;
+        if (pos(t) == 0) {
+          if (q < cap) s_cells[q] = cidx(t);
+          idx[cidx(t)] = (uint16_t)q;
           ++q;
         }
     }
@@ -1249,7 +1261,6 @@ __global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
   if (ns > cap) {
     if (tid == 0) {
       P.hdr[0] = (int)k; P.hdr[1] = 0; P.hdr[2] = ERR_CONTRIB;
-      *cp.pk = k + 1;
     }
     return;
   }
@@ -1259,7 +1270,7 @@ __global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
     const int per = (ns + MDF_THREADS - 1) / MDF_THREADS;
     const int q0 = min(ns, tid * per), q1 = min(ns, q0 + per);
     int sum = 0;
-    for (int q = q0; q < q1; ++q) sum += cnt[s_cells[q]];
+    for (int q = q0; q < q1; ++q) sum += count_of(s_cells[q]);
     int incl = sum;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -1273,7 +1284,7 @@ __global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
     int run = wbase + incl - sum;
     for (int q = q0; q < q1; ++q) {
       s_start[q] = run;
-      run += cnt[s_cells[q]];
+      run += count_of(s_cells[q]);
     }
   }
   __syncthreads();
@@ -1282,8 +1293,8 @@ __global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
   if (own) {
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
-      const int q = idx[cidx[t]];
-      s_list[s_start[q] + pos[t]] = (uint16_t)tid;
+      const int q = idx[cidx(t)];
+      s_list[s_start[q] + pos(t)] = (uint16_t)tid;
       P.tap[(size_t)t * nm + tid] = (uint16_t)q;
     }
   }
@@ -1294,7 +1305,7 @@ __global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
   //    found at its corners; all must be owned finest blocks)
   for (int q = tid; q < ns; q += MDF_THREADS) {
     const int c = s_cells[q];
-    const int n_c = cnt[c], st = s_start[q];
+    const int n_c = count_of(c), st = s_start[q];
     const int gx = wx0 + c % ww, gy = wy0 + c / ww;
     uint16_t *L = s_list + st;
     uint16_t *O = P.list + st;
@@ -1332,18 +1343,21 @@ __global__ __launch_bounds__(MDF_THREADS) void ibm_prep_kernel(IbmArgs a) {
     P.hdr[0] = (int)k;
     P.hdr[1] = ns;
     P.hdr[2] = s_bad ? ERR_MARKER : 0;
-    *cp.pk = k + 1;
   }
 }
 
 __device__ __forceinline__ void mdf_fail(const CaseDev &cp, int *err, int code, int64_t k) {
   atomicOr(err, code);
   IbmWindow e = {0, 0, 0, 0};
-  cp.win[k & 1] = e;
+  cp.win[k & cp.plan_mask] = e;
   *cp.kcount = k + 1;
 }
 
 constexpr int kCellsPerLane = 4;  // stencil cells owned per lane (cell_cap <= 4096)
+#ifndef SBT_MDF_CACHED
+#define SBT_MDF_CACHED 12
+#endif
+constexpr int kCached = SBT_MDF_CACHED;  // contributors whose weights a lane keeps in registers
 
 // Block of the finest cell (sx, sy) inside the 3x3 neighbourhood of (gx, gy),
 // from the four corner blocks of that neighbourhood.
@@ -1361,16 +1375,14 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
   const int nm = cp.nm_cap;
   const int tid = threadIdx.x;
   const int NM = a.max_markers, CC = a.cell_cap;  // LDS table strides
-  extern __shared__ double lds[];
-  double *s_wx = lds;               // [4][NM]
+  extern __shared__ __align__(16) double lds[];
+  double2 *s_dF = reinterpret_cast<double2 *>(lds);  // [NM] marker force of the iteration
+  double2 *s_uv = s_dF + NM;        // [CC] corrected velocity of the cell
+  double *s_wx = reinterpret_cast<double *>(s_uv + CC);  // [4][NM]
   double *s_wy = s_wx + 4 * NM;     // [4][NM]
-  double *s_dFx = s_wy + 4 * NM;    // [NM]
-  double *s_dFy = s_dFx + NM;
-  double *s_ds = s_dFy + NM;
+  double *s_ds = s_wy + 4 * NM;     // [NM]
   double *s_rho = s_ds + NM;        // [CC]
-  double *s_u = s_rho + CC;         // [CC]
-  double *s_v = s_u + CC;           // [CC]
-  double *s_fx = s_v + CC;          // [CC] accumulated force of the cell
+  double *s_fx = s_rho + CC;        // [CC] accumulated force of the cell
   double *s_fy = s_fx + CC;         // [CC]
   int *s_i0 = reinterpret_cast<int *>(s_fy + CC);  // [NM]
   int *s_j0 = s_i0 + NM;
@@ -1399,7 +1411,7 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
   }
   const int ns = hdr.y;
   int status = hdr.z;
-  if (hdr.x != (int)k || (k & 1) != b) status = ERR_PLAN;
+  if (hdr.x != (int)k || (k & cp.plan_mask) != b) status = ERR_PLAN;
   if (!status && ns > cap) status = ERR_CONTRIB;
   if (status) {
     if (tid == 0) mdf_fail(cp, a.err, status, k);
@@ -1443,8 +1455,7 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
       moments64(f, rho, jx, jy);
       if constexpr (Store<ST>::kShift) rho = cp.rho0 + rho;
       s_rho[q] = rho;
-      s_u[q] = (jx + 0.5 * cp.fx[l]) / rho;
-      s_v[q] = (jy + 0.5 * cp.fy[l]) / rho;
+      s_uv[q] = make_double2((jx + 0.5 * cp.fx[l]) / rho, (jy + 0.5 * cp.fy[l]) / rho);
       s_fx[q] = 0.0;
       s_fy[q] = 0.0;
     }
@@ -1470,12 +1481,48 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     s_ds[tid] = cp.ds[tid];
   }
   __syncthreads();
+  // Loop invariants.  A marker's interpolated density (the densities do not
+  // change in the loop).  A stencil cell's Peskin weights w_x w_y of up to
+  // kCached contributors, in ascending marker order, with the markers'
+  // indices: held in registers for the lane's first cell, so a contribution
+  // of an iteration reads only the marker's force and arc length (LDS).
+  double sr = 0.0;
+  if (own) {
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      const double py = s_wy[bb * NM + tid];
+#pragma unroll
+      for (int aa = 0; aa < 4; ++aa) {
+        const int t = bb * 4 + aa;
+        const int q = (taps[t >> 1] >> ((t & 1) * 16)) & 0xffff;
+        sr += s_rho[q] * (s_wx[aa * NM + tid] * py);
+      }
+    }
+  }
+  auto weight = [&](int j, int gx, int gy) -> double {
+    return s_wx[(gx - s_i0[j]) * NM + j] * s_wy[(gy - s_j0[j]) * NM + j];
+  };
+  const int cnt0 = tid < ns ? csc[0] >> 16 : 0;
+  const bool cached = cnt0 <= kCached;
+  double cw[kCached];
+  uint32_t cj[kCached / 2];
+#pragma unroll
+  for (int e = 0; e < kCached / 2; ++e) cj[e] = 0;
+#pragma unroll
+  for (int e = 0; e < kCached; ++e) {
+    cw[e] = 0.0;
+    if (cached && e < cnt0) {
+      const int j = s_list[(csc[0] & 0xffff) + e];
+      cw[e] = weight(j, cxy[0] & 0xffff, cxy[0] >> 16);
+      cj[e >> 1] |= (uint32_t)j << ((e & 1) * 16);
+    }
+  }
   // 3. N_F iterations: interpolate (Eq. 12), boundary force (Eq. 11),
   //    spread (Eq. 15), correct velocity and accumulate force
   double ftx = 0.0, fty = 0.0;
   for (int it = 0; it < cp.mdf_iters; ++it) {
     if (own) {
-      double su = 0.0, sv = 0.0, sr = 0.0;
+      double su = 0.0, sv = 0.0;
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) {
         const double py = s_wy[bb * NM + tid];
@@ -1484,15 +1531,14 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
           const int t = bb * 4 + aa;
           const int q = (taps[t >> 1] >> ((t & 1) * 16)) & 0xffff;
           const double w = s_wx[aa * NM + tid] * py;
-          su += s_u[q] * w;
-          sv += s_v[q] * w;
-          sr += s_rho[q] * w;
+          const double2 uv = s_uv[q];
+          su += uv.x * w;
+          sv += uv.y * w;
         }
       }
       const double gx = 2.0 * sr * (udx - su);
       const double gy = 2.0 * sr * (udy - sv);
-      s_dFx[tid] = gx;
-      s_dFy[tid] = gy;
+      s_dF[tid] = make_double2(gx, gy);
       ftx += gx;
       fty += gy;
     }
@@ -1501,36 +1547,33 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     for (int r = 0; r < kCellsPerLane; ++r) {
       const int q = tid + r * MDF_THREADS;
       if (q < ns) {
-        const int gx = cxy[r] & 0xffff, gy = cxy[r] >> 16;
-        const int st = csc[r] & 0xffff, cnt = csc[r] >> 16;
         double dfx = 0.0, dfy = 0.0;
-        // contributors four at a time (their LDS reads overlap), summed in
-        // ascending marker order
-        for (int e0 = 0; e0 < cnt; e0 += 4) {
-          int js[4];
-          double wv[4], fxv[4], fyv[4], dsv[4];
+        if (r == 0 && cached) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) js[u] = e0 + u < cnt ? (int)s_list[st + e0 + u] : -1;
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int j = js[u] < 0 ? 0 : js[u];
-            wv[u] = s_wx[(gx - s_i0[j]) * NM + j] * s_wy[(gy - s_j0[j]) * NM + j];
-            fxv[u] = s_dFx[j];
-            fyv[u] = s_dFy[j];
-            dsv[u] = s_ds[j];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (js[u] >= 0) {
-              dfx += fxv[u] * wv[u] * dsv[u];
-              dfy += fyv[u] * wv[u] * dsv[u];
+          for (int e = 0; e < kCached; ++e)
+            if (e < cnt0) {
+              const int j = (cj[e >> 1] >> ((e & 1) * 16)) & 0xffff;
+              const double2 d = s_dF[j];
+              const double dsj = s_ds[j];
+              dfx += d.x * cw[e] * dsj;
+              dfy += d.y * cw[e] * dsj;
             }
+        } else {  // more contributors than cached, or a lane's further cells
+          const int gx = cxy[r] & 0xffff, gy = cxy[r] >> 16;
+          const int st = csc[r] & 0xffff, cnt = csc[r] >> 16;
+          for (int e = 0; e < cnt; ++e) {
+            const int j = s_list[st + e];
+            const double2 d = s_dF[j];
+            const double w = weight(j, gx, gy), dsj = s_ds[j];
+            dfx += d.x * w * dsj;
+            dfy += d.y * w * dsj;
+          }
         }
         s_fx[q] = s_fx[q] + dfx;
         s_fy[q] = s_fy[q] + dfy;
         const double r2 = 2.0 * s_rho[q];
-        s_u[q] = s_u[q] + dfx / r2;
-        s_v[q] = s_v[q] + dfy / r2;
+        const double2 uv = s_uv[q];
+        s_uv[q] = make_double2(uv.x + dfx / r2, uv.y + dfy / r2);
       }
     }
     __syncthreads();
@@ -1538,10 +1581,7 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
   // 4. body force of Eq. (16) summed in marker order by the last lane (its
   //    wave rarely owns markers or cells), while the other lanes write the
   //    force density of the stencil cells and the total marker forces
-  if (own) {
-    s_dFx[tid] = ftx * s_ds[tid];
-    s_dFy[tid] = fty * s_ds[tid];
-  }
+  if (own) s_dF[tid] = make_double2(ftx * s_ds[tid], fty * s_ds[tid]);
   __syncthreads();
   if (tid == MDF_THREADS - 1) {
     double fsx = 0.0, fsy = 0.0;
@@ -1550,8 +1590,9 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
       double vx[8], vy[8];
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        vx[r] = s_dFx[j + r];
-        vy[r] = s_dFy[j + r];
+        const double2 d = s_dF[j + r];
+        vx[r] = d.x;
+        vy[r] = d.y;
       }
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
@@ -1560,8 +1601,8 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
       }
     }
     for (; j < n; ++j) {
-      fsx -= s_dFx[j];
-      fsy -= s_dFy[j];
+      fsx -= s_dF[j].x;
+      fsy -= s_dF[j].y;
     }
     int64_t slot = k % cp.hist_cap;
     cp.hist[2 * slot] = fsx;
@@ -1709,13 +1750,13 @@ extern "C" size_t sbt_mdf_lds_bytes(int max_markers, int cell_cap) {
 
 extern "C" size_t sbt_prep_lds_bytes(int max_markers, int cell_cap, int lds_window) {
   return (size_t)cell_cap * 2 * sizeof(int) + (size_t)max_markers * 16 * sizeof(uint16_t) +
-         (size_t)lds_window * 2 * sizeof(int);
+         (size_t)(lds_window + 1) / 2 * sizeof(uint32_t) + (size_t)lds_window * sizeof(uint16_t);
 }
 
-extern "C" hipError_t sbt_launch_ibm_prep(const IbmArgs *a, int n_bodies, hipStream_t s) {
-  if (n_bodies <= 0) return hipSuccess;
+extern "C" hipError_t sbt_launch_ibm_prep(const IbmArgs *a, hipStream_t s) {
+  if (a->n_bodies <= 0 || a->n_plans <= 0) return hipSuccess;
   size_t lds = sbt_prep_lds_bytes(a->max_markers, a->cell_cap, a->lds_window);
-  hipLaunchKernelGGL(ibm_prep_kernel, dim3(n_bodies), dim3(MDF_THREADS), lds, s, *a);
+  hipLaunchKernelGGL(ibm_prep_kernel, dim3(a->n_bodies * a->n_plans), dim3(MDF_THREADS), lds, s, *a);
   return hipGetLastError();
 }
 
