@@ -662,7 +662,12 @@ struct Tile {
   using T = typename Store<ST>::T;
   static constexpr int DENSE = kQ * kCells;                   // elements
   static constexpr int HALO = 192;                            // 188 used
-  static constexpr int SIZE = DENSE + HALO;
+  // Halo populations of 4 bytes or less arrive by direct global->LDS copy,
+  // which puts each lane's value in a 32-bit slot (low bytes); 8-byte ones
+  // go through a register into dense slots.
+  static constexpr bool kDmaHalo = sizeof(T) <= 4;
+  static constexpr int HSTRIDE = kDmaHalo ? 4 / (int)sizeof(T) : 1;  // elements per halo slot
+  static constexpr int SIZE = DENSE + HALO * HSTRIDE;
   static constexpr int NVEC = DENSE * (int)sizeof(T) / 16;    // 16-byte vectors
   static constexpr int NOPS = (NVEC + 255) / 256;             // copies per lane
 };
@@ -724,6 +729,7 @@ __device__ __forceinline__ int halo_nbr(const Blk &k, int code) {
 // LDS element holding the population of direction i that streams into
 // local cell (x, y): the dense plane when its source cell is inside the
 // block, else the halo slot of that source (inverse of halo_slot).
+template <int HSTRIDE>
 __device__ __forceinline__ int tile_index(int i, int x, int y) {
   const int sx = x - CX[i], sy = y - CY[i];
   if ((unsigned)sx < 16u && (unsigned)sy < 16u) return i * kCells + sy * 16 + sx;
@@ -738,15 +744,29 @@ __device__ __forceinline__ int tile_index(int i, int x, int y) {
     case 7: slot = 126 + (x == 15 ? y : 16 + x); break;
     default: slot = 157 + (x == 0 ? y : 15 + x); break;
   }
-  return kQ * kCells + slot;
+  return kQ * kCells + slot * HSTRIDE;
+}
+
+// Source of the halo population of a missing neighbour: NaN in each storage
+// type (f32 word 0; bf16 high half of word 0; f16 low half of word 1).
+__device__ uint32_t kNanSrc[2] = {0x7FC00000u, 0x7FC07E00u};
+
+template <int ST>
+__device__ __forceinline__ const typename Store<ST>::T *nan_src() {
+  using T = typename Store<ST>::T;
+  const char *p = reinterpret_cast<const char *>(kNanSrc);
+  if constexpr (sizeof(T) == 4) return reinterpret_cast<const T *>(p);
+  else if constexpr (ST == 3) return reinterpret_cast<const T *>(p + 2);  // bf16
+  else return reinterpret_cast<const T *>(p + 4);
 }
 
 // Issue the loads of block k into LDS image `buf`: the dense planes by
 // direct global->LDS copies (16 bytes per lane, no registers), and this
-// lane's halo population into h (NaN where the neighbour is missing).
+// lane's halo population (NaN where the neighbour is missing) by a direct
+// copy too, or into h for 8-byte storage.
 template <int ST>
 __device__ __forceinline__ void fetch_tile(const LevelArgs &a, const Blk &k, typename Store<ST>::T *buf,
-                                           typename Store<ST>::T &h) {
+                                           typename Store<ST>::T &h, uint32_t he) {
   using S = Store<ST>;
   using T = typename S::T;
   using C = typename S::C;
@@ -763,49 +783,41 @@ __device__ __forceinline__ void fetch_tile(const LevelArgs &a, const Blk &k, typ
                                        16, 0, 0);
   }
   if (tid < 188) {
-    const uint32_t e = kHalo.e[tid];
+    const uint32_t e = he;
     const int nb = halo_nbr(k, (int)(e >> 16));
-    h = nb < 0 ? S::st(C(__builtin_nan(""))) : src[(size_t)nb * kQ * kCells + (e & 0xffff)];
+    if constexpr (TL::kDmaHalo) {
+      const T *p = nb < 0 ? nan_src<ST>() : src + (size_t)nb * kQ * kCells + (e & 0xffff);
+      __builtin_amdgcn_global_load_lds(p, (lds_void *)(reinterpret_cast<char *>(buf + TL::DENSE) + wv * 64 * 4),
+                                       (int)sizeof(T), 0, 0);
+    } else {
+      h = nb < 0 ? S::st(C(__builtin_nan(""))) : src[(size_t)nb * kQ * kCells + (e & 0xffff)];
+    }
   }
 }
 
-// Make buf complete for every lane: this lane's halo value, then wait for
-// this wave's direct copies before the barrier (other waves read them).
+// Make buf complete for every lane: this lane's halo value (8-byte
+// storage), then wait for this wave's direct copies before the barrier
+// (other waves read them).  Vector memory operations complete in issue
+// order, so when at least 9 were issued after this buffer's copies (the
+// previous block's stores), vmcnt(9) covers the copies without waiting
+// for those stores.  The barrier then carries no memory fence: a fence
+// would wait for the stores too.  Only LDS is shared across it, and every
+// LDS access before it has completed (the copies by the wait, the reads
+// because their values were used); the empty asm statements keep the
+// compiler from moving memory accesses across it.
 template <int ST>
-__device__ __forceinline__ void commit_tile(typename Store<ST>::T *buf, typename Store<ST>::T h) {
-  if (threadIdx.x < 188) buf[Tile<ST>::DENSE + threadIdx.x] = h;
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-  __syncthreads();
-}
-
-// Block metadata read as one 32-bit word per lane (lanes 0..17), so it is
-// waited for together with the block data rather than on the scalar path.
-__device__ __forceinline__ int meta_word(const BlockMeta *meta, int b, int lane) {
-  return reinterpret_cast<const int32_t *>(meta + b)[min(lane, 17)];
-}
-
-__device__ __forceinline__ Blk blk_from_lanes(int mv, int self) {
-  Blk k;
-  k.self = self;
-  k.ox = __builtin_amdgcn_readlane(mv, 0);
-  k.oy = __builtin_amdgcn_readlane(mv, 1);
-  k.nE = __builtin_amdgcn_readlane(mv, 2);
-  k.nN = __builtin_amdgcn_readlane(mv, 3);
-  k.nW = __builtin_amdgcn_readlane(mv, 4);
-  k.nS = __builtin_amdgcn_readlane(mv, 5);
-  k.nNE = __builtin_amdgcn_readlane(mv, 6);
-  k.nNW = __builtin_amdgcn_readlane(mv, 7);
-  k.nSW = __builtin_amdgcn_readlane(mv, 8);
-  k.nSE = __builtin_amdgcn_readlane(mv, 9);
-  k.c0 = __builtin_amdgcn_readlane(mv, 10);
-  k.c1 = __builtin_amdgcn_readlane(mv, 11);
-  k.c2 = __builtin_amdgcn_readlane(mv, 12);
-  k.c3 = __builtin_amdgcn_readlane(mv, 13);
-  k.cid = __builtin_amdgcn_readlane(mv, 14);
-  k.level = __builtin_amdgcn_readlane(mv, 15);
-  k.flags = __builtin_amdgcn_readlane(mv, 16);
-  k.code = __builtin_amdgcn_readlane(mv, 17);
-  return k;
+__device__ __forceinline__ void commit_tile(typename Store<ST>::T *buf, typename Store<ST>::T h, bool after9 = false) {
+  if constexpr (!Tile<ST>::kDmaHalo) {
+    if (threadIdx.x < 188) buf[Tile<ST>::DENSE + threadIdx.x] = h;
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+  } else {
+    if (after9) __builtin_amdgcn_s_waitcnt(0x0F79);  // vmcnt(9)
+    else __builtin_amdgcn_s_waitcnt(0x0F70);         // vmcnt(0)
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  }
 }
 
 // Stream (from the staged tile) + collide of block k; interface, edge and
@@ -833,7 +845,7 @@ __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev 
   C f[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i)
-    f[i] = S::ld(tile[tile_index(i, x, y)]);
+    f[i] = S::ld(tile[tile_index<Tile<ST>::HSTRIDE>(i, x, y)]);
   if (SLOW) {
     const int gx = k.ox + x, gy = k.oy + y;
     const bool edge = (k.flags & BF_EDGE) != 0;
@@ -906,21 +918,23 @@ __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev 
 }
 
 // One pipelined step over a run of interior blocks: make `cur` (block j)
-// complete, start block j+1's copies into `nxt` and its metadata for j+2,
-// then stream + collide block j from `cur`.
+// complete, start block j+1's copies into `nxt`, stream + collide block j
+// from `cur`, then issue the scalar load of block j+2's metadata (used
+// after the next barrier).  No vector load whose value the step needs is
+// issued after the copies, so nothing waits for them before the barrier of
+// the next step.
 template <int ST>
 __device__ __forceinline__ void pipe_step(const LevelArgs &a, const CaseDev *__restrict__ cases,
-                                          const BlockMeta *__restrict__ meta, Blk &k, int &mvn, int lv, int j, int cnt,
+                                          const BlockMeta *__restrict__ meta, Blk &kc, Blk &kn, int lv, int j, int cnt,
                                           typename Store<ST>::T *cur, typename Store<ST>::T *nxt,
-                                          typename Store<ST>::T &h) {
-  commit_tile<ST>(cur, h);
-  const Blk kc = k;
-  if (j + 1 < cnt) {
-    k = blk_from_lanes(mvn, __builtin_amdgcn_readlane(lv, j + 1));
-    fetch_tile<ST>(a, k, nxt, h);
-    if (j + 2 < cnt) mvn = meta_word(meta, __builtin_amdgcn_readlane(lv, j + 2), threadIdx.x & 63);
-  }
+                                          typename Store<ST>::T &h, uint32_t he) {
+  // after the first block, the previous block's 9 stores were issued after
+  // this buffer's copies
+  commit_tile<ST>(cur, h, j > 0);
+  if (j + 1 < cnt) fetch_tile<ST>(a, kn, nxt, h, he);
   compute_block<ST, false>(a, cases, kc, cur);
+  kc = kn;
+  if (j + 2 < cnt) kn = load_blk(meta, __builtin_amdgcn_readlane(lv, j + 2));
 }
 
 // One launch per level substep.  With NBUF = 2, workgroups [0, n_fast_wg)
@@ -944,33 +958,35 @@ __global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a, const Case
       tile_role(blockIdx.x, n_fast_wg, a.n_blocks - a.n_fast, n_band_wg, a.xcd_remap, w0));
   const int w = __builtin_amdgcn_readfirstlane(w0);  // wave-uniform: keeps block metadata on the scalar path
   const int lane = threadIdx.x & 63;
+  // this lane's halo slot (neighbour code, element), the same for every
+  // block: loaded before any copy is in flight
+  const uint32_t he = threadIdx.x < 188 ? kHalo.e[threadIdx.x] : 0u;
   T h;
   if (role == 0) {
     const int first = w * kpw;
     const int cnt = min(kpw, a.n_fast - first);
     if (NBUF == 1 || cnt == 1) {
       const Blk k = load_blk(meta, list[first]);
-      fetch_tile<ST>(a, k, bufA, h);
+      fetch_tile<ST>(a, k, bufA, h, he);
       commit_tile<ST>(bufA, h);
       compute_block<ST, false>(a, cases, k, bufA);
       return;
     }
     // the run's block ids (one per lane) and the first two blocks' metadata
+    // (scalar loads)
     const int lv = list[first + min(lane, cnt - 1)];
-    const int b0 = __builtin_amdgcn_readlane(lv, 0);
-    Blk k = blk_from_lanes(meta_word(meta, b0, lane), b0);
-    fetch_tile<ST>(a, k, bufA, h);
-    int mvn = meta_word(meta, __builtin_amdgcn_readlane(lv, 1), lane);
-    Blk kk = k;
+    Blk kc = load_blk(meta, __builtin_amdgcn_readlane(lv, 0));
+    Blk kn = load_blk(meta, __builtin_amdgcn_readlane(lv, 1));
+    fetch_tile<ST>(a, kc, bufA, h, he);
     for (int j = 0; j < cnt; j += 2) {
-      pipe_step<ST>(a, cases, meta, kk, mvn, lv, j, cnt, bufA, bufB, h);
-      if (j + 1 < cnt) pipe_step<ST>(a, cases, meta, kk, mvn, lv, j + 1, cnt, bufB, bufA, h);
+      pipe_step<ST>(a, cases, meta, kc, kn, lv, j, cnt, bufA, bufB, h, he);
+      if (j + 1 < cnt) pipe_step<ST>(a, cases, meta, kc, kn, lv, j + 1, cnt, bufB, bufA, h, he);
     }
     return;
   }
   if (role == 1) {
     const Blk k = load_blk(meta, list[a.n_fast + w]);
-    fetch_tile<ST>(a, k, bufA, h);
+    fetch_tile<ST>(a, k, bufA, h, he);
     commit_tile<ST>(bufA, h);
     compute_block<ST, true>(a, cases, k, bufA);
   } else if (role == 2) {
