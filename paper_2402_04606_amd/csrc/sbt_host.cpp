@@ -397,7 +397,8 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     int nm = 0;
     for (auto &C : X.cs) nm = std::max(nm, C.has_body ? C.d.max_markers : 0);
     long cap = ((long)kLdsBytes - 2048 - (long)sbt_mdf_lds_bytes(nm, 0)) / (long)sbt_mdf_lds_bytes(0, 1);
-    X.cell_cap = (int)std::max(0L, std::min(4096L, cap));
+    // a multiple of 4 keeps the forcing kernel's LDS list 16-byte aligned
+    X.cell_cap = (int)std::max(0L, std::min(4096L, cap)) & ~3;
     if (nm > 0 && X.cell_cap < 64) return fail(SBT_ERR_ARG, "max_markers too large for one workgroup's LDS");
   }
   build_tables(X);

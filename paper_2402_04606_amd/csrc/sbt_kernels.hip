@@ -1410,20 +1410,46 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
   const int64_t k = *cp.kcount;
   const int4 hdr = *reinterpret_cast<const int4 *>(P.hdr);
   const IbmWindow win = cp.win[b];
-  // 1. load the plan: this lane's stencil-cell records (up to the plan
-  //    capacity, so before the header is known) and the contributor lists
-  //    (LDS)
+  // 1. load the plan before the header is known, all in one round: this
+  //    lane's first stencil-cell record, the contributor lists (direct
+  //    global->LDS copies, 16 bytes per lane) and the marker tables
   const int cap = min(cp.cell_cap, min(CC, kCellsPerLane * MDF_THREADS));
   int4 rec0[kCellsPerLane], rec1[kCellsPerLane];
-  if (tid < cap) {  // first owned cell: before the header is known
+  if (tid < cap) {
     const int4 *R = reinterpret_cast<const int4 *>(P.cell + (size_t)tid * 8);
     rec0[0] = R[0];
     rec1[0] = R[1];
   }
   {
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(P.list);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(s_list);
-    for (int e = tid; e < 8 * n; e += MDF_THREADS) dst[e] = src[e];
+    const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const char *src = reinterpret_cast<const char *>(P.list);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {  // 32 n bytes = 2 n vectors, n <= 1024
+      const int v0 = r * MDF_THREADS + wv * 64;  // wave-uniform first vector
+      if (v0 < 2 * n && v0 + lane < 2 * n)
+        __builtin_amdgcn_global_load_lds(src + (size_t)(v0 + lane) * 16,
+                                         (lds_void *)(reinterpret_cast<char *>(s_list) + (size_t)v0 * 16), 16, 0, 0);
+    }
+  }
+  const bool own = tid < n;
+  double wxr[4] = {0.0, 0.0, 0.0, 0.0}, wyr[4] = {0.0, 0.0, 0.0, 0.0};
+  double udx = 0.0, udy = 0.0, dsr = 0.0;
+  int i0r = 0, j0r = 0;
+  uint32_t taps[8];  // stencil cells of the 16 taps, two per word
+  if (own) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      wxr[t] = P.w[(size_t)t * nm + tid];
+      wyr[t] = P.w[(size_t)(4 + t) * nm + tid];
+    }
+    udx = P.ud[tid];
+    udy = P.ud[nm + tid];
+#pragma unroll
+    for (int t = 0; t < 8; ++t)
+      taps[t] = (uint32_t)P.tap[(size_t)(2 * t) * nm + tid] | ((uint32_t)P.tap[(size_t)(2 * t + 1) * nm + tid] << 16);
+    i0r = P.i0[tid];
+    j0r = P.j0[tid];
+    dsr = cp.ds[tid];
   }
   const int ns = hdr.y;
   int status = hdr.z;
@@ -1431,6 +1457,7 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
   if (!status && ns > cap) status = ERR_CONTRIB;
   if (status) {
     if (tid == 0) mdf_fail(cp, a.err, status, k);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // the list copies land before the LDS is released
     return;
   }
   // 2. moments of the owned stencil cells from the post-stream populations
@@ -1476,32 +1503,25 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
       s_fy[q] = 0.0;
     }
   }
-  // marker weights and desired velocity (registers and LDS), loaded while
-  // the gathers above are in flight
-  const bool own = tid < n;
-  double udx = 0.0, udy = 0.0;
-  uint32_t taps[8];  // stencil cells of the 16 taps, two per word
+  // the marker tables to LDS
   if (own) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      s_wx[t * NM + tid] = P.w[(size_t)t * nm + tid];
-      s_wy[t * NM + tid] = P.w[(size_t)(4 + t) * nm + tid];
+      s_wx[t * NM + tid] = wxr[t];
+      s_wy[t * NM + tid] = wyr[t];
     }
-    udx = P.ud[tid];
-    udy = P.ud[nm + tid];
-#pragma unroll
-    for (int t = 0; t < 8; ++t)
-      taps[t] = (uint32_t)P.tap[(size_t)(2 * t) * nm + tid] | ((uint32_t)P.tap[(size_t)(2 * t + 1) * nm + tid] << 16);
-    s_i0[tid] = P.i0[tid];
-    s_j0[tid] = P.j0[tid];
-    s_ds[tid] = cp.ds[tid];
+    s_i0[tid] = i0r;
+    s_j0[tid] = j0r;
+    s_ds[tid] = dsr;
   }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the list copies
   __syncthreads();
   // Loop invariants.  A marker's interpolated density (the densities do not
-  // change in the loop).  A stencil cell's Peskin weights w_x w_y of up to
-  // kCached contributors, in ascending marker order, with the markers'
-  // indices: held in registers for the lane's first cell, so a contribution
-  // of an iteration reads only the marker's force and arc length (LDS).
+  // change in the loop).  A stencil cell's Peskin weights w_x w_y of its
+  // first kCached contributors (ascending marker order), with the markers'
+  // indices: held in registers for the lane's first cell, so such a
+  // contribution of an iteration reads only the marker's force and arc
+  // length (LDS); further contributors are looked up in LDS.
   double sr = 0.0;
   if (own) {
 #pragma unroll
@@ -1519,7 +1539,6 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     return s_wx[(gx - s_i0[j]) * NM + j] * s_wy[(gy - s_j0[j]) * NM + j];
   };
   const int cnt0 = tid < ns ? csc[0] >> 16 : 0;
-  const bool cached = cnt0 <= kCached;
   double cw[kCached];
   uint32_t cj[kCached / 2];
 #pragma unroll
@@ -1527,7 +1546,7 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
 #pragma unroll
   for (int e = 0; e < kCached; ++e) {
     cw[e] = 0.0;
-    if (cached && e < cnt0) {
+    if (e < cnt0) {
       const int j = s_list[(csc[0] & 0xffff) + e];
       cw[e] = weight(j, cxy[0] & 0xffff, cxy[0] >> 16);
       cj[e >> 1] |= (uint32_t)j << ((e & 1) * 16);
@@ -1564,7 +1583,7 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
       const int q = tid + r * MDF_THREADS;
       if (q < ns) {
         double dfx = 0.0, dfy = 0.0;
-        if (r == 0 && cached) {
+        if (r == 0) {
 #pragma unroll
           for (int e = 0; e < kCached; ++e)
             if (e < cnt0) {
@@ -1574,7 +1593,16 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
               dfx += d.x * cw[e] * dsj;
               dfy += d.y * cw[e] * dsj;
             }
-        } else {  // more contributors than cached, or a lane's further cells
+          // contributors beyond the cached ones, in the same ascending order
+          const int gx = cxy[0] & 0xffff, gy = cxy[0] >> 16, st = csc[0] & 0xffff;
+          for (int e = kCached; e < cnt0; ++e) {
+            const int j = s_list[st + e];
+            const double2 d = s_dF[j];
+            const double w = weight(j, gx, gy), dsj = s_ds[j];
+            dfx += d.x * w * dsj;
+            dfy += d.y * w * dsj;
+          }
+        } else {  // a lane's further cells
           const int gx = cxy[r] & 0xffff, gy = cxy[r] >> 16;
           const int st = csc[r] & 0xffff, cnt = csc[r] >> 16;
           for (int e = 0; e < cnt; ++e) {
@@ -1594,35 +1622,29 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
     }
     __syncthreads();
   }
-  // 4. body force of Eq. (16) summed in marker order by the last lane (its
-  //    wave rarely owns markers or cells), while the other lanes write the
-  //    force density of the stencil cells and the total marker forces
+  // 4. body force of Eq. (16) summed in marker order by the last two lanes
+  //    (their wave rarely owns markers or cells), while the other lanes
+  //    write the force density of the stencil cells and the total marker
+  //    forces
   if (own) s_dF[tid] = make_double2(ftx * s_ds[tid], fty * s_ds[tid]);
   __syncthreads();
-  if (tid == MDF_THREADS - 1) {
-    double fsx = 0.0, fsy = 0.0;
+  if (tid >= MDF_THREADS - 2) {
+    // the x sum on the second-to-last lane and the y sum on the last: one
+    // instruction stream carries both serial chains
+    const int comp = tid & 1;
+    const double *v = reinterpret_cast<const double *>(s_dF) + comp;
+    double fs = 0.0;
     int j = 0;
-    for (; j + 8 <= n; j += 8) {
-      double vx[8], vy[8];
+    for (; j + 16 <= n; j += 16) {
+      double t[16];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const double2 d = s_dF[j + r];
-        vx[r] = d.x;
-        vy[r] = d.y;
-      }
+      for (int r = 0; r < 16; ++r) t[r] = v[2 * (j + r)];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        fsx -= vx[r];
-        fsy -= vy[r];
-      }
+      for (int r = 0; r < 16; ++r) fs -= t[r];
     }
-    for (; j < n; ++j) {
-      fsx -= s_dF[j].x;
-      fsy -= s_dF[j].y;
-    }
-    int64_t slot = k % cp.hist_cap;
-    cp.hist[2 * slot] = fsx;
-    cp.hist[2 * slot + 1] = fsy;
+    for (; j < n; ++j) fs -= v[2 * j];
+    const int64_t slot = k % cp.hist_cap;
+    cp.hist[2 * slot + comp] = fs;
   }
   {
     double *F = cp.wF + (size_t)b * 2 * cp.win_cap;
