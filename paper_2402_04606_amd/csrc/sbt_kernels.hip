@@ -31,6 +31,11 @@ __device__ constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 __device__ constexpr int MIRX[9] = {0, 3, 2, 1, 4, 6, 5, 8, 7};  // reflect about an x-normal edge
 __device__ constexpr int MIRY[9] = {0, 1, 4, 3, 2, 8, 7, 6, 5};  // reflect about a y-normal edge
 
+// c_x, c_y of a direction known only at run time, from 2-bit fields (c + 1)
+// of a constant: no table load
+__device__ __forceinline__ int cx_of(int p) { return (int)((0x20919u >> (2 * p)) & 3u) - 1; }
+__device__ __forceinline__ int cy_of(int p) { return (int)((0x2865u >> (2 * p)) & 3u) - 1; }
+
 template <typename C>
 __device__ __forceinline__ C wgt(int i) {
   return i == 0 ? C(4.0 / 9.0) : (i < 5 ? C(1.0 / 9.0) : C(1.0 / 36.0));
@@ -321,26 +326,63 @@ __device__ __forceinline__ void frame_moments(const CaseDev &cp, const typename 
 // ---- domain-edge rules -----------------------------------------------------
 // Unknown population q of cell (x, y) (local coordinates of block `self`,
 // level-0 global cell (gx, gy)); its source lies beyond a non-periodic edge.
-template <int ST>
-__device__ __forceinline__ typename Store<ST>::C edge_value(const CaseDev &cp, const void *src, const Blk &k, int x, int y,
-                                            int gx, int gy, int q) {
+// rd(lx, ly, p) reads the post-collision population p of the cell at local
+// coordinates (lx, ly) (block `self` or a neighbour).  The edge kinds and
+// velocities are read at constant indices (scalar loads of the wave-uniform
+// case) and selected per lane, never indexed by the lane's edge.
+// The case parameters every edge decision uses, read once per block and
+// packed into three registers.  An empty asm statement that takes
+// them as operands pins the loads before the per-direction branches (sunk
+// into those branches, each scalar load would wait on its own).  The wall
+// and inflow velocities and rho0 are read where those rules apply.
+struct EdgeParams {
+  int nx, ny;
+  int bits;  // per_x | per_y << 1 | bc[e] << (4 + 4 e)
+  const CaseDev *cp;
+  __device__ int per_x() const { return bits & 1; }
+  __device__ int per_y() const { return (bits >> 1) & 1; }
+  __device__ int bc(int e) const { return (bits >> (4 + 4 * e)) & 15; }
+};
+
+__device__ __forceinline__ EdgeParams edge_params(const CaseDev &cp) {
+  EdgeParams ep;
+  int nx = cp.nx[0], ny = cp.ny[0];
+  int bits = (cp.per_x ? 1 : 0) | (cp.per_y ? 2 : 0);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) bits |= (cp.bc[e] & 15) << (4 + 4 * e);
+  asm volatile("" : "+v"(nx), "+v"(ny), "+v"(bits));
+  ep.nx = nx;
+  ep.ny = ny;
+  ep.bits = bits;
+  ep.cp = &cp;
+  return ep;
+}
+
+template <int ST, class Reader>
+__device__ __forceinline__ typename Store<ST>::C edge_value_rd(const EdgeParams &ep, int x, int y, int gx, int gy, int q,
+                                                               Reader &&rd) {
 #pragma clang fp contract(off)
   using C = typename Store<ST>::C;
-  const int nx = cp.nx[0], ny = cp.ny[0];
+  const int nx = ep.nx, ny = ep.ny;
+  const int bc0 = ep.bc(0), bc1 = ep.bc(1), bc2 = ep.bc(2), bc3 = ep.bc(3);
+  const CaseDev &cp = *ep.cp;
+  auto pick = [](int e, auto v0, auto v1, auto v2, auto v3) { return e == 0 ? v0 : (e == 1 ? v1 : (e == 2 ? v2 : v3)); };
   int sx = gx - CX[q], sy = gy - CY[q];
-  bool outx = (sx < 0 || sx >= nx) && !cp.per_x;
-  bool outy = (sy < 0 || sy >= ny) && !cp.per_y;
+  bool outx = (sx < 0 || sx >= nx) && !ep.per_x();
+  bool outy = (sy < 0 || sy >= ny) && !ep.per_y();
   int ex = sx < 0 ? 0 : 1, ey = sy < 0 ? 2 : 3;
   int e = outx ? ex : ey;
   if (outx && outy) {
-    int kx = cp.bc[ex], ky = cp.bc[ey];
+    int kx = ex == 0 ? bc0 : bc1, ky = ey == 2 ? bc2 : bc3;
     bool lx = kx == 1 || kx == 2, ly = ky == 1 || ky == 2;
     if (!lx && ly) e = ey;
   }
-  const double uwx = cp.bcu[e][0], uwy = cp.bcu[e][1];
-  switch (cp.bc[e]) {
+  const int kind = pick(e, bc0, bc1, bc2, bc3);
+  auto uwall = [&](int c) { return pick(e, cp.bcu[0][c], cp.bcu[1][c], cp.bcu[2][c], cp.bcu[3][c]); };
+  switch (kind) {
     case 1: {  // wall: half-way bounce-back with moving-wall term
-      C fs = ldv<ST>(src, k.self, OPP[q], y * 16 + x);
+      const double uwx = uwall(0), uwy = uwall(1);
+      C fs = rd(x, y, OPP[q]);
       if constexpr (!Store<ST>::kShift) {
         return fs + 6.0 * wgt<double>(q) * cp.rho0 * (CX[q] * uwx + CY[q] * uwy);
       } else {
@@ -348,6 +390,7 @@ __device__ __forceinline__ typename Store<ST>::C edge_value(const CaseDev &cp, c
       }
     }
     case 2: {  // equilibrium inflow at (rho0, u_in)
+      const double uwx = uwall(0), uwy = uwall(1);
       if constexpr (!Store<ST>::kShift) {
         return feq64(q, cp.rho0, uwx, uwy, uwx * uwx + uwy * uwy);
       } else {
@@ -361,7 +404,7 @@ __device__ __forceinline__ typename Store<ST>::C edge_value(const CaseDev &cp, c
       const int nrx = e == 0 ? -1 : (e == 1 ? 1 : 0), nry = e == 2 ? -1 : (e == 3 ? 1 : 0);
       const bool xn = (e == 0 || e == 1);
       int px, py, qq = q;
-      if (cp.bc[e] == 3) {
+      if (kind == 3) {
         px = gx - nrx - CX[q];
         py = gy - nry - CY[q];
       } else {
@@ -370,13 +413,21 @@ __device__ __forceinline__ typename Store<ST>::C edge_value(const CaseDev &cp, c
         qq = xn ? MIRX[q] : MIRY[q];
       }
       // periodic axes wrap through the neighbour table; others clamp (corners)
-      if (!cp.per_x) px = px < 0 ? 0 : (px >= nx ? nx - 1 : px);
-      if (!cp.per_y) py = py < 0 ? 0 : (py >= ny ? ny - 1 : py);
-      return fetch<ST>(src, k, x + (px - gx), y + (py - gy), qq);
+      if (!ep.per_x()) px = px < 0 ? 0 : (px >= nx ? nx - 1 : px);
+      if (!ep.per_y()) py = py < 0 ? 0 : (py >= ny ? ny - 1 : py);
+      return rd(x + (px - gx), y + (py - gy), qq);
     }
     default:
       return C(__builtin_nan(""));
   }
+}
+
+// The same, reading every source from the lattice in memory.
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::C edge_value(const CaseDev &cp, const void *src, const Blk &k, int x, int y,
+                                                            int gx, int gy, int q) {
+  return edge_value_rd<ST>(edge_params(cp), x, y, gx, gy, q,
+                           [&](int lx, int ly, int p) { return fetch<ST>(src, k, lx, ly, p); });
 }
 
 // ---- fine-to-coarse coalescence (step (6) of Sec. 2.4), on read ------------
@@ -731,7 +782,7 @@ __device__ __forceinline__ int halo_nbr(const Blk &k, int code) {
 // block, else the halo slot of that source (inverse of halo_slot).
 template <int HSTRIDE>
 __device__ __forceinline__ int tile_index(int i, int x, int y) {
-  const int sx = x - CX[i], sy = y - CY[i];
+  const int sx = x - cx_of(i), sy = y - cy_of(i);
   if ((unsigned)sx < 16u && (unsigned)sy < 16u) return i * kCells + sy * 16 + sx;
   int slot;
   switch (i) {
@@ -849,14 +900,24 @@ __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev 
   if (SLOW) {
     const int gx = k.ox + x, gy = k.oy + y;
     const bool edge = (k.flags & BF_EDGE) != 0;
+    // post-collision population p of local cell (lx, ly): from the staged
+    // tile when the block holds it or when it is the halo value that some
+    // cell of the block streams in, else from memory (block corners)
+    const EdgeParams ep = edge_params(cp);
+    auto tile_reader = [&](int lx, int ly, int p) -> C {
+      if ((unsigned)lx < 16u && (unsigned)ly < 16u) return S::ld(tile[p * kCells + ly * 16 + lx]);
+      const int cx = lx + cx_of(p), cy = ly + cy_of(p);
+      if ((unsigned)cx < 16u && (unsigned)cy < 16u) return S::ld(tile[tile_index<Tile<ST>::HSTRIDE>(p, cx, cy)]);
+      return fetch<ST>(a.src, k, lx, ly, p);
+    };
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       if (code & (1u << i)) {
         f[i] = coalesce<ST>(a, k, x, y, i);
       } else if (edge) {
         int sx = gx - CX[i], sy = gy - CY[i];
-        bool out = (!cp.per_x && (sx < 0 || sx >= cp.nx[0])) || (!cp.per_y && (sy < 0 || sy >= cp.ny[0]));
-        if (out) f[i] = edge_value<ST>(cp, a.src, k, x, y, gx, gy, i);
+        bool out = (!ep.per_x() && (sx < 0 || sx >= ep.nx)) || (!ep.per_y() && (sy < 0 || sy >= ep.ny));
+        if (out) f[i] = edge_value_rd<ST>(ep, x, y, gx, gy, i, tile_reader);
       }
     }
     if ((code & CC_HSRC) && cp.cf_mode == 1) {  // RESCALE the coalesced populations
