@@ -875,7 +875,7 @@ __device__ __forceinline__ void commit_tile(typename Store<ST>::T *buf, typename
 // explosion work only when SLOW.
 template <int ST, bool SLOW>
 __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev *__restrict__ cases, const Blk &k,
-                                              const typename Store<ST>::T *tile) {
+                                              const typename Store<ST>::T *tile, uint16_t code_in = 0) {
 #pragma clang fp contract(off)
   using S = Store<ST>;
   using T = typename S::T;
@@ -890,7 +890,7 @@ __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev 
   const int l = __builtin_amdgcn_readfirstlane(k.level);
   uint16_t code = 0;
   if (SLOW) {
-    code = (k.flags & BF_CODES) ? a.codes[(size_t)k.code * kCells + tid] : (uint16_t)0;
+    code = code_in;  // loaded by the caller while the tile copies were in flight
     if (code & CC_HIDDEN) return;  // covered by the finer level
   }
   C f[9];
@@ -1048,8 +1048,9 @@ __global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a, const Case
   if (role == 1) {
     const Blk k = load_blk(meta, list[a.n_fast + w]);
     fetch_tile<ST>(a, k, bufA, h, he);
+    const uint16_t code = (k.flags & BF_CODES) ? a.codes[(size_t)k.code * kCells + threadIdx.x] : (uint16_t)0;
     commit_tile<ST>(bufA, h);
-    compute_block<ST, true>(a, cases, k, bufA);
+    compute_block<ST, true>(a, cases, k, bufA, code);
   } else if (role == 2) {
     int idx = w * 256 + threadIdx.x;
     if (idx < a.n_band) band_cell<ST>(a, a.band[idx]);
