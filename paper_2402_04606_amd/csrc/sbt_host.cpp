@@ -259,6 +259,7 @@ struct Phase {
 struct GroupInfo {
   std::vector<int> cases;          // case indices of the group
   int32_t *d_body_cases = nullptr; // cases of the group that carry a body
+  CaseDev *d_bodies = nullptr;     // their parameters, in the same order (one per forcing workgroup)
   int n_bodies = 0;
 };
 
@@ -421,7 +422,10 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
   X.d_diag = (double *)cv.take(sizeof(double) * 4);
   X.d_err = (int32_t *)cv.take(sizeof(int32_t) * 4);
   X.d_cases = (CaseDev *)cv.take(sizeof(CaseDev) * n_cases);
-  for (auto &Gr : X.groups) Gr.d_body_cases = (int32_t *)cv.take(sizeof(int32_t) * n_cases);
+  for (auto &Gr : X.groups) {
+    Gr.d_body_cases = (int32_t *)cv.take(sizeof(int32_t) * n_cases);
+    Gr.d_bodies = (CaseDev *)cv.take(sizeof(CaseDev) * n_cases);
+  }
   for (int c = 0; c < n_cases; ++c) {
     CaseHost &C = X.cs[c];
     CaseDev &D = C.dev;
@@ -724,7 +728,7 @@ sbt_status launch_mdf(sbt_ctx &X, int g, bool first, hipStream_t s) {
   a.meta = P.d_meta;
   a.src = P.lat[P.cur];
   a.cases = X.d_cases;
-  a.body_cases = Gr.d_body_cases;
+  a.bodies = Gr.d_bodies;
   a.first = first ? 1 : 0;
   a.err = X.d_err;
   a.max_markers = X.max_body_markers;
@@ -761,7 +765,7 @@ sbt_status launch_prep(sbt_ctx &X, int g, int n_plans, hipStream_t s) {
   if (n_plans > X.plan_bufs) return fail(SBT_ERR_STATE, "more IBM plans than plan buffers");
   IbmArgs a;
   a.cases = X.d_cases;
-  a.body_cases = Gr.d_body_cases;
+  a.bodies = Gr.d_bodies;
   a.max_markers = X.max_body_markers;
   a.cell_cap = X.cell_cap;
   a.lds_window = X.lds_window;
@@ -1189,8 +1193,12 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
       if (X.cs[k].has_body && X.cs[k].n_markers > 0) bc.push_back(k);
     Gr.n_bodies = (int)bc.size();
     X.n_bodies += Gr.n_bodies;
-    if (!bc.empty())
+    if (!bc.empty()) {
       HIPCHK(hipMemcpy(Gr.d_body_cases, bc.data(), sizeof(int32_t) * bc.size(), hipMemcpyHostToDevice));
+      std::vector<CaseDev> bd;
+      for (int k : bc) bd.push_back(X.cs[k].dev);
+      HIPCHK(hipMemcpy(Gr.d_bodies, bd.data(), sizeof(CaseDev) * bd.size(), hipMemcpyHostToDevice));
+    }
   }
   destroy_graphs(X);
   return SBT_OK;

@@ -115,7 +115,7 @@ struct MdfArgs {
   const BlockMeta *meta;       // finest pool
   const void *src;             // finest pool lattice the next level launch reads
   const CaseDev *cases;
-  const int32_t *body_cases;   // case index per workgroup
+  const CaseDev *bodies;       // copies of the body cases' parameters, one per body (workgroup)
   int32_t first;               // 1: local read (initial pre-collision state)
   int32_t max_markers;         // LDS marker-table stride (>= every body's markers)
   int32_t cell_cap;            // LDS stencil-cell table size (>= every plan's cells)
@@ -125,7 +125,7 @@ struct MdfArgs {
 
 struct IbmArgs {
   const CaseDev *cases;
-  const int32_t *body_cases;   // case index per workgroup
+  const CaseDev *bodies;       // copies of the body cases' parameters, one per body (workgroup)
   int32_t max_markers;         // LDS list stride (>= every body's markers)
   int32_t cell_cap;            // stencil-cell capacity
   int32_t lds_window;          // window cells whose counters fit in LDS

@@ -1185,9 +1185,8 @@ __device__ __forceinline__ PlanView plan_view(const CaseDev &cp, int b) {
 // lists while they are filled.
 __global__ __launch_bounds__(MDF_THREADS, 8) void ibm_prep_kernel(IbmArgs a) {
 #pragma clang fp contract(off)
-  const int ci = a.body_cases[blockIdx.x % a.n_bodies];
   const int64_t j = blockIdx.x / a.n_bodies;  // plan of the launch's j-th substep
-  const CaseDev &cp = a.cases[ci];
+  const CaseDev &cp = a.bodies[blockIdx.x % a.n_bodies];
   const int n = cp.n_markers;
   const int nm = cp.nm_cap, cap = cp.cell_cap;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1447,8 +1446,7 @@ __device__ __forceinline__ int corner_block(int gx, int gy, int sx, int sy, int 
 template <int ST>
 __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
 #pragma clang fp contract(off)
-  const int ci = a.body_cases[blockIdx.x];
-  const CaseDev &cp = a.cases[ci];
+  const CaseDev &cp = a.bodies[blockIdx.x];
   const int n = cp.n_markers;
   const int nm = cp.nm_cap;
   const int tid = threadIdx.x;
