@@ -144,8 +144,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the batched sweep shards by whole "
-              "cases with no exchange (see the design notes). Use --gpus 1.", file=sys.stderr)
+        print("bench.py: this build runs on one GPU only; the batched sweep would shard by "
+              "whole cases with no exchange between GPUs. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
