@@ -202,7 +202,8 @@ sbt_status sbt_read_state(sbt_ctx *ctx, void *host, size_t bytes);
 sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes);
 
 /* Tuning and measurement.
- * SBT_OPT_GRAPH (default 1): replay each step as a captured HIP graph.
+ * SBT_OPT_GRAPH (default 1): replay steps as captured HIP graphs (of 4, 2 and 1
+ *   steps; all are captured at the first step that uses one).
  * SBT_OPT_TILE: interior 16x16 blocks per workgroup of the stream+collide
  *   launch, 1..16 for every level (a workgroup loads block j+1 while it
  *   computes block j); 0 (default) = automatic per launch size.
@@ -210,7 +211,7 @@ sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes);
 enum { SBT_OPT_GRAPH = 0, SBT_OPT_TILE = 1, SBT_OPT_XCD_REMAP = 2 };
 sbt_status sbt_set_option(sbt_ctx *ctx, int32_t option, int32_t value);
 /* Pick the blocks per workgroup of each level by timing `steps` steps per
- * trial (1, 2, 4, 8; finest level first, one level at a time) and keep the
+ * trial (1, 2, 3, 4, 6, 8; finest level first, one level at a time) and keep the
  * fastest; if cache_path is non-NULL the choice is read from / written to
  * that JSON file keyed by the storage and the block counts.  The simulation
  * state is restored afterwards. */

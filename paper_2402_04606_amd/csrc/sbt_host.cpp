@@ -286,7 +286,7 @@ struct sbt_ctx {
   int64_t k_host = 0;           // finest substeps issued (every body's forcing-loop counter)
 
   std::vector<Phase> step_phases;
-  std::vector<hipGraphExec_t> graph;   // [lattice parity + 2 * plan buffer]
+  std::vector<hipGraphExec_t> graph;   // [level-0 parity + 2 * plan buffer + 2 * plan_bufs * size index]
   hipEvent_t step_event = nullptr;
   bool graph_dirty = true;
   size_t bytes_used = 0;
@@ -823,15 +823,38 @@ void destroy_graphs(sbt_ctx &X) {
   X.graph_dirty = true;
 }
 
+// Steps per graph launch: a call of n steps replays graphs of 4, 2 and 1
+// steps, so the launch gap between graphs is paid once per 4 steps.
+constexpr int kGraphSteps[3] = {1, 2, 4};
+
 sbt_status ensure_capture_stream(sbt_ctx &X) {
   if (!X.cap_stream) HIPCHK(hipStreamCreateWithFlags(&X.cap_stream, hipStreamNonBlocking));
-  if ((int)X.graph.size() != 2 * X.plan_bufs) X.graph.assign(2 * X.plan_bufs, nullptr);
+  if ((int)X.graph.size() != 3 * 2 * X.plan_bufs) X.graph.assign(3 * 2 * X.plan_bufs, nullptr);
   return SBT_OK;
 }
 
-// One step as a graph: the eager launch list captured on one stream (the
-// launches depend on each other in order, so the graph is a chain).
-sbt_status capture_graph(sbt_ctx &X, int key) {
+// A graph bakes in the lattice parities and the IBM plan buffers of its
+// substeps.  Over a step only level 0's parity flips (every finer level
+// runs an even number of substeps) and the forcing-loop counter advances by
+// the number of plan buffers, so the key is level 0's parity and the plan
+// buffer of the step's first substep.
+int graph_slot(const sbt_ctx &X, int si) {
+  return X.pools[0].cur + 2 * (int)(X.k_host & (X.plan_bufs - 1)) + 2 * X.plan_bufs * si;
+}
+
+// The host-side state changes of `steps` graph-replayed steps.
+void advance_host(sbt_ctx &X, int steps) {
+  for (int t = 0; t < steps; ++t) {
+    for (int g = 0; g < X.G; ++g)
+      for (const Phase &ph : X.step_phases)
+        if (ph.type == PH_LEVEL) X.pools[(size_t)g * X.V + ph.v].cur ^= 1;
+    if (X.n_bodies > 0) X.k_host += forcing_phases(X);
+  }
+}
+
+// `steps` steps as one graph: the eager launch list captured on one stream
+// (the launches depend on each other in order, so the graph is a chain).
+sbt_status capture_graph(sbt_ctx &X, int slot, int steps) {
   sbt_status st = ensure_capture_stream(X);
   if (st) return st;
   std::vector<int> saved(X.pools.size());
@@ -839,7 +862,8 @@ sbt_status capture_graph(sbt_ctx &X, int key) {
   const int64_t saved_k = X.k_host;
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(X.cap_stream, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < X.G && !st; ++k) st = run_group_step(X, k, X.cap_stream);
+  for (int t = 0; t < steps && !st; ++t)
+    for (int k = 0; k < X.G && !st; ++k) st = run_group_step(X, k, X.cap_stream);
   hipError_t e = hipStreamEndCapture(X.cap_stream, &g);
   for (size_t i = 0; i < X.pools.size(); ++i) X.pools[i].cur = saved[i];
   X.k_host = saved_k;
@@ -848,9 +872,27 @@ sbt_status capture_graph(sbt_ctx &X, int key) {
     return st;
   }
   if (e != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(&X.graph[key], g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&X.graph[slot], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(SBT_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return SBT_OK;
+}
+
+// Every graph size for both parities of level 0 at the current plan buffer,
+// so a long call never captures inside its run.
+sbt_status capture_all(sbt_ctx &X) {
+  for (int flip = 0; flip < 2; ++flip) {
+    if (flip)
+      for (int g = 0; g < X.G; ++g) X.pools[(size_t)g * X.V].cur ^= 1;
+    sbt_status st = SBT_OK;
+    for (int si = 0; si < 3 && !st; ++si) {
+      const int slot = graph_slot(X, si);
+      if (!X.graph[slot]) st = capture_graph(X, slot, kGraphSteps[si]);
+    }
+    if (flip)
+      for (int g = 0; g < X.G; ++g) X.pools[(size_t)g * X.V].cur ^= 1;
+    if (st) return st;
+  }
   return SBT_OK;
 }
 
@@ -1231,27 +1273,25 @@ sbt_status sbt_step(sbt_ctx *ctx, int32_t n) {
     sbt_status st = run_prologue(X, X.stream);
     if (st) return st;
   }
-  for (int t = 0; t < n; ++t) {
+  for (int t = 0; t < n;) {
     if (X.use_graph && !X.profiling) {
       sbt_status st = ensure_capture_stream(X);
       if (st) return st;
-      // a graph bakes in the lattice parities and the IBM plan buffers of
-      // its substeps
-      const int par = X.pools[0].cur + 2 * (int)(X.k_host & (X.plan_bufs - 1));
-      if (!X.graph[par]) {
-        st = capture_graph(X, par);
+      const int rem = n - t, si = rem >= 4 ? 2 : (rem >= 2 ? 1 : 0);
+      const int slot = graph_slot(X, si);
+      if (!X.graph[slot]) {
+        st = capture_all(X);
         if (st) return st;
       }
-      HIPCHK(hipGraphLaunch(X.graph[par], X.stream));
+      HIPCHK(hipGraphLaunch(X.graph[slot], X.stream));
       // the graph performs the same lattice flips and forcing loops as the
       // eager list
-      for (int g = 0; g < X.G; ++g)
-        for (const Phase &ph : X.step_phases)
-          if (ph.type == PH_LEVEL) X.pools[(size_t)g * X.V + ph.v].cur ^= 1;
-      if (X.n_bodies > 0) X.k_host += forcing_phases(X);
+      advance_host(X, kGraphSteps[si]);
+      t += kGraphSteps[si];
     } else {
       sbt_status st = run_step_eager(X, X.stream);
       if (st) return st;
+      ++t;
     }
   }
   return SBT_OK;
@@ -1617,7 +1657,7 @@ sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path) {
   float best_ms = 0;
   st = trial(cur, best_ms);
   for (int v = X.V - 1; v >= 0 && !st; --v) {
-    for (int k : {1, 2, 4, 8}) {
+    for (int k : {1, 2, 3, 4, 6, 8}) {
       if (k == cur[v]) continue;
       std::vector<int> t = cur;
       t[v] = k;
