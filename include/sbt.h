@@ -88,8 +88,27 @@ enum { SBT_CF_HOMOGENEOUS = 0, SBT_CF_RESCALE = 1 };
  *        alpha = p[2] - p[3] sin(theta + p[7]),
  *        centre = (p[0], p[1]) + (p[4]/2) cos(theta) (cos p[5], sin p[5]),
  *        r_j = centre + (xb cos a + yb sin a, -xb sin a + yb cos a).
- *        p = {x0, y0, alpha0, A_pitch, A0, beta, T, phi, U_ref, chord}. */
-enum { SBT_BODY_FIXED = 0, SBT_BODY_FLAP = 1, SBT_BODY_HOST = 2 };
+ *        p = {x0, y0, alpha0, A_pitch, A0, beta, T, phi, U_ref, chord}.
+ * HOST : positions and desired velocities given by sbt_set_markers.
+ * RAMP : the pitch-up ramp of Sec. 3.5, a pure pitch about the pivot
+ *        (p[0], p[1]) (the body-frame origin; the paper pivots about the
+ *        leading edge): ts as for FLAP, t2 = t1 + A / (2K),
+ *        G(ts) = log[cosh(a_s (ts - t1)) / cosh(a_s (ts - t2))] - a_s (t1 - t2),
+ *        alpha = A G / (2 a_s (t2 - t1)) (the supremum of G, so alpha -> A),
+ *        r_j = (p[0], p[1]) + (xb cos a + yb sin a, -xb sin a + yb cos a).
+ *        p = {x0, y0, A, a_s, K, t1, -, -, U_ref, chord}; a_s, K > 0.
+ * TRI  : the smoothed asymmetric triangular pitching law of Sec. 3.6 about
+ *        (p[0], p[1]), period T in ts units (T = pi / k for reduced
+ *        frequency k = pi f c / U), ta = p[5] T: ramps of rate
+ *        2 alpha0 / (xi T - ta) and -2 alpha0 / ((1 - xi) T - ta) joined by
+ *        quartic blends of duration ta before and after each extreme
+ *        +alpha0 at ts = xi T / 2 and -alpha0 at ts = T (1 - xi / 2); the
+ *        quartics use ta in every denominator (the only choice that keeps
+ *        alpha and its rate continuous).  alpha(0) = 0, rising.
+ *        p = {x0, y0, alpha0, xi, T, ta/T, -, -, U_ref, chord};
+ *        0 < xi < 1, 0 < ta/T <= min(xi, 1 - xi) / 2.
+ * Every moving kind: desired velocity u_d = r_j(t + 1) - r_j(t). */
+enum { SBT_BODY_FIXED = 0, SBT_BODY_FLAP = 1, SBT_BODY_HOST = 2, SBT_BODY_RAMP = 3, SBT_BODY_TRI = 4 };
 
 typedef struct {
     int32_t level;                 /* >= 1                                        */
@@ -193,6 +212,40 @@ sbt_status sbt_read_force_history(sbt_ctx *ctx, int32_t c, int32_t cap, double *
  * sum_i c_i f_i, weighted by the cell volume 4^-l.  Computed on the device in
  * FP64 with a fixed reduction order. */
 sbt_status sbt_diagnostics(sbt_ctx *ctx, int32_t c, double out[3]);
+
+/* Force-coefficient statistics of Sec. 3.3, Eq. (21), over the most recent
+ * min(n_last, recorded, history_cap) finest substeps of the force history:
+ * C_D = F_s,x / (rho0 U^2 L / 2), C_L = F_s,y / (rho0 U^2 L / 2), with U the
+ * reference velocity (lattice units) and L the reference length (finest
+ * cells).  out = {mean C_D, mean C_L, rms of C_D about its mean (C_D'), rms
+ * of C_L about its mean (C_L'), St, upward crossings of C_L through its mean,
+ * samples}.  St = f L / U, where f is the lift frequency taken from the
+ * history: (crossings - 1) periods between the first and the last upward
+ * crossing, crossing times interpolated linearly between substeps (finest
+ * substeps as the time unit); St = 0 with fewer than two crossings.
+ * Computed on the device in FP64 (fixed reduction order).  Errors:
+ * SBT_ERR_ARG (n_last <= 0, U or L not positive, null out), SBT_ERR_STATE
+ * (no body, or fewer than two recorded substeps).  Synchronises. */
+sbt_status sbt_force_stats(sbt_ctx *ctx, int32_t c, int32_t n_last, double U, double L, double out[7]);
+
+/* Convergence criterion of Sec. 3.2: E = sum_x |u(x, t) - u(x, t0)| /
+ * sum_x |u(x, t)| over the leaf cells x of the case (owned cells not covered
+ * by a finer level, every level), each weighted by its area 4^-l (a uniform
+ * grid gives the paper's plain sums); |.| is the Euclidean norm of the
+ * velocity (Eq. (8) without the IBM force, as sbt_read_fields).  The velocity
+ * at t0 lives in a caller-owned DEVICE buffer `snapshot` (8-byte aligned, at
+ * least sbt_snapshot_bytes; layout [level][owned block][ux, uy][256] FP64,
+ * levels in order, blocks in sbt_level_blocks order; covered cells hold 0).
+ * mode SBT_SNAP_STORE: the snapshot takes the current velocity (out unused,
+ * may be NULL); SBT_SNAP_COMPARE: out = {sum |u - u0|, sum |u|, E};
+ * both: compare, then store (a rolling check every fixed number of steps,
+ * 1000 in the paper).  Device reductions in FP64, fixed order.  Errors:
+ * SBT_ERR_ARG (bad mode, null or misaligned snapshot), SBT_ERR_BUFSIZE.
+ * Synchronises. */
+enum { SBT_SNAP_STORE = 1, SBT_SNAP_COMPARE = 2 };
+sbt_status sbt_snapshot_bytes(sbt_ctx *ctx, int32_t c, size_t *bytes);
+sbt_status sbt_convergence(sbt_ctx *ctx, int32_t c, void *snapshot, size_t bytes, int32_t mode,
+                           double out[3]);
 
 /* Checkpoint: raw state (populations of both lattices of every level, halo
  * cells, substep counters, marker forces, force history).  sbt_state_bytes

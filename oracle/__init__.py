@@ -71,6 +71,9 @@ def lib():
         _lib.orc_phi.argtypes = [C.c_double]
         _lib.orc_phi.restype = C.c_double
         _lib.orc_body_positions.argtypes = [C.POINTER(_Case), C.c_double, d, d]
+        for f in (_lib.orc_ramp_alpha, _lib.orc_tri_alpha):
+            f.argtypes = [d, C.c_double]
+            f.restype = C.c_double
         _lib.orc_mdf.argtypes = [C.c_int32, C.c_int32, d, d, d, d, d, C.c_int32, d, d, d, d, d,
                                  C.c_int32, d, d]
         _lib.orc_interpolate.argtypes = [C.c_int32, C.c_int32, d, d, C.c_int32, d, d, d, d]
@@ -245,6 +248,18 @@ def body_positions(wl, k):
     if rc:
         raise RuntimeError(rc)
     return X, Y
+
+
+def ramp_alpha(p, tstar):
+    """Pitch angle of the Sec. 3.5 ramp law at t* (p: the body's 16 parameters)."""
+    p = _f64(np.asarray(p, dtype=np.float64))
+    return lib().orc_ramp_alpha(_dp(p), float(tstar))
+
+
+def tri_alpha(p, tstar):
+    """Pitch angle of the Sec. 3.6 smoothed triangular law at t*."""
+    p = _f64(np.asarray(p, dtype=np.float64))
+    return lib().orc_tri_alpha(_dp(p), float(tstar))
 
 
 def mdf(rho, ux, uy, X, Y, udx, udy, ds, iters):

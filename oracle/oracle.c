@@ -136,13 +136,62 @@ double orc_phi(double r) {
     return 0.0;
 }
 
+/* Pitch-up ramp of Sec. 3.5 (Eldredge's smoothing function G):
+ *   G(t*) = log[cosh(a_s (t* - t1*)) / cosh(a_s (t* - t2*))] - a_s (t1* - t2*),
+ *   t2* = t1* + A / (2K),   alpha = A G / max G.
+ * G rises monotonically from 0 to its supremum 2 a_s (t2* - t1*), the value
+ * the paper calls approximately max G; that supremum is used, so alpha ends
+ * at A.  log cosh is evaluated as |x| - log 2 + log1p(exp(-2|x|)), the same
+ * function without the overflow of cosh for |x| > 710.
+ * p = {x0, y0, A, a_s, K, t1*, -, -, U_ref, c}. */
+static double logcosh(double x) {
+    double a = fabs(x);
+    return a - M_LN2 + log1p(exp(-2.0 * a));
+}
+
+double orc_ramp_alpha(const double *p, double tstar) {
+    double A = p[2], as = p[3], K = p[4], t1 = p[5];
+    double t2 = t1 + A / (2.0 * K);
+    double G = logcosh(as * (tstar - t1)) - logcosh(as * (tstar - t2)) - as * (t1 - t2);
+    return A * G / (2.0 * as * (t2 - t1));
+}
+
+/* Smoothed asymmetric triangular pitching of Sec. 3.6 (E5): straight ramps
+ * of rate adot1 = 2 alpha0 / (xi T - ta) and adot2 = -2 alpha0 / ((1 - xi) T - ta)
+ * joined at the extremes alpha0 (t2 = xi T / 2) and -alpha0 (t5 = T (1 - xi/2))
+ * by quartics of duration ta on each side.  The printed law has t2 in place
+ * of ta in some quartic denominators; only ta makes alpha and its rate
+ * continuous at every breakpoint, so ta is used throughout.  Time runs in
+ * t* = t U_ref / c, periodic in T.
+ * p = {x0, y0, alpha0, xi, T, ta/T, -, -, U_ref, c}. */
+double orc_tri_alpha(const double *p, double tstar) {
+    double a0 = p[2], xi = p[3], T = p[4], ta = p[5] * p[4];
+    double r1 = 2.0 * a0 / (xi * T - ta);
+    double r2 = -2.0 * a0 / ((1.0 - xi) * T - ta);
+    double t2 = 0.5 * xi * T, t1 = t2 - ta, t3 = t2 + ta;
+    double t5 = T * (1.0 - 0.5 * xi), t4 = t5 - ta, t6 = t5 + ta;
+    double t = fmod(tstar, T);
+    if (t < 0.0) t += T;
+    double ta2 = ta * ta, ta3 = ta2 * ta;
+    if (t < t1) return r1 * t;
+    if (t < t2) { double s = t - t2; return r1 / (2.0 * ta3) * s * s * s * s + r1 / ta2 * s * s * s + a0; }
+    if (t < t3) { double s = t - t2; return -r2 / (2.0 * ta3) * s * s * s * s + r2 / ta2 * s * s * s + a0; }
+    if (t < t4) return r2 * (t - t4) - r2 * ta / 2.0 - a0;
+    if (t < t5) { double s = t - t5; return r2 / (2.0 * ta3) * s * s * s * s + r2 / ta2 * s * s * s - a0; }
+    if (t < t6) { double s = t - t5; return -r1 / (2.0 * ta3) * s * s * s * s + r1 / ta2 * s * s * s - a0; }
+    return r1 * (t - T);
+}
+
 /* Kinematics.  FIXED: X = (x0 + xb, y0 + yb).  FLAP (Sec. 3.6 law, with the
  * pitch amplitude and stroke angle as parameters):
  *   t* = t U_ref / c,  theta = 2 pi t* / T
  *   alpha = alpha0 - A_pitch sin(theta + phi)
  *   (xc, yc) = (x0, y0) + (A0/2) cos(theta) (cos beta, sin beta)
- *   X = xc + xb cos(alpha) + yb sin(alpha),  Y = yc - xb sin(alpha) + yb cos(alpha)
- * bp = {x0, y0, alpha0, A_pitch, A0, beta, T, phi, U_ref, c}. */
+ * bp = {x0, y0, alpha0, A_pitch, A0, beta, T, phi, U_ref, c}.
+ * RAMP and TRI: pure pitch alpha(t*) (orc_ramp_alpha, orc_tri_alpha) about
+ * the pivot (xc, yc) = (x0, y0), t* = t U_ref / c.
+ * Every moving body: X = xc + xb cos(alpha) + yb sin(alpha),
+ *                    Y = yc - xb sin(alpha) + yb cos(alpha). */
 int orc_body_positions(const orc_case *c, double k, double *X, double *Y) {
     const double *p = c->bp;
     if (c->body_kind == ORC_BODY_FIXED) {
@@ -153,13 +202,21 @@ int orc_body_positions(const orc_case *c, double k, double *X, double *Y) {
         for (int j = 0; j < c->n_markers; ++j) { X[j] = c->xb[j]; Y[j] = c->yb[j]; }
         return ORC_OK;
     }
-    if (c->body_kind != ORC_BODY_FLAP) return ORC_ERR_ARG;
     double tstar = k * p[8] / p[9];
-    double theta = 2.0 * M_PI * tstar / p[6];
-    double alpha = p[2] - p[3] * sin(theta + p[7]);
-    double h = 0.5 * p[4] * cos(theta);
-    double xc = p[0] + h * cos(p[5]);
-    double yc = p[1] + h * sin(p[5]);
+    double alpha, xc = p[0], yc = p[1];
+    if (c->body_kind == ORC_BODY_FLAP) {
+        double theta = 2.0 * M_PI * tstar / p[6];
+        alpha = p[2] - p[3] * sin(theta + p[7]);
+        double h = 0.5 * p[4] * cos(theta);
+        xc = p[0] + h * cos(p[5]);
+        yc = p[1] + h * sin(p[5]);
+    } else if (c->body_kind == ORC_BODY_RAMP) {
+        alpha = orc_ramp_alpha(p, tstar);
+    } else if (c->body_kind == ORC_BODY_TRI) {
+        alpha = orc_tri_alpha(p, tstar);
+    } else {
+        return ORC_ERR_ARG;
+    }
     double ca = cos(alpha), sa = sin(alpha);
     for (int j = 0; j < c->n_markers; ++j) {
         X[j] = xc + c->xb[j] * ca + c->yb[j] * sa;

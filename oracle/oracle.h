@@ -27,7 +27,8 @@ enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_TOPOLOGY = -2, ORC_ERR_MARKER = -7 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_WALL = 1, ORC_BC_INFLOW = 2, ORC_BC_OUTFLOW = 3,
        ORC_BC_SYMMETRY = 4 };
 enum { ORC_CF_HOMOGENEOUS = 0, ORC_CF_RESCALE = 1 };
-enum { ORC_BODY_NONE = -1, ORC_BODY_FIXED = 0, ORC_BODY_FLAP = 1, ORC_BODY_HOST = 2 };
+enum { ORC_BODY_NONE = -1, ORC_BODY_FIXED = 0, ORC_BODY_FLAP = 1, ORC_BODY_HOST = 2,
+       ORC_BODY_RAMP = 3, ORC_BODY_TRI = 4 };
 enum { ORC_W = 0, ORC_E = 1, ORC_S = 2, ORC_N = 3 };
 
 typedef struct {
@@ -87,6 +88,9 @@ void   orc_collide_cell(double tau, const double f[9], double Fx, double Fy, dou
 double orc_phi(double r);
 /* Marker positions of the body at finest substep k (time t_k = k). */
 int    orc_body_positions(const orc_case *c, double k, double *X, double *Y);
+/* Pitch angle of the ramp (Sec. 3.5) and triangular (Sec. 3.6) laws at t*. */
+double orc_ramp_alpha(const double *p, double tstar);
+double orc_tri_alpha(const double *p, double tstar);
 /* The multi-direct-forcing loop on a dense periodic nx x ny grid of cell
  * moments: rho (fixed), u (corrected in place), F (accumulated in place);
  * markers X, Y, desired velocity ud, arc length ds; returns the per-marker

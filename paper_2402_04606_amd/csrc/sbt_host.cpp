@@ -419,7 +419,7 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
   X.stage_blocks = max_blocks;
   X.d_stage = (double *)cv.take(sizeof(double) * 3 * kCells * max_blocks);
   X.d_partial = (double *)cv.take(sizeof(double) * 3 * max_blocks);
-  X.d_diag = (double *)cv.take(sizeof(double) * 4);
+  X.d_diag = (double *)cv.take(sizeof(double) * 16);  // diagnostics [0, 4), force stats [4, 12), E [12, 16)
   X.d_err = (int32_t *)cv.take(sizeof(int32_t) * 4);
   X.d_cases = (CaseDev *)cv.take(sizeof(CaseDev) * n_cases);
   for (auto &Gr : X.groups) {
@@ -1196,10 +1196,20 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
   if (!C.has_body) return fail(SBT_ERR_ARG, "case was created with max_markers = 0");
   if (!body || body->n <= 0 || body->n > C.d.max_markers) return fail(SBT_ERR_ARG, "marker count out of range");
   if (!body->xb || !body->yb || !body->ds) return fail(SBT_ERR_ARG, "null marker arrays");
-  if (body->kind != SBT_BODY_FIXED && body->kind != SBT_BODY_FLAP && body->kind != SBT_BODY_HOST)
-    return fail(SBT_ERR_ARG, "bad body kind");
-  if (body->kind == SBT_BODY_FLAP && (body->p[6] == 0.0 || body->p[9] == 0.0))
-    return fail(SBT_ERR_ARG, "flap period and chord must be nonzero");
+  if (body->kind < SBT_BODY_FIXED || body->kind > SBT_BODY_TRI) return fail(SBT_ERR_ARG, "bad body kind");
+  for (int i = 0; i < 16; ++i)
+    if (!std::isfinite(body->p[i])) return fail(SBT_ERR_ARG, "kinematic parameters must be finite");
+  {
+    const double *p = body->p;
+    const bool moving = body->kind == SBT_BODY_FLAP || body->kind == SBT_BODY_RAMP || body->kind == SBT_BODY_TRI;
+    if (moving && (p[8] == 0.0 || p[9] == 0.0)) return fail(SBT_ERR_ARG, "U_ref and chord must be nonzero");
+    if (body->kind == SBT_BODY_FLAP && p[6] == 0.0) return fail(SBT_ERR_ARG, "flap period must be nonzero");
+    if (body->kind == SBT_BODY_RAMP && !(p[3] > 0.0 && p[4] > 0.0 && p[2] != 0.0))
+      return fail(SBT_ERR_ARG, "ramp needs A != 0, a_s > 0 and K > 0");
+    if (body->kind == SBT_BODY_TRI &&
+        !(p[3] > 0.0 && p[3] < 1.0 && p[4] > 0.0 && p[5] > 0.0 && 2.0 * p[5] <= std::min(p[3], 1.0 - p[3])))
+      return fail(SBT_ERR_ARG, "triangular law needs 0 < xi < 1, T > 0 and 0 < ta/T <= min(xi, 1 - xi)/2");
+  }
   {
     int dev = 0, lds_max = 0;
     HIPCHK(hipGetDevice(&dev));
@@ -1370,6 +1380,54 @@ sbt_status sbt_diagnostics(sbt_ctx *ctx, int32_t c, double out[3]) {
   return SBT_OK;
 }
 
+sbt_status sbt_snapshot_bytes(sbt_ctx *ctx, int32_t c, size_t *bytes) {
+  sbt_status st = check_case(ctx, c);
+  if (st) return st;
+  if (!bytes) return fail(SBT_ERR_ARG, "null output");
+  const CaseHost &C = ctx->cs[c];
+  size_t n = 0;
+  for (int l = 0; l < C.F.m; ++l) n += (size_t)(C.lr[l].own1 - C.lr[l].own0);
+  *bytes = n * 2 * kCells * sizeof(double);
+  return SBT_OK;
+}
+
+sbt_status sbt_convergence(sbt_ctx *ctx, int32_t c, void *snapshot, size_t bytes, int32_t mode, double out[3]) {
+  sbt_status st = check_case(ctx, c);
+  if (st) return st;
+  size_t need = 0;
+  sbt_snapshot_bytes(ctx, c, &need);
+  if (mode < SBT_SNAP_STORE || mode > (SBT_SNAP_STORE | SBT_SNAP_COMPARE)) return fail(SBT_ERR_ARG, "bad mode");
+  if (!snapshot || ((uintptr_t)snapshot & 7)) return fail(SBT_ERR_ARG, "snapshot must be an 8-byte aligned device pointer");
+  if (bytes < need) return fail(SBT_ERR_BUFSIZE, "snapshot needs " + std::to_string(need) + " bytes");
+  if ((mode & SBT_SNAP_COMPARE) && !out) return fail(SBT_ERR_ARG, "null output");
+  sbt_ctx &X = *ctx;
+  CaseHost &C = X.cs[c];
+  double *snap = (double *)snapshot;
+  double *acc = X.d_diag + 12;
+  for (int l = 0; l < C.F.m; ++l) {
+    const int n = C.lr[l].own1 - C.lr[l].own0;
+    st = readout_level(X, c, l, X.stream);
+    if (st) return st;
+    const Pool &P = X.pools[(size_t)C.group * X.V + C.lr[l].v];
+    HIPCHK(sbt_launch_velocity_change(P.d_meta, P.d_codes, C.lr[l].own0, n, X.d_stage, snap, mode, X.d_partial,
+                                      X.stream));
+    if (mode & SBT_SNAP_COMPARE)
+      HIPCHK(sbt_launch_reduce(X.d_partial, n, 1.0 / (double)(1 << (2 * l)), acc, l > 0 ? 1 : 0, X.stream));
+    snap += (size_t)n * 2 * kCells;
+  }
+  if (mode & SBT_SNAP_COMPARE) {
+    double h[3];
+    HIPCHK(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, X.stream));
+    HIPCHK(hipStreamSynchronize(X.stream));
+    out[0] = h[0];
+    out[1] = h[1];
+    out[2] = h[0] / h[1];
+  } else {
+    HIPCHK(hipStreamSynchronize(X.stream));
+  }
+  return SBT_OK;
+}
+
 static int64_t read_kcount(sbt_ctx &X, CaseHost &C) {
   int64_t k = 0;
   if (hipMemcpyAsync(&k, C.dev.kcount, sizeof(k), hipMemcpyDeviceToHost, X.stream) != hipSuccess) return -1;
@@ -1419,6 +1477,25 @@ sbt_status sbt_read_force_history(sbt_ctx *ctx, int32_t c, int32_t cap, double *
     fy[t] = h[2 * slot + 1];
   }
   *n_out = (int32_t)n;
+  return SBT_OK;
+}
+
+sbt_status sbt_force_stats(sbt_ctx *ctx, int32_t c, int32_t n_last, double U, double L, double out[7]) {
+  sbt_status st = check_case(ctx, c);
+  if (st) return st;
+  if (!out || n_last <= 0 || !(U > 0.0) || !(L > 0.0)) return fail(SBT_ERR_ARG, "need n_last > 0, U > 0, L > 0, out");
+  sbt_ctx &X = *ctx;
+  CaseHost &C = X.cs[c];
+  if (!C.has_body || C.n_markers == 0) return fail(SBT_ERR_STATE, "case has no body");
+  int64_t k = read_kcount(X, C);
+  if (k < 0) return fail(SBT_ERR_DEVICE, "kcount read");
+  const int64_t done = X.post ? k - 1 : 0;
+  const int64_t n = std::min<int64_t>({done, (int64_t)n_last, (int64_t)C.hist_cap});
+  if (n < 2) return fail(SBT_ERR_STATE, "fewer than two recorded substeps");
+  const double scale = 1.0 / (0.5 * C.dev.rho0 * U * U * L);
+  HIPCHK(sbt_launch_force_stats(C.dev.hist, (int64_t)C.hist_cap, done - n, n, scale, L / U, X.d_diag + 4, X.stream));
+  HIPCHK(hipMemcpyAsync(out, X.d_diag + 4, sizeof(double) * 7, hipMemcpyDeviceToHost, X.stream));
+  HIPCHK(hipStreamSynchronize(X.stream));
   return SBT_OK;
 }
 

@@ -1091,23 +1091,71 @@ struct Pose {
   double xc, yc, ca, sa;
 };
 
+// log cosh x without the overflow of cosh: |x| - log 2 + log1p(e^-2|x|).
+__device__ __forceinline__ double log_cosh(double x) {
+#pragma clang fp contract(off)
+  const double a = fabs(x);
+  return a - 0.69314718055994530942 + log1p(exp(-2.0 * a));
+}
+
+// Pitch angle at nondimensional time ts (= k U_ref / c) of the moving kinds.
+//  FLAP (Sec. 3.6): alpha0 - A_pitch sin(2 pi ts / T + phi).
+//  RAMP (Sec. 3.5): A G(ts) / sup G with Eldredge's smoothing
+//    G = log cosh(a_s (ts - t1)) - log cosh(a_s (ts - t2)) + a_s (t2 - t1),
+//    t2 = t1 + A / (2K), sup G = 2 a_s (t2 - t1); p = {x0, y0, A, a_s, K, t1}.
+//  TRI (Sec. 3.6, E5): period T of two straight ramps (rates r1 > 0, r2 < 0)
+//    blended into the extremes +-alpha0 by quartics of duration ta on both
+//    sides of t2 = xi T / 2 and t5 = T (1 - xi / 2); p = {x0, y0, alpha0, xi,
+//    T, ta / T}.  Every blend is r (s^3 / ta^2 +- s^4 / (2 ta^3)) away from the
+//    extreme, s = t - t_extreme, which keeps alpha and its rate continuous.
+__device__ __forceinline__ double pitch_angle(const CaseDev &cp, double ts) {
+#pragma clang fp contract(off)
+  const double *p = cp.bp;
+  if (cp.body_kind == 1) return p[2] - p[3] * sin(2.0 * M_PI * ts / p[6] + p[7]);
+  if (cp.body_kind == 3) {
+    const double A = p[2], as = p[3];
+    const double t1 = p[5], t2 = t1 + A / (2.0 * p[4]);
+    const double g = log_cosh(as * (ts - t1)) - log_cosh(as * (ts - t2)) - as * (t1 - t2);
+    return A * g / (2.0 * as * (t2 - t1));
+  }
+  // kind 4
+  const double a0 = p[2], xi = p[3], T = p[4], ta = p[5] * p[4];
+  const double r1 = 2.0 * a0 / (xi * T - ta);
+  const double r2 = -2.0 * a0 / ((1.0 - xi) * T - ta);
+  const double te = 0.5 * xi * T;            // +alpha0
+  const double tm = T * (1.0 - 0.5 * xi);    // -alpha0
+  double t = fmod(ts, T);
+  if (t < 0.0) t += T;
+  if (t < te - ta) return r1 * t;
+  if (t >= tm + ta) return r1 * (t - T);
+  if (t >= te + ta && t < tm - ta) return r2 * (t - (tm - ta)) - r2 * ta / 2.0 - a0;
+  // one of the four blends: extreme e, incoming/outgoing rate r, sign of s^4
+  const bool up = t < te + ta;
+  const double s = t - (up ? te : tm);
+  const double r = (up ? (s < 0.0 ? r1 : r2) : (s < 0.0 ? r2 : r1));
+  const double q = s < 0.0 ? 1.0 : -1.0;
+  const double ta2 = ta * ta, ta3 = ta2 * ta;
+  return q * r / (2.0 * ta3) * s * s * s * s + r / ta2 * s * s * s + (up ? a0 : -a0);
+}
+
 __device__ Pose body_pose(const CaseDev &cp, double k) {
 #pragma clang fp contract(off)
   const double *p = cp.bp;
   Pose r;
+  r.xc = p[0];
+  r.yc = p[1];
   if (cp.body_kind == 0) {
-    r.xc = p[0];
-    r.yc = p[1];
     r.ca = 1.0;
     r.sa = 0.0;
     return r;
   }
-  double tstar = k * p[8] / p[9];
-  double theta = 2.0 * M_PI * tstar / p[6];
-  double alpha = p[2] - p[3] * sin(theta + p[7]);
-  double h = 0.5 * p[4] * cos(theta);
-  r.xc = p[0] + h * cos(p[5]);
-  r.yc = p[1] + h * sin(p[5]);
+  const double tstar = k * p[8] / p[9];
+  const double alpha = pitch_angle(cp, tstar);
+  if (cp.body_kind == 1) {  // plunge along the stroke angle
+    const double h = 0.5 * p[4] * cos(2.0 * M_PI * tstar / p[6]);
+    r.xc = p[0] + h * cos(p[5]);
+    r.yc = p[1] + h * sin(p[5]);
+  }
   r.ca = cos(alpha);
   r.sa = sin(alpha);
   return r;

@@ -182,6 +182,21 @@ def test_moving_body_refined(env):
     assert np.abs(fyg - fyo).max() <= 1e-11 * np.abs(fyo).max()
 
 
+@pytest.mark.parametrize("make,steps", [(W.small_pitch_up, 16), (W.small_pitching_airfoil, 30)])
+def test_pitching_laws_refined(env, make, steps):
+    """Sec. 3.5 ramp (plate pitched about its leading edge) and Sec. 3.6
+    smoothed triangular law (over a full period, every breakpoint) on a
+    3-level forest: fields and force history against the oracle."""
+    wl = make()
+    g, o = run_pair(env, wl, steps)
+    compare_levels(g, o, wl, TOL64)
+    fxg, fyg = g.force_history()
+    fxo, fyo = o.force_history()
+    assert len(fxg) == len(fxo) > 0
+    assert np.abs(fxg - fxo).max() <= 1e-11 * np.abs(fxo).max()
+    assert np.abs(fyg - fyo).max() <= 1e-11 * np.abs(fyo).max()
+
+
 def test_flapping_ellipse_four_levels(env):
     """Workload C4 (4 levels, 200 moving markers) at a short horizon."""
     wl = W.flapping_ellipse()

@@ -200,6 +200,95 @@ def test_flap_with_zero_amplitudes_is_fixed(orc):
         assert np.abs(Xm - Xf).max() < 1e-12 and np.abs(Ym - Yf).max() < 1e-12
 
 
+def _ramp(orc, **kw):
+    p = W.ramp_params(100.0, 50.0, 32.0, 0.05, **kw)
+    return p, (lambda t: orc.ramp_alpha(p, t))
+
+
+@pytest.mark.parametrize("A,a_s,K,t1", [(math.pi / 2, 11.0, 0.2, 1.0), (0.7, 4.0, 0.05, 0.3)])
+def test_ramp_law_closed_forms(orc, A, a_s, K, t1):
+    """Sec. 3.5 ramp.  G is 0 long before t1 and 2 a_s (t2 - t1) long after t2
+    (t2 = t1 + A / (2K)), so alpha runs from 0 to A; it is point-symmetric about
+    the mid-ramp, alpha(t) + alpha(t1 + t2 - t) = A; G(t1) = log 2 up to
+    exp(-2 a_s (t2 - t1)); and the mid-ramp rate is dalpha/dt* = 2K, the
+    definition of the pitch rate K = alpha_dot c / (2 U)."""
+    p, al = _ramp(orc, A=A, a_s=a_s, K=K, t1=t1)
+    t2 = t1 + A / (2 * K)
+    span = 2 * a_s * (t2 - t1)
+    assert abs(al(t1 - 40.0 / a_s)) < 1e-12 * A
+    assert abs(al(t2 + 40.0 / a_s) - A) < 1e-12 * A
+    assert abs(al(t2 + 2000.0) - A) < 1e-12 * A          # no overflow far past the ramp
+    for t in (t1 - 1.0, t1, 0.5 * (t1 + t2) + 0.3 * (t2 - t1), t2 + 0.1):
+        assert abs(al(t) + al(t1 + t2 - t) - A) < 1e-12 * A
+    tail = math.exp(-2 * a_s * (t2 - t1))
+    assert abs(al(t1) - A * math.log(2.0) / span) < 1e-12 * A + 2 * A * tail
+    assert abs(al(0.5 * (t1 + t2)) - 0.5 * A) < 1e-13 * A
+    h, tm = 1e-4, 0.5 * (t1 + t2)
+    rate = (al(tm + h) - al(tm - h)) / (2 * h)
+    assert abs(rate - 2 * K) < 1e-7 * 2 * K + 4 * a_s * A * tail
+    ts = np.linspace(t1 - 2, t2 + 2, 2001)
+    a = np.array([al(t) for t in ts])
+    assert np.all(np.diff(a) >= -1e-15)                   # monotone ramp, no overshoot
+    assert a.max() <= A * (1 + 1e-14)
+
+
+@pytest.mark.parametrize("xi", [0.5, 0.35, 0.6])
+def test_triangular_law_closed_forms(orc, xi):
+    """Sec. 3.6 smoothed triangular law: alpha(0) = 0; extremes +alpha0 at
+    xi T / 2 and -alpha0 at T (1 - xi / 2) and nowhere beyond them; straight
+    ramps of the printed rates 2 alpha0 / (xi T - ta) and -2 alpha0 /
+    ((1 - xi) T - ta); alpha and its rate continuous at all six breakpoints
+    (this is what fixes the quartic denominators to ta); period T; and for
+    xi = 1/2 the second half-period mirrors the first."""
+    a0, T, taf = math.radians(64.0), math.pi / 0.22, 0.15
+    p = W.tri_params(0.0, 0.0, 64.0, 0.05, 64.0, 0.22, xi=xi, ta_frac=taf)
+    al = lambda t: orc.tri_alpha(p, t)
+    ta = taf * T
+    r1, r2 = 2 * a0 / (xi * T - ta), -2 * a0 / ((1 - xi) * T - ta)
+    te, tm = 0.5 * xi * T, T * (1 - 0.5 * xi)
+    assert al(0.0) == 0.0
+    assert abs(al(te) - a0) < 1e-14 and abs(al(tm) + a0) < 1e-14
+    h = 1e-6 * T
+    for t in (0.3 * (te - ta), te + ta + 0.5 * (tm - te - 2 * ta), tm + ta + 0.5 * (T - tm - ta)):
+        r = (al(t + h) - al(t - h)) / (2 * h)
+        want = r2 if te + ta < t < tm - ta else r1
+        assert abs(r - want) < 1e-7 * abs(want)
+    eps = 1e-9 * T
+    for b in (te - ta, te, te + ta, tm - ta, tm, tm + ta):
+        assert abs(al(b + eps) - al(b - eps)) < 1e-12 + 2 * eps * max(abs(r1), abs(r2))
+        left = (al(b - eps) - al(b - eps - h)) / h
+        right = (al(b + eps + h) - al(b + eps)) / h
+        assert abs(left - right) < 1e-4 * max(abs(r1), abs(r2)), (b, left, right)
+    ts = np.linspace(0.0, T, 4001)
+    a = np.array([al(t) for t in ts])
+    assert a.max() <= a0 * (1 + 1e-14) and a.min() >= -a0 * (1 + 1e-14)
+    for t in (0.1 * T, 0.55 * T, 0.93 * T):
+        assert abs(al(t + T) - al(t)) < 1e-12 and abs(al(t + 7 * T) - al(t)) < 1e-11
+    if xi == 0.5:
+        for t in ts[::97]:
+            assert abs(al(t + 0.5 * T) + al(t)) < 1e-12
+
+
+@pytest.mark.parametrize("make", [W.small_pitch_up, W.small_pitching_airfoil])
+def test_pitching_bodies_rotate_rigidly_about_the_pivot(orc, make):
+    """RAMP and TRI bodies: every marker keeps its distance to the pivot
+    (x0, y0) and to every other marker, and the chord line turns by exactly
+    the law's alpha (positive alpha: trailing edge down, nose up)."""
+    wl = make()
+    p = wl.body.params
+    law = orc.ramp_alpha if wl.body.kind == W.BODY_RAMP else orc.tri_alpha
+    xb, yb = np.asarray(wl.body.xb), np.asarray(wl.body.yb)
+    r0 = np.hypot(xb, yb)
+    j = int(np.argmax(xb))                                  # trailing-edge marker
+    for k in (0.0, 7.0, 40.5, 123.0, 1000.0):
+        X, Y = orc.body_positions(wl, k)
+        assert np.abs(np.hypot(X - p[0], Y - p[1]) - r0).max() < 1e-10
+        alpha = law(p, k * p[8] / p[9])
+        th0 = math.atan2(yb[j], xb[j])
+        th = math.atan2(Y[j] - p[1], X[j] - p[0])
+        assert abs(math.remainder(th0 - th - alpha, 2 * math.pi)) < 1e-10
+
+
 # ---- Whole-step invariants and closed forms ------------------------------
 
 def test_periodic_conservation_with_body_force(orc):

@@ -13,6 +13,9 @@ workloads this package is measured on:
   cavity(...)         Sec. 3.2 lid-driven cavity with a central cylinder,
                       3 levels of 16x16-cell blocks
   flapping_ellipse()  Sec. 3.5/3.6 pitching and plunging wing, 4 levels
+  pitch_up_plate()    Sec. 3.5 pitch-up ramp of a thin flat plate, 3 levels
+  pitching_airfoil()  Sec. 3.6 smoothed triangular pitching of a 18 %-thick
+                      symmetric section, 3 levels
   batch_sweep()       64 uneven flapping cases drawn from a fixed seed
 Plus small cases used as pins (Poiseuille channel, uniform flow on a refined
 forest, refined periodic band).
@@ -29,7 +32,7 @@ import numpy as np
 PERIODIC, WALL, INFLOW, OUTFLOW, SYMMETRY = 0, 1, 2, 3, 4
 W, E, S, N = 0, 1, 2, 3
 CF_HOMOGENEOUS, CF_RESCALE = 0, 1
-BODY_FIXED, BODY_FLAP, BODY_HOST = 0, 1, 2
+BODY_FIXED, BODY_FLAP, BODY_HOST, BODY_RAMP, BODY_TRI = 0, 1, 2, 3, 4
 
 
 @dataclasses.dataclass
@@ -41,6 +44,8 @@ class Body:
     params: list                   # 16 kinematic parameters
     # FIXED: params[0:2] = (x0, y0)
     # FLAP : (x0, y0, alpha0, A_pitch, A0, beta, T, phi, U_ref, chord)
+    # RAMP : (x0, y0, A, a_s, K, t1, -, -, U_ref, chord), pivot (x0, y0)
+    # TRI  : (x0, y0, alpha0, xi, T, ta/T, -, -, U_ref, chord), pivot (x0, y0)
 
 
 @dataclasses.dataclass
@@ -285,3 +290,119 @@ def small_refined_flap(Re=100.0, m=3):
     wl = flapping_case(256, m, 40.0, Re, 60, 2.5 * math.pi, name=f"small_flap{m}")
     assert wl is not None
     return wl
+
+
+# ---- pitch-up ramp (Sec. 3.5) and triangular pitching (Sec. 3.6) ------------
+
+def ramp_params(x0, y0, chord, U, A=math.pi / 2, a_s=11.0, K=0.2, t1=1.0):
+    """Sec. 3.5 ramp: amplitude A (rad), smoothing a_s, pitch rate K, start t1 (t* units)."""
+    return [x0, y0, A, a_s, K, t1, 0.0, 0.0, U, chord] + [0.0] * 6
+
+
+def tri_params(x0, y0, chord, U, alpha0_deg, k_red, xi=0.5, ta_frac=0.15):
+    """Sec. 3.6 triangular law: amplitude alpha0, reduced frequency k = pi f c / U
+    (period pi / k in t* = t U / c), asymmetry xi, blend time ta = ta_frac T."""
+    return [x0, y0, math.radians(alpha0_deg), xi, math.pi / k_red, ta_frac, 0.0, 0.0, U, chord] + [0.0] * 6
+
+
+def _resample_closed(x, y, n):
+    """n points at equal arc length along the closed polyline (x, y)."""
+    xs, ys = np.append(x, x[0]), np.append(y, y[0])
+    seg = np.hypot(np.diff(xs), np.diff(ys))
+    arc = np.concatenate([[0.0], np.cumsum(seg)])
+    target = arc[-1] * np.arange(n) / n
+    return np.interp(target, arc, xs), np.interp(target, arc, ys), np.full(n, arc[-1] / n)
+
+
+def plate_markers(chord, thickness, n):
+    """Outline of the rectangle [0, chord] x [-t/2, t/2] (leading edge at the
+    body-frame origin, the pivot of the ramp), n markers at equal spacing."""
+    h = 0.5 * thickness
+    x = np.array([0.0, chord, chord, 0.0])
+    y = np.array([-h, -h, h, h])
+    return _resample_closed(x, y, n)
+
+
+def naca_symmetric_markers(chord, t, n, pivot=0.25, samples=20000):
+    """Symmetric NACA four-digit section of thickness t (fraction of chord),
+    half-thickness 5 t c (0.2969 sqrt(s) - 0.1260 s - 0.3516 s^2 + 0.2843 s^3
+    - 0.1015 s^4), s = x / c, closed at the trailing edge; the body-frame
+    origin (pivot) sits at x = pivot * chord on the chord line."""
+    b = 0.5 * (1.0 - np.cos(np.linspace(0.0, math.pi, samples)))   # dense near both ends
+    yt = 5.0 * t * chord * (0.2969 * np.sqrt(b) - 0.1260 * b - 0.3516 * b ** 2 + 0.2843 * b ** 3
+                            - 0.1015 * b ** 4)
+    yt[-1] = 0.0
+    x = np.concatenate([b[::-1], b[1:-1]]) * chord - pivot * chord
+    y = np.concatenate([-yt[::-1], yt[1:-1]])
+    return _resample_closed(x, y, n)
+
+
+def _pitching_case(name, body_of, sweep_box, chord, m, Re, U, nx_c, ny_c, x_c, ds_target=0.65,
+                   perimeter=None):
+    """Inflow / outflow / symmetry channel nx_c x ny_c chords (level-0 cells =
+    chords * chord / 2^(m-1)); pivot at x_c chords from the inlet, mid-height;
+    refined boxes nest around the region the body sweeps (sweep_box, relative
+    to the pivot, finest cells)."""
+    B = 16
+    f = 2 ** (m - 1)
+    c0 = chord / f
+    nx0 = int(math.ceil(nx_c * c0 / B)) * B
+    ny0 = int(math.ceil(ny_c * c0 / B)) * B
+    xp, yp = x_c * chord, 0.5 * ny0 * f
+    sx0, sy0, sx1, sy1 = sweep_box
+    boxes = _nested_boxes((xp + sx0 - 6.0, yp + sy0 - 6.0, xp + sx1 + 6.0, yp + sy1 + 6.0), m, B, nx0, ny0)
+    assert boxes is not None, "refined region does not fit the channel"
+    n = int(round(perimeter / ds_target))
+    body = body_of(xp, yp, n)
+    nu_f = U * chord / Re
+    return Workload(name=name, nx0=nx0, ny0=ny0, n_levels=m, boxes=boxes, tau0=0.5 + 3 * nu_f / f,
+                    bc=(INFLOW, OUTFLOW, SYMMETRY, SYMMETRY), bc_u=((U, 0.0),) + ((0.0, 0.0),) * 3,
+                    body=body, init=uniform_init(1.0, U, 0.0),
+                    meta=dict(U=U, Re=Re, chord=chord, D=chord))
+
+
+def pitch_up_plate(chord=64.0, m=3, Re=1000.0, U=0.05, nx_c=70.0, ny_c=40.0, x_c=20.0,
+                   thickness=0.023, A=math.pi / 2, a_s=11.0, K=0.2, t1=1.0, name=None):
+    """Sec. 3.5: flat plate of 2.3 % thickness pitched up about its leading
+    edge from 0 to A by the smoothed ramp, Re = U c / nu, in a 70c x 40c
+    channel with 3 levels (streamwise length read as the longer side)."""
+    t = thickness * chord
+
+    def body_of(xp, yp, n):
+        xb, yb, ds = plate_markers(chord, t, n)
+        return Body(BODY_RAMP, xb, yb, ds, ramp_params(xp, yp, chord, U, A, a_s, K, t1))
+
+    reach = chord + t
+    return _pitching_case(name or f"pitch_up_plate_c{int(chord)}", body_of, (-reach, -reach, reach, t),
+                          chord, m, Re, U, nx_c, ny_c, x_c, perimeter=2.0 * (chord + t))
+
+
+def pitching_airfoil(chord=64.0, m=3, Re=1000.0, U=0.05, alpha0_deg=64.0, k_red=0.22, xi=0.5,
+                     ta_frac=0.15, thickness=0.18, pivot=0.25, nx_c=70.0, ny_c=40.0, x_c=20.0,
+                     name=None):
+    """Sec. 3.6: a symmetric 18 %-thick section pitching about its quarter
+    chord by the smoothed triangular law (alpha0, k, xi), same channel and
+    levels as the pitch-up plate."""
+    def body_of(xp, yp, n):
+        xb, yb, ds = naca_symmetric_markers(chord, thickness, n, pivot)
+        return Body(BODY_TRI, xb, yb, ds, tri_params(xp, yp, chord, U, alpha0_deg, k_red, xi, ta_frac))
+
+    reach = (1.0 - pivot) * chord + 1.0
+    return _pitching_case(name or f"pitching_airfoil_c{int(chord)}", body_of, (-reach, -reach, reach, reach),
+                          chord, m, Re, U, nx_c, ny_c, x_c, perimeter=2.04 * chord)
+
+
+def small_pitch_up(m=3, Re=100.0):
+    """Parity-test size of the ramp case: chord 32 finest cells, 16c x 12c
+    channel, ramp centred near the start (t1 = 0, K = 0.5) so that a short
+    run turns the plate at a trailing-edge speed near U."""
+    return pitch_up_plate(chord=32.0, m=m, Re=Re, nx_c=16.0, ny_c=12.0, x_c=5.0, t1=0.0, K=0.5,
+                          name=f"small_pitch_up{m}")
+
+
+def small_pitching_airfoil(m=3, Re=100.0):
+    """Parity-test size of the triangular case: alpha0 = 4 deg at k = 20 (a
+    period of about 100 finest substeps), so that a run of 30 coarse steps
+    crosses every breakpoint of the law."""
+    return pitching_airfoil(chord=32.0, m=m, Re=Re, alpha0_deg=4.0, k_red=20.0, nx_c=16.0, ny_c=12.0,
+                            x_c=5.0, name=f"small_pitching_airfoil{m}")
