@@ -78,6 +78,7 @@ def lib():
                                  C.c_int32, d, d]
         _lib.orc_interpolate.argtypes = [C.c_int32, C.c_int32, d, d, C.c_int32, d, d, d, d]
         _lib.orc_spread.argtypes = [C.c_int32, C.c_int32, C.c_int32, d, d, d, d, d, d, d]
+        _lib.orc_force_stats.argtypes = [d, d, C.c_int32, C.c_double, C.c_double, d]
         _lib.orc_num_threads.argtypes = []
     return _lib
 
@@ -199,6 +200,14 @@ class OracleSim:
         lib().orc_force_history(self._h, cap, _dp(fx), _dp(fy), C.byref(n))
         return fx[: n.value].copy(), fy[: n.value].copy()
 
+    def velocity(self):
+        """[(ux, uy)] per level, NaN off the leaf cells."""
+        out = []
+        for l in range(self.wl.n_levels):
+            _, ux, uy = self.fields(l)
+            out.append((ux, uy))
+        return out
+
     def diagnostics(self):
         out = np.zeros(3)
         lib().orc_diagnostics(self._h, _dp(out))
@@ -260,6 +269,33 @@ def tri_alpha(p, tstar):
     """Pitch angle of the Sec. 3.6 smoothed triangular law at t*."""
     p = _f64(np.asarray(p, dtype=np.float64))
     return lib().orc_tri_alpha(_dp(p), float(tstar))
+
+
+def force_stats(fx, fy, U, L, rho0=1.0):
+    """Sec. 3.3, Eq. (21) statistics of a force history: dict with CD_mean,
+    CL_mean, CD_rms, CL_rms, St, crossings, samples."""
+    fx, fy = _f64(fx), _f64(fy)
+    out = np.zeros(7)
+    rc = lib().orc_force_stats(_dp(fx), _dp(fy), len(fx), 1.0 / (0.5 * rho0 * U * U * L), L / U, _dp(out))
+    if rc:
+        raise RuntimeError(rc)
+    keys = ("CD_mean", "CL_mean", "CD_rms", "CL_rms", "St", "crossings", "samples")
+    return dict(zip(keys, out.tolist()))
+
+
+def velocity_change(now, then):
+    """Sec. 3.2 convergence measure between two velocity states, each a list
+    over levels l of (ux, uy) dense arrays that are NaN off the level's leaf
+    cells (owned, not covered by level l+1), as OracleSim.velocity() gives:
+    returns (sum |u - u0|, sum |u|, E = ratio), every cell weighted by its
+    area 4^-l, |.| the Euclidean norm."""
+    num = den = 0.0
+    for l, ((ux, uy), (vx, vy)) in enumerate(zip(now, then)):
+        m = ~np.isnan(ux)
+        w = 0.25 ** l
+        num += w * np.sum(np.hypot(ux[m] - vx[m], uy[m] - vy[m]))
+        den += w * np.sum(np.hypot(ux[m], uy[m]))
+    return num, den, num / den
 
 
 def mdf(rho, ux, uy, X, Y, udx, udy, ds, iters):

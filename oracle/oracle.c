@@ -868,3 +868,43 @@ int orc_diagnostics(const orc_sim *s, double out[3]) {
     out[0] = M; out[1] = Px; out[2] = Py;
     return ORC_OK;
 }
+
+/* Sec. 3.3, Eq. (21): statistics of the coefficient histories
+ * C_D = scale fx, C_L = scale fy (scale = 1 / (rho0 U^2 L / 2)), n samples
+ * one finest substep apart.  out = {mean C_D, mean C_L, rms(C_D - mean),
+ * rms(C_L - mean), St, upward crossings, n}.  The lift frequency is read off
+ * the history as (crossings - 1) periods between the first and the last
+ * upward crossing of C_L through its mean, each crossing time interpolated
+ * linearly between the two samples around it; St = f L / U = f l_over_u. */
+int orc_force_stats(const double *fx, const double *fy, int32_t n, double scale, double l_over_u,
+                    double out[7]) {
+    if (n < 2) return ORC_ERR_ARG;
+    double sd = 0.0, sl = 0.0;
+    for (int32_t i = 0; i < n; ++i) { sd += fx[i] * scale; sl += fy[i] * scale; }
+    double md = sd / n, ml = sl / n;
+    double vd = 0.0, vl = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double dd = fx[i] * scale - md, dl = fy[i] * scale - ml;
+        vd += dd * dd;
+        vl += dl * dl;
+    }
+    int32_t up = 0;
+    double first = 0.0, last = 0.0;
+    for (int32_t i = 0; i + 1 < n; ++i) {
+        double c0 = fy[i] * scale - ml, c1 = fy[i + 1] * scale - ml;
+        if (c0 < 0.0 && c1 >= 0.0) {
+            double t = (double)i + c0 / (c0 - c1);
+            if (up == 0) first = t;
+            last = t;
+            ++up;
+        }
+    }
+    out[0] = md;
+    out[1] = ml;
+    out[2] = sqrt(vd / n);
+    out[3] = sqrt(vl / n);
+    out[4] = up >= 2 ? (double)(up - 1) / (last - first) * l_over_u : 0.0;
+    out[5] = up;
+    out[6] = n;
+    return ORC_OK;
+}

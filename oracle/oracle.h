@@ -106,6 +106,10 @@ int    orc_interpolate(int32_t nx, int32_t ny, const double *ux, const double *u
 int    orc_spread(int32_t nx, int32_t ny, int32_t n, const double *X, const double *Y,
                   const double *Fjx, const double *Fjy, const double *ds,
                   double *Fx, double *Fy);
+/* Eq. (21) statistics of a force history (coefficients C = scale F):
+ * out = {mean C_D, mean C_L, C_D', C_L', St, upward crossings, n}. */
+int    orc_force_stats(const double *fx, const double *fy, int32_t n, double scale,
+                       double l_over_u, double out[7]);
 int    orc_num_threads(void);
 
 #ifdef __cplusplus

@@ -28,7 +28,8 @@ ABI_SYMBOLS = [
     "sbt_plan", "sbt_create", "sbt_destroy", "sbt_level_blocks", "sbt_level_info", "sbt_init_fields",
     "sbt_init_uniform", "sbt_set_body", "sbt_set_markers", "sbt_step", "sbt_synchronize", "sbt_read_fields",
     "sbt_read_fields_blocks", "sbt_read_marker_forces",
-    "sbt_read_force_history", "sbt_diagnostics", "sbt_state_bytes", "sbt_read_state",
+    "sbt_read_force_history", "sbt_diagnostics", "sbt_force_stats", "sbt_snapshot_bytes",
+    "sbt_convergence", "sbt_state_bytes", "sbt_read_state",
     "sbt_write_state", "sbt_set_option", "sbt_autotune", "sbt_profile", "sbt_updates_per_step",
     "sbt_last_error",
 ]
@@ -90,6 +91,9 @@ def lib():
             "sbt_read_marker_forces": [vp, i32, d, d],
             "sbt_read_force_history": [vp, i32, i32, d, d, C.POINTER(i32)],
             "sbt_diagnostics": [vp, i32, d],
+            "sbt_force_stats": [vp, i32, i32, C.c_double, C.c_double, d],
+            "sbt_snapshot_bytes": [vp, i32, C.POINTER(C.c_size_t)],
+            "sbt_convergence": [vp, i32, vp, C.c_size_t, i32, d],
             "sbt_state_bytes": [vp, C.POINTER(C.c_size_t)],
             "sbt_read_state": [vp, vp, C.c_size_t],
             "sbt_write_state": [vp, vp, C.c_size_t],
@@ -292,6 +296,36 @@ class Sim:
     def diagnostics(self, c=0):
         out = np.zeros(3)
         _check(lib().sbt_diagnostics(self._h, c, _dp(out)))
+        return out
+
+    def force_stats(self, c=0, n_last=1 << 30, U=None, L=None):
+        """Eq. (21) statistics of the last n_last finest substeps (device
+        reduction): dict with CD_mean, CL_mean, CD_rms, CL_rms, St, crossings,
+        samples.  U, L default to the workload's meta U and D (or chord)."""
+        meta = self.workloads[c].meta or {}
+        U = meta["U"] if U is None else U
+        L = (meta.get("D") or meta.get("chord")) if L is None else L
+        out = np.zeros(7)
+        _check(lib().sbt_force_stats(self._h, c, int(min(n_last, 2 ** 31 - 1)), float(U), float(L), _dp(out)))
+        keys = ("CD_mean", "CL_mean", "CD_rms", "CL_rms", "St", "crossings", "samples")
+        return dict(zip(keys, out.tolist()))
+
+    def snapshot(self, c=0):
+        """A device buffer holding the velocity of every leaf cell now (for
+        convergence())."""
+        import torch
+        n = C.c_size_t()
+        _check(lib().sbt_snapshot_bytes(self._h, c, C.byref(n)))
+        buf = torch.empty(max(1, n.value // 8), dtype=torch.float64, device="cuda")
+        _check(lib().sbt_convergence(self._h, c, C.c_void_p(buf.data_ptr()), n.value, 1, None))
+        return buf
+
+    def convergence(self, snap, c=0, update=False):
+        """Sec. 3.2 criterion E of the current velocity against a snapshot
+        (sum |u - u0|, sum |u|, E); update=True also refreshes the snapshot."""
+        out = np.zeros(3)
+        _check(lib().sbt_convergence(self._h, c, C.c_void_p(snap.data_ptr()), snap.numel() * 8,
+                                     3 if update else 2, _dp(out)))
         return out
 
     def state_bytes(self):

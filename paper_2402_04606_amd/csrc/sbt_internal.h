@@ -159,6 +159,14 @@ size_t sbt_mdf_lds_bytes(int max_markers, int cell_cap);
 size_t sbt_prep_lds_bytes(int max_markers, int cell_cap, int lds_window);
 hipError_t sbt_launch_reduce(const double *partial, int n_blocks, double vol, double *out,
                              int accumulate, hipStream_t s);
+// Force statistics of history entries [first, first + n) (ring of cap
+// entries) into out[7]; velocity change / snapshot of one level's owned blocks
+// (sbt_stats.hip).
+hipError_t sbt_launch_force_stats(const double *hist, int64_t cap, int64_t first, int64_t n, double scale,
+                                  double l_over_u, double *out, hipStream_t s);
+hipError_t sbt_launch_velocity_change(const sbt::BlockMeta *meta, const uint16_t *codes, int b0, int n,
+                                      const double *fields, double *snap, int mode, double *partial,
+                                      hipStream_t s);
 hipError_t sbt_launch_fill_nan(void *p, size_t n_elems, int storage, hipStream_t s);
 // f = f^eq(rho, u) on the owned cells of blocks [b0, b0+n) from per-block FP64
 // fields [n][3][256], or from the constant state u0 = {rho, ux, uy} when

@@ -197,6 +197,47 @@ def test_pitching_laws_refined(env, make, steps):
     assert np.abs(fyg - fyo).max() <= 1e-11 * np.abs(fyo).max()
 
 
+def test_force_stats_and_convergence_on_device(env):
+    """Eq. (21) statistics reduced on the device against the oracle's reading
+    of the same history, and against the oracle run's own history; the
+    Sec. 3.2 measure E against the oracle's fields; a refreshed snapshot
+    reads E = 0."""
+    import oracle
+    wl = W.small_pitching_airfoil()
+    P, O = env
+    g = P.Sim(wl, "f64")
+    o = O.OracleSim(wl)
+    g.step(10)
+    o.step(10)
+    snap = g.snapshot()
+    then = o.velocity()
+    g.step(20)
+    o.step(20)
+    g.synchronize()
+    U, L = wl.meta["U"], wl.meta["chord"]
+    fxg, fyg = g.force_history()
+    sd = g.force_stats(U=U, L=L)
+    so = oracle.force_stats(fxg, fyg, U, L)
+    sr = oracle.force_stats(*o.force_history(), U, L)
+    print("  device", sd, "\n  oracle", sr, flush=True)
+    assert sd["samples"] == so["samples"] == len(fxg) == sr["samples"]
+    assert sd["crossings"] == so["crossings"] == sr["crossings"] >= 2
+    for key in ("CD_mean", "CL_mean", "CD_rms", "CL_rms", "St"):
+        assert abs(sd[key] - so[key]) <= 1e-12 * abs(so[key]), key
+        assert abs(sd[key] - sr[key]) <= 1e-9 * abs(sr[key]), key
+    # the last 50 substeps only
+    sd50 = g.force_stats(n_last=50, U=U, L=L)
+    so50 = oracle.force_stats(fxg[-50:], fyg[-50:], U, L)
+    assert sd50["samples"] == 50 and abs(sd50["CL_rms"] - so50["CL_rms"]) <= 1e-12 * so50["CL_rms"]
+    Eg = g.convergence(snap, update=True)
+    Eo = oracle.velocity_change(o.velocity(), then)
+    print(f"  E device {Eg[2]:.15e} oracle {Eo[2]:.15e}", flush=True)
+    assert Eg[2] > 0.0
+    for a, b in zip(Eg, Eo):
+        assert abs(a - b) <= 1e-10 * abs(b)
+    assert g.convergence(snap)[0] == 0.0
+
+
 def test_flapping_ellipse_four_levels(env):
     """Workload C4 (4 levels, 200 moving markers) at a short horizon."""
     wl = W.flapping_ellipse()

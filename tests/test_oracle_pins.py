@@ -289,6 +289,79 @@ def test_pitching_bodies_rotate_rigidly_about_the_pivot(orc, make):
         assert abs(math.remainder(th0 - th - alpha, 2 * math.pi)) < 1e-10
 
 
+# ---- Run statistics (Sec. 3.2 criterion E, Sec. 3.3 Eq. (21)) ------------
+
+def test_force_stats_of_a_sampled_sinusoid(orc):
+    """Lift A sin(2 pi t / P + phi) + b over whole periods of P samples: mean
+    b and rms A / sqrt(2) exactly (sums of sampled sines over whole periods
+    vanish); St = L / (P U) from the crossings; drag constant -> rms 0."""
+    U, L, P, periods, A, b, cd = 0.05, 20.0, 100, 30, 0.7, 0.2, 1.4
+    t = np.arange(P * periods)
+    scale = 0.5 * U * U * L
+    fy = (A * np.sin(2 * np.pi * t / P + 0.3) + b) * scale
+    fx = np.full(len(t), cd * scale)
+    r = orc.force_stats(fx, fy, U, L)
+    assert abs(r["CL_mean"] - b) < 1e-13 and abs(r["CL_rms"] - A / math.sqrt(2)) < 1e-13
+    assert abs(r["CD_mean"] - cd) < 1e-13 and r["CD_rms"] < 1e-13
+    assert r["crossings"] in (periods - 1, periods) and r["samples"] == len(t)
+    assert abs(r["St"] - L / (P * U)) < 1e-6 * L / (P * U)
+
+
+def test_force_stats_against_numpy_on_noise(orc):
+    """Means and rms deviations against numpy's mean and std; the crossing
+    count and the first and last crossing against a brute-force scan."""
+    rng = np.random.default_rng(7)
+    n, U, L = 5001, 0.05, 12.0
+    fx, fy = rng.normal(1.0, 0.3, n), np.cumsum(rng.normal(0.0, 1.0, n))
+    r = orc.force_stats(fx, fy, U, L)
+    s = 1.0 / (0.5 * U * U * L)
+    cd, cl = fx * s, fy * s
+    assert abs(r["CD_mean"] - cd.mean()) < 1e-12 * abs(cd.mean())
+    assert abs(r["CD_rms"] - cd.std()) < 1e-11 * cd.std()
+    assert abs(r["CL_rms"] - cl.std()) < 1e-11 * cl.std()
+    c = cl - r["CL_mean"]
+    up = np.nonzero((c[:-1] < 0) & (c[1:] >= 0))[0]
+    assert r["crossings"] == len(up) and len(up) >= 3
+    t0 = up[0] + c[up[0]] / (c[up[0]] - c[up[0] + 1])
+    t1 = up[-1] + c[up[-1]] / (c[up[-1]] - c[up[-1] + 1])
+    assert abs(r["St"] - (len(up) - 1) / (t1 - t0) * L / U) < 1e-12 * r["St"]
+
+
+def test_velocity_change_measure(orc):
+    """E = 0 between a state and itself; E = eps / (1 + eps) when every
+    velocity grows by the factor 1 + eps; a level-1 cell weighs 1/4 of a
+    level-0 cell; NaN (non-leaf) cells are left out."""
+    rng = np.random.default_rng(3)
+    u0 = [(rng.normal(size=(8, 8)), rng.normal(size=(8, 8))), (rng.normal(size=(16, 16)), rng.normal(size=(16, 16)))]
+    for l in range(2):
+        u0[l][0][:2, :2] = np.nan
+        u0[l][1][:2, :2] = np.nan
+    assert orc.velocity_change(u0, u0)[0] == 0.0
+    eps = 0.125
+    u1 = [(ux * (1 + eps), uy * (1 + eps)) for ux, uy in u0]
+    assert abs(orc.velocity_change(u1, u0)[2] - eps / (1 + eps)) < 1e-14
+    z = [(np.zeros((8, 8)), np.zeros((8, 8))), (np.zeros((16, 16)), np.zeros((16, 16)))]
+    one = [(np.ones((8, 8)), np.zeros((8, 8))), (np.ones((16, 16)), np.zeros((16, 16)))]
+    one[1][0][0, 0] = np.nan
+    num, den, _ = orc.velocity_change(one, z)
+    assert num == den == 64 + 255 / 4
+
+
+def test_velocity_change_of_decaying_tgv(orc):
+    """Taylor-Green decay: u(t + dt) = u(t) exp(-2 nu k^2 dt), so
+    E = 1 - exp(-2 nu k^2 dt) up to the scheme's error (Sec. 3.1 flow, Sec. 3.2
+    criterion with dt = 200 steps instead of 1000)."""
+    wl = W.tgv(32, tau=0.8, u0=0.02)
+    s = orc.OracleSim(wl)
+    s.step(50)
+    then = s.velocity()
+    s.step(200)
+    E = orc.velocity_change(s.velocity(), then)[2]
+    k, nu = wl.meta["k"], wl.meta["nu"]
+    want = math.exp(2 * nu * k * k * 200) - 1.0      # |u(t) - u(t+dt)| / |u(t+dt)|
+    assert abs(E - want) < 0.01 * want, (E, want)
+
+
 # ---- Whole-step invariants and closed forms ------------------------------
 
 def test_periodic_conservation_with_body_force(orc):
