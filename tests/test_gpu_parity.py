@@ -488,6 +488,39 @@ def test_cylinder_table1_full_size(env):
     assert lo <= c.std() <= 1.2 * hi, c.std()
 
 
+def test_pitch_up_plate_first_lift_peak(env):
+    """Sec. 3.5 workload (flat plate of 2.3 % thickness, chord 64 finest
+    cells, Re 1000, 70c x 40c channel, 3 levels) run to t* = 1.6: the lift
+    history has its first peak near the printed C_L = 2.6 at t* = 1.2
+    (tests/golden/pitch_up_plate.json), after which lift keeps rising as the
+    leading-edge vortex grows.  Measured here: 3.11 at t* = 1.04 (the ramp
+    accelerates at t1 = 1, and this resolution responds earlier than the
+    paper's, which it reports as delayed against other solvers), so the
+    peak is held to 0.75-1.35 x 2.6 within t* 0.95-1.35; a wrong pitch
+    direction, a lost factor 2 or a missing ds fails it."""
+    import json
+    import os
+    P, _ = env
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pitch_up_plate.json")))
+    pk = gold["first_lift_peak"]
+    wl = W.pitch_up_plate()
+    g = P.Sim(wl, "f64")
+    U, c = wl.meta["U"], wl.meta["chord"]
+    per_t = c / U
+    g.step(int(round(1.6 * per_t / 4)))
+    g.synchronize()
+    fx, fy = g.force_history()
+    cl = fy / (0.5 * U * U * c)
+    t = (np.arange(len(cl)) + 1) / per_t
+    w = (t > 0.9) & (t < 1.4)
+    i = int(np.argmax(np.where(w, cl, -np.inf)))
+    print(f"  first lift peak C_L {cl[i]:.3f} at t* {t[i]:.3f}; C_L(1.6) {cl[-1]:.3f}", flush=True)
+    assert 0.75 * pk["CL"] <= cl[i] <= 1.35 * pk["CL"], cl[i]
+    assert 0.95 <= t[i] <= 1.35, t[i]
+    assert np.abs(cl[t < 0.8]).max() < 0.3          # no lift before the ramp starts
+    assert cl[-1] > 0.6 * cl[i]
+
+
 def test_host_markers_match_oracle(env):
     """sbt_set_markers on the graph path against the oracle's caller-placed
     body: the markers of a flapping motion (positions r(t_k), desired

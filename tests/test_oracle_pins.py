@@ -232,6 +232,21 @@ def test_ramp_law_closed_forms(orc, A, a_s, K, t1):
     assert a.max() <= A * (1 + 1e-14)
 
 
+def test_ramp_angle_at_the_printed_lift_peak(orc):
+    """Sec. 3.5 prints a pitch angle of about 5 deg at t* = 1.2, when lift
+    peaks first (tests/golden/pitch_up_plate.json).  With the printed
+    A, a_s, K, t1 the law gives 4.6 deg there, while reading t2 = t1 + A / K
+    gives 1.2 deg.  (Normalising G by its value at t2 instead of its
+    supremum changes alpha by only log 2 / (2 a_s (t2 - t1)) ~ 0.8 %.)"""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pitch_up_plate.json")))
+    st, pk = gold["setup"], gold["first_lift_peak"]
+    p = W.ramp_params(0.0, 0.0, 64.0, st["U0"], A=st["A_rad"], a_s=st["a_s"], K=st["K"], t1=st["t1_star"])
+    a = math.degrees(orc.ramp_alpha(p, pk["t_star"]))
+    assert abs(a - pk["alpha_deg"]) < 1.0, a
+
+
 @pytest.mark.parametrize("xi", [0.5, 0.35, 0.6])
 def test_triangular_law_closed_forms(orc, xi):
     """Sec. 3.6 smoothed triangular law: alpha(0) = 0; extremes +alpha0 at
