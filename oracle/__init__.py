@@ -31,6 +31,7 @@ class _Case(C.Structure):
         ("n_markers", C.c_int32),
         ("xb", C.POINTER(C.c_double)), ("yb", C.POINTER(C.c_double)), ("ds", C.POINTER(C.c_double)),
         ("bp", C.c_double * 16),
+        ("collision", C.c_int32), ("mrt", C.c_double * 3),
     ]
 
 
@@ -68,6 +69,10 @@ def lib():
         _lib.orc_guo.restype = None
         _lib.orc_collide_cell.argtypes = [C.c_double, d, C.c_double, C.c_double, d]
         _lib.orc_collide_cell.restype = None
+        _lib.orc_mrt_matrices.argtypes = [d, d]
+        _lib.orc_mrt_matrices.restype = None
+        _lib.orc_collide_cell_mrt.argtypes = [C.c_double, d, d, C.c_double, C.c_double, d]
+        _lib.orc_collide_cell_mrt.restype = None
         _lib.orc_phi.argtypes = [C.c_double]
         _lib.orc_phi.restype = C.c_double
         _lib.orc_body_positions.argtypes = [C.POINTER(_Case), C.c_double, d, d]
@@ -106,6 +111,9 @@ def make_case(wl):
         c.bc_u[2 * e], c.bc_u[2 * e + 1] = wl.bc_u[e]
     c.fext[0], c.fext[1] = wl.fext
     c.cf_mode, c.mdf_iters = wl.cf_mode, wl.mdf_iters
+    c.collision = wl.collision
+    for k in range(3):
+        c.mrt[k] = wl.mrt_rates[k]
     keep = [boxes]
     if wl.body is None:
         c.body_kind, c.n_markers = ORC_BODY_NONE, 0
@@ -242,6 +250,21 @@ def collide_cell(tau, f, Fx=0.0, Fy=0.0):
     f = _f64(f)
     out = np.zeros(9)
     lib().orc_collide_cell(tau, _dp(f), Fx, Fy, _dp(out))
+    return out
+
+
+def mrt_matrices():
+    """The MRT moment basis M (9 x 9, rows rho, e, eps, jx, qx, jy, qy, pxx, pxy) and its inverse."""
+    M, Mi = np.zeros(81), np.zeros(81)
+    lib().orc_mrt_matrices(_dp(M), _dp(Mi))
+    return M.reshape(9, 9), Mi.reshape(9, 9)
+
+
+def collide_cell_mrt(tau, rates, f, Fx=0.0, Fy=0.0):
+    f = _f64(f)
+    r = _f64(np.asarray(rates, dtype=np.float64))
+    out = np.zeros(9)
+    lib().orc_collide_cell_mrt(float(tau), _dp(r), _dp(f), float(Fx), float(Fy), _dp(out))
     return out
 
 

@@ -128,6 +128,79 @@ void orc_collide_cell(double tau, const double f[9], double Fx, double Fy, doubl
     collide_cell(tau, f, Fx, Fy, out, NULL);
 }
 
+/* The multiple-relaxation-time collision the paper names as an option for
+ * low viscosity (Sec. 2.1, after Du et al.), on the usual orthogonal D2Q9
+ * moment basis m = M f: density, energy e, energy square eps, momentum jx,
+ * energy flux qx, jy, qy, and the stresses pxx, pxy.  Row k of M is the
+ * polynomial of c_i named below; the rows are orthogonal, so
+ * M^-1 = M^T diag(1 / |row_k|^2). */
+void orc_mrt_matrices(double M[81], double Minv[81]) {
+    for (int i = 0; i < Q; ++i) {
+        double cx = CX[i], cy = CY[i], c2 = cx * cx + cy * cy;
+        M[0 * Q + i] = 1.0;
+        M[1 * Q + i] = -4.0 + 3.0 * c2;
+        M[2 * Q + i] = 4.0 - 10.5 * c2 + 4.5 * c2 * c2;
+        M[3 * Q + i] = cx;
+        M[4 * Q + i] = (3.0 * c2 - 5.0) * cx;
+        M[5 * Q + i] = cy;
+        M[6 * Q + i] = (3.0 * c2 - 5.0) * cy;
+        M[7 * Q + i] = cx * cx - cy * cy;
+        M[8 * Q + i] = cx * cy;
+    }
+    for (int k = 0; k < Q; ++k) {
+        double n2 = 0.0;
+        for (int i = 0; i < Q; ++i) n2 += M[k * Q + i] * M[k * Q + i];
+        for (int i = 0; i < Q; ++i) Minv[i * Q + k] = M[k * Q + i] / n2;
+    }
+}
+
+/* MRT step: every moment relaxes toward the moments of the Eq. (7)
+ * equilibrium, m_eq = M f^eq(rho, u), at its own rate, and Guo's forcing
+ * enters in moment space as (I - S/2) M Fbar, Fbar_i = w_i (3 c.F +
+ * 9 (c.u)(c.F) - 3 u.F) (Eq. (3) without its 1 - 1/(2 tau) factor):
+ *   m* = m - S (m - m_eq) + (I - S/2) M Fbar,  f* = M^-1 m*,
+ *   S = diag(1, s_e, s_eps, 1, s_q, 1, s_q, 1/tau, 1/tau).
+ * u is the half-force velocity of Eq. (8).  With every rate 1/tau this is
+ * Eqs. (2)-(3) exactly.  rates = {s_e, s_eps, s_q}. */
+static void collide_mrt(double tau, const double rates[3], const double *f, double Fx, double Fy,
+                        double *out, double *mom) {
+    double M[81], Minv[81];
+    orc_mrt_matrices(M, Minv);
+    double rho = 0.0, jx = 0.0, jy = 0.0;
+    for (int i = 0; i < Q; ++i) { rho += f[i]; jx += CX[i] * f[i]; jy += CY[i] * f[i]; }
+    double ux = (jx + 0.5 * Fx) / rho;
+    double uy = (jy + 0.5 * Fy) / rho;
+    double feq[Q], fbar[Q];
+    orc_feq(rho, ux, uy, feq);
+    double uF = ux * Fx + uy * Fy;
+    for (int i = 0; i < Q; ++i) {
+        double cu = CX[i] * ux + CY[i] * uy, cF = CX[i] * Fx + CY[i] * Fy;
+        fbar[i] = WT[i] * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
+    }
+    double S[Q] = {1.0, rates[0], rates[1], 1.0, rates[2], 1.0, rates[2], 1.0 / tau, 1.0 / tau};
+    double ms[Q];
+    for (int k = 0; k < Q; ++k) {
+        double m = 0.0, me = 0.0, g = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            m += M[k * Q + i] * f[i];
+            me += M[k * Q + i] * feq[i];
+            g += M[k * Q + i] * fbar[i];
+        }
+        ms[k] = m - S[k] * (m - me) + (1.0 - 0.5 * S[k]) * g;
+    }
+    for (int i = 0; i < Q; ++i) {
+        double v = 0.0;
+        for (int k = 0; k < Q; ++k) v += Minv[i * Q + k] * ms[k];
+        out[i] = v;
+    }
+    if (mom) { mom[0] = rho; mom[1] = ux; mom[2] = uy; }
+}
+
+void orc_collide_cell_mrt(double tau, const double rates[3], const double f[9], double Fx, double Fy,
+                          double out[9]) {
+    collide_mrt(tau, rates, f, Fx, Fy, out, NULL);
+}
+
 /* Eq. (14): Peskin's 4-point kernel (dx = 1). */
 double orc_phi(double r) {
     double a = fabs(r);
@@ -421,6 +494,10 @@ int orc_create(const orc_case *c, orc_sim **out) {
     if (c->n_levels < 1 || c->n_levels > MAXL || c->nx0 <= 0 || c->ny0 <= 0 || c->block_n <= 0 ||
         c->tau0 <= 0.5)
         return ORC_ERR_ARG;
+    if (c->collision != ORC_COLL_BGK && c->collision != ORC_COLL_MRT) return ORC_ERR_ARG;
+    if (c->collision == ORC_COLL_MRT)
+        for (int k = 0; k < 3; ++k)
+            if (!(c->mrt[k] > 0.0 && c->mrt[k] < 2.0)) return ORC_ERR_ARG;
     for (int e = 0; e < 4; ++e)
         if (c->bc[e] < 0 || c->bc[e] > ORC_BC_SYMMETRY) return ORC_ERR_ARG;
     if ((c->bc[ORC_W] == ORC_BC_PERIODIC) != (c->bc[ORC_E] == ORC_BC_PERIODIC) ||
@@ -587,7 +664,10 @@ static void collision(orc_sim *s, int l) {
             double Fx = L->fx, Fy = L->fy;
             if (finest) { Fx += L->Fx[q]; Fy += L->Fy[q]; }
             double mom[3];
-            collide_cell(L->tau, L->f + q * Q, Fx, Fy, L->fs + q * Q, mom);
+            if (s->c.collision == ORC_COLL_MRT)
+                collide_mrt(L->tau, s->c.mrt, L->f + q * Q, Fx, Fy, L->fs + q * Q, mom);
+            else
+                collide_cell(L->tau, L->f + q * Q, Fx, Fy, L->fs + q * Q, mom);
             L->rho[q] = mom[0]; L->ux[q] = mom[1]; L->uy[q] = mom[2];
         }
 }

@@ -30,6 +30,7 @@ enum { ORC_CF_HOMOGENEOUS = 0, ORC_CF_RESCALE = 1 };
 enum { ORC_BODY_NONE = -1, ORC_BODY_FIXED = 0, ORC_BODY_FLAP = 1, ORC_BODY_HOST = 2,
        ORC_BODY_RAMP = 3, ORC_BODY_TRI = 4 };
 enum { ORC_W = 0, ORC_E = 1, ORC_S = 2, ORC_N = 3 };
+enum { ORC_COLL_BGK = 0, ORC_COLL_MRT = 1 };
 
 typedef struct {
     int32_t nx0, ny0;        /* level-0 cells                                   */
@@ -50,6 +51,8 @@ typedef struct {
                                 (ORC_BODY_HOST: absolute positions)              */
     const double *ds;        /* marker arc lengths, finest cells                 */
     double bp[16];           /* kinematic parameters (see orc_body_positions)    */
+    int32_t collision;       /* ORC_COLL_*                                       */
+    double mrt[3];           /* MRT rates s_e, s_eps, s_q (shear rate 1/tau_l)   */
 } orc_case;
 
 typedef struct orc_sim orc_sim;
@@ -85,6 +88,10 @@ void   orc_velocity_set(int32_t cx[9], int32_t cy[9], double w[9]);
 void   orc_feq(double rho, double ux, double uy, double out[9]);
 void   orc_guo(double tau, double ux, double uy, double Fx, double Fy, double out[9]);
 void   orc_collide_cell(double tau, const double f[9], double Fx, double Fy, double out[9]);
+/* MRT collision (moment basis M, its inverse; rates = {s_e, s_eps, s_q}). */
+void   orc_mrt_matrices(double M[81], double Minv[81]);
+void   orc_collide_cell_mrt(double tau, const double rates[3], const double f[9], double Fx,
+                            double Fy, double out[9]);
 double orc_phi(double r);
 /* Marker positions of the body at finest substep k (time t_k = k). */
 int    orc_body_positions(const orc_case *c, double k, double *X, double *Y);

@@ -85,6 +85,87 @@ def test_collision_conserves_mass_and_adds_force(orc):
 
 # ---- Eq. (14): Peskin kernel (P3) ----------------------------------------
 
+# ---- MRT collision (Sec. 2.1 option) ---------------------------------------
+
+def test_mrt_basis_and_equilibrium_moments(orc):
+    """The moment basis is orthogonal with row norms (9, 36, 36, 6, 12, 6, 12,
+    4, 4), its inverse inverts it, and the moments of the Eq. (7)
+    equilibrium are the textbook D2Q9 ones: rho, rho(-2 + 3u^2),
+    rho(1 - 3u^2), rho ux, -rho ux, rho uy, -rho uy, rho(ux^2 - uy^2),
+    rho ux uy."""
+    M, Mi = orc.mrt_matrices()
+    G = M @ M.T
+    assert np.allclose(G, np.diag([9, 36, 36, 6, 12, 6, 12, 4, 4]), atol=1e-14, rtol=0)
+    assert np.abs(Mi @ M - np.eye(9)).max() < 1e-15
+    rho, ux, uy = 1.03, 0.07, -0.04
+    u2 = ux * ux + uy * uy
+    want = [rho, rho * (-2 + 3 * u2), rho * (1 - 3 * u2), rho * ux, -rho * ux, rho * uy, -rho * uy,
+            rho * (ux * ux - uy * uy), rho * ux * uy]
+    assert np.abs(M @ orc.feq(rho, ux, uy) - want).max() < 1e-15
+
+
+def test_mrt_forcing_moments(orc):
+    """Moments of Guo's forcing term without its prefactor: (0, 6 u.F, -6 u.F,
+    Fx, -Fx, Fy, -Fy, 2(ux Fx - uy Fy), ux Fy + uy Fx)."""
+    M, _ = orc.mrt_matrices()
+    ux, uy, Fx, Fy = 0.06, -0.03, 2e-4, -5e-5
+    fbar = orc.guo(1e300, ux, uy, Fx, Fy)          # prefactor 1 - 1/(2 tau) -> 1
+    uF = ux * Fx + uy * Fy
+    want = [0, 6 * uF, -6 * uF, Fx, -Fx, Fy, -Fy, 2 * (ux * Fx - uy * Fy), ux * Fy + uy * Fx]
+    assert np.abs(M @ fbar - want).max() < 1e-18
+
+
+def test_mrt_with_equal_rates_is_bgk(orc):
+    """All rates 1/tau: the MRT step is Eqs. (2)-(3) (BGK with Guo forcing)."""
+    rng = np.random.default_rng(11)
+    tau = 0.63
+    f = orc.feq(1.02, 0.05, -0.02) * (1 + 0.01 * rng.normal(size=9))
+    for F in ((0.0, 0.0), (3e-4, -1e-4)):
+        a = orc.collide_cell_mrt(tau, [1 / tau] * 3, f, *F)
+        b = orc.collide_cell(tau, f, *F)
+        assert np.abs(a - b).max() < 1e-15
+
+
+def test_mrt_relaxes_each_moment_at_its_rate(orc):
+    """From equilibrium plus eps times one basis moment (no force), the
+    collision leaves (1 - s_k) eps in that moment and nothing in the others;
+    density and momentum are conserved, and a force adds exactly F to the
+    momentum."""
+    M, Mi = orc.mrt_matrices()
+    tau, rates = 0.57, (1.64, 1.54, 1.9)
+    S = [1.0, rates[0], rates[1], 1.0, rates[2], 1.0, rates[2], 1 / tau, 1 / tau]
+    feq = orc.feq(0.98, 0.04, 0.03)
+    for k in (1, 2, 4, 6, 7, 8):
+        e = np.zeros(9)
+        e[k] = 1e-3
+        out = orc.collide_cell_mrt(tau, rates, feq + Mi @ e)
+        d = M @ (out - feq)
+        want = np.zeros(9)
+        want[k] = (1 - S[k]) * 1e-3
+        assert np.abs(d - want).max() < 1e-15, k
+    rng = np.random.default_rng(5)
+    f = feq * (1 + 0.02 * rng.normal(size=9))
+    F = (2e-4, 1e-4)
+    out = orc.collide_cell_mrt(tau, rates, f, *F)
+    cx, cy, _ = orc.velocity_set()
+    assert abs(out.sum() - f.sum()) < 1e-15
+    assert abs((cx * out).sum() - (cx * f).sum() - F[0]) < 1e-16
+    assert abs((cy * out).sum() - (cy * f).sum() - F[1]) < 1e-16
+
+
+def test_mrt_tgv_decays_at_the_shear_viscosity(orc):
+    """A Taylor-Green vortex under MRT decays at nu = (tau - 1/2) / 3: the
+    shear rate is 1/tau; the other rates only damp non-hydrodynamic modes."""
+    wl = W.tgv(64).replace(collision=W.COLL_MRT)
+    err, _ = _tgv_error(orc, wl, 1000)
+    assert err < 1e-2
+    bgk = orc.OracleSim(W.tgv(64))
+    mrt = orc.OracleSim(wl)
+    bgk.step(20)
+    mrt.step(20)
+    assert np.abs(bgk.fields(0)[1] - mrt.fields(0)[1]).max() > 1e-12      # the MRT path ran
+
+
 def test_peskin_kernel_moments(orc):
     rng = np.random.default_rng(4)
     assert orc.phi(2.0) == 0.0 and orc.phi(-2.5) == 0.0 and orc.phi(7.0) == 0.0

@@ -32,6 +32,9 @@ import numpy as np
 PERIODIC, WALL, INFLOW, OUTFLOW, SYMMETRY = 0, 1, 2, 3, 4
 W, E, S, N = 0, 1, 2, 3
 CF_HOMOGENEOUS, CF_RESCALE = 0, 1
+COLL_BGK, COLL_MRT = 0, 1
+# MRT rates of the non-hydrodynamic moments (e, eps, q), Lallemand and Luo's values
+MRT_RATES = (1.64, 1.54, 1.9)
 BODY_FIXED, BODY_FLAP, BODY_HOST, BODY_RAMP, BODY_TRI = 0, 1, 2, 3, 4
 
 
@@ -63,6 +66,8 @@ class Workload:
     fext: tuple = (0.0, 0.0)
     cf_mode: int = CF_HOMOGENEOUS
     mdf_iters: int = 3
+    collision: int = COLL_BGK
+    mrt_rates: tuple = MRT_RATES
     body: Optional[Body] = None
     init: Optional[Callable] = None   # init(level, nx, ny) -> (rho, ux, uy) dense [ny, nx]
     meta: dict = dataclasses.field(default_factory=dict)
