@@ -81,6 +81,16 @@ enum { SBT_EDGE_W = 0, SBT_EDGE_E = 1, SBT_EDGE_S = 2, SBT_EDGE_N = 3 };
  * 2 tau_c / tau_f fine->coarse; it requires |tau - 1| > 1e-6 on coarse levels. */
 enum { SBT_CF_HOMOGENEOUS = 0, SBT_CF_RESCALE = 1 };
 
+/* Collision (Sec. 2.1).  BGK: Eqs. (2)-(3) with Guo forcing.  MRT: the
+ * multiple-relaxation-time option the paper names for low viscosity, on the
+ * orthogonal D2Q9 moment basis (rho, e, eps, jx, qx, jy, qy, pxx, pxy).  The
+ * moments relax toward those of the Eq. (7) equilibrium at rates
+ * (-, s_e, s_eps, -, s_q, -, s_q, 1/tau_l, 1/tau_l); Guo's forcing enters in
+ * moment space as (I - S/2) M Fbar, Fbar being Eq. (3)'s term without its
+ * 1 - 1/(2 tau) factor.  Equal rates 1/tau reproduce BGK.  Same viscosity
+ * nu = (tau - 1/2)/3; the interface rescaling uses tau as for BGK. */
+enum { SBT_COLL_BGK = 0, SBT_COLL_MRT = 1 };
+
 /* Body kinematics (marker positions r_j(t) of Sec. 2.2):
  * FIXED: r_j = (p[0] + xb_j, p[1] + yb_j), desired velocity 0.
  * FLAP : the flapping law of Sec. 3.6 with free amplitudes:
@@ -131,6 +141,8 @@ typedef struct {
     int32_t mdf_iters;             /* N_F of the multi-direct-forcing loop         */
     int32_t max_markers;           /* capacity for sbt_set_body; 0 = no body       */
     int32_t history_cap;           /* finest substeps of force history kept        */
+    int32_t collision;             /* SBT_COLL_* (same for every case of a ctx)    */
+    double mrt_rates[3];           /* SBT_COLL_MRT: s_e, s_eps, s_q in (0, 2)      */
 } sbt_case_desc;
 
 typedef struct {

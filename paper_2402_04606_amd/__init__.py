@@ -54,6 +54,7 @@ class CaseDesc(C.Structure):
         ("bc", C.c_int32 * 4), ("bc_u", (C.c_double * 2) * 4), ("fext", C.c_double * 2),
         ("storage", C.c_int32), ("cf_mode", C.c_int32), ("mdf_iters", C.c_int32),
         ("max_markers", C.c_int32), ("history_cap", C.c_int32),
+        ("collision", C.c_int32), ("mrt_rates", C.c_double * 3),
     ]
 
 
@@ -141,6 +142,9 @@ def make_desc(wl, storage=F64, history_cap=1 << 16, max_markers=None):
     nm = 0 if wl.body is None else len(wl.body.xb)
     d.max_markers = nm if max_markers is None else max_markers
     d.history_cap = history_cap
+    d.collision = getattr(wl, "collision", 0)
+    for k, v in enumerate(getattr(wl, "mrt_rates", (0.0, 0.0, 0.0))):
+        d.mrt_rates[k] = v
     return d, boxes
 
 

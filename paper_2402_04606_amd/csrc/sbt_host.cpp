@@ -129,6 +129,10 @@ sbt_status build_forest(const sbt_case_desc &d, Forest &F) {
     return fail(SBT_ERR_ARG, "periodic edges must come in W/E or S/N pairs");
   if (d.storage < SBT_F64 || d.storage > SBT_BF16S) return fail(SBT_ERR_ARG, "bad storage");
   if (d.cf_mode != SBT_CF_HOMOGENEOUS && d.cf_mode != SBT_CF_RESCALE) return fail(SBT_ERR_ARG, "bad cf_mode");
+  if (d.collision != SBT_COLL_BGK && d.collision != SBT_COLL_MRT) return fail(SBT_ERR_ARG, "bad collision model");
+  if (d.collision == SBT_COLL_MRT)
+    for (int k = 0; k < 3; ++k)
+      if (!(d.mrt_rates[k] > 0.0 && d.mrt_rates[k] < 2.0)) return fail(SBT_ERR_ARG, "MRT rates must lie in (0, 2)");
   if (d.max_markers < 0 || d.mdf_iters < 0) return fail(SBT_ERR_ARG, "negative marker count or N_F");
   if (d.max_markers > 0 && d.history_cap <= 0) return fail(SBT_ERR_ARG, "history_cap must be positive");
   if (d.max_markers > kMaxMarkers) return fail(SBT_ERR_ARG, "at most 1024 markers per body");
@@ -265,6 +269,7 @@ struct GroupInfo {
 
 struct sbt_ctx {
   int n_cases = 0, V = 1, storage = 0;
+  int kvar = 0;  // level-launch variant: storage | (collision model << 2)
   int G = 1;                       // case groups: independent launch chains
   std::vector<CaseHost> cs;
   std::vector<Pool> pools;         // pool of group g, virtual level v at g * V + v
@@ -306,10 +311,12 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
   X.cs.resize(n_cases);
   X.V = 1;
   X.storage = cases[0].storage;
+  X.kvar = X.storage | (cases[0].collision == SBT_COLL_MRT ? 4 : 0);
   for (int c = 0; c < n_cases; ++c) {
     CaseHost &C = X.cs[c];
     C.d = cases[c];
     if (C.d.storage != X.storage) return fail(SBT_ERR_ARG, "all cases of a context share one storage");
+    if (C.d.collision != cases[0].collision) return fail(SBT_ERR_ARG, "all cases of a context share one collision model");
     C.boxes.assign(C.d.refine, C.d.refine + std::max(0, C.d.n_refine));
     C.d.refine = C.boxes.data();
     sbt_status st = build_forest(C.d, C.F);
@@ -572,6 +579,10 @@ void build_tables(sbt_ctx &X) {
       D.s_fc_f[l] = (float)D.s_fc[l];
     }
     D.rho0 = d.rho0;
+    for (int k = 0; k < 3; ++k) {
+      D.mrt_s[k] = d.collision == SBT_COLL_MRT ? d.mrt_rates[k] : 0.0;
+      D.mrt_s_f[k] = (float)D.mrt_s[k];
+    }
     for (int e = 0; e < 4; ++e) {
       D.bc[e] = d.bc[e];
       D.bcu[e][0] = d.bc_u[e][0];
@@ -708,12 +719,12 @@ sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s
       t.band = P.d_band;
       t.n_band = (int)P.band.size();
     }
-    if (t.n_blocks + t.n_band > 0) st = timed(true, [&] { return sbt_launch_level_tile(X.storage, &t, s); });
+    if (t.n_blocks + t.n_band > 0) st = timed(true, [&] { return sbt_launch_level_tile(X.kvar, &t, s); });
   } else {
     a.list = nullptr;
     a.b0 = 0;
     a.n_blocks = P.n_own;
-    st = timed(false, [&] { return sbt_launch_level(X.storage, 0, &a, s); });
+    st = timed(false, [&] { return sbt_launch_level(X.kvar, 0, &a, s); });
   }
   if (st) return st;
   P.cur = 1 - P.cur;
@@ -953,7 +964,7 @@ sbt_status readout_level(sbt_ctx &X, int c, int l, hipStream_t s) {
   a.out = X.d_stage;
   a.partial = X.d_partial;
   a.err = X.d_err;
-  HIPCHK(sbt_launch_level(X.storage, 0, &a, s));
+  HIPCHK(sbt_launch_level(X.kvar, 0, &a, s));
   return SBT_OK;
 }
 
@@ -1678,7 +1689,7 @@ sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path) {
   sbt_ctx &X = *ctx;
   // cache key: storage and the block counts of every pool
   std::ostringstream key;
-  key << "st" << X.storage << "_g" << X.G;
+  key << "st" << X.kvar << "_g" << X.G;
   for (auto &P : X.pools) key << "_" << P.n_own << "/" << P.n_ghost;
   if (cache_path) {
     std::ifstream in(cache_path);

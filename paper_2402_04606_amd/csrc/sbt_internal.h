@@ -53,6 +53,8 @@ struct alignas(16) CaseDev {
   float pre_f[kMaxLevels];
   float fx_f[kMaxLevels], fy_f[kMaxLevels];
   float s_cf_f[kMaxLevels], s_fc_f[kMaxLevels];
+  double mrt_s[3];             // MRT rates s_e, s_eps, s_q (the shear rate is 1/tau of the level)
+  float mrt_s_f[3];
   double rho0;
   double bcu[4][2];
   int32_t bc[4];
@@ -145,6 +147,7 @@ enum : int32_t { ERR_NONFINITE = 1, ERR_MARKER = 2, ERR_CONTRIB = 4, ERR_WINDOW 
 extern "C" {
 // Generic level kernel: any block (interfaces, domain edges, readout,
 // initial collision) and halo-band cells.
+// `storage` of the level launches: SBT_F64 .. SBT_BF16S, plus 4 for the MRT collision.
 hipError_t sbt_launch_level(int storage, int tile, const sbt::LevelArgs *a, hipStream_t s);
 // One LDS-staged stream + collide launch for a level substep: list entries
 // [0, n_fast) are interior blocks (no cell codes, no domain edge, all eight

@@ -42,29 +42,31 @@ __device__ __forceinline__ C wgt(int i) {
 }
 
 // ---- storage types ---------------------------------------------------------
-template <int ST> struct Store;
-template <> struct Store<0> {  // FP64: f itself, FP64 arithmetic
+// Kernel variant ST = storage | (collision model << 2): bits 0-1 select the
+// storage form, bit 2 the MRT collision (kMrt).
+template <int SB> struct StoreOf;
+template <> struct StoreOf<0> {  // FP64: f itself, FP64 arithmetic
   using T = double;
   using C = double;
   static constexpr bool kShift = false;
   __device__ static C ld(T v) { return v; }
   __device__ static T st(C v) { return v; }
 };
-template <> struct Store<1> {  // FP32 deviation
+template <> struct StoreOf<1> {  // FP32 deviation
   using T = float;
   using C = float;
   static constexpr bool kShift = true;
   __device__ static C ld(T v) { return v; }
   __device__ static T st(C v) { return v; }
 };
-template <> struct Store<2> {  // FP16 deviation, round to nearest even
+template <> struct StoreOf<2> {  // FP16 deviation, round to nearest even
   using T = _Float16;
   using C = float;
   static constexpr bool kShift = true;
   __device__ static C ld(T v) { return (float)v; }
   __device__ static T st(C v) { return (_Float16)v; }
 };
-template <> struct Store<3> {  // BF16 deviation, round to nearest even
+template <> struct StoreOf<3> {  // BF16 deviation, round to nearest even
   using T = uint16_t;
   using C = float;
   static constexpr bool kShift = true;
@@ -75,6 +77,9 @@ template <> struct Store<3> {  // BF16 deviation, round to nearest even
     u += 0x7fffu + ((u >> 16) & 1u);
     return (T)(u >> 16);
   }
+};
+template <int ST> struct Store : StoreOf<ST & 3> {
+  static constexpr bool kMrt = (ST & 4) != 0;
 };
 
 // Scalar (wave-uniform) context of one block: the workgroup's block id,
@@ -188,11 +193,11 @@ __device__ __forceinline__ void moments64(const double f[9], double &rho, double
 }
 
 // ---- collision (Eqs. (3), (6)-(8)) -----------------------------------------
-template <int ST>
-struct Collide;
+template <int SB>
+struct CollideBGK;
 
 template <>
-struct Collide<0> {
+struct CollideBGK<0> {
   __device__ __forceinline__ static void run(const CaseDev &cp, int l, double f[9], double Fx, double Fy, double &rho,
                              double &ux, double &uy) {
 #pragma clang fp contract(off)
@@ -219,8 +224,8 @@ struct Collide<0> {
   }
 };
 
-template <int ST>
-struct Collide {
+template <int SB>
+struct CollideBGK {
   // Deviation form (f = w rho0 + d): rho = rho0 + sum d, sum c f = sum c d,
   // and d^eq = w (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2)), evaluated with
   // the shared terms of the D2Q9 directions.  The Guo term is added only
@@ -265,6 +270,104 @@ struct Collide {
     }
   }
 };
+
+// MRT collision, the option Sec. 2.1 names for low viscosity: the D2Q9
+// moments e, eps (energy and its square), qx, qy (energy flux) and pxx, pxy
+// (stresses) relax toward the moments of the Eq. (7) equilibrium at rates
+// s_e, s_eps, s_q and 1/tau; density and momentum are conserved except for
+// the force, which enters in moment space as (1 - s/2) times the moments of
+// Guo's term: (6 u.F, -6 u.F, -Fx, -Fy, 2 (ux Fx - uy Fy), ux Fy + uy Fx),
+// and adds exactly F to the momentum.  The change of each moment goes back
+// through the orthogonal basis (row norms 36, 36, 6, 12, 6, 12, 4, 4):
+//   axis i (c = (+-1, 0), (0, +-1)): -De/36 - Deps/18 +- (Dj - Dq)/6 +- Dxx/4
+//   diagonal i:  De/18 + Deps/36 + cx (Djx/6 + Dqx/12) + cy (Djy/6 + Dqy/12)
+//                + cx cy Dxy/4
+//   rest:        (Deps - De)/9
+// so equal rates 1/tau give Eqs. (2)-(3).  Direction order of Eq. (1):
+// 1 (+x), 2 (+y), 3 (-x), 4 (-y), 5 (+x+y), 6 (-x+y), 7 (-x-y), 8 (+x-y).
+template <typename C>
+__device__ __forceinline__ void mrt_update(C f[9], C rho, C ux, C uy, C Fx, C Fy, C e_eq, C ep_eq, C se, C sp, C sq,
+                                           C sn) {
+#pragma clang fp contract(off)
+  const C h = C(0.5);
+  const C ax = f[1] + f[3], ay = f[2] + f[4];
+  const C sa = ax + ay, sd = (f[5] + f[6]) + (f[7] + f[8]);
+  const C e = (C(-4) * f[0] - sa) + C(2) * sd;
+  const C ep = (C(4) * f[0] - C(2) * sa) + sd;
+  const C qx = C(-2) * (f[1] - f[3]) + ((f[5] - f[6]) - (f[7] - f[8]));
+  const C qy = C(-2) * (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
+  const C pxx = ax - ay;
+  const C pxy = (f[5] - f[6]) + (f[7] - f[8]);
+  const C rux = rho * ux, ruy = rho * uy;
+  C De = -se * (e - e_eq), Dp = -sp * (ep - ep_eq);
+  C Dqx = -sq * (qx + rux), Dqy = -sq * (qy + ruy);
+  C Dxx = -sn * (pxx - rho * (ux * ux - uy * uy)), Dxy = -sn * (pxy - rux * uy);
+  C Djx = C(0), Djy = C(0);
+  if (Fx != C(0) || Fy != C(0)) {
+    const C uF = ux * Fx + uy * Fy;
+    De = De + (C(1) - h * se) * (C(6) * uF);
+    Dp = Dp + (C(1) - h * sp) * (C(-6) * uF);
+    Dqx = Dqx + (C(1) - h * sq) * (-Fx);
+    Dqy = Dqy + (C(1) - h * sq) * (-Fy);
+    Dxx = Dxx + (C(1) - h * sn) * (C(2) * (ux * Fx - uy * Fy));
+    Dxy = Dxy + (C(1) - h * sn) * (ux * Fy + uy * Fx);
+    Djx = Fx;
+    Djy = Fy;
+  }
+  const C a0 = -De / C(36) - Dp / C(18);
+  const C gx = (Djx - Dqx) / C(6), gy = (Djy - Dqy) / C(6), P = Dxx / C(4);
+  const C d0 = De / C(18) + Dp / C(36);
+  const C hx = Djx / C(6) + Dqx / C(12), hy = Djy / C(6) + Dqy / C(12), X = Dxy / C(4);
+  f[0] = f[0] + (Dp - De) / C(9);
+  f[1] = f[1] + ((a0 + gx) + P);
+  f[3] = f[3] + ((a0 - gx) + P);
+  f[2] = f[2] + ((a0 + gy) - P);
+  f[4] = f[4] + ((a0 - gy) - P);
+  f[5] = f[5] + (((d0 + hx) + hy) + X);
+  f[6] = f[6] + (((d0 - hx) + hy) - X);
+  f[7] = f[7] + (((d0 - hx) - hy) + X);
+  f[8] = f[8] + (((d0 + hx) - hy) - X);
+}
+
+template <int SB>
+struct CollideMRT {
+  // Deviation form: the moments of d = f - w rho0 differ from those of f by
+  // rho0 (1, -2, 1, 0, ...), so e_eq and eps_eq shift by 2 rho0 and -rho0.
+  __device__ __forceinline__ static void run(const CaseDev &cp, int l, float d[9], float Fx, float Fy, float &rho,
+                                             float &ux, float &uy) {
+    const float e = d[1] + d[5] + d[8], w = d[3] + d[6] + d[7];
+    const float n = d[2] + d[5] + d[6], s = d[4] + d[7] + d[8];
+    const float jx = e - w, jy = n - s;
+    const float drho = d[0] + (e + w) + (d[2] + d[4]);
+    rho = (float)cp.rho0 + drho;
+    const float ir = __builtin_amdgcn_rcpf(rho);
+    ux = (jx + 0.5f * Fx) * ir;
+    uy = (jy + 0.5f * Fy) * ir;
+    const float ru2 = rho * (3.0f * (ux * ux + uy * uy));
+    mrt_update<float>(d, rho, ux, uy, Fx, Fy, -2.0f * drho + ru2, drho - ru2, cp.mrt_s_f[0], cp.mrt_s_f[1],
+                      cp.mrt_s_f[2], cp.omega_f[l]);
+  }
+};
+
+template <>
+struct CollideMRT<0> {
+  __device__ __forceinline__ static void run(const CaseDev &cp, int l, double f[9], double Fx, double Fy, double &rho,
+                                             double &ux, double &uy) {
+#pragma clang fp contract(off)
+    double jx, jy;
+    moments64(f, rho, jx, jy);
+    ux = (jx + 0.5 * Fx) / rho;
+    uy = (jy + 0.5 * Fy) / rho;
+    const double u2 = ux * ux + uy * uy;
+    mrt_update<double>(f, rho, ux, uy, Fx, Fy, rho * (-2.0 + 3.0 * u2), rho * (1.0 - 3.0 * u2), cp.mrt_s[0],
+                       cp.mrt_s[1], cp.mrt_s[2], 1.0 / cp.tau[l]);
+  }
+};
+
+template <bool B, class A, class Z> struct PickT { using type = A; };
+template <class A, class Z> struct PickT<false, A, Z> { using type = Z; };
+template <int ST>
+struct Collide : PickT<(ST & 4) != 0, CollideMRT<ST & 3>, CollideBGK<ST & 3>>::type {};
 
 // IBM force density at cell (x, y) of the finest block at (ox, oy) for the
 // collision of the substep the last forcing loop ran for (zero outside its
@@ -807,7 +910,7 @@ __device__ __forceinline__ const typename Store<ST>::T *nan_src() {
   using T = typename Store<ST>::T;
   const char *p = reinterpret_cast<const char *>(kNanSrc);
   if constexpr (sizeof(T) == 4) return reinterpret_cast<const T *>(p);
-  else if constexpr (ST == 3) return reinterpret_cast<const T *>(p + 2);  // bf16
+  else if constexpr ((ST & 3) == 3) return reinterpret_cast<const T *>(p + 2);  // bf16
   else return reinterpret_cast<const T *>(p + 4);
 }
 
@@ -1873,6 +1976,10 @@ extern "C" hipError_t sbt_launch_level_tile(int storage, const LevelArgs *a, hip
     case 1: SBT_TILE_LAUNCH(1); break;
     case 2: SBT_TILE_LAUNCH(2); break;
     case 3: SBT_TILE_LAUNCH(3); break;
+    case 4: SBT_TILE_LAUNCH(4); break;
+    case 5: SBT_TILE_LAUNCH(5); break;
+    case 6: SBT_TILE_LAUNCH(6); break;
+    case 7: SBT_TILE_LAUNCH(7); break;
     default: return hipErrorInvalidValue;
   }
 #undef SBT_TILE_LAUNCH
@@ -1885,6 +1992,10 @@ extern "C" hipError_t sbt_launch_level(int storage, int tile, const LevelArgs *a
     case 1: return launch_level_st<1>(tile, a, s);
     case 2: return launch_level_st<2>(tile, a, s);
     case 3: return launch_level_st<3>(tile, a, s);
+    case 4: return launch_level_st<4>(tile, a, s);
+    case 5: return launch_level_st<5>(tile, a, s);
+    case 6: return launch_level_st<6>(tile, a, s);
+    case 7: return launch_level_st<7>(tile, a, s);
   }
   return hipErrorInvalidValue;
 }

@@ -67,6 +67,20 @@ def test_plan_rejects_mixed_storage(pkg):
     assert pkg.lib().sbt_plan(arr, 2, C.byref(n)) == -1
 
 
+def test_plan_rejects_mixed_collision_and_bad_mrt_rates(pkg):
+    import ctypes as C
+    arr = (pkg.CaseDesc * 2)()
+    d0, k0 = pkg.make_desc(W.tgv(32), pkg.F32)
+    d1, k1 = pkg.make_desc(W.tgv(32).replace(collision=W.COLL_MRT), pkg.F32)
+    arr[0], arr[1] = d0, d1
+    n = C.c_size_t()
+    assert pkg.lib().sbt_plan(arr, 2, C.byref(n)) == -1
+    assert pkg.plan([W.tgv(32).replace(collision=W.COLL_MRT)]) > 0
+    for bad in ((0.0, 1.5, 1.5), (1.5, 2.0, 1.5), (1.5, 1.5, -1.0)):
+        with pytest.raises(pkg.SbtError):
+            pkg.plan([W.tgv(32).replace(collision=W.COLL_MRT, mrt_rates=bad)])
+
+
 def test_rescale_rejects_unit_tau(pkg):
     wl = W.tgv_patch(m=2, tau=1.0, cf_mode=W.CF_RESCALE)
     with pytest.raises(pkg.SbtError):

@@ -47,7 +47,10 @@ def run_pair(env, wl, steps, storage="f64", **kw):
     return g, o
 
 
-def compare_levels(g, o, wl, tol, c=0):
+def compare_levels(g, o, wl, tol, c=0, abs_u=0.0):
+    """Per level: relative L2 of u within tol, or (abs_u > 0: a level still
+    near rest, where relative error measures rounding only) every velocity
+    component within abs_u of the oracle's; densities within 10 tol."""
     errs = []
     for l in range(wl.n_levels):
         rg, ug, vg = g.fields(c, l)
@@ -55,9 +58,10 @@ def compare_levels(g, o, wl, tol, c=0):
         e = rel_l2(ug, vg, uo, vo)
         m = ~np.isnan(ro)
         er = np.abs(rg[m] - ro[m]).max()
-        print(f"  level {l}: rel L2 u {e:.3e}  max |drho| {er:.3e}", flush=True)
+        ea = max(np.abs(ug[m] - uo[m]).max(), np.abs(vg[m] - vo[m]).max())
+        print(f"  level {l}: rel L2 u {e:.3e}  max |du| {ea:.3e}  max |drho| {er:.3e}", flush=True)
         errs.append(e)
-        assert e <= tol, (l, e)
+        assert e <= tol or ea <= abs_u, (l, e, ea)
         assert er <= max(tol, 1e-15) * 10, (l, er)
     return errs
 
@@ -236,6 +240,40 @@ def test_force_stats_and_convergence_on_device(env):
     for a, b in zip(Eg, Eo):
         assert abs(a - b) <= 1e-10 * abs(b)
     assert g.convergence(snap)[0] == 0.0
+
+
+# ---- MRT collision --------------------------------------------------------
+
+@pytest.mark.parametrize("storage,tol", [("f64", TOL64), ("f32", 2e-5), ("f16s", 3e-3), ("bf16s", 3e-2)])
+def test_mrt_tgv(env, storage, tol):
+    """MRT collision (Sec. 2.1 option) on the 64^2 Taylor-Green vortex,
+    500 steps, every storage form against the FP64 oracle."""
+    wl = W.tgv(64).replace(collision=W.COLL_MRT)
+    g, o = run_pair(env, wl, 500, storage)
+    compare_levels(g, o, wl, tol)
+
+
+def test_mrt_refined_moving_body(env):
+    """MRT on a 3-level forest with a flapping body: interface, IBM forcing
+    in moment space and force history against the oracle (FP64)."""
+    wl = W.small_refined_flap().replace(collision=W.COLL_MRT)
+    g, o = run_pair(env, wl, 8)
+    compare_levels(g, o, wl, TOL64)
+    fxg, fyg = g.force_history()
+    fxo, fyo = o.force_history()
+    assert len(fxg) == len(fxo) > 0
+    assert np.abs(fyg - fyo).max() <= 1e-11 * np.abs(fyo).max()
+
+
+def test_mrt_cavity_rescale(env):
+    """MRT with the RESCALE interface and moving-wall edges (C3, 3 levels,
+    FP64, 10 steps).  The MRT forms round differently on the two sides (the
+    oracle multiplies by the moment matrices, the kernel uses their closed
+    forms), so the inner levels, still at rest to ~1e-8 after 10 steps, are
+    held to an absolute 1e-14 on u (a few ulps of the populations)."""
+    wl = W.cavity().replace(collision=W.COLL_MRT)
+    g, o = run_pair(env, wl, 10)
+    compare_levels(g, o, wl, TOL64, abs_u=1e-14)
 
 
 def test_flapping_ellipse_four_levels(env):
