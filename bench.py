@@ -138,6 +138,10 @@ def main():
     ap.add_argument("--tile", type=int, default=None)
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="automatic blocks per workgroup instead of the autotuner's choice")
+    ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"],
+                    help="collision model of the headline run")
+    ap.add_argument("--no-mrt", dest="mrt", action="store_false",
+                    help="skip the extra MRT-collision timing at the headline storage form")
     ap.add_argument("--copy-calib", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -163,7 +167,11 @@ def main():
         return
 
     import paper_2402_04606_amd as P
+    import workloads as W
     wls, wname = workload_list(args.workload)
+    if args.collision == "mrt":
+        wls = [w.replace(collision=W.COLL_MRT) for w in wls]
+        wname += "_mrt"
     V = max(w.n_levels for w in wls)
 
     # ---- headline form, timed with graphs --------------------------------------
@@ -224,6 +232,17 @@ def main():
                 forms[st]["worst_case_rel_l2_u"] = float(f"{worst:.3e}")
                 forms[st]["after_steps"] = total_steps
 
+    # ---- the same step with the other collision model --------------------------
+    if args.mrt:
+        other = W.COLL_BGK if args.collision == "mrt" else W.COLL_MRT
+        wo = [w.replace(collision=other) for w in wls]
+        s3, dt3, _ = time_form(P, wo, args.storage, args.steps, args.warmup, args.tile, args.autotune)
+        p3 = s3.profile(args.profile_steps)
+        forms[("bgk" if other == W.COLL_BGK else "mrt") + "_" + args.storage] = {
+            "mlups": round(ups * args.steps / dt3 / 1e6, 1), "ms_per_step": round(dt3 * 1e3 / args.steps, 3),
+            "tile_gbs": round(p3["fast_bytes"] / (p3["fast_ms"] * 1e-3) / 1e9, 1) if p3["fast_ms"] > 0 else 0.0}
+        del s3
+
     out = {
         "metric": "MLUPS & HBM GB/s fraction; FP16/FP32-storage vs FP64 at stated L2 error",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -231,7 +250,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic",
         "config": {"workload": wname, "cases": len(wls), "levels": sorted({w.n_levels for w in wls}),
-                   "storage": args.storage, "updates_per_step": ups, "block": "16x16",
+                   "storage": args.storage, "collision": args.collision, "updates_per_step": ups,
+                   "block": "16x16",
                    "parallelism": "single GPU, all cases in one context"},
         "roofline": roofline,
         "forms": forms,
