@@ -84,6 +84,7 @@ def lib():
         _lib.orc_interpolate.argtypes = [C.c_int32, C.c_int32, d, d, C.c_int32, d, d, d, d]
         _lib.orc_spread.argtypes = [C.c_int32, C.c_int32, C.c_int32, d, d, d, d, d, d, d]
         _lib.orc_force_stats.argtypes = [d, d, C.c_int32, C.c_double, C.c_double, d]
+        _lib.orc_set_solid.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_uint8), d]
         _lib.orc_num_threads.argtypes = []
     return _lib
 
@@ -140,6 +141,13 @@ class OracleSim:
             raise RuntimeError(f"orc_create failed: {rc}")
         self._h = h
         self.n_levels = wl.n_levels
+        for level, mask, q in getattr(wl, "solids", ()):
+            m = np.ascontiguousarray(mask, dtype=np.uint8)
+            qq = None if q is None else _f64(q)
+            rc = lib().orc_set_solid(h, level, m.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                     None if qq is None else _dp(qq))
+            if rc != 0:
+                raise RuntimeError(f"orc_set_solid failed: {rc}")
         if wl.init is not None:
             for l in range(wl.n_levels):
                 nx, ny = self.level_size(l)

@@ -65,6 +65,9 @@ typedef struct {
     double *f, *fs;           /* pre-collision / post-collision populations */
     double *rho, *ux, *uy;    /* moments used by the last collision          */
     double *Fx, *Fy;          /* IBM force density (finest level only)       */
+    uint8_t *solid;           /* solid (bounce-back) cells, or NULL          */
+    double *sq;               /* [cell][9] wall fraction of link i from a fluid
+                                 cell toward a solid neighbour x + c_i       */
 } olev;
 
 struct orc_sim {
@@ -482,7 +485,7 @@ void orc_destroy(orc_sim *s) {
     for (int l = 0; l < MAXL; ++l) {
         olev *L = &s->L[l];
         free(L->kind); free(L->f); free(L->fs); free(L->rho); free(L->ux); free(L->uy);
-        free(L->Fx); free(L->Fy);
+        free(L->Fx); free(L->Fy); free(L->solid); free(L->sq);
     }
     free(s->boxes); free(s->xb); free(s->yb); free(s->ds); free(s->hist); free(s->hud);
     free(s->ftx); free(s->fty);
@@ -660,7 +663,7 @@ static void collision(orc_sim *s, int l) {
     for (int y = 0; y < L->ny; ++y)
         for (int x = 0; x < L->nx; ++x) {
             size_t q = cid(L, x, y);
-            if (L->kind[q] != K_OWN) continue;
+            if (L->kind[q] != K_OWN || (L->solid && L->solid[q])) continue;
             double Fx = L->fx, Fy = L->fy;
             if (finest) { Fx += L->Fx[q]; Fy += L->Fy[q]; }
             double mom[3];
@@ -699,6 +702,29 @@ static void coarse_to_fine(orc_sim *s, int lc, int lf) {
 /* StreamingStep, Eq. (10), over owned and halo cells; same-level exchange is
  * implicit in the dense arrays (with the periodic wrap).  Unknown incoming
  * populations are left NaN for the boundary and fine-to-coarse steps. */
+static int opposite(int i);
+
+/* Interpolated bounce-back of Bouzidi, Firdaouss and Lallemand (linear form,
+ * resting wall), the solid-cell alternative to the IBM named in Sec. 2.1 and
+ * used in Sec. 3.2.  The population of direction i that fluid cell x would
+ * pull from a solid neighbour x - c_i instead comes from the population
+ * o = opposite(i) that x sent toward the wall, which sits at fraction q of
+ * the link x -> x + c_o:
+ *   q <  1/2:  f_i(x) = 2q f*_o(x) + (1 - 2q) f*_o(x - c_o)
+ *   q >= 1/2:  f_i(x) = f*_o(x) / (2q) + (2q - 1)/(2q) f*_i(x).
+ * (q = 1/2 is half-way bounce-back.) */
+static double bouzidi(const orc_sim *s, const olev *L, int x, int y, int i) {
+    int o = opposite(i);
+    size_t c = cid(L, x, y);
+    double q = L->sq[c * Q + o];
+    if (q < 0.5) {
+        int ux = x - CX[o], uy = y - CY[o];
+        wrap_level(s, L, &ux, &uy);
+        return 2.0 * q * L->fs[c * Q + o] + (1.0 - 2.0 * q) * L->fs[cid(L, ux, uy) * Q + o];
+    }
+    return L->fs[c * Q + o] / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * L->fs[c * Q + i];
+}
+
 static void streaming(orc_sim *s, int l) {
     olev *L = &s->L[l];
 #pragma omp parallel for schedule(static)
@@ -707,12 +733,17 @@ static void streaming(orc_sim *s, int l) {
             size_t q = cid(L, x, y);
             uint8_t kd = L->kind[q];
             if (kd != K_OWN && kd != K_GHOST) continue;
+            if (L->solid && L->solid[q]) continue;
             for (int i = 0; i < Q; ++i) {
                 int sx = x - CX[i], sy = y - CY[i];
                 double v = NAN;
                 if (wrap_level(s, L, &sx, &sy)) {
                     size_t p = cid(L, sx, sy);
-                    if (L->kind[p] == K_OWN || L->kind[p] == K_GHOST) v = L->fs[p * Q + i];
+                    if (L->solid && L->solid[p]) {
+                        v = bouzidi(s, L, x, y, i);
+                    } else if (L->kind[p] == K_OWN || L->kind[p] == K_GHOST) {
+                        v = L->fs[p * Q + i];
+                    }
                 }
                 L->f[q * Q + i] = v;
             }
@@ -886,7 +917,7 @@ int orc_read_fields(const orc_sim *s, int level, double *rho, double *ux, double
     if (level < 0 || level >= s->m) return ORC_ERR_ARG;
     const olev *L = &s->L[level];
     for (size_t q = 0; q < (size_t)L->nx * L->ny; ++q) {
-        if (L->kind[q] != K_OWN) { rho[q] = ux[q] = uy[q] = NAN; continue; }
+        if (L->kind[q] != K_OWN || (L->solid && L->solid[q])) { rho[q] = ux[q] = uy[q] = NAN; continue; }
         const double *f = L->f + q * Q;
         double r = 0.0, jx = 0.0, jy = 0.0;
         for (int i = 0; i < Q; ++i) { r += f[i]; jx += CX[i] * f[i]; jy += CY[i] * f[i]; }
@@ -939,7 +970,7 @@ int orc_diagnostics(const orc_sim *s, double out[3]) {
         double vol = 1.0 / (double)(1 << (2 * l));
         double m = 0.0, px = 0.0, py = 0.0;
         for (size_t q = 0; q < (size_t)L->nx * L->ny; ++q) {
-            if (L->kind[q] != K_OWN) continue;
+            if (L->kind[q] != K_OWN || (L->solid && L->solid[q])) continue;
             const double *f = L->f + q * Q;
             for (int i = 0; i < Q; ++i) { m += f[i]; px += CX[i] * f[i]; py += CY[i] * f[i]; }
         }
@@ -986,5 +1017,52 @@ int orc_force_stats(const double *fx, const double *fy, int32_t n, double scale,
     out[4] = up >= 2 ? (double)(up - 1) / (last - first) * l_over_u : 0.0;
     out[5] = up;
     out[6] = n;
+    return ORC_OK;
+}
+
+/* Solid cells of a level for the interpolated bounce-back (see bouzidi()).
+ * mask: dense level cells, 1 = solid.  q: dense [cell][9], read for fluid
+ * cells x whose neighbour x + c_i is solid (0 < q <= 1; NULL: 1/2 on every
+ * link).  Every cell within two cells of a solid cell must be an owned cell
+ * of this level (no halo, no covered cell, no domain edge).  Where q < 1/2
+ * and the upstream cell x - c_i is solid too, the link takes q = 1/2
+ * (half-way bounce-back).  Only before the first step. */
+int orc_set_solid(orc_sim *s, int level, const uint8_t *mask, const double *q) {
+    if (level < 0 || level >= s->m || !mask) return ORC_ERR_ARG;
+    olev *L = &s->L[level];
+    size_t n = (size_t)L->nx * L->ny;
+    uint8_t *sm = calloc(n, 1);
+    double *sq = malloc(sizeof(double) * n * Q);
+    for (size_t c = 0; c < n * Q; ++c) sq[c] = 0.5;
+    for (size_t c = 0; c < n; ++c) sm[c] = mask[c] ? 1 : 0;
+    for (int y = 0; y < L->ny; ++y)
+        for (int x = 0; x < L->nx; ++x) {
+            if (!sm[cid(L, x, y)]) continue;
+            for (int dy = -2; dy <= 2; ++dy)
+                for (int dx = -2; dx <= 2; ++dx) {
+                    int xx = x + dx, yy = y + dy;
+                    if (!wrap_level(s, L, &xx, &yy) || L->kind[cid(L, xx, yy)] != K_OWN) {
+                        free(sm); free(sq);
+                        return ORC_ERR_TOPOLOGY;
+                    }
+                }
+        }
+    for (int y = 0; y < L->ny; ++y)
+        for (int x = 0; x < L->nx; ++x) {
+            size_t c = cid(L, x, y);
+            if (sm[c]) continue;
+            for (int i = 1; i < Q; ++i) {
+                int nx_ = x + CX[i], ny_ = y + CY[i];
+                if (!wrap_level(s, L, &nx_, &ny_) || !sm[cid(L, nx_, ny_)]) continue;
+                double v = q ? q[c * Q + i] : 0.5;
+                if (!(v > 0.0 && v <= 1.0)) { free(sm); free(sq); return ORC_ERR_ARG; }
+                int ux = x - CX[i], uy = y - CY[i];
+                if (v < 0.5 && (!wrap_level(s, L, &ux, &uy) || sm[cid(L, ux, uy)])) v = 0.5;
+                sq[c * Q + i] = v;
+            }
+        }
+    free(L->solid); free(L->sq);
+    L->solid = sm;
+    L->sq = sq;
     return ORC_OK;
 }

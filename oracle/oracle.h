@@ -82,6 +82,11 @@ int  orc_force_history(const orc_sim *s, int32_t cap, double *fx, double *fy, in
  * volume weight 4^-l; momentum is the bare first moment sum_i c_i f_i. */
 int  orc_diagnostics(const orc_sim *s, double out[3]);
 int64_t orc_substeps(const orc_sim *s);
+/* Solid cells of a level with interpolated bounce-back on their links (the
+ * solid-cell alternative to the IBM, Sec. 2.1 / Sec. 3.2): mask dense level
+ * cells (1 = solid), q dense [cell][9] wall fraction of link i from a fluid
+ * cell toward a solid x + c_i (NULL: 1/2).  Before the first step. */
+int  orc_set_solid(orc_sim *s, int level, const uint8_t *mask, const double *q);
 
 /* ---- building blocks, exposed so the test-suite can pin them ------------ */
 void   orc_velocity_set(int32_t cx[9], int32_t cy[9], double w[9]);

@@ -385,6 +385,67 @@ def test_pitching_bodies_rotate_rigidly_about_the_pivot(orc, make):
         assert abs(math.remainder(th0 - th - alpha, 2 * math.pi)) < 1e-10
 
 
+# ---- Solid cells with interpolated bounce-back (Sec. 2.1, Sec. 3.2) --------
+
+def _ibb_profile_error(orc, ny, qb, qt, tau, steps):
+    wl = W.ibb_channel(nx=4, ny=ny, tau=tau, q_bottom=qb, q_top=qt)
+    s = orc.OracleSim(wl)
+    s.step(steps)
+    _, u, v = s.fields(0)
+    g, nu = wl.meta["g"], wl.meta["nu"]
+    y = np.arange(ny) + 0.5
+    ua = g / (2 * nu) * (y - wl.meta["y_b"]) * (wl.meta["y_t"] - y)
+    m = ~np.isnan(u[:, 0])
+    assert m.sum() == ny - 2 and np.isnan(u[:2]).all()          # the solid rows read NaN
+    assert np.abs(v[m]).max() < 1e-13
+    return np.abs(u[m, 0] - ua[m]).max() / ua[m].max()
+
+
+def test_ibb_half_way_walls_give_the_exact_channel(orc):
+    """q = 1/2 is half-way bounce-back: at tau = 1/2 + sqrt(3)/4 the body-
+    forced channel between solid rows is the exact parabola with walls half
+    a cell beyond the last fluid rows (as P8 for domain walls)."""
+    assert _ibb_profile_error(orc, 20, 0.5, 0.5, 0.5 + math.sqrt(3) / 4, 30000) < 1e-9
+
+
+def test_ibb_off_grid_walls_converge_at_second_order(orc):
+    """Walls at fractions 0.3 and 0.7 of the wall links: the steady profile
+    approaches the parabola between the interpolated wall positions, the
+    error falling about fourfold per doubling of the channel (second order
+    in space)."""
+    errs = [_ibb_profile_error(orc, ny, 0.3, 0.7, 0.8, int(3 * ny * ny / 0.1)) for ny in (12, 22, 42)]
+    assert errs[2] < 1e-3
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+def test_ibb_short_link_without_fluid_behind_is_half_way(orc):
+    """A one-row fluid gap between solid rows: no fluid cell lies behind any
+    short link, so q = 0.3 acts as q = 1/2 (the rule of the solid-cell
+    interface), bit for bit."""
+    runs = []
+    for qb in (0.3, 0.5):
+        s = orc.OracleSim(W.ibb_channel(nx=4, ny=3, tau=0.8, q_bottom=qb, q_top=qb))
+        s.step(50)
+        runs.append(s.populations(0))
+    assert np.array_equal(runs[0], runs[1], equal_nan=True)
+
+
+def test_ibb_cylinder_flow_is_mirror_symmetric(orc):
+    """A solid circle on the centre line of a symmetric channel: u even and v
+    odd about the centre line (a wrong link fraction or direction in the
+    bounce-back breaks the mirror symmetry)."""
+    wl = W.ibb_cylinder()
+    s = orc.OracleSim(wl)
+    s.step(300)
+    _, u, v = s.fields(0)
+    m = ~np.isnan(u)
+    assert np.array_equal(m, m[::-1])
+    su = np.abs(np.nan_to_num(u - u[::-1])).max()
+    sv = np.abs(np.nan_to_num(v + v[::-1])).max()
+    assert su < 1e-12 * np.nanmax(np.abs(u)) and sv < 1e-12 * np.nanmax(np.abs(u)), (su, sv)
+    assert np.nanmax(np.abs(v)) > 1e-4                                # the body deflects the flow
+
+
 # ---- Run statistics (Sec. 3.2 criterion E, Sec. 3.3 Eq. (21)) ------------
 
 def test_force_stats_of_a_sampled_sinusoid(orc):

@@ -69,6 +69,9 @@ class Workload:
     collision: int = COLL_BGK
     mrt_rates: tuple = MRT_RATES
     body: Optional[Body] = None
+    # solid cells with interpolated bounce-back: (level, mask [ny, nx] uint8,
+    # q [ny, nx, 9] wall fraction of link i toward a solid neighbour, or None)
+    solids: list = dataclasses.field(default_factory=list)
     init: Optional[Callable] = None   # init(level, nx, ny) -> (rho, ux, uy) dense [ny, nx]
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -411,3 +414,75 @@ def small_pitching_airfoil(m=3, Re=100.0):
     crosses every breakpoint of the law."""
     return pitching_airfoil(chord=32.0, m=m, Re=Re, alpha0_deg=4.0, k_red=20.0, nx_c=16.0, ny_c=12.0,
                             x_c=5.0, name=f"small_pitching_airfoil{m}")
+
+
+# ---- solid cells for the interpolated bounce-back (Sec. 2.1, Sec. 3.2) -----
+
+_CX = (0, 1, 0, -1, 0, 1, -1, -1, 1)
+_CY = (0, 0, 1, 0, -1, 1, 1, -1, -1)
+
+
+def solid_circle(nx, ny, cx, cy, r):
+    """Cells whose centres lie inside the circle (centre (cx, cy), radius r,
+    level cells) are solid; for a fluid cell x and a direction i with
+    x + c_i solid, q is the fraction of the link from the centre of x along
+    c_i at which it meets the circle."""
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    px, py = xx + 0.5, yy + 0.5
+    mask = ((px - cx) ** 2 + (py - cy) ** 2 < r * r).astype(np.uint8)
+    q = np.full((ny, nx, 9), 0.5)
+    for i in range(1, 9):
+        dx, dy = _CX[i], _CY[i]
+        a = dx * dx + dy * dy
+        b = 2 * (dx * (px - cx) + dy * (py - cy))
+        c = (px - cx) ** 2 + (py - cy) ** 2 - r * r
+        disc = np.sqrt(np.maximum(b * b - 4 * a * c, 0.0))
+        t = (-b - disc) / (2 * a)
+        nb = np.roll(np.roll(mask, -dy, axis=0), -dx, axis=1)
+        hit = (mask == 0) & (nb == 1)
+        q[..., i] = np.where(hit, np.clip(t, 1e-6, 1.0), 0.5)
+    return mask, q
+
+
+def solid_channel(nx, ny, q_bottom=0.5, q_top=0.5):
+    """Periodic channel whose rows 0 and 1 are solid: fluid rows 2 .. ny-1
+    see a wall q_bottom below the centre of row 2 and q_top above the
+    centre of row ny-1 (through the periodic wrap)."""
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    mask[0:2] = 1
+    q = np.full((ny, nx, 9), 0.5)
+    for i in range(1, 9):
+        if _CY[i] < 0:
+            q[2, :, i] = q_bottom
+        if _CY[i] > 0:
+            q[ny - 1, :, i] = q_top
+    return mask, q
+
+
+def ibb_channel(nx=16, ny=32, tau=0.5 + math.sqrt(3) / 4, g=1e-6, q_bottom=0.5, q_top=0.5):
+    """Body-forced flow between the walls of solid_channel (fully periodic
+    domain); wall positions y_b = 2.5 - q_bottom, y_t = ny - 0.5 + q_top."""
+    mask, q = solid_channel(nx, ny, q_bottom, q_top)
+    return Workload(name=f"ibb_channel_q{q_bottom}_{q_top}", nx0=nx, ny0=ny, tau0=tau, fext=(g, 0.0),
+                    solids=[(0, mask, q)], init=uniform_init(1.0, 0.0, 0.0),
+                    meta=dict(g=g, nu=(tau - 0.5) / 3.0, y_b=2.5 - q_bottom, y_t=ny - 0.5 + q_top))
+
+
+def ibb_cylinder(nx=128, ny=64, D=12.0, centre=(40.0, 32.0), U=0.05, Re=40.0):
+    """Stationary cylinder as solid cells with interpolated bounce-back in the
+    channel of small_cylinder (inflow, outflow, symmetry edges)."""
+    nu = U * D / Re
+    mask, q = solid_circle(nx, ny, centre[0], centre[1], D / 2.0)
+    return Workload(name=f"ibb_cylinder{nx}x{ny}", nx0=nx, ny0=ny, tau0=3 * nu + 0.5,
+                    bc=(INFLOW, OUTFLOW, SYMMETRY, SYMMETRY), bc_u=((U, 0.0),) + ((0.0, 0.0),) * 3,
+                    solids=[(0, mask, q)], init=uniform_init(1.0, U, 0.0), meta=dict(U=U, D=D, Re=Re))
+
+
+def cavity_ibb(cf_mode=CF_RESCALE, U=0.1, Re=1000.0):
+    """The 3-level cavity of cavity() with its cylinder (D = 128 finest cells at
+    the centre) as solid cells with interpolated bounce-back instead of IBM
+    markers -- the comparison of Sec. 3.2."""
+    wl = cavity(cf_mode, U, Re)
+    n2 = wl.nx0 * 4
+    mask, q = solid_circle(n2, n2, 512.0, 512.0, 64.0)
+    return wl.replace(name="cavity256_3lvl_ibb", body=None, solids=[(2, mask, q)])
