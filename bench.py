@@ -31,6 +31,8 @@ def workload_list(name):
         return [W.cylinder()], "cylinder_1024x512_D40_126markers"
     if name == "cavity":
         return [W.cavity()], "cavity_256_3levels_D32_lid0.1_rescale"
+    if name == "cavity_ibb":
+        return [W.cavity_ibb()], "cavity_256_3levels_D32_lid0.1_rescale_solid_cylinder_ibb"
     if name == "flap":
         return [W.flapping_ellipse()], "flapping_ellipse_512x256_4levels_200markers"
     if name == "tgv8192":

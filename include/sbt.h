@@ -125,6 +125,28 @@ typedef struct {
     int32_t bx0, by0, bx1, by1;    /* half-open box in level-`level` block units  */
 } sbt_box;
 
+/* Solid cells with interpolated bounce-back: the paper's solid-cell
+ * alternative to the IBM (Sec. 2.1; compared with it in Sec. 3.2), in the
+ * linear form of Bouzidi, Firdaouss and Lallemand for a resting wall.  A
+ * fluid cell x pulls population i from a solid neighbour x - c_i instead
+ * from the population o = opposite(i) it sent toward the wall, which sits at
+ * fraction q of the link x -> x + c_o:
+ *   q <  1/2:  f_i(x) = 2q f*_o(x) + (1 - 2q) f*_o(x - c_o),
+ *   q >= 1/2:  f_i(x) = f*_o(x) / (2q) + (2q - 1)/(2q) f*_i(x)
+ * (q = 1/2 is half-way bounce-back; where q < 1/2 and x - c_o is solid too,
+ * the link takes q = 1/2).  Solid cells are not collided and read out as NaN.
+ * mask: dense level cells [ny][nx], nonzero = solid.  q: dense [ny][nx][9],
+ * q[x][i] the wall fraction of the link from fluid cell x toward a solid
+ * x + c_i (0 < q <= 1, read only there); NULL = 1/2 everywhere.  Every cell
+ * within two cells of a solid cell must be an owned cell of that level not
+ * covered by a finer level (no halo, no interface, inside the domain or
+ * across a periodic edge).  Host arrays, read during sbt_plan/sbt_create. */
+typedef struct {
+    int32_t level;
+    const uint8_t *mask;
+    const double *q;
+} sbt_solid;
+
 typedef struct {
     int32_t nx0, ny0;              /* level-0 cells, multiples of block_n          */
     int32_t block_n;               /* cells per block edge; must be 16             */
@@ -143,6 +165,8 @@ typedef struct {
     int32_t history_cap;           /* finest substeps of force history kept        */
     int32_t collision;             /* SBT_COLL_* (same for every case of a ctx)    */
     double mrt_rates[3];           /* SBT_COLL_MRT: s_e, s_eps, s_q in (0, 2)      */
+    const sbt_solid *solids;       /* solid regions (at most one per level)        */
+    int32_t n_solids;
 } sbt_case_desc;
 
 typedef struct {

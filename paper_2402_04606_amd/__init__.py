@@ -46,6 +46,10 @@ class Box(C.Structure):
                 ("by1", C.c_int32)]
 
 
+class Solid(C.Structure):
+    _fields_ = [("level", C.c_int32), ("mask", C.POINTER(C.c_uint8)), ("q", C.POINTER(C.c_double))]
+
+
 class CaseDesc(C.Structure):
     _fields_ = [
         ("nx0", C.c_int32), ("ny0", C.c_int32), ("block_n", C.c_int32), ("n_levels", C.c_int32),
@@ -55,6 +59,7 @@ class CaseDesc(C.Structure):
         ("storage", C.c_int32), ("cf_mode", C.c_int32), ("mdf_iters", C.c_int32),
         ("max_markers", C.c_int32), ("history_cap", C.c_int32),
         ("collision", C.c_int32), ("mrt_rates", C.c_double * 3),
+        ("solids", C.POINTER(Solid)), ("n_solids", C.c_int32),
     ]
 
 
@@ -145,7 +150,23 @@ def make_desc(wl, storage=F64, history_cap=1 << 16, max_markers=None):
     d.collision = getattr(wl, "collision", 0)
     for k, v in enumerate(getattr(wl, "mrt_rates", (0.0, 0.0, 0.0))):
         d.mrt_rates[k] = v
-    return d, boxes
+    keep = [boxes]
+    solids = list(getattr(wl, "solids", ()))
+    if solids:
+        arr = (Solid * len(solids))()
+        for k, (level, mask, q) in enumerate(solids):
+            m = np.ascontiguousarray(mask, dtype=np.uint8)
+            keep.append(m)
+            arr[k].level = level
+            arr[k].mask = m.ctypes.data_as(C.POINTER(C.c_uint8))
+            if q is not None:
+                qq = np.ascontiguousarray(q, dtype=np.float64)
+                keep.append(qq)
+                arr[k].q = _dp(qq)
+        keep.append(arr)
+        d.solids = C.cast(arr, C.POINTER(Solid))
+        d.n_solids = len(solids)
+    return d, keep
 
 
 def plan(workloads, storage=F64):

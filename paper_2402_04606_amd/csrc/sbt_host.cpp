@@ -51,6 +51,7 @@ uint32_t morton(uint32_t x, uint32_t y) {
 }
 
 const int DCX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};  // opposite direction
 const int DCY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 // ---------------------------------------------------------------------------
@@ -230,6 +231,12 @@ struct Pool {
   std::vector<BlockMeta> meta;
   std::vector<uint16_t> codes;
   std::vector<int32_t> fast, slow, band;   // interior blocks, other owned blocks, halo-band cells
+  std::vector<int32_t> solid;              // blocks with solid cells or links (generic kernel)
+  std::vector<uint16_t> sbits;             // solid records [record][256]
+  std::vector<double> sq;                  // [record][9][256]
+  uint16_t *d_sbits = nullptr;
+  double *d_sq = nullptr;
+  int32_t *d_solid = nullptr;
   BlockMeta *d_meta = nullptr;
   uint16_t *d_codes = nullptr;
   int32_t *d_list = nullptr, *d_band = nullptr;   // d_list = fast blocks, then slow blocks
@@ -248,6 +255,8 @@ struct CaseHost {
   CaseDev dev;                     // host copy (pointers already device)
   std::vector<int32_t> bmap;
   bool has_body = false;
+  std::vector<std::vector<uint8_t>> smask;  // per level: dense solid mask (empty = none)
+  std::vector<std::vector<double>> sq;      // per level: dense [cell][9] wall fractions
   int n_markers = 0;
   int win_cap = 0;
   size_t hist_cap = 0;
@@ -305,6 +314,54 @@ namespace {
 
 void build_tables(sbt_ctx &X);
 
+// Copy and validate a case's solid regions (dense per level), applying the
+// q = 1/2 rule where a short link has no fluid cell behind it.
+sbt_status take_solids(CaseHost &C) {
+  const Forest &F = C.F;
+  C.smask.assign(F.m, {});
+  C.sq.assign(F.m, {});
+  if (C.d.n_solids < 0 || (C.d.n_solids > 0 && !C.d.solids)) return fail(SBT_ERR_ARG, "bad solid list");
+  for (int k = 0; k < C.d.n_solids; ++k) {
+    const sbt_solid &S = C.d.solids[k];
+    if (S.level < 0 || S.level >= F.m || !S.mask) return fail(SBT_ERR_ARG, "bad solid level or mask");
+    const int l = S.level, nx = F.nx[l], ny = F.ny[l];
+    if (!C.smask[l].empty()) return fail(SBT_ERR_ARG, "one solid region per level");
+    std::vector<uint8_t> &m = C.smask[l];
+    m.assign((size_t)nx * ny, 0);
+    bool any = false;
+    for (size_t q = 0; q < m.size(); ++q) any |= (m[q] = S.mask[q] ? 1 : 0) != 0;
+    if (!any) {
+      m.clear();
+      continue;
+    }
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        if (!m[(size_t)y * nx + x]) continue;
+        for (int dy = -2; dy <= 2; ++dy)
+          for (int dx = -2; dx <= 2; ++dx)
+            if (!F.cell_own(l, x + dx, y + dy))
+              return fail(SBT_ERR_TOPOLOGY, "solid cells need two owned, uncovered cells of their level around them");
+      }
+    std::vector<double> &sq = C.sq[l];
+    sq.assign((size_t)nx * ny * kQ, 0.5);
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const size_t c = (size_t)y * nx + x;
+        if (m[c]) continue;
+        for (int i = 1; i < kQ; ++i) {
+          int ax = x + DCX[i], ay = y + DCY[i];
+          if (!F.wrapc(l, ax, ay) || !m[(size_t)ay * nx + ax]) continue;
+          double v = S.q ? S.q[c * kQ + i] : 0.5;
+          if (!(v > 0.0 && v <= 1.0)) return fail(SBT_ERR_ARG, "wall fractions must lie in (0, 1]");
+          int ux = x - DCX[i], uy = y - DCY[i];
+          if (v < 0.5 && (!F.wrapc(l, ux, uy) || m[(size_t)uy * nx + ux])) v = 0.5;
+          sq[c * kQ + i] = v;
+        }
+      }
+  }
+  return SBT_OK;
+}
+
 sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Carver &cv) {
   if (!cases || n_cases <= 0) return fail(SBT_ERR_ARG, "no cases");
   X.n_cases = n_cases;
@@ -320,6 +377,8 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     C.boxes.assign(C.d.refine, C.d.refine + std::max(0, C.d.n_refine));
     C.d.refine = C.boxes.data();
     sbt_status st = build_forest(C.d, C.F);
+    if (st) return fail(st, "case " + std::to_string(c) + ": " + g_err);
+    st = take_solids(C);
     if (st) return fail(st, "case " + std::to_string(c) + ": " + g_err);
     if (C.d.cf_mode == SBT_CF_RESCALE)
       for (int l = 0; l + 1 < C.F.m; ++l) {
@@ -417,6 +476,9 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
     P.d_codes = (uint16_t *)cv.take(sizeof(uint16_t) * std::max<size_t>(1, P.codes.size()));
     P.d_list = (int32_t *)cv.take(sizeof(int32_t) * std::max<size_t>(1, P.fast.size() + P.slow.size()));
     P.d_band = (int32_t *)cv.take(sizeof(int32_t) * std::max<size_t>(1, P.band.size()));
+    P.d_solid = (int32_t *)cv.take(sizeof(int32_t) * std::max<size_t>(1, P.solid.size()));
+    P.d_sbits = (uint16_t *)cv.take(sizeof(uint16_t) * std::max<size_t>(1, P.sbits.size()));
+    P.d_sq = (double *)cv.take(sizeof(double) * std::max<size_t>(1, P.sq.size()));
     P.lat[0] = cv.take(s * kQ * kCells * (size_t)P.total());
     P.lat[1] = cv.take(s * kQ * kCells * (size_t)P.total());
   }
@@ -468,6 +530,8 @@ void build_tables(sbt_ctx &X) {
   for (auto &P : X.pools) {
     P.meta.assign(P.total(), BlockMeta());
     P.codes.clear();
+    P.sbits.clear();
+    P.sq.clear();
   }
   for (int c = 0; c < X.n_cases; ++c) {
     CaseHost &C = X.cs[c];
@@ -507,6 +571,36 @@ void build_tables(sbt_ctx &X) {
           M.level = l;
           M.flags = pass == 1 ? BF_GHOST : 0;
           M.code = -1;
+          M.solid = -1;
+          if (pass == 0 && !C.smask[l].empty()) {  // solid cells and the links into them
+            const std::vector<uint8_t> &sm = C.smask[l];
+            std::vector<uint16_t> bits(kCells, 0);
+            std::vector<double> qv((size_t)kQ * kCells, 0.5);
+            bool any = false;
+            for (int cell = 0; cell < kCells; ++cell) {
+              const int gx = M.ox + (cell & 15), gy = M.oy + (cell >> 4);
+              const size_t g = (size_t)gy * F.nx[l] + gx;
+              if (sm[g]) {
+                bits[cell] = SB_SOLID;
+                any = true;
+                continue;
+              }
+              for (int i = 1; i < kQ; ++i) {
+                int sx = gx - DCX[i], sy = gy - DCY[i];
+                if (!F.wrapc(l, sx, sy) || !sm[(size_t)sy * F.nx[l] + sx]) continue;
+                const int o = OPP[i];  // the population sent toward the wall
+                bits[cell] |= (uint16_t)(1u << i);
+                qv[(size_t)i * kCells + cell] = C.sq[l][g * kQ + o];
+                any = true;
+              }
+            }
+            if (any) {
+              M.flags |= BF_SOLID;
+              M.solid = (int32_t)(P.sbits.size() / kCells);
+              P.sbits.insert(P.sbits.end(), bits.begin(), bits.end());
+              P.sq.insert(P.sq.end(), qv.begin(), qv.end());
+            }
+          }
           if (pass == 0 && l == 0) {
             if ((!F.per_x && (bx == 0 || bx == F.nbx[0] - 1)) || (!F.per_y && (by == 0 || by == F.nby[0] - 1)))
               M.flags |= BF_EDGE;
@@ -604,8 +698,13 @@ void build_tables(sbt_ctx &X) {
     P.fast.clear();
     P.slow.clear();
     P.band.clear();
+    P.solid.clear();
     for (int b = 0; b < P.n_own; ++b) {
       const BlockMeta &M = P.meta[b];
+      if (M.flags & BF_SOLID) {
+        P.solid.push_back(b);
+        continue;
+      }
       bool all_nbr = true;
       for (int d = 0; d < 8; ++d) all_nbr &= M.nbr[d] >= 0;
       if (!(M.flags & (BF_CODES | BF_EDGE)) && all_nbr) P.fast.push_back(b);
@@ -679,6 +778,8 @@ sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s
   std::memset(&a, 0, sizeof(a));
   a.meta = P.d_meta;
   a.codes = P.d_codes;
+  a.sbits = P.d_sbits;
+  a.sq = P.d_sq;
   a.src = P.lat[P.cur];
   a.dst = P.lat[1 - P.cur];
   if (v + 1 < X.V) {
@@ -720,6 +821,12 @@ sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s
       t.n_band = (int)P.band.size();
     }
     if (t.n_blocks + t.n_band > 0) st = timed(true, [&] { return sbt_launch_level_tile(X.kvar, &t, s); });
+    if (!st && !P.solid.empty()) {  // blocks next to solid cells: generic kernel, same substep
+      LevelArgs u = a;
+      u.list = P.d_solid;
+      u.n_blocks = (int)P.solid.size();
+      st = timed(false, [&] { return sbt_launch_level(X.kvar, 0, &u, s); });
+    }
   } else {
     a.list = nullptr;
     a.b0 = 0;
@@ -946,6 +1053,8 @@ sbt_status readout_level(sbt_ctx &X, int c, int l, hipStream_t s) {
   a.kpw = 1;
   a.meta = P.d_meta;
   a.codes = P.d_codes;
+  a.sbits = P.d_sbits;
+  a.sq = P.d_sq;
   // after a step the state to read is the one the last launch streamed from
   a.src = X.post ? P.lat[1 - P.cur] : P.lat[P.cur];
   if (v + 1 < X.V) {
@@ -1051,6 +1160,13 @@ sbt_status sbt_create(const sbt_case_desc *cases, int32_t n_cases, void *device_
                            hipMemcpyHostToDevice, s) == hipSuccess;
     if (!P.band.empty())
       ok &= hipMemcpyAsync(P.d_band, P.band.data(), sizeof(int32_t) * P.band.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    if (!P.solid.empty()) {
+      ok &= hipMemcpyAsync(P.d_solid, P.solid.data(), sizeof(int32_t) * P.solid.size(), hipMemcpyHostToDevice, s) ==
+            hipSuccess;
+      ok &= hipMemcpyAsync(P.d_sbits, P.sbits.data(), sizeof(uint16_t) * P.sbits.size(), hipMemcpyHostToDevice, s) ==
+            hipSuccess;
+      ok &= hipMemcpyAsync(P.d_sq, P.sq.data(), sizeof(double) * P.sq.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+    }
     if (!ok) return cleanup_fail(fail(SBT_ERR_DEVICE, "list upload"));
     size_t n = (size_t)P.total() * kQ * kCells;
     if (sbt_launch_fill_nan(P.lat[0], n, X->storage, s) != hipSuccess ||
@@ -1420,7 +1536,7 @@ sbt_status sbt_convergence(sbt_ctx *ctx, int32_t c, void *snapshot, size_t bytes
     st = readout_level(X, c, l, X.stream);
     if (st) return st;
     const Pool &P = X.pools[(size_t)C.group * X.V + C.lr[l].v];
-    HIPCHK(sbt_launch_velocity_change(P.d_meta, P.d_codes, C.lr[l].own0, n, X.d_stage, snap, mode, X.d_partial,
+    HIPCHK(sbt_launch_velocity_change(P.d_meta, P.d_codes, P.d_sbits, C.lr[l].own0, n, X.d_stage, snap, mode, X.d_partial,
                                       X.stream));
     if (mode & SBT_SNAP_COMPARE)
       HIPCHK(sbt_launch_reduce(X.d_partial, n, 1.0 / (double)(1 << (2 * l)), acc, l > 0 ? 1 : 0, X.stream));

@@ -17,7 +17,12 @@ enum : int32_t {
   BF_CODES = 2,    // block has a per-cell code array (hidden / interface / hidden sources)
   BF_EDGE = 4,     // some source of this block lies outside a non-periodic domain edge
   BF_IBM = 8,      // finest-level block of a case with a body
+  BF_SOLID = 16,   // block with solid cells or links into them (interpolated bounce-back)
 };
+
+// Per-cell solid bits (blocks with BF_SOLID): bit i = the source x - c_i of
+// direction i is solid; SB_SOLID = the cell itself is solid.
+enum : uint16_t { SB_SOLID = 0x200 };
 
 // Per-cell code bits (blocks with BF_CODES).
 enum : uint16_t {
@@ -35,7 +40,9 @@ struct alignas(16) BlockMeta {
   int32_t level;       // true level of the case
   int32_t flags;
   int32_t code;        // index into the cell-code array, or -1
+  int32_t solid;       // index into the solid-record arrays, or -1
 };
+static_assert(sizeof(BlockMeta) == 80, "block table entries stay 80 bytes");
 
 // IBM window of one body for the current finest substep: a dense box of
 // finest cells covering every marker stencil.
@@ -95,6 +102,8 @@ struct LevelArgs {
   void *dst;                   // lattice written
   const BlockMeta *fmeta;      // pool v+1 (finer) or null
   const uint16_t *fcodes;
+  const uint16_t *sbits;       // solid records: [record][256] SB_* bits
+  const double *sq;            // [record][9][256] wall fraction of the link of each pulled direction
   const void *fprev;           // finer pool lattice read by its last substep
   void *fcur;                  // finer pool current lattice (explosion target)
   const CaseDev *cases;
@@ -167,7 +176,7 @@ hipError_t sbt_launch_reduce(const double *partial, int n_blocks, double vol, do
 // (sbt_stats.hip).
 hipError_t sbt_launch_force_stats(const double *hist, int64_t cap, int64_t first, int64_t n, double scale,
                                   double l_over_u, double *out, hipStream_t s);
-hipError_t sbt_launch_velocity_change(const sbt::BlockMeta *meta, const uint16_t *codes, int b0, int n,
+hipError_t sbt_launch_velocity_change(const sbt::BlockMeta *meta, const uint16_t *codes, const uint16_t *sbits, int b0, int n,
                                       const double *fields, double *snap, int mode, double *partial,
                                       hipStream_t s);
 hipError_t sbt_launch_fill_nan(void *p, size_t n_elems, int storage, hipStream_t s);

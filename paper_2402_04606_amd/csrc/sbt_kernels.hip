@@ -555,6 +555,32 @@ __device__ __forceinline__ typename Store<ST>::C coalesce(const LevelArgs &a, co
   return C(0.25) * sum;
 }
 
+// Interpolated bounce-back (linear Bouzidi form, resting wall) of pulled
+// direction i at cell (x, y) of block k, whose source x - c_i is solid: the
+// population o = opposite(i) that the cell sent toward the wall, at wall
+// fraction q of its link, comes back as
+//   q <  1/2:  2q f*_o(x) + (1 - 2q) f*_o(x + c_i)
+//   q >= 1/2:  f*_o(x) / (2q) + (2q - 1)/(2q) f*_i(x).
+// Both forms are affine with weights summing to 1 and w_o = w_i, so they
+// hold unchanged for the deviation storage forms.
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::C bouzidi(const LevelArgs &a, const Blk &k, int srec, int x, int y,
+                                                         int i) {
+#pragma clang fp contract(off)
+  using C = typename Store<ST>::C;
+  const int cell = y * 16 + x, o = OPP[i];
+  const double q = a.sq[((size_t)srec * kQ + i) * kCells + cell];
+  const C fo = ldv<ST>(a.src, k.self, o, cell);
+  if (q < 0.5) {
+    const int ux = x + CX[i], uy = y + CY[i];
+    const int nb = pick_nbr(k, ux, uy);
+    const C fu = ldv<ST>(a.src, nb, o, (uy & 15) * 16 + (ux & 15));
+    return C(2.0 * q) * fo + C(1.0 - 2.0 * q) * fu;
+  }
+  const C fi = ldv<ST>(a.src, k.self, i, cell);
+  return fo / C(2.0 * q) + C((2.0 * q - 1.0) / (2.0 * q)) * fi;
+}
+
 // ---- one cell of a level launch --------------------------------------------
 template <int ST>
 __device__ __forceinline__ void level_cell(const LevelArgs &a, const Blk &k, int cell, const CaseDev &cp,
@@ -567,6 +593,8 @@ __device__ __forceinline__ void level_cell(const LevelArgs &a, const Blk &k, int
   const int l = k.level;
   const int b = k.self;
   uint16_t code = (k.flags & BF_CODES) ? a.codes[(size_t)k.code * kCells + cell] : (uint16_t)0;
+  const int srec = (k.flags & BF_SOLID) ? a.meta[b].solid : -1;
+  const uint16_t sb = srec >= 0 ? a.sbits[(size_t)srec * kCells + cell] : (uint16_t)0;
 
   if (k.flags & BF_GHOST) {  // halo layers: streamed, never collided
     if (!(code & CC_BAND)) return;
@@ -584,7 +612,7 @@ __device__ __forceinline__ void level_cell(const LevelArgs &a, const Blk &k, int
   }
 
   const size_t ob = (size_t)(b - a.b0);
-  if (code & CC_HIDDEN) {
+  if ((code & CC_HIDDEN) || (sb & SB_SOLID)) {  // covered by the finer level, or solid
     if (a.mode & MODE_READOUT) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) a.out[(ob * 3 + q) * kCells + cell] = __builtin_nan("");
@@ -605,7 +633,9 @@ __device__ __forceinline__ void level_cell(const LevelArgs &a, const Blk &k, int
     for (int i = 0; i < 9; ++i) {
       int sx = x - CX[i], sy = y - CY[i];
       int nb = pick_nbr(k, sx, sy);
-      if (code & (1u << i)) {
+      if (sb & (1u << i)) {
+        f[i] = bouzidi<ST>(a, k, srec, x, y, i);
+      } else if (code & (1u << i)) {
         f[i] = coalesce<ST>(a, k, x, y, i);
       } else if (nb < 0) {
         f[i] = edge_value<ST>(cp, a.src, k, x, y, gx, gy, i);
@@ -769,7 +799,7 @@ __global__ __launch_bounds__(256 / CPT) void level_kernel(LevelArgs a) {
   const int bl = b - a.b0;
   const Blk k = load_blk(a.meta, b);
   const CaseDev &cp = a.cases[k.cid];
-  const bool slow = (k.flags & (BF_CODES | BF_EDGE)) != 0;
+  const bool slow = (k.flags & (BF_CODES | BF_EDGE | BF_SOLID)) != 0;
   double part[3] = {0.0, 0.0, 0.0};
   double acc[3] = {0.0, 0.0, 0.0};
 #pragma unroll

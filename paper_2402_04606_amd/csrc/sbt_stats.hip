@@ -96,17 +96,18 @@ __global__ __launch_bounds__(kStatThreads) void force_stats_kernel(const double 
 // One workgroup per owned block of a level, one thread per cell.  fields is
 // the level's readout [block][rho, ux, uy][256]; snap holds [block][ux, uy][256].
 // mode 2: per-block partial {sum |u - u_snap|, sum |u|, leaf cells} over the
-// block's leaf cells (cells not covered by the finer level); mode 1: the
+// block's leaf cells (cells neither covered by the finer level nor solid); mode 1: the
 // snapshot takes the current velocity; mode 3 does both (compare first).
-__global__ __launch_bounds__(256) void velocity_change_kernel(const BlockMeta *meta, const uint16_t *codes, int b0,
-                                                              const double *fields, double *snap, int mode,
-                                                              double *partial) {
+__global__ __launch_bounds__(256) void velocity_change_kernel(const BlockMeta *meta, const uint16_t *codes,
+                                                              const uint16_t *sbits, int b0, const double *fields,
+                                                              double *snap, int mode, double *partial) {
 #pragma clang fp contract(off)
   __shared__ double red[3][256];
   const int ob = blockIdx.x, cell = threadIdx.x;
   const BlockMeta m = meta[b0 + ob];
   const uint16_t code = (m.flags & BF_CODES) ? codes[(size_t)m.code * kCells + cell] : (uint16_t)0;
-  const bool leaf = !(code & CC_HIDDEN);
+  const uint16_t sb = (m.flags & BF_SOLID) ? sbits[(size_t)m.solid * kCells + cell] : (uint16_t)0;
+  const bool leaf = !(code & CC_HIDDEN) && !(sb & SB_SOLID);
   const double ux = fields[((size_t)ob * 3 + 1) * kCells + cell];
   const double uy = fields[((size_t)ob * 3 + 2) * kCells + cell];
   double *sp = snap + (size_t)ob * 2 * kCells;
@@ -145,10 +146,11 @@ extern "C" hipError_t sbt_launch_force_stats(const double *hist, int64_t cap, in
   return hipGetLastError();
 }
 
-extern "C" hipError_t sbt_launch_velocity_change(const BlockMeta *meta, const uint16_t *codes, int b0, int n,
-                                                 const double *fields, double *snap, int mode, double *partial,
-                                                 hipStream_t s) {
+extern "C" hipError_t sbt_launch_velocity_change(const BlockMeta *meta, const uint16_t *codes, const uint16_t *sbits,
+                                                 int b0, int n, const double *fields, double *snap, int mode,
+                                                 double *partial, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(velocity_change_kernel, dim3(n), dim3(256), 0, s, meta, codes, b0, fields, snap, mode, partial);
+  hipLaunchKernelGGL(velocity_change_kernel, dim3(n), dim3(256), 0, s, meta, codes, sbits, b0, fields, snap, mode,
+                     partial);
   return hipGetLastError();
 }

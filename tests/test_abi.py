@@ -81,6 +81,23 @@ def test_plan_rejects_mixed_collision_and_bad_mrt_rates(pkg):
             pkg.plan([W.tgv(32).replace(collision=W.COLL_MRT, mrt_rates=bad)])
 
 
+def test_plan_rejects_bad_solids(pkg):
+    import numpy as np
+    ok = W.ibb_cylinder()
+    assert pkg.plan([ok]) > 0
+    mask, q = W.solid_circle(128, 64, 2.0, 32.0, 5.0)          # touches the inflow edge
+    with pytest.raises(pkg.SbtError):
+        pkg.plan([ok.replace(solids=[(0, mask, q)])])
+    mask, q = W.solid_circle(128, 64, 40.0, 32.0, 6.0)
+    with pytest.raises(pkg.SbtError):
+        pkg.plan([ok.replace(solids=[(0, mask, np.zeros_like(q))])])   # q must lie in (0, 1]
+    cav = W.cavity_ibb()
+    lvl, mask, q = cav.solids[0]
+    with pytest.raises(pkg.SbtError):                          # level 1 is covered there
+        pkg.plan([cav.replace(solids=[(1, mask[::2, ::2][:512, :512], None)])])
+    assert pkg.plan([cav]) > 0
+
+
 def test_rescale_rejects_unit_tau(pkg):
     wl = W.tgv_patch(m=2, tau=1.0, cf_mode=W.CF_RESCALE)
     with pytest.raises(pkg.SbtError):
