@@ -35,6 +35,10 @@ def workload_list(name):
         return [W.cavity_ibb()], "cavity_256_3levels_D32_lid0.1_rescale_solid_cylinder_ibb"
     if name == "flap":
         return [W.flapping_ellipse()], "flapping_ellipse_512x256_4levels_200markers"
+    if name == "pitch_up":
+        return [W.pitch_up_plate()], "pitch_up_plate_1120x640_3levels_chord64_ramp"
+    if name == "pitching_airfoil":
+        return [W.pitching_airfoil()], "pitching_airfoil_1120x640_3levels_chord64_tri"
     if name == "tgv8192":
         return [W.tgv(8192, tau=0.8, u0=0.02)], "tgv_8192x8192_single_level"
     raise SystemExit(f"unknown workload {name}")
