@@ -85,6 +85,16 @@ def lib():
         _lib.orc_spread.argtypes = [C.c_int32, C.c_int32, C.c_int32, d, d, d, d, d, d, d]
         _lib.orc_force_stats.argtypes = [d, d, C.c_int32, C.c_double, C.c_double, d]
         _lib.orc_set_solid.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_uint8), d]
+        _lib.orc3_velocity_set.argtypes = [C.POINTER(C.c_int32)] * 3 + [d]
+        _lib.orc3_velocity_set.restype = None
+        _lib.orc3_feq.argtypes = [C.c_double] * 4 + [d]
+        _lib.orc3_feq.restype = None
+        _lib.orc3_create.argtypes = [C.c_int32] * 3 + [C.c_double, d, C.POINTER(C.c_void_p)]
+        _lib.orc3_destroy.argtypes = [C.c_void_p]
+        _lib.orc3_destroy.restype = None
+        _lib.orc3_init_fields.argtypes = [C.c_void_p, d, d, d, d]
+        _lib.orc3_step.argtypes = [C.c_void_p, C.c_int32]
+        _lib.orc3_read_fields.argtypes = [C.c_void_p, d, d, d, d]
         _lib.orc_num_threads.argtypes = []
     return _lib
 
@@ -361,3 +371,48 @@ def spread(shape, X, Y, Fjx, Fjy, ds):
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+# ---- three dimensions ----------------------------------------------------------
+
+def velocity_set3():
+    cx, cy, cz = (np.zeros(19, dtype=np.int32) for _ in range(3))
+    w = np.zeros(19)
+    p32 = C.POINTER(C.c_int32)
+    lib().orc3_velocity_set(cx.ctypes.data_as(p32), cy.ctypes.data_as(p32), cz.ctypes.data_as(p32), _dp(w))
+    return cx, cy, cz, w
+
+
+def feq3(rho, ux, uy, uz):
+    out = np.zeros(19)
+    lib().orc3_feq(float(rho), float(ux), float(uy), float(uz), _dp(out))
+    return out
+
+
+class Oracle3Sim:
+    """D3Q19 BGK + Guo forcing on one periodic level (a ``workloads.Workload3``)."""
+
+    def __init__(self, wl):
+        self.wl = wl
+        F = _f64(np.asarray(wl.fext, dtype=np.float64))
+        h = C.c_void_p()
+        rc = lib().orc3_create(wl.nx, wl.ny, wl.nz, wl.tau, _dp(F), C.byref(h))
+        if rc:
+            raise RuntimeError(f"orc3_create failed: {rc}")
+        self._h = h
+        r, u, v, w = (_f64(a) for a in wl.init(wl.nx, wl.ny, wl.nz))
+        lib().orc3_init_fields(h, _dp(r), _dp(u), _dp(v), _dp(w))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.orc3_destroy(h)
+
+    def step(self, n=1):
+        lib().orc3_step(self._h, int(n))
+
+    def fields(self):
+        shape = (self.wl.nz, self.wl.ny, self.wl.nx)
+        out = [np.empty(shape) for _ in range(4)]
+        lib().orc3_read_fields(self._h, *[_dp(a) for a in out])
+        return out

@@ -761,3 +761,76 @@ def test_host_markers_reproduce_prescribed_motion(orc):
         for a, c in zip(ref.fields(l), h.fields(l)):
             assert np.array_equal(a, c, equal_nan=True)
     assert np.array_equal(ref.force_history()[0], h.force_history()[0])
+
+
+# ---- three dimensions: D3Q19 ---------------------------------------------------
+
+def test_d3q19_isotropy_and_equilibrium_moments(orc):
+    """Weights sum to 1; odd moments vanish; sum w c_a c_b = delta_ab / 3 and
+    sum w c_a c_b c_c c_d = (d_ab d_cd + d_ac d_bd + d_ad d_bc) / 9; the
+    equilibrium carries rho, rho u and rho (u u + I/3)."""
+    cx, cy, cz, w = orc.velocity_set3()
+    c = np.stack([cx, cy, cz]).astype(float)
+    assert abs(w.sum() - 1) < 1e-15
+    assert np.abs(c @ w).max() < 1e-15
+    d = np.eye(3)
+    assert np.abs(np.einsum("i,ai,bi->ab", w, c, c) - d / 3).max() < 1e-15
+    m4 = np.einsum("i,ai,bi,ci,di->abcd", w, c, c, c, c)
+    want = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d) + np.einsum("ad,bc->abcd", d, d)) / 9
+    assert np.abs(m4 - want).max() < 1e-15
+    assert np.abs(np.einsum("i,ai,bi,ci->abc", w, c, c, c)).max() < 1e-15
+    rho, u = 1.04, np.array([0.03, -0.02, 0.05])
+    f = orc.feq3(rho, *u)
+    assert abs(f.sum() - rho) < 1e-15 and np.abs(c @ f - rho * u).max() < 1e-15
+    assert np.abs(np.einsum("i,ai,bi->ab", f, c, c) - rho * (np.outer(u, u) + d / 3)).max() < 1e-15
+
+
+@pytest.mark.parametrize("axis", ["shear", "tgv"])
+def test_d3q19_decay_converges_to_closed_form(orc, axis):
+    """A shear wave u_x(z) and the Sec. 3.1 vortex extended along z are exact
+    solutions decaying as exp(-nu k^2 t) and exp(-2 nu k^2 t); at fixed
+    diffusive time the error falls about fourfold per doubling of n."""
+    errs = []
+    for n in (16, 32, 64):
+        t = int(round(0.5 * (n / 16) ** 2 * 100))
+        if axis == "shear":
+            wl = W.shear_wave3(4, nz=n, tau=0.8)
+            fac = math.exp(-wl.meta["nu"] * wl.meta["k"] ** 2 * t)
+        else:
+            wl = W.tgv3(n, nz=2, tau=0.8)
+            fac = math.exp(-2 * wl.meta["nu"] * wl.meta["k"] ** 2 * t)
+        s = orc.Oracle3Sim(wl)
+        s.step(t)
+        _, u, v, w = s.fields()
+        _, ua, va, _ = wl.init(wl.nx, wl.ny, wl.nz)
+        num = np.sqrt(((u - fac * ua) ** 2 + (v - fac * va) ** 2 + w ** 2).sum())
+        errs.append(num / np.sqrt(((fac * ua) ** 2 + (fac * va) ** 2).sum()))
+    assert errs[2] < 2e-3 and errs[0] / errs[1] > 3.3 and errs[1] / errs[2] > 3.3, errs
+
+
+def test_d3q19_conservation_and_translation(orc):
+    """Mass is constant and momentum grows by N F per step under a uniform
+    force; an initial state shifted by one cell along each axis gives the
+    shifted result (periodic streaming indexes)."""
+    F = (2e-6, -1e-6, 3e-6)
+    wl = W.tgv3(16, nz=8, tau=0.7).replace(fext=F)
+    s = orc.Oracle3Sim(wl)
+    r0 = s.fields()[0].sum()
+    s.step(20)
+    r, u, v, w = s.fields()
+    n = 16 * 16 * 8
+    assert abs(r.sum() - r0) < 1e-11 * n
+    for comp, Fk in zip((u, v, w), F):
+        # momentum = sum(rho u) - N F / 2 (half-force velocity); initial momentum 0 in every direction
+        assert abs((r * comp).sum() - n * Fk / 2 - 20 * n * Fk) < 1e-13 * n
+    base = W.tgv3(16, nz=8, tau=0.7)
+    init0 = base.init
+
+    def shifted(nx, ny, nz):
+        return tuple(np.roll(a, (1, 1, 1), axis=(0, 1, 2)) for a in init0(nx, ny, nz))
+
+    a, b = orc.Oracle3Sim(base), orc.Oracle3Sim(base.replace(init=shifted))
+    a.step(7)
+    b.step(7)
+    for fa, fb in zip(a.fields(), b.fields()):
+        assert np.array_equal(np.roll(fa, (1, 1, 1), axis=(0, 1, 2)), fb)

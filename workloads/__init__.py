@@ -486,3 +486,60 @@ def cavity_ibb(cf_mode=CF_RESCALE, U=0.1, Re=1000.0):
     n2 = wl.nx0 * 4
     mask, q = solid_circle(n2, n2, 512.0, 512.0, 64.0)
     return wl.replace(name="cavity256_3lvl_ibb", body=None, solids=[(2, mask, q)])
+
+
+# ---- three dimensions: D3Q19 on one periodic level ----------------------------
+
+@dataclasses.dataclass
+class Workload3:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    tau: float = 0.8
+    rho0: float = 1.0
+    fext: tuple = (0.0, 0.0, 0.0)
+    init: Optional[Callable] = None   # init(nx, ny, nz) -> (rho, ux, uy, uz) dense [nz, ny, nx]
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    def replace(self, **kw):
+        return dataclasses.replace(self, **kw)
+
+
+def shear_wave3(n=32, nz=None, tau=0.8, u0=0.01, period=None):
+    """u_x = u0 sin(2 pi (z + 1/2) / period), a pure shear wave: an exact
+    Navier-Stokes solution decaying as exp(-nu k^2 t)."""
+    nz = nz or n
+    period = period or nz
+    k = 2 * math.pi / period
+
+    def init(nx, ny, nz_):
+        z = np.arange(nz_) + 0.5
+        ux = np.broadcast_to((u0 * np.sin(k * z))[:, None, None], (nz_, ny, nx)).copy()
+        zero = np.zeros((nz_, ny, nx))
+        return np.ones((nz_, ny, nx)), ux, zero, zero.copy()
+
+    return Workload3(name=f"shear_wave3_{n}x{n}x{nz}", nx=n, ny=n, nz=nz, tau=tau, init=init,
+                     meta=dict(u0=u0, k=k, nu=(tau - 0.5) / 3.0))
+
+
+def tgv3(n=32, nz=8, tau=0.8, u0=0.02, period=None):
+    """The Sec. 3.1 Taylor-Green vortex in the x-y plane, uniform along z
+    (an exact 3D solution with the 2D decay exp(-2 nu k^2 t)); the pressure
+    term of Sec. 3.1 sets rho."""
+    period = period or n
+    k = 2 * math.pi / period
+
+    def init(nx, ny, nz_):
+        x = np.arange(nx) + 0.5
+        y = np.arange(ny) + 0.5
+        X, Y = np.meshgrid(x, y)
+        u = -u0 * np.cos(k * X) * np.sin(k * Y)
+        v = u0 * np.sin(k * X) * np.cos(k * Y)
+        p = -(u0 * u0 / 4) * (np.cos(2 * k * X) + np.cos(2 * k * Y))
+        r = 1.0 + 3.0 * p
+        rep = lambda a: np.broadcast_to(a[None], (nz_, ny, nx)).copy()
+        return rep(r), rep(u), rep(v), np.zeros((nz_, ny, nx))
+
+    return Workload3(name=f"tgv3_{n}x{n}x{nz}", nx=n, ny=n, nz=nz, tau=tau, init=init,
+                     meta=dict(u0=u0, k=k, nu=(tau - 0.5) / 3.0))
