@@ -1,0 +1,65 @@
+/*
+ * sbt3d.h -- the three-dimensional (D3Q19) form of the lattice-Boltzmann
+ * collide+stream of SBoTFlow (arXiv 2402.04606, Sec. 2.1 written for the
+ * 19-velocity 3D lattice the method extends to), on one periodic level.
+ *
+ * One step is Eqs. (2)-(3), (6)-(8) in 3D: BGK collision with Guo's forcing
+ * term and the half-force velocity, then streaming f(x + c_i, i) = f*(x, i)
+ * across periodic faces.  D3Q19: rest (w = 1/3), 6 axis (1/18) and 12 edge
+ * (1/36) velocities, c_s^2 = 1/3.
+ *
+ * Storage forms as for the 2D library (sbt.h): SBT_F64 (f itself, FP64
+ * arithmetic) and SBT_F32 / SBT_F16S / SBT_BF16S (the deviation
+ * f - w rho0, FP32 arithmetic).  Layout in the caller's device buffer:
+ * two lattices [19][nz][ny][nx] (x fastest) and a staging area for the
+ * field transfers.  All functions return sbt_status; sbt_last_error()
+ * describes the last failure.  A context must not be used from two threads
+ * at once.
+ */
+#ifndef SBT3D_H
+#define SBT3D_H
+#include <stddef.h>
+#include <stdint.h>
+
+#include "sbt.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbt3_ctx sbt3_ctx;
+
+typedef struct {
+    int32_t nx, ny, nz;            /* cells per axis, each >= 1 (periodic)          */
+    double tau, rho0;              /* relaxation time (> 1/2), reference density     */
+    double fext[3];                /* uniform body-force density                     */
+    int32_t storage;               /* SBT_F64 ... SBT_BF16S                          */
+} sbt3_desc;
+
+/* Device bytes sbt3_create needs.  Host only.  Errors: SBT_ERR_ARG. */
+sbt_status sbt3_plan(const sbt3_desc *desc, size_t *device_bytes);
+/* Lay the lattices out in device_buf (caller-owned, >= planned bytes,
+ * 256-byte aligned) and bind hip_stream (a hipStream_t; NULL = legacy
+ * default stream).  The state is undefined until sbt3_init_slab has covered
+ * every plane. */
+sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, void *hip_stream,
+                       sbt3_ctx **out);
+sbt_status sbt3_destroy(sbt3_ctx *ctx);
+/* f = f^eq(rho, u) (Eq. (7) in 3D) on planes z0 .. z0 + nz - 1, from host
+ * FP64 arrays [nz][ny][nx].  Synchronises.  Errors: SBT_ERR_ARG (planes out
+ * of range, null arrays). */
+sbt_status sbt3_init_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, const double *rho, const double *ux,
+                          const double *uy, const double *uz);
+/* Advance n steps.  Asynchronous, stream-ordered. */
+sbt_status sbt3_step(sbt3_ctx *ctx, int32_t n);
+/* Wait for the stream; SBT_ERR_NONFINITE if a density became NaN or Inf. */
+sbt_status sbt3_synchronize(sbt3_ctx *ctx);
+/* rho and u = (sum_i c_i f_i + F/2) / rho on planes z0 .. z0 + nz - 1 into
+ * host FP64 arrays [nz][ny][nx].  Synchronises. */
+sbt_status sbt3_read_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, double *rho, double *ux, double *uy,
+                          double *uz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -32,6 +32,8 @@ ABI_SYMBOLS = [
     "sbt_convergence", "sbt_state_bytes", "sbt_read_state",
     "sbt_write_state", "sbt_set_option", "sbt_autotune", "sbt_profile", "sbt_updates_per_step",
     "sbt_last_error",
+    "sbt3_plan", "sbt3_create", "sbt3_destroy", "sbt3_init_slab", "sbt3_step", "sbt3_synchronize",
+    "sbt3_read_slab",
 ]
 
 
@@ -48,6 +50,11 @@ class Box(C.Structure):
 
 class Solid(C.Structure):
     _fields_ = [("level", C.c_int32), ("mask", C.POINTER(C.c_uint8)), ("q", C.POINTER(C.c_double))]
+
+
+class Desc3(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
+                ("rho0", C.c_double), ("fext", C.c_double * 3), ("storage", C.c_int32)]
 
 
 class CaseDesc(C.Structure):
@@ -107,6 +114,13 @@ def lib():
             "sbt_autotune": [vp, i32, C.c_char_p],
             "sbt_profile": [vp, i32, d],
             "sbt_updates_per_step": [vp, C.POINTER(i64)],
+            "sbt3_plan": [C.POINTER(Desc3), C.POINTER(C.c_size_t)],
+            "sbt3_create": [C.POINTER(Desc3), vp, C.c_size_t, vp, C.POINTER(vp)],
+            "sbt3_destroy": [vp],
+            "sbt3_init_slab": [vp, i32, i32, d, d, d, d],
+            "sbt3_step": [vp, i32],
+            "sbt3_synchronize": [vp],
+            "sbt3_read_slab": [vp, i32, i32, d, d, d, d],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -380,3 +394,63 @@ class Sim:
         return dict(level_ms=out[0], level_launches=int(out[1]), mdf_ms=out[2],
                     mdf_launches=int(out[3]), level_bytes=out[4], updates=out[5],
                     fast_ms=out[6], fast_launches=int(out[7]), fast_bytes=out[8])
+
+
+class Sim3:
+    """A D3Q19 periodic box (``workloads.Workload3``) on cuda:0: torch device
+    buffer, torch's current stream."""
+
+    def __init__(self, wl, storage="f64", stream=None, slab=None):
+        import torch
+        self.wl = wl
+        self.storage = STORAGE[storage] if isinstance(storage, str) else storage
+        d = Desc3()
+        d.nx, d.ny, d.nz, d.tau, d.rho0 = wl.nx, wl.ny, wl.nz, wl.tau, wl.rho0
+        for k in range(3):
+            d.fext[k] = wl.fext[k]
+        d.storage = self.storage
+        self._desc = d
+        n = C.c_size_t()
+        _check(lib().sbt3_plan(C.byref(d), C.byref(n)))
+        self.device_bytes = n.value
+        self._buf = torch.empty(n.value + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self._buf.data_ptr() + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().sbt3_create(C.byref(d), C.c_void_p(ptr), n.value, C.c_void_p(self._stream.cuda_stream),
+                                 C.byref(h)))
+        self._h = h
+        # initial state, a few planes at a time
+        self.slab = slab or max(1, min(wl.nz, (1 << 24) // (wl.nx * wl.ny)))
+        for z0 in range(0, wl.nz, self.slab):
+            z1 = min(wl.nz, z0 + self.slab)
+            r, u, v, w = (np.ascontiguousarray(a, dtype=np.float64) for a in wl.init(wl.nx, wl.ny, wl.nz, z0, z1))
+            _check(lib().sbt3_init_slab(h, z0, z1 - z0, _dp(r), _dp(u), _dp(v), _dp(w)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().sbt3_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        _check(lib().sbt3_step(self._h, int(n)))
+
+    def synchronize(self):
+        _check(lib().sbt3_synchronize(self._h))
+
+    def fields(self, z0=0, z1=None):
+        """(rho, ux, uy, uz), each [z1 - z0, ny, nx] FP64."""
+        z1 = self.wl.nz if z1 is None else z1
+        shape = (z1 - z0, self.wl.ny, self.wl.nx)
+        out = [np.empty(shape) for _ in range(4)]
+        _check(lib().sbt3_read_slab(self._h, z0, z1 - z0, *[_dp(a) for a in out]))
+        return out
+
+    def updates_per_step(self):
+        return self.wl.nx * self.wl.ny * self.wl.nz

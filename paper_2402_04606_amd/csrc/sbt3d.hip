@@ -1,0 +1,384 @@
+// D3Q19 collide + stream on one periodic level (the 3D form of Sec. 2.1),
+// fused into one launch per step: each thread loads its cell's 19
+// pre-collision populations (coalesced along x), collides them (BGK + Guo,
+// Eqs. (2)-(3), (6)-(8)) and pushes f*(x, i) to x + c_i in the other
+// lattice.  HBM-bound: 2 * 19 * s bytes per cell update.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "sbt3d.h"
+#include "sbt_internal.h"
+
+namespace {
+
+constexpr int kQ3 = 19;
+constexpr int kThreads = 256;
+constexpr int kXcds = 8;
+
+// Rest, +x -x +y -y +z -z, then the 12 edges (+-1, +-1, 0), (+-1, 0, +-1), (0, +-1, +-1).
+__device__ constexpr int E3X[kQ3] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+__device__ constexpr int E3Y[kQ3] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+__device__ constexpr int E3Z[kQ3] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+
+template <typename C>
+__device__ __forceinline__ C w3(int i) {
+  return i == 0 ? C(1.0 / 3.0) : (i < 7 ? C(1.0 / 18.0) : C(1.0 / 36.0));
+}
+
+template <int ST> struct Store3;
+template <> struct Store3<0> {
+  using T = double;
+  __device__ static double ld(T v) { return v; }
+  __device__ static T st(double v) { return v; }
+};
+template <> struct Store3<1> {
+  using T = float;
+  __device__ static float ld(T v) { return v; }
+  __device__ static T st(float v) { return v; }
+};
+template <> struct Store3<2> {
+  using T = _Float16;
+  __device__ static float ld(T v) { return (float)v; }
+  __device__ static T st(float v) { return (_Float16)v; }
+};
+template <> struct Store3<3> {  // bf16, round to nearest even
+  using T = uint16_t;
+  __device__ static float ld(T v) { return __uint_as_float(((uint32_t)v) << 16); }
+  __device__ static T st(float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (T)(u >> 16);
+  }
+};
+
+struct Params {
+  int nx, ny, nz;
+  long long n;
+  double tau, pre, rho0, F[3];
+  float om_f, pre_f, rho0_f, F_f[3];
+};
+
+// Workgroup w of the launch -> logical block: each XCD (w mod 8) takes one
+// contiguous eighth of the grid, so the neighbouring rows a block streams
+// into were most likely touched by the same L2.
+__device__ __forceinline__ long long logical_block(int w, int per) { return (long long)(w % kXcds) * per + w / kXcds; }
+
+template <int ST>
+__global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *src_, void *dst_, int per,
+                                                         int *err) {
+#pragma clang fp contract(off)
+  using S = Store3<ST>;
+  using T = typename S::T;
+  const long long c = logical_block(blockIdx.x, per) * kThreads + threadIdx.x;
+  if (c >= p.n) return;
+  const T *src = static_cast<const T *>(src_);
+  T *dst = static_cast<T *>(dst_);
+  const int x = (int)(c % p.nx);
+  const int y = (int)((c / p.nx) % p.ny);
+  const int z = (int)(c / ((long long)p.nx * p.ny));
+  const long long plane = (long long)p.nx * p.ny;
+  // neighbour offsets along each axis (periodic)
+  const long long ox[3] = {x == 0 ? (long long)(p.nx - 1) : -1, 0, x == p.nx - 1 ? -(long long)(p.nx - 1) : 1};
+  const long long oy[3] = {y == 0 ? (long long)(p.ny - 1) * p.nx : -(long long)p.nx, 0,
+                           y == p.ny - 1 ? -(long long)(p.ny - 1) * p.nx : (long long)p.nx};
+  const long long oz[3] = {z == 0 ? (long long)(p.nz - 1) * plane : -plane, 0,
+                           z == p.nz - 1 ? -(long long)(p.nz - 1) * plane : plane};
+  if constexpr (ST == 0) {
+    double f[kQ3];
+#pragma unroll
+    for (int i = 0; i < kQ3; ++i) f[i] = S::ld(src[(long long)i * p.n + c]);
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < kQ3; ++i) {
+      rho += f[i];
+      jx += E3X[i] * f[i];
+      jy += E3Y[i] * f[i];
+      jz += E3Z[i] * f[i];
+    }
+    const double Fx = p.F[0], Fy = p.F[1], Fz = p.F[2];
+    const double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho, uz = (jz + 0.5 * Fz) / rho;
+    const double usq = ux * ux + uy * uy + uz * uz;
+    const double uF = ux * Fx + uy * Fy + uz * Fz;
+    if (!(rho == rho) || rho > 1e30 || rho < -1e30) atomicOr(err, 1);
+#pragma unroll
+    for (int i = 0; i < kQ3; ++i) {
+      const double cu = E3X[i] * ux + E3Y[i] * uy + E3Z[i] * uz;
+      const double cF = E3X[i] * Fx + E3Y[i] * Fy + E3Z[i] * Fz;
+      const double fe = w3<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+      const double fi = w3<double>(i) * p.pre * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
+      const double v = f[i] - (f[i] - fe) / p.tau + fi;
+      dst[(long long)i * p.n + c + ox[E3X[i] + 1] + oy[E3Y[i] + 1] + oz[E3Z[i] + 1]] = S::st(v);
+    }
+  } else {
+    // deviation form d = f - w rho0 (FP32 arithmetic)
+    float d[kQ3];
+#pragma unroll
+    for (int i = 0; i < kQ3; ++i) d[i] = S::ld(src[(long long)i * p.n + c]);
+    float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < kQ3; ++i) {
+      dr += d[i];
+      jx += E3X[i] * d[i];
+      jy += E3Y[i] * d[i];
+      jz += E3Z[i] * d[i];
+    }
+    const float rho = p.rho0_f + dr;
+    const float ir = __builtin_amdgcn_rcpf(rho);
+    const float Fx = p.F_f[0], Fy = p.F_f[1], Fz = p.F_f[2];
+    const float ux = (jx + 0.5f * Fx) * ir, uy = (jy + 0.5f * Fy) * ir, uz = (jz + 0.5f * Fz) * ir;
+    const float A = dr - rho * (1.5f * (ux * ux + uy * uy + uz * uz));
+    const bool forced = Fx != 0.f || Fy != 0.f || Fz != 0.f;
+    const float uF = ux * Fx + uy * Fy + uz * Fz;
+    if (!(rho == rho) || rho > 1e30f || rho < -1e30f) atomicOr(err, 1);
+#pragma unroll
+    for (int i = 0; i < kQ3; ++i) {
+      const float cu = E3X[i] * ux + E3Y[i] * uy + E3Z[i] * uz;
+      const float de = w3<float>(i) * fmaf(rho * cu, fmaf(4.5f, cu, 3.0f), A);
+      float v = fmaf(p.om_f, de - d[i], d[i]);
+      if (forced) {
+        const float cF = E3X[i] * Fx + E3Y[i] * Fy + E3Z[i] * Fz;
+        v += w3<float>(i) * p.pre_f * (3.f * cF + 9.f * cu * cF - 3.f * uF);
+      }
+      dst[(long long)i * p.n + c + ox[E3X[i] + 1] + oy[E3Y[i] + 1] + oz[E3Z[i] + 1]] = S::st(v);
+    }
+  }
+}
+
+// f = f^eq(rho, u) of cells [c0, c0 + m) from staged FP64 fields [4][m].
+template <int ST>
+__global__ __launch_bounds__(kThreads) void init3_kernel(Params p, void *lat_, const double *fld, long long c0,
+                                                         long long m) {
+#pragma clang fp contract(off)
+  using S = Store3<ST>;
+  using T = typename S::T;
+  const long long k = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= m) return;
+  T *lat = static_cast<T *>(lat_);
+  const double rho = fld[k], ux = fld[m + k], uy = fld[2 * m + k], uz = fld[3 * m + k];
+  const double usq = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+  for (int i = 0; i < kQ3; ++i) {
+    const double cu = E3X[i] * ux + E3Y[i] * uy + E3Z[i] * uz;
+    const double fe = w3<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+    if constexpr (ST == 0) lat[(long long)i * p.n + c0 + k] = S::st(fe);
+    else lat[(long long)i * p.n + c0 + k] = S::st((float)(fe - w3<double>(i) * p.rho0));
+  }
+}
+
+// rho, u of cells [c0, c0 + m) into [4][m] (FP64).
+template <int ST>
+__global__ __launch_bounds__(kThreads) void read3_kernel(Params p, const void *lat_, double *fld, long long c0,
+                                                         long long m) {
+#pragma clang fp contract(off)
+  using S = Store3<ST>;
+  using T = typename S::T;
+  const long long k = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= m) return;
+  const T *lat = static_cast<const T *>(lat_);
+  double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+  for (int i = 0; i < kQ3; ++i) {
+    const double f = (double)S::ld(lat[(long long)i * p.n + c0 + k]);
+    r += f;
+    jx += E3X[i] * f;
+    jy += E3Y[i] * f;
+    jz += E3Z[i] * f;
+  }
+  if constexpr (ST != 0) r = p.rho0 + r;
+  fld[k] = r;
+  fld[m + k] = (jx + 0.5 * p.F[0]) / r;
+  fld[2 * m + k] = (jy + 0.5 * p.F[1]) / r;
+  fld[3 * m + k] = (jz + 0.5 * p.F[2]) / r;
+}
+
+size_t storage_bytes3(int st) { return st == 0 ? 8 : (st == 1 ? 4 : 2); }
+
+constexpr long long kStageCells = 1ll << 22;
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+}  // namespace
+
+struct sbt3_ctx {
+  sbt3_desc d;
+  Params p;
+  void *lat[2];
+  double *stage;
+  int *err;
+  long long stage_cells;
+  int cur = 0;
+  hipStream_t stream;
+};
+
+namespace {
+
+sbt_status check_desc(const sbt3_desc *d) {
+  if (!d) return sbt_set_error(SBT_ERR_ARG, "null descriptor");
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return sbt_set_error(SBT_ERR_ARG, "nx, ny, nz must be >= 1");
+  if ((long long)d->nx * d->ny * d->nz * kQ3 >= (1ll << 40)) return sbt_set_error(SBT_ERR_ARG, "grid too large");
+  if (!(d->tau > 0.5)) return sbt_set_error(SBT_ERR_ARG, "tau must exceed 1/2");
+  if (!(d->rho0 > 0.0)) return sbt_set_error(SBT_ERR_ARG, "rho0 must be positive");
+  if (d->storage < SBT_F64 || d->storage > SBT_BF16S) return sbt_set_error(SBT_ERR_ARG, "bad storage");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(d->fext[k])) return sbt_set_error(SBT_ERR_ARG, "body force must be finite");
+  return SBT_OK;
+}
+
+size_t plan_bytes(const sbt3_desc *d, long long *stage) {
+  const long long n = (long long)d->nx * d->ny * d->nz;
+  *stage = std::min<long long>(n, std::max<long long>(kStageCells, (long long)d->nx * d->ny));
+  return 2 * align256((size_t)n * kQ3 * storage_bytes3(d->storage)) + align256((size_t)*stage * 4 * sizeof(double)) +
+         256;
+}
+
+#define HIP3(x)                                                                   \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess) return sbt_set_error(SBT_ERR_DEVICE, hipGetErrorString(e_)); \
+  } while (0)
+
+#define SBT3_LAUNCH(K, st, g, s, ...)                                                   \
+  [&]() -> hipError_t {                                                                  \
+    switch (st) {                                                                        \
+      case 0: hipLaunchKernelGGL(K<0>, g, dim3(kThreads), 0, s, __VA_ARGS__); break;      \
+      case 1: hipLaunchKernelGGL(K<1>, g, dim3(kThreads), 0, s, __VA_ARGS__); break;      \
+      case 2: hipLaunchKernelGGL(K<2>, g, dim3(kThreads), 0, s, __VA_ARGS__); break;      \
+      case 3: hipLaunchKernelGGL(K<3>, g, dim3(kThreads), 0, s, __VA_ARGS__); break;      \
+      default: return hipErrorInvalidValue;                                              \
+    }                                                                                    \
+    return hipGetLastError();                                                            \
+  }()
+
+sbt_status check_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, const void *a, const void *b, const void *c,
+                      const void *e) {
+  if (!ctx) return sbt_set_error(SBT_ERR_ARG, "null context");
+  if (z0 < 0 || nz < 1 || z0 + nz > ctx->d.nz) return sbt_set_error(SBT_ERR_ARG, "planes out of range");
+  if (!a || !b || !c || !e) return sbt_set_error(SBT_ERR_ARG, "null field");
+  return SBT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sbt_status sbt3_plan(const sbt3_desc *desc, size_t *device_bytes) {
+  sbt_status st = check_desc(desc);
+  if (st) return st;
+  if (!device_bytes) return sbt_set_error(SBT_ERR_ARG, "null output");
+  long long stage;
+  *device_bytes = plan_bytes(desc, &stage);
+  return SBT_OK;
+}
+
+sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, void *hip_stream, sbt3_ctx **out) {
+  sbt_status st = check_desc(desc);
+  if (st) return st;
+  if (!out) return sbt_set_error(SBT_ERR_ARG, "null output");
+  *out = nullptr;
+  long long stage;
+  const size_t need = plan_bytes(desc, &stage);
+  if (!device_buf || bytes < need) return sbt_set_error(SBT_ERR_BUFSIZE, "device buffer smaller than planned");
+  if ((uintptr_t)device_buf & 255) return sbt_set_error(SBT_ERR_ARG, "device buffer must be 256-byte aligned");
+  sbt3_ctx *X = new sbt3_ctx();
+  X->d = *desc;
+  Params &p = X->p;
+  p.nx = desc->nx;
+  p.ny = desc->ny;
+  p.nz = desc->nz;
+  p.n = (long long)desc->nx * desc->ny * desc->nz;
+  p.tau = desc->tau;
+  p.pre = 1.0 - 0.5 / desc->tau;
+  p.rho0 = desc->rho0;
+  p.om_f = (float)(1.0 / desc->tau);
+  p.pre_f = (float)p.pre;
+  p.rho0_f = (float)desc->rho0;
+  for (int k = 0; k < 3; ++k) {
+    p.F[k] = desc->fext[k];
+    p.F_f[k] = (float)desc->fext[k];
+  }
+  char *b = static_cast<char *>(device_buf);
+  const size_t lat = align256((size_t)p.n * kQ3 * storage_bytes3(desc->storage));
+  X->lat[0] = b;
+  X->lat[1] = b + lat;
+  X->stage = reinterpret_cast<double *>(b + 2 * lat);
+  X->err = reinterpret_cast<int *>(b + 2 * lat + align256((size_t)stage * 4 * sizeof(double)));
+  X->stage_cells = stage;
+  X->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipMemsetAsync(X->err, 0, sizeof(int), X->stream) != hipSuccess) {
+    delete X;
+    return sbt_set_error(SBT_ERR_DEVICE, "error flag clear");
+  }
+  *out = X;
+  return SBT_OK;
+}
+
+sbt_status sbt3_destroy(sbt3_ctx *ctx) {
+  delete ctx;
+  return SBT_OK;
+}
+
+sbt_status sbt3_init_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, const double *rho, const double *ux,
+                          const double *uy, const double *uz) {
+  sbt_status st = check_slab(ctx, z0, nz, rho, ux, uy, uz);
+  if (st) return st;
+  sbt3_ctx &X = *ctx;
+  const long long plane = (long long)X.p.nx * X.p.ny, total = plane * nz;
+  for (long long k0 = 0; k0 < total; k0 += X.stage_cells) {
+    const long long m = std::min(X.stage_cells, total - k0);
+    const double *src[4] = {rho, ux, uy, uz};
+    for (int q = 0; q < 4; ++q)
+      HIP3(hipMemcpyAsync(X.stage + q * m, src[q] + k0, sizeof(double) * m, hipMemcpyHostToDevice, X.stream));
+    HIP3(SBT3_LAUNCH(init3_kernel, X.d.storage, dim3((unsigned)((m + kThreads - 1) / kThreads)), X.stream, X.p,
+                     X.lat[X.cur], (const double *)X.stage, (long long)z0 * plane + k0, m));
+    HIP3(hipStreamSynchronize(X.stream));
+  }
+  return SBT_OK;
+}
+
+sbt_status sbt3_step(sbt3_ctx *ctx, int32_t n) {
+  if (!ctx || n < 0) return sbt_set_error(SBT_ERR_ARG, "bad argument");
+  sbt3_ctx &X = *ctx;
+  const long long blocks = (X.p.n + kThreads - 1) / kThreads;
+  const int per = (int)((blocks + kXcds - 1) / kXcds);
+  for (int t = 0; t < n; ++t) {
+    HIP3(SBT3_LAUNCH(step3_kernel, X.d.storage, dim3((unsigned)(per * kXcds)), X.stream, X.p,
+                     (const void *)X.lat[X.cur], X.lat[1 - X.cur], per, X.err));
+    X.cur = 1 - X.cur;
+  }
+  return SBT_OK;
+}
+
+sbt_status sbt3_synchronize(sbt3_ctx *ctx) {
+  if (!ctx) return sbt_set_error(SBT_ERR_ARG, "null context");
+  HIP3(hipStreamSynchronize(ctx->stream));
+  int e = 0;
+  HIP3(hipMemcpy(&e, ctx->err, sizeof(int), hipMemcpyDeviceToHost));
+  if (e) {
+    HIP3(hipMemset(ctx->err, 0, sizeof(int)));
+    return sbt_set_error(SBT_ERR_NONFINITE, "a density became NaN or Inf");
+  }
+  return SBT_OK;
+}
+
+sbt_status sbt3_read_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, double *rho, double *ux, double *uy, double *uz) {
+  sbt_status st = check_slab(ctx, z0, nz, rho, ux, uy, uz);
+  if (st) return st;
+  sbt3_ctx &X = *ctx;
+  const long long plane = (long long)X.p.nx * X.p.ny, total = plane * nz;
+  for (long long k0 = 0; k0 < total; k0 += X.stage_cells) {
+    const long long m = std::min(X.stage_cells, total - k0);
+    HIP3(SBT3_LAUNCH(read3_kernel, X.d.storage, dim3((unsigned)((m + kThreads - 1) / kThreads)), X.stream, X.p,
+                     (const void *)X.lat[X.cur], X.stage, (long long)z0 * plane + k0, m));
+    double *dst[4] = {rho, ux, uy, uz};
+    for (int q = 0; q < 4; ++q)
+      HIP3(hipMemcpyAsync(dst[q] + k0, X.stage + q * m, sizeof(double) * m, hipMemcpyDeviceToHost, X.stream));
+    HIP3(hipStreamSynchronize(X.stream));
+  }
+  return SBT_OK;
+}
+
+}  // extern "C"

@@ -1105,6 +1105,8 @@ extern "C" {
 
 const char *sbt_last_error(void) { return g_err.c_str(); }
 
+sbt_status sbt_set_error(sbt_status code, const char *msg) { return fail(code, msg); }
+
 sbt_status sbt_plan(const sbt_case_desc *cases, int32_t n_cases, size_t *device_bytes) {
   if (!device_bytes) return fail(SBT_ERR_ARG, "null output");
   sbt_ctx X;

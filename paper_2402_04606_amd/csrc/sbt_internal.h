@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sbt.h"
+
 namespace sbt {
 
 constexpr int kQ = 9;
@@ -154,6 +156,8 @@ enum : int32_t { ERR_NONFINITE = 1, ERR_MARKER = 2, ERR_CONTRIB = 4, ERR_WINDOW 
 
 // Launchers implemented in sbt_kernels.hip.
 extern "C" {
+// Message for sbt_last_error (the thread's last failure); returns code.
+sbt_status sbt_set_error(sbt_status code, const char *msg);
 // Generic level kernel: any block (interfaces, domain edges, readout,
 // initial collision) and halo-band cells.
 // `storage` of the level launches: SBT_F64 .. SBT_BF16S, plus 4 for the MRT collision.

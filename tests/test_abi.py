@@ -18,9 +18,14 @@ def pkg():
 
 
 def declared_symbols():
-    src = open(os.path.join(ROOT, "include", "sbt.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(sbt_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(sbt3?_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_and_binding_agree(pkg):
@@ -96,6 +101,19 @@ def test_plan_rejects_bad_solids(pkg):
     with pytest.raises(pkg.SbtError):                          # level 1 is covered there
         pkg.plan([cav.replace(solids=[(1, mask[::2, ::2][:512, :512], None)])])
     assert pkg.plan([cav]) > 0
+
+
+def test_3d_plan_and_validation(pkg):
+    import ctypes as C
+    d = pkg.Desc3()
+    d.nx, d.ny, d.nz, d.tau, d.rho0, d.storage = 64, 32, 16, 0.8, 1.0, pkg.F32
+    n = C.c_size_t()
+    assert pkg.lib().sbt3_plan(C.byref(d), C.byref(n)) == 0
+    assert n.value >= 2 * 19 * 64 * 32 * 16 * 4
+    for field, bad in (("tau", 0.5), ("nx", 0), ("storage", 7), ("rho0", 0.0)):
+        e = pkg.Desc3.from_buffer_copy(d)
+        setattr(e, field, bad)
+        assert pkg.lib().sbt3_plan(C.byref(e), C.byref(n)) == -1, field
 
 
 def test_rescale_rejects_unit_tau(pkg):

@@ -683,3 +683,81 @@ def test_set_markers_rejects_other_bodies(env):
     with pytest.raises(P.SbtError) as e:
         g.set_markers(0, np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n))
     assert e.value.code == -1
+
+
+# ---- three dimensions: D3Q19 on one periodic level ---------------------------
+
+def rel_l2_3(g, o):
+    _, u, v, w = g
+    _, uo, vo, wo = o
+    num = np.sqrt(((u - uo) ** 2 + (v - vo) ** 2 + (w - wo) ** 2).sum())
+    return num / np.sqrt((uo ** 2 + vo ** 2 + wo ** 2).sum())
+
+
+@pytest.mark.parametrize("make", [lambda: W.shear_wave3(32, nz=32).replace(fext=(2e-6, -1e-6, 3e-6)),
+                                  lambda: W.tgv3(32, nz=16, tau=0.6)])
+def test_3d_fp64_matches_oracle(env, make):
+    """D3Q19 FP64 against the oracle after 60 steps (forced shear wave,
+    z-extended vortex): every field within 1e-12, in practice bit-exact."""
+    P, O = env
+    wl = make()
+    print(f"case {wl.name} f64", flush=True)
+    g = P.Sim3(wl, "f64")
+    o = O.Oracle3Sim(wl)
+    g.step(60)
+    g.synchronize()
+    o.step(60)
+    fg, fo = g.fields(), o.fields()
+    e = rel_l2_3(fg, fo)
+    dr = np.abs(fg[0] - fo[0]).max()
+    print(f"  rel L2 u {e:.3e}  max |drho| {dr:.3e}", flush=True)
+    assert e <= TOL64 and dr <= 1e-14
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-5), ("f16s", 3e-3), ("bf16s", 3e-2)])
+def test_3d_storage_forms(env, storage, tol):
+    """The reduced storage forms on a 32x32x8 vortex, 300 steps, against the
+    FP64 oracle (the 2D ceilings)."""
+    P, O = env
+    wl = W.tgv3(32, nz=8)
+    print(f"case {wl.name} {storage}", flush=True)
+    g = P.Sim3(wl, storage)
+    o = O.Oracle3Sim(wl)
+    g.step(300)
+    g.synchronize()
+    o.step(300)
+    e = rel_l2_3(g.fields(), o.fields())
+    print(f"  rel L2 u {e:.3e}", flush=True)
+    assert e <= tol
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 0.0), ("f16s", 3e-3)])
+def test_3d_full_size_periodic_tiling(env, storage, tol):
+    """512^3 (the size the 3D benchmark times) started from one 32x32 plane
+    of the vortex tiled across x, y and z: by translation invariance every
+    cell must equal the oracle's 32x32x2 run at (x mod 32, y mod 32); checked
+    on sampled planes after 20 steps.  FP64 bit-exact; F16S within its
+    ceiling."""
+    P, O = env
+    small = W.tgv3(32, nz=2, period=32)
+    cell = small.init(32, 32, 2, 0, 1)        # one plane, tiled exactly (no re-rounded cosines)
+
+    def tiled(nx, ny, nz, z0=0, z1=None):
+        z1 = nz if z1 is None else z1
+        return tuple(np.tile(a, (z1 - z0, ny // 32, nx // 32)) for a in cell)
+
+    big = W.tgv3(512, nz=512, period=32).replace(init=tiled)
+    print(f"case tgv3 512^3 period 32 {storage}", flush=True)
+    g = P.Sim3(big, storage)
+    o = O.Oracle3Sim(small)
+    g.step(20)
+    g.synchronize()
+    o.step(20)
+    ref = [np.tile(a[:1], (1, 16, 16)) for a in o.fields()]
+    for z in (0, 255, 511):
+        fg = g.fields(z, z + 1)
+        e = rel_l2_3(fg, ref)
+        print(f"  plane {z}: rel L2 u {e:.3e}", flush=True)
+        assert e <= tol
+        if storage == "f64":
+            assert all(np.array_equal(a, b) for a, b in zip(fg, ref))
