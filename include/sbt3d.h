@@ -12,7 +12,9 @@
  * arithmetic) and SBT_F32 / SBT_F16S / SBT_BF16S (the deviation
  * f - w rho0, FP32 arithmetic).  Layout in the caller's device buffer:
  * two lattices [19][nz][ny][nx] (x fastest) and a staging area for the
- * field transfers.  All functions return sbt_status; sbt_last_error()
+ * field transfers.  The kernels pull: after a step a lattice holds
+ * post-collision populations and the readout gathers the streamed state
+ * from the lattice the last step read.  All functions return sbt_status; sbt_last_error()
  * describes the last failure.  A context must not be used from two threads
  * at once.
  */
@@ -46,8 +48,10 @@ sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, vo
                        sbt3_ctx **out);
 sbt_status sbt3_destroy(sbt3_ctx *ctx);
 /* f = f^eq(rho, u) (Eq. (7) in 3D) on planes z0 .. z0 + nz - 1, from host
- * FP64 arrays [nz][ny][nx].  Synchronises.  Errors: SBT_ERR_ARG (planes out
- * of range, null arrays). */
+ * FP64 arrays [nz][ny][nx].  Puts the context back to an initial
+ * (pre-collision) state: after a step, every plane must be initialised
+ * again before the next one.  Synchronises.  Errors: SBT_ERR_ARG (planes
+ * out of range, null arrays). */
 sbt_status sbt3_init_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, const double *rho, const double *ux,
                           const double *uy, const double *uz);
 /* Advance n steps.  Asynchronous, stream-ordered. */
