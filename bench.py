@@ -44,6 +44,19 @@ def workload_list(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def measured_traffic_3d(storage):
+    """HBM bytes per launch of the 3D kernel from its committed counter
+    summary (same method as measured_traffic), or None."""
+    path = os.path.join(ROOT, "profiles", f"step3_kernel_box3d_{storage}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2402_04606_amd", "csrc", "sbt3d.hip")
+    if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
 def measured_traffic(workload, storage):
     """HBM bytes per launch of the level kernel from the committed counter
     summary of this workload and storage form (rocprofv3 FETCH_SIZE and
@@ -163,8 +176,9 @@ def bench3d(args, P, W):
         "config": {"workload": f"d3q19_box_{n}^3_periodic_vortex", "storage": args.storage,
                    "updates_per_step": ups, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "step3_kernel (fused D3Q19 collide + push stream)",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic_3d(args.storage) if n == 512 else None,
+                     "kernel": "step3_kernel (fused D3Q19 pull stream + collide)",
                      "bytes_per_update": 2 * 19 * s, "algorithmic_bytes_per_launch": algo,
                      "avg_launch_us": round(launch_ms * 1e3, 2)},
     }
