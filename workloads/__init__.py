@@ -499,7 +499,7 @@ class Workload3:
     tau: float = 0.8
     rho0: float = 1.0
     fext: tuple = (0.0, 0.0, 0.0)
-    init: Optional[Callable] = None   # init(nx, ny, nz) -> (rho, ux, uy, uz) dense [nz, ny, nx]
+    init: Optional[Callable] = None   # init(nx, ny, nz, z0=0, z1=nz) -> (rho, ux, uy, uz), each [z1 - z0, ny, nx]
     meta: dict = dataclasses.field(default_factory=dict)
 
     def replace(self, **kw):
@@ -513,11 +513,13 @@ def shear_wave3(n=32, nz=None, tau=0.8, u0=0.01, period=None):
     period = period or nz
     k = 2 * math.pi / period
 
-    def init(nx, ny, nz_):
-        z = np.arange(nz_) + 0.5
-        ux = np.broadcast_to((u0 * np.sin(k * z))[:, None, None], (nz_, ny, nx)).copy()
-        zero = np.zeros((nz_, ny, nx))
-        return np.ones((nz_, ny, nx)), ux, zero, zero.copy()
+    def init(nx, ny, nz_, z0=0, z1=None):
+        z1 = nz_ if z1 is None else z1
+        z = np.arange(z0, z1) + 0.5
+        m = z1 - z0
+        ux = np.broadcast_to((u0 * np.sin(k * z))[:, None, None], (m, ny, nx)).copy()
+        zero = np.zeros((m, ny, nx))
+        return np.ones((m, ny, nx)), ux, zero, zero.copy()
 
     return Workload3(name=f"shear_wave3_{n}x{n}x{nz}", nx=n, ny=n, nz=nz, tau=tau, init=init,
                      meta=dict(u0=u0, k=k, nu=(tau - 0.5) / 3.0))
@@ -530,7 +532,8 @@ def tgv3(n=32, nz=8, tau=0.8, u0=0.02, period=None):
     period = period or n
     k = 2 * math.pi / period
 
-    def init(nx, ny, nz_):
+    def init(nx, ny, nz_, z0=0, z1=None):
+        z1 = nz_ if z1 is None else z1
         x = np.arange(nx) + 0.5
         y = np.arange(ny) + 0.5
         X, Y = np.meshgrid(x, y)
@@ -538,8 +541,9 @@ def tgv3(n=32, nz=8, tau=0.8, u0=0.02, period=None):
         v = u0 * np.sin(k * X) * np.cos(k * Y)
         p = -(u0 * u0 / 4) * (np.cos(2 * k * X) + np.cos(2 * k * Y))
         r = 1.0 + 3.0 * p
-        rep = lambda a: np.broadcast_to(a[None], (nz_, ny, nx)).copy()
-        return rep(r), rep(u), rep(v), np.zeros((nz_, ny, nx))
+        m = z1 - z0
+        rep = lambda a: np.broadcast_to(a[None], (m, ny, nx)).copy()
+        return rep(r), rep(u), rep(v), np.zeros((m, ny, nx))
 
     return Workload3(name=f"tgv3_{n}x{n}x{nz}", nx=n, ny=n, nz=nz, tau=tau, init=init,
                      meta=dict(u0=u0, k=k, nu=(tau - 0.5) / 3.0))
