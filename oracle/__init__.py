@@ -85,11 +85,11 @@ def lib():
         _lib.orc_spread.argtypes = [C.c_int32, C.c_int32, C.c_int32, d, d, d, d, d, d, d]
         _lib.orc_force_stats.argtypes = [d, d, C.c_int32, C.c_double, C.c_double, d]
         _lib.orc_set_solid.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_uint8), d]
-        _lib.orc3_velocity_set.argtypes = [C.POINTER(C.c_int32)] * 3 + [d]
+        _lib.orc3_velocity_set.argtypes = [C.c_int32] + [C.POINTER(C.c_int32)] * 3 + [d]
         _lib.orc3_velocity_set.restype = None
-        _lib.orc3_feq.argtypes = [C.c_double] * 4 + [d]
+        _lib.orc3_feq.argtypes = [C.c_int32] + [C.c_double] * 4 + [d]
         _lib.orc3_feq.restype = None
-        _lib.orc3_create.argtypes = [C.c_int32] * 3 + [C.c_double, d, C.POINTER(C.c_void_p)]
+        _lib.orc3_create.argtypes = [C.c_int32] * 4 + [C.c_double, d, C.POINTER(C.c_void_p)]
         _lib.orc3_destroy.argtypes = [C.c_void_p]
         _lib.orc3_destroy.restype = None
         _lib.orc3_init_fields.argtypes = [C.c_void_p, d, d, d, d]
@@ -375,28 +375,28 @@ def num_threads():
 
 # ---- three dimensions ----------------------------------------------------------
 
-def velocity_set3():
-    cx, cy, cz = (np.zeros(19, dtype=np.int32) for _ in range(3))
-    w = np.zeros(19)
+def velocity_set3(q=19):
+    cx, cy, cz = (np.zeros(q, dtype=np.int32) for _ in range(3))
+    w = np.zeros(q)
     p32 = C.POINTER(C.c_int32)
-    lib().orc3_velocity_set(cx.ctypes.data_as(p32), cy.ctypes.data_as(p32), cz.ctypes.data_as(p32), _dp(w))
+    lib().orc3_velocity_set(q, cx.ctypes.data_as(p32), cy.ctypes.data_as(p32), cz.ctypes.data_as(p32), _dp(w))
     return cx, cy, cz, w
 
 
-def feq3(rho, ux, uy, uz):
-    out = np.zeros(19)
-    lib().orc3_feq(float(rho), float(ux), float(uy), float(uz), _dp(out))
+def feq3(rho, ux, uy, uz, q=19):
+    out = np.zeros(q)
+    lib().orc3_feq(q, float(rho), float(ux), float(uy), float(uz), _dp(out))
     return out
 
 
 class Oracle3Sim:
-    """D3Q19 BGK + Guo forcing on one periodic level (a ``workloads.Workload3``)."""
+    """D3Q19 / D3Q27 BGK + Guo forcing on one periodic level (a ``workloads.Workload3``)."""
 
     def __init__(self, wl):
         self.wl = wl
         F = _f64(np.asarray(wl.fext, dtype=np.float64))
         h = C.c_void_p()
-        rc = lib().orc3_create(wl.nx, wl.ny, wl.nz, wl.tau, _dp(F), C.byref(h))
+        rc = lib().orc3_create(wl.nx, wl.ny, wl.nz, wl.lattice, wl.tau, _dp(F), C.byref(h))
         if rc:
             raise RuntimeError(f"orc3_create failed: {rc}")
         self._h = h

@@ -1068,48 +1068,55 @@ int orc_set_solid(orc_sim *s, int level, const uint8_t *mask, const double *q) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Three dimensions: D3Q19 on one periodic level                            */
+/* Three dimensions: D3Q19 and D3Q27 on one periodic level                  */
 /* ------------------------------------------------------------------------ */
 
-/* The D3Q19 velocity set (rest, 6 axis, 12 edge directions) with weights
- * 1/3, 1/18, 1/36 and c_s^2 = 1/3: the 3D counterpart of Eq. (1) that the
- * paper's method extends to.  Order: rest, +x -x +y -y +z -z, then the
- * edges (+-1, +-1, 0), (+-1, 0, +-1), (0, +-1, +-1). */
-static const int C3X[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-static const int C3Y[19] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
-static const int C3Z[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+/* The 3D velocity sets the paper's method extends to, with c_s^2 = 1/3.
+ * D3Q19: rest (w = 1/3), 6 axis (1/18), 12 edge (1/36) velocities.  D3Q27
+ * adds the 8 corners: rest 8/27, axis 2/27, edge 1/54, corner 1/216.
+ * Order: rest, +x -x +y -y +z -z, the edges (+-1, +-1, 0), (+-1, 0, +-1),
+ * (0, +-1, +-1), then (D3Q27) the corners. */
+static const int C3X[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                            1, -1, 1, -1, 1, -1, 1, -1};
+static const int C3Y[27] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1,
+                            1, 1, -1, -1, 1, 1, -1, -1};
+static const int C3Z[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1,
+                            1, 1, 1, 1, -1, -1, -1, -1};
 
-static double w3(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
+static double w3(int q, int i) {
+    if (q == 19) return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+    return i == 0 ? 8.0 / 27.0 : (i < 7 ? 2.0 / 27.0 : (i < 19 ? 1.0 / 54.0 : 1.0 / 216.0));
+}
 
-void orc3_velocity_set(int32_t cx[19], int32_t cy[19], int32_t cz[19], double w[19]) {
-    for (int i = 0; i < 19; ++i) { cx[i] = C3X[i]; cy[i] = C3Y[i]; cz[i] = C3Z[i]; w[i] = w3(i); }
+void orc3_velocity_set(int32_t q, int32_t *cx, int32_t *cy, int32_t *cz, double *w) {
+    for (int i = 0; i < q; ++i) { cx[i] = C3X[i]; cy[i] = C3Y[i]; cz[i] = C3Z[i]; w[i] = w3(q, i); }
 }
 
 /* Eq. (7) in 3D. */
-void orc3_feq(double rho, double ux, double uy, double uz, double out[19]) {
+void orc3_feq(int32_t q, double rho, double ux, double uy, double uz, double *out) {
     double usq = ux * ux + uy * uy + uz * uz;
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < q; ++i) {
         double cu = C3X[i] * ux + C3Y[i] * uy + C3Z[i] * uz;
-        out[i] = w3(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+        out[i] = w3(q, i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
     }
 }
 
 struct orc3_sim {
-    int nx, ny, nz;
+    int nx, ny, nz, q;
     double tau, F[3];
-    double *f, *fs;           /* [cell][19], cell = (z ny + y) nx + x */
+    double *f, *fs;           /* [cell][q], cell = (z ny + y) nx + x */
 };
 
-int orc3_create(int32_t nx, int32_t ny, int32_t nz, double tau, const double F[3], orc3_sim **out) {
+int orc3_create(int32_t nx, int32_t ny, int32_t nz, int32_t q, double tau, const double F[3], orc3_sim **out) {
     *out = NULL;
-    if (nx <= 0 || ny <= 0 || nz <= 0 || !(tau > 0.5)) return ORC_ERR_ARG;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || !(tau > 0.5) || (q != 19 && q != 27)) return ORC_ERR_ARG;
     orc3_sim *s = calloc(1, sizeof(orc3_sim));
-    s->nx = nx; s->ny = ny; s->nz = nz; s->tau = tau;
+    s->nx = nx; s->ny = ny; s->nz = nz; s->q = q; s->tau = tau;
     for (int k = 0; k < 3; ++k) s->F[k] = F ? F[k] : 0.0;
-    size_t n = (size_t)nx * ny * nz * 19;
+    size_t n = (size_t)nx * ny * nz * q;
     s->f = malloc(sizeof(double) * n);
     s->fs = malloc(sizeof(double) * n);
-    for (size_t q = 0; q < n; ++q) s->f[q] = s->fs[q] = NAN;
+    for (size_t c = 0; c < n; ++c) s->f[c] = s->fs[c] = NAN;
     *out = s;
     return ORC_OK;
 }
@@ -1121,41 +1128,41 @@ void orc3_destroy(orc3_sim *s) {
 
 int orc3_init_fields(orc3_sim *s, const double *rho, const double *ux, const double *uy, const double *uz) {
     size_t n = (size_t)s->nx * s->ny * s->nz;
-    for (size_t q = 0; q < n; ++q) orc3_feq(rho[q], ux[q], uy[q], uz[q], s->f + q * 19);
+    for (size_t c = 0; c < n; ++c) orc3_feq(s->q, rho[c], ux[c], uy[c], uz[c], s->f + c * s->q);
     return ORC_OK;
 }
 
 /* One step: BGK + Guo forcing with the half-force velocity (Eqs. (2)-(3),
  * (6)-(8) in 3D), then periodic streaming f(x, i) <- f*(x - c_i, i). */
 int orc3_step(orc3_sim *s, int32_t steps) {
-    const int nx = s->nx, ny = s->ny, nz = s->nz;
+    const int nx = s->nx, ny = s->ny, nz = s->nz, Q3 = s->q;
     const size_t n = (size_t)nx * ny * nz;
     const double tau = s->tau, Fx = s->F[0], Fy = s->F[1], Fz = s->F[2];
     for (int32_t t = 0; t < steps; ++t) {
 #pragma omp parallel for schedule(static)
-        for (size_t q = 0; q < n; ++q) {
-            const double *f = s->f + q * 19;
+        for (size_t c = 0; c < n; ++c) {
+            const double *f = s->f + c * Q3;
             double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-            for (int i = 0; i < 19; ++i) { rho += f[i]; jx += C3X[i] * f[i]; jy += C3Y[i] * f[i]; jz += C3Z[i] * f[i]; }
+            for (int i = 0; i < Q3; ++i) { rho += f[i]; jx += C3X[i] * f[i]; jy += C3Y[i] * f[i]; jz += C3Z[i] * f[i]; }
             double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho, uz = (jz + 0.5 * Fz) / rho;
-            double feq[19];
-            orc3_feq(rho, ux, uy, uz, feq);
+            double feq[27];
+            orc3_feq(Q3, rho, ux, uy, uz, feq);
             double uF = ux * Fx + uy * Fy + uz * Fz, pre = 1.0 - 0.5 / tau;
-            for (int i = 0; i < 19; ++i) {
+            for (int i = 0; i < Q3; ++i) {
                 double cu = C3X[i] * ux + C3Y[i] * uy + C3Z[i] * uz;
                 double cF = C3X[i] * Fx + C3Y[i] * Fy + C3Z[i] * Fz;
-                double fi = w3(i) * pre * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
-                s->fs[q * 19 + i] = f[i] - (f[i] - feq[i]) / tau + fi;
+                double fi = w3(Q3, i) * pre * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
+                s->fs[c * Q3 + i] = f[i] - (f[i] - feq[i]) / tau + fi;
             }
         }
 #pragma omp parallel for schedule(static)
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x)
-                    for (int i = 0; i < 19; ++i) {
+                    for (int i = 0; i < Q3; ++i) {
                         int sx = (x - C3X[i] + nx) % nx, sy = (y - C3Y[i] + ny) % ny, sz = (z - C3Z[i] + nz) % nz;
-                        s->f[(((size_t)z * ny + y) * nx + x) * 19 + i] =
-                            s->fs[(((size_t)sz * ny + sy) * nx + sx) * 19 + i];
+                        s->f[(((size_t)z * ny + y) * nx + x) * Q3 + i] =
+                            s->fs[(((size_t)sz * ny + sy) * nx + sx) * Q3 + i];
                     }
     }
     return ORC_OK;
@@ -1164,14 +1171,14 @@ int orc3_step(orc3_sim *s, int32_t steps) {
 /* rho and u = (sum_i c_i f_i + F/2) / rho of every cell (dense arrays). */
 int orc3_read_fields(const orc3_sim *s, double *rho, double *ux, double *uy, double *uz) {
     size_t n = (size_t)s->nx * s->ny * s->nz;
-    for (size_t q = 0; q < n; ++q) {
-        const double *f = s->f + q * 19;
+    for (size_t c = 0; c < n; ++c) {
+        const double *f = s->f + c * s->q;
         double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-        for (int i = 0; i < 19; ++i) { r += f[i]; jx += C3X[i] * f[i]; jy += C3Y[i] * f[i]; jz += C3Z[i] * f[i]; }
-        rho[q] = r;
-        ux[q] = (jx + 0.5 * s->F[0]) / r;
-        uy[q] = (jy + 0.5 * s->F[1]) / r;
-        uz[q] = (jz + 0.5 * s->F[2]) / r;
+        for (int i = 0; i < s->q; ++i) { r += f[i]; jx += C3X[i] * f[i]; jy += C3Y[i] * f[i]; jz += C3Z[i] * f[i]; }
+        rho[c] = r;
+        ux[c] = (jx + 0.5 * s->F[0]) / r;
+        uy[c] = (jy + 0.5 * s->F[1]) / r;
+        uz[c] = (jz + 0.5 * s->F[2]) / r;
     }
     return ORC_OK;
 }

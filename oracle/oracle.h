@@ -124,11 +124,11 @@ int    orc_force_stats(const double *fx, const double *fy, int32_t n, double sca
                        double l_over_u, double out[7]);
 int    orc_num_threads(void);
 
-/* ---- three dimensions: D3Q19, one periodic level --------------------------- */
+/* ---- three dimensions: D3Q19 or D3Q27 (q), one periodic level ------------ */
 typedef struct orc3_sim orc3_sim;
-void orc3_velocity_set(int32_t cx[19], int32_t cy[19], int32_t cz[19], double w[19]);
-void orc3_feq(double rho, double ux, double uy, double uz, double out[19]);
-int  orc3_create(int32_t nx, int32_t ny, int32_t nz, double tau, const double F[3], orc3_sim **out);
+void orc3_velocity_set(int32_t q, int32_t *cx, int32_t *cy, int32_t *cz, double *w);
+void orc3_feq(int32_t q, double rho, double ux, double uy, double uz, double *out);
+int  orc3_create(int32_t nx, int32_t ny, int32_t nz, int32_t q, double tau, const double F[3], orc3_sim **out);
 void orc3_destroy(orc3_sim *s);
 /* f = f^eq(rho, u), dense arrays, cell (z ny + y) nx + x. */
 int  orc3_init_fields(orc3_sim *s, const double *rho, const double *ux, const double *uy, const double *uz);

@@ -765,12 +765,14 @@ def test_host_markers_reproduce_prescribed_motion(orc):
 
 # ---- three dimensions: D3Q19 ---------------------------------------------------
 
-def test_d3q19_isotropy_and_equilibrium_moments(orc):
-    """Weights sum to 1; odd moments vanish; sum w c_a c_b = delta_ab / 3 and
+@pytest.mark.parametrize("q", [19, 27])
+def test_d3q19_isotropy_and_equilibrium_moments(orc, q):
+    """D3Q19 and D3Q27: weights sum to 1; odd moments vanish; sum w c_a c_b = delta_ab / 3 and
     sum w c_a c_b c_c c_d = (d_ab d_cd + d_ac d_bd + d_ad d_bc) / 9; the
     equilibrium carries rho, rho u and rho (u u + I/3)."""
-    cx, cy, cz, w = orc.velocity_set3()
+    cx, cy, cz, w = orc.velocity_set3(q)
     c = np.stack([cx, cy, cz]).astype(float)
+    assert len({(a, b, e) for a, b, e in zip(cx, cy, cz)}) == q
     assert abs(w.sum() - 1) < 1e-15
     assert np.abs(c @ w).max() < 1e-15
     d = np.eye(3)
@@ -780,13 +782,13 @@ def test_d3q19_isotropy_and_equilibrium_moments(orc):
     assert np.abs(m4 - want).max() < 1e-15
     assert np.abs(np.einsum("i,ai,bi,ci->abc", w, c, c, c)).max() < 1e-15
     rho, u = 1.04, np.array([0.03, -0.02, 0.05])
-    f = orc.feq3(rho, *u)
+    f = orc.feq3(rho, *u, q=q)
     assert abs(f.sum() - rho) < 1e-15 and np.abs(c @ f - rho * u).max() < 1e-15
     assert np.abs(np.einsum("i,ai,bi->ab", f, c, c) - rho * (np.outer(u, u) + d / 3)).max() < 1e-15
 
 
-@pytest.mark.parametrize("axis", ["shear", "tgv"])
-def test_d3q19_decay_converges_to_closed_form(orc, axis):
+@pytest.mark.parametrize("axis,q", [("shear", 19), ("tgv", 19), ("shear", 27), ("tgv", 27)])
+def test_d3q19_decay_converges_to_closed_form(orc, axis, q):
     """A shear wave u_x(z) and the Sec. 3.1 vortex extended along z are exact
     solutions decaying as exp(-nu k^2 t) and exp(-2 nu k^2 t); at fixed
     diffusive time the error falls about fourfold per doubling of n."""
@@ -794,10 +796,10 @@ def test_d3q19_decay_converges_to_closed_form(orc, axis):
     for n in (16, 32, 64):
         t = int(round(0.5 * (n / 16) ** 2 * 100))
         if axis == "shear":
-            wl = W.shear_wave3(4, nz=n, tau=0.8)
+            wl = W.shear_wave3(4, nz=n, tau=0.8).replace(lattice=q)
             fac = math.exp(-wl.meta["nu"] * wl.meta["k"] ** 2 * t)
         else:
-            wl = W.tgv3(n, nz=2, tau=0.8)
+            wl = W.tgv3(n, nz=2, tau=0.8).replace(lattice=q)
             fac = math.exp(-2 * wl.meta["nu"] * wl.meta["k"] ** 2 * t)
         s = orc.Oracle3Sim(wl)
         s.step(t)
@@ -808,12 +810,13 @@ def test_d3q19_decay_converges_to_closed_form(orc, axis):
     assert errs[2] < 2e-3 and errs[0] / errs[1] > 3.3 and errs[1] / errs[2] > 3.3, errs
 
 
-def test_d3q19_conservation_and_translation(orc):
-    """Mass is constant and momentum grows by N F per step under a uniform
+@pytest.mark.parametrize("q", [19, 27])
+def test_d3q19_conservation_and_translation(orc, q):
+    """D3Q19 and D3Q27: mass is constant and momentum grows by N F per step under a uniform
     force; an initial state shifted by one cell along each axis gives the
     shifted result (periodic streaming indexes)."""
     F = (2e-6, -1e-6, 3e-6)
-    wl = W.tgv3(16, nz=8, tau=0.7).replace(fext=F)
+    wl = W.tgv3(16, nz=8, tau=0.7).replace(fext=F, lattice=q)
     s = orc.Oracle3Sim(wl)
     r0 = s.fields()[0].sum()
     s.step(20)
@@ -823,7 +826,7 @@ def test_d3q19_conservation_and_translation(orc):
     for comp, Fk in zip((u, v, w), F):
         # momentum = sum(rho u) - N F / 2 (half-force velocity); initial momentum 0 in every direction
         assert abs((r * comp).sum() - n * Fk / 2 - 20 * n * Fk) < 1e-13 * n
-    base = W.tgv3(16, nz=8, tau=0.7)
+    base = W.tgv3(16, nz=8, tau=0.7).replace(lattice=q)
     init0 = base.init
 
     def shifted(nx, ny, nz):

@@ -499,6 +499,7 @@ class Workload3:
     tau: float = 0.8
     rho0: float = 1.0
     fext: tuple = (0.0, 0.0, 0.0)
+    lattice: int = 19                 # D3Q19 or D3Q27
     init: Optional[Callable] = None   # init(nx, ny, nz, z0=0, z1=nz) -> (rho, ux, uy, uz), each [z1 - z0, ny, nx]
     meta: dict = dataclasses.field(default_factory=dict)
 
