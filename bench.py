@@ -144,11 +144,13 @@ def cpu_baseline(wls, budget_s, V):
 
 
 def bench3d(args, P, W):
-    """D3Q19 periodic box (box3d = 512^3, box3d_256 = 256^3): MLUPS and the
-    fused kernel's bandwidth from HIP events on the stream it runs on."""
+    """D3Q19 / D3Q27 periodic box (box3d = 512^3 D3Q19, box3d_q27 = 512^3
+    D3Q27, box3d_256 = 256^3 D3Q19): MLUPS and the fused kernel's bandwidth
+    from HIP events on the stream it runs on."""
     import torch
     n = 256 if args.workload == "box3d_256" else 512
-    wl = W.tgv3(n, nz=n)
+    q = 27 if args.workload == "box3d_q27" else 19
+    wl = W.tgv3(n, nz=n).replace(lattice=q)
     sim = P.Sim3(wl, args.storage)
     sim.step(args.warmup)
     sim.synchronize()
@@ -165,27 +167,27 @@ def bench3d(args, P, W):
     ups = sim.updates_per_step()
     s = P.STORAGE_BYTES[P.STORAGE[args.storage]]
     launch_ms = e0.elapsed_time(e1) / args.steps
-    algo = ups * 2 * 19 * s
+    algo = ups * 2 * q * s
     gbs = algo / (launch_ms * 1e-3) / 1e9
     out = {
-        "metric": "MLUPS & HBM GB/s fraction (D3Q19 periodic box)",
+        "metric": f"MLUPS & HBM GB/s fraction (D3Q{q} periodic box)",
         "value": round(ups * args.steps / dt / 1e6, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"d3q19_box_{n}^3_periodic_vortex", "storage": args.storage,
+        "config": {"workload": f"d3q{q}_box_{n}^3_periodic_vortex", "storage": args.storage,
                    "updates_per_step": ups, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic_3d(args.storage) if n == 512 else None,
-                     "kernel": "step3_kernel (fused D3Q19 pull stream + collide)",
-                     "bytes_per_update": 2 * 19 * s, "algorithmic_bytes_per_launch": algo,
+                     "traffic": measured_traffic_3d(args.storage) if (n, q) == (512, 19) else None,
+                     "kernel": f"step3_kernel (fused D3Q{q} pull stream + collide)",
+                     "bytes_per_update": 2 * q * s, "algorithmic_bytes_per_launch": algo,
                      "avg_launch_us": round(launch_ms * 1e3, 2)},
     }
     if not args.no_cpu:
         import oracle
         m = 64
-        o = oracle.Oracle3Sim(W.tgv3(m, nz=m))
+        o = oracle.Oracle3Sim(W.tgv3(m, nz=m).replace(lattice=q))
         k, t_used = 0, 0.0
         while t_used < args.cpu_budget:
             t1 = time.perf_counter()

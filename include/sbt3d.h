@@ -1,17 +1,20 @@
 /*
  * sbt3d.h -- the three-dimensional (D3Q19) form of the lattice-Boltzmann
  * collide+stream of SBoTFlow (arXiv 2402.04606, Sec. 2.1 written for the
- * 19-velocity 3D lattice the method extends to), on one periodic level.
+ * 3D lattices the method extends to), on one periodic level.
  *
  * One step is Eqs. (2)-(3), (6)-(8) in 3D: BGK collision with Guo's forcing
  * term and the half-force velocity, then streaming f(x + c_i, i) = f*(x, i)
  * across periodic faces.  D3Q19: rest (w = 1/3), 6 axis (1/18) and 12 edge
- * (1/36) velocities, c_s^2 = 1/3.
+ * (1/36) velocities; D3Q27 adds the 8 corners (rest 8/27, axis 2/27, edge
+ * 1/54, corner 1/216); c_s^2 = 1/3 for both.  Direction order: rest,
+ * +x -x +y -y +z -z, the edges (+-1, +-1, 0), (+-1, 0, +-1), (0, +-1, +-1),
+ * then the corners.
  *
  * Storage forms as for the 2D library (sbt.h): SBT_F64 (f itself, FP64
  * arithmetic) and SBT_F32 / SBT_F16S / SBT_BF16S (the deviation
  * f - w rho0, FP32 arithmetic).  Layout in the caller's device buffer:
- * two lattices [19][nz][ny][nx] (x fastest) and a staging area for the
+ * two lattices [Q][nz][ny][nx] (x fastest) and a staging area for the
  * field transfers.  The kernels pull: after a step a lattice holds
  * post-collision populations and the readout gathers the streamed state
  * from the lattice the last step read.  All functions return sbt_status; sbt_last_error()
@@ -36,6 +39,7 @@ typedef struct {
     double tau, rho0;              /* relaxation time (> 1/2), reference density     */
     double fext[3];                /* uniform body-force density                     */
     int32_t storage;               /* SBT_F64 ... SBT_BF16S                          */
+    int32_t lattice;               /* 19 (D3Q19) or 27 (D3Q27)                       */
 } sbt3_desc;
 
 /* Device bytes sbt3_create needs.  Host only.  Errors: SBT_ERR_ARG. */

@@ -54,7 +54,8 @@ class Solid(C.Structure):
 
 class Desc3(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
-                ("rho0", C.c_double), ("fext", C.c_double * 3), ("storage", C.c_int32)]
+                ("rho0", C.c_double), ("fext", C.c_double * 3), ("storage", C.c_int32),
+                ("lattice", C.c_int32)]
 
 
 class CaseDesc(C.Structure):
@@ -409,6 +410,7 @@ class Sim3:
         for k in range(3):
             d.fext[k] = wl.fext[k]
         d.storage = self.storage
+        d.lattice = getattr(wl, "lattice", 19)
         self._desc = d
         n = C.c_size_t()
         _check(lib().sbt3_plan(C.byref(d), C.byref(n)))

@@ -1,11 +1,11 @@
-// D3Q19 stream + collide on one periodic level (the 3D form of Sec. 2.1),
+// D3Q19 / D3Q27 stream + collide on one periodic level (the 3D form of Sec. 2.1),
 // fused into one launch per step with the pull scheme: a lattice holds
 // post-collision populations f*; each thread gathers f*(x - c_i, i) (the
 // streamed, pre-collision state of its cell), collides it (BGK + Guo,
 // Eqs. (2)-(3), (6)-(8)) and stores f*(x) at its own cell, coalesced along
 // x.  The first launch after an initialisation collides the cells' own
-// populations in place of the gather.  HBM-bound: 2 * 19 * s bytes per cell
-// update.  (Measured against the push form -- own loads, scattered stores
+// populations in place of the gather.  HBM-bound: 2 * Q * s bytes per cell
+// update (D3Q19 or D3Q27).  (Measured against the push form -- own loads, scattered stores
 // -- the gather is 7 % faster in FP32 and 17 % in FP16.)
 #include <hip/hip_runtime.h>
 
@@ -18,17 +18,22 @@
 
 namespace {
 
-constexpr int kQ3 = 19;
 constexpr int kThreads = 256;
 
-// Rest, +x -x +y -y +z -z, then the 12 edges (+-1, +-1, 0), (+-1, 0, +-1), (0, +-1, +-1).
-__device__ constexpr int E3X[kQ3] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-__device__ constexpr int E3Y[kQ3] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
-__device__ constexpr int E3Z[kQ3] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+// Rest, +x -x +y -y +z -z, the 12 edges (+-1, +-1, 0), (+-1, 0, +-1),
+// (0, +-1, +-1), then (D3Q27 only) the 8 corners.
+__device__ constexpr int E3X[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                                    1, -1, 1, -1, 1, -1, 1, -1};
+__device__ constexpr int E3Y[27] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1,
+                                    1, 1, -1, -1, 1, 1, -1, -1};
+__device__ constexpr int E3Z[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1,
+                                    1, 1, 1, 1, -1, -1, -1, -1};
 
-template <typename C>
+// Weights: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216.
+template <typename C, int Q>
 __device__ __forceinline__ C w3(int i) {
-  return i == 0 ? C(1.0 / 3.0) : (i < 7 ? C(1.0 / 18.0) : C(1.0 / 36.0));
+  if constexpr (Q == 19) return i == 0 ? C(1.0 / 3.0) : (i < 7 ? C(1.0 / 18.0) : C(1.0 / 36.0));
+  return i == 0 ? C(8.0 / 27.0) : (i < 7 ? C(2.0 / 27.0) : (i < 19 ? C(1.0 / 54.0) : C(1.0 / 216.0)));
 }
 
 template <int ST> struct Store3;
@@ -93,7 +98,7 @@ __device__ __forceinline__ long long source(const Offsets &o, long long c, int i
   return pull ? c + o.ox[1 - E3X[i]] + o.oy[1 - E3Y[i]] + o.oz[1 - E3Z[i]] : c;
 }
 
-template <int ST>
+template <int ST, int kQ3>
 __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *src_, void *dst_, int pull,
                                                          int *err) {
 #pragma clang fp contract(off)
@@ -125,8 +130,8 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
     for (int i = 0; i < kQ3; ++i) {
       const double cu = E3X[i] * ux + E3Y[i] * uy + E3Z[i] * uz;
       const double cF = E3X[i] * Fx + E3Y[i] * Fy + E3Z[i] * Fz;
-      const double fe = w3<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-      const double fi = w3<double>(i) * p.pre * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
+      const double fe = w3<double, kQ3>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+      const double fi = w3<double, kQ3>(i) * p.pre * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
       const double v = f[i] - (f[i] - fe) / p.tau + fi;
       dst[(long long)i * p.n + c] = S::st(v);
     }
@@ -154,11 +159,11 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
 #pragma unroll
     for (int i = 0; i < kQ3; ++i) {
       const float cu = E3X[i] * ux + E3Y[i] * uy + E3Z[i] * uz;
-      const float de = w3<float>(i) * fmaf(rho * cu, fmaf(4.5f, cu, 3.0f), A);
+      const float de = w3<float, kQ3>(i) * fmaf(rho * cu, fmaf(4.5f, cu, 3.0f), A);
       float v = fmaf(p.om_f, de - d[i], d[i]);
       if (forced) {
         const float cF = E3X[i] * Fx + E3Y[i] * Fy + E3Z[i] * Fz;
-        v += w3<float>(i) * p.pre_f * (3.f * cF + 9.f * cu * cF - 3.f * uF);
+        v += w3<float, kQ3>(i) * p.pre_f * (3.f * cF + 9.f * cu * cF - 3.f * uF);
       }
       dst[(long long)i * p.n + c] = S::st(v);
     }
@@ -166,7 +171,7 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
 }
 
 // f = f^eq(rho, u) of cells [c0, c0 + m) from staged FP64 fields [4][m].
-template <int ST>
+template <int ST, int kQ3>
 __global__ __launch_bounds__(kThreads) void init3_kernel(Params p, void *lat_, const double *fld, long long c0,
                                                          long long m) {
 #pragma clang fp contract(off)
@@ -180,16 +185,16 @@ __global__ __launch_bounds__(kThreads) void init3_kernel(Params p, void *lat_, c
 #pragma unroll
   for (int i = 0; i < kQ3; ++i) {
     const double cu = E3X[i] * ux + E3Y[i] * uy + E3Z[i] * uz;
-    const double fe = w3<double>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+    const double fe = w3<double, kQ3>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
     if constexpr (ST == 0) lat[(long long)i * p.n + c0 + k] = S::st(fe);
-    else lat[(long long)i * p.n + c0 + k] = S::st((float)(fe - w3<double>(i) * p.rho0));
+    else lat[(long long)i * p.n + c0 + k] = S::st((float)(fe - w3<double, kQ3>(i) * p.rho0));
   }
 }
 
 // rho, u of cells [c0, c0 + m) into [4][m] (FP64), from the streamed state:
 // gathered from the post-collision lattice the last step read (pull), or the
 // cells' own populations before the first step.
-template <int ST>
+template <int ST, int kQ3>
 __global__ __launch_bounds__(kThreads) void read3_kernel(Params p, const void *lat_, double *fld, long long c0,
                                                          long long m, int pull) {
 #pragma clang fp contract(off)
@@ -240,10 +245,11 @@ namespace {
 sbt_status check_desc(const sbt3_desc *d) {
   if (!d) return sbt_set_error(SBT_ERR_ARG, "null descriptor");
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) return sbt_set_error(SBT_ERR_ARG, "nx, ny, nz must be >= 1");
-  if ((long long)d->nx * d->ny * d->nz * kQ3 >= (1ll << 40)) return sbt_set_error(SBT_ERR_ARG, "grid too large");
+  if ((long long)d->nx * d->ny * d->nz * 27 >= (1ll << 40)) return sbt_set_error(SBT_ERR_ARG, "grid too large");
   if (!(d->tau > 0.5)) return sbt_set_error(SBT_ERR_ARG, "tau must exceed 1/2");
   if (!(d->rho0 > 0.0)) return sbt_set_error(SBT_ERR_ARG, "rho0 must be positive");
   if (d->storage < SBT_F64 || d->storage > SBT_BF16S) return sbt_set_error(SBT_ERR_ARG, "bad storage");
+  if (d->lattice != 19 && d->lattice != 27) return sbt_set_error(SBT_ERR_ARG, "lattice must be 19 or 27");
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(d->fext[k])) return sbt_set_error(SBT_ERR_ARG, "body force must be finite");
   return SBT_OK;
@@ -252,7 +258,7 @@ sbt_status check_desc(const sbt3_desc *d) {
 size_t plan_bytes(const sbt3_desc *d, long long *stage) {
   const long long n = (long long)d->nx * d->ny * d->nz;
   *stage = std::min<long long>(n, std::max<long long>(kStageCells, (long long)d->nx * d->ny));
-  return 2 * align256((size_t)n * kQ3 * storage_bytes3(d->storage)) + align256((size_t)*stage * 4 * sizeof(double)) +
+  return 2 * align256((size_t)n * d->lattice * storage_bytes3(d->storage)) + align256((size_t)*stage * 4 * sizeof(double)) +
          256;
 }
 
@@ -262,16 +268,20 @@ size_t plan_bytes(const sbt3_desc *d, long long *stage) {
     if (e_ != hipSuccess) return sbt_set_error(SBT_ERR_DEVICE, hipGetErrorString(e_)); \
   } while (0)
 
-#define SBT3_LAUNCH(K, st, g, s, ...)                                                   \
-  [&]() -> hipError_t {                                                                  \
-    switch (st) {                                                                        \
-      case 0: hipLaunchKernelGGL(K<0>, g, dim3(kThreads), 0, s, __VA_ARGS__); break;      \
-      case 1: hipLaunchKernelGGL(K<1>, g, dim3(kThreads), 0, s, __VA_ARGS__); break;      \
-      case 2: hipLaunchKernelGGL(K<2>, g, dim3(kThreads), 0, s, __VA_ARGS__); break;      \
-      case 3: hipLaunchKernelGGL(K<3>, g, dim3(kThreads), 0, s, __VA_ARGS__); break;      \
-      default: return hipErrorInvalidValue;                                              \
-    }                                                                                    \
-    return hipGetLastError();                                                            \
+#define SBT3_LAUNCH(K, st, q, g, s, ...)                                                          \
+  [&]() -> hipError_t {                                                                             \
+    switch ((st) + 4 * ((q) == 27)) {                                                               \
+      case 0: hipLaunchKernelGGL((K<0, 19>), g, dim3(kThreads), 0, s, __VA_ARGS__); break;          \
+      case 1: hipLaunchKernelGGL((K<1, 19>), g, dim3(kThreads), 0, s, __VA_ARGS__); break;          \
+      case 2: hipLaunchKernelGGL((K<2, 19>), g, dim3(kThreads), 0, s, __VA_ARGS__); break;          \
+      case 3: hipLaunchKernelGGL((K<3, 19>), g, dim3(kThreads), 0, s, __VA_ARGS__); break;          \
+      case 4: hipLaunchKernelGGL((K<0, 27>), g, dim3(kThreads), 0, s, __VA_ARGS__); break;          \
+      case 5: hipLaunchKernelGGL((K<1, 27>), g, dim3(kThreads), 0, s, __VA_ARGS__); break;          \
+      case 6: hipLaunchKernelGGL((K<2, 27>), g, dim3(kThreads), 0, s, __VA_ARGS__); break;          \
+      case 7: hipLaunchKernelGGL((K<3, 27>), g, dim3(kThreads), 0, s, __VA_ARGS__); break;          \
+      default: return hipErrorInvalidValue;                                                         \
+    }                                                                                               \
+    return hipGetLastError();                                                                       \
   }()
 
 sbt_status check_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, const void *a, const void *b, const void *c,
@@ -322,7 +332,7 @@ sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, vo
     p.F_f[k] = (float)desc->fext[k];
   }
   char *b = static_cast<char *>(device_buf);
-  const size_t lat = align256((size_t)p.n * kQ3 * storage_bytes3(desc->storage));
+  const size_t lat = align256((size_t)p.n * desc->lattice * storage_bytes3(desc->storage));
   X->lat[0] = b;
   X->lat[1] = b + lat;
   X->stage = reinterpret_cast<double *>(b + 2 * lat);
@@ -354,7 +364,7 @@ sbt_status sbt3_init_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, const double *r
     for (int q = 0; q < 4; ++q)
       HIP3(hipMemcpyAsync(X.stage + q * m, src[q] + k0, sizeof(double) * m, hipMemcpyHostToDevice, X.stream));
     X.post = false;  // the lattice holds an initial, pre-collision state again
-    HIP3(SBT3_LAUNCH(init3_kernel, X.d.storage, dim3((unsigned)((m + kThreads - 1) / kThreads)), X.stream, X.p,
+    HIP3(SBT3_LAUNCH(init3_kernel, X.d.storage, X.d.lattice, dim3((unsigned)((m + kThreads - 1) / kThreads)), X.stream, X.p,
                      X.lat[X.cur], (const double *)X.stage, (long long)z0 * plane + k0, m));
     HIP3(hipStreamSynchronize(X.stream));
   }
@@ -367,13 +377,13 @@ sbt_status sbt3_step(sbt3_ctx *ctx, int32_t n) {
   if (n == 0) return SBT_OK;
   const dim3 grid((unsigned)((X.p.n + kThreads - 1) / kThreads));
   if (!X.post) {  // collide the initial state in place: the lattice then holds f*
-    HIP3(SBT3_LAUNCH(step3_kernel, X.d.storage, grid, X.stream, X.p, (const void *)X.lat[X.cur], X.lat[1 - X.cur], 0,
+    HIP3(SBT3_LAUNCH(step3_kernel, X.d.storage, X.d.lattice, grid, X.stream, X.p, (const void *)X.lat[X.cur], X.lat[1 - X.cur], 0,
                      X.err));
     X.cur = 1 - X.cur;
     X.post = true;
   }
   for (int t = 0; t < n; ++t) {
-    HIP3(SBT3_LAUNCH(step3_kernel, X.d.storage, grid, X.stream, X.p, (const void *)X.lat[X.cur], X.lat[1 - X.cur], 1,
+    HIP3(SBT3_LAUNCH(step3_kernel, X.d.storage, X.d.lattice, grid, X.stream, X.p, (const void *)X.lat[X.cur], X.lat[1 - X.cur], 1,
                      X.err));
     X.cur = 1 - X.cur;
   }
@@ -401,7 +411,7 @@ sbt_status sbt3_read_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, double *rho, do
     const long long m = std::min(X.stage_cells, total - k0);
     // after a step the streamed state is gathered from the lattice the last step read
     const void *src = X.post ? X.lat[1 - X.cur] : X.lat[X.cur];
-    HIP3(SBT3_LAUNCH(read3_kernel, X.d.storage, dim3((unsigned)((m + kThreads - 1) / kThreads)), X.stream, X.p, src,
+    HIP3(SBT3_LAUNCH(read3_kernel, X.d.storage, X.d.lattice, dim3((unsigned)((m + kThreads - 1) / kThreads)), X.stream, X.p, src,
                      X.stage, (long long)z0 * plane + k0, m, X.post ? 1 : 0));
     double *dst[4] = {rho, ux, uy, uz};
     for (int q = 0; q < 4; ++q)

@@ -106,11 +106,13 @@ def test_plan_rejects_bad_solids(pkg):
 def test_3d_plan_and_validation(pkg):
     import ctypes as C
     d = pkg.Desc3()
-    d.nx, d.ny, d.nz, d.tau, d.rho0, d.storage = 64, 32, 16, 0.8, 1.0, pkg.F32
+    d.nx, d.ny, d.nz, d.tau, d.rho0, d.storage, d.lattice = 64, 32, 16, 0.8, 1.0, pkg.F32, 19
     n = C.c_size_t()
     assert pkg.lib().sbt3_plan(C.byref(d), C.byref(n)) == 0
     assert n.value >= 2 * 19 * 64 * 32 * 16 * 4
-    for field, bad in (("tau", 0.5), ("nx", 0), ("storage", 7), ("rho0", 0.0)):
+    d.lattice = 27
+    assert pkg.lib().sbt3_plan(C.byref(d), C.byref(n)) == 0 and n.value >= 2 * 27 * 64 * 32 * 16 * 4
+    for field, bad in (("tau", 0.5), ("nx", 0), ("storage", 7), ("rho0", 0.0), ("lattice", 15)):
         e = pkg.Desc3.from_buffer_copy(d)
         setattr(e, field, bad)
         assert pkg.lib().sbt3_plan(C.byref(e), C.byref(n)) == -1, field

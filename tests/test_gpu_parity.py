@@ -694,13 +694,15 @@ def rel_l2_3(g, o):
     return num / np.sqrt((uo ** 2 + vo ** 2 + wo ** 2).sum())
 
 
+@pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("make", [lambda: W.shear_wave3(32, nz=32).replace(fext=(2e-6, -1e-6, 3e-6)),
                                   lambda: W.tgv3(32, nz=16, tau=0.6)])
-def test_3d_fp64_matches_oracle(env, make):
-    """D3Q19 FP64 against the oracle after 60 steps (forced shear wave,
-    z-extended vortex): every field within 1e-12, in practice bit-exact."""
+def test_3d_fp64_matches_oracle(env, make, q):
+    """D3Q19 and D3Q27, FP64, against the oracle after 60 steps (forced shear
+    wave, z-extended vortex): every field within 1e-12, in practice
+    bit-exact."""
     P, O = env
-    wl = make()
+    wl = make().replace(lattice=q)
     print(f"case {wl.name} f64", flush=True)
     g = P.Sim3(wl, "f64")
     o = O.Oracle3Sim(wl)
@@ -714,12 +716,13 @@ def test_3d_fp64_matches_oracle(env, make):
     assert e <= TOL64 and dr <= 1e-14
 
 
+@pytest.mark.parametrize("q", [19, 27])
 @pytest.mark.parametrize("storage,tol", [("f32", 2e-5), ("f16s", 3e-3), ("bf16s", 3e-2)])
-def test_3d_storage_forms(env, storage, tol):
+def test_3d_storage_forms(env, storage, tol, q):
     """The reduced storage forms on a 32x32x8 vortex, 300 steps, against the
     FP64 oracle (the 2D ceilings)."""
     P, O = env
-    wl = W.tgv3(32, nz=8)
+    wl = W.tgv3(32, nz=8).replace(lattice=q)
     print(f"case {wl.name} {storage}", flush=True)
     g = P.Sim3(wl, storage)
     o = O.Oracle3Sim(wl)
@@ -731,23 +734,23 @@ def test_3d_storage_forms(env, storage, tol):
     assert e <= tol
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 0.0), ("f16s", 3e-3)])
-def test_3d_full_size_periodic_tiling(env, storage, tol):
+@pytest.mark.parametrize("storage,tol,q", [("f64", 0.0, 19), ("f16s", 3e-3, 19), ("f32", 2e-5, 27)])
+def test_3d_full_size_periodic_tiling(env, storage, tol, q):
     """512^3 (the size the 3D benchmark times) started from one 32x32 plane
     of the vortex tiled across x, y and z: by translation invariance every
     cell must equal the oracle's 32x32x2 run at (x mod 32, y mod 32); checked
     on sampled planes after 20 steps.  FP64 bit-exact; F16S within its
     ceiling."""
     P, O = env
-    small = W.tgv3(32, nz=2, period=32)
+    small = W.tgv3(32, nz=2, period=32).replace(lattice=q)
     cell = small.init(32, 32, 2, 0, 1)        # one plane, tiled exactly (no re-rounded cosines)
 
     def tiled(nx, ny, nz, z0=0, z1=None):
         z1 = nz if z1 is None else z1
         return tuple(np.tile(a, (z1 - z0, ny // 32, nx // 32)) for a in cell)
 
-    big = W.tgv3(512, nz=512, period=32).replace(init=tiled)
-    print(f"case tgv3 512^3 period 32 {storage}", flush=True)
+    big = W.tgv3(512, nz=512, period=32).replace(init=tiled, lattice=q)
+    print(f"case tgv3 512^3 period 32 D3Q{q} {storage}", flush=True)
     g = P.Sim3(big, storage)
     o = O.Oracle3Sim(small)
     g.step(20)
