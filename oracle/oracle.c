@@ -1101,8 +1101,16 @@ void orc3_feq(int32_t q, double rho, double ux, double uy, double uz, double *ou
     }
 }
 
+static int opposite3(int i) {
+    for (int k = 0; k < 27; ++k)
+        if (C3X[k] == -C3X[i] && C3Y[k] == -C3Y[i] && C3Z[k] == -C3Z[i]) return k;
+    return -1;
+}
+
 struct orc3_sim {
     int nx, ny, nz, q;
+    int walls;                /* 1: half-way bounce-back walls below z = 0 and above z = nz - 1 */
+    double uw[2][3];          /* bottom and top wall velocities                                  */
     double tau, F[3];
     double *f, *fs;           /* [cell][q], cell = (z ny + y) nx + x */
 };
@@ -1160,11 +1168,29 @@ int orc3_step(orc3_sim *s, int32_t steps) {
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x)
                     for (int i = 0; i < Q3; ++i) {
-                        int sx = (x - C3X[i] + nx) % nx, sy = (y - C3Y[i] + ny) % ny, sz = (z - C3Z[i] + nz) % nz;
-                        s->f[(((size_t)z * ny + y) * nx + x) * Q3 + i] =
-                            s->fs[(((size_t)sz * ny + sy) * nx + sx) * Q3 + i];
+                        size_t c = ((size_t)z * ny + y) * nx + x;
+                        int zs = z - C3Z[i];
+                        if (s->walls && (zs < 0 || zs >= nz)) {
+                            int o = opposite3(i);
+                            const double *u = s->uw[zs < 0 ? 0 : 1];
+                            double cu = C3X[o] * u[0] + C3Y[o] * u[1] + C3Z[o] * u[2];
+                            s->f[c * Q3 + i] = s->fs[c * Q3 + o] - 6.0 * w3(Q3, i) * 1.0 * cu;
+                            continue;
+                        }
+                        int sx = (x - C3X[i] + nx) % nx, sy = (y - C3Y[i] + ny) % ny, sz = (zs + nz) % nz;
+                        s->f[c * Q3 + i] = s->fs[(((size_t)sz * ny + sy) * nx + sx) * Q3 + i];
                     }
     }
+    return ORC_OK;
+}
+
+/* Walls across z: a population that would stream in from outside the box is
+ * the opposite population of the same cell bounced back half-way, with the
+ * moving-wall term of the 2D walls (density rho0 = 1 at the wall):
+ * f_i(x) = f*_o(x) - 6 w_i rho0 (c_o . u_wall), o = opposite(i). */
+int orc3_set_walls(orc3_sim *s, const double ub[3], const double ut[3]) {
+    s->walls = 1;
+    for (int k = 0; k < 3; ++k) { s->uw[0][k] = ub ? ub[k] : 0.0; s->uw[1][k] = ut ? ut[k] : 0.0; }
     return ORC_OK;
 }
 

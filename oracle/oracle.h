@@ -133,6 +133,9 @@ void orc3_destroy(orc3_sim *s);
 /* f = f^eq(rho, u), dense arrays, cell (z ny + y) nx + x. */
 int  orc3_init_fields(orc3_sim *s, const double *rho, const double *ux, const double *uy, const double *uz);
 int  orc3_step(orc3_sim *s, int32_t steps);
+/* Half-way bounce-back walls below z = 0 and above z = nz - 1 (velocities
+ * ub, ut; NULL = at rest) instead of the periodic z faces. */
+int  orc3_set_walls(orc3_sim *s, const double ub[3], const double ut[3]);
 int  orc3_read_fields(const orc3_sim *s, double *rho, double *ux, double *uy, double *uz);
 
 #ifdef __cplusplus

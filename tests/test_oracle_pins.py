@@ -837,3 +837,26 @@ def test_d3q19_conservation_and_translation(orc, q):
     b.step(7)
     for fa, fb in zip(a.fields(), b.fields()):
         assert np.array_equal(np.roll(fa, (1, 1, 1), axis=(0, 1, 2)), fb)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_3d_walls_give_exact_channel_flows(orc, q):
+    """Half-way bounce-back walls across z: body-forced flow is the exact
+    parabola at tau = 1/2 + sqrt(3)/4 with the walls half a cell beyond the
+    last rows, and a moving top wall gives the exact linear profile (as the
+    2D walls)."""
+    nz = 16
+    z = np.arange(nz) + 0.5
+    wl = W.channel3(nz=nz, lattice=q)
+    s = orc.Oracle3Sim(wl)
+    s.step(30000)
+    _, u, v, w = s.fields()
+    g, nu = wl.meta["g"], wl.meta["nu"]
+    ua = g / (2 * nu) * z * (nz - z)
+    assert np.abs(u[:, 0, 0] - ua).max() < 1e-9 * ua.max()
+    assert np.abs(u - u[:, :1, :1]).max() < 1e-18 and np.abs(w).max() < 1e-13
+    wl = W.channel3(nz=nz, g=0.0, lid=0.01, tau=0.8, lattice=q)
+    s = orc.Oracle3Sim(wl)
+    s.step(8000)
+    _, u, _, _ = s.fields()
+    assert np.abs(u[:, 0, 0] - 0.01 * z / nz).max() < 1e-9

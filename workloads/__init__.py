@@ -500,6 +500,8 @@ class Workload3:
     rho0: float = 1.0
     fext: tuple = (0.0, 0.0, 0.0)
     lattice: int = 19                 # D3Q19 or D3Q27
+    walls_z: bool = False             # half-way bounce-back walls across z instead of periodic
+    wall_u: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))   # bottom, top wall velocities
     init: Optional[Callable] = None   # init(nx, ny, nz, z0=0, z1=nz) -> (rho, ux, uy, uz), each [z1 - z0, ny, nx]
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -548,3 +550,17 @@ def tgv3(n=32, nz=8, tau=0.8, u0=0.02, period=None):
 
     return Workload3(name=f"tgv3_{n}x{n}x{nz}", nx=n, ny=n, nz=nz, tau=tau, init=init,
                      meta=dict(u0=u0, k=k, nu=(tau - 0.5) / 3.0))
+
+
+def channel3(n=8, nz=16, tau=0.5 + math.sqrt(3) / 4, g=1e-6, lid=0.0, lattice=19):
+    """Flow between walls across z (periodic in x and y): body force g along
+    x (Poiseuille) and/or a top wall moving at lid along x (Couette)."""
+    def init(nx, ny, nz_, z0=0, z1=None):
+        z1 = nz_ if z1 is None else z1
+        m = z1 - z0
+        zero = np.zeros((m, ny, nx))
+        return np.ones((m, ny, nx)), zero, zero.copy(), zero.copy()
+
+    return Workload3(name=f"channel3_{n}x{n}x{nz}", nx=n, ny=n, nz=nz, tau=tau, fext=(g, 0.0, 0.0),
+                     lattice=lattice, walls_z=True, wall_u=((0.0, 0.0, 0.0), (lid, 0.0, 0.0)), init=init,
+                     meta=dict(g=g, lid=lid, nu=(tau - 0.5) / 3.0))
