@@ -5,7 +5,9 @@
  *
  * One step is Eqs. (2)-(3), (6)-(8) in 3D: BGK collision with Guo's forcing
  * term and the half-force velocity, then streaming f(x + c_i, i) = f*(x, i)
- * across periodic faces.  D3Q19: rest (w = 1/3), 6 axis (1/18) and 12 edge
+ * across periodic faces (or, across z, half-way bounce-back walls with the
+ * moving-wall term f_i = f*_o - 6 w_i rho0 (c_o . u_wall), o = opposite(i),
+ * as the 2D walls).  D3Q19: rest (w = 1/3), 6 axis (1/18) and 12 edge
  * (1/36) velocities; D3Q27 adds the 8 corners (rest 8/27, axis 2/27, edge
  * 1/54, corner 1/216); c_s^2 = 1/3 for both.  Direction order: rest,
  * +x -x +y -y +z -z, the edges (+-1, +-1, 0), (+-1, 0, +-1), (0, +-1, +-1),
@@ -40,6 +42,9 @@ typedef struct {
     double fext[3];                /* uniform body-force density                     */
     int32_t storage;               /* SBT_F64 ... SBT_BF16S                          */
     int32_t lattice;               /* 19 (D3Q19) or 27 (D3Q27)                       */
+    int32_t walls_z;               /* 0: periodic in z; 1: half-way bounce-back
+                                      walls below z = 0 and above z = nz - 1         */
+    double wall_u[2][3];           /* bottom and top wall velocities (walls_z = 1)   */
 } sbt3_desc;
 
 /* Device bytes sbt3_create needs.  Host only.  Errors: SBT_ERR_ARG. */

@@ -95,7 +95,7 @@ def lib():
         _lib.orc3_init_fields.argtypes = [C.c_void_p, d, d, d, d]
         _lib.orc3_step.argtypes = [C.c_void_p, C.c_int32]
         _lib.orc3_read_fields.argtypes = [C.c_void_p, d, d, d, d]
-        _lib.orc3_set_walls.argtypes = [C.c_void_p, d, d]
+        _lib.orc3_set_walls.argtypes = [C.c_void_p, C.c_double, d, d]
         _lib.orc_num_threads.argtypes = []
     return _lib
 
@@ -403,7 +403,7 @@ class Oracle3Sim:
         self._h = h
         if getattr(wl, "walls_z", False):
             ub, ut = (_f64(np.asarray(a, dtype=np.float64)) for a in wl.wall_u)
-            lib().orc3_set_walls(h, _dp(ub), _dp(ut))
+            lib().orc3_set_walls(h, float(wl.rho0), _dp(ub), _dp(ut))
         r, u, v, w = (_f64(a) for a in wl.init(wl.nx, wl.ny, wl.nz))
         lib().orc3_init_fields(h, _dp(r), _dp(u), _dp(v), _dp(w))
 

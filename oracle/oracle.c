@@ -1111,6 +1111,7 @@ struct orc3_sim {
     int nx, ny, nz, q;
     int walls;                /* 1: half-way bounce-back walls below z = 0 and above z = nz - 1 */
     double uw[2][3];          /* bottom and top wall velocities                                  */
+    double rho_w;             /* wall density of the moving-wall term                            */
     double tau, F[3];
     double *f, *fs;           /* [cell][q], cell = (z ny + y) nx + x */
 };
@@ -1174,7 +1175,7 @@ int orc3_step(orc3_sim *s, int32_t steps) {
                             int o = opposite3(i);
                             const double *u = s->uw[zs < 0 ? 0 : 1];
                             double cu = C3X[o] * u[0] + C3Y[o] * u[1] + C3Z[o] * u[2];
-                            s->f[c * Q3 + i] = s->fs[c * Q3 + o] - 6.0 * w3(Q3, i) * 1.0 * cu;
+                            s->f[c * Q3 + i] = s->fs[c * Q3 + o] - 6.0 * w3(Q3, i) * s->rho_w * cu;
                             continue;
                         }
                         int sx = (x - C3X[i] + nx) % nx, sy = (y - C3Y[i] + ny) % ny, sz = (zs + nz) % nz;
@@ -1186,10 +1187,11 @@ int orc3_step(orc3_sim *s, int32_t steps) {
 
 /* Walls across z: a population that would stream in from outside the box is
  * the opposite population of the same cell bounced back half-way, with the
- * moving-wall term of the 2D walls (density rho0 = 1 at the wall):
- * f_i(x) = f*_o(x) - 6 w_i rho0 (c_o . u_wall), o = opposite(i). */
-int orc3_set_walls(orc3_sim *s, const double ub[3], const double ut[3]) {
+ * moving-wall term of the 2D walls (wall density rho0, the reference
+ * density): f_i(x) = f*_o(x) - 6 w_i rho0 (c_o . u_wall), o = opposite(i). */
+int orc3_set_walls(orc3_sim *s, double rho0, const double ub[3], const double ut[3]) {
     s->walls = 1;
+    s->rho_w = rho0;
     for (int k = 0; k < 3; ++k) { s->uw[0][k] = ub ? ub[k] : 0.0; s->uw[1][k] = ut ? ut[k] : 0.0; }
     return ORC_OK;
 }

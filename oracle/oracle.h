@@ -134,8 +134,8 @@ void orc3_destroy(orc3_sim *s);
 int  orc3_init_fields(orc3_sim *s, const double *rho, const double *ux, const double *uy, const double *uz);
 int  orc3_step(orc3_sim *s, int32_t steps);
 /* Half-way bounce-back walls below z = 0 and above z = nz - 1 (velocities
- * ub, ut; NULL = at rest) instead of the periodic z faces. */
-int  orc3_set_walls(orc3_sim *s, const double ub[3], const double ut[3]);
+ * ub, ut; NULL = at rest; wall density rho0) instead of the periodic z faces. */
+int  orc3_set_walls(orc3_sim *s, double rho0, const double ub[3], const double ut[3]);
 int  orc3_read_fields(const orc3_sim *s, double *rho, double *ux, double *uy, double *uz);
 
 #ifdef __cplusplus

@@ -55,7 +55,7 @@ class Solid(C.Structure):
 class Desc3(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
                 ("rho0", C.c_double), ("fext", C.c_double * 3), ("storage", C.c_int32),
-                ("lattice", C.c_int32)]
+                ("lattice", C.c_int32), ("walls_z", C.c_int32), ("wall_u", (C.c_double * 3) * 2)]
 
 
 class CaseDesc(C.Structure):
@@ -411,6 +411,10 @@ class Sim3:
             d.fext[k] = wl.fext[k]
         d.storage = self.storage
         d.lattice = getattr(wl, "lattice", 19)
+        d.walls_z = 1 if getattr(wl, "walls_z", False) else 0
+        for a, u in enumerate(getattr(wl, "wall_u", ((0.0,) * 3,) * 2)):
+            for k in range(3):
+                d.wall_u[a][k] = u[k]
         self._desc = d
         n = C.c_size_t()
         _check(lib().sbt3_plan(C.byref(d), C.byref(n)))

@@ -29,6 +29,9 @@ __device__ constexpr int E3Y[27] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0,
 __device__ constexpr int E3Z[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1,
                                     1, 1, 1, 1, -1, -1, -1, -1};
 
+__device__ constexpr int OPP3[27] = {0,  2,  1,  4,  3,  6,  5,  10, 9,  8,  7,  14, 13, 12,
+                                     11, 18, 17, 16, 15, 26, 25, 24, 23, 22, 21, 20, 19};
+
 // Weights: D3Q19 1/3, 1/18, 1/36; D3Q27 8/27, 2/27, 1/54, 1/216.
 template <typename C, int Q>
 __device__ __forceinline__ C w3(int i) {
@@ -64,9 +67,10 @@ template <> struct Store3<3> {  // bf16, round to nearest even
 };
 
 struct Params {
-  int nx, ny, nz;
+  int nx, ny, nz, walls;
   long long n;
   double tau, pre, rho0, F[3];
+  double uw[2][3];             // bottom and top wall velocities (walls across z)
   float om_f, pre_f, rho0_f, F_f[3];
 };
 
@@ -98,6 +102,27 @@ __device__ __forceinline__ long long source(const Offsets &o, long long c, int i
   return pull ? c + o.ox[1 - E3X[i]] + o.oy[1 - E3Y[i]] + o.oz[1 - E3Z[i]] : c;
 }
 
+// The pulled population of direction i at cell c (plane z).  With walls
+// across z, a source below z = 0 or above z = nz - 1 is replaced by half-way
+// bounce-back of the opposite population o of the same cell with the
+// moving-wall term: f_i = f*_o - 6 w_i rho0 (c_o . u_wall).  The term is
+// the same in the deviation frame (w_i = w_o).
+template <int ST, int Q>
+__device__ __forceinline__ auto gather(const Params &p, const typename Store3<ST>::T *src, const Offsets &o,
+                                       long long c, int z, int i, bool pull) {
+#pragma clang fp contract(off)
+  using S = Store3<ST>;
+  if (pull && p.walls && ((E3Z[i] > 0 && z == 0) || (E3Z[i] < 0 && z == p.nz - 1))) {
+    const int oi = OPP3[i];
+    const double *u = p.uw[E3Z[i] > 0 ? 0 : 1];
+    const double cu = E3X[oi] * u[0] + E3Y[oi] * u[1] + E3Z[oi] * u[2];
+    const double t = 6.0 * w3<double, Q>(i) * p.rho0 * cu;
+    if constexpr (ST == 0) return S::ld(src[(long long)oi * p.n + c]) - t;
+    else return S::ld(src[(long long)oi * p.n + c]) - (float)t;
+  }
+  return S::ld(src[(long long)i * p.n + source(o, c, i, pull)]);
+}
+
 template <int ST, int kQ3>
 __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *src_, void *dst_, int pull,
                                                          int *err) {
@@ -109,10 +134,11 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
   const T *src = static_cast<const T *>(src_);
   T *dst = static_cast<T *>(dst_);
   const Offsets o = offsets(p, c);
+  const int z = (int)(c / ((long long)p.nx * p.ny));
   if constexpr (ST == 0) {
     double f[kQ3];
 #pragma unroll
-    for (int i = 0; i < kQ3; ++i) f[i] = S::ld(src[(long long)i * p.n + source(o, c, i, pull)]);
+    for (int i = 0; i < kQ3; ++i) f[i] = gather<ST, kQ3>(p, src, o, c, z, i, pull);
     double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < kQ3; ++i) {
@@ -139,7 +165,7 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
     // deviation form d = f - w rho0 (FP32 arithmetic)
     float d[kQ3];
 #pragma unroll
-    for (int i = 0; i < kQ3; ++i) d[i] = S::ld(src[(long long)i * p.n + source(o, c, i, pull)]);
+    for (int i = 0; i < kQ3; ++i) d[i] = gather<ST, kQ3>(p, src, o, c, z, i, pull);
     float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
     for (int i = 0; i < kQ3; ++i) {
@@ -204,10 +230,11 @@ __global__ __launch_bounds__(kThreads) void read3_kernel(Params p, const void *l
   if (k >= m) return;
   const T *lat = static_cast<const T *>(lat_);
   const Offsets o = offsets(p, c0 + k);
+  const int z = (int)((c0 + k) / ((long long)p.nx * p.ny));
   double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
   for (int i = 0; i < kQ3; ++i) {
-    const double f = (double)S::ld(lat[(long long)i * p.n + source(o, c0 + k, i, pull)]);
+    const double f = (double)gather<ST, kQ3>(p, lat, o, c0 + k, z, i, pull);
     r += f;
     jx += E3X[i] * f;
     jy += E3Y[i] * f;
@@ -251,7 +278,8 @@ sbt_status check_desc(const sbt3_desc *d) {
   if (d->storage < SBT_F64 || d->storage > SBT_BF16S) return sbt_set_error(SBT_ERR_ARG, "bad storage");
   if (d->lattice != 19 && d->lattice != 27) return sbt_set_error(SBT_ERR_ARG, "lattice must be 19 or 27");
   for (int k = 0; k < 3; ++k)
-    if (!std::isfinite(d->fext[k])) return sbt_set_error(SBT_ERR_ARG, "body force must be finite");
+    if (!std::isfinite(d->fext[k]) || !std::isfinite(d->wall_u[0][k]) || !std::isfinite(d->wall_u[1][k]))
+      return sbt_set_error(SBT_ERR_ARG, "body force and wall velocities must be finite");
   return SBT_OK;
 }
 
@@ -330,7 +358,10 @@ sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, vo
   for (int k = 0; k < 3; ++k) {
     p.F[k] = desc->fext[k];
     p.F_f[k] = (float)desc->fext[k];
+    p.uw[0][k] = desc->wall_u[0][k];
+    p.uw[1][k] = desc->wall_u[1][k];
   }
+  p.walls = desc->walls_z ? 1 : 0;
   char *b = static_cast<char *>(device_buf);
   const size_t lat = align256((size_t)p.n * desc->lattice * storage_bytes3(desc->storage));
   X->lat[0] = b;

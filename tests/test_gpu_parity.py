@@ -764,3 +764,24 @@ def test_3d_full_size_periodic_tiling(env, storage, tol, q):
         assert e <= tol
         if storage == "f64":
             assert all(np.array_equal(a, b) for a, b in zip(fg, ref))
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", TOL64), ("f32", 2e-5), ("f16s", 3e-3)])
+def test_3d_walls_channel(env, storage, tol, q):
+    """Walls across z with a moving top wall and a body force (Couette plus
+    Poiseuille), 400 steps from rest, against the oracle."""
+    P, O = env
+    wl = W.channel3(n=16, nz=24, tau=0.8, g=2e-6, lid=0.02, lattice=q)
+    print(f"case {wl.name} D3Q{q} {storage}", flush=True)
+    g = P.Sim3(wl, storage)
+    o = O.Oracle3Sim(wl)
+    g.step(400)
+    g.synchronize()
+    o.step(400)
+    fg, fo = g.fields(), o.fields()
+    e = rel_l2_3(fg, fo)
+    print(f"  rel L2 u {e:.3e}", flush=True)
+    assert e <= tol
+    if storage == "f64":
+        assert all(np.array_equal(a, b) for a, b in zip(fg, fo))
