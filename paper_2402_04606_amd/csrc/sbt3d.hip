@@ -102,25 +102,40 @@ __device__ __forceinline__ long long source(const Offsets &o, long long c, int i
   return pull ? c + o.ox[1 - E3X[i]] + o.oy[1 - E3Y[i]] + o.oz[1 - E3Z[i]] : c;
 }
 
-// The pulled population of direction i at cell c (plane z).  With walls
-// across z, a source below z = 0 or above z = nz - 1 is replaced by half-way
-// bounce-back of the opposite population o of the same cell with the
-// moving-wall term: f_i = f*_o - 6 w_i rho0 (c_o . u_wall).  The term is
-// the same in the deviation frame (w_i = w_o).
-template <int ST, int Q>
-__device__ __forceinline__ auto gather(const Params &p, const typename Store3<ST>::T *src, const Offsets &o,
-                                       long long c, int z, int i, bool pull) {
+// Walls across z: a population whose source lies below z = 0 or above
+// z = nz - 1 is the opposite population o of the same cell bounced back
+// half-way, with the moving-wall term f_i = f*_o - 6 w_i rho0 (c_o . u_wall)
+// (the same in the deviation frame, w_i = w_o).  The choice of address is a
+// select, so the 19 or 27 loads of a thread stay one unbranched batch; the
+// term is applied after them.
+struct WallSide {
+  bool lo, hi;  // the cell's sources below z = 0 / above z = nz - 1 are walls
+};
+
+__device__ __forceinline__ WallSide wall_side(const Params &p, long long c, bool pull) {
+  const int z = (int)(c / ((long long)p.nx * p.ny));
+  WallSide w;
+  w.lo = pull && p.walls && z == 0;
+  w.hi = pull && p.walls && z == p.nz - 1;
+  return w;
+}
+
+__device__ __forceinline__ bool bounced(const WallSide &w, int i) {
+  return (E3Z[i] > 0 && w.lo) || (E3Z[i] < 0 && w.hi);
+}
+
+__device__ __forceinline__ long long gather_index(const Params &p, const Offsets &o, long long c, int i, bool pull,
+                                                  const WallSide &w) {
+  return bounced(w, i) ? (long long)OPP3[i] * p.n + c : (long long)i * p.n + source(o, c, i, pull);
+}
+
+template <int Q>
+__device__ __forceinline__ double wall_term(const Params &p, int i) {
 #pragma clang fp contract(off)
-  using S = Store3<ST>;
-  if (pull && p.walls && ((E3Z[i] > 0 && z == 0) || (E3Z[i] < 0 && z == p.nz - 1))) {
-    const int oi = OPP3[i];
-    const double *u = p.uw[E3Z[i] > 0 ? 0 : 1];
-    const double cu = E3X[oi] * u[0] + E3Y[oi] * u[1] + E3Z[oi] * u[2];
-    const double t = 6.0 * w3<double, Q>(i) * p.rho0 * cu;
-    if constexpr (ST == 0) return S::ld(src[(long long)oi * p.n + c]) - t;
-    else return S::ld(src[(long long)oi * p.n + c]) - (float)t;
-  }
-  return S::ld(src[(long long)i * p.n + source(o, c, i, pull)]);
+  const int oi = OPP3[i];
+  const double *u = p.uw[E3Z[i] > 0 ? 0 : 1];
+  const double cu = E3X[oi] * u[0] + E3Y[oi] * u[1] + E3Z[oi] * u[2];
+  return 6.0 * w3<double, Q>(i) * p.rho0 * cu;
 }
 
 template <int ST, int kQ3>
@@ -134,11 +149,16 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
   const T *src = static_cast<const T *>(src_);
   T *dst = static_cast<T *>(dst_);
   const Offsets o = offsets(p, c);
-  const int z = (int)(c / ((long long)p.nx * p.ny));
+  const WallSide ws = wall_side(p, c, pull);
   if constexpr (ST == 0) {
     double f[kQ3];
 #pragma unroll
-    for (int i = 0; i < kQ3; ++i) f[i] = gather<ST, kQ3>(p, src, o, c, z, i, pull);
+    for (int i = 0; i < kQ3; ++i) f[i] = S::ld(src[gather_index(p, o, c, i, pull, ws)]);
+    if (ws.lo || ws.hi) {
+#pragma unroll
+      for (int i = 0; i < kQ3; ++i)
+        if (bounced(ws, i)) f[i] = f[i] - wall_term<kQ3>(p, i);
+    }
     double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
     for (int i = 0; i < kQ3; ++i) {
@@ -165,7 +185,12 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
     // deviation form d = f - w rho0 (FP32 arithmetic)
     float d[kQ3];
 #pragma unroll
-    for (int i = 0; i < kQ3; ++i) d[i] = gather<ST, kQ3>(p, src, o, c, z, i, pull);
+    for (int i = 0; i < kQ3; ++i) d[i] = S::ld(src[gather_index(p, o, c, i, pull, ws)]);
+    if (ws.lo || ws.hi) {
+#pragma unroll
+      for (int i = 0; i < kQ3; ++i)
+        if (bounced(ws, i)) d[i] = d[i] - (float)wall_term<kQ3>(p, i);
+    }
     float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
     for (int i = 0; i < kQ3; ++i) {
@@ -230,11 +255,13 @@ __global__ __launch_bounds__(kThreads) void read3_kernel(Params p, const void *l
   if (k >= m) return;
   const T *lat = static_cast<const T *>(lat_);
   const Offsets o = offsets(p, c0 + k);
-  const int z = (int)((c0 + k) / ((long long)p.nx * p.ny));
+  const WallSide ws = wall_side(p, c0 + k, pull);
   double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
   for (int i = 0; i < kQ3; ++i) {
-    const double f = (double)gather<ST, kQ3>(p, lat, o, c0 + k, z, i, pull);
+    auto v = S::ld(lat[gather_index(p, o, c0 + k, i, pull, ws)]);
+    if (bounced(ws, i)) v = v - (decltype(v))wall_term<kQ3>(p, i);
+    const double f = (double)v;
     r += f;
     jx += E3X[i] * f;
     jy += E3Y[i] * f;
