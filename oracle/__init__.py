@@ -96,6 +96,7 @@ def lib():
         _lib.orc3_step.argtypes = [C.c_void_p, C.c_int32]
         _lib.orc3_read_fields.argtypes = [C.c_void_p, d, d, d, d]
         _lib.orc3_set_walls.argtypes = [C.c_void_p, C.c_double, d, d]
+        _lib.orc3_set_solid.argtypes = [C.c_void_p, C.POINTER(C.c_uint8), d]
         _lib.orc_num_threads.argtypes = []
     return _lib
 
@@ -404,6 +405,13 @@ class Oracle3Sim:
         if getattr(wl, "walls_z", False):
             ub, ut = (_f64(np.asarray(a, dtype=np.float64)) for a in wl.wall_u)
             lib().orc3_set_walls(h, float(wl.rho0), _dp(ub), _dp(ut))
+        if getattr(wl, "solid", None) is not None:
+            mask, q = wl.solid
+            m = np.ascontiguousarray(mask, dtype=np.uint8)
+            qq = None if q is None else _f64(q)
+            rc = lib().orc3_set_solid(h, m.ctypes.data_as(C.POINTER(C.c_uint8)), None if qq is None else _dp(qq))
+            if rc:
+                raise RuntimeError(f"orc3_set_solid failed: {rc}")
         r, u, v, w = (_f64(a) for a in wl.init(wl.nx, wl.ny, wl.nz))
         lib().orc3_init_fields(h, _dp(r), _dp(u), _dp(v), _dp(w))
 

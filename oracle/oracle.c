@@ -1107,11 +1107,16 @@ static int opposite3(int i) {
     return -1;
 }
 
+struct orc3_sim;
+static double bouzidi3(const struct orc3_sim *s, int x, int y, int z, int i);
+
 struct orc3_sim {
     int nx, ny, nz, q;
     int walls;                /* 1: half-way bounce-back walls below z = 0 and above z = nz - 1 */
     double uw[2][3];          /* bottom and top wall velocities                                  */
     double rho_w;             /* wall density of the moving-wall term                            */
+    uint8_t *solid;           /* solid cells (interpolated bounce-back), or NULL                 */
+    double *sq;               /* [cell][q] wall fraction of link i from a fluid cell toward x + c_i */
     double tau, F[3];
     double *f, *fs;           /* [cell][q], cell = (z ny + y) nx + x */
 };
@@ -1130,9 +1135,25 @@ int orc3_create(int32_t nx, int32_t ny, int32_t nz, int32_t q, double tau, const
     return ORC_OK;
 }
 
+/* The population of direction i that fluid cell (x, y, z) would pull from a
+ * solid neighbour x - c_i: o = opposite(i) at wall fraction q of the link
+ * x -> x + c_o,  q < 1/2: 2q f*_o(x) + (1 - 2q) f*_o(x - c_o);
+ * q >= 1/2: f*_o(x) / (2q) + (2q - 1)/(2q) f*_i(x). */
+static double bouzidi3(const struct orc3_sim *s, int x, int y, int z, int i) {
+    const int nx = s->nx, ny = s->ny, nz = s->nz, Q3 = s->q;
+    int o = opposite3(i);
+    size_t c = ((size_t)z * ny + y) * nx + x;
+    double q = s->sq[c * Q3 + o];
+    if (q < 0.5) {
+        int ux = (x - C3X[o] + nx) % nx, uy = (y - C3Y[o] + ny) % ny, uz = (z - C3Z[o] + nz) % nz;
+        return 2.0 * q * s->fs[c * Q3 + o] + (1.0 - 2.0 * q) * s->fs[(((size_t)uz * ny + uy) * nx + ux) * Q3 + o];
+    }
+    return s->fs[c * Q3 + o] / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * s->fs[c * Q3 + i];
+}
+
 void orc3_destroy(orc3_sim *s) {
     if (!s) return;
-    free(s->f); free(s->fs); free(s);
+    free(s->f); free(s->fs); free(s->solid); free(s->sq); free(s);
 }
 
 int orc3_init_fields(orc3_sim *s, const double *rho, const double *ux, const double *uy, const double *uz) {
@@ -1150,6 +1171,7 @@ int orc3_step(orc3_sim *s, int32_t steps) {
     for (int32_t t = 0; t < steps; ++t) {
 #pragma omp parallel for schedule(static)
         for (size_t c = 0; c < n; ++c) {
+            if (s->solid && s->solid[c]) continue;
             const double *f = s->f + c * Q3;
             double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
             for (int i = 0; i < Q3; ++i) { rho += f[i]; jx += C3X[i] * f[i]; jy += C3Y[i] * f[i]; jz += C3Z[i] * f[i]; }
@@ -1170,7 +1192,15 @@ int orc3_step(orc3_sim *s, int32_t steps) {
                 for (int x = 0; x < nx; ++x)
                     for (int i = 0; i < Q3; ++i) {
                         size_t c = ((size_t)z * ny + y) * nx + x;
+                        if (s->solid && s->solid[c]) continue;
                         int zs = z - C3Z[i];
+                        if (s->solid && !(s->walls && (zs < 0 || zs >= nz))) {
+                            int sx0 = (x - C3X[i] + nx) % nx, sy0 = (y - C3Y[i] + ny) % ny, sz0 = (zs + nz) % nz;
+                            if (s->solid[((size_t)sz0 * ny + sy0) * nx + sx0]) {
+                                s->f[c * Q3 + i] = bouzidi3(s, x, y, z, i);
+                                continue;
+                            }
+                        }
                         if (s->walls && (zs < 0 || zs >= nz)) {
                             int o = opposite3(i);
                             const double *u = s->uw[zs < 0 ? 0 : 1];
@@ -1196,10 +1226,51 @@ int orc3_set_walls(orc3_sim *s, double rho0, const double ub[3], const double ut
     return ORC_OK;
 }
 
+/* Solid cells with the interpolated bounce-back of the 2D solid cells
+ * (Bouzidi, Firdaouss and Lallemand, linear form, resting wall) in 3D.
+ * mask [cell] nonzero = solid; q [cell][q] the wall fraction of the link from
+ * a fluid cell x toward a solid x + c_i (NULL: 1/2), read there only.  A short
+ * link (q < 1/2) whose upstream cell x - c_i is solid or beyond a z wall
+ * takes q = 1/2.  Solid cells are not collided and read out as NaN. */
+int orc3_set_solid(orc3_sim *s, const uint8_t *mask, const double *q) {
+    const int nx = s->nx, ny = s->ny, nz = s->nz, Q3 = s->q;
+    size_t n = (size_t)nx * ny * nz;
+    uint8_t *sm = malloc(n);
+    double *sq = malloc(sizeof(double) * n * Q3);
+    for (size_t c = 0; c < n; ++c) sm[c] = mask[c] ? 1 : 0;
+    for (size_t c = 0; c < n * Q3; ++c) sq[c] = 0.5;
+    for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+            for (int x = 0; x < nx; ++x) {
+                size_t c = ((size_t)z * ny + y) * nx + x;
+                if (sm[c]) continue;
+                for (int i = 1; i < Q3; ++i) {
+                    int az = z + C3Z[i];
+                    if (s->walls && (az < 0 || az >= nz)) continue;
+                    int ax = (x + C3X[i] + nx) % nx, ay = (y + C3Y[i] + ny) % ny;
+                    az = (az + nz) % nz;
+                    if (!sm[((size_t)az * ny + ay) * nx + ax]) continue;
+                    double v = q ? q[c * Q3 + i] : 0.5;
+                    if (!(v > 0.0 && v <= 1.0)) { free(sm); free(sq); return ORC_ERR_ARG; }
+                    int uz = z - C3Z[i];
+                    int ux = (x - C3X[i] + nx) % nx, uy = (y - C3Y[i] + ny) % ny;
+                    int behind_solid = (s->walls && (uz < 0 || uz >= nz)) ||
+                                       sm[((size_t)((uz + nz) % nz) * ny + uy) * nx + ux];
+                    if (v < 0.5 && behind_solid) v = 0.5;
+                    sq[c * Q3 + i] = v;
+                }
+            }
+    free(s->solid); free(s->sq);
+    s->solid = sm;
+    s->sq = sq;
+    return ORC_OK;
+}
+
 /* rho and u = (sum_i c_i f_i + F/2) / rho of every cell (dense arrays). */
 int orc3_read_fields(const orc3_sim *s, double *rho, double *ux, double *uy, double *uz) {
     size_t n = (size_t)s->nx * s->ny * s->nz;
     for (size_t c = 0; c < n; ++c) {
+        if (s->solid && s->solid[c]) { rho[c] = ux[c] = uy[c] = uz[c] = NAN; continue; }
         const double *f = s->f + c * s->q;
         double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
         for (int i = 0; i < s->q; ++i) { r += f[i]; jx += C3X[i] * f[i]; jy += C3Y[i] * f[i]; jz += C3Z[i] * f[i]; }

@@ -136,6 +136,10 @@ int  orc3_step(orc3_sim *s, int32_t steps);
 /* Half-way bounce-back walls below z = 0 and above z = nz - 1 (velocities
  * ub, ut; NULL = at rest; wall density rho0) instead of the periodic z faces. */
 int  orc3_set_walls(orc3_sim *s, double rho0, const double ub[3], const double ut[3]);
+/* Solid cells with interpolated bounce-back (mask [cell], q [cell][q] wall
+ * fraction of the link from a fluid cell toward a solid x + c_i, NULL = 1/2).
+ * After orc3_set_walls when both are used. */
+int  orc3_set_solid(orc3_sim *s, const uint8_t *mask, const double *q);
 int  orc3_read_fields(const orc3_sim *s, double *rho, double *ux, double *uy, double *uz);
 
 #ifdef __cplusplus

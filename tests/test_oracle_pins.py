@@ -860,3 +860,33 @@ def test_3d_walls_give_exact_channel_flows(orc, q):
     s.step(8000)
     _, u, _, _ = s.fields()
     assert np.abs(u[:, 0, 0] - 0.01 * z / nz).max() < 1e-9
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_3d_solid_cells_channel_and_sphere(orc, q):
+    """3D solid cells with interpolated bounce-back: half-way links give the
+    exact channel at the magic tau; walls at fractions 0.3 / 0.7 converge to
+    the parabola at second order; a centred sphere in a box driven along x
+    keeps the flow mirror-symmetric in y and z, and reads NaN inside."""
+    def err(nz, qb, qt, tau):
+        wl = W.solid_channel3(nz=nz, q_bottom=qb, q_top=qt, tau=tau, lattice=q)
+        s = orc.Oracle3Sim(wl)
+        s.step(int(3 * nz * nz / wl.meta["nu"]))
+        _, u, _, w = s.fields()
+        z = np.arange(nz) + 0.5
+        ua = wl.meta["g"] / (2 * wl.meta["nu"]) * (z - wl.meta["z_b"]) * (wl.meta["z_t"] - z)
+        m = ~np.isnan(u[:, 0, 0])
+        assert m.sum() == nz - 2 and np.abs(w[m]).max() < 1e-13
+        return np.abs(u[m, 0, 0] - ua[m]).max() / ua[m].max()
+
+    assert err(20, 0.5, 0.5, 0.5 + math.sqrt(3) / 4) < 1e-9
+    e = [err(nz, 0.3, 0.7, 0.8) for nz in (12, 22, 42)]
+    assert e[2] < 1e-3 and e[0] / e[1] > 3.5 and e[1] / e[2] > 3.5, e
+    wl = W.sphere3(24, r=4.0, lattice=q)
+    s = orc.Oracle3Sim(wl)
+    s.step(150)
+    _, u, v, w = s.fields()
+    assert np.isnan(u[12, 12, 12]) and np.nanmax(np.abs(v)) > 1e-7
+    # mirror about the centre plane y = 12 (cell y <-> 23 - y), and z likewise
+    for a, b, sgn in ((u, u[:, ::-1, :], 1), (v, v[:, ::-1, :], -1), (u, u[::-1], 1), (w, w[::-1], -1)):
+        assert np.nanmax(np.abs(a - sgn * b)) < 1e-12 * np.nanmax(np.abs(u))

@@ -502,6 +502,9 @@ class Workload3:
     lattice: int = 19                 # D3Q19 or D3Q27
     walls_z: bool = False             # half-way bounce-back walls across z instead of periodic
     wall_u: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))   # bottom, top wall velocities
+    # solid cells with interpolated bounce-back: (mask [nz, ny, nx] uint8,
+    # q [nz, ny, nx, lattice] wall fraction of link i toward a solid neighbour, or None)
+    solid: Optional[tuple] = None
     init: Optional[Callable] = None   # init(nx, ny, nz, z0=0, z1=nz) -> (rho, ux, uy, uz), each [z1 - z0, ny, nx]
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -564,3 +567,67 @@ def channel3(n=8, nz=16, tau=0.5 + math.sqrt(3) / 4, g=1e-6, lid=0.0, lattice=19
     return Workload3(name=f"channel3_{n}x{n}x{nz}", nx=n, ny=n, nz=nz, tau=tau, fext=(g, 0.0, 0.0),
                      lattice=lattice, walls_z=True, wall_u=((0.0, 0.0, 0.0), (lid, 0.0, 0.0)), init=init,
                      meta=dict(g=g, lid=lid, nu=(tau - 0.5) / 3.0))
+
+
+_C3X = (0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1)
+_C3Y = (0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, 1, -1, -1, 1, 1, -1, -1)
+_C3Z = (0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1)
+
+
+def solid_sphere3(nx, ny, nz, centre, r, lattice=19):
+    """Cells whose centres lie inside the sphere are solid; q is the fraction
+    of the link from a fluid cell centre along c_i at which it meets the
+    sphere (3D counterpart of solid_circle)."""
+    zz, yy, xx = np.mgrid[0:nz, 0:ny, 0:nx]
+    px, py, pz = xx + 0.5 - centre[0], yy + 0.5 - centre[1], zz + 0.5 - centre[2]
+    mask = (px * px + py * py + pz * pz < r * r).astype(np.uint8)
+    q = np.full((nz, ny, nx, lattice), 0.5)
+    for i in range(1, lattice):
+        dx, dy, dz = _C3X[i], _C3Y[i], _C3Z[i]
+        a = dx * dx + dy * dy + dz * dz
+        b = 2 * (dx * px + dy * py + dz * pz)
+        c = px * px + py * py + pz * pz - r * r
+        t = (-b - np.sqrt(np.maximum(b * b - 4 * a * c, 0.0))) / (2 * a)
+        nb = np.roll(mask, (-dz, -dy, -dx), axis=(0, 1, 2))
+        hit = (mask == 0) & (nb == 1)
+        q[..., i] = np.where(hit, np.clip(t, 1e-6, 1.0), 0.5)
+    return mask, q
+
+
+def solid_channel3(n=4, nz=20, tau=0.5 + math.sqrt(3) / 4, g=1e-6, q_bottom=0.5, q_top=0.5, lattice=19):
+    """Periodic box whose planes z = 0 and 1 are solid: body-forced flow
+    between walls at q_bottom below the centre of plane 2 and q_top above the
+    centre of plane nz - 1 (3D counterpart of ibb_channel)."""
+    mask = np.zeros((nz, n, n), dtype=np.uint8)
+    mask[0:2] = 1
+    q = np.full((nz, n, n, lattice), 0.5)
+    for i in range(1, lattice):
+        if _C3Z[i] < 0:
+            q[2, :, :, i] = q_bottom
+        if _C3Z[i] > 0:
+            q[nz - 1, :, :, i] = q_top
+
+    def init(nx, ny, nz_, z0=0, z1=None):
+        z1 = nz_ if z1 is None else z1
+        m = z1 - z0
+        zero = np.zeros((m, ny, nx))
+        return np.ones((m, ny, nx)), zero, zero.copy(), zero.copy()
+
+    return Workload3(name=f"solid_channel3_q{q_bottom}_{q_top}", nx=n, ny=n, nz=nz, tau=tau, fext=(g, 0.0, 0.0),
+                     lattice=lattice, solid=(mask, q), init=init,
+                     meta=dict(g=g, nu=(tau - 0.5) / 3.0, z_b=2.5 - q_bottom, z_t=nz - 0.5 + q_top))
+
+
+def sphere3(n=32, r=5.0, tau=0.8, g=2e-6, lattice=19):
+    """A solid sphere at the centre of a periodic box driven by a body force
+    along x (a periodic array of spheres)."""
+    mask, q = solid_sphere3(n, n, n, (n / 2, n / 2, n / 2), r, lattice)
+
+    def init(nx, ny, nz_, z0=0, z1=None):
+        z1 = nz_ if z1 is None else z1
+        m = z1 - z0
+        zero = np.zeros((m, ny, nx))
+        return np.ones((m, ny, nx)), zero, zero.copy(), zero.copy()
+
+    return Workload3(name=f"sphere3_{n}_r{r}", nx=n, ny=n, nz=n, tau=tau, fext=(g, 0.0, 0.0), lattice=lattice,
+                     solid=(mask, q), init=init, meta=dict(g=g, r=r))
