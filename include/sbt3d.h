@@ -7,7 +7,14 @@
  * term and the half-force velocity, then streaming f(x + c_i, i) = f*(x, i)
  * across periodic faces (or, across z, half-way bounce-back walls with the
  * moving-wall term f_i = f*_o - 6 w_i rho0 (c_o . u_wall), o = opposite(i),
- * as the 2D walls).  D3Q19: rest (w = 1/3), 6 axis (1/18) and 12 edge
+ * as the 2D walls).  Solid cells (solid_mask) take the interpolated
+ * bounce-back of the 2D solid cells (linear Bouzidi form, resting wall): a
+ * fluid cell pulls direction i from a solid x - c_i as
+ *   q <  1/2: 2q f*_o(x) + (1 - 2q) f*_o(x - c_o),
+ *   q >= 1/2: f*_o(x) / (2q) + (2q - 1)/(2q) f*_i(x),  o = opposite(i),
+ * q = 1/2 where a short link has no fluid cell behind it; solid cells are
+ * not collided and read out as NaN.  They add a 4-byte code per cell to
+ * each step's reads.  D3Q19: rest (w = 1/3), 6 axis (1/18) and 12 edge
  * (1/36) velocities; D3Q27 adds the 8 corners (rest 8/27, axis 2/27, edge
  * 1/54, corner 1/216); c_s^2 = 1/3 for both.  Direction order: rest,
  * +x -x +y -y +z -z, the edges (+-1, +-1, 0), (+-1, 0, +-1), (0, +-1, +-1),
@@ -45,6 +52,11 @@ typedef struct {
     int32_t walls_z;               /* 0: periodic in z; 1: half-way bounce-back
                                       walls below z = 0 and above z = nz - 1         */
     double wall_u[2][3];           /* bottom and top wall velocities (walls_z = 1)   */
+    const uint8_t *solid_mask;     /* solid cells [nz][ny][nx] (nonzero = solid), or
+                                      NULL; read during sbt3_plan / sbt3_create      */
+    const double *solid_q;         /* [nz][ny][nx][Q] wall fraction of the link from a
+                                      fluid cell x toward a solid x + c_i (0 < q <= 1,
+                                      read there only); NULL = 1/2 everywhere         */
 } sbt3_desc;
 
 /* Device bytes sbt3_create needs.  Host only.  Errors: SBT_ERR_ARG. */

@@ -55,7 +55,8 @@ class Solid(C.Structure):
 class Desc3(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
                 ("rho0", C.c_double), ("fext", C.c_double * 3), ("storage", C.c_int32),
-                ("lattice", C.c_int32), ("walls_z", C.c_int32), ("wall_u", (C.c_double * 3) * 2)]
+                ("lattice", C.c_int32), ("walls_z", C.c_int32), ("wall_u", (C.c_double * 3) * 2),
+                ("solid_mask", C.POINTER(C.c_uint8)), ("solid_q", C.POINTER(C.c_double))]
 
 
 class CaseDesc(C.Structure):
@@ -412,6 +413,16 @@ class Sim3:
         d.storage = self.storage
         d.lattice = getattr(wl, "lattice", 19)
         d.walls_z = 1 if getattr(wl, "walls_z", False) else 0
+        self._solid_keep = []
+        if getattr(wl, "solid", None) is not None:
+            mask, q = wl.solid
+            m = np.ascontiguousarray(mask, dtype=np.uint8)
+            self._solid_keep.append(m)
+            d.solid_mask = m.ctypes.data_as(C.POINTER(C.c_uint8))
+            if q is not None:
+                qq = np.ascontiguousarray(q, dtype=np.float64)
+                self._solid_keep.append(qq)
+                d.solid_q = _dp(qq)
         for a, u in enumerate(getattr(wl, "wall_u", ((0.0,) * 3,) * 2)):
             for k in range(3):
                 d.wall_u[a][k] = u[k]

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "sbt3d.h"
 #include "sbt_internal.h"
@@ -66,8 +67,13 @@ template <> struct Store3<3> {  // bf16, round to nearest even
   }
 };
 
+constexpr uint32_t kSolidBit = 1u << 31;  // solid-record bits: the cell itself is solid
+
 struct Params {
   int nx, ny, nz, walls;
+  const int32_t *scode;        // solid cells: per cell 0, or 1 + its record; null without solids
+  const uint32_t *rbits;       // per record: bit i = the source of direction i is solid; kSolidBit
+  const double *rq;            // per record [Q]: wall fraction of the link of pulled direction i
   long long n;
   double tau, pre, rho0, F[3];
   double uw[2][3];             // bottom and top wall velocities (walls across z)
@@ -129,6 +135,30 @@ __device__ __forceinline__ long long gather_index(const Params &p, const Offsets
   return bounced(w, i) ? (long long)OPP3[i] * p.n + c : (long long)i * p.n + source(o, c, i, pull);
 }
 
+// Interpolated bounce-back (linear Bouzidi form, resting wall) of pulled
+// direction i, whose source x - c_i is solid: o = opposite(i) at wall
+// fraction q of the link x -> x + c_o,
+//   q <  1/2:  2q f*_o(x) + (1 - 2q) f*_o(x + c_i)
+//   q >= 1/2:  f*_o(x) / (2q) + (2q - 1)/(2q) f*_i(x)
+// (affine with weights summing to 1 and w_o = w_i, so it holds for the
+// deviation storage forms too).
+template <int ST, int Q>
+__device__ __forceinline__ auto bouzidi3(const Params &p, const typename Store3<ST>::T *src, const Offsets &o,
+                                         long long c, int rec, int i) {
+#pragma clang fp contract(off)
+  using S = Store3<ST>;
+  using C = decltype(S::ld(src[0]));
+  const double q = p.rq[(long long)rec * Q + i];
+  const int oi = OPP3[i];
+  const C fo = S::ld(src[(long long)oi * p.n + c]);
+  if (q < 0.5) {
+    const C fu = S::ld(src[(long long)oi * p.n + source(o, c, oi, true)]);
+    return C(2.0 * q) * fo + C(1.0 - 2.0 * q) * fu;
+  }
+  const C fi = S::ld(src[(long long)i * p.n + c]);
+  return fo / C(2.0 * q) + C((2.0 * q - 1.0) / (2.0 * q)) * fi;
+}
+
 template <int Q>
 __device__ __forceinline__ double wall_term(const Params &p, int i) {
 #pragma clang fp contract(off)
@@ -150,6 +180,10 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
   T *dst = static_cast<T *>(dst_);
   const Offsets o = offsets(p, c);
   const WallSide ws = wall_side(p, c, pull);
+  const int rec = p.scode ? p.scode[c] - 1 : -1;
+  const uint32_t sbits = rec >= 0 ? p.rbits[rec] : 0u;
+  if (sbits & kSolidBit) return;  // solid cells are not collided
+  const bool bz = pull && sbits != 0u;
   if constexpr (ST == 0) {
     double f[kQ3];
 #pragma unroll
@@ -158,6 +192,11 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
 #pragma unroll
       for (int i = 0; i < kQ3; ++i)
         if (bounced(ws, i)) f[i] = f[i] - wall_term<kQ3>(p, i);
+    }
+    if (bz) {
+#pragma unroll
+      for (int i = 1; i < kQ3; ++i)
+        if (sbits & (1u << i)) f[i] = bouzidi3<ST, kQ3>(p, src, o, c, rec, i);
     }
     double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
@@ -190,6 +229,11 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
 #pragma unroll
       for (int i = 0; i < kQ3; ++i)
         if (bounced(ws, i)) d[i] = d[i] - (float)wall_term<kQ3>(p, i);
+    }
+    if (bz) {
+#pragma unroll
+      for (int i = 1; i < kQ3; ++i)
+        if (sbits & (1u << i)) d[i] = bouzidi3<ST, kQ3>(p, src, o, c, rec, i);
     }
     float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
@@ -256,11 +300,18 @@ __global__ __launch_bounds__(kThreads) void read3_kernel(Params p, const void *l
   const T *lat = static_cast<const T *>(lat_);
   const Offsets o = offsets(p, c0 + k);
   const WallSide ws = wall_side(p, c0 + k, pull);
+  const int rec = p.scode ? p.scode[c0 + k] - 1 : -1;
+  const uint32_t sbits = rec >= 0 ? p.rbits[rec] : 0u;
+  if (sbits & kSolidBit) {
+    for (int q = 0; q < 4; ++q) fld[q * m + k] = __builtin_nan("");
+    return;
+  }
   double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
   for (int i = 0; i < kQ3; ++i) {
     auto v = S::ld(lat[gather_index(p, o, c0 + k, i, pull, ws)]);
     if (bounced(ws, i)) v = v - (decltype(v))wall_term<kQ3>(p, i);
+    if (pull && (sbits & (1u << i))) v = bouzidi3<ST, kQ3>(p, lat, o, c0 + k, rec, i);
     const double f = (double)v;
     r += f;
     jx += E3X[i] * f;
@@ -292,6 +343,7 @@ struct sbt3_ctx {
   int cur = 0;
   bool post = false;  // the lattices hold post-collision populations (a step has run)
   hipStream_t stream;
+  long long n_records = 0;
 };
 
 namespace {
@@ -310,11 +362,75 @@ sbt_status check_desc(const sbt3_desc *d) {
   return SBT_OK;
 }
 
-size_t plan_bytes(const sbt3_desc *d, long long *stage) {
+constexpr int H3X[27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+constexpr int H3Y[27] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, 1, -1, -1, 1, 1, -1, -1};
+constexpr int H3Z[27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 1, 1, 1, 1, -1, -1, -1, -1};
+constexpr int HOPP[27] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15, 26, 25, 24, 23, 22, 21, 20, 19};
+
+// Solid records of a descriptor's mask: code[c] = 0 for a plain cell, else
+// 1 + record; a record per solid cell (kSolidBit) and per fluid cell with a
+// solid source.  The wall fraction of pulled direction i is the caller's
+// q of the link toward the wall (direction opposite(i)); a short link with
+// no fluid cell behind it takes 1/2.  Counts only when code is null.
+sbt_status solid_records(const sbt3_desc *d, std::vector<int32_t> *code, std::vector<uint32_t> *bits,
+                         std::vector<double> *rq, long long *count) {
+  const int nx = d->nx, ny = d->ny, nz = d->nz, Q = d->lattice;
+  const long long n = (long long)nx * ny * nz;
+  auto cell = [&](int x, int y, int z, long long &out) -> bool {
+    if (z < 0 || z >= nz) {
+      if (d->walls_z) return false;
+      z = (z + nz) % nz;
+    }
+    x = (x + nx) % nx;
+    y = (y + ny) % ny;
+    out = ((long long)z * ny + y) * nx + x;
+    return true;
+  };
+  long long r = 0;
+  if (code) code->assign(n, 0);
+  for (int z = 0; z < nz; ++z)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        const long long c = ((long long)z * ny + y) * nx + x;
+        uint32_t b = 0;
+        double qv[27];
+        if (d->solid_mask[c]) {
+          b = kSolidBit;
+        } else {
+          for (int i = 1; i < Q; ++i) {
+            long long s;
+            if (!cell(x - H3X[i], y - H3Y[i], z - H3Z[i], s) || !d->solid_mask[s]) continue;
+            const int o = HOPP[i];
+            double v = d->solid_q ? d->solid_q[c * Q + o] : 0.5;
+            if (!(v > 0.0 && v <= 1.0)) return sbt_set_error(SBT_ERR_ARG, "wall fractions must lie in (0, 1]");
+            long long u;
+            if (v < 0.5 && (!cell(x + H3X[i], y + H3Y[i], z + H3Z[i], u) || d->solid_mask[u])) v = 0.5;
+            b |= 1u << i;
+            qv[i] = v;
+          }
+        }
+        if (!b) continue;
+        if (code) {
+          (*code)[c] = (int32_t)(r + 1);
+          bits->push_back(b);
+          for (int i = 0; i < Q; ++i) rq->push_back((b & (1u << i)) && i > 0 ? qv[i] : 0.5);
+        }
+        ++r;
+      }
+  if (r >= (1ll << 31) - 1) return sbt_set_error(SBT_ERR_ARG, "too many solid records");
+  *count = r;
+  return SBT_OK;
+}
+
+size_t plan_bytes(const sbt3_desc *d, long long *stage, long long records) {
   const long long n = (long long)d->nx * d->ny * d->nz;
   *stage = std::min<long long>(n, std::max<long long>(kStageCells, (long long)d->nx * d->ny));
-  return 2 * align256((size_t)n * d->lattice * storage_bytes3(d->storage)) + align256((size_t)*stage * 4 * sizeof(double)) +
-         256;
+  size_t b = 2 * align256((size_t)n * d->lattice * storage_bytes3(d->storage)) +
+             align256((size_t)*stage * 4 * sizeof(double)) + 256;
+  if (d->solid_mask)
+    b += align256((size_t)n * sizeof(int32_t)) + align256((size_t)records * sizeof(uint32_t)) +
+         align256((size_t)records * d->lattice * sizeof(double));
+  return b;
 }
 
 #define HIP3(x)                                                                   \
@@ -355,8 +471,12 @@ sbt_status sbt3_plan(const sbt3_desc *desc, size_t *device_bytes) {
   sbt_status st = check_desc(desc);
   if (st) return st;
   if (!device_bytes) return sbt_set_error(SBT_ERR_ARG, "null output");
-  long long stage;
-  *device_bytes = plan_bytes(desc, &stage);
+  long long stage, records = 0;
+  if (desc->solid_mask) {
+    st = solid_records(desc, nullptr, nullptr, nullptr, &records);
+    if (st) return st;
+  }
+  *device_bytes = plan_bytes(desc, &stage, records);
   return SBT_OK;
 }
 
@@ -365,8 +485,15 @@ sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, vo
   if (st) return st;
   if (!out) return sbt_set_error(SBT_ERR_ARG, "null output");
   *out = nullptr;
-  long long stage;
-  const size_t need = plan_bytes(desc, &stage);
+  long long stage, records = 0;
+  std::vector<int32_t> code;
+  std::vector<uint32_t> bits;
+  std::vector<double> rq;
+  if (desc->solid_mask) {
+    st = solid_records(desc, &code, &bits, &rq, &records);
+    if (st) return st;
+  }
+  const size_t need = plan_bytes(desc, &stage, records);
   if (!device_buf || bytes < need) return sbt_set_error(SBT_ERR_BUFSIZE, "device buffer smaller than planned");
   if ((uintptr_t)device_buf & 255) return sbt_set_error(SBT_ERR_ARG, "device buffer must be 256-byte aligned");
   sbt3_ctx *X = new sbt3_ctx();
@@ -397,6 +524,31 @@ sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, vo
   X->err = reinterpret_cast<int *>(b + 2 * lat + align256((size_t)stage * 4 * sizeof(double)));
   X->stage_cells = stage;
   X->stream = static_cast<hipStream_t>(hip_stream);
+  X->d.solid_mask = nullptr;  // borrowed for this call only
+  X->d.solid_q = nullptr;
+  p.scode = nullptr;
+  p.rbits = nullptr;
+  p.rq = nullptr;
+  if (desc->solid_mask) {
+    char *sb = b + 2 * lat + align256((size_t)stage * 4 * sizeof(double)) + 256;
+    int32_t *dcode = reinterpret_cast<int32_t *>(sb);
+    uint32_t *dbits = reinterpret_cast<uint32_t *>(sb + align256((size_t)p.n * sizeof(int32_t)));
+    double *dq = reinterpret_cast<double *>(sb + align256((size_t)p.n * sizeof(int32_t)) +
+                                            align256((size_t)records * sizeof(uint32_t)));
+    bool ok = hipMemcpy(dcode, code.data(), sizeof(int32_t) * code.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (records > 0) {
+      ok &= hipMemcpy(dbits, bits.data(), sizeof(uint32_t) * bits.size(), hipMemcpyHostToDevice) == hipSuccess;
+      ok &= hipMemcpy(dq, rq.data(), sizeof(double) * rq.size(), hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (!ok) {
+      delete X;
+      return sbt_set_error(SBT_ERR_DEVICE, "solid table upload");
+    }
+    p.scode = dcode;
+    p.rbits = dbits;
+    p.rq = dq;
+    X->n_records = records;
+  }
   if (hipMemsetAsync(X->err, 0, sizeof(int), X->stream) != hipSuccess) {
     delete X;
     return sbt_set_error(SBT_ERR_DEVICE, "error flag clear");
