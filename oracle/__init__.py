@@ -97,6 +97,8 @@ def lib():
         _lib.orc3_read_fields.argtypes = [C.c_void_p, d, d, d, d]
         _lib.orc3_set_walls.argtypes = [C.c_void_p, C.c_double, d, d]
         _lib.orc3_set_solid.argtypes = [C.c_void_p, C.POINTER(C.c_uint8), d]
+        _lib.orc3_set_body.argtypes = [C.c_void_p, C.c_int32, d, d, d, d, C.c_int32]
+        _lib.orc3_body_force.argtypes = [C.c_void_p, d]
         _lib.orc_num_threads.argtypes = []
     return _lib
 
@@ -412,6 +414,13 @@ class Oracle3Sim:
             rc = lib().orc3_set_solid(h, m.ctypes.data_as(C.POINTER(C.c_uint8)), None if qq is None else _dp(qq))
             if rc:
                 raise RuntimeError(f"orc3_set_solid failed: {rc}")
+        if getattr(wl, "body", None) is not None:
+            X, Y, Z, dA, iters = wl.body
+            X, Y, Z, dA = (_f64(a) for a in (X, Y, Z, dA))
+            self._body = (X, Y, Z, dA)
+            rc = lib().orc3_set_body(h, len(X), _dp(X), _dp(Y), _dp(Z), _dp(dA), int(iters))
+            if rc:
+                raise RuntimeError(f"orc3_set_body failed: {rc}")
         r, u, v, w = (_f64(a) for a in wl.init(wl.nx, wl.ny, wl.nz))
         lib().orc3_init_fields(h, _dp(r), _dp(u), _dp(v), _dp(w))
 
@@ -422,6 +431,12 @@ class Oracle3Sim:
 
     def step(self, n=1):
         lib().orc3_step(self._h, int(n))
+
+    def body_force(self):
+        """F_s = -sum_j F_j dA_j of the last step (3 components)."""
+        out = np.zeros(3)
+        lib().orc3_body_force(self._h, _dp(out))
+        return out
 
     def fields(self):
         shape = (self.wl.nz, self.wl.ny, self.wl.nx)

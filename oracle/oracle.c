@@ -1117,6 +1117,10 @@ struct orc3_sim {
     double rho_w;             /* wall density of the moving-wall term                            */
     uint8_t *solid;           /* solid cells (interpolated bounce-back), or NULL                 */
     double *sq;               /* [cell][q] wall fraction of link i from a fluid cell toward x + c_i */
+    int nm, iters;            /* fixed immersed body: markers, N_F                               */
+    double *bx, *by, *bz, *bdA;
+    double *Fb;               /* [3][cell] IBM force density of the current step                 */
+    double fsb[3];            /* body force F_s of the last step                                 */
     double tau, F[3];
     double *f, *fs;           /* [cell][q], cell = (z ny + y) nx + x */
 };
@@ -1153,7 +1157,8 @@ static double bouzidi3(const struct orc3_sim *s, int x, int y, int z, int i) {
 
 void orc3_destroy(orc3_sim *s) {
     if (!s) return;
-    free(s->f); free(s->fs); free(s->solid); free(s->sq); free(s);
+    free(s->f); free(s->fs); free(s->solid); free(s->sq);
+    free(s->bx); free(s->Fb); free(s);
 }
 
 int orc3_init_fields(orc3_sim *s, const double *rho, const double *ux, const double *uy, const double *uz) {
@@ -1164,14 +1169,116 @@ int orc3_init_fields(orc3_sim *s, const double *rho, const double *ux, const dou
 
 /* One step: BGK + Guo forcing with the half-force velocity (Eqs. (2)-(3),
  * (6)-(8) in 3D), then periodic streaming f(x, i) <- f*(x - c_i, i). */
+/* Sec. 2.2 in 3D for a fixed body (desired velocity 0): the multi-direct
+ * forcing loop on the current pre-collision state, with the Peskin kernel of
+ * Eq. (14) in each axis (taps z outer, y, x inner; weight phi_x (phi_y phi_z)).
+ * Per iteration: U_j and rho_j interpolated, g_j = 2 rho_j (0 - U_j),
+ * spread in marker order as g_j w dA_j, F += dF and u += dF / (2 rho); then
+ * F_s = -sum_j F_j dA_j.  Fills s->Fb and s->fs. */
+static void mdf3(orc3_sim *s) {
+    const int nx = s->nx, ny = s->ny, nz = s->nz, Q3 = s->q, nm = s->nm;
+    const size_t n = (size_t)nx * ny * nz;
+    double *rho = malloc(sizeof(double) * n * 7), *u = rho + n, *dF = rho + 4 * n;
+    for (size_t c = 0; c < n; ++c) {
+        const double *f = s->f + c * Q3;
+        double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int i = 0; i < Q3; ++i) { r += f[i]; jx += C3X[i] * f[i]; jy += C3Y[i] * f[i]; jz += C3Z[i] * f[i]; }
+        rho[c] = r;
+        u[c] = (jx + 0.5 * s->F[0]) / r;
+        u[n + c] = (jy + 0.5 * s->F[1]) / r;
+        u[2 * n + c] = (jz + 0.5 * s->F[2]) / r;
+    }
+    memset(s->Fb, 0, sizeof(double) * 3 * n);
+    double *g = malloc(sizeof(double) * nm * 6), *ft = g + 3 * nm;
+    for (int j = 0; j < 3 * nm; ++j) ft[j] = 0.0;
+    for (int it = 0; it < s->iters; ++it) {
+        for (int j = 0; j < nm; ++j) {
+            int i0 = tap0(s->bx[j]), j0 = tap0(s->by[j]), k0 = tap0(s->bz[j]);
+            double U[3] = {0.0, 0.0, 0.0}, R = 0.0;
+            for (int cc = 0; cc < 4; ++cc) {
+                double pz = orc_phi(k0 + cc + 0.5 - s->bz[j]);
+                int zz = (k0 + cc + nz) % nz;
+                for (int b = 0; b < 4; ++b) {
+                    double pyz = orc_phi(j0 + b + 0.5 - s->by[j]) * pz;
+                    int yy = (j0 + b + ny) % ny;
+                    for (int a = 0; a < 4; ++a) {
+                        double w = orc_phi(i0 + a + 0.5 - s->bx[j]) * pyz;
+                        size_t c = ((size_t)zz * ny + yy) * nx + (i0 + a + nx) % nx;
+                        U[0] += u[c] * w;
+                        U[1] += u[n + c] * w;
+                        U[2] += u[2 * n + c] * w;
+                        R += rho[c] * w;
+                    }
+                }
+            }
+            for (int k = 0; k < 3; ++k) {
+                g[3 * j + k] = 2.0 * R * (0.0 - U[k]);
+                ft[3 * j + k] += g[3 * j + k];
+            }
+        }
+        memset(dF, 0, sizeof(double) * 3 * n);
+        for (int j = 0; j < nm; ++j) {
+            int i0 = tap0(s->bx[j]), j0 = tap0(s->by[j]), k0 = tap0(s->bz[j]);
+            for (int cc = 0; cc < 4; ++cc) {
+                double pz = orc_phi(k0 + cc + 0.5 - s->bz[j]);
+                int zz = (k0 + cc + nz) % nz;
+                for (int b = 0; b < 4; ++b) {
+                    double pyz = orc_phi(j0 + b + 0.5 - s->by[j]) * pz;
+                    int yy = (j0 + b + ny) % ny;
+                    for (int a = 0; a < 4; ++a) {
+                        double w = orc_phi(i0 + a + 0.5 - s->bx[j]) * pyz;
+                        size_t c = ((size_t)zz * ny + yy) * nx + (i0 + a + nx) % nx;
+                        for (int k = 0; k < 3; ++k) dF[k * n + c] += g[3 * j + k] * w * s->bdA[j];
+                    }
+                }
+            }
+        }
+        for (size_t c = 0; c < n; ++c) {
+            if (dF[c] == 0.0 && dF[n + c] == 0.0 && dF[2 * n + c] == 0.0) continue;
+            for (int k = 0; k < 3; ++k) {
+                s->Fb[k * n + c] += dF[k * n + c];
+                u[k * n + c] += dF[k * n + c] / (2.0 * rho[c]);
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        double t = 0.0;
+        for (int j = 0; j < nm; ++j) t -= ft[3 * j + k] * s->bdA[j];
+        s->fsb[k] = t;
+    }
+    free(g); free(rho);
+}
+
+int orc3_set_body(orc3_sim *s, int32_t n, const double *X, const double *Y, const double *Z, const double *dA,
+                  int32_t iters) {
+    if (n <= 0 || iters < 0) return ORC_ERR_ARG;
+    free(s->bx); free(s->Fb);
+    s->bx = malloc(sizeof(double) * 4 * n);
+    s->by = s->bx + n; s->bz = s->bx + 2 * n; s->bdA = s->bx + 3 * n;
+    memcpy(s->bx, X, sizeof(double) * n); memcpy(s->by, Y, sizeof(double) * n);
+    memcpy(s->bz, Z, sizeof(double) * n); memcpy(s->bdA, dA, sizeof(double) * n);
+    s->nm = n;
+    s->iters = iters;
+    s->Fb = calloc((size_t)3 * s->nx * s->ny * s->nz, sizeof(double));
+    return ORC_OK;
+}
+
+int orc3_body_force(const orc3_sim *s, double out[3]) {
+    for (int k = 0; k < 3; ++k) out[k] = s->fsb[k];
+    return ORC_OK;
+}
+
 int orc3_step(orc3_sim *s, int32_t steps) {
     const int nx = s->nx, ny = s->ny, nz = s->nz, Q3 = s->q;
     const size_t n = (size_t)nx * ny * nz;
-    const double tau = s->tau, Fx = s->F[0], Fy = s->F[1], Fz = s->F[2];
+    const double tau = s->tau;
     for (int32_t t = 0; t < steps; ++t) {
+        if (s->nm > 0) mdf3(s);
 #pragma omp parallel for schedule(static)
         for (size_t c = 0; c < n; ++c) {
             if (s->solid && s->solid[c]) continue;
+            double Fx = s->F[0], Fy = s->F[1], Fz = s->F[2];
+            if (s->nm > 0) { Fx += s->Fb[c]; Fy += s->Fb[n + c]; Fz += s->Fb[2 * n + c]; }
             const double *f = s->f + c * Q3;
             double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
             for (int i = 0; i < Q3; ++i) { rho += f[i]; jx += C3X[i] * f[i]; jy += C3Y[i] * f[i]; jz += C3Z[i] * f[i]; }

@@ -140,6 +140,12 @@ int  orc3_set_walls(orc3_sim *s, double rho0, const double ub[3], const double u
  * fraction of the link from a fluid cell toward a solid x + c_i, NULL = 1/2).
  * After orc3_set_walls when both are used. */
 int  orc3_set_solid(orc3_sim *s, const uint8_t *mask, const double *q);
+/* A fixed immersed body (Sec. 2.2 in 3D): n markers X, Y, Z (cells), surface
+ * elements dA, N_F iterations of the forcing loop before every collision. */
+int  orc3_set_body(orc3_sim *s, int32_t n, const double *X, const double *Y, const double *Z,
+                   const double *dA, int32_t iters);
+/* F_s = -sum_j F_j dA_j of the last step. */
+int  orc3_body_force(const orc3_sim *s, double out[3]);
 int  orc3_read_fields(const orc3_sim *s, double *rho, double *ux, double *uy, double *uz);
 
 #ifdef __cplusplus

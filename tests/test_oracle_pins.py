@@ -890,3 +890,24 @@ def test_3d_solid_cells_channel_and_sphere(orc, q):
     # mirror about the centre plane y = 12 (cell y <-> 23 - y), and z likewise
     for a, b, sgn in ((u, u[:, ::-1, :], 1), (v, v[:, ::-1, :], -1), (u, u[::-1], 1), (w, w[::-1], -1)):
         assert np.nanmax(np.abs(a - sgn * b)) < 1e-12 * np.nanmax(np.abs(u))
+
+
+def test_3d_ibm_sphere_momentum_balance_and_stokes_drag(orc):
+    """Sec. 2.2 in 3D: a fixed IBM sphere (r = 4) in a periodic box forced
+    along x.  At steady state the body force F_s balances the force on all
+    the fluid, g n^3, exactly (momentum balance; the cross components
+    vanish); the drag factor F / (6 pi mu r U) sits above Hasimoto's
+    periodic-array value K(c) (1.83 here) by the diffuse interface's larger
+    effective radius, within [1.0, 1.6] x K."""
+    n, g, r = 24, 1e-5, 4.0
+    wl = W.ibm_sphere3(n, r=r, tau=1.0, g=g)
+    s = orc.Oracle3Sim(wl)
+    s.step(4000)
+    F = s.body_force()
+    assert abs(F[0] / (g * n ** 3) - 1.0) < 5e-3, F
+    assert abs(F[1]) < 1e-4 * F[0] and abs(F[2]) < 1e-4 * F[0]
+    _, u, _, _ = s.fields()
+    c = 4.0 / 3.0 * math.pi * r ** 3 / n ** 3
+    K = 1.0 / (1 - 1.7601 * c ** (1 / 3) + c - 1.5593 * c ** 2 + 3.9799 * c ** (7 / 3) - 3.0734 * c ** (8 / 3))
+    k = F[0] / (6 * math.pi * (0.5 / 3) * r * u.mean())
+    assert 1.0 * K <= k <= 1.6 * K, (k, K)

@@ -505,6 +505,8 @@ class Workload3:
     # solid cells with interpolated bounce-back: (mask [nz, ny, nx] uint8,
     # q [nz, ny, nx, lattice] wall fraction of link i toward a solid neighbour, or None)
     solid: Optional[tuple] = None
+    # fixed immersed body: (X, Y, Z, dA, N_F), marker positions in cells
+    body: Optional[tuple] = None
     init: Optional[Callable] = None   # init(nx, ny, nz, z0=0, z1=nz) -> (rho, ux, uy, uz), each [z1 - z0, ny, nx]
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -631,3 +633,33 @@ def sphere3(n=32, r=5.0, tau=0.8, g=2e-6, lattice=19):
 
     return Workload3(name=f"sphere3_{n}_r{r}", nx=n, ny=n, nz=n, tau=tau, fext=(g, 0.0, 0.0), lattice=lattice,
                      solid=(mask, q), init=init, meta=dict(g=g, r=r))
+
+
+def sphere_markers(centre, r, n):
+    """n markers spread evenly over a sphere (golden-angle spiral), each
+    carrying the surface element 4 pi r^2 / n."""
+    k = np.arange(n) + 0.5
+    zc = 1.0 - 2.0 * k / n
+    rho = np.sqrt(1.0 - zc * zc)
+    phi = k * math.pi * (3.0 - math.sqrt(5.0))
+    X = centre[0] + r * rho * np.cos(phi)
+    Y = centre[1] + r * rho * np.sin(phi)
+    Z = centre[2] + r * zc
+    return X, Y, Z, np.full(n, 4.0 * math.pi * r * r / n)
+
+
+def ibm_sphere3(n=24, r=4.0, tau=0.8, g=1e-5, n_markers=None, mdf_iters=3, lattice=19):
+    """A fixed IBM sphere (markers about 0.7 cells apart) at the centre of a
+    periodic box driven by a body force along x: a periodic array of
+    spheres (Sec. 2.2 in 3D)."""
+    nm = n_markers or int(round(4 * math.pi * r * r / 0.5))
+    X, Y, Z, dA = sphere_markers((n / 2, n / 2, n / 2), r, nm)
+
+    def init(nx, ny, nz_, z0=0, z1=None):
+        z1 = nz_ if z1 is None else z1
+        m = z1 - z0
+        zero = np.zeros((m, ny, nx))
+        return np.ones((m, ny, nx)), zero, zero.copy(), zero.copy()
+
+    return Workload3(name=f"ibm_sphere3_{n}_r{r}", nx=n, ny=n, nz=n, tau=tau, fext=(g, 0.0, 0.0), lattice=lattice,
+                     body=(X, Y, Z, dA, mdf_iters), init=init, meta=dict(g=g, r=r, n_markers=nm))
