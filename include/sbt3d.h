@@ -14,7 +14,13 @@
  *   q >= 1/2: f*_o(x) / (2q) + (2q - 1)/(2q) f*_i(x),  o = opposite(i),
  * q = 1/2 where a short link has no fluid cell behind it; solid cells are
  * not collided and read out as NaN.  They add a 4-byte code per cell to
- * each step's reads.  D3Q19: rest (w = 1/3), 6 axis (1/18) and 12 edge
+ * each step's reads.  A fixed immersed body (n_markers > 0; Sec. 2.2 in 3D,
+ * desired velocity 0) runs the multi-direct forcing loop before every
+ * collision with Peskin's kernel (Eq. (14)) in each axis: N_F passes of
+ * U_j, rho_j interpolation over the 4x4x4 taps, g_j = 2 rho_j (0 - U_j),
+ * spreading g_j w dA_j in marker order and u += dF / (2 rho); the cells
+ * collide with F_ext + F.  It needs a fully periodic box without solid
+ * cells, and stencils that do not wrap across a face.  D3Q19: rest (w = 1/3), 6 axis (1/18) and 12 edge
  * (1/36) velocities; D3Q27 adds the 8 corners (rest 8/27, axis 2/27, edge
  * 1/54, corner 1/216); c_s^2 = 1/3 for both.  Direction order: rest,
  * +x -x +y -y +z -z, the edges (+-1, +-1, 0), (+-1, 0, +-1), (0, +-1, +-1),
@@ -57,6 +63,11 @@ typedef struct {
     const double *solid_q;         /* [nz][ny][nx][Q] wall fraction of the link from a
                                       fluid cell x toward a solid x + c_i (0 < q <= 1,
                                       read there only); NULL = 1/2 everywhere         */
+    int32_t n_markers;             /* fixed immersed body (0 = none): markers        */
+    const double *marker_xyz;      /* [3][n_markers] positions (cells; centres at
+                                      i + 1/2); read during plan / create           */
+    const double *marker_dA;       /* [n_markers] surface element of each marker     */
+    int32_t mdf_iters;             /* N_F of the forcing loop                        */
 } sbt3_desc;
 
 /* Device bytes sbt3_create needs.  Host only.  Errors: SBT_ERR_ARG. */
@@ -79,6 +90,10 @@ sbt_status sbt3_init_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, const double *r
 sbt_status sbt3_step(sbt3_ctx *ctx, int32_t n);
 /* Wait for the stream; SBT_ERR_NONFINITE if a density became NaN or Inf. */
 sbt_status sbt3_synchronize(sbt3_ctx *ctx);
+/* Body force F_s = -sum_j F_j dA_j of the last completed step (sum over
+ * the N_F passes of each marker's force).  Synchronises.  SBT_ERR_STATE
+ * without a body or before the first step. */
+sbt_status sbt3_body_force(sbt3_ctx *ctx, double out[3]);
 /* rho and u = (sum_i c_i f_i + F/2) / rho on planes z0 .. z0 + nz - 1 into
  * host FP64 arrays [nz][ny][nx].  Synchronises. */
 sbt_status sbt3_read_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, double *rho, double *ux, double *uy,

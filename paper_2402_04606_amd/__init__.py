@@ -33,7 +33,7 @@ ABI_SYMBOLS = [
     "sbt_write_state", "sbt_set_option", "sbt_autotune", "sbt_profile", "sbt_updates_per_step",
     "sbt_last_error",
     "sbt3_plan", "sbt3_create", "sbt3_destroy", "sbt3_init_slab", "sbt3_step", "sbt3_synchronize",
-    "sbt3_read_slab",
+    "sbt3_read_slab", "sbt3_body_force",
 ]
 
 
@@ -56,7 +56,9 @@ class Desc3(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("tau", C.c_double),
                 ("rho0", C.c_double), ("fext", C.c_double * 3), ("storage", C.c_int32),
                 ("lattice", C.c_int32), ("walls_z", C.c_int32), ("wall_u", (C.c_double * 3) * 2),
-                ("solid_mask", C.POINTER(C.c_uint8)), ("solid_q", C.POINTER(C.c_double))]
+                ("solid_mask", C.POINTER(C.c_uint8)), ("solid_q", C.POINTER(C.c_double)),
+                ("n_markers", C.c_int32), ("marker_xyz", C.POINTER(C.c_double)),
+                ("marker_dA", C.POINTER(C.c_double)), ("mdf_iters", C.c_int32)]
 
 
 class CaseDesc(C.Structure):
@@ -123,6 +125,7 @@ def lib():
             "sbt3_step": [vp, i32],
             "sbt3_synchronize": [vp],
             "sbt3_read_slab": [vp, i32, i32, d, d, d, d],
+            "sbt3_body_force": [vp, d],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -423,6 +426,15 @@ class Sim3:
                 qq = np.ascontiguousarray(q, dtype=np.float64)
                 self._solid_keep.append(qq)
                 d.solid_q = _dp(qq)
+        if getattr(wl, "body", None) is not None:
+            X, Y, Z, dA, iters = wl.body
+            xyz = np.ascontiguousarray(np.concatenate([X, Y, Z]), dtype=np.float64)
+            da = np.ascontiguousarray(dA, dtype=np.float64)
+            self._solid_keep += [xyz, da]
+            d.n_markers = len(X)
+            d.marker_xyz = _dp(xyz)
+            d.marker_dA = _dp(da)
+            d.mdf_iters = int(iters)
         for a, u in enumerate(getattr(wl, "wall_u", ((0.0,) * 3,) * 2)):
             for k in range(3):
                 d.wall_u[a][k] = u[k]
@@ -467,6 +479,12 @@ class Sim3:
         shape = (z1 - z0, self.wl.ny, self.wl.nx)
         out = [np.empty(shape) for _ in range(4)]
         _check(lib().sbt3_read_slab(self._h, z0, z1 - z0, *[_dp(a) for a in out]))
+        return out
+
+    def body_force(self):
+        """F_s of the last step (3 components)."""
+        out = np.zeros(3)
+        _check(lib().sbt3_body_force(self._h, _dp(out)))
         return out
 
     def updates_per_step(self):

@@ -77,6 +77,8 @@ struct Params {
   long long n;
   double tau, pre, rho0, F[3];
   double uw[2][3];             // bottom and top wall velocities (walls across z)
+  const double *ibm_F;         // immersed body: force density [3][box] over the box below, or null
+  int bx0, by0, bz0, bwx, bwy, bwz;
   float om_f, pre_f, rho0_f, F_f[3];
 };
 
@@ -159,6 +161,15 @@ __device__ __forceinline__ auto bouzidi3(const Params &p, const typename Store3<
   return fo / C(2.0 * q) + C((2.0 * q - 1.0) / (2.0 * q)) * fi;
 }
 
+// Index of cell c in the immersed body's force box, or -1 (no body, or outside).
+__device__ __forceinline__ long long ibm_box_index(const Params &p, long long c) {
+  if (!p.ibm_F) return -1;
+  const int x = (int)(c % p.nx) - p.bx0, y = (int)((c / p.nx) % p.ny) - p.by0;
+  const int z = (int)(c / ((long long)p.nx * p.ny)) - p.bz0;
+  if (x < 0 || y < 0 || z < 0 || x >= p.bwx || y >= p.bwy || z >= p.bwz) return -1;
+  return ((long long)z * p.bwy + y) * p.bwx + x;
+}
+
 template <int Q>
 __device__ __forceinline__ double wall_term(const Params &p, int i) {
 #pragma clang fp contract(off)
@@ -206,7 +217,14 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
       jy += E3Y[i] * f[i];
       jz += E3Z[i] * f[i];
     }
-    const double Fx = p.F[0], Fy = p.F[1], Fz = p.F[2];
+    double Fx = p.F[0], Fy = p.F[1], Fz = p.F[2];
+    const long long bi = ibm_box_index(p, c);
+    if (bi >= 0) {
+      const long long bn = (long long)p.bwx * p.bwy * p.bwz;
+      Fx = Fx + p.ibm_F[bi];
+      Fy = Fy + p.ibm_F[bn + bi];
+      Fz = Fz + p.ibm_F[2 * bn + bi];
+    }
     const double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho, uz = (jz + 0.5 * Fz) / rho;
     const double usq = ux * ux + uy * uy + uz * uz;
     const double uF = ux * Fx + uy * Fy + uz * Fz;
@@ -245,7 +263,14 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
     }
     const float rho = p.rho0_f + dr;
     const float ir = __builtin_amdgcn_rcpf(rho);
-    const float Fx = p.F_f[0], Fy = p.F_f[1], Fz = p.F_f[2];
+    float Fx = p.F_f[0], Fy = p.F_f[1], Fz = p.F_f[2];
+    const long long bi = ibm_box_index(p, c);
+    if (bi >= 0) {
+      const long long bn = (long long)p.bwx * p.bwy * p.bwz;
+      Fx += (float)p.ibm_F[bi];
+      Fy += (float)p.ibm_F[bn + bi];
+      Fz += (float)p.ibm_F[2 * bn + bi];
+    }
     const float ux = (jx + 0.5f * Fx) * ir, uy = (jy + 0.5f * Fy) * ir, uz = (jz + 0.5f * Fz) * ir;
     const float A = dr - rho * (1.5f * (ux * ux + uy * uy + uz * uz));
     const bool forced = Fx != 0.f || Fy != 0.f || Fz != 0.f;
@@ -262,6 +287,110 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
       }
       dst[(long long)i * p.n + c] = S::st(v);
     }
+  }
+}
+
+// Tables of a fixed immersed body (built on the host from its markers).
+struct Ibm3 {
+  int n, iters, K;             // markers, N_F, stencil cells
+  const long long *scell;      // [K] lattice index of each stencil cell
+  const int *tapk;             // [n][64] stencil index of each tap (z outer, y, x inner)
+  const double *tapw;          // [n][64] tap weight phi_x (phi_y phi_z)
+  const int *cstart;           // [K + 1] contributor list of each stencil cell
+  const int *cj;               // [E] contributing marker, ascending
+  const double *cw;            // [E] its tap weight
+  const double *dA;            // [n] surface element
+  double *rho, *u, *F;         // [K], [3][K], [3][K] work arrays
+  double *g, *ft;              // [3][n] force of the iteration, total force per marker
+  double *Fbox;                // [3][box] force density read by the step kernel
+  double *fs;                  // [6] body force F_s of this forcing loop, then of the previous one
+};
+
+// Sec. 2.2 in 3D for a fixed body (desired velocity 0), one workgroup: the
+// moments of the stencil cells from the state the next step collides
+// (gathered when the lattice holds post-collision populations), then N_F
+// passes of interpolation (U_j, rho_j), force g_j = 2 rho_j (0 - U_j) and
+// spreading in marker order with the velocity correction dF / (2 rho);
+// finally F_s = -sum_j F_j dA_j and the force density of the box.
+template <int ST, int kQ3>
+__global__ __launch_bounds__(1024) void ibm3_kernel(Params p, const void *lat_, int pull, Ibm3 b) {
+#pragma clang fp contract(off)
+  using S = Store3<ST>;
+  using T = typename S::T;
+  const T *lat = static_cast<const T *>(lat_);
+  const int tid = threadIdx.x, nt = blockDim.x;
+  if (tid < 3) b.fs[3 + tid] = b.fs[tid];  // the step this loop precedes is one ahead of the readouts
+  for (int k = tid; k < b.K; k += nt) {
+    const long long c = b.scell[k];
+    const Offsets o = offsets(p, c);
+    double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < kQ3; ++i) {
+      const double f = (double)S::ld(lat[(long long)i * p.n + source(o, c, i, pull)]);
+      r += f;
+      jx += E3X[i] * f;
+      jy += E3Y[i] * f;
+      jz += E3Z[i] * f;
+    }
+    if constexpr (ST != 0) r = p.rho0 + r;
+    b.rho[k] = r;
+    b.u[k] = (jx + 0.5 * p.F[0]) / r;
+    b.u[b.K + k] = (jy + 0.5 * p.F[1]) / r;
+    b.u[2 * b.K + k] = (jz + 0.5 * p.F[2]) / r;
+    b.F[k] = b.F[b.K + k] = b.F[2 * b.K + k] = 0.0;
+  }
+  for (int j = tid; j < b.n; j += nt) b.ft[j] = b.ft[b.n + j] = b.ft[2 * b.n + j] = 0.0;
+  __syncthreads();
+  for (int it = 0; it < b.iters; ++it) {
+    for (int j = tid; j < b.n; j += nt) {
+      double U0 = 0.0, U1 = 0.0, U2 = 0.0, R = 0.0;
+      for (int t = 0; t < 64; ++t) {
+        const int k = b.tapk[j * 64 + t];
+        const double w = b.tapw[j * 64 + t];
+        U0 += b.u[k] * w;
+        U1 += b.u[b.K + k] * w;
+        U2 += b.u[2 * b.K + k] * w;
+        R += b.rho[k] * w;
+      }
+      const double g0 = 2.0 * R * (0.0 - U0), g1 = 2.0 * R * (0.0 - U1), g2 = 2.0 * R * (0.0 - U2);
+      b.g[j] = g0;
+      b.g[b.n + j] = g1;
+      b.g[2 * b.n + j] = g2;
+      b.ft[j] += g0;
+      b.ft[b.n + j] += g1;
+      b.ft[2 * b.n + j] += g2;
+    }
+    __syncthreads();
+    for (int k = tid; k < b.K; k += nt) {
+      double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+      for (int e = b.cstart[k]; e < b.cstart[k + 1]; ++e) {
+        const int j = b.cj[e];
+        const double w = b.cw[e];
+        d0 += b.g[j] * w * b.dA[j];
+        d1 += b.g[b.n + j] * w * b.dA[j];
+        d2 += b.g[2 * b.n + j] * w * b.dA[j];
+      }
+      if (d0 == 0.0 && d1 == 0.0 && d2 == 0.0) continue;
+      b.F[k] += d0;
+      b.F[b.K + k] += d1;
+      b.F[2 * b.K + k] += d2;
+      b.u[k] += d0 / (2.0 * b.rho[k]);
+      b.u[b.K + k] += d1 / (2.0 * b.rho[k]);
+      b.u[2 * b.K + k] += d2 / (2.0 * b.rho[k]);
+    }
+    __syncthreads();
+  }
+  if (tid < 3) {
+    double t = 0.0;
+    for (int j = 0; j < b.n; ++j) t -= b.ft[tid * b.n + j] * b.dA[j];
+    b.fs[tid] = t;
+  }
+  const long long bn = (long long)p.bwx * p.bwy * p.bwz;
+  for (int k = tid; k < b.K; k += nt) {
+    const long long bi = ibm_box_index(p, b.scell[k]);
+    b.Fbox[bi] = b.F[k];
+    b.Fbox[bn + bi] = b.F[b.K + k];
+    b.Fbox[2 * bn + bi] = b.F[2 * b.K + k];
   }
 }
 
@@ -344,6 +473,7 @@ struct sbt3_ctx {
   bool post = false;  // the lattices hold post-collision populations (a step has run)
   hipStream_t stream;
   long long n_records = 0;
+  Ibm3 ibm{};                 // immersed body tables (ibm.n == 0: none)
 };
 
 namespace {
@@ -356,6 +486,10 @@ sbt_status check_desc(const sbt3_desc *d) {
   if (!(d->rho0 > 0.0)) return sbt_set_error(SBT_ERR_ARG, "rho0 must be positive");
   if (d->storage < SBT_F64 || d->storage > SBT_BF16S) return sbt_set_error(SBT_ERR_ARG, "bad storage");
   if (d->lattice != 19 && d->lattice != 27) return sbt_set_error(SBT_ERR_ARG, "lattice must be 19 or 27");
+  if (d->n_markers < 0 || (d->n_markers > 0 && (!d->marker_xyz || !d->marker_dA || d->mdf_iters < 0)))
+    return sbt_set_error(SBT_ERR_ARG, "bad immersed body");
+  if (d->n_markers > 0 && (d->walls_z || d->solid_mask))
+    return sbt_set_error(SBT_ERR_ARG, "an immersed body needs a fully periodic box without solid cells");
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(d->fext[k]) || !std::isfinite(d->wall_u[0][k]) || !std::isfinite(d->wall_u[1][k]))
       return sbt_set_error(SBT_ERR_ARG, "body force and wall velocities must be finite");
@@ -422,6 +556,91 @@ sbt_status solid_records(const sbt3_desc *d, std::vector<int32_t> *code, std::ve
   return SBT_OK;
 }
 
+// Peskin's 4-point kernel (Eq. (14), unit spacing).
+double peskin3(double r) {
+  const double a = std::fabs(r);
+  if (a <= 1.0) return 0.125 * (3.0 - 2.0 * a + std::sqrt(1.0 + 4.0 * a - 4.0 * a * a));
+  if (a <= 2.0) return 0.125 * (5.0 - 2.0 * a - std::sqrt(-7.0 + 12.0 * a - 4.0 * a * a));
+  return 0.0;
+}
+
+// Host tables of a fixed immersed body: the 64 taps of each marker (cells
+// from floor(X - 1.5) on, z outer, y, x inner; weight phi_x (phi_y phi_z)),
+// the stencil cells they touch, each cell's contributors in marker order,
+// and the box of cells the stencils cover (no periodic wrap).
+struct BodyTables {
+  std::vector<long long> scell;
+  std::vector<int> tapk, cstart, cj;
+  std::vector<double> tapw, cw;
+  int bx0 = 0, by0 = 0, bz0 = 0, bwx = 0, bwy = 0, bwz = 0;
+};
+
+sbt_status body_tables(const sbt3_desc *d, BodyTables &T) {
+  const int n = d->n_markers, nx = d->nx, ny = d->ny, nz = d->nz;
+  const double *X = d->marker_xyz, *Y = X + n, *Z = X + 2 * n;
+  int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+  for (int j = 0; j < n; ++j) {
+    const int t0[3] = {(int)std::floor(X[j] - 1.5), (int)std::floor(Y[j] - 1.5), (int)std::floor(Z[j] - 1.5)};
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], t0[a]);
+      hi[a] = std::max(hi[a], t0[a] + 4);
+    }
+  }
+  if (lo[0] < 0 || lo[1] < 0 || lo[2] < 0 || hi[0] > nx || hi[1] > ny || hi[2] > nz)
+    return sbt_set_error(SBT_ERR_ARG, "marker stencils must lie inside the box (no periodic wrap)");
+  T.bx0 = lo[0];
+  T.by0 = lo[1];
+  T.bz0 = lo[2];
+  T.bwx = hi[0] - lo[0];
+  T.bwy = hi[1] - lo[1];
+  T.bwz = hi[2] - lo[2];
+  const long long boxn = (long long)T.bwx * T.bwy * T.bwz;
+  std::vector<int> kof(boxn, -1);
+  T.tapk.resize((size_t)n * 64);
+  T.tapw.resize((size_t)n * 64);
+  std::vector<std::vector<std::pair<int, double>>> lists;
+  for (int j = 0; j < n; ++j) {
+    const int i0 = (int)std::floor(X[j] - 1.5), j0 = (int)std::floor(Y[j] - 1.5), k0 = (int)std::floor(Z[j] - 1.5);
+    int t = 0;
+    for (int c = 0; c < 4; ++c) {
+      const double pz = peskin3(k0 + c + 0.5 - Z[j]);
+      for (int b = 0; b < 4; ++b) {
+        const double pyz = peskin3(j0 + b + 0.5 - Y[j]) * pz;
+        for (int a = 0; a < 4; ++a, ++t) {
+          const double w = peskin3(i0 + a + 0.5 - X[j]) * pyz;
+          const long long bi = ((long long)(k0 + c - T.bz0) * T.bwy + (j0 + b - T.by0)) * T.bwx + (i0 + a - T.bx0);
+          int &k = kof[bi];
+          if (k < 0) {
+            k = (int)T.scell.size();
+            T.scell.push_back(((long long)(k0 + c) * ny + (j0 + b)) * nx + (i0 + a));
+            lists.emplace_back();
+          }
+          T.tapk[(size_t)j * 64 + t] = k;
+          T.tapw[(size_t)j * 64 + t] = w;
+          lists[k].push_back({j, w});
+        }
+      }
+    }
+  }
+  T.cstart.assign(1, 0);
+  for (auto &L : lists) {
+    for (auto &e : L) {
+      T.cj.push_back(e.first);
+      T.cw.push_back(e.second);
+    }
+    T.cstart.push_back((int)T.cj.size());
+  }
+  return SBT_OK;
+}
+
+size_t body_bytes(const sbt3_desc *d, const BodyTables &T) {
+  const size_t n = d->n_markers, K = T.scell.size(), E = T.cj.size();
+  const size_t boxn = (size_t)T.bwx * T.bwy * T.bwz;
+  return align256(K * 8) + align256(n * 64 * 4) + align256(n * 64 * 8) + align256((K + 1) * 4) + align256(E * 4) +
+         align256(E * 8) + align256(n * 8) + align256(K * 8) + 2 * align256(3 * K * 8) + 2 * align256(3 * n * 8) +
+         align256(3 * boxn * 8) + align256(6 * 8);
+}
+
 size_t plan_bytes(const sbt3_desc *d, long long *stage, long long records) {
   const long long n = (long long)d->nx * d->ny * d->nz;
   *stage = std::min<long long>(n, std::max<long long>(kStageCells, (long long)d->nx * d->ny));
@@ -430,6 +649,11 @@ size_t plan_bytes(const sbt3_desc *d, long long *stage, long long records) {
   if (d->solid_mask)
     b += align256((size_t)n * sizeof(int32_t)) + align256((size_t)records * sizeof(uint32_t)) +
          align256((size_t)records * d->lattice * sizeof(double));
+  if (d->n_markers > 0) {
+    BodyTables T;
+    if (body_tables(d, T)) return 0;
+    b += body_bytes(d, T);
+  }
   return b;
 }
 
@@ -455,6 +679,21 @@ size_t plan_bytes(const sbt3_desc *d, long long *stage, long long records) {
     return hipGetLastError();                                                                       \
   }()
 
+hipError_t launch_ibm(sbt3_ctx &X, int pull) {
+  switch (X.d.storage + 4 * (X.d.lattice == 27)) {
+    case 0: hipLaunchKernelGGL((ibm3_kernel<0, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
+    case 1: hipLaunchKernelGGL((ibm3_kernel<1, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
+    case 2: hipLaunchKernelGGL((ibm3_kernel<2, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
+    case 3: hipLaunchKernelGGL((ibm3_kernel<3, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
+    case 4: hipLaunchKernelGGL((ibm3_kernel<0, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
+    case 5: hipLaunchKernelGGL((ibm3_kernel<1, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
+    case 6: hipLaunchKernelGGL((ibm3_kernel<2, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
+    case 7: hipLaunchKernelGGL((ibm3_kernel<3, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 sbt_status check_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, const void *a, const void *b, const void *c,
                       const void *e) {
   if (!ctx) return sbt_set_error(SBT_ERR_ARG, "null context");
@@ -474,6 +713,11 @@ sbt_status sbt3_plan(const sbt3_desc *desc, size_t *device_bytes) {
   long long stage, records = 0;
   if (desc->solid_mask) {
     st = solid_records(desc, nullptr, nullptr, nullptr, &records);
+    if (st) return st;
+  }
+  if (desc->n_markers > 0) {
+    BodyTables T;
+    st = body_tables(desc, T);
     if (st) return st;
   }
   *device_bytes = plan_bytes(desc, &stage, records);
@@ -549,6 +793,67 @@ sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, vo
     p.rq = dq;
     X->n_records = records;
   }
+  p.ibm_F = nullptr;
+  if (desc->n_markers > 0) {
+    BodyTables T;
+    st = body_tables(desc, T);
+    if (st) {
+      delete X;
+      return st;
+    }
+    size_t off = 2 * lat + align256((size_t)stage * 4 * sizeof(double)) + 256;
+    if (desc->solid_mask)
+      off += align256((size_t)p.n * sizeof(int32_t)) + align256((size_t)records * sizeof(uint32_t)) +
+             align256((size_t)records * desc->lattice * sizeof(double));
+    char *q = b + off;
+    auto take = [&](size_t bytes) {
+      char *r = q;
+      q += align256(bytes);
+      return r;
+    };
+    const int n = desc->n_markers, K = (int)T.scell.size();
+    const size_t boxn = (size_t)T.bwx * T.bwy * T.bwz;
+    Ibm3 &B = X->ibm;
+    B.n = n;
+    B.iters = desc->mdf_iters;
+    B.K = K;
+    B.scell = reinterpret_cast<const long long *>(take((size_t)K * 8));
+    B.tapk = reinterpret_cast<const int *>(take((size_t)n * 64 * 4));
+    B.tapw = reinterpret_cast<const double *>(take((size_t)n * 64 * 8));
+    B.cstart = reinterpret_cast<const int *>(take((size_t)(K + 1) * 4));
+    B.cj = reinterpret_cast<const int *>(take(T.cj.size() * 4));
+    B.cw = reinterpret_cast<const double *>(take(T.cw.size() * 8));
+    B.dA = reinterpret_cast<const double *>(take((size_t)n * 8));
+    B.rho = reinterpret_cast<double *>(take((size_t)K * 8));
+    B.u = reinterpret_cast<double *>(take((size_t)3 * K * 8));
+    B.F = reinterpret_cast<double *>(take((size_t)3 * K * 8));
+    B.g = reinterpret_cast<double *>(take((size_t)3 * n * 8));
+    B.ft = reinterpret_cast<double *>(take((size_t)3 * n * 8));
+    B.Fbox = reinterpret_cast<double *>(take(3 * boxn * 8));
+    B.fs = reinterpret_cast<double *>(take(6 * 8));
+    bool ok = hipMemcpy((void *)B.scell, T.scell.data(), (size_t)K * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy((void *)B.tapk, T.tapk.data(), T.tapk.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy((void *)B.tapw, T.tapw.data(), T.tapw.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy((void *)B.cstart, T.cstart.data(), T.cstart.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy((void *)B.cj, T.cj.data(), T.cj.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy((void *)B.cw, T.cw.data(), T.cw.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy((void *)B.dA, desc->marker_dA, (size_t)n * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemset(B.Fbox, 0, 3 * boxn * 8) == hipSuccess;
+    ok &= hipMemset(B.fs, 0, 6 * 8) == hipSuccess;
+    if (!ok) {
+      delete X;
+      return sbt_set_error(SBT_ERR_DEVICE, "immersed-body table upload");
+    }
+    p.ibm_F = B.Fbox;
+    p.bx0 = T.bx0;
+    p.by0 = T.by0;
+    p.bz0 = T.bz0;
+    p.bwx = T.bwx;
+    p.bwy = T.bwy;
+    p.bwz = T.bwz;
+  }
+  X->d.marker_xyz = nullptr;  // borrowed for this call only
+  X->d.marker_dA = nullptr;
   if (hipMemsetAsync(X->err, 0, sizeof(int), X->stream) != hipSuccess) {
     delete X;
     return sbt_set_error(SBT_ERR_DEVICE, "error flag clear");
@@ -587,12 +892,14 @@ sbt_status sbt3_step(sbt3_ctx *ctx, int32_t n) {
   if (n == 0) return SBT_OK;
   const dim3 grid((unsigned)((X.p.n + kThreads - 1) / kThreads));
   if (!X.post) {  // collide the initial state in place: the lattice then holds f*
+    if (X.ibm.n > 0) HIP3(launch_ibm(X, 0));
     HIP3(SBT3_LAUNCH(step3_kernel, X.d.storage, X.d.lattice, grid, X.stream, X.p, (const void *)X.lat[X.cur], X.lat[1 - X.cur], 0,
                      X.err));
     X.cur = 1 - X.cur;
     X.post = true;
   }
   for (int t = 0; t < n; ++t) {
+    if (X.ibm.n > 0) HIP3(launch_ibm(X, 1));
     HIP3(SBT3_LAUNCH(step3_kernel, X.d.storage, X.d.lattice, grid, X.stream, X.p, (const void *)X.lat[X.cur], X.lat[1 - X.cur], 1,
                      X.err));
     X.cur = 1 - X.cur;
@@ -609,6 +916,16 @@ sbt_status sbt3_synchronize(sbt3_ctx *ctx) {
     HIP3(hipMemset(ctx->err, 0, sizeof(int)));
     return sbt_set_error(SBT_ERR_NONFINITE, "a density became NaN or Inf");
   }
+  return SBT_OK;
+}
+
+sbt_status sbt3_body_force(sbt3_ctx *ctx, double out[3]) {
+  if (!ctx || !out) return sbt_set_error(SBT_ERR_ARG, "null argument");
+  if (ctx->ibm.n == 0) return sbt_set_error(SBT_ERR_STATE, "no immersed body");
+  if (!ctx->post) return sbt_set_error(SBT_ERR_STATE, "no completed step");
+  // the last launch ran the forcing loop of the step after the last completed one
+  HIP3(hipMemcpyAsync(out, ctx->ibm.fs + 3, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIP3(hipStreamSynchronize(ctx->stream));
   return SBT_OK;
 }
 

@@ -842,3 +842,27 @@ def test_3d_solid_cells(env, make, steps, storage, tol, q):
     assert e <= tol
     if storage == "f64":
         assert all(np.array_equal(a, b) for a, b in zip(fgm, fom))
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", TOL64), ("f32", 2e-5)])
+def test_3d_immersed_sphere(env, storage, tol, q):
+    """A fixed IBM sphere (402 markers, N_F = 3) in a forced periodic box:
+    fields and body force against the oracle after 150 steps; FP64
+    bit-exact."""
+    P, O = env
+    wl = W.ibm_sphere3(24, r=4.0, tau=1.0, g=1e-5, lattice=q)
+    print(f"case {wl.name} D3Q{q} {storage}", flush=True)
+    g = P.Sim3(wl, storage)
+    o = O.Oracle3Sim(wl)
+    g.step(150)
+    g.synchronize()
+    o.step(150)
+    e = rel_l2_3(g.fields(), o.fields())
+    fg, fo = g.body_force(), o.body_force()
+    ef = np.abs(fg - fo).max() / np.abs(fo).max()
+    print(f"  rel L2 u {e:.3e}  body force {fg}  rel err {ef:.3e}", flush=True)
+    assert e <= tol and ef <= max(tol, 1e-12) * 10
+    if storage == "f64":
+        assert all(np.array_equal(a, b) for a, b in zip(g.fields(), o.fields()))
+        assert np.array_equal(fg, fo)
