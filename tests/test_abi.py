@@ -118,6 +118,44 @@ def test_3d_plan_and_validation(pkg):
         assert pkg.lib().sbt3_plan(C.byref(e), C.byref(n)) == -1, field
 
 
+def test_3d_body_and_solid_validation(pkg):
+    """sbt3_plan rejects an immersed body whose stencils wrap across a face,
+    a body in a walled or solid box, and wall fractions outside (0, 1]."""
+    import ctypes as C
+    import numpy as np
+
+    def plan(wl):
+        d = pkg.Desc3()
+        d.nx, d.ny, d.nz, d.tau, d.rho0, d.storage, d.lattice = wl.nx, wl.ny, wl.nz, wl.tau, 1.0, pkg.F32, wl.lattice
+        d.walls_z = 1 if wl.walls_z else 0
+        keep = []
+        if wl.body is not None:
+            X, Y, Z, dA, it = wl.body
+            xyz = np.ascontiguousarray(np.concatenate([X, Y, Z]))
+            da = np.ascontiguousarray(dA)
+            keep += [xyz, da]
+            d.n_markers, d.mdf_iters = len(X), it
+            d.marker_xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
+            d.marker_dA = da.ctypes.data_as(C.POINTER(C.c_double))
+        if wl.solid is not None:
+            m, q = (np.ascontiguousarray(a) for a in wl.solid)
+            keep += [m, q]
+            d.solid_mask = m.ctypes.data_as(C.POINTER(C.c_uint8))
+            d.solid_q = q.ctypes.data_as(C.POINTER(C.c_double))
+        n = C.c_size_t()
+        return pkg.lib().sbt3_plan(C.byref(d), C.byref(n)), n.value
+
+    ok = W.ibm_sphere3(24, r=4.0)
+    rc, n = plan(ok)
+    assert rc == 0 and n > 2 * 19 * 24 ** 3 * 4
+    X, Y, Z, dA, it = ok.body
+    assert plan(ok.replace(body=(X - 10.5, Y, Z, dA, it)))[0] == -1       # stencils wrap across x = 0
+    assert plan(ok.replace(walls_z=True))[0] == -1
+    assert plan(W.sphere3(16, r=3.0))[0] == 0
+    m, q = W.sphere3(16, r=3.0).solid
+    assert plan(W.sphere3(16, r=3.0).replace(solid=(m, np.zeros_like(q))))[0] == -1
+
+
 def test_rescale_rejects_unit_tau(pkg):
     wl = W.tgv_patch(m=2, tau=1.0, cf_mode=W.CF_RESCALE)
     with pytest.raises(pkg.SbtError):
