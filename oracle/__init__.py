@@ -99,6 +99,7 @@ def lib():
         _lib.orc3_set_solid.argtypes = [C.c_void_p, C.POINTER(C.c_uint8), d]
         _lib.orc3_set_body.argtypes = [C.c_void_p, C.c_int32, d, d, d, d, C.c_int32]
         _lib.orc3_body_force.argtypes = [C.c_void_p, d]
+        _lib.orc3_set_motion.argtypes = [C.c_void_p, C.c_int32, d]
         _lib.orc_num_threads.argtypes = []
     return _lib
 
@@ -421,6 +422,9 @@ class Oracle3Sim:
             rc = lib().orc3_set_body(h, len(X), _dp(X), _dp(Y), _dp(Z), _dp(dA), int(iters))
             if rc:
                 raise RuntimeError(f"orc3_set_body failed: {rc}")
+            kind, params = getattr(wl, "motion", (0, None))
+            pm = _f64(np.asarray(params if params is not None else [0.0] * 10, dtype=np.float64))
+            lib().orc3_set_motion(h, int(kind), _dp(pm))
         r, u, v, w = (_f64(a) for a in wl.init(wl.nx, wl.ny, wl.nz))
         lib().orc3_init_fields(h, _dp(r), _dp(u), _dp(v), _dp(w))
 

@@ -1117,8 +1117,11 @@ struct orc3_sim {
     double rho_w;             /* wall density of the moving-wall term                            */
     uint8_t *solid;           /* solid cells (interpolated bounce-back), or NULL                 */
     double *sq;               /* [cell][q] wall fraction of link i from a fluid cell toward x + c_i */
-    int nm, iters;            /* fixed immersed body: markers, N_F                               */
-    double *bx, *by, *bz, *bdA;
+    int nm, iters;            /* immersed body: markers, N_F                                     */
+    double *bx, *by, *bz, *bdA;   /* markers: absolute (kind 0) or body frame (kind 1)           */
+    int kind;                 /* 0 fixed, 1 pitch about y + plunge along z                       */
+    double bp[10];            /* kind 1: x0, y0, z0, alpha0, A_pitch, A0, T, phi, U_ref, chord   */
+    int64_t k;                /* steps whose forcing loop has run                                */
     double *Fb;               /* [3][cell] IBM force density of the current step                 */
     double fsb[3];            /* body force F_s of the last step                                 */
     double tau, F[3];
@@ -1175,9 +1178,41 @@ int orc3_init_fields(orc3_sim *s, const double *rho, const double *ux, const dou
  * Per iteration: U_j and rho_j interpolated, g_j = 2 rho_j (0 - U_j),
  * spread in marker order as g_j w dA_j, F += dF and u += dF / (2 rho); then
  * F_s = -sum_j F_j dA_j.  Fills s->Fb and s->fs. */
+/* Marker positions at step t: kind 0 as given; kind 1 the Sec. 3.6 law in
+ * the x-z plane (pitch alpha about the y axis, plunge along z):
+ *   t* = t U_ref / c, theta = 2 pi t* / T, alpha = alpha0 - A_pitch sin(theta + phi),
+ *   centre (x0, y0, z0 + (A0/2) cos theta),
+ *   X = xc + xb cos a + zb sin a,  Y = yc + yb,  Z = zc - xb sin a + zb cos a. */
+static void body3_positions(const orc3_sim *s, double t, double *X, double *Y, double *Z) {
+    const double *p = s->bp;
+    if (s->kind == 0) {
+        for (int j = 0; j < s->nm; ++j) { X[j] = s->bx[j]; Y[j] = s->by[j]; Z[j] = s->bz[j]; }
+        return;
+    }
+    double tstar = t * p[8] / p[9];
+    double theta = 2.0 * M_PI * tstar / p[6];
+    double alpha = p[3] - p[4] * sin(theta + p[7]);
+    double zc = p[2] + 0.5 * p[5] * cos(theta);
+    double ca = cos(alpha), sa = sin(alpha);
+    for (int j = 0; j < s->nm; ++j) {
+        X[j] = p[0] + s->bx[j] * ca + s->bz[j] * sa;
+        Y[j] = p[1] + s->by[j];
+        Z[j] = zc - s->bx[j] * sa + s->bz[j] * ca;
+    }
+}
+
 static void mdf3(orc3_sim *s) {
     const int nx = s->nx, ny = s->ny, nz = s->nz, Q3 = s->q, nm = s->nm;
     const size_t n = (size_t)nx * ny * nz;
+    double *pos = malloc(sizeof(double) * nm * 9), *PX = pos, *PY = pos + nm, *PZ = pos + 2 * nm;
+    double *ud = pos + 3 * nm, *Q1 = pos + 6 * nm;
+    body3_positions(s, (double)s->k, PX, PY, PZ);
+    body3_positions(s, (double)(s->k + 1), Q1, Q1 + nm, Q1 + 2 * nm);
+    for (int j = 0; j < nm; ++j) {
+        ud[3 * j] = Q1[j] - PX[j];
+        ud[3 * j + 1] = Q1[nm + j] - PY[j];
+        ud[3 * j + 2] = Q1[2 * nm + j] - PZ[j];
+    }
     double *rho = malloc(sizeof(double) * n * 7), *u = rho + n, *dF = rho + 4 * n;
     for (size_t c = 0; c < n; ++c) {
         const double *f = s->f + c * Q3;
@@ -1193,16 +1228,16 @@ static void mdf3(orc3_sim *s) {
     for (int j = 0; j < 3 * nm; ++j) ft[j] = 0.0;
     for (int it = 0; it < s->iters; ++it) {
         for (int j = 0; j < nm; ++j) {
-            int i0 = tap0(s->bx[j]), j0 = tap0(s->by[j]), k0 = tap0(s->bz[j]);
+            int i0 = tap0(PX[j]), j0 = tap0(PY[j]), k0 = tap0(PZ[j]);
             double U[3] = {0.0, 0.0, 0.0}, R = 0.0;
             for (int cc = 0; cc < 4; ++cc) {
-                double pz = orc_phi(k0 + cc + 0.5 - s->bz[j]);
+                double pz = orc_phi(k0 + cc + 0.5 - PZ[j]);
                 int zz = (k0 + cc + nz) % nz;
                 for (int b = 0; b < 4; ++b) {
-                    double pyz = orc_phi(j0 + b + 0.5 - s->by[j]) * pz;
+                    double pyz = orc_phi(j0 + b + 0.5 - PY[j]) * pz;
                     int yy = (j0 + b + ny) % ny;
                     for (int a = 0; a < 4; ++a) {
-                        double w = orc_phi(i0 + a + 0.5 - s->bx[j]) * pyz;
+                        double w = orc_phi(i0 + a + 0.5 - PX[j]) * pyz;
                         size_t c = ((size_t)zz * ny + yy) * nx + (i0 + a + nx) % nx;
                         U[0] += u[c] * w;
                         U[1] += u[n + c] * w;
@@ -1212,21 +1247,21 @@ static void mdf3(orc3_sim *s) {
                 }
             }
             for (int k = 0; k < 3; ++k) {
-                g[3 * j + k] = 2.0 * R * (0.0 - U[k]);
+                g[3 * j + k] = 2.0 * R * (ud[3 * j + k] - U[k]);
                 ft[3 * j + k] += g[3 * j + k];
             }
         }
         memset(dF, 0, sizeof(double) * 3 * n);
         for (int j = 0; j < nm; ++j) {
-            int i0 = tap0(s->bx[j]), j0 = tap0(s->by[j]), k0 = tap0(s->bz[j]);
+            int i0 = tap0(PX[j]), j0 = tap0(PY[j]), k0 = tap0(PZ[j]);
             for (int cc = 0; cc < 4; ++cc) {
-                double pz = orc_phi(k0 + cc + 0.5 - s->bz[j]);
+                double pz = orc_phi(k0 + cc + 0.5 - PZ[j]);
                 int zz = (k0 + cc + nz) % nz;
                 for (int b = 0; b < 4; ++b) {
-                    double pyz = orc_phi(j0 + b + 0.5 - s->by[j]) * pz;
+                    double pyz = orc_phi(j0 + b + 0.5 - PY[j]) * pz;
                     int yy = (j0 + b + ny) % ny;
                     for (int a = 0; a < 4; ++a) {
-                        double w = orc_phi(i0 + a + 0.5 - s->bx[j]) * pyz;
+                        double w = orc_phi(i0 + a + 0.5 - PX[j]) * pyz;
                         size_t c = ((size_t)zz * ny + yy) * nx + (i0 + a + nx) % nx;
                         for (int k = 0; k < 3; ++k) dF[k * n + c] += g[3 * j + k] * w * s->bdA[j];
                     }
@@ -1246,7 +1281,8 @@ static void mdf3(orc3_sim *s) {
         for (int j = 0; j < nm; ++j) t -= ft[3 * j + k] * s->bdA[j];
         s->fsb[k] = t;
     }
-    free(g); free(rho);
+    free(g); free(rho); free(pos);
+    s->k++;
 }
 
 int orc3_set_body(orc3_sim *s, int32_t n, const double *X, const double *Y, const double *Z, const double *dA,
@@ -1259,7 +1295,18 @@ int orc3_set_body(orc3_sim *s, int32_t n, const double *X, const double *Y, cons
     memcpy(s->bz, Z, sizeof(double) * n); memcpy(s->bdA, dA, sizeof(double) * n);
     s->nm = n;
     s->iters = iters;
+    s->kind = 0;
+    s->k = 0;
     s->Fb = calloc((size_t)3 * s->nx * s->ny * s->nz, sizeof(double));
+    return ORC_OK;
+}
+
+/* Motion of the body (after orc3_set_body): kind 0 fixed (markers absolute),
+ * kind 1 the pitch/plunge law of body3_positions (markers in the body frame). */
+int orc3_set_motion(orc3_sim *s, int32_t kind, const double p[10]) {
+    if (kind != 0 && kind != 1) return ORC_ERR_ARG;
+    s->kind = kind;
+    for (int i = 0; i < 10; ++i) s->bp[i] = p ? p[i] : 0.0;
     return ORC_OK;
 }
 

@@ -144,6 +144,10 @@ int  orc3_set_solid(orc3_sim *s, const uint8_t *mask, const double *q);
  * elements dA, N_F iterations of the forcing loop before every collision. */
 int  orc3_set_body(orc3_sim *s, int32_t n, const double *X, const double *Y, const double *Z,
                    const double *dA, int32_t iters);
+/* Motion: kind 0 fixed (markers absolute), kind 1 pitch about the y axis and
+ * plunge along z, p = {x0, y0, z0, alpha0, A_pitch, A0, T, phi, U_ref, chord}
+ * (markers in the body frame); desired velocity r(t + 1) - r(t). */
+int  orc3_set_motion(orc3_sim *s, int32_t kind, const double p[10]);
 /* F_s = -sum_j F_j dA_j of the last step. */
 int  orc3_body_force(const orc3_sim *s, double out[3]);
 int  orc3_read_fields(const orc3_sim *s, double *rho, double *ux, double *uy, double *uz);

@@ -911,3 +911,21 @@ def test_3d_ibm_sphere_momentum_balance_and_stokes_drag(orc):
     K = 1.0 / (1 - 1.7601 * c ** (1 / 3) + c - 1.5593 * c ** 2 + 3.9799 * c ** (7 / 3) - 3.0734 * c ** (8 / 3))
     k = F[0] / (6 * math.pi * (0.5 / 3) * r * u.mean())
     assert 1.0 * K <= k <= 1.6 * K, (k, K)
+
+
+def test_3d_moving_body_with_zero_amplitudes_is_fixed(orc):
+    """The 3D pitch/plunge law with zero amplitudes is the fixed body at the
+    pivot: same run, bit for bit (markers in the body frame shifted by the
+    pivot against markers given absolute)."""
+    wl = W.flapping_ellipsoid3(24, chord=8.0)
+    xb, yb, zb, dA, it = wl.body
+    p = list(wl.motion[1])
+    p[4] = p[5] = 0.0
+    moving = wl.replace(motion=(1, p))
+    fixed = wl.replace(body=(p[0] + xb, p[1] + yb, p[2] + zb, dA, it), motion=(0, None))
+    a, b = orc.Oracle3Sim(moving), orc.Oracle3Sim(fixed)
+    a.step(20)
+    b.step(20)
+    assert np.array_equal(a.body_force(), b.body_force())
+    for x, y in zip(a.fields(), b.fields()):
+        assert np.array_equal(x, y)

@@ -505,8 +505,11 @@ class Workload3:
     # solid cells with interpolated bounce-back: (mask [nz, ny, nx] uint8,
     # q [nz, ny, nx, lattice] wall fraction of link i toward a solid neighbour, or None)
     solid: Optional[tuple] = None
-    # fixed immersed body: (X, Y, Z, dA, N_F), marker positions in cells
+    # immersed body: (X, Y, Z, dA, N_F), marker positions in cells
     body: Optional[tuple] = None
+    # its motion: (0, None) fixed (markers absolute) or (1, 10 parameters) pitch
+    # about y + plunge along z with markers in the body frame
+    motion: tuple = (0, None)
     init: Optional[Callable] = None   # init(nx, ny, nz, z0=0, z1=nz) -> (rho, ux, uy, uz), each [z1 - z0, ny, nx]
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -663,3 +666,32 @@ def ibm_sphere3(n=24, r=4.0, tau=0.8, g=1e-5, n_markers=None, mdf_iters=3, latti
 
     return Workload3(name=f"ibm_sphere3_{n}_r{r}", nx=n, ny=n, nz=n, tau=tau, fext=(g, 0.0, 0.0), lattice=lattice,
                      body=(X, Y, Z, dA, mdf_iters), init=init, meta=dict(g=g, r=r, n_markers=nm))
+
+
+def flapping_ellipsoid3(n=32, chord=12.0, amp_deg=30.0, T=1.0, U=0.05, tau=0.8, A0_over_c=0.5, n_markers=None,
+                        mdf_iters=3, lattice=19):
+    """A thin ellipsoid (semi-axes c/2, c/4 along y, c/8 along z) pitching
+    about the y axis and plunging along z (the Sec. 3.6 law in the x-z
+    plane) in a periodic box with a uniform stream U along x."""
+    a, b, cz = chord / 2, chord / 4, chord / 8
+    nm = n_markers or 400
+    k = np.arange(nm) + 0.5
+    zc = 1.0 - 2.0 * k / nm
+    rr = np.sqrt(1.0 - zc * zc)
+    ph = k * math.pi * (3.0 - math.sqrt(5.0))
+    xb, yb, zb = a * rr * np.cos(ph), b * rr * np.sin(ph), cz * zc
+    # surface element: the ellipsoid's area (Knud Thomsen's approximation) shared evenly
+    pp = 1.6075
+    area = 4 * math.pi * (((a * b) ** pp + (a * cz) ** pp + (b * cz) ** pp) / 3) ** (1 / pp)
+    dA = np.full(nm, area / nm)
+    params = [n / 2, n / 2, n / 2, 0.0, math.radians(amp_deg), A0_over_c * chord, T, 0.0, U, chord]
+
+    def init(nx, ny, nz_, z0=0, z1=None):
+        z1 = nz_ if z1 is None else z1
+        m = z1 - z0
+        zero = np.zeros((m, ny, nx))
+        return np.ones((m, ny, nx)), np.full((m, ny, nx), U), zero, zero.copy()
+
+    return Workload3(name=f"flapping_ellipsoid3_{n}", nx=n, ny=n, nz=n, tau=tau, lattice=lattice,
+                     body=(xb, yb, zb, dA, mdf_iters), motion=(1, params), init=init,
+                     meta=dict(U=U, chord=chord, n_markers=nm))
