@@ -14,13 +14,17 @@
  *   q >= 1/2: f*_o(x) / (2q) + (2q - 1)/(2q) f*_i(x),  o = opposite(i),
  * q = 1/2 where a short link has no fluid cell behind it; solid cells are
  * not collided and read out as NaN.  They add a 4-byte code per cell to
- * each step's reads.  A fixed immersed body (n_markers > 0; Sec. 2.2 in 3D,
- * desired velocity 0) runs the multi-direct forcing loop before every
+ * each step's reads.  An immersed body (n_markers > 0; Sec. 2.2 in 3D, fixed
+ * or in the pitch/plunge motion of motion_p, desired velocity
+ * r(t + 1) - r(t)) runs the multi-direct forcing loop before every
  * collision with Peskin's kernel (Eq. (14)) in each axis: N_F passes of
- * U_j, rho_j interpolation over the 4x4x4 taps, g_j = 2 rho_j (0 - U_j),
+ * U_j, rho_j interpolation over the 4x4x4 taps, g_j = 2 rho_j (u_d - U_j),
  * spreading g_j w dA_j in marker order and u += dF / (2 rho); the cells
  * collide with F_ext + F.  It needs a fully periodic box without solid
- * cells, and stencils that do not wrap across a face.  D3Q19: rest (w = 1/3), 6 axis (1/18) and 12 edge
+ * cells.  Each step's stencils must stay inside the box (no wrap) and
+ * inside a box of at most ibm_box_cells cells; a step where they do not
+ * runs without the body force and sbt3_synchronize reports
+ * SBT_ERR_MARKER_OUTSIDE.  D3Q19: rest (w = 1/3), 6 axis (1/18) and 12 edge
  * (1/36) velocities; D3Q27 adds the 8 corners (rest 8/27, axis 2/27, edge
  * 1/54, corner 1/216); c_s^2 = 1/3 for both.  Direction order: rest,
  * +x -x +y -y +z -z, the edges (+-1, +-1, 0), (+-1, 0, +-1), (0, +-1, +-1),
@@ -68,6 +72,17 @@ typedef struct {
                                       i + 1/2); read during plan / create           */
     const double *marker_dA;       /* [n_markers] surface element of each marker     */
     int32_t mdf_iters;             /* N_F of the forcing loop                        */
+    int64_t ibm_box_cells;         /* capacity (>= 64) of the box of stencil cells
+                                      the body's forcing works in                    */
+    int32_t body_motion;           /* 0: fixed (marker_xyz absolute); 1: pitch about
+                                      the y axis and plunge along z (marker_xyz in
+                                      the body frame)                                */
+    double motion_p[10];           /* motion 1: x0, y0, z0, alpha0, A_pitch, A0, T,
+                                      phi, U_ref, chord: t* = t U_ref / chord,
+                                      theta = 2 pi t* / T, alpha = alpha0 - A_pitch
+                                      sin(theta + phi), centre (x0, y0, z0 + (A0/2)
+                                      cos theta), X = xc + xb cos a + zb sin a,
+                                      Y = yc + yb, Z = zc - xb sin a + zb cos a      */
 } sbt3_desc;
 
 /* Device bytes sbt3_create needs.  Host only.  Errors: SBT_ERR_ARG. */
@@ -88,7 +103,9 @@ sbt_status sbt3_init_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, const double *r
                           const double *uy, const double *uz);
 /* Advance n steps.  Asynchronous, stream-ordered. */
 sbt_status sbt3_step(sbt3_ctx *ctx, int32_t n);
-/* Wait for the stream; SBT_ERR_NONFINITE if a density became NaN or Inf. */
+/* Wait for the stream; SBT_ERR_NONFINITE if a density became NaN or Inf,
+ * SBT_ERR_MARKER_OUTSIDE if a body's stencils left the box or outgrew
+ * ibm_box_cells. */
 sbt_status sbt3_synchronize(sbt3_ctx *ctx);
 /* Body force F_s = -sum_j F_j dA_j of the last completed step (sum over
  * the N_F passes of each marker's force).  Synchronises.  SBT_ERR_STATE

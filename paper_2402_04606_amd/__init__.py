@@ -58,7 +58,8 @@ class Desc3(C.Structure):
                 ("lattice", C.c_int32), ("walls_z", C.c_int32), ("wall_u", (C.c_double * 3) * 2),
                 ("solid_mask", C.POINTER(C.c_uint8)), ("solid_q", C.POINTER(C.c_double)),
                 ("n_markers", C.c_int32), ("marker_xyz", C.POINTER(C.c_double)),
-                ("marker_dA", C.POINTER(C.c_double)), ("mdf_iters", C.c_int32)]
+                ("marker_dA", C.POINTER(C.c_double)), ("mdf_iters", C.c_int32),
+                ("ibm_box_cells", C.c_int64), ("body_motion", C.c_int32), ("motion_p", C.c_double * 10)]
 
 
 class CaseDesc(C.Structure):
@@ -402,10 +403,12 @@ class Sim:
 
 
 class Sim3:
-    """A D3Q19 periodic box (``workloads.Workload3``) on cuda:0: torch device
-    buffer, torch's current stream."""
+    """A D3Q19/D3Q27 box (``workloads.Workload3``) on cuda:0: torch device
+    buffer, torch's current stream.  ``box_cells`` overrides the capacity of
+    an immersed body's stencil box (default: the body's reach over its
+    motion plus the stencil, capped at the lattice)."""
 
-    def __init__(self, wl, storage="f64", stream=None, slab=None):
+    def __init__(self, wl, storage="f64", stream=None, slab=None, box_cells=None):
         import torch
         self.wl = wl
         self.storage = STORAGE[storage] if isinstance(storage, str) else storage
@@ -435,6 +438,18 @@ class Sim3:
             d.marker_xyz = _dp(xyz)
             d.marker_dA = _dp(da)
             d.mdf_iters = int(iters)
+            # the box of stencil cells: the body's reach (over its motion) plus
+            # the 4-cell stencil, capped at the whole lattice
+            kind, params = getattr(wl, "motion", (0, None))
+            ext = [np.ptp(np.asarray(v, dtype=np.float64)) for v in (X, Y, Z)]
+            if kind == 1:
+                r = float(np.max(np.hypot(X, Z)))
+                ext = [2 * r, ext[1], 2 * r + abs(params[5])]
+            cells = int(np.prod([int(np.ceil(e)) + 6 for e in ext]))
+            d.ibm_box_cells = box_cells or max(64, min(cells, wl.nx * wl.ny * wl.nz))
+            d.body_motion = int(kind)
+            for i, v in enumerate(params or ()):
+                d.motion_p[i] = float(v)
         for a, u in enumerate(getattr(wl, "wall_u", ((0.0,) * 3,) * 2)):
             for k in range(3):
                 d.wall_u[a][k] = u[k]

@@ -77,8 +77,8 @@ struct Params {
   long long n;
   double tau, pre, rho0, F[3];
   double uw[2][3];             // bottom and top wall velocities (walls across z)
-  const double *ibm_F;         // immersed body: force density [3][box] over the box below, or null
-  int bx0, by0, bz0, bwx, bwy, bwz;
+  const double *ibm_F;         // immersed body: force density [3][box] over its current box, or null
+  const int *ibm_box;          // [6] that box: origin x, y, z and size x, y, z
   float om_f, pre_f, rho0_f, F_f[3];
 };
 
@@ -164,10 +164,11 @@ __device__ __forceinline__ auto bouzidi3(const Params &p, const typename Store3<
 // Index of cell c in the immersed body's force box, or -1 (no body, or outside).
 __device__ __forceinline__ long long ibm_box_index(const Params &p, long long c) {
   if (!p.ibm_F) return -1;
-  const int x = (int)(c % p.nx) - p.bx0, y = (int)((c / p.nx) % p.ny) - p.by0;
-  const int z = (int)(c / ((long long)p.nx * p.ny)) - p.bz0;
-  if (x < 0 || y < 0 || z < 0 || x >= p.bwx || y >= p.bwy || z >= p.bwz) return -1;
-  return ((long long)z * p.bwy + y) * p.bwx + x;
+  const int *B = p.ibm_box;
+  const int x = (int)(c % p.nx) - B[0], y = (int)((c / p.nx) % p.ny) - B[1];
+  const int z = (int)(c / ((long long)p.nx * p.ny)) - B[2];
+  if (x < 0 || y < 0 || z < 0 || x >= B[3] || y >= B[4] || z >= B[5]) return -1;
+  return ((long long)z * B[4] + y) * B[3] + x;
 }
 
 template <int Q>
@@ -220,7 +221,7 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
     double Fx = p.F[0], Fy = p.F[1], Fz = p.F[2];
     const long long bi = ibm_box_index(p, c);
     if (bi >= 0) {
-      const long long bn = (long long)p.bwx * p.bwy * p.bwz;
+      const long long bn = (long long)p.ibm_box[3] * p.ibm_box[4] * p.ibm_box[5];
       Fx = Fx + p.ibm_F[bi];
       Fy = Fy + p.ibm_F[bn + bi];
       Fz = Fz + p.ibm_F[2 * bn + bi];
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
     float Fx = p.F_f[0], Fy = p.F_f[1], Fz = p.F_f[2];
     const long long bi = ibm_box_index(p, c);
     if (bi >= 0) {
-      const long long bn = (long long)p.bwx * p.bwy * p.bwz;
+      const long long bn = (long long)p.ibm_box[3] * p.ibm_box[4] * p.ibm_box[5];
       Fx += (float)p.ibm_F[bi];
       Fy += (float)p.ibm_F[bn + bi];
       Fz += (float)p.ibm_F[2 * bn + bi];
@@ -290,38 +291,128 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
   }
 }
 
-// Tables of a fixed immersed body (built on the host from its markers).
+// An immersed body: its markers and the device work arrays of its forcing
+// loop.  Marker positions are rebuilt every step from the motion law.
 struct Ibm3 {
-  int n, iters, K;             // markers, N_F, stencil cells
-  const long long *scell;      // [K] lattice index of each stencil cell
-  const int *tapk;             // [n][64] stencil index of each tap (z outer, y, x inner)
-  const double *tapw;          // [n][64] tap weight phi_x (phi_y phi_z)
-  const int *cstart;           // [K + 1] contributor list of each stencil cell
-  const int *cj;               // [E] contributing marker, ascending
-  const double *cw;            // [E] its tap weight
+  int n, iters, kind;          // markers, N_F, motion (0 fixed, 1 pitch about y + plunge along z)
+  long long cap;               // cells the box arrays hold
+  double mp[10];               // kind 1: x0, y0, z0, alpha0, A_pitch, A0, T, phi, U_ref, chord
+  const double *xb, *yb, *zb;  // [n] absolute (kind 0) or body-frame (kind 1) positions
   const double *dA;            // [n] surface element
-  double *rho, *u, *F;         // [K], [3][K], [3][K] work arrays
-  double *g, *ft;              // [3][n] force of the iteration, total force per marker
-  double *Fbox;                // [3][box] force density read by the step kernel
-  double *fs;                  // [6] body force F_s of this forcing loop, then of the previous one
+  int *tap;                    // [3][n] first tap cell per axis
+  double *phi;                 // [12][n] the 4 weights per axis (x, y, z)
+  double *ud;                  // [3][n] desired velocity r(t + 1) - r(t)
+  double *rho, *u, *F;         // [cap], [3][cap], [3][cap] box moments and force
+  double *g, *ft;              // [3][n] force of the pass, total force per marker
+  double *Fbox;                // [3][cap] force density read by the step kernel
+  int *box;                    // [6] the box: origin and size
+  double *fs;                  // [6] F_s of this forcing loop, then of the previous one
+  int *err;                    // set when the box outgrows cap
 };
 
-// Sec. 2.2 in 3D for a fixed body (desired velocity 0), one workgroup: the
-// moments of the stencil cells from the state the next step collides
-// (gathered when the lattice holds post-collision populations), then N_F
-// passes of interpolation (U_j, rho_j), force g_j = 2 rho_j (0 - U_j) and
-// spreading in marker order with the velocity correction dF / (2 rho);
-// finally F_s = -sum_j F_j dA_j and the force density of the box.
+__device__ __forceinline__ double peskin3d(double r) {
+#pragma clang fp contract(off)
+  const double a = fabs(r);
+  if (a <= 1.0) return 0.125 * (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a));
+  if (a <= 2.0) return 0.125 * (5.0 - 2.0 * a - sqrt(-7.0 + 12.0 * a - 4.0 * a * a));
+  return 0.0;
+}
+
+// Position of marker j at step t (the Sec. 3.6 law in the x-z plane for
+// kind 1: t* = t U_ref / c, theta = 2 pi t* / T, alpha = alpha0 -
+// A_pitch sin(theta + phi), centre (x0, y0, z0 + (A0/2) cos theta),
+// X = xc + xb cos a + zb sin a, Y = yc + yb, Z = zc - xb sin a + zb cos a).
+struct Pose3 {
+  double zc, ca, sa;
+};
+
+__device__ Pose3 pose3(const Ibm3 &b, double t) {
+#pragma clang fp contract(off)
+  Pose3 q;
+  const double *p = b.mp;
+  const double tstar = t * p[8] / p[9];
+  const double theta = 2.0 * M_PI * tstar / p[6];
+  const double alpha = p[3] - p[4] * sin(theta + p[7]);
+  q.zc = p[2] + 0.5 * p[5] * cos(theta);
+  q.ca = cos(alpha);
+  q.sa = sin(alpha);
+  return q;
+}
+
+__device__ __forceinline__ void marker3(const Ibm3 &b, const Pose3 &q, int j, double &X, double &Y, double &Z) {
+#pragma clang fp contract(off)
+  if (b.kind == 0) {
+    X = b.xb[j];
+    Y = b.yb[j];
+    Z = b.zb[j];
+    return;
+  }
+  X = b.mp[0] + b.xb[j] * q.ca + b.zb[j] * q.sa;
+  Y = b.mp[1] + b.yb[j];
+  Z = q.zc - b.xb[j] * q.sa + b.zb[j] * q.ca;
+}
+
+// Sec. 2.2 in 3D, one workgroup, at step t: marker positions and desired
+// velocities, the 4x4x4 taps (Peskin's kernel per axis, weight
+// phi_x (phi_y phi_z), z outer, y, x inner), the box of cells they cover,
+// the moments of the box from the state the next step collides (gathered
+// when the lattice holds post-collision populations); then N_F passes of
+// interpolation (U_j, rho_j), g_j = 2 rho_j (u_d - U_j), spreading over the
+// box in marker order with u += dF / (2 rho); finally F_s = -sum_j F_j dA_j
+// and the box force the step kernel adds.
 template <int ST, int kQ3>
-__global__ __launch_bounds__(1024) void ibm3_kernel(Params p, const void *lat_, int pull, Ibm3 b) {
+__global__ __launch_bounds__(1024) void ibm3_kernel(Params p, const void *lat_, int pull, long long t, Ibm3 b) {
 #pragma clang fp contract(off)
   using S = Store3<ST>;
   using T = typename S::T;
+  __shared__ Pose3 s_pose[2];
+  __shared__ int s_lo[3], s_hi[3];
   const T *lat = static_cast<const T *>(lat_);
-  const int tid = threadIdx.x, nt = blockDim.x;
-  if (tid < 3) b.fs[3 + tid] = b.fs[tid];  // the step this loop precedes is one ahead of the readouts
-  for (int k = tid; k < b.K; k += nt) {
-    const long long c = b.scell[k];
+  const int tid = threadIdx.x, nt = blockDim.x, n = b.n;
+  if (tid < 3) {
+    b.fs[3 + tid] = b.fs[tid];  // the step this loop precedes is one ahead of the readouts
+    s_lo[tid] = 1 << 30;
+    s_hi[tid] = -(1 << 30);
+  }
+  if (b.kind != 0 && tid < 2) s_pose[tid] = pose3(b, (double)(t + tid));
+  __syncthreads();
+  for (int j = tid; j < n; j += nt) {
+    double X, Y, Z, X1, Y1, Z1;
+    marker3(b, s_pose[0], j, X, Y, Z);
+    if (b.kind == 0) {
+      X1 = X;
+      Y1 = Y;
+      Z1 = Z;
+    } else {
+      marker3(b, s_pose[1], j, X1, Y1, Z1);
+    }
+    b.ud[j] = X1 - X;
+    b.ud[n + j] = Y1 - Y;
+    b.ud[2 * n + j] = Z1 - Z;
+    const double P[3] = {X, Y, Z};
+    for (int a = 0; a < 3; ++a) {
+      const int t0 = (int)floor(P[a] - 1.5);
+      b.tap[a * n + j] = t0;
+      for (int k = 0; k < 4; ++k) b.phi[(a * 4 + k) * n + j] = peskin3d(t0 + k + 0.5 - P[a]);
+      atomicMin(&s_lo[a], t0);
+      atomicMax(&s_hi[a], t0 + 4);
+    }
+  }
+  __syncthreads();
+  const int bx0 = s_lo[0], by0 = s_lo[1], bz0 = s_lo[2];
+  const int bwx = s_hi[0] - bx0, bwy = s_hi[1] - by0, bwz = s_hi[2] - bz0;
+  const long long K = (long long)bwx * bwy * bwz;
+  const bool bad = K > b.cap || bx0 < 0 || by0 < 0 || bz0 < 0 || s_hi[0] > p.nx || s_hi[1] > p.ny || s_hi[2] > p.nz;
+  if (bad) {  // no force this step; the host reports the error at the next synchronisation
+    if (tid == 0) {
+      atomicOr(b.err, 2);
+      b.box[3] = b.box[4] = b.box[5] = 0;
+    }
+    return;
+  }
+  for (long long k = tid; k < K; k += nt) {
+    const int x = bx0 + (int)(k % bwx), y = by0 + (int)((k / bwx) % bwy), z = bz0 + (int)(k / ((long long)bwx * bwy));
+    const long long c = ((long long)z * p.ny + y) * p.nx + x;
     const Offsets o = offsets(p, c);
     double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
@@ -335,62 +426,78 @@ __global__ __launch_bounds__(1024) void ibm3_kernel(Params p, const void *lat_, 
     if constexpr (ST != 0) r = p.rho0 + r;
     b.rho[k] = r;
     b.u[k] = (jx + 0.5 * p.F[0]) / r;
-    b.u[b.K + k] = (jy + 0.5 * p.F[1]) / r;
-    b.u[2 * b.K + k] = (jz + 0.5 * p.F[2]) / r;
-    b.F[k] = b.F[b.K + k] = b.F[2 * b.K + k] = 0.0;
+    b.u[b.cap + k] = (jy + 0.5 * p.F[1]) / r;
+    b.u[2 * b.cap + k] = (jz + 0.5 * p.F[2]) / r;
+    b.F[k] = b.F[b.cap + k] = b.F[2 * b.cap + k] = 0.0;
   }
-  for (int j = tid; j < b.n; j += nt) b.ft[j] = b.ft[b.n + j] = b.ft[2 * b.n + j] = 0.0;
+  for (int j = tid; j < n; j += nt) b.ft[j] = b.ft[n + j] = b.ft[2 * n + j] = 0.0;
   __syncthreads();
   for (int it = 0; it < b.iters; ++it) {
-    for (int j = tid; j < b.n; j += nt) {
+    for (int j = tid; j < n; j += nt) {
       double U0 = 0.0, U1 = 0.0, U2 = 0.0, R = 0.0;
-      for (int t = 0; t < 64; ++t) {
-        const int k = b.tapk[j * 64 + t];
-        const double w = b.tapw[j * 64 + t];
-        U0 += b.u[k] * w;
-        U1 += b.u[b.K + k] * w;
-        U2 += b.u[2 * b.K + k] * w;
-        R += b.rho[k] * w;
+      const int i0 = b.tap[j] - bx0, j0 = b.tap[n + j] - by0, k0 = b.tap[2 * n + j] - bz0;
+      for (int cz = 0; cz < 4; ++cz) {
+        const double pz = b.phi[(8 + cz) * n + j];
+        for (int cy = 0; cy < 4; ++cy) {
+          const double pyz = b.phi[(4 + cy) * n + j] * pz;
+          for (int cx = 0; cx < 4; ++cx) {
+            const double w = b.phi[cx * n + j] * pyz;
+            const long long k = ((long long)(k0 + cz) * bwy + (j0 + cy)) * bwx + (i0 + cx);
+            U0 += b.u[k] * w;
+            U1 += b.u[b.cap + k] * w;
+            U2 += b.u[2 * b.cap + k] * w;
+            R += b.rho[k] * w;
+          }
+        }
       }
-      const double g0 = 2.0 * R * (0.0 - U0), g1 = 2.0 * R * (0.0 - U1), g2 = 2.0 * R * (0.0 - U2);
+      const double g0 = 2.0 * R * (b.ud[j] - U0), g1 = 2.0 * R * (b.ud[n + j] - U1);
+      const double g2 = 2.0 * R * (b.ud[2 * n + j] - U2);
       b.g[j] = g0;
-      b.g[b.n + j] = g1;
-      b.g[2 * b.n + j] = g2;
+      b.g[n + j] = g1;
+      b.g[2 * n + j] = g2;
       b.ft[j] += g0;
-      b.ft[b.n + j] += g1;
-      b.ft[2 * b.n + j] += g2;
+      b.ft[n + j] += g1;
+      b.ft[2 * n + j] += g2;
     }
     __syncthreads();
-    for (int k = tid; k < b.K; k += nt) {
+    for (long long k = tid; k < K; k += nt) {
+      const int x = bx0 + (int)(k % bwx), y = by0 + (int)((k / bwx) % bwy), z = bz0 + (int)(k / ((long long)bwx * bwy));
       double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-      for (int e = b.cstart[k]; e < b.cstart[k + 1]; ++e) {
-        const int j = b.cj[e];
-        const double w = b.cw[e];
+      for (int j = 0; j < n; ++j) {
+        const int dx = x - b.tap[j], dy = y - b.tap[n + j], dz = z - b.tap[2 * n + j];
+        if ((unsigned)dx > 3u || (unsigned)dy > 3u || (unsigned)dz > 3u) continue;
+        const double w = b.phi[dx * n + j] * (b.phi[(4 + dy) * n + j] * b.phi[(8 + dz) * n + j]);
         d0 += b.g[j] * w * b.dA[j];
-        d1 += b.g[b.n + j] * w * b.dA[j];
-        d2 += b.g[2 * b.n + j] * w * b.dA[j];
+        d1 += b.g[n + j] * w * b.dA[j];
+        d2 += b.g[2 * n + j] * w * b.dA[j];
       }
       if (d0 == 0.0 && d1 == 0.0 && d2 == 0.0) continue;
       b.F[k] += d0;
-      b.F[b.K + k] += d1;
-      b.F[2 * b.K + k] += d2;
+      b.F[b.cap + k] += d1;
+      b.F[2 * b.cap + k] += d2;
       b.u[k] += d0 / (2.0 * b.rho[k]);
-      b.u[b.K + k] += d1 / (2.0 * b.rho[k]);
-      b.u[2 * b.K + k] += d2 / (2.0 * b.rho[k]);
+      b.u[b.cap + k] += d1 / (2.0 * b.rho[k]);
+      b.u[2 * b.cap + k] += d2 / (2.0 * b.rho[k]);
     }
     __syncthreads();
   }
   if (tid < 3) {
-    double t = 0.0;
-    for (int j = 0; j < b.n; ++j) t -= b.ft[tid * b.n + j] * b.dA[j];
-    b.fs[tid] = t;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s -= b.ft[tid * n + j] * b.dA[j];
+    b.fs[tid] = s;
   }
-  const long long bn = (long long)p.bwx * p.bwy * p.bwz;
-  for (int k = tid; k < b.K; k += nt) {
-    const long long bi = ibm_box_index(p, b.scell[k]);
-    b.Fbox[bi] = b.F[k];
-    b.Fbox[bn + bi] = b.F[b.K + k];
-    b.Fbox[2 * bn + bi] = b.F[2 * b.K + k];
+  if (tid == 0) {
+    b.box[0] = bx0;
+    b.box[1] = by0;
+    b.box[2] = bz0;
+    b.box[3] = bwx;
+    b.box[4] = bwy;
+    b.box[5] = bwz;
+  }
+  for (long long k = tid; k < K; k += nt) {
+    b.Fbox[k] = b.F[k];
+    b.Fbox[K + k] = b.F[b.cap + k];
+    b.Fbox[2 * K + k] = b.F[2 * b.cap + k];
   }
 }
 
@@ -473,7 +580,8 @@ struct sbt3_ctx {
   bool post = false;  // the lattices hold post-collision populations (a step has run)
   hipStream_t stream;
   long long n_records = 0;
-  Ibm3 ibm{};                 // immersed body tables (ibm.n == 0: none)
+  Ibm3 ibm{};                 // immersed body (ibm.n == 0: none)
+  long long ibm_t = 0;        // step of the next forcing loop
 };
 
 namespace {
@@ -490,6 +598,41 @@ sbt_status check_desc(const sbt3_desc *d) {
     return sbt_set_error(SBT_ERR_ARG, "bad immersed body");
   if (d->n_markers > 0 && (d->walls_z || d->solid_mask))
     return sbt_set_error(SBT_ERR_ARG, "an immersed body needs a fully periodic box without solid cells");
+  if (d->n_markers > 0 && (d->ibm_box_cells < 64 || (d->body_motion != 0 && d->body_motion != 1)))
+    return sbt_set_error(SBT_ERR_ARG, "an immersed body needs ibm_box_cells >= 64 and motion 0 or 1");
+  if (d->n_markers > 0 && d->body_motion == 1 && (d->motion_p[6] == 0.0 || d->motion_p[9] == 0.0))
+    return sbt_set_error(SBT_ERR_ARG, "motion period and chord must be nonzero");
+  if (d->n_markers > 0) {
+    // the stencils at t = 0 (every step's are checked again on the device)
+    const int n = d->n_markers;
+    const int dims[3] = {d->nx, d->ny, d->nz};
+    const double *mp = d->motion_p;
+    double ca = 1.0, sa = 0.0, zc = 0.0;
+    if (d->body_motion == 1) {
+      const double alpha = mp[3] - mp[4] * std::sin(mp[7]);
+      ca = std::cos(alpha);
+      sa = std::sin(alpha);
+      zc = mp[2] + 0.5 * mp[5];
+    }
+    long long cells = 1;
+    for (int a = 0; a < 3; ++a) {
+      int lo = 1 << 30, hi = -(1 << 30);
+      for (int j = 0; j < n; ++j) {
+        const double xb = d->marker_xyz[j], yb = d->marker_xyz[n + j], zb = d->marker_xyz[2 * n + j];
+        double P = d->marker_xyz[a * n + j];
+        if (d->body_motion == 1)
+          P = a == 0 ? mp[0] + xb * ca + zb * sa : a == 1 ? mp[1] + yb : zc - xb * sa + zb * ca;
+        if (!std::isfinite(P)) return sbt_set_error(SBT_ERR_ARG, "marker positions must be finite");
+        const int t0 = (int)std::floor(P - 1.5);
+        lo = std::min(lo, t0);
+        hi = std::max(hi, t0 + 4);
+      }
+      if (lo < 0 || hi > dims[a])
+        return sbt_set_error(SBT_ERR_ARG, "an immersed body's stencils must not wrap across a face");
+      cells *= hi - lo;
+    }
+    if (cells > d->ibm_box_cells) return sbt_set_error(SBT_ERR_ARG, "the body's stencil box exceeds ibm_box_cells");
+  }
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(d->fext[k]) || !std::isfinite(d->wall_u[0][k]) || !std::isfinite(d->wall_u[1][k]))
       return sbt_set_error(SBT_ERR_ARG, "body force and wall velocities must be finite");
@@ -556,89 +699,10 @@ sbt_status solid_records(const sbt3_desc *d, std::vector<int32_t> *code, std::ve
   return SBT_OK;
 }
 
-// Peskin's 4-point kernel (Eq. (14), unit spacing).
-double peskin3(double r) {
-  const double a = std::fabs(r);
-  if (a <= 1.0) return 0.125 * (3.0 - 2.0 * a + std::sqrt(1.0 + 4.0 * a - 4.0 * a * a));
-  if (a <= 2.0) return 0.125 * (5.0 - 2.0 * a - std::sqrt(-7.0 + 12.0 * a - 4.0 * a * a));
-  return 0.0;
-}
-
-// Host tables of a fixed immersed body: the 64 taps of each marker (cells
-// from floor(X - 1.5) on, z outer, y, x inner; weight phi_x (phi_y phi_z)),
-// the stencil cells they touch, each cell's contributors in marker order,
-// and the box of cells the stencils cover (no periodic wrap).
-struct BodyTables {
-  std::vector<long long> scell;
-  std::vector<int> tapk, cstart, cj;
-  std::vector<double> tapw, cw;
-  int bx0 = 0, by0 = 0, bz0 = 0, bwx = 0, bwy = 0, bwz = 0;
-};
-
-sbt_status body_tables(const sbt3_desc *d, BodyTables &T) {
-  const int n = d->n_markers, nx = d->nx, ny = d->ny, nz = d->nz;
-  const double *X = d->marker_xyz, *Y = X + n, *Z = X + 2 * n;
-  int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-  for (int j = 0; j < n; ++j) {
-    const int t0[3] = {(int)std::floor(X[j] - 1.5), (int)std::floor(Y[j] - 1.5), (int)std::floor(Z[j] - 1.5)};
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = std::min(lo[a], t0[a]);
-      hi[a] = std::max(hi[a], t0[a] + 4);
-    }
-  }
-  if (lo[0] < 0 || lo[1] < 0 || lo[2] < 0 || hi[0] > nx || hi[1] > ny || hi[2] > nz)
-    return sbt_set_error(SBT_ERR_ARG, "marker stencils must lie inside the box (no periodic wrap)");
-  T.bx0 = lo[0];
-  T.by0 = lo[1];
-  T.bz0 = lo[2];
-  T.bwx = hi[0] - lo[0];
-  T.bwy = hi[1] - lo[1];
-  T.bwz = hi[2] - lo[2];
-  const long long boxn = (long long)T.bwx * T.bwy * T.bwz;
-  std::vector<int> kof(boxn, -1);
-  T.tapk.resize((size_t)n * 64);
-  T.tapw.resize((size_t)n * 64);
-  std::vector<std::vector<std::pair<int, double>>> lists;
-  for (int j = 0; j < n; ++j) {
-    const int i0 = (int)std::floor(X[j] - 1.5), j0 = (int)std::floor(Y[j] - 1.5), k0 = (int)std::floor(Z[j] - 1.5);
-    int t = 0;
-    for (int c = 0; c < 4; ++c) {
-      const double pz = peskin3(k0 + c + 0.5 - Z[j]);
-      for (int b = 0; b < 4; ++b) {
-        const double pyz = peskin3(j0 + b + 0.5 - Y[j]) * pz;
-        for (int a = 0; a < 4; ++a, ++t) {
-          const double w = peskin3(i0 + a + 0.5 - X[j]) * pyz;
-          const long long bi = ((long long)(k0 + c - T.bz0) * T.bwy + (j0 + b - T.by0)) * T.bwx + (i0 + a - T.bx0);
-          int &k = kof[bi];
-          if (k < 0) {
-            k = (int)T.scell.size();
-            T.scell.push_back(((long long)(k0 + c) * ny + (j0 + b)) * nx + (i0 + a));
-            lists.emplace_back();
-          }
-          T.tapk[(size_t)j * 64 + t] = k;
-          T.tapw[(size_t)j * 64 + t] = w;
-          lists[k].push_back({j, w});
-        }
-      }
-    }
-  }
-  T.cstart.assign(1, 0);
-  for (auto &L : lists) {
-    for (auto &e : L) {
-      T.cj.push_back(e.first);
-      T.cw.push_back(e.second);
-    }
-    T.cstart.push_back((int)T.cj.size());
-  }
-  return SBT_OK;
-}
-
-size_t body_bytes(const sbt3_desc *d, const BodyTables &T) {
-  const size_t n = d->n_markers, K = T.scell.size(), E = T.cj.size();
-  const size_t boxn = (size_t)T.bwx * T.bwy * T.bwz;
-  return align256(K * 8) + align256(n * 64 * 4) + align256(n * 64 * 8) + align256((K + 1) * 4) + align256(E * 4) +
-         align256(E * 8) + align256(n * 8) + align256(K * 8) + 2 * align256(3 * K * 8) + 2 * align256(3 * n * 8) +
-         align256(3 * boxn * 8) + align256(6 * 8);
+size_t body_bytes(const sbt3_desc *d) {
+  const size_t n = d->n_markers, cap = (size_t)d->ibm_box_cells;
+  return 4 * align256(n * 8) + align256(3 * n * 4) + align256(12 * n * 8) + 3 * align256(3 * n * 8) +
+         align256(cap * 8) + 3 * align256(3 * cap * 8) + align256(6 * 4) + align256(6 * 8) + align256(4);
 }
 
 size_t plan_bytes(const sbt3_desc *d, long long *stage, long long records) {
@@ -649,11 +713,7 @@ size_t plan_bytes(const sbt3_desc *d, long long *stage, long long records) {
   if (d->solid_mask)
     b += align256((size_t)n * sizeof(int32_t)) + align256((size_t)records * sizeof(uint32_t)) +
          align256((size_t)records * d->lattice * sizeof(double));
-  if (d->n_markers > 0) {
-    BodyTables T;
-    if (body_tables(d, T)) return 0;
-    b += body_bytes(d, T);
-  }
+  if (d->n_markers > 0) b += body_bytes(d);
   return b;
 }
 
@@ -681,14 +741,14 @@ size_t plan_bytes(const sbt3_desc *d, long long *stage, long long records) {
 
 hipError_t launch_ibm(sbt3_ctx &X, int pull) {
   switch (X.d.storage + 4 * (X.d.lattice == 27)) {
-    case 0: hipLaunchKernelGGL((ibm3_kernel<0, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
-    case 1: hipLaunchKernelGGL((ibm3_kernel<1, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
-    case 2: hipLaunchKernelGGL((ibm3_kernel<2, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
-    case 3: hipLaunchKernelGGL((ibm3_kernel<3, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
-    case 4: hipLaunchKernelGGL((ibm3_kernel<0, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
-    case 5: hipLaunchKernelGGL((ibm3_kernel<1, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
-    case 6: hipLaunchKernelGGL((ibm3_kernel<2, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
-    case 7: hipLaunchKernelGGL((ibm3_kernel<3, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm); break;
+    case 0: hipLaunchKernelGGL((ibm3_kernel<0, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
+    case 1: hipLaunchKernelGGL((ibm3_kernel<1, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
+    case 2: hipLaunchKernelGGL((ibm3_kernel<2, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
+    case 3: hipLaunchKernelGGL((ibm3_kernel<3, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
+    case 4: hipLaunchKernelGGL((ibm3_kernel<0, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
+    case 5: hipLaunchKernelGGL((ibm3_kernel<1, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
+    case 6: hipLaunchKernelGGL((ibm3_kernel<2, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
+    case 7: hipLaunchKernelGGL((ibm3_kernel<3, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -713,11 +773,6 @@ sbt_status sbt3_plan(const sbt3_desc *desc, size_t *device_bytes) {
   long long stage, records = 0;
   if (desc->solid_mask) {
     st = solid_records(desc, nullptr, nullptr, nullptr, &records);
-    if (st) return st;
-  }
-  if (desc->n_markers > 0) {
-    BodyTables T;
-    st = body_tables(desc, T);
     if (st) return st;
   }
   *device_bytes = plan_bytes(desc, &stage, records);
@@ -794,13 +849,8 @@ sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, vo
     X->n_records = records;
   }
   p.ibm_F = nullptr;
+  p.ibm_box = nullptr;
   if (desc->n_markers > 0) {
-    BodyTables T;
-    st = body_tables(desc, T);
-    if (st) {
-      delete X;
-      return st;
-    }
     size_t off = 2 * lat + align256((size_t)stage * 4 * sizeof(double)) + 256;
     if (desc->solid_mask)
       off += align256((size_t)p.n * sizeof(int32_t)) + align256((size_t)records * sizeof(uint32_t)) +
@@ -811,46 +861,46 @@ sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, vo
       q += align256(bytes);
       return r;
     };
-    const int n = desc->n_markers, K = (int)T.scell.size();
-    const size_t boxn = (size_t)T.bwx * T.bwy * T.bwz;
+    const int n = desc->n_markers;
+    const size_t cap = (size_t)desc->ibm_box_cells;
     Ibm3 &B = X->ibm;
     B.n = n;
     B.iters = desc->mdf_iters;
-    B.K = K;
-    B.scell = reinterpret_cast<const long long *>(take((size_t)K * 8));
-    B.tapk = reinterpret_cast<const int *>(take((size_t)n * 64 * 4));
-    B.tapw = reinterpret_cast<const double *>(take((size_t)n * 64 * 8));
-    B.cstart = reinterpret_cast<const int *>(take((size_t)(K + 1) * 4));
-    B.cj = reinterpret_cast<const int *>(take(T.cj.size() * 4));
-    B.cw = reinterpret_cast<const double *>(take(T.cw.size() * 8));
-    B.dA = reinterpret_cast<const double *>(take((size_t)n * 8));
-    B.rho = reinterpret_cast<double *>(take((size_t)K * 8));
-    B.u = reinterpret_cast<double *>(take((size_t)3 * K * 8));
-    B.F = reinterpret_cast<double *>(take((size_t)3 * K * 8));
-    B.g = reinterpret_cast<double *>(take((size_t)3 * n * 8));
-    B.ft = reinterpret_cast<double *>(take((size_t)3 * n * 8));
-    B.Fbox = reinterpret_cast<double *>(take(3 * boxn * 8));
+    B.kind = desc->body_motion;
+    B.cap = (long long)cap;
+    for (int i = 0; i < 10; ++i) B.mp[i] = desc->motion_p[i];
+    double *xb = reinterpret_cast<double *>(take(n * 8));
+    double *yb = reinterpret_cast<double *>(take(n * 8));
+    double *zb = reinterpret_cast<double *>(take(n * 8));
+    double *dA = reinterpret_cast<double *>(take(n * 8));
+    B.xb = xb;
+    B.yb = yb;
+    B.zb = zb;
+    B.dA = dA;
+    B.tap = reinterpret_cast<int *>(take(3 * n * 4));
+    B.phi = reinterpret_cast<double *>(take(12 * n * 8));
+    B.ud = reinterpret_cast<double *>(take(3 * n * 8));
+    B.g = reinterpret_cast<double *>(take(3 * n * 8));
+    B.ft = reinterpret_cast<double *>(take(3 * n * 8));
+    B.rho = reinterpret_cast<double *>(take(cap * 8));
+    B.u = reinterpret_cast<double *>(take(3 * cap * 8));
+    B.F = reinterpret_cast<double *>(take(3 * cap * 8));
+    B.Fbox = reinterpret_cast<double *>(take(3 * cap * 8));
+    B.box = reinterpret_cast<int *>(take(6 * 4));
     B.fs = reinterpret_cast<double *>(take(6 * 8));
-    bool ok = hipMemcpy((void *)B.scell, T.scell.data(), (size_t)K * 8, hipMemcpyHostToDevice) == hipSuccess;
-    ok &= hipMemcpy((void *)B.tapk, T.tapk.data(), T.tapk.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
-    ok &= hipMemcpy((void *)B.tapw, T.tapw.data(), T.tapw.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
-    ok &= hipMemcpy((void *)B.cstart, T.cstart.data(), T.cstart.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
-    ok &= hipMemcpy((void *)B.cj, T.cj.data(), T.cj.size() * 4, hipMemcpyHostToDevice) == hipSuccess;
-    ok &= hipMemcpy((void *)B.cw, T.cw.data(), T.cw.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
-    ok &= hipMemcpy((void *)B.dA, desc->marker_dA, (size_t)n * 8, hipMemcpyHostToDevice) == hipSuccess;
-    ok &= hipMemset(B.Fbox, 0, 3 * boxn * 8) == hipSuccess;
+    B.err = X->err;
+    bool ok = hipMemcpy(xb, desc->marker_xyz, n * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(yb, desc->marker_xyz + n, n * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(zb, desc->marker_xyz + 2 * n, n * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemcpy(dA, desc->marker_dA, n * 8, hipMemcpyHostToDevice) == hipSuccess;
+    ok &= hipMemset(B.box, 0, 6 * 4) == hipSuccess;
     ok &= hipMemset(B.fs, 0, 6 * 8) == hipSuccess;
     if (!ok) {
       delete X;
-      return sbt_set_error(SBT_ERR_DEVICE, "immersed-body table upload");
+      return sbt_set_error(SBT_ERR_DEVICE, "immersed-body upload");
     }
     p.ibm_F = B.Fbox;
-    p.bx0 = T.bx0;
-    p.by0 = T.by0;
-    p.bz0 = T.bz0;
-    p.bwx = T.bwx;
-    p.bwy = T.bwy;
-    p.bwz = T.bwz;
+    p.ibm_box = B.box;
   }
   X->d.marker_xyz = nullptr;  // borrowed for this call only
   X->d.marker_dA = nullptr;
@@ -892,14 +942,21 @@ sbt_status sbt3_step(sbt3_ctx *ctx, int32_t n) {
   if (n == 0) return SBT_OK;
   const dim3 grid((unsigned)((X.p.n + kThreads - 1) / kThreads));
   if (!X.post) {  // collide the initial state in place: the lattice then holds f*
-    if (X.ibm.n > 0) HIP3(launch_ibm(X, 0));
+    if (X.ibm.n > 0) {
+      X.ibm_t = 0;
+      HIP3(launch_ibm(X, 0));
+      ++X.ibm_t;
+    }
     HIP3(SBT3_LAUNCH(step3_kernel, X.d.storage, X.d.lattice, grid, X.stream, X.p, (const void *)X.lat[X.cur], X.lat[1 - X.cur], 0,
                      X.err));
     X.cur = 1 - X.cur;
     X.post = true;
   }
   for (int t = 0; t < n; ++t) {
-    if (X.ibm.n > 0) HIP3(launch_ibm(X, 1));
+    if (X.ibm.n > 0) {
+      HIP3(launch_ibm(X, 1));
+      ++X.ibm_t;
+    }
     HIP3(SBT3_LAUNCH(step3_kernel, X.d.storage, X.d.lattice, grid, X.stream, X.p, (const void *)X.lat[X.cur], X.lat[1 - X.cur], 1,
                      X.err));
     X.cur = 1 - X.cur;
@@ -914,7 +971,8 @@ sbt_status sbt3_synchronize(sbt3_ctx *ctx) {
   HIP3(hipMemcpy(&e, ctx->err, sizeof(int), hipMemcpyDeviceToHost));
   if (e) {
     HIP3(hipMemset(ctx->err, 0, sizeof(int)));
-    return sbt_set_error(SBT_ERR_NONFINITE, "a density became NaN or Inf");
+    if (e & 1) return sbt_set_error(SBT_ERR_NONFINITE, "a density became NaN or Inf");
+    return sbt_set_error(SBT_ERR_MARKER_OUTSIDE, "the immersed body's stencils outgrew ibm_box_cells or left the box");
   }
   return SBT_OK;
 }

@@ -135,6 +135,7 @@ def test_3d_body_and_solid_validation(pkg):
             da = np.ascontiguousarray(dA)
             keep += [xyz, da]
             d.n_markers, d.mdf_iters = len(X), it
+            d.ibm_box_cells = wl.nx * wl.ny * wl.nz
             d.marker_xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
             d.marker_dA = da.ctypes.data_as(C.POINTER(C.c_double))
         if wl.solid is not None:
@@ -154,6 +155,45 @@ def test_3d_body_and_solid_validation(pkg):
     assert plan(W.sphere3(16, r=3.0))[0] == 0
     m, q = W.sphere3(16, r=3.0).solid
     assert plan(W.sphere3(16, r=3.0).replace(solid=(m, np.zeros_like(q))))[0] == -1
+
+
+def test_3d_moving_body_validation(pkg):
+    """sbt3_plan rejects a moving body with an unknown motion, a zero period
+    or chord, a box capacity below 64 cells or below the stencil box, and
+    a pose at t = 0 whose stencils wrap; the binding sizes the box from the
+    body's reach over its motion."""
+    import ctypes as C
+    import numpy as np
+
+    wl = W.flapping_ellipsoid3(32)
+
+    def plan(kind=1, params=None, cap=None, shift=0.0):
+        X, Y, Z, dA, it = wl.body
+        kind_, p = wl.motion
+        p = list(p if params is None else params)
+        p[0] += shift
+        d = pkg.Desc3()
+        d.nx, d.ny, d.nz, d.tau, d.rho0, d.storage, d.lattice = wl.nx, wl.ny, wl.nz, wl.tau, 1.0, pkg.F32, 19
+        xyz = np.ascontiguousarray(np.concatenate([X, Y, Z]))
+        da = np.ascontiguousarray(dA)
+        d.n_markers, d.mdf_iters = len(X), it
+        d.marker_xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
+        d.marker_dA = da.ctypes.data_as(C.POINTER(C.c_double))
+        d.ibm_box_cells = wl.nx * wl.ny * wl.nz if cap is None else cap
+        d.body_motion = kind
+        for i, v in enumerate(p):
+            d.motion_p[i] = v
+        n = C.c_size_t()
+        return pkg.lib().sbt3_plan(C.byref(d), C.byref(n))
+
+    assert plan() == 0
+    assert plan(kind=2) == -1
+    p = list(wl.motion[1])
+    assert plan(params=p[:6] + [0.0] + p[7:]) == -1          # period T = 0
+    assert plan(params=p[:9] + [0.0]) == -1                   # chord = 0
+    assert plan(cap=32) == -1
+    assert plan(cap=100) == -1                                # below the stencil box
+    assert plan(shift=-12.0) == -1                            # stencils wrap across x = 0
 
 
 def test_rescale_rejects_unit_tau(pkg):

@@ -866,3 +866,46 @@ def test_3d_immersed_sphere(env, storage, tol, q):
     if storage == "f64":
         assert all(np.array_equal(a, b) for a, b in zip(g.fields(), o.fields()))
         assert np.array_equal(fg, fo)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("storage,tol", [("f64", TOL64), ("f32", 2e-5)])
+def test_3d_flapping_ellipsoid(env, storage, tol, q):
+    """An IBM ellipsoid pitching about y and plunging along z in a uniform
+    stream (400 markers, N_F = 3, 240-step period): the forcing loop
+    rebuilds the markers, desired velocities, taps and box every step.
+    Fields and body force against the oracle over half a period."""
+    P, O = env
+    wl = W.flapping_ellipsoid3(32, lattice=q)
+    print(f"case {wl.name} D3Q{q} {storage}", flush=True)
+    g = P.Sim3(wl, storage)
+    o = O.Oracle3Sim(wl)
+    for _ in range(3):
+        g.step(40)
+        g.synchronize()
+        o.step(40)
+        e = rel_l2_3(g.fields(), o.fields())
+        fg, fo = g.body_force(), o.body_force()
+        ef = np.abs(fg - fo).max() / np.abs(fo).max()
+        print(f"  rel L2 u {e:.3e}  body force {fg}  rel err {ef:.3e}", flush=True)
+        assert e <= tol and ef <= max(tol, 1e-12) * 10
+    g.close()
+
+
+def test_3d_moving_body_box_overflow(env):
+    """A moving body whose stencil box outgrows the capacity the caller gave
+    (the t = 0 box exactly): the forcing loop skips the force and the next
+    synchronisation reports SBT_ERR_MARKER_OUTSIDE."""
+    P, _ = env
+    wl = W.flapping_ellipsoid3(32)
+    X, Y, Z, dA, it = wl.body
+    p = wl.motion[1]
+    ca, sa = math.cos(p[3] - p[4] * math.sin(p[7])), math.sin(p[3] - p[4] * math.sin(p[7]))
+    zc = p[2] + 0.5 * p[5]
+    pos = (p[0] + X * ca + Z * sa, p[1] + Y, zc - X * sa + Z * ca)
+    cells = int(np.prod([np.floor(v - 1.5).max() - np.floor(v - 1.5).min() + 4 for v in pos]))
+    g = P.Sim3(wl, "f32", box_cells=cells)
+    g.step(60)
+    with pytest.raises(P.SbtError, match="ibm_box_cells"):
+        g.synchronize()
+    g.close()
