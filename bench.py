@@ -145,12 +145,19 @@ def cpu_baseline(wls, budget_s, V):
 
 def bench3d(args, P, W):
     """D3Q19 / D3Q27 periodic box (box3d = 512^3 D3Q19, box3d_q27 = 512^3
-    D3Q27, box3d_256 = 256^3 D3Q19): MLUPS and the fused kernel's bandwidth
-    from HIP events on the stream it runs on."""
+    D3Q27, box3d_256 = 256^3 D3Q19; flap3d = 256^3 D3Q19 with a pitching and
+    plunging IBM ellipsoid of chord 48 and 2400 markers in a uniform stream):
+    MLUPS and the bandwidth of the whole step (for flap3d including the
+    forcing loop's launches) from HIP events on the stream it runs on."""
     import torch
-    n = 256 if args.workload == "box3d_256" else 512
+    n = 256 if args.workload in ("box3d_256", "flap3d") else 512
     q = 27 if args.workload == "box3d_q27" else 19
-    wl = W.tgv3(n, nz=n).replace(lattice=q)
+    if args.workload == "flap3d":
+        wl = W.flapping_ellipsoid3(n, chord=48.0, n_markers=2400, U=0.05, tau=0.6)
+        name = f"d3q19_box_{n}^3_flapping_ellipsoid_chord48_2400_markers"
+    else:
+        wl = W.tgv3(n, nz=n).replace(lattice=q)
+        name = f"d3q{q}_box_{n}^3_periodic_vortex"
     sim = P.Sim3(wl, args.storage)
     sim.step(args.warmup)
     sim.synchronize()
@@ -175,16 +182,17 @@ def bench3d(args, P, W):
         "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.storage == "f64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"d3q{q}_box_{n}^3_periodic_vortex", "storage": args.storage,
+        "config": {"workload": name, "storage": args.storage,
                    "updates_per_step": ups, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic_3d(args.storage) if (n, q) == (512, 19) else None,
-                     "kernel": f"step3_kernel (fused D3Q{q} pull stream + collide)",
+                     "kernel": f"step3_kernel (fused D3Q{q} pull stream + collide)" + (
+                         " + the forcing loop's kernels (stream time per step)" if args.workload == "flap3d" else ""),
                      "bytes_per_update": 2 * q * s, "algorithmic_bytes_per_launch": algo,
                      "avg_launch_us": round(launch_ms * 1e3, 2)},
     }
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload != "flap3d":
         import oracle
         m = 64
         o = oracle.Oracle3Sim(W.tgv3(m, nz=m).replace(lattice=q))
@@ -244,7 +252,7 @@ def main():
 
     import paper_2402_04606_amd as P
     import workloads as W
-    if args.workload.startswith("box3d"):
+    if args.workload.startswith("box3d") or args.workload == "flap3d":
         return bench3d(args, P, W)
     wls, wname = workload_list(args.workload)
     if args.collision == "mrt":

@@ -292,7 +292,8 @@ __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *s
 }
 
 // An immersed body: its markers and the device work arrays of its forcing
-// loop.  Marker positions are rebuilt every step from the motion law.
+// loop.  Marker positions are rebuilt every step from the motion law.  The
+// box arrays hold K = box[3] box[4] box[5] <= cap cells, x fastest.
 struct Ibm3 {
   int n, iters, kind;          // markers, N_F, motion (0 fixed, 1 pitch about y + plunge along z)
   long long cap;               // cells the box arrays hold
@@ -302,12 +303,12 @@ struct Ibm3 {
   int *tap;                    // [3][n] first tap cell per axis
   double *phi;                 // [12][n] the 4 weights per axis (x, y, z)
   double *ud;                  // [3][n] desired velocity r(t + 1) - r(t)
-  double *rho, *u, *F;         // [cap], [3][cap], [3][cap] box moments and force
+  double *rho, *u;             // [K], [3][K] box moments
   double *g, *ft;              // [3][n] force of the pass, total force per marker
-  double *Fbox;                // [3][cap] force density read by the step kernel
-  int *box;                    // [6] the box: origin and size
-  double *fs;                  // [6] F_s of this forcing loop, then of the previous one
-  int *err;                    // set when the box outgrows cap
+  double *Fbox;                // [3][K] force density the step kernel adds
+  int *box;                    // [6] the box: origin and size (size 0: no force this step)
+  double *fs;                  // [6]: [3..5] F_s of the previous forcing loop
+  int *err;                    // bit 2: the box outgrew cap or left the lattice
 };
 
 __device__ __forceinline__ double peskin3d(double r) {
@@ -352,25 +353,52 @@ __device__ __forceinline__ void marker3(const Ibm3 &b, const Pose3 &q, int j, do
   Z = q.zc - b.xb[j] * q.sa + b.zb[j] * q.ca;
 }
 
-// Sec. 2.2 in 3D, one workgroup, at step t: marker positions and desired
-// velocities, the 4x4x4 taps (Peskin's kernel per axis, weight
-// phi_x (phi_y phi_z), z outer, y, x inner), the box of cells they cover,
-// the moments of the box from the state the next step collides (gathered
-// when the lattice holds post-collision populations); then N_F passes of
-// interpolation (U_j, rho_j), g_j = 2 rho_j (u_d - U_j), spreading over the
-// box in marker order with u += dF / (2 rho); finally F_s = -sum_j F_j dA_j
-// and the box force the step kernel adds.
-template <int ST, int kQ3>
-__global__ __launch_bounds__(1024) void ibm3_kernel(Params p, const void *lat_, int pull, long long t, Ibm3 b) {
+__device__ __forceinline__ long long box_cells(const int *B) { return (long long)B[3] * B[4] * B[5]; }
+
+// Sec. 2.2 in 3D, the forcing loop before the collision of step t, as a
+// chain of launches on the stream: ibm3_pose_kernel (markers, desired
+// velocities, 4x4x4 taps with weight phi_x (phi_y phi_z), the box they
+// cover), ibm3_moments_kernel (rho, u of the box cells from the state the
+// step collides), then N_F times ibm3_interp_kernel (U_j, rho_j over the
+// taps, z outer, y, x inner; g_j = 2 rho_j (u_d - U_j)) and
+// ibm3_spread_kernel (each box cell sums g_j phi dA_j over the markers in
+// marker order, then F += dF, u += dF / (2 rho)).
+//
+// One workgroup.  First F_s of the previous loop, -sum_j F_j dA_j in marker
+// order, into fs[3..5] (the step about to run is one ahead of the readouts);
+// then this loop's markers and box.
+constexpr int kPoseThreads = 1024;
+
+__global__ __launch_bounds__(kPoseThreads) void ibm3_pose_kernel(Params p, long long t, Ibm3 b) {
 #pragma clang fp contract(off)
-  using S = Store3<ST>;
-  using T = typename S::T;
   __shared__ Pose3 s_pose[2];
   __shared__ int s_lo[3], s_hi[3];
-  const T *lat = static_cast<const T *>(lat_);
-  const int tid = threadIdx.x, nt = blockDim.x, n = b.n;
+  __shared__ double s_prod[3][kPoseThreads];
+  const int tid = threadIdx.x, nt = kPoseThreads, n = b.n;
+  // the products F_j dA_j are formed in parallel, chunk by chunk, and
+  // summed in marker order by one thread per component
+  double fsum = 0.0;
+  for (int j0 = 0; j0 < n; j0 += nt) {
+    const int j = j0 + tid;
+    if (j < n)
+      for (int a = 0; a < 3; ++a) s_prod[a][tid] = b.ft[a * n + j] * b.dA[j];
+    __syncthreads();
+    if (tid < 3) {
+      const int m = min(nt, n - j0);
+      int i = 0;
+      for (; i + 8 <= m; i += 8) {  // loads ahead of the (ordered) subtractions
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = s_prod[tid][i + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) fsum -= v[q];
+      }
+      for (; i < m; ++i) fsum -= s_prod[tid][i];
+    }
+    __syncthreads();
+  }
   if (tid < 3) {
-    b.fs[3 + tid] = b.fs[tid];  // the step this loop precedes is one ahead of the readouts
+    b.fs[3 + tid] = fsum;
     s_lo[tid] = 1 << 30;
     s_hi[tid] = -(1 << 30);
   }
@@ -389,6 +417,7 @@ __global__ __launch_bounds__(1024) void ibm3_kernel(Params p, const void *lat_, 
     b.ud[j] = X1 - X;
     b.ud[n + j] = Y1 - Y;
     b.ud[2 * n + j] = Z1 - Z;
+    b.ft[j] = b.ft[n + j] = b.ft[2 * n + j] = 0.0;
     const double P[3] = {X, Y, Z};
     for (int a = 0; a < 3; ++a) {
       const int t0 = (int)floor(P[a] - 1.5);
@@ -399,105 +428,165 @@ __global__ __launch_bounds__(1024) void ibm3_kernel(Params p, const void *lat_, 
     }
   }
   __syncthreads();
-  const int bx0 = s_lo[0], by0 = s_lo[1], bz0 = s_lo[2];
-  const int bwx = s_hi[0] - bx0, bwy = s_hi[1] - by0, bwz = s_hi[2] - bz0;
-  const long long K = (long long)bwx * bwy * bwz;
-  const bool bad = K > b.cap || bx0 < 0 || by0 < 0 || bz0 < 0 || s_hi[0] > p.nx || s_hi[1] > p.ny || s_hi[2] > p.nz;
-  if (bad) {  // no force this step; the host reports the error at the next synchronisation
-    if (tid == 0) {
-      atomicOr(b.err, 2);
-      b.box[3] = b.box[4] = b.box[5] = 0;
-    }
+  if (tid != 0) return;
+  const int dims[3] = {p.nx, p.ny, p.nz};
+  long long K = 1;
+  bool bad = false;
+  for (int a = 0; a < 3; ++a) {
+    K *= s_hi[a] - s_lo[a];
+    bad |= s_lo[a] < 0 || s_hi[a] > dims[a];
+  }
+  if (bad || K > b.cap) {  // no force this step; the host reports it at the next synchronisation
+    atomicOr(b.err, 2);
+    for (int a = 0; a < 6; ++a) b.box[a] = 0;
     return;
   }
-  for (long long k = tid; k < K; k += nt) {
-    const int x = bx0 + (int)(k % bwx), y = by0 + (int)((k / bwx) % bwy), z = bz0 + (int)(k / ((long long)bwx * bwy));
-    const long long c = ((long long)z * p.ny + y) * p.nx + x;
-    const Offsets o = offsets(p, c);
-    double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
-    for (int i = 0; i < kQ3; ++i) {
-      const double f = (double)S::ld(lat[(long long)i * p.n + source(o, c, i, pull)]);
-      r += f;
-      jx += E3X[i] * f;
-      jy += E3Y[i] * f;
-      jz += E3Z[i] * f;
-    }
-    if constexpr (ST != 0) r = p.rho0 + r;
-    b.rho[k] = r;
-    b.u[k] = (jx + 0.5 * p.F[0]) / r;
-    b.u[b.cap + k] = (jy + 0.5 * p.F[1]) / r;
-    b.u[2 * b.cap + k] = (jz + 0.5 * p.F[2]) / r;
-    b.F[k] = b.F[b.cap + k] = b.F[2 * b.cap + k] = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    b.box[a] = s_lo[a];
+    b.box[3 + a] = s_hi[a] - s_lo[a];
   }
-  for (int j = tid; j < n; j += nt) b.ft[j] = b.ft[n + j] = b.ft[2 * n + j] = 0.0;
-  __syncthreads();
-  for (int it = 0; it < b.iters; ++it) {
-    for (int j = tid; j < n; j += nt) {
-      double U0 = 0.0, U1 = 0.0, U2 = 0.0, R = 0.0;
-      const int i0 = b.tap[j] - bx0, j0 = b.tap[n + j] - by0, k0 = b.tap[2 * n + j] - bz0;
-      for (int cz = 0; cz < 4; ++cz) {
-        const double pz = b.phi[(8 + cz) * n + j];
-        for (int cy = 0; cy < 4; ++cy) {
-          const double pyz = b.phi[(4 + cy) * n + j] * pz;
-          for (int cx = 0; cx < 4; ++cx) {
-            const double w = b.phi[cx * n + j] * pyz;
-            const long long k = ((long long)(k0 + cz) * bwy + (j0 + cy)) * bwx + (i0 + cx);
-            U0 += b.u[k] * w;
-            U1 += b.u[b.cap + k] * w;
-            U2 += b.u[2 * b.cap + k] * w;
-            R += b.rho[k] * w;
-          }
+}
+
+// rho, u of box cell k from the state the next step collides (gathered when
+// the lattice holds post-collision populations); clears the box force.
+template <int ST, int kQ3>
+__global__ __launch_bounds__(kThreads) void ibm3_moments_kernel(Params p, const void *lat_, int pull, Ibm3 b) {
+#pragma clang fp contract(off)
+  using S = Store3<ST>;
+  using T = typename S::T;
+  const int *B = b.box;
+  const long long K = box_cells(B), k = (long long)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= K) return;
+  const T *lat = static_cast<const T *>(lat_);
+  const int x = B[0] + (int)(k % B[3]), y = B[1] + (int)((k / B[3]) % B[4]), z = B[2] + (int)(k / ((long long)B[3] * B[4]));
+  const long long c = ((long long)z * p.ny + y) * p.nx + x;
+  const Offsets o = offsets(p, c);
+  double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+  for (int i = 0; i < kQ3; ++i) {
+    const double f = (double)S::ld(lat[(long long)i * p.n + source(o, c, i, pull)]);
+    r += f;
+    jx += E3X[i] * f;
+    jy += E3Y[i] * f;
+    jz += E3Z[i] * f;
+  }
+  if constexpr (ST != 0) r = p.rho0 + r;
+  b.rho[k] = r;
+  b.u[k] = (jx + 0.5 * p.F[0]) / r;
+  b.u[K + k] = (jy + 0.5 * p.F[1]) / r;
+  b.u[2 * K + k] = (jz + 0.5 * p.F[2]) / r;
+  b.Fbox[k] = b.Fbox[K + k] = b.Fbox[2 * K + k] = 0.0;
+}
+
+// One pass's interpolation for marker j: U_j, rho_j, g_j; ft_j += g_j.
+__global__ __launch_bounds__(kThreads) void ibm3_interp_kernel(Ibm3 b) {
+#pragma clang fp contract(off)
+  const int *B = b.box;
+  const int n = b.n, j = blockIdx.x * kThreads + threadIdx.x;
+  if (j >= n || B[3] == 0) return;
+  const int bwx = B[3], bwy = B[4];
+  const int i0 = b.tap[j] - B[0], j0 = b.tap[n + j] - B[1], k0 = b.tap[2 * n + j] - B[2];
+  const long long K = box_cells(B);
+  double U0 = 0.0, U1 = 0.0, U2 = 0.0, R = 0.0;
+  for (int cz = 0; cz < 4; ++cz) {
+    const double pz = b.phi[(8 + cz) * n + j];
+    for (int cy = 0; cy < 4; ++cy) {
+      const double pyz = b.phi[(4 + cy) * n + j] * pz;
+      for (int cx = 0; cx < 4; ++cx) {
+        const double w = b.phi[cx * n + j] * pyz;
+        const long long k = ((long long)(k0 + cz) * bwy + (j0 + cy)) * bwx + (i0 + cx);
+        U0 += b.u[k] * w;
+        U1 += b.u[K + k] * w;
+        U2 += b.u[2 * K + k] * w;
+        R += b.rho[k] * w;
+      }
+    }
+  }
+  const double g0 = 2.0 * R * (b.ud[j] - U0), g1 = 2.0 * R * (b.ud[n + j] - U1);
+  const double g2 = 2.0 * R * (b.ud[2 * n + j] - U2);
+  b.g[j] = g0;
+  b.g[n + j] = g1;
+  b.g[2 * n + j] = g2;
+  b.ft[j] += g0;
+  b.ft[n + j] += g1;
+  b.ft[2 * n + j] += g2;
+}
+
+// One pass's spreading, markers in order.  A workgroup takes 8x8x4 tiles of
+// the box (grid-stride); for each tile it gathers into LDS, chunk by chunk
+// and in marker order, the markers whose 4x4x4 stencil reaches the tile
+// (their taps, weights, g_j and dA_j), and each cell sums over that list.
+constexpr int kSpTx = 8, kSpTy = 8, kSpTz = kThreads / (kSpTx * kSpTy);
+static_assert(kSpTz * kSpTx * kSpTy == kThreads && kThreads % 64 == 0, "tile of one cell per thread");
+
+__global__ __launch_bounds__(kThreads) void ibm3_spread_kernel(Ibm3 b) {
+#pragma clang fp contract(off)
+  __shared__ int s_t[3][kThreads];
+  __shared__ double s_phi[12][kThreads];
+  __shared__ double s_g[3][kThreads];
+  __shared__ double s_dA[kThreads];
+  __shared__ int s_wave[kThreads / 64];
+  const int *B = b.box;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = b.n;
+  const int bwx = B[3], bwy = B[4], bwz = B[5];
+  if (bwx == 0) return;  // the whole grid: no force this step
+  const long long K = box_cells(B);
+  const int ntx = (bwx + kSpTx - 1) / kSpTx, nty = (bwy + kSpTy - 1) / kSpTy, ntz = (bwz + kSpTz - 1) / kSpTz;
+  const int tiles = ntx * nty * ntz;
+  for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int xlo = (tile % ntx) * kSpTx, ylo = ((tile / ntx) % nty) * kSpTy, zlo = (tile / (ntx * nty)) * kSpTz;
+    const int xhi = min(xlo + kSpTx, bwx) - 1, yhi = min(ylo + kSpTy, bwy) - 1, zhi = min(zlo + kSpTz, bwz) - 1;
+    const int x = xlo + tid % kSpTx, y = ylo + (tid / kSpTx) % kSpTy, z = zlo + tid / (kSpTx * kSpTy);
+    const bool live = x <= xhi && y <= yhi && z <= zhi;
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+    for (int j0 = 0; j0 < n; j0 += kThreads) {
+      const int jc = j0 + tid;
+      int tx = 0, ty = 0, tz = 0;
+      bool f = false;
+      if (jc < n) {
+        tx = b.tap[jc] - B[0];
+        ty = b.tap[n + jc] - B[1];
+        tz = b.tap[2 * n + jc] - B[2];
+        f = tx <= xhi && tx + 3 >= xlo && ty <= yhi && ty + 3 >= ylo && tz <= zhi && tz + 3 >= zlo;
+      }
+      const unsigned long long m = __ballot(f);
+      if (lane == 0) s_wave[wave] = __popcll(m);
+      __syncthreads();
+      int base = 0, total = 0;
+      for (int w = 0; w < kThreads / 64; ++w) {
+        base += w < wave ? s_wave[w] : 0;
+        total += s_wave[w];
+      }
+      if (f) {
+        const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+        s_t[0][pos] = tx;
+        s_t[1][pos] = ty;
+        s_t[2][pos] = tz;
+        for (int q = 0; q < 12; ++q) s_phi[q][pos] = b.phi[q * n + jc];
+        for (int a = 0; a < 3; ++a) s_g[a][pos] = b.g[a * n + jc];
+        s_dA[pos] = b.dA[jc];
+      }
+      __syncthreads();
+      if (live) {
+        for (int i = 0; i < total; ++i) {
+          const int dx = x - s_t[0][i], dy = y - s_t[1][i], dz = z - s_t[2][i];
+          if ((unsigned)dx > 3u || (unsigned)dy > 3u || (unsigned)dz > 3u) continue;
+          const double w = s_phi[dx][i] * (s_phi[4 + dy][i] * s_phi[8 + dz][i]);
+          d0 += s_g[0][i] * w * s_dA[i];
+          d1 += s_g[1][i] * w * s_dA[i];
+          d2 += s_g[2][i] * w * s_dA[i];
         }
       }
-      const double g0 = 2.0 * R * (b.ud[j] - U0), g1 = 2.0 * R * (b.ud[n + j] - U1);
-      const double g2 = 2.0 * R * (b.ud[2 * n + j] - U2);
-      b.g[j] = g0;
-      b.g[n + j] = g1;
-      b.g[2 * n + j] = g2;
-      b.ft[j] += g0;
-      b.ft[n + j] += g1;
-      b.ft[2 * n + j] += g2;
+      __syncthreads();  // the lists are rebuilt by the next chunk
     }
-    __syncthreads();
-    for (long long k = tid; k < K; k += nt) {
-      const int x = bx0 + (int)(k % bwx), y = by0 + (int)((k / bwx) % bwy), z = bz0 + (int)(k / ((long long)bwx * bwy));
-      double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-      for (int j = 0; j < n; ++j) {
-        const int dx = x - b.tap[j], dy = y - b.tap[n + j], dz = z - b.tap[2 * n + j];
-        if ((unsigned)dx > 3u || (unsigned)dy > 3u || (unsigned)dz > 3u) continue;
-        const double w = b.phi[dx * n + j] * (b.phi[(4 + dy) * n + j] * b.phi[(8 + dz) * n + j]);
-        d0 += b.g[j] * w * b.dA[j];
-        d1 += b.g[n + j] * w * b.dA[j];
-        d2 += b.g[2 * n + j] * w * b.dA[j];
-      }
-      if (d0 == 0.0 && d1 == 0.0 && d2 == 0.0) continue;
-      b.F[k] += d0;
-      b.F[b.cap + k] += d1;
-      b.F[2 * b.cap + k] += d2;
-      b.u[k] += d0 / (2.0 * b.rho[k]);
-      b.u[b.cap + k] += d1 / (2.0 * b.rho[k]);
-      b.u[2 * b.cap + k] += d2 / (2.0 * b.rho[k]);
-    }
-    __syncthreads();
-  }
-  if (tid < 3) {
-    double s = 0.0;
-    for (int j = 0; j < n; ++j) s -= b.ft[tid * n + j] * b.dA[j];
-    b.fs[tid] = s;
-  }
-  if (tid == 0) {
-    b.box[0] = bx0;
-    b.box[1] = by0;
-    b.box[2] = bz0;
-    b.box[3] = bwx;
-    b.box[4] = bwy;
-    b.box[5] = bwz;
-  }
-  for (long long k = tid; k < K; k += nt) {
-    b.Fbox[k] = b.F[k];
-    b.Fbox[K + k] = b.F[b.cap + k];
-    b.Fbox[2 * K + k] = b.F[2 * b.cap + k];
+    if (!live || (d0 == 0.0 && d1 == 0.0 && d2 == 0.0)) continue;
+    const long long k = ((long long)z * bwy + y) * bwx + x;
+    b.Fbox[k] += d0;
+    b.Fbox[K + k] += d1;
+    b.Fbox[2 * K + k] += d2;
+    b.u[k] += d0 / (2.0 * b.rho[k]);
+    b.u[K + k] += d1 / (2.0 * b.rho[k]);
+    b.u[2 * K + k] += d2 / (2.0 * b.rho[k]);
   }
 }
 
@@ -702,7 +791,7 @@ sbt_status solid_records(const sbt3_desc *d, std::vector<int32_t> *code, std::ve
 size_t body_bytes(const sbt3_desc *d) {
   const size_t n = d->n_markers, cap = (size_t)d->ibm_box_cells;
   return 4 * align256(n * 8) + align256(3 * n * 4) + align256(12 * n * 8) + 3 * align256(3 * n * 8) +
-         align256(cap * 8) + 3 * align256(3 * cap * 8) + align256(6 * 4) + align256(6 * 8) + align256(4);
+         align256(cap * 8) + 2 * align256(3 * cap * 8) + align256(6 * 4) + align256(6 * 8) + align256(4);
 }
 
 size_t plan_bytes(const sbt3_desc *d, long long *stage, long long records) {
@@ -740,16 +829,25 @@ size_t plan_bytes(const sbt3_desc *d, long long *stage, long long records) {
   }()
 
 hipError_t launch_ibm(sbt3_ctx &X, int pull) {
+  const Ibm3 &B = X.ibm;
+  const dim3 gk((unsigned)((B.cap + kThreads - 1) / kThreads)), gn((unsigned)((B.n + kThreads - 1) / kThreads));
+  const dim3 gs((unsigned)std::min<long long>(2048, (B.cap + kThreads - 1) / kThreads));  // tiles, grid-stride
+  hipLaunchKernelGGL(ibm3_pose_kernel, dim3(1), dim3(kPoseThreads), 0, X.stream, X.p, X.ibm_t, B);
+  const void *lat = X.lat[X.cur];
   switch (X.d.storage + 4 * (X.d.lattice == 27)) {
-    case 0: hipLaunchKernelGGL((ibm3_kernel<0, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
-    case 1: hipLaunchKernelGGL((ibm3_kernel<1, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
-    case 2: hipLaunchKernelGGL((ibm3_kernel<2, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
-    case 3: hipLaunchKernelGGL((ibm3_kernel<3, 19>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
-    case 4: hipLaunchKernelGGL((ibm3_kernel<0, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
-    case 5: hipLaunchKernelGGL((ibm3_kernel<1, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
-    case 6: hipLaunchKernelGGL((ibm3_kernel<2, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
-    case 7: hipLaunchKernelGGL((ibm3_kernel<3, 27>), dim3(1), dim3(1024), 0, X.stream, X.p, (const void *)X.lat[X.cur], pull, X.ibm_t, X.ibm); break;
+    case 0: hipLaunchKernelGGL((ibm3_moments_kernel<0, 19>), gk, dim3(kThreads), 0, X.stream, X.p, lat, pull, B); break;
+    case 1: hipLaunchKernelGGL((ibm3_moments_kernel<1, 19>), gk, dim3(kThreads), 0, X.stream, X.p, lat, pull, B); break;
+    case 2: hipLaunchKernelGGL((ibm3_moments_kernel<2, 19>), gk, dim3(kThreads), 0, X.stream, X.p, lat, pull, B); break;
+    case 3: hipLaunchKernelGGL((ibm3_moments_kernel<3, 19>), gk, dim3(kThreads), 0, X.stream, X.p, lat, pull, B); break;
+    case 4: hipLaunchKernelGGL((ibm3_moments_kernel<0, 27>), gk, dim3(kThreads), 0, X.stream, X.p, lat, pull, B); break;
+    case 5: hipLaunchKernelGGL((ibm3_moments_kernel<1, 27>), gk, dim3(kThreads), 0, X.stream, X.p, lat, pull, B); break;
+    case 6: hipLaunchKernelGGL((ibm3_moments_kernel<2, 27>), gk, dim3(kThreads), 0, X.stream, X.p, lat, pull, B); break;
+    case 7: hipLaunchKernelGGL((ibm3_moments_kernel<3, 27>), gk, dim3(kThreads), 0, X.stream, X.p, lat, pull, B); break;
     default: return hipErrorInvalidValue;
+  }
+  for (int it = 0; it < B.iters; ++it) {
+    hipLaunchKernelGGL(ibm3_interp_kernel, gn, dim3(kThreads), 0, X.stream, B);
+    hipLaunchKernelGGL(ibm3_spread_kernel, gs, dim3(kThreads), 0, X.stream, B);
   }
   return hipGetLastError();
 }
@@ -884,7 +982,6 @@ sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, vo
     B.ft = reinterpret_cast<double *>(take(3 * n * 8));
     B.rho = reinterpret_cast<double *>(take(cap * 8));
     B.u = reinterpret_cast<double *>(take(3 * cap * 8));
-    B.F = reinterpret_cast<double *>(take(3 * cap * 8));
     B.Fbox = reinterpret_cast<double *>(take(3 * cap * 8));
     B.box = reinterpret_cast<int *>(take(6 * 4));
     B.fs = reinterpret_cast<double *>(take(6 * 8));
@@ -895,6 +992,7 @@ sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, vo
     ok &= hipMemcpy(dA, desc->marker_dA, n * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok &= hipMemset(B.box, 0, 6 * 4) == hipSuccess;
     ok &= hipMemset(B.fs, 0, 6 * 8) == hipSuccess;
+    ok &= hipMemset(B.ft, 0, 3 * n * 8) == hipSuccess;
     if (!ok) {
       delete X;
       return sbt_set_error(SBT_ERR_DEVICE, "immersed-body upload");
