@@ -307,6 +307,7 @@ struct Ibm3 {
   double *g, *ft;              // [3][n] force of the pass, total force per marker
   double *Fbox;                // [3][K] force density the step kernel adds
   int *box;                    // [6] the box: origin and size (size 0: no force this step)
+  int *lohi;                   // [6] tap bounds reduced over the markers
   double *fs;                  // [6]: [3..5] F_s of the previous forcing loop
   int *err;                    // bit 2: the box outgrew cap or left the lattice
 };
@@ -356,27 +357,24 @@ __device__ __forceinline__ void marker3(const Ibm3 &b, const Pose3 &q, int j, do
 __device__ __forceinline__ long long box_cells(const int *B) { return (long long)B[3] * B[4] * B[5]; }
 
 // Sec. 2.2 in 3D, the forcing loop before the collision of step t, as a
-// chain of launches on the stream: ibm3_pose_kernel (markers, desired
-// velocities, 4x4x4 taps with weight phi_x (phi_y phi_z), the box they
-// cover), ibm3_moments_kernel (rho, u of the box cells from the state the
-// step collides), then N_F times ibm3_interp_kernel (U_j, rho_j over the
-// taps, z outer, y, x inner; g_j = 2 rho_j (u_d - U_j)) and
-// ibm3_spread_kernel (each box cell sums g_j phi dA_j over the markers in
-// marker order, then F += dF, u += dF / (2 rho)).
-//
-// One workgroup.  First F_s of the previous loop, -sum_j F_j dA_j in marker
-// order, into fs[3..5] (the step about to run is one ahead of the readouts);
-// then this loop's markers and box.
+// chain of launches on the stream: ibm3_fs_kernel (F_s of the previous
+// loop), ibm3_markers_kernel (markers, desired velocities, 4x4x4 taps with
+// weight phi_x (phi_y phi_z)), ibm3_box_kernel (the box they cover),
+// ibm3_moments_kernel (rho, u of the box cells from the state the step
+// collides), then N_F times ibm3_interp_kernel (U_j, rho_j over the taps,
+// z outer, y, x inner; g_j = 2 rho_j (u_d - U_j)) and ibm3_spread_kernel
+// (each box cell sums g_j phi dA_j over the markers in marker order, then
+// F += dF, u += dF / (2 rho)).
 constexpr int kPoseThreads = 1024;
 
-__global__ __launch_bounds__(kPoseThreads) void ibm3_pose_kernel(Params p, long long t, Ibm3 b) {
+// F_s of the previous loop, -sum_j F_j dA_j in marker order, into fs[3..5]
+// (the step about to run is one ahead of the readouts): the products are
+// formed in parallel chunk by chunk and summed in order by one thread per
+// component.  Also resets the box bounds the marker kernel reduces into.
+__global__ __launch_bounds__(kPoseThreads) void ibm3_fs_kernel(Ibm3 b) {
 #pragma clang fp contract(off)
-  __shared__ Pose3 s_pose[2];
-  __shared__ int s_lo[3], s_hi[3];
   __shared__ double s_prod[3][kPoseThreads];
   const int tid = threadIdx.x, nt = kPoseThreads, n = b.n;
-  // the products F_j dA_j are formed in parallel, chunk by chunk, and
-  // summed in marker order by one thread per component
   double fsum = 0.0;
   for (int j0 = 0; j0 < n; j0 += nt) {
     const int j = j0 + tid;
@@ -399,12 +397,25 @@ __global__ __launch_bounds__(kPoseThreads) void ibm3_pose_kernel(Params p, long 
   }
   if (tid < 3) {
     b.fs[3 + tid] = fsum;
+    b.lohi[tid] = 1 << 30;
+    b.lohi[3 + tid] = -(1 << 30);
+  }
+}
+
+// Marker j at step t: position, desired velocity, taps and weights; clears
+// its force total; the workgroup's tap bounds go into lohi.
+__global__ __launch_bounds__(kThreads) void ibm3_markers_kernel(long long t, Ibm3 b) {
+#pragma clang fp contract(off)
+  __shared__ Pose3 s_pose[2];
+  __shared__ int s_lo[3], s_hi[3];
+  const int tid = threadIdx.x, n = b.n, j = blockIdx.x * kThreads + tid;
+  if (tid < 3) {
     s_lo[tid] = 1 << 30;
     s_hi[tid] = -(1 << 30);
   }
   if (b.kind != 0 && tid < 2) s_pose[tid] = pose3(b, (double)(t + tid));
   __syncthreads();
-  for (int j = tid; j < n; j += nt) {
+  if (j < n) {
     double X, Y, Z, X1, Y1, Z1;
     marker3(b, s_pose[0], j, X, Y, Z);
     if (b.kind == 0) {
@@ -419,31 +430,47 @@ __global__ __launch_bounds__(kPoseThreads) void ibm3_pose_kernel(Params p, long 
     b.ud[2 * n + j] = Z1 - Z;
     b.ft[j] = b.ft[n + j] = b.ft[2 * n + j] = 0.0;
     const double P[3] = {X, Y, Z};
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       const int t0 = (int)floor(P[a] - 1.5);
       b.tap[a * n + j] = t0;
+#pragma unroll
       for (int k = 0; k < 4; ++k) b.phi[(a * 4 + k) * n + j] = peskin3d(t0 + k + 0.5 - P[a]);
       atomicMin(&s_lo[a], t0);
       atomicMax(&s_hi[a], t0 + 4);
     }
   }
   __syncthreads();
-  if (tid != 0) return;
+  if (tid < 3) {
+    atomicMin(&b.lohi[tid], s_lo[tid]);
+    atomicMax(&b.lohi[3 + tid], s_hi[tid]);
+  }
+}
+
+// The box of this loop from the reduced bounds; a box outside the lattice
+// or above cap gives no force this step (the host reports it at the next
+// synchronisation).
+__global__ __launch_bounds__(64) void ibm3_box_kernel(Params p, Ibm3 b) {
+  if (threadIdx.x != 0) return;
   const int dims[3] = {p.nx, p.ny, p.nz};
   long long K = 1;
   bool bad = false;
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    K *= s_hi[a] - s_lo[a];
-    bad |= s_lo[a] < 0 || s_hi[a] > dims[a];
+    const int lo = b.lohi[a], hi = b.lohi[3 + a];
+    K *= hi - lo;
+    bad |= lo < 0 || hi > dims[a];
   }
-  if (bad || K > b.cap) {  // no force this step; the host reports it at the next synchronisation
+  if (bad || K > b.cap) {
     atomicOr(b.err, 2);
+#pragma unroll
     for (int a = 0; a < 6; ++a) b.box[a] = 0;
     return;
   }
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    b.box[a] = s_lo[a];
-    b.box[3 + a] = s_hi[a] - s_lo[a];
+    b.box[a] = b.lohi[a];
+    b.box[3 + a] = b.lohi[3 + a] - b.lohi[a];
   }
 }
 
@@ -791,7 +818,7 @@ sbt_status solid_records(const sbt3_desc *d, std::vector<int32_t> *code, std::ve
 size_t body_bytes(const sbt3_desc *d) {
   const size_t n = d->n_markers, cap = (size_t)d->ibm_box_cells;
   return 4 * align256(n * 8) + align256(3 * n * 4) + align256(12 * n * 8) + 3 * align256(3 * n * 8) +
-         align256(cap * 8) + 2 * align256(3 * cap * 8) + align256(6 * 4) + align256(6 * 8) + align256(4);
+         align256(cap * 8) + 2 * align256(3 * cap * 8) + 2 * align256(6 * 4) + align256(6 * 8) + align256(4);
 }
 
 size_t plan_bytes(const sbt3_desc *d, long long *stage, long long records) {
@@ -832,7 +859,9 @@ hipError_t launch_ibm(sbt3_ctx &X, int pull) {
   const Ibm3 &B = X.ibm;
   const dim3 gk((unsigned)((B.cap + kThreads - 1) / kThreads)), gn((unsigned)((B.n + kThreads - 1) / kThreads));
   const dim3 gs((unsigned)std::min<long long>(2048, (B.cap + kThreads - 1) / kThreads));  // tiles, grid-stride
-  hipLaunchKernelGGL(ibm3_pose_kernel, dim3(1), dim3(kPoseThreads), 0, X.stream, X.p, X.ibm_t, B);
+  hipLaunchKernelGGL(ibm3_fs_kernel, dim3(1), dim3(kPoseThreads), 0, X.stream, B);
+  hipLaunchKernelGGL(ibm3_markers_kernel, gn, dim3(kThreads), 0, X.stream, X.ibm_t, B);
+  hipLaunchKernelGGL(ibm3_box_kernel, dim3(1), dim3(64), 0, X.stream, X.p, B);
   const void *lat = X.lat[X.cur];
   switch (X.d.storage + 4 * (X.d.lattice == 27)) {
     case 0: hipLaunchKernelGGL((ibm3_moments_kernel<0, 19>), gk, dim3(kThreads), 0, X.stream, X.p, lat, pull, B); break;
@@ -984,6 +1013,7 @@ sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, vo
     B.u = reinterpret_cast<double *>(take(3 * cap * 8));
     B.Fbox = reinterpret_cast<double *>(take(3 * cap * 8));
     B.box = reinterpret_cast<int *>(take(6 * 4));
+    B.lohi = reinterpret_cast<int *>(take(6 * 4));
     B.fs = reinterpret_cast<double *>(take(6 * 8));
     B.err = X->err;
     bool ok = hipMemcpy(xb, desc->marker_xyz, n * 8, hipMemcpyHostToDevice) == hipSuccess;
