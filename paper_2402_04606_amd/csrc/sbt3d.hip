@@ -408,7 +408,7 @@ __global__ __launch_bounds__(kThreads) void ibm3_markers_kernel(long long t, Ibm
 #pragma clang fp contract(off)
   __shared__ Pose3 s_pose[2];
   __shared__ int s_lo[3], s_hi[3];
-  const int tid = threadIdx.x, n = b.n, j = blockIdx.x * kThreads + tid;
+  const int tid = threadIdx.x, n = b.n, j = blockIdx.x * blockDim.x + tid;
   if (tid < 3) {
     s_lo[tid] = 1 << 30;
     s_hi[tid] = -(1 << 30);
@@ -509,7 +509,7 @@ __global__ __launch_bounds__(kThreads) void ibm3_moments_kernel(Params p, const 
 __global__ __launch_bounds__(kThreads) void ibm3_interp_kernel(Ibm3 b) {
 #pragma clang fp contract(off)
   const int *B = b.box;
-  const int n = b.n, j = blockIdx.x * kThreads + threadIdx.x;
+  const int n = b.n, j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n || B[3] == 0) return;
   const int bwx = B[3], bwy = B[4];
   const int i0 = b.tap[j] - B[0], j0 = b.tap[n + j] - B[1], k0 = b.tap[2 * n + j] - B[2];
@@ -857,10 +857,12 @@ size_t plan_bytes(const sbt3_desc *d, long long *stage, long long records) {
 
 hipError_t launch_ibm(sbt3_ctx &X, int pull) {
   const Ibm3 &B = X.ibm;
-  const dim3 gk((unsigned)((B.cap + kThreads - 1) / kThreads)), gn((unsigned)((B.n + kThreads - 1) / kThreads));
+  // one wave per workgroup for the per-marker kernels: their threads are
+  // few and latency-bound, so they are spread over as many CUs as possible
+  const dim3 gk((unsigned)((B.cap + kThreads - 1) / kThreads)), gn((unsigned)((B.n + 63) / 64));
   const dim3 gs((unsigned)std::min<long long>(2048, (B.cap + kThreads - 1) / kThreads));  // tiles, grid-stride
   hipLaunchKernelGGL(ibm3_fs_kernel, dim3(1), dim3(kPoseThreads), 0, X.stream, B);
-  hipLaunchKernelGGL(ibm3_markers_kernel, gn, dim3(kThreads), 0, X.stream, X.ibm_t, B);
+  hipLaunchKernelGGL(ibm3_markers_kernel, gn, dim3(64), 0, X.stream, X.ibm_t, B);
   hipLaunchKernelGGL(ibm3_box_kernel, dim3(1), dim3(64), 0, X.stream, X.p, B);
   const void *lat = X.lat[X.cur];
   switch (X.d.storage + 4 * (X.d.lattice == 27)) {
@@ -875,7 +877,7 @@ hipError_t launch_ibm(sbt3_ctx &X, int pull) {
     default: return hipErrorInvalidValue;
   }
   for (int it = 0; it < B.iters; ++it) {
-    hipLaunchKernelGGL(ibm3_interp_kernel, gn, dim3(kThreads), 0, X.stream, B);
+    hipLaunchKernelGGL(ibm3_interp_kernel, gn, dim3(64), 0, X.stream, B);
     hipLaunchKernelGGL(ibm3_spread_kernel, gs, dim3(kThreads), 0, X.stream, B);
   }
   return hipGetLastError();
