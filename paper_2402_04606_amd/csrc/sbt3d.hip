@@ -539,22 +539,23 @@ __global__ __launch_bounds__(kThreads) void ibm3_interp_kernel(Ibm3 b) {
   b.ft[2 * n + j] += g2;
 }
 
-// One pass's spreading, markers in order.  A workgroup takes 8x8x4 tiles of
-// the box (grid-stride); for each tile it gathers into LDS, chunk by chunk
-// and in marker order, the markers whose 4x4x4 stencil reaches the tile
-// (their taps, weights, g_j and dA_j), and each cell sums over that list.
-constexpr int kSpTx = 8, kSpTy = 8, kSpTz = kThreads / (kSpTx * kSpTy);
-static_assert(kSpTz * kSpTx * kSpTy == kThreads && kThreads % 64 == 0, "tile of one cell per thread");
+// One pass's spreading, markers in order.  A one-wave workgroup takes 4x4x4
+// tiles of the box (grid-stride).  For each tile it stages the taps of up to
+// kSpBlock markers in LDS at once, keeps (64 at a time, in marker order) the
+// markers whose 4x4x4 stencil reaches the tile, stages their weights, g_j
+// and dA_j, and each cell sums over that list.
+constexpr int kSpThreads = 64, kSpTx = 4, kSpTy = 4, kSpTz = kSpThreads / (kSpTx * kSpTy), kSpBlock = 1024;
+static_assert(kSpTz * kSpTx * kSpTy == kSpThreads && kSpThreads == 64, "one wave, one cell per lane");
 
-__global__ __launch_bounds__(kThreads) void ibm3_spread_kernel(Ibm3 b) {
+__global__ __launch_bounds__(kSpThreads) void ibm3_spread_kernel(Ibm3 b) {
 #pragma clang fp contract(off)
-  __shared__ int s_t[3][kThreads];
-  __shared__ double s_phi[12][kThreads];
-  __shared__ double s_g[3][kThreads];
-  __shared__ double s_dA[kThreads];
-  __shared__ int s_wave[kThreads / 64];
+  __shared__ int s_tap[3][kSpBlock];
+  __shared__ int s_t[3][kSpThreads];
+  __shared__ double s_phi[12][kSpThreads];
+  __shared__ double s_g[3][kSpThreads];
+  __shared__ double s_dA[kSpThreads];
   const int *B = b.box;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, n = b.n;
+  const int lane = threadIdx.x, n = b.n;
   const int bwx = B[3], bwy = B[4], bwz = B[5];
   if (bwx == 0) return;  // the whole grid: no force this step
   const long long K = box_cells(B);
@@ -563,48 +564,64 @@ __global__ __launch_bounds__(kThreads) void ibm3_spread_kernel(Ibm3 b) {
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
     const int xlo = (tile % ntx) * kSpTx, ylo = ((tile / ntx) % nty) * kSpTy, zlo = (tile / (ntx * nty)) * kSpTz;
     const int xhi = min(xlo + kSpTx, bwx) - 1, yhi = min(ylo + kSpTy, bwy) - 1, zhi = min(zlo + kSpTz, bwz) - 1;
-    const int x = xlo + tid % kSpTx, y = ylo + (tid / kSpTx) % kSpTy, z = zlo + tid / (kSpTx * kSpTy);
+    const int x = xlo + lane % kSpTx, y = ylo + (lane / kSpTx) % kSpTy, z = zlo + lane / (kSpTx * kSpTy);
     const bool live = x <= xhi && y <= yhi && z <= zhi;
     double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-    for (int j0 = 0; j0 < n; j0 += kThreads) {
-      const int jc = j0 + tid;
-      int tx = 0, ty = 0, tz = 0;
-      bool f = false;
-      if (jc < n) {
-        tx = b.tap[jc] - B[0];
-        ty = b.tap[n + jc] - B[1];
-        tz = b.tap[2 * n + jc] - B[2];
-        f = tx <= xhi && tx + 3 >= xlo && ty <= yhi && ty + 3 >= ylo && tz <= zhi && tz + 3 >= zlo;
-      }
-      const unsigned long long m = __ballot(f);
-      if (lane == 0) s_wave[wave] = __popcll(m);
-      __syncthreads();
-      int base = 0, total = 0;
-      for (int w = 0; w < kThreads / 64; ++w) {
-        base += w < wave ? s_wave[w] : 0;
-        total += s_wave[w];
-      }
-      if (f) {
-        const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
-        s_t[0][pos] = tx;
-        s_t[1][pos] = ty;
-        s_t[2][pos] = tz;
-        for (int q = 0; q < 12; ++q) s_phi[q][pos] = b.phi[q * n + jc];
-        for (int a = 0; a < 3; ++a) s_g[a][pos] = b.g[a * n + jc];
-        s_dA[pos] = b.dA[jc];
-      }
-      __syncthreads();
-      if (live) {
-        for (int i = 0; i < total; ++i) {
-          const int dx = x - s_t[0][i], dy = y - s_t[1][i], dz = z - s_t[2][i];
-          if ((unsigned)dx > 3u || (unsigned)dy > 3u || (unsigned)dz > 3u) continue;
-          const double w = s_phi[dx][i] * (s_phi[4 + dy][i] * s_phi[8 + dz][i]);
-          d0 += s_g[0][i] * w * s_dA[i];
-          d1 += s_g[1][i] * w * s_dA[i];
-          d2 += s_g[2][i] * w * s_dA[i];
+    for (int b0 = 0; b0 < n; b0 += kSpBlock) {
+      const int bn = min(kSpBlock, n - b0);
+      {  // taps in the box frame: all loads issued before the LDS stores
+        constexpr int kPer = kSpBlock / kSpThreads;
+        int v[3][kPer];
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+          const int i = r * kSpThreads + lane;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) v[a][r] = i < bn ? b.tap[a * n + b0 + i] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+          const int i = r * kSpThreads + lane;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) s_tap[a][i] = v[a][r] - B[a];
         }
       }
-      __syncthreads();  // the lists are rebuilt by the next chunk
+      __syncthreads();
+      for (int c0 = 0; c0 < bn; c0 += kSpThreads) {
+        const int i = c0 + lane;
+        bool f = false;
+        int tx = 0, ty = 0, tz = 0;
+        if (i < bn) {
+          tx = s_tap[0][i];
+          ty = s_tap[1][i];
+          tz = s_tap[2][i];
+          f = tx <= xhi && tx + 3 >= xlo && ty <= yhi && ty + 3 >= ylo && tz <= zhi && tz + 3 >= zlo;
+        }
+        const unsigned long long m = __ballot(f);
+        if (m == 0ull) continue;  // the whole wave
+        const int total = __popcll(m);
+        if (f) {
+          const int pos = __popcll(m & ((1ull << lane) - 1ull)), jc = b0 + i;
+          s_t[0][pos] = tx;
+          s_t[1][pos] = ty;
+          s_t[2][pos] = tz;
+          for (int q = 0; q < 12; ++q) s_phi[q][pos] = b.phi[q * n + jc];
+          for (int a = 0; a < 3; ++a) s_g[a][pos] = b.g[a * n + jc];
+          s_dA[pos] = b.dA[jc];
+        }
+        __syncthreads();
+        if (live) {
+          for (int c = 0; c < total; ++c) {
+            const int dx = x - s_t[0][c], dy = y - s_t[1][c], dz = z - s_t[2][c];
+            if ((unsigned)dx > 3u || (unsigned)dy > 3u || (unsigned)dz > 3u) continue;
+            const double w = s_phi[dx][c] * (s_phi[4 + dy][c] * s_phi[8 + dz][c]);
+            d0 += s_g[0][c] * w * s_dA[c];
+            d1 += s_g[1][c] * w * s_dA[c];
+            d2 += s_g[2][c] * w * s_dA[c];
+          }
+        }
+        __syncthreads();  // the list is rebuilt by the next chunk
+      }
+      __syncthreads();  // the taps are restaged by the next block
     }
     if (!live || (d0 == 0.0 && d1 == 0.0 && d2 == 0.0)) continue;
     const long long k = ((long long)z * bwy + y) * bwx + x;
@@ -860,7 +877,7 @@ hipError_t launch_ibm(sbt3_ctx &X, int pull) {
   // one wave per workgroup for the per-marker kernels: their threads are
   // few and latency-bound, so they are spread over as many CUs as possible
   const dim3 gk((unsigned)((B.cap + kThreads - 1) / kThreads)), gn((unsigned)((B.n + 63) / 64));
-  const dim3 gs((unsigned)std::min<long long>(2048, (B.cap + kThreads - 1) / kThreads));  // tiles, grid-stride
+  const dim3 gs((unsigned)std::min<long long>(8192, (B.cap + kSpThreads - 1) / kSpThreads));  // tiles, grid-stride
   hipLaunchKernelGGL(ibm3_fs_kernel, dim3(1), dim3(kPoseThreads), 0, X.stream, B);
   hipLaunchKernelGGL(ibm3_markers_kernel, gn, dim3(64), 0, X.stream, X.ibm_t, B);
   hipLaunchKernelGGL(ibm3_box_kernel, dim3(1), dim3(64), 0, X.stream, X.p, B);
@@ -878,7 +895,7 @@ hipError_t launch_ibm(sbt3_ctx &X, int pull) {
   }
   for (int it = 0; it < B.iters; ++it) {
     hipLaunchKernelGGL(ibm3_interp_kernel, gn, dim3(64), 0, X.stream, B);
-    hipLaunchKernelGGL(ibm3_spread_kernel, gs, dim3(kThreads), 0, X.stream, B);
+    hipLaunchKernelGGL(ibm3_spread_kernel, gs, dim3(kSpThreads), 0, X.stream, B);
   }
   return hipGetLastError();
 }
