@@ -877,7 +877,10 @@ hipError_t launch_ibm(sbt3_ctx &X, int pull) {
   // one wave per workgroup for the per-marker kernels: their threads are
   // few and latency-bound, so they are spread over as many CUs as possible
   const dim3 gk((unsigned)((B.cap + kThreads - 1) / kThreads)), gn((unsigned)((B.n + 63) / 64));
-  const dim3 gs((unsigned)std::min<long long>(8192, (B.cap + kSpThreads - 1) / kSpThreads));  // tiles, grid-stride
+  // tiles, grid-stride: the box is known only on the device and is mostly
+  // smaller than cap, and workgroups that find no tile still cost dispatch
+  // time, so the grid is capped at two small workgroups per CU
+  const dim3 gs((unsigned)std::min<long long>(512, (B.cap + kSpThreads - 1) / kSpThreads));
   hipLaunchKernelGGL(ibm3_fs_kernel, dim3(1), dim3(kPoseThreads), 0, X.stream, B);
   hipLaunchKernelGGL(ibm3_markers_kernel, gn, dim3(64), 0, X.stream, X.ibm_t, B);
   hipLaunchKernelGGL(ibm3_box_kernel, dim3(1), dim3(64), 0, X.stream, X.p, B);
