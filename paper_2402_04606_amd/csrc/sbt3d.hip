@@ -328,7 +328,9 @@ struct Pose3 {
   double zc, ca, sa;
 };
 
-__device__ Pose3 pose3(const Ibm3 &b, double t) {
+// Evaluated on the host (C library sin / cos) once per forcing loop and
+// passed to the marker kernel.
+Pose3 pose3(const Ibm3 &b, double t) {
 #pragma clang fp contract(off)
   Pose3 q;
   const double *p = b.mp;
@@ -404,26 +406,24 @@ __global__ __launch_bounds__(kPoseThreads) void ibm3_fs_kernel(Ibm3 b) {
 
 // Marker j at step t: position, desired velocity, taps and weights; clears
 // its force total; the workgroup's tap bounds go into lohi.
-__global__ __launch_bounds__(kThreads) void ibm3_markers_kernel(long long t, Ibm3 b) {
+__global__ __launch_bounds__(kThreads) void ibm3_markers_kernel(Pose3 q0, Pose3 q1, Ibm3 b) {
 #pragma clang fp contract(off)
-  __shared__ Pose3 s_pose[2];
   __shared__ int s_lo[3], s_hi[3];
   const int tid = threadIdx.x, n = b.n, j = blockIdx.x * blockDim.x + tid;
   if (tid < 3) {
     s_lo[tid] = 1 << 30;
     s_hi[tid] = -(1 << 30);
   }
-  if (b.kind != 0 && tid < 2) s_pose[tid] = pose3(b, (double)(t + tid));
   __syncthreads();
   if (j < n) {
     double X, Y, Z, X1, Y1, Z1;
-    marker3(b, s_pose[0], j, X, Y, Z);
+    marker3(b, q0, j, X, Y, Z);
     if (b.kind == 0) {
       X1 = X;
       Y1 = Y;
       Z1 = Z;
     } else {
-      marker3(b, s_pose[1], j, X1, Y1, Z1);
+      marker3(b, q1, j, X1, Y1, Z1);
     }
     b.ud[j] = X1 - X;
     b.ud[n + j] = Y1 - Y;
@@ -882,7 +882,8 @@ hipError_t launch_ibm(sbt3_ctx &X, int pull) {
   // time, so the grid is capped at two small workgroups per CU
   const dim3 gs((unsigned)std::min<long long>(512, (B.cap + kSpThreads - 1) / kSpThreads));
   hipLaunchKernelGGL(ibm3_fs_kernel, dim3(1), dim3(kPoseThreads), 0, X.stream, B);
-  hipLaunchKernelGGL(ibm3_markers_kernel, gn, dim3(64), 0, X.stream, X.ibm_t, B);
+  const Pose3 q0 = B.kind ? pose3(B, (double)X.ibm_t) : Pose3{}, q1 = B.kind ? pose3(B, (double)(X.ibm_t + 1)) : Pose3{};
+  hipLaunchKernelGGL(ibm3_markers_kernel, gn, dim3(64), 0, X.stream, q0, q1, B);
   hipLaunchKernelGGL(ibm3_box_kernel, dim3(1), dim3(64), 0, X.stream, X.p, B);
   const void *lat = X.lat[X.cur];
   switch (X.d.storage + 4 * (X.d.lattice == 27)) {

@@ -874,7 +874,8 @@ def test_3d_flapping_ellipsoid(env, storage, tol, q):
     """An IBM ellipsoid pitching about y and plunging along z in a uniform
     stream (400 markers, N_F = 3, 240-step period): the forcing loop
     rebuilds the markers, desired velocities, taps and box every step.
-    Fields and body force against the oracle over half a period."""
+    Fields and body force against the oracle over half a period; FP64
+    bit-exact."""
     P, O = env
     wl = W.flapping_ellipsoid3(32, lattice=q)
     print(f"case {wl.name} D3Q{q} {storage}", flush=True)
@@ -889,6 +890,9 @@ def test_3d_flapping_ellipsoid(env, storage, tol, q):
         ef = np.abs(fg - fo).max() / np.abs(fo).max()
         print(f"  rel L2 u {e:.3e}  body force {fg}  rel err {ef:.3e}", flush=True)
         assert e <= tol and ef <= max(tol, 1e-12) * 10
+        if storage == "f64":  # the pose comes from the same C library sin / cos as the oracle's
+            assert all(np.array_equal(a, b) for a, b in zip(g.fields(), o.fields()))
+            assert np.array_equal(fg, fo)
     g.close()
 
 
