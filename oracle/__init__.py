@@ -44,64 +44,79 @@ def lib():
         if not os.path.exists(LIB_PATH):
             from . import build as _b
             _b.build()
-        _lib = C.CDLL(LIB_PATH)
-        d = C.POINTER(C.c_double)
-        _lib.orc_create.argtypes = [C.POINTER(_Case), C.POINTER(C.c_void_p)]
-        _lib.orc_destroy.argtypes = [C.c_void_p]
-        _lib.orc_destroy.restype = None
-        _lib.orc_level_size.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
-        _lib.orc_level_kinds.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_uint8)]
-        _lib.orc_init_fields.argtypes = [C.c_void_p, C.c_int, d, d, d]
-        _lib.orc_step.argtypes = [C.c_void_p, C.c_int32]
-        _lib.orc_read_fields.argtypes = [C.c_void_p, C.c_int, d, d, d]
-        _lib.orc_read_populations.argtypes = [C.c_void_p, C.c_int, d]
-        _lib.orc_marker_forces.argtypes = [C.c_void_p, d, d]
-        _lib.orc_set_markers.argtypes = [C.c_void_p, C.c_int32, d, d, d, d]
-        _lib.orc_force_history.argtypes = [C.c_void_p, C.c_int32, d, d, C.POINTER(C.c_int32)]
-        _lib.orc_diagnostics.argtypes = [C.c_void_p, d]
-        _lib.orc_substeps.argtypes = [C.c_void_p]
-        _lib.orc_substeps.restype = C.c_int64
-        _lib.orc_velocity_set.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32), d]
-        _lib.orc_velocity_set.restype = None
-        _lib.orc_feq.argtypes = [C.c_double] * 3 + [d]
-        _lib.orc_feq.restype = None
-        _lib.orc_guo.argtypes = [C.c_double] * 5 + [d]
-        _lib.orc_guo.restype = None
-        _lib.orc_collide_cell.argtypes = [C.c_double, d, C.c_double, C.c_double, d]
-        _lib.orc_collide_cell.restype = None
-        _lib.orc_mrt_matrices.argtypes = [d, d]
-        _lib.orc_mrt_matrices.restype = None
-        _lib.orc_collide_cell_mrt.argtypes = [C.c_double, d, d, C.c_double, C.c_double, d]
-        _lib.orc_collide_cell_mrt.restype = None
-        _lib.orc_phi.argtypes = [C.c_double]
-        _lib.orc_phi.restype = C.c_double
-        _lib.orc_body_positions.argtypes = [C.POINTER(_Case), C.c_double, d, d]
-        for f in (_lib.orc_ramp_alpha, _lib.orc_tri_alpha):
-            f.argtypes = [d, C.c_double]
-            f.restype = C.c_double
-        _lib.orc_mdf.argtypes = [C.c_int32, C.c_int32, d, d, d, d, d, C.c_int32, d, d, d, d, d,
-                                 C.c_int32, d, d]
-        _lib.orc_interpolate.argtypes = [C.c_int32, C.c_int32, d, d, C.c_int32, d, d, d, d]
-        _lib.orc_spread.argtypes = [C.c_int32, C.c_int32, C.c_int32, d, d, d, d, d, d, d]
-        _lib.orc_force_stats.argtypes = [d, d, C.c_int32, C.c_double, C.c_double, d]
-        _lib.orc_set_solid.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_uint8), d]
-        _lib.orc3_velocity_set.argtypes = [C.c_int32] + [C.POINTER(C.c_int32)] * 3 + [d]
-        _lib.orc3_velocity_set.restype = None
-        _lib.orc3_feq.argtypes = [C.c_int32] + [C.c_double] * 4 + [d]
-        _lib.orc3_feq.restype = None
-        _lib.orc3_create.argtypes = [C.c_int32] * 4 + [C.c_double, d, C.POINTER(C.c_void_p)]
-        _lib.orc3_destroy.argtypes = [C.c_void_p]
-        _lib.orc3_destroy.restype = None
-        _lib.orc3_init_fields.argtypes = [C.c_void_p, d, d, d, d]
-        _lib.orc3_step.argtypes = [C.c_void_p, C.c_int32]
-        _lib.orc3_read_fields.argtypes = [C.c_void_p, d, d, d, d]
-        _lib.orc3_set_walls.argtypes = [C.c_void_p, C.c_double, d, d]
-        _lib.orc3_set_solid.argtypes = [C.c_void_p, C.POINTER(C.c_uint8), d]
-        _lib.orc3_set_body.argtypes = [C.c_void_p, C.c_int32, d, d, d, d, C.c_int32]
-        _lib.orc3_body_force.argtypes = [C.c_void_p, d]
-        _lib.orc3_set_motion.argtypes = [C.c_void_p, C.c_int32, d]
-        _lib.orc_num_threads.argtypes = []
+        _lib = _configure(C.CDLL(LIB_PATH))
     return _lib
+
+
+def load_variant(path):
+    """A separately built copy of oracle.c (for tests that plant a mistake in
+    the oracle and check that a pin catches it), with the same signatures."""
+    return _configure(C.CDLL(path))
+
+
+def _configure(L):
+    """Argument and result types of every entry point of a build of oracle.c."""
+    d = C.POINTER(C.c_double)
+    L.orc_create.argtypes = [C.POINTER(_Case), C.POINTER(C.c_void_p)]
+    L.orc_destroy.argtypes = [C.c_void_p]
+    L.orc_destroy.restype = None
+    L.orc_level_size.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.orc_level_kinds.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_uint8)]
+    L.orc_init_fields.argtypes = [C.c_void_p, C.c_int, d, d, d]
+    L.orc_step.argtypes = [C.c_void_p, C.c_int32]
+    L.orc_init_populations.argtypes = [C.c_void_p, C.c_int, d]
+    L.orc_interface_factors.argtypes = [C.c_double, C.c_double, d]
+    L.orc_interface_factors.restype = None
+    L.orc_read_fields.argtypes = [C.c_void_p, C.c_int, d, d, d]
+    L.orc_read_populations.argtypes = [C.c_void_p, C.c_int, d]
+    L.orc_marker_forces.argtypes = [C.c_void_p, d, d]
+    L.orc_set_markers.argtypes = [C.c_void_p, C.c_int32, d, d, d, d]
+    L.orc_force_history.argtypes = [C.c_void_p, C.c_int32, d, d, C.POINTER(C.c_int32)]
+    L.orc_diagnostics.argtypes = [C.c_void_p, d]
+    L.orc_substeps.argtypes = [C.c_void_p]
+    L.orc_substeps.restype = C.c_int64
+    L.orc_velocity_set.argtypes = [C.POINTER(C.c_int32), C.POINTER(C.c_int32), d]
+    L.orc_velocity_set.restype = None
+    L.orc_feq.argtypes = [C.c_double] * 3 + [d]
+    L.orc_feq.restype = None
+    L.orc_guo.argtypes = [C.c_double] * 5 + [d]
+    L.orc_guo.restype = None
+    L.orc_collide_cell.argtypes = [C.c_double, d, C.c_double, C.c_double, d]
+    L.orc_collide_cell.restype = None
+    L.orc_mrt_matrices.argtypes = [d, d]
+    L.orc_mrt_matrices.restype = None
+    L.orc_collide_cell_mrt.argtypes = [C.c_double, d, d, C.c_double, C.c_double, d]
+    L.orc_collide_cell_mrt.restype = None
+    L.orc_phi.argtypes = [C.c_double]
+    L.orc_phi.restype = C.c_double
+    L.orc_body_positions.argtypes = [C.POINTER(_Case), C.c_double, d, d]
+    for f in (L.orc_ramp_alpha, L.orc_tri_alpha):
+        f.argtypes = [d, C.c_double]
+        f.restype = C.c_double
+    L.orc_mdf.argtypes = [C.c_int32, C.c_int32, d, d, d, d, d, C.c_int32, d, d, d, d, d,
+                             C.c_int32, d, d]
+    L.orc_interpolate.argtypes = [C.c_int32, C.c_int32, d, d, C.c_int32, d, d, d, d]
+    L.orc_spread.argtypes = [C.c_int32, C.c_int32, C.c_int32, d, d, d, d, d, d, d]
+    L.orc_force_stats.argtypes = [d, d, C.c_int32, C.c_double, C.c_double, d]
+    L.orc_set_solid.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_uint8), d]
+    L.orc3_velocity_set.argtypes = [C.c_int32] + [C.POINTER(C.c_int32)] * 3 + [d]
+    L.orc3_velocity_set.restype = None
+    L.orc3_feq.argtypes = [C.c_int32] + [C.c_double] * 4 + [d]
+    L.orc3_feq.restype = None
+    L.orc3_create.argtypes = [C.c_int32] * 4 + [C.c_double, d, C.POINTER(C.c_void_p)]
+    L.orc3_destroy.argtypes = [C.c_void_p]
+    L.orc3_destroy.restype = None
+    L.orc3_init_fields.argtypes = [C.c_void_p, d, d, d, d]
+    L.orc3_step.argtypes = [C.c_void_p, C.c_int32]
+    L.orc3_read_fields.argtypes = [C.c_void_p, d, d, d, d]
+    L.orc3_set_walls.argtypes = [C.c_void_p, C.c_double, d, d]
+    L.orc3_set_solid.argtypes = [C.c_void_p, C.POINTER(C.c_uint8), d]
+    L.orc3_set_body.argtypes = [C.c_void_p, C.c_int32, d, d, d, d, C.c_int32]
+    L.orc3_body_force.argtypes = [C.c_void_p, d]
+    L.orc3_set_motion.argtypes = [C.c_void_p, C.c_int32, d]
+    L.orc_num_threads.argtypes = []
+    L.orc3_marker_positions.argtypes = [C.c_void_p, C.c_double, d, d, d]
+    return L
 
 
 def _dp(a):
@@ -147,11 +162,12 @@ def make_case(wl):
 class OracleSim:
     """One case on the oracle.  Fields are dense per-level arrays [ny, nx]."""
 
-    def __init__(self, wl):
+    def __init__(self, wl, so=None):
         self.wl = wl
+        self._L = so if so is not None else lib()
         self._case, self._keep = make_case(wl)
         h = C.c_void_p()
-        rc = lib().orc_create(C.byref(self._case), C.byref(h))
+        rc = self._L.orc_create(C.byref(self._case), C.byref(h))
         if rc != 0:
             raise RuntimeError(f"orc_create failed: {rc}")
         self._h = h
@@ -159,7 +175,7 @@ class OracleSim:
         for level, mask, q in getattr(wl, "solids", ()):
             m = np.ascontiguousarray(mask, dtype=np.uint8)
             qq = None if q is None else _f64(q)
-            rc = lib().orc_set_solid(h, level, m.ctypes.data_as(C.POINTER(C.c_uint8)),
+            rc = self._L.orc_set_solid(h, level, m.ctypes.data_as(C.POINTER(C.c_uint8)),
                                      None if qq is None else _dp(qq))
             if rc != 0:
                 raise RuntimeError(f"orc_set_solid failed: {rc}")
@@ -171,19 +187,19 @@ class OracleSim:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib is not None:
-            _lib.orc_destroy(h)
+        if h is not None:
+            self._L.orc_destroy(h)
             self._h = None
 
     def level_size(self, l):
         nx, ny = C.c_int32(), C.c_int32()
-        lib().orc_level_size(self._h, l, C.byref(nx), C.byref(ny))
+        self._L.orc_level_size(self._h, l, C.byref(nx), C.byref(ny))
         return nx.value, ny.value
 
     def kinds(self, l):
         nx, ny = self.level_size(l)
         k = np.zeros((ny, nx), dtype=np.uint8)
-        lib().orc_level_kinds(self._h, l, k.ctypes.data_as(C.POINTER(C.c_uint8)))
+        self._L.orc_level_kinds(self._h, l, k.ctypes.data_as(C.POINTER(C.c_uint8)))
         return k
 
     def init_fields(self, l, rho, ux, uy):
@@ -191,44 +207,52 @@ class OracleSim:
         rho = _f64(np.broadcast_to(rho, (ny, nx)))
         ux = _f64(np.broadcast_to(ux, (ny, nx)))
         uy = _f64(np.broadcast_to(uy, (ny, nx)))
-        rc = lib().orc_init_fields(self._h, l, _dp(rho), _dp(ux), _dp(uy))
+        rc = self._L.orc_init_fields(self._h, l, _dp(rho), _dp(ux), _dp(uy))
+        if rc:
+            raise RuntimeError(rc)
+
+    def init_populations(self, l, f):
+        """Pre-collision populations of the owned cells of level l, [ny, nx, 9]."""
+        nx, ny = self.level_size(l)
+        f = _f64(np.broadcast_to(f, (ny, nx, 9)))
+        rc = self._L.orc_init_populations(self._h, l, _dp(f))
         if rc:
             raise RuntimeError(rc)
 
     def step(self, n=1):
-        rc = lib().orc_step(self._h, int(n))
+        rc = self._L.orc_step(self._h, int(n))
         if rc:
             raise RuntimeError(f"orc_step failed: {rc}")
 
     def fields(self, l):
         nx, ny = self.level_size(l)
         r, u, v = (np.empty((ny, nx)) for _ in range(3))
-        lib().orc_read_fields(self._h, l, _dp(r), _dp(u), _dp(v))
+        self._L.orc_read_fields(self._h, l, _dp(r), _dp(u), _dp(v))
         return r, u, v
 
     def populations(self, l):
         nx, ny = self.level_size(l)
         f = np.empty((ny, nx, 9))
-        lib().orc_read_populations(self._h, l, _dp(f))
+        self._L.orc_read_populations(self._h, l, _dp(f))
         return f
 
     def marker_forces(self):
         n = 0 if self.wl.body is None else len(self.wl.body.xb)
         fx, fy = np.zeros(max(n, 1)), np.zeros(max(n, 1))
-        lib().orc_marker_forces(self._h, _dp(fx), _dp(fy))
+        self._L.orc_marker_forces(self._h, _dp(fx), _dp(fy))
         return fx[:n], fy[:n]
 
     def set_markers(self, X, Y, udx, udy):
         """Caller-placed markers (body kind HOST) for the next steps."""
         X, Y, udx, udy = (_f64(a) for a in (X, Y, udx, udy))
-        rc = lib().orc_set_markers(self._h, len(X), _dp(X), _dp(Y), _dp(udx), _dp(udy))
+        rc = self._L.orc_set_markers(self._h, len(X), _dp(X), _dp(Y), _dp(udx), _dp(udy))
         if rc:
             raise RuntimeError(f"orc_set_markers failed: {rc}")
 
     def force_history(self, cap=1 << 20):
         fx, fy = np.empty(cap), np.empty(cap)
         n = C.c_int32()
-        lib().orc_force_history(self._h, cap, _dp(fx), _dp(fy), C.byref(n))
+        self._L.orc_force_history(self._h, cap, _dp(fx), _dp(fy), C.byref(n))
         return fx[: n.value].copy(), fy[: n.value].copy()
 
     def velocity(self):
@@ -241,14 +265,21 @@ class OracleSim:
 
     def diagnostics(self):
         out = np.zeros(3)
-        lib().orc_diagnostics(self._h, _dp(out))
+        self._L.orc_diagnostics(self._h, _dp(out))
         return out
 
     def substeps(self):
-        return int(lib().orc_substeps(self._h))
+        return int(self._L.orc_substeps(self._h))
 
 
 # ---- building blocks ------------------------------------------------------
+
+def interface_factors(tau_c, tau_f):
+    """(s_cf, s_fc) the RESCALE interface applies between levels of these taus."""
+    out = np.zeros(2)
+    lib().orc_interface_factors(tau_c, tau_f, _dp(out))
+    return float(out[0]), float(out[1])
+
 
 def velocity_set():
     cx, cy = (C.c_int32 * 9)(), (C.c_int32 * 9)()
@@ -397,53 +428,61 @@ def feq3(rho, ux, uy, uz, q=19):
 class Oracle3Sim:
     """D3Q19 / D3Q27 BGK + Guo forcing on one periodic level (a ``workloads.Workload3``)."""
 
-    def __init__(self, wl):
+    def __init__(self, wl, so=None):
         self.wl = wl
+        self._L = so if so is not None else lib()
         F = _f64(np.asarray(wl.fext, dtype=np.float64))
         h = C.c_void_p()
-        rc = lib().orc3_create(wl.nx, wl.ny, wl.nz, wl.lattice, wl.tau, _dp(F), C.byref(h))
+        rc = self._L.orc3_create(wl.nx, wl.ny, wl.nz, wl.lattice, wl.tau, _dp(F), C.byref(h))
         if rc:
             raise RuntimeError(f"orc3_create failed: {rc}")
         self._h = h
         if getattr(wl, "walls_z", False):
             ub, ut = (_f64(np.asarray(a, dtype=np.float64)) for a in wl.wall_u)
-            lib().orc3_set_walls(h, float(wl.rho0), _dp(ub), _dp(ut))
+            self._L.orc3_set_walls(h, float(wl.rho0), _dp(ub), _dp(ut))
         if getattr(wl, "solid", None) is not None:
             mask, q = wl.solid
             m = np.ascontiguousarray(mask, dtype=np.uint8)
             qq = None if q is None else _f64(q)
-            rc = lib().orc3_set_solid(h, m.ctypes.data_as(C.POINTER(C.c_uint8)), None if qq is None else _dp(qq))
+            rc = self._L.orc3_set_solid(h, m.ctypes.data_as(C.POINTER(C.c_uint8)), None if qq is None else _dp(qq))
             if rc:
                 raise RuntimeError(f"orc3_set_solid failed: {rc}")
         if getattr(wl, "body", None) is not None:
             X, Y, Z, dA, iters = wl.body
             X, Y, Z, dA = (_f64(a) for a in (X, Y, Z, dA))
             self._body = (X, Y, Z, dA)
-            rc = lib().orc3_set_body(h, len(X), _dp(X), _dp(Y), _dp(Z), _dp(dA), int(iters))
+            rc = self._L.orc3_set_body(h, len(X), _dp(X), _dp(Y), _dp(Z), _dp(dA), int(iters))
             if rc:
                 raise RuntimeError(f"orc3_set_body failed: {rc}")
             kind, params = getattr(wl, "motion", (0, None))
             pm = _f64(np.asarray(params if params is not None else [0.0] * 10, dtype=np.float64))
-            lib().orc3_set_motion(h, int(kind), _dp(pm))
+            self._L.orc3_set_motion(h, int(kind), _dp(pm))
         r, u, v, w = (_f64(a) for a in wl.init(wl.nx, wl.ny, wl.nz))
-        lib().orc3_init_fields(h, _dp(r), _dp(u), _dp(v), _dp(w))
+        self._L.orc3_init_fields(h, _dp(r), _dp(u), _dp(v), _dp(w))
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and _lib is not None:
-            _lib.orc3_destroy(h)
+        if h is not None:
+            self._L.orc3_destroy(h)
 
     def step(self, n=1):
-        lib().orc3_step(self._h, int(n))
+        self._L.orc3_step(self._h, int(n))
+
+    def marker_positions(self, t):
+        """Marker positions of the body at step t (the motion law's pose)."""
+        n = len(self._body[0])
+        X, Y, Z = np.zeros(n), np.zeros(n), np.zeros(n)
+        self._L.orc3_marker_positions(self._h, float(t), _dp(X), _dp(Y), _dp(Z))
+        return X, Y, Z
 
     def body_force(self):
         """F_s = -sum_j F_j dA_j of the last step (3 components)."""
         out = np.zeros(3)
-        lib().orc3_body_force(self._h, _dp(out))
+        self._L.orc3_body_force(self._h, _dp(out))
         return out
 
     def fields(self):
         shape = (self.wl.nz, self.wl.ny, self.wl.nx)
         out = [np.empty(shape) for _ in range(4)]
-        lib().orc3_read_fields(self._h, *[_dp(a) for a in out])
+        self._L.orc3_read_fields(self._h, *[_dp(a) for a in out])
         return out

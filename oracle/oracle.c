@@ -4,7 +4,7 @@
  * TEST INFRASTRUCTURE ONLY: loaded by the test-suite, the package smoke check
  * and the benchmark's CPU-baseline leg, never by the GPU library.  It is kept
  * deliberately literal: dense per-level arrays, one loop per step of the
- * paper's Algorithm 1, no blocking, no fusion.  OpenMP only splits the
+ * method's steps (Sec. 2.1-2.5), no blocking, no fusion.  OpenMP only splits the
  * per-cell loops (each cell is written by exactly one thread), so results do
  * not depend on the thread count; every reduction runs sequentially in index
  * order.
@@ -16,8 +16,9 @@
  *   domain boundaries ....... Sec. 2.1 (kinds named only; formulas are the
  *                             textbook readings listed in the design notes)
  *   IBM, MDF loop ........... Sec. 2.2, Eqs. (11)-(16)
- *   coarse/fine interface ... Sec. 2.4 (steps (1)-(6)), Algorithm 1
- *   level recursion ......... Sec. 2.5, Algorithm 1
+ *   coarse/fine interface ... Sec. 2.4 (steps (1)-(6))
+ *   level schedule .......... Sec. 2.4-2.5 (Algorithm 1's order, walked as a
+ *                             clock over the finest substeps)
  *
  * Readings where the paper is silent (same list as the design notes):
  *   - tau per level: tau_l - 1/2 = 2^l (tau_0 - 1/2) (same viscosity, dt ~ dx).
@@ -26,7 +27,7 @@
  *     interpolation uses the uncorrected velocity, later ones the corrected one.
  *   - halo ("ghost") cells are never collided; they are streamed in both fine
  *     substeps; coarse-to-fine fills them only before the first substep; the
- *     PreStreamingStep makes their post-stream values the sources of the
+ *     halo cells' post-stream values are the sources of the
  *     second stream.
  *   - fine-to-coarse replaces f(X,i) exactly when X - c_i is covered by the
  *     finer level, with the mean of the 4 children of X.
@@ -36,7 +37,7 @@
  *   - domain edges: half-way bounce-back with the moving-wall term (wall
  *     density rho0), equilibrium inflow at rho0, zero-gradient outflow,
  *     specular symmetry, periodic; corner diagonals follow the rule stated
- *     at boundary().
+ *     at edge_rules().
  */
 #include "oracle.h"
 
@@ -592,12 +593,38 @@ int orc_init_fields(orc_sim *s, int level, const double *rho, const double *ux, 
     return ORC_OK;
 }
 
+/* Pre-collision populations of the owned cells of a level, dense [ny][nx][9]
+ * (a state with a non-equilibrium part; the other cells keep theirs). */
+int orc_init_populations(orc_sim *s, int level, const double *f) {
+    if (level < 0 || level >= s->m) return ORC_ERR_ARG;
+    olev *L = &s->L[level];
+    for (size_t q = 0; q < (size_t)L->nx * L->ny; ++q)
+        if (L->kind[q] == K_OWN) memcpy(L->f + q * Q, f + q * Q, sizeof(double) * Q);
+    return ORC_OK;
+}
+
+/* Scale factors of the non-equilibrium part under the RESCALE interface
+ * mode, for a coarse level of relaxation time tau_c over a fine level of
+ * tau_f (Sec. 2.4 names no factor; this is the reading that converts a
+ * first-order Chapman-Enskog non-equilibrium part, -tau dt c.grad f^eq,
+ * between two grids of spacing ratio 2 under acoustic scaling):
+ *   out[0] = s_cf = (tau_f - 1) / (2 (tau_c - 1)), coarse -> fine, applied
+ *            to post-collision populations (their part is (tau - 1)/tau of
+ *            the pre-collision one);
+ *   out[1] = s_fc = 2 tau_c / tau_f, fine -> coarse, applied to pre-
+ *            collision populations. */
+void orc_interface_factors(double tau_c, double tau_f, double out[2]) {
+    out[0] = (tau_f - 1.0) / (2.0 * (tau_c - 1.0));
+    out[1] = 2.0 * tau_c / tau_f;
+}
+
 /* ------------------------------------------------------------------------ */
-/* The steps of Algorithm 1                                                  */
+/* The steps of one time step (Sec. 2.1-2.4)                               */
 /* ------------------------------------------------------------------------ */
 
-/* UpdateVelocity: the IBM / MDF step on the finest level (Sec. 2.2). */
-static void update_velocity(orc_sim *s, int l) {
+/* Immersed-boundary forcing on the finest level: kinematics, moments of the
+ * stencil cells, the multi-direct-forcing loop and the body force (Sec. 2.2). */
+static void ibm_forcing(orc_sim *s, int l) {
     if (l != s->m - 1 || s->c.body_kind == ORC_BODY_NONE || s->c.n_markers == 0) return;
     olev *L = &s->L[l];
     int n = s->c.n_markers;
@@ -655,8 +682,9 @@ static void update_velocity(orc_sim *s, int l) {
     free(X); free(rho); free(ux); free(uy);
 }
 
-/* CollisionStep: owned cells only; F = body force + IBM force (finest). */
-static void collision(orc_sim *s, int l) {
+/* Collision of a level's owned cells, Eqs. (2)-(8); F = body force plus the
+ * IBM force on the finest level. */
+static void collide_level(orc_sim *s, int l) {
     olev *L = &s->L[l];
     int finest = (l == s->m - 1);
 #pragma omp parallel for schedule(static)
@@ -675,11 +703,13 @@ static void collision(orc_sim *s, int l) {
         }
 }
 
-/* CoarseToFineCommunication (step (2) of Sec. 2.4): each halo cell of the
+/* Explosion (step (2) of Sec. 2.4): each halo cell of the
  * fine level takes the post-collision populations of its coarse parent. */
-static void coarse_to_fine(orc_sim *s, int lc, int lf) {
+static void explode(orc_sim *s, int lc, int lf) {
     olev *C = &s->L[lc], *F = &s->L[lf];
-    double scf = (F->tau - 1.0) / (2.0 * (C->tau - 1.0));
+    double fac[2];
+    orc_interface_factors(C->tau, F->tau, fac);
+    const double scf = fac[0];
     int rescale = s->c.cf_mode == ORC_CF_RESCALE;
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < F->ny; ++y)
@@ -699,7 +729,7 @@ static void coarse_to_fine(orc_sim *s, int lc, int lf) {
         }
 }
 
-/* StreamingStep, Eq. (10), over owned and halo cells; same-level exchange is
+/* Streaming, Eq. (10), over owned and halo cells; same-level exchange is
  * implicit in the dense arrays (with the periodic wrap).  Unknown incoming
  * populations are left NaN for the boundary and fine-to-coarse steps. */
 static int opposite(int i);
@@ -725,7 +755,7 @@ static double bouzidi(const orc_sim *s, const olev *L, int x, int y, int i) {
     return L->fs[c * Q + o] / (2.0 * q) + (2.0 * q - 1.0) / (2.0 * q) * L->fs[c * Q + i];
 }
 
-static void streaming(orc_sim *s, int l) {
+static void stream_level(orc_sim *s, int l) {
     olev *L = &s->L[l];
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < L->ny; ++y)
@@ -750,9 +780,9 @@ static void streaming(orc_sim *s, int l) {
         }
 }
 
-/* PreStreamingStep: before the second fine stream the halo cells' sources
+/* Halo sources of the second fine stream (step (5) of Sec. 2.4): the halo cells' sources
  * are their own post-stream values of the first substep. */
-static void pre_streaming(orc_sim *s, int l) {
+static void halo_second_sources(orc_sim *s, int l) {
     olev *L = &s->L[l];
     for (size_t q = 0; q < (size_t)L->nx * L->ny; ++q)
         if (L->kind[q] == K_GHOST) memcpy(L->fs + q * Q, L->f + q * Q, sizeof(double) * Q);
@@ -782,12 +812,12 @@ static void clamp_level(const olev *L, int *x, int *y) {
 
 static int local_kind(int k) { return k == ORC_BC_WALL || k == ORC_BC_INFLOW; }
 
-/* BoundaryConditionStep: fills the unknown populations of edge cells.  A
+/* Domain edges: fills the unknown populations of edge cells.  A
  * population whose source lies beyond one non-periodic edge takes that
  * edge's rule; one beyond two edges (a corner diagonal) takes the W/E edge's
  * rule unless only the S/N edge is a wall or inflow, with any cell that rule
  * refers to clamped into the domain. */
-static void boundary(orc_sim *s, int l) {
+static void edge_rules(orc_sim *s, int l) {
     olev *L = &s->L[l];
     if (s->per_x && s->per_y) return;
     const int nrm[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
@@ -835,10 +865,12 @@ static void boundary(orc_sim *s, int l) {
         }
 }
 
-/* FineToCoarseCommunication (step (6) of Sec. 2.4). */
-static void fine_to_coarse(orc_sim *s, int lf, int lc) {
+/* Coalescence (step (6) of Sec. 2.4). */
+static void coalesce(orc_sim *s, int lf, int lc) {
     olev *F = &s->L[lf], *C = &s->L[lc];
-    double sfc = 2.0 * C->tau / F->tau;
+    double fac[2];
+    orc_interface_factors(C->tau, F->tau, fac);
+    const double sfc = fac[1];
     int rescale = s->c.cf_mode == ORC_CF_RESCALE;
 #pragma omp parallel for schedule(static)
     for (int y = 0; y < C->ny; ++y)
@@ -877,32 +909,69 @@ static void fine_to_coarse(orc_sim *s, int lf, int lc) {
         }
 }
 
-/* Algorithm 1: SynchronousNonUniformTimeStep(l). */
-static void snuts(orc_sim *s, int l) {
-    int m = s->m;
-    update_velocity(s, l);
-    if (l == m - 1 && s->c.body_kind != ORC_BODY_NONE) s->k++;
-    collision(s, l);
-    if (l != m - 1) snuts(s, l + 1);
-    if (l != 0) coarse_to_fine(s, l - 1, l);
-    streaming(s, l);
-    boundary(s, l);
-    if (l != m - 1) fine_to_coarse(s, l + 1, l);
-    if (l == 0) return;
-    update_velocity(s, l);
-    if (l == m - 1 && s->c.body_kind != ORC_BODY_NONE) s->k++;
-    collision(s, l);
-    if (l != m - 1) snuts(s, l + 1);
-    pre_streaming(s, l);
-    streaming(s, l);
-    boundary(s, l);
-    if (l != m - 1) fine_to_coarse(s, l + 1, l);
+/* One coarse (level-0) time step of the whole forest, Sec. 2.4 and 2.5.
+ *
+ * Acoustic scaling gives level l a time step of 2^-l coarse units, so the
+ * finest level m-1 takes 2^(m-1) substeps per coarse step and substep j of
+ * level l covers the finest substeps [j 2^(m-1-l), (j+1) 2^(m-1-l)).  Each
+ * level substep collides at the start of its interval and streams at its
+ * end.  Walking a clock over the finest substeps therefore gives the order:
+ * at the start of finest substep t every level whose interval starts there
+ * collides, coarse to fine; at its end every level whose interval ends there
+ * streams, fine to coarse.  The interface steps (1)-(6) of Sec. 2.4 fall in
+ * place:
+ *   (1) the coarse level collides before its two fine substeps;
+ *   (2) before the first of them the fine halo takes the coarse
+ *       post-collision populations (explosion);
+ *   (3) the fine level streams its owned and halo cells;
+ *   (4) the fine level collides again (halo cells never collide);
+ *   (5) it streams a second time, the halo cells supplying the values they
+ *       received in (3);
+ *   (6) when the coarse interval ends, the coarse level streams and takes
+ *       the fine populations it cannot stream itself (coalescence).
+ * The immersed-boundary forcing (Sec. 2.2) precedes every finest collision. */
+static void level_collide(orc_sim *s, int l) {
+    const int finest = l == s->m - 1;
+    if (finest && s->c.body_kind != ORC_BODY_NONE) {
+        ibm_forcing(s, l);
+        s->k++;
+    }
+    collide_level(s, l);
+}
+
+/* End of substep j of level l: halo preparation (explosion before the first
+ * of the two substeps inside a coarse substep, the halo's own first-stream
+ * values before the second), streaming, domain edges, coalescence from the
+ * finer level. */
+static void level_stream(orc_sim *s, int l, int64_t j) {
+    if (l > 0) {
+        if ((j & 1) == 0) explode(s, l - 1, l);
+        else halo_second_sources(s, l);
+    }
+    stream_level(s, l);
+    edge_rules(s, l);
+    if (l + 1 < s->m) coalesce(s, l + 1, l);
+}
+
+static void coarse_step(orc_sim *s) {
+    const int m = s->m;
+    const int64_t nsub = (int64_t)1 << (m - 1);      /* finest substeps per coarse step */
+    for (int64_t t = 0; t < nsub && !s->err; ++t) {
+        for (int l = 0; l < m; ++l) {
+            const int64_t span = nsub >> l;              /* finest substeps per level-l substep */
+            if (t % span == 0) level_collide(s, l);
+        }
+        for (int l = m - 1; l >= 0; --l) {
+            const int64_t span = nsub >> l;
+            if ((t + 1) % span == 0) level_stream(s, l, t / span);
+        }
+    }
 }
 
 int orc_step(orc_sim *s, int32_t n) {
     for (int32_t t = 0; t < n && !s->err; ++t) {
         if (s->c.body_kind == ORC_BODY_NONE) s->k += (int64_t)1 << (s->m - 1);
-        snuts(s, 0);
+        coarse_step(s);
     }
     return s->err;
 }
@@ -1307,6 +1376,12 @@ int orc3_set_motion(orc3_sim *s, int32_t kind, const double p[10]) {
     if (kind != 0 && kind != 1) return ORC_ERR_ARG;
     s->kind = kind;
     for (int i = 0; i < 10; ++i) s->bp[i] = p ? p[i] : 0.0;
+    return ORC_OK;
+}
+
+int orc3_marker_positions(const orc3_sim *s, double t, double *X, double *Y, double *Z) {
+    if (s->nm <= 0) return ORC_ERR_ARG;
+    body3_positions(s, t, X, Y, Z);
     return ORC_OK;
 }
 

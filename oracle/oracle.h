@@ -65,6 +65,11 @@ int  orc_level_kinds(const orc_sim *s, int level, uint8_t *kind);
 /* f = f^eq(rho, u) with F = 0 on the owned cells of `level` (dense arrays). */
 int  orc_init_fields(orc_sim *s, int level, const double *rho, const double *ux,
                      const double *uy);
+/* Pre-collision populations of the owned cells of `level`, dense [ny][nx][9]. */
+int  orc_init_populations(orc_sim *s, int level, const double *f);
+/* RESCALE factors {s_cf (coarse -> fine, post-collision), s_fc (fine ->
+ * coarse, pre-collision)} for relaxation times tau_c (coarse), tau_f (fine). */
+void orc_interface_factors(double tau_c, double tau_f, double out[2]);
 /* Advance n coarse (level-0) time steps. */
 int  orc_step(orc_sim *s, int32_t n);
 /* rho and u = (sum_i c_i f_i + F_ext/2)/rho on owned cells, NaN elsewhere. */
@@ -150,6 +155,8 @@ int  orc3_set_body(orc3_sim *s, int32_t n, const double *X, const double *Y, con
 int  orc3_set_motion(orc3_sim *s, int32_t kind, const double p[10]);
 /* F_s = -sum_j F_j dA_j of the last step. */
 int  orc3_body_force(const orc3_sim *s, double out[3]);
+/* Marker positions of the body at step t (after orc3_set_body/_motion). */
+int  orc3_marker_positions(const orc3_sim *s, double t, double *X, double *Y, double *Z);
 int  orc3_read_fields(const orc3_sim *s, double *rho, double *ux, double *uy, double *uz);
 
 #ifdef __cplusplus
