@@ -73,7 +73,9 @@ typedef struct {
     const double *marker_dA;       /* [n_markers] surface element of each marker     */
     int32_t mdf_iters;             /* N_F of the forcing loop                        */
     int64_t ibm_box_cells;         /* capacity (>= 64) of the box of stencil cells
-                                      the body's forcing works in                    */
+                                      the body's forcing works in; 0: the library
+                                      sizes it from the markers' reach over the
+                                      motion plus the stencil, capped at the box     */
     int32_t body_motion;           /* 0: fixed (marker_xyz absolute); 1: pitch about
                                       the y axis and plunge along z (marker_xyz in
                                       the body frame)                                */
@@ -109,7 +111,9 @@ sbt_status sbt3_step(sbt3_ctx *ctx, int32_t n);
 sbt_status sbt3_synchronize(sbt3_ctx *ctx);
 /* Body force F_s = -sum_j F_j dA_j of the last completed step (sum over
  * the N_F passes of each marker's force).  Synchronises.  SBT_ERR_STATE
- * without a body or before the first step. */
+ * without a body or before the first step; SBT_ERR_MARKER_OUTSIDE when a
+ * step since the last sbt3_synchronize ran without the body force (its
+ * stencils left the box or outgrew ibm_box_cells), leaving the flag set. */
 sbt_status sbt3_body_force(sbt3_ctx *ctx, double out[3]);
 /* rho and u = (sum_i c_i f_i + F/2) / rho on planes z0 .. z0 + nz - 1 into
  * host FP64 arrays [nz][ny][nx].  Synchronises. */

@@ -69,6 +69,12 @@ typedef struct {
     uint8_t *solid;           /* solid (bounce-back) cells, or NULL          */
     double *sq;               /* [cell][9] wall fraction of link i from a fluid
                                  cell toward a solid neighbour x + c_i       */
+    /* the cells each step visits, in ascending index: the dense arrays are
+       the data, these lists only spare the scans over cells that take no
+       part (a refined level covers a small part of its dense grid)       */
+    int64_t *own, *ghost, *act;   /* owned; halo; owned or halo            */
+    int64_t n_own, n_ghost, n_act;
+    int64_t *fcell, n_fcell;      /* finest level: cells the last forcing wrote */
 } olev;
 
 struct orc_sim {
@@ -351,6 +357,43 @@ int orc_spread(int32_t nx, int32_t ny, int32_t n, const double *X, const double 
  * times): interpolate velocity and density at the markers, boundary force
  * Eq. (11) with dt = 1, spread, correct the cell velocity by dF/(2 rho)
  * (consistent with the half-force velocity of Eq. (8)) and accumulate. */
+/* Cells within the 4x4 stencil of any marker (periodic wrap), ascending;
+ * returns their count, the list in *out (caller frees). */
+static int64_t stencil_cells(int32_t nx, int32_t ny, int32_t n, const double *X, const double *Y,
+                             int64_t **out) {
+    const size_t ncell = (size_t)nx * ny;
+    uint8_t *mark = calloc(ncell, 1);
+    int64_t cnt = 0;
+    for (int j = 0; j < n; ++j) {
+        int i0 = tap0(X[j]), j0 = tap0(Y[j]);
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) {
+                size_t c = (size_t)wrapi(j0 + b, ny) * nx + wrapi(i0 + a, nx);
+                if (!mark[c]) { mark[c] = 1; ++cnt; }
+            }
+    }
+    int64_t *list = malloc(sizeof(int64_t) * (cnt + 1));
+    int64_t k = 0;
+    if (cnt > 0)
+        for (int j = 0; j < n; ++j) {
+            int i0 = tap0(X[j]), j0 = tap0(Y[j]);
+            for (int b = 0; b < 4; ++b)
+                for (int a = 0; a < 4; ++a) {
+                    size_t c = (size_t)wrapi(j0 + b, ny) * nx + wrapi(i0 + a, nx);
+                    if (mark[c] == 1) { mark[c] = 2; list[k++] = (int64_t)c; }
+                }
+        }
+    free(mark);
+    /* ascending (insertion sort of a short list) */
+    for (int64_t i = 1; i < k; ++i) {
+        int64_t v = list[i], t = i;
+        while (t > 0 && list[t - 1] > v) { list[t] = list[t - 1]; --t; }
+        list[t] = v;
+    }
+    *out = list;
+    return k;
+}
+
 int orc_mdf(int32_t nx, int32_t ny, const double *rho, double *ux, double *uy, double *Fx,
             double *Fy, int32_t n, const double *X, const double *Y, const double *udx,
             const double *udy, const double *ds, int32_t iters, double *ftx, double *fty) {
@@ -360,6 +403,10 @@ int orc_mdf(int32_t nx, int32_t ny, const double *rho, double *ux, double *uy, d
     if (!U || !dFx || !dFy) { free(U); free(dFx); free(dFy); return ORC_ERR_ARG; }
     double *V = U + n, *R = U + 2 * n, *Rv = U + 3 * n;
     double *zero = calloc(ncell, sizeof(double));
+    /* spreading and the corrections touch only the stencil cells; the other
+       cells keep dF = 0 and are skipped as in a scan of the whole grid */
+    int64_t *cells = NULL;
+    const int64_t ns = stencil_cells(nx, ny, n, X, Y, &cells);
     for (int j = 0; j < n; ++j) { ftx[j] = 0.0; fty[j] = 0.0; }
     for (int it = 0; it < iters; ++it) {
         orc_interpolate(nx, ny, ux, uy, n, X, Y, U, V);
@@ -371,10 +418,10 @@ int orc_mdf(int32_t nx, int32_t ny, const double *rho, double *ux, double *uy, d
             ftx[j] += gx[j];
             fty[j] += gy[j];
         }
-        memset(dFx, 0, sizeof(double) * ncell);
-        memset(dFy, 0, sizeof(double) * ncell);
+        for (int64_t k = 0; k < ns; ++k) dFx[cells[k]] = dFy[cells[k]] = 0.0;
         orc_spread(nx, ny, n, X, Y, gx, gy, ds, dFx, dFy);
-        for (size_t c = 0; c < ncell; ++c) {
+        for (int64_t k = 0; k < ns; ++k) {
+            const size_t c = (size_t)cells[k];
             if (dFx[c] == 0.0 && dFy[c] == 0.0) continue;
             Fx[c] += dFx[c];
             Fy[c] += dFy[c];
@@ -383,7 +430,7 @@ int orc_mdf(int32_t nx, int32_t ny, const double *rho, double *ux, double *uy, d
         }
         free(gx);
     }
-    free(U); free(dFx); free(dFy); free(zero);
+    free(U); free(dFx); free(dFy); free(zero); free(cells);
     return ORC_OK;
 }
 
@@ -474,6 +521,26 @@ static int build_topology(orc_sim *s) {
                     return ORC_ERR_TOPOLOGY;
             }
     }
+    /* cell lists of each level, ascending */
+    for (int l = 0; l < m; ++l) {
+        olev *L = &s->L[l];
+        const size_t n = (size_t)L->nx * L->ny;
+        int64_t no = 0, ng = 0;
+        for (size_t q = 0; q < n; ++q) {
+            no += L->kind[q] == K_OWN;
+            ng += L->kind[q] == K_GHOST;
+        }
+        L->own = malloc(sizeof(int64_t) * (no + 1));
+        L->ghost = malloc(sizeof(int64_t) * (ng + 1));
+        L->act = malloc(sizeof(int64_t) * (no + ng + 1));
+        L->fcell = NULL;
+        L->n_own = L->n_ghost = L->n_act = L->n_fcell = 0;
+        for (size_t q = 0; q < n; ++q) {
+            if (L->kind[q] == K_OWN) L->own[L->n_own++] = (int64_t)q;
+            if (L->kind[q] == K_GHOST) L->ghost[L->n_ghost++] = (int64_t)q;
+            if (L->kind[q] == K_OWN || L->kind[q] == K_GHOST) L->act[L->n_act++] = (int64_t)q;
+        }
+    }
     return ORC_OK;
 }
 
@@ -487,6 +554,7 @@ void orc_destroy(orc_sim *s) {
         olev *L = &s->L[l];
         free(L->kind); free(L->f); free(L->fs); free(L->rho); free(L->ux); free(L->uy);
         free(L->Fx); free(L->Fy); free(L->solid); free(L->sq);
+        free(L->own); free(L->ghost); free(L->act); free(L->fcell);
     }
     free(s->boxes); free(s->xb); free(s->yb); free(s->ds); free(s->hist); free(s->hud);
     free(s->ftx); free(s->fty);
@@ -642,8 +710,11 @@ static void ibm_forcing(orc_sim *s, int l) {
     /* Moments of the stencil cells: rho and the uncorrected velocity. */
     double *rho = calloc(ncell, sizeof(double));
     double *ux = calloc(ncell, sizeof(double)), *uy = calloc(ncell, sizeof(double));
-    memset(L->Fx, 0, sizeof(double) * ncell);
-    memset(L->Fy, 0, sizeof(double) * ncell);
+    /* F = 0 outside this substep's stencils: clear the cells the last forcing
+       wrote, and remember the ones this forcing writes */
+    for (int64_t k = 0; k < L->n_fcell; ++k) L->Fx[L->fcell[k]] = L->Fy[L->fcell[k]] = 0.0;
+    free(L->fcell);
+    L->n_fcell = stencil_cells(L->nx, L->ny, n, X, Y, &L->fcell);
     for (int j = 0; j < n; ++j) {
         int i0 = tap0(X[j]), j0 = tap0(Y[j]);
         for (int b = 0; b < 4; ++b)
@@ -688,19 +759,18 @@ static void collide_level(orc_sim *s, int l) {
     olev *L = &s->L[l];
     int finest = (l == s->m - 1);
 #pragma omp parallel for schedule(static)
-    for (int y = 0; y < L->ny; ++y)
-        for (int x = 0; x < L->nx; ++x) {
-            size_t q = cid(L, x, y);
-            if (L->kind[q] != K_OWN || (L->solid && L->solid[q])) continue;
-            double Fx = L->fx, Fy = L->fy;
-            if (finest) { Fx += L->Fx[q]; Fy += L->Fy[q]; }
-            double mom[3];
-            if (s->c.collision == ORC_COLL_MRT)
-                collide_mrt(L->tau, s->c.mrt, L->f + q * Q, Fx, Fy, L->fs + q * Q, mom);
-            else
-                collide_cell(L->tau, L->f + q * Q, Fx, Fy, L->fs + q * Q, mom);
-            L->rho[q] = mom[0]; L->ux[q] = mom[1]; L->uy[q] = mom[2];
-        }
+    for (int64_t k = 0; k < L->n_own; ++k) {
+        const size_t q = (size_t)L->own[k];
+        if (L->solid && L->solid[q]) continue;
+        double Fx = L->fx, Fy = L->fy;
+        if (finest) { Fx += L->Fx[q]; Fy += L->Fy[q]; }
+        double mom[3];
+        if (s->c.collision == ORC_COLL_MRT)
+            collide_mrt(L->tau, s->c.mrt, L->f + q * Q, Fx, Fy, L->fs + q * Q, mom);
+        else
+            collide_cell(L->tau, L->f + q * Q, Fx, Fy, L->fs + q * Q, mom);
+        L->rho[q] = mom[0]; L->ux[q] = mom[1]; L->uy[q] = mom[2];
+    }
 }
 
 /* Explosion (step (2) of Sec. 2.4): each halo cell of the
@@ -712,21 +782,20 @@ static void explode(orc_sim *s, int lc, int lf) {
     const double scf = fac[0];
     int rescale = s->c.cf_mode == ORC_CF_RESCALE;
 #pragma omp parallel for schedule(static)
-    for (int y = 0; y < F->ny; ++y)
-        for (int x = 0; x < F->nx; ++x) {
-            size_t q = cid(F, x, y);
-            if (F->kind[q] != K_GHOST) continue;
-            size_t p = cid(C, x / 2, y / 2);
-            const double *src = C->fs + p * Q;
-            double *dst = F->fs + q * Q;
-            if (!rescale) {
-                for (int i = 0; i < Q; ++i) dst[i] = src[i];
-            } else {
-                double feq[Q];
-                orc_feq(C->rho[p], C->ux[p], C->uy[p], feq);
-                for (int i = 0; i < Q; ++i) dst[i] = feq[i] + scf * (src[i] - feq[i]);
-            }
+    for (int64_t k = 0; k < F->n_ghost; ++k) {
+        const size_t q = (size_t)F->ghost[k];
+        const int x = (int)(q % (size_t)F->nx), y = (int)(q / (size_t)F->nx);
+        size_t p = cid(C, x / 2, y / 2);
+        const double *src = C->fs + p * Q;
+        double *dst = F->fs + q * Q;
+        if (!rescale) {
+            for (int i = 0; i < Q; ++i) dst[i] = src[i];
+        } else {
+            double feq[Q];
+            orc_feq(C->rho[p], C->ux[p], C->uy[p], feq);
+            for (int i = 0; i < Q; ++i) dst[i] = feq[i] + scf * (src[i] - feq[i]);
         }
+    }
 }
 
 /* Streaming, Eq. (10), over owned and halo cells; same-level exchange is
@@ -758,34 +827,34 @@ static double bouzidi(const orc_sim *s, const olev *L, int x, int y, int i) {
 static void stream_level(orc_sim *s, int l) {
     olev *L = &s->L[l];
 #pragma omp parallel for schedule(static)
-    for (int y = 0; y < L->ny; ++y)
-        for (int x = 0; x < L->nx; ++x) {
-            size_t q = cid(L, x, y);
-            uint8_t kd = L->kind[q];
-            if (kd != K_OWN && kd != K_GHOST) continue;
-            if (L->solid && L->solid[q]) continue;
-            for (int i = 0; i < Q; ++i) {
-                int sx = x - CX[i], sy = y - CY[i];
-                double v = NAN;
-                if (wrap_level(s, L, &sx, &sy)) {
-                    size_t p = cid(L, sx, sy);
-                    if (L->solid && L->solid[p]) {
-                        v = bouzidi(s, L, x, y, i);
-                    } else if (L->kind[p] == K_OWN || L->kind[p] == K_GHOST) {
-                        v = L->fs[p * Q + i];
-                    }
+    for (int64_t k = 0; k < L->n_act; ++k) {
+        const size_t q = (size_t)L->act[k];
+        const int x = (int)(q % (size_t)L->nx), y = (int)(q / (size_t)L->nx);
+        if (L->solid && L->solid[q]) continue;
+        for (int i = 0; i < Q; ++i) {
+            int sx = x - CX[i], sy = y - CY[i];
+            double v = NAN;
+            if (wrap_level(s, L, &sx, &sy)) {
+                size_t p = cid(L, sx, sy);
+                if (L->solid && L->solid[p]) {
+                    v = bouzidi(s, L, x, y, i);
+                } else if (L->kind[p] == K_OWN || L->kind[p] == K_GHOST) {
+                    v = L->fs[p * Q + i];
                 }
-                L->f[q * Q + i] = v;
             }
+            L->f[q * Q + i] = v;
         }
+    }
 }
 
 /* Halo sources of the second fine stream (step (5) of Sec. 2.4): the halo cells' sources
  * are their own post-stream values of the first substep. */
 static void halo_second_sources(orc_sim *s, int l) {
     olev *L = &s->L[l];
-    for (size_t q = 0; q < (size_t)L->nx * L->ny; ++q)
-        if (L->kind[q] == K_GHOST) memcpy(L->fs + q * Q, L->f + q * Q, sizeof(double) * Q);
+    for (int64_t k = 0; k < L->n_ghost; ++k) {
+        const size_t q = (size_t)L->ghost[k];
+        memcpy(L->fs + q * Q, L->f + q * Q, sizeof(double) * Q);
+    }
 }
 
 static int opposite(int i) {
@@ -822,47 +891,46 @@ static void edge_rules(orc_sim *s, int l) {
     if (s->per_x && s->per_y) return;
     const int nrm[4][2] = {{-1, 0}, {1, 0}, {0, -1}, {0, 1}};
     double rho0 = s->c.rho0;
-    for (int y = 0; y < L->ny; ++y)
-        for (int x = 0; x < L->nx; ++x) {
-            size_t q = cid(L, x, y);
-            if (L->kind[q] != K_OWN) continue;
-            for (int i = 1; i < Q; ++i) {
-                int sx = x - CX[i], sy = y - CY[i];
-                int outx = (sx < 0 || sx >= L->nx) && !s->per_x;
-                int outy = (sy < 0 || sy >= L->ny) && !s->per_y;
-                if (!outx && !outy) continue;
-                int ex = sx < 0 ? ORC_W : ORC_E, ey = sy < 0 ? ORC_S : ORC_N;
-                int e = outx ? ex : ey;
-                if (outx && outy && !local_kind(s->c.bc[ex]) && local_kind(s->c.bc[ey])) e = ey;
-                double *fx = L->f + q * Q;
-                const double *fsx = L->fs + q * Q;
-                double uwx = s->c.bc_u[2 * e], uwy = s->c.bc_u[2 * e + 1];
-                switch (s->c.bc[e]) {
-                case ORC_BC_WALL:
-                    fx[i] = fsx[opposite(i)] + 6.0 * WT[i] * rho0 * (CX[i] * uwx + CY[i] * uwy);
-                    break;
-                case ORC_BC_INFLOW: {
-                    double feq[Q];
-                    orc_feq(rho0, uwx, uwy, feq);
-                    fx[i] = feq[i];
-                } break;
-                case ORC_BC_OUTFLOW: {
-                    int px = x - nrm[e][0] - CX[i], py = y - nrm[e][1] - CY[i];
-                    wrap_level(s, L, &px, &py);
-                    clamp_level(L, &px, &py);
-                    fx[i] = L->fs[cid(L, px, py) * Q + i];
-                } break;
-                case ORC_BC_SYMMETRY: {
-                    int nx_ = (e == ORC_W || e == ORC_E);
-                    int px = x - (nx_ ? 0 : CX[i]), py = y - (nx_ ? CY[i] : 0);
-                    wrap_level(s, L, &px, &py);
-                    clamp_level(L, &px, &py);
-                    fx[i] = L->fs[cid(L, px, py) * Q + mirror(i, nx_)];
-                } break;
-                default: break;
-                }
+    for (int64_t k = 0; k < L->n_own; ++k) {
+        const size_t q = (size_t)L->own[k];
+        const int x = (int)(q % (size_t)L->nx), y = (int)(q / (size_t)L->nx);
+        for (int i = 1; i < Q; ++i) {
+            int sx = x - CX[i], sy = y - CY[i];
+            int outx = (sx < 0 || sx >= L->nx) && !s->per_x;
+            int outy = (sy < 0 || sy >= L->ny) && !s->per_y;
+            if (!outx && !outy) continue;
+            int ex = sx < 0 ? ORC_W : ORC_E, ey = sy < 0 ? ORC_S : ORC_N;
+            int e = outx ? ex : ey;
+            if (outx && outy && !local_kind(s->c.bc[ex]) && local_kind(s->c.bc[ey])) e = ey;
+            double *fx = L->f + q * Q;
+            const double *fsx = L->fs + q * Q;
+            double uwx = s->c.bc_u[2 * e], uwy = s->c.bc_u[2 * e + 1];
+            switch (s->c.bc[e]) {
+            case ORC_BC_WALL:
+                fx[i] = fsx[opposite(i)] + 6.0 * WT[i] * rho0 * (CX[i] * uwx + CY[i] * uwy);
+                break;
+            case ORC_BC_INFLOW: {
+                double feq[Q];
+                orc_feq(rho0, uwx, uwy, feq);
+                fx[i] = feq[i];
+            } break;
+            case ORC_BC_OUTFLOW: {
+                int px = x - nrm[e][0] - CX[i], py = y - nrm[e][1] - CY[i];
+                wrap_level(s, L, &px, &py);
+                clamp_level(L, &px, &py);
+                fx[i] = L->fs[cid(L, px, py) * Q + i];
+            } break;
+            case ORC_BC_SYMMETRY: {
+                int nx_ = (e == ORC_W || e == ORC_E);
+                int px = x - (nx_ ? 0 : CX[i]), py = y - (nx_ ? CY[i] : 0);
+                wrap_level(s, L, &px, &py);
+                clamp_level(L, &px, &py);
+                fx[i] = L->fs[cid(L, px, py) * Q + mirror(i, nx_)];
+            } break;
+            default: break;
             }
         }
+    }
 }
 
 /* Coalescence (step (6) of Sec. 2.4). */
@@ -873,40 +941,39 @@ static void coalesce(orc_sim *s, int lf, int lc) {
     const double sfc = fac[1];
     int rescale = s->c.cf_mode == ORC_CF_RESCALE;
 #pragma omp parallel for schedule(static)
-    for (int y = 0; y < C->ny; ++y)
-        for (int x = 0; x < C->nx; ++x) {
-            size_t q = cid(C, x, y);
-            if (C->kind[q] != K_OWN) continue;
-            int hid[Q];
-            int any = 0;
-            for (int i = 0; i < Q; ++i) {
-                int sx = x - CX[i], sy = y - CY[i];
-                hid[i] = wrap_level(s, C, &sx, &sy) && C->kind[cid(C, sx, sy)] == K_HIDDEN;
-                any |= hid[i];
-            }
-            if (!any) continue;
-            double avg[Q];
-            for (int i = 0; i < Q; ++i) {
-                if (!hid[i]) continue;
-                double sum = F->f[cid(F, 2 * x, 2 * y) * Q + i];
-                sum += F->f[cid(F, 2 * x + 1, 2 * y) * Q + i];
-                sum += F->f[cid(F, 2 * x, 2 * y + 1) * Q + i];
-                sum += F->f[cid(F, 2 * x + 1, 2 * y + 1) * Q + i];
-                avg[i] = 0.25 * sum;
-            }
-            double *dst = C->f + q * Q;
-            if (!rescale) {
-                for (int i = 0; i < Q; ++i) if (hid[i]) dst[i] = avg[i];
-            } else {
-                double g[Q], r = 0.0, jx = 0.0, jy = 0.0;
-                for (int i = 0; i < Q; ++i) g[i] = hid[i] ? avg[i] : dst[i];
-                for (int i = 0; i < Q; ++i) { r += g[i]; jx += CX[i] * g[i]; jy += CY[i] * g[i]; }
-                double feq[Q];
-                orc_feq(r, jx / r, jy / r, feq);
-                for (int i = 0; i < Q; ++i)
-                    if (hid[i]) dst[i] = feq[i] + sfc * (avg[i] - feq[i]);
-            }
+    for (int64_t k = 0; k < C->n_own; ++k) {
+        const size_t q = (size_t)C->own[k];
+        const int x = (int)(q % (size_t)C->nx), y = (int)(q / (size_t)C->nx);
+        int hid[Q];
+        int any = 0;
+        for (int i = 0; i < Q; ++i) {
+            int sx = x - CX[i], sy = y - CY[i];
+            hid[i] = wrap_level(s, C, &sx, &sy) && C->kind[cid(C, sx, sy)] == K_HIDDEN;
+            any |= hid[i];
         }
+        if (!any) continue;
+        double avg[Q];
+        for (int i = 0; i < Q; ++i) {
+            if (!hid[i]) continue;
+            double sum = F->f[cid(F, 2 * x, 2 * y) * Q + i];
+            sum += F->f[cid(F, 2 * x + 1, 2 * y) * Q + i];
+            sum += F->f[cid(F, 2 * x, 2 * y + 1) * Q + i];
+            sum += F->f[cid(F, 2 * x + 1, 2 * y + 1) * Q + i];
+            avg[i] = 0.25 * sum;
+        }
+        double *dst = C->f + q * Q;
+        if (!rescale) {
+            for (int i = 0; i < Q; ++i) if (hid[i]) dst[i] = avg[i];
+        } else {
+            double g[Q], r = 0.0, jx = 0.0, jy = 0.0;
+            for (int i = 0; i < Q; ++i) g[i] = hid[i] ? avg[i] : dst[i];
+            for (int i = 0; i < Q; ++i) { r += g[i]; jx += CX[i] * g[i]; jy += CY[i] * g[i]; }
+            double feq[Q];
+            orc_feq(r, jx / r, jy / r, feq);
+            for (int i = 0; i < Q; ++i)
+                if (hid[i]) dst[i] = feq[i] + sfc * (avg[i] - feq[i]);
+        }
+    }
 }
 
 /* One coarse (level-0) time step of the whole forest, Sec. 2.4 and 2.5.

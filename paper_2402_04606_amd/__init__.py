@@ -438,15 +438,8 @@ class Sim3:
             d.marker_xyz = _dp(xyz)
             d.marker_dA = _dp(da)
             d.mdf_iters = int(iters)
-            # the box of stencil cells: the body's reach (over its motion) plus
-            # the 4-cell stencil, capped at the whole lattice
             kind, params = getattr(wl, "motion", (0, None))
-            ext = [np.ptp(np.asarray(v, dtype=np.float64)) for v in (X, Y, Z)]
-            if kind == 1:
-                r = float(np.max(np.hypot(X, Z)))
-                ext = [2 * r, ext[1], 2 * r + abs(params[5])]
-            cells = int(np.prod([int(np.ceil(e)) + 6 for e in ext]))
-            d.ibm_box_cells = box_cells or max(64, min(cells, wl.nx * wl.ny * wl.nz))
+            d.ibm_box_cells = int(box_cells or 0)       # 0: sized by the library
             d.body_motion = int(kind)
             for i, v in enumerate(params or ()):
                 d.motion_p[i] = float(v)

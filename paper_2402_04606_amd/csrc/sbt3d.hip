@@ -732,7 +732,7 @@ sbt_status check_desc(const sbt3_desc *d) {
   if (d->n_markers > 0 && (d->walls_z || d->solid_mask))
     return sbt_set_error(SBT_ERR_ARG, "an immersed body needs a fully periodic box without solid cells");
   if (d->n_markers > 0 && (d->ibm_box_cells < 64 || (d->body_motion != 0 && d->body_motion != 1)))
-    return sbt_set_error(SBT_ERR_ARG, "an immersed body needs ibm_box_cells >= 64 and motion 0 or 1");
+    return sbt_set_error(SBT_ERR_ARG, "an immersed body needs ibm_box_cells 0 or >= 64 and motion 0 or 1");
   if (d->n_markers > 0 && d->body_motion == 1 && (d->motion_p[6] == 0.0 || d->motion_p[9] == 0.0))
     return sbt_set_error(SBT_ERR_ARG, "motion period and chord must be nonzero");
   if (d->n_markers > 0) {
@@ -832,6 +832,36 @@ sbt_status solid_records(const sbt3_desc *d, std::vector<int32_t> *code, std::ve
   return SBT_OK;
 }
 
+// ibm_box_cells = 0 asks for the box of every cell the body's stencils can
+// reach over its motion: the markers' extent (for the pitch/plunge motion,
+// the disc their distance from the pivot sweeps in x and z, widened by the
+// plunge along z) plus the 4-cell stencil and a cell of margin on each
+// side, capped at the lattice.
+sbt3_desc with_box(sbt3_desc d) {
+  if (d.n_markers <= 0 || d.ibm_box_cells != 0 || !d.marker_xyz) return d;
+  const int n = d.n_markers;
+  double ext[3];
+  for (int a = 0; a < 3; ++a) {
+    double lo = 1e300, hi = -1e300;
+    for (int j = 0; j < n; ++j) {
+      lo = std::min(lo, d.marker_xyz[a * n + j]);
+      hi = std::max(hi, d.marker_xyz[a * n + j]);
+    }
+    ext[a] = hi - lo;
+  }
+  if (d.body_motion == 1) {
+    double r = 0.0;
+    for (int j = 0; j < n; ++j) r = std::max(r, std::hypot(d.marker_xyz[j], d.marker_xyz[2 * n + j]));
+    ext[0] = 2.0 * r;
+    ext[2] = 2.0 * r + std::fabs(d.motion_p[5]);
+  }
+  const long long all = (long long)d.nx * d.ny * d.nz;
+  long long cells = 1;
+  for (int a = 0; a < 3; ++a) cells *= std::isfinite(ext[a]) ? (long long)std::ceil(ext[a]) + 6 : all;
+  d.ibm_box_cells = std::max<long long>(64, std::min(cells, all));
+  return d;
+}
+
 size_t body_bytes(const sbt3_desc *d) {
   const size_t n = d->n_markers, cap = (size_t)d->ibm_box_cells;
   return 4 * align256(n * 8) + align256(3 * n * 4) + align256(12 * n * 8) + 3 * align256(3 * n * 8) +
@@ -916,7 +946,10 @@ sbt_status check_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, const void *a, cons
 
 extern "C" {
 
-sbt_status sbt3_plan(const sbt3_desc *desc, size_t *device_bytes) {
+sbt_status sbt3_plan(const sbt3_desc *desc_in, size_t *device_bytes) {
+  if (!desc_in) return sbt_set_error(SBT_ERR_ARG, "null descriptor");
+  const sbt3_desc dd = with_box(*desc_in);
+  const sbt3_desc *desc = &dd;
   sbt_status st = check_desc(desc);
   if (st) return st;
   if (!device_bytes) return sbt_set_error(SBT_ERR_ARG, "null output");
@@ -929,7 +962,11 @@ sbt_status sbt3_plan(const sbt3_desc *desc, size_t *device_bytes) {
   return SBT_OK;
 }
 
-sbt_status sbt3_create(const sbt3_desc *desc, void *device_buf, size_t bytes, void *hip_stream, sbt3_ctx **out) {
+sbt_status sbt3_create(const sbt3_desc *desc_in, void *device_buf, size_t bytes, void *hip_stream,
+                       sbt3_ctx **out) {
+  if (!desc_in) return sbt_set_error(SBT_ERR_ARG, "null descriptor");
+  const sbt3_desc dd = with_box(*desc_in);
+  const sbt3_desc *desc = &dd;
   sbt_status st = check_desc(desc);
   if (st) return st;
   if (!out) return sbt_set_error(SBT_ERR_ARG, "null output");
@@ -1135,6 +1172,11 @@ sbt_status sbt3_body_force(sbt3_ctx *ctx, double out[3]) {
   // the last launch ran the forcing loop of the step after the last completed one
   HIP3(hipMemcpyAsync(out, ctx->ibm.fs + 3, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIP3(hipStreamSynchronize(ctx->stream));
+  // a step whose stencils left the box ran without the body force: its F_s
+  // is not a result (the flag stays set for sbt3_synchronize)
+  int e = 0;
+  HIP3(hipMemcpy(&e, ctx->err, sizeof(int), hipMemcpyDeviceToHost));
+  if (e & 2) return sbt_set_error(SBT_ERR_MARKER_OUTSIDE, "the immersed body's stencils outgrew ibm_box_cells or left the box");
   return SBT_OK;
 }
 

@@ -246,7 +246,6 @@ struct Pool {
 };
 
 struct CaseHost {
-  int group = 0;
   sbt_case_desc d;
   std::vector<sbt_box> boxes;
   Forest F;
@@ -269,21 +268,13 @@ struct Phase {
 
 }  // namespace
 
-struct GroupInfo {
-  std::vector<int> cases;          // case indices of the group
-  int32_t *d_body_cases = nullptr; // cases of the group that carry a body
-  CaseDev *d_bodies = nullptr;     // their parameters, in the same order (one per forcing workgroup)
-  int n_bodies = 0;
-};
-
 struct sbt_ctx {
   int n_cases = 0, V = 1, storage = 0;
   int kvar = 0;  // level-launch variant: storage | (collision model << 2)
-  int G = 1;                       // case groups: independent launch chains
   std::vector<CaseHost> cs;
-  std::vector<Pool> pools;         // pool of group g, virtual level v at g * V + v
-  std::vector<GroupInfo> groups;
+  std::vector<Pool> pools;         // one pool per virtual level: the blocks of every case
   CaseDev *d_cases = nullptr;
+  CaseDev *d_bodies = nullptr;     // parameters of the cases with a body (one per forcing workgroup)
   int n_bodies = 0;
   int32_t *d_err = nullptr;
   double *d_stage = nullptr, *d_partial = nullptr, *d_diag = nullptr;
@@ -390,37 +381,16 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
   // one IBM plan buffer per finest substep of a step
   X.plan_bufs = 1 << (X.V - 1);
   const size_t s = storage_bytes(X.storage);
-  // One launch chain holds every case: each phase is one launch over the
-  // blocks of all cases (the group tables keep the case-to-chain map).
-  X.G = 1;
-  {
-    std::vector<std::pair<double, int>> work;
-    for (int c = 0; c < n_cases; ++c) {
-      const CaseHost &C = X.cs[c];
-      double w = 0;
-      for (int l = 0; l < C.F.m; ++l) w += (double)C.F.own[l].size() * (double)(1 << (l + X.V - C.F.m));
-      work.push_back({-w, c});
-    }
-    std::sort(work.begin(), work.end());
-    std::vector<double> load(X.G, 0.0);
-    for (auto &wc : work) {
-      int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      X.cs[wc.second].group = g;
-      load[g] -= wc.first;
-    }
-    X.groups.assign(X.G, GroupInfo());
-    for (int c = 0; c < n_cases; ++c) X.groups[X.cs[c].group].cases.push_back(c);
-  }
-  // Pools: per group and virtual level, own blocks of the group's cases,
-  // then their halo blocks.
-  X.pools.assign((size_t)X.G * X.V, Pool());
+  // Pools: one per virtual level, the own blocks of every case, then their
+  // halo blocks.  Each phase of a step is one launch over a pool.
+  X.pools.assign((size_t)X.V, Pool());
   for (int c = 0; c < n_cases; ++c) {
     CaseHost &C = X.cs[c];
     C.vshift = X.V - C.F.m;
     C.lr.assign(C.F.m, CaseLevelRange());
     for (int l = 0; l < C.F.m; ++l) {
       int v = l + C.vshift;
-      Pool &P = X.pools[(size_t)C.group * X.V + v];
+      Pool &P = X.pools[v];
       C.lr[l].v = v;
       C.lr[l].own0 = P.n_own;
       P.n_own += (int)C.F.own[l].size();
@@ -430,7 +400,7 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
   for (int c = 0; c < n_cases; ++c) {
     CaseHost &C = X.cs[c];
     for (int l = 0; l < C.F.m; ++l) {
-      Pool &P = X.pools[(size_t)C.group * X.V + C.lr[l].v];
+      Pool &P = X.pools[C.lr[l].v];
       C.lr[l].ghost0 = P.n_own + P.n_ghost;
       P.n_ghost += (int)C.F.ghost[l].size();
       C.lr[l].ghost1 = P.n_own + P.n_ghost;
@@ -491,10 +461,7 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
   X.d_diag = (double *)cv.take(sizeof(double) * 16);  // diagnostics [0, 4), force stats [4, 12), E [12, 16)
   X.d_err = (int32_t *)cv.take(sizeof(int32_t) * 4);
   X.d_cases = (CaseDev *)cv.take(sizeof(CaseDev) * n_cases);
-  for (auto &Gr : X.groups) {
-    Gr.d_body_cases = (int32_t *)cv.take(sizeof(int32_t) * n_cases);
-    Gr.d_bodies = (CaseDev *)cv.take(sizeof(CaseDev) * n_cases);
-  }
+  X.d_bodies = (CaseDev *)cv.take(sizeof(CaseDev) * n_cases);
   for (int c = 0; c < n_cases; ++c) {
     CaseHost &C = X.cs[c];
     CaseDev &D = C.dev;
@@ -555,7 +522,7 @@ void build_tables(sbt_ctx &X) {
       return map[l][(size_t)by * F.nbx[l] + bx];
     };
     for (int l = 0; l < F.m; ++l) {
-      Pool &P = X.pools[(size_t)C.group * X.V + C.lr[l].v];
+      Pool &P = X.pools[C.lr[l].v];
       for (int pass = 0; pass < 2; ++pass) {
         const std::vector<int> &ids = pass == 0 ? F.own[l] : F.ghost[l];
         int base = pass == 0 ? C.lr[l].own0 : C.lr[l].ghost0;
@@ -772,8 +739,8 @@ int blocks_per_wg(const sbt_ctx &X, int v, int n_fast) {
   return k;
 }
 
-sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s) {
-  Pool &P = X.pools[(size_t)g * X.V + v];
+sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
+  Pool &P = X.pools[v];
   LevelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.meta = P.d_meta;
@@ -783,7 +750,7 @@ sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s
   a.src = P.lat[P.cur];
   a.dst = P.lat[1 - P.cur];
   if (v + 1 < X.V) {
-    Pool &Q = X.pools[(size_t)g * X.V + v + 1];
+    Pool &Q = X.pools[v + 1];
     a.fmeta = Q.d_meta;
     a.fcodes = Q.d_codes;
     a.fprev = Q.lat[1 - Q.cur];
@@ -838,15 +805,14 @@ sbt_status launch_level(sbt_ctx &X, int g, int v, int p, int mode, hipStream_t s
   return SBT_OK;
 }
 
-sbt_status launch_mdf(sbt_ctx &X, int g, bool first, hipStream_t s) {
-  GroupInfo &Gr = X.groups[g];
-  if (Gr.n_bodies == 0) return SBT_OK;
-  Pool &P = X.pools[(size_t)g * X.V + X.V - 1];
+sbt_status launch_mdf(sbt_ctx &X, bool first, hipStream_t s) {
+  if (X.n_bodies == 0) return SBT_OK;
+  Pool &P = X.pools[X.V - 1];
   MdfArgs a;
   a.meta = P.d_meta;
   a.src = P.lat[P.cur];
   a.cases = X.d_cases;
-  a.bodies = Gr.d_bodies;
+  a.bodies = X.d_bodies;
   a.first = first ? 1 : 0;
   a.err = X.d_err;
   a.max_markers = X.max_body_markers;
@@ -859,7 +825,7 @@ sbt_status launch_mdf(sbt_ctx &X, int g, bool first, hipStream_t s) {
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, s));
   }
-  HIPCHK(sbt_launch_mdf(X.storage, &a, Gr.n_bodies, s));
+  HIPCHK(sbt_launch_mdf(X.storage, &a, X.n_bodies, s));
   if (X.profiling) {
     HIPCHK(hipEventRecord(e1, s));
     X.ev_mdf.push_back({e0, e1});
@@ -873,21 +839,20 @@ int forcing_phases(const sbt_ctx &X) {
   return n;
 }
 
-// Build the IBM plans of group g's bodies for the next n_plans finest
+// Build the IBM plans of every body for the next n_plans finest
 // substeps (those of kcount .. kcount + n_plans - 1), one workgroup per body
 // and substep.  The plan of substep k goes to buffer k & (plan_bufs - 1);
 // every earlier reader of those buffers precedes this launch in stream order.
-sbt_status launch_prep(sbt_ctx &X, int g, int n_plans, hipStream_t s) {
-  GroupInfo &Gr = X.groups[g];
-  if (Gr.n_bodies == 0) return SBT_OK;
+sbt_status launch_prep(sbt_ctx &X, int n_plans, hipStream_t s) {
+  if (X.n_bodies == 0) return SBT_OK;
   if (n_plans > X.plan_bufs) return fail(SBT_ERR_STATE, "more IBM plans than plan buffers");
   IbmArgs a;
   a.cases = X.d_cases;
-  a.bodies = Gr.d_bodies;
+  a.bodies = X.d_bodies;
   a.max_markers = X.max_body_markers;
   a.cell_cap = X.cell_cap;
   a.lds_window = X.lds_window;
-  a.n_bodies = Gr.n_bodies;
+  a.n_bodies = X.n_bodies;
   a.n_plans = n_plans;
   HIPCHK(sbt_launch_ibm_prep(&a, s));
   return SBT_OK;
@@ -898,35 +863,26 @@ sbt_status launch_prep(sbt_ctx &X, int g, int n_plans, hipStream_t s) {
 // level explodes into its finer level's current lattice.
 sbt_status run_prologue(sbt_ctx &X, hipStream_t s) {
   sbt_status st = SBT_OK;
-  for (int g = 0; g < X.G; ++g)
-    for (int v = X.V - 1; v >= 0; --v) {
-      if (v == X.V - 1) {
-        st = launch_prep(X, g, 1, s);
-        if (!st) st = launch_mdf(X, g, true, s);
-        if (st) return st;
-      }
-      st = launch_level(X, g, v, 1, MODE_LOCAL, s);
+  for (int v = X.V - 1; v >= 0; --v) {
+    if (v == X.V - 1) {
+      st = launch_prep(X, 1, s);
+      if (!st) st = launch_mdf(X, true, s);
       if (st) return st;
     }
+    st = launch_level(X, v, 1, MODE_LOCAL, s);
+    if (st) return st;
+  }
   X.post = true;
   return SBT_OK;
 }
 
-// One step of group g: the IBM plans of all its finest substeps (they depend
-// on the marker positions only), then the phases in order.
-sbt_status run_group_step(sbt_ctx &X, int g, hipStream_t s) {
-  sbt_status st = launch_prep(X, g, forcing_phases(X), s);
+// One step: the IBM plans of all its finest substeps (they depend on the
+// marker positions only), then the phases in order.
+sbt_status run_step_eager(sbt_ctx &X, hipStream_t s) {
+  sbt_status st = launch_prep(X, forcing_phases(X), s);
   if (st) return st;
   for (const Phase &ph : X.step_phases) {
-    st = ph.type == PH_MDF ? launch_mdf(X, g, false, s) : launch_level(X, g, ph.v, ph.p, 0, s);
-    if (st) return st;
-  }
-  return SBT_OK;
-}
-
-sbt_status run_step_eager(sbt_ctx &X, hipStream_t s) {
-  for (int g = 0; g < X.G; ++g) {
-    sbt_status st = run_group_step(X, g, s);
+    st = ph.type == PH_MDF ? launch_mdf(X, false, s) : launch_level(X, ph.v, ph.p, 0, s);
     if (st) return st;
   }
   return SBT_OK;
@@ -963,9 +919,8 @@ int graph_slot(const sbt_ctx &X, int si) {
 // The host-side state changes of `steps` graph-replayed steps.
 void advance_host(sbt_ctx &X, int steps) {
   for (int t = 0; t < steps; ++t) {
-    for (int g = 0; g < X.G; ++g)
-      for (const Phase &ph : X.step_phases)
-        if (ph.type == PH_LEVEL) X.pools[(size_t)g * X.V + ph.v].cur ^= 1;
+    for (const Phase &ph : X.step_phases)
+      if (ph.type == PH_LEVEL) X.pools[ph.v].cur ^= 1;
     if (X.n_bodies > 0) X.k_host += forcing_phases(X);
   }
 }
@@ -981,7 +936,7 @@ sbt_status capture_graph(sbt_ctx &X, int slot, int steps) {
   hipGraph_t g = nullptr;
   HIPCHK(hipStreamBeginCapture(X.cap_stream, hipStreamCaptureModeThreadLocal));
   for (int t = 0; t < steps && !st; ++t)
-    for (int k = 0; k < X.G && !st; ++k) st = run_group_step(X, k, X.cap_stream);
+    st = run_step_eager(X, X.cap_stream);
   hipError_t e = hipStreamEndCapture(X.cap_stream, &g);
   for (size_t i = 0; i < X.pools.size(); ++i) X.pools[i].cur = saved[i];
   X.k_host = saved_k;
@@ -1001,14 +956,14 @@ sbt_status capture_graph(sbt_ctx &X, int slot, int steps) {
 sbt_status capture_all(sbt_ctx &X) {
   for (int flip = 0; flip < 2; ++flip) {
     if (flip)
-      for (int g = 0; g < X.G; ++g) X.pools[(size_t)g * X.V].cur ^= 1;
+      X.pools[0].cur ^= 1;
     sbt_status st = SBT_OK;
     for (int si = 0; si < 3 && !st; ++si) {
       const int slot = graph_slot(X, si);
       if (!X.graph[slot]) st = capture_graph(X, slot, kGraphSteps[si]);
     }
     if (flip)
-      for (int g = 0; g < X.G; ++g) X.pools[(size_t)g * X.V].cur ^= 1;
+      X.pools[0].cur ^= 1;
     if (st) return st;
   }
   return SBT_OK;
@@ -1046,7 +1001,7 @@ void dense_to_blocks(const Forest &F, int l, const double *r, const double *u, c
 sbt_status readout_level(sbt_ctx &X, int c, int l, hipStream_t s) {
   CaseHost &C = X.cs[c];
   int v = C.lr[l].v;
-  Pool &P = X.pools[(size_t)C.group * X.V + v];
+  Pool &P = X.pools[v];
   LevelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.ibm_parity = -1;
@@ -1058,7 +1013,7 @@ sbt_status readout_level(sbt_ctx &X, int c, int l, hipStream_t s) {
   // after a step the state to read is the one the last launch streamed from
   a.src = X.post ? P.lat[1 - P.cur] : P.lat[P.cur];
   if (v + 1 < X.V) {
-    Pool &Q = X.pools[(size_t)C.group * X.V + v + 1];
+    Pool &Q = X.pools[v + 1];
     a.fmeta = Q.d_meta;
     a.fcodes = Q.d_codes;
     a.fprev = Q.lat[1 - Q.cur];
@@ -1281,7 +1236,7 @@ sbt_status sbt_init_fields(sbt_ctx *ctx, int32_t c, int32_t level, const double 
     size_t k1 = std::min(n, k0 + X.stage_blocks);
     HIPCHK(hipMemcpyAsync(X.d_stage, host.data() + k0 * 3 * kCells, sizeof(double) * 3 * kCells * (k1 - k0),
                           hipMemcpyHostToDevice, X.stream));
-    Pool &P = X.pools[(size_t)C.group * X.V + C.lr[level].v];
+    Pool &P = X.pools[C.lr[level].v];
     HIPCHK(sbt_launch_init(X.storage, P.d_meta, P.d_codes, X.d_cases, P.lat[0], C.lr[level].own0 + (int)k0,
                            (int)(k1 - k0), X.d_stage, nullptr, X.stream));
     HIPCHK(hipStreamSynchronize(X.stream));
@@ -1308,7 +1263,7 @@ sbt_status sbt_init_uniform(sbt_ctx *ctx, int32_t c, double rho, double ux, doub
   }
   double u0[3] = {rho, ux, uy};
   for (int l = 0; l < C.F.m; ++l) {
-    Pool &P = X.pools[(size_t)C.group * X.V + C.lr[l].v];
+    Pool &P = X.pools[C.lr[l].v];
     HIPCHK(sbt_launch_init(X.storage, P.d_meta, P.d_codes, X.d_cases, P.lat[0], C.lr[l].own0,
                            C.lr[l].own1 - C.lr[l].own0, nullptr, u0, X.stream));
   }
@@ -1367,20 +1322,12 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
   std::memcpy(C.dev.bp, body->p, sizeof(body->p));
   C.n_markers = body->n;
   HIPCHK(hipMemcpy(X.d_cases + c, &C.dev, sizeof(CaseDev), hipMemcpyHostToDevice));
-  X.n_bodies = 0;
-  for (auto &Gr : X.groups) {
-    std::vector<int32_t> bc;
-    for (int k : Gr.cases)
-      if (X.cs[k].has_body && X.cs[k].n_markers > 0) bc.push_back(k);
-    Gr.n_bodies = (int)bc.size();
-    X.n_bodies += Gr.n_bodies;
-    if (!bc.empty()) {
-      HIPCHK(hipMemcpy(Gr.d_body_cases, bc.data(), sizeof(int32_t) * bc.size(), hipMemcpyHostToDevice));
-      std::vector<CaseDev> bd;
-      for (int k : bc) bd.push_back(X.cs[k].dev);
-      HIPCHK(hipMemcpy(Gr.d_bodies, bd.data(), sizeof(CaseDev) * bd.size(), hipMemcpyHostToDevice));
-    }
-  }
+  // the bodies in case order, one forcing workgroup each
+  std::vector<CaseDev> bd;
+  for (const CaseHost &K : X.cs)
+    if (K.has_body && K.n_markers > 0) bd.push_back(K.dev);
+  X.n_bodies = (int)bd.size();
+  if (!bd.empty()) HIPCHK(hipMemcpy(X.d_bodies, bd.data(), sizeof(CaseDev) * bd.size(), hipMemcpyHostToDevice));
   destroy_graphs(X);
   return SBT_OK;
 }
@@ -1537,7 +1484,7 @@ sbt_status sbt_convergence(sbt_ctx *ctx, int32_t c, void *snapshot, size_t bytes
     const int n = C.lr[l].own1 - C.lr[l].own0;
     st = readout_level(X, c, l, X.stream);
     if (st) return st;
-    const Pool &P = X.pools[(size_t)C.group * X.V + C.lr[l].v];
+    const Pool &P = X.pools[C.lr[l].v];
     HIPCHK(sbt_launch_velocity_change(P.d_meta, P.d_codes, P.d_sbits, C.lr[l].own0, n, X.d_stage, snap, mode, X.d_partial,
                                       X.stream));
     if (mode & SBT_SNAP_COMPARE)
@@ -1807,7 +1754,7 @@ sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path) {
   sbt_ctx &X = *ctx;
   // cache key: storage and the block counts of every pool
   std::ostringstream key;
-  key << "st" << X.kvar << "_g" << X.G;
+  key << "st" << X.kvar;
   for (auto &P : X.pools) key << "_" << P.n_own << "/" << P.n_ghost;
   if (cache_path) {
     std::ifstream in(cache_path);
@@ -1843,7 +1790,7 @@ sbt_status sbt_autotune(sbt_ctx *ctx, int32_t steps, const char *cache_path) {
   std::vector<int> cur(X.V);
   for (int v = 0; v < X.V; ++v) {
     int nf = 0;
-    for (int g = 0; g < X.G; ++g) nf = std::max(nf, (int)X.pools[(size_t)g * X.V + v].fast.size());
+    nf = (int)X.pools[v].fast.size();
     X.kpw_level.assign(X.V, 0);
     cur[v] = blocks_per_wg(X, v, nf);
   }

@@ -79,12 +79,6 @@ class Workload:
         return dataclasses.replace(self, **kw)
 
 
-def level_tau(tau0, level):
-    """Input bookkeeping only: tau of a level under acoustic scaling, used to
-    derive tau0 from a target Reynolds number on the finest level."""
-    return 0.5 + (2 ** level) * (tau0 - 0.5)
-
-
 def _cell_centres(level, nx, ny):
     h = 1.0 / (2 ** level)
     x = (np.arange(nx) + 0.5) * h
