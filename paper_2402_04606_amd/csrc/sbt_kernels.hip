@@ -397,6 +397,7 @@ __device__ __forceinline__ typename Store<ST>::C feq_frame(const CaseDev &cp, in
                                                           typename Store<ST>::C rho,
                                                           typename Store<ST>::C ux,
                                                           typename Store<ST>::C uy) {
+#pragma clang fp contract(off)
   using C = typename Store<ST>::C;
   if constexpr (!Store<ST>::kShift) {
     return feq64(i, rho, ux, uy, ux * ux + uy * uy);

@@ -83,6 +83,13 @@ def compare_levels(g, o, wl, tol, c=0, exact=False, abs_u=0.0):
     return errs
 
 
+# Bodies in prescribed motion (2D): the poses use the device's sin and cos,
+# which may differ from the host library's by an ulp; the flow amplifies that
+# over hundreds of substeps, most in the body force (a sum of marker forces of
+# both signs).  Their histories are held to this bound (fields to TOL64).
+TOL_MOVING_HISTORY = 1e-10
+
+
 def compare_history(g, o, c=0, exact=False, tol=TOL64):
     """The F_s history (per finest substep): bit for bit, or within tol of
     its largest value."""
@@ -221,7 +228,7 @@ def test_moving_body_refined(env):
     wl = W.small_refined_flap()
     g, o = run_pair(env, wl, 8)
     compare_levels(g, o, wl, TOL64)
-    compare_history(g, o)
+    compare_history(g, o, tol=TOL_MOVING_HISTORY)
 
 
 @pytest.mark.parametrize("make,steps", [(W.small_pitch_up, 16), (W.small_pitching_airfoil, 30)])
@@ -232,7 +239,7 @@ def test_pitching_laws_refined(env, make, steps):
     wl = make()
     g, o = run_pair(env, wl, steps)
     compare_levels(g, o, wl, TOL64)
-    compare_history(g, o)
+    compare_history(g, o, tol=TOL_MOVING_HISTORY)
 
 
 def test_force_stats_and_convergence_on_device(env):
@@ -337,7 +344,7 @@ def test_mrt_refined_moving_body(env):
     wl = W.small_refined_flap().replace(collision=W.COLL_MRT)
     g, o = run_pair(env, wl, 8)
     compare_levels(g, o, wl, TOL64)
-    compare_history(g, o)
+    compare_history(g, o, tol=TOL_MOVING_HISTORY)
 
 
 def test_mrt_cavity_rescale(env):
@@ -384,7 +391,7 @@ def test_flapping_ellipse_four_levels(env):
     wl = W.flapping_ellipse()
     g, o = run_pair(env, wl, 50)
     compare_levels(g, o, wl, TOL64)
-    fxg, _ = compare_history(g, o)
+    fxg, _ = compare_history(g, o, tol=TOL_MOVING_HISTORY)
     assert len(fxg) == 400
 
 
@@ -557,7 +564,7 @@ def test_sweep_cases_match_oracle(env, sweep_f64):
         o.step(SWEEP_STEPS * 2 ** (V - wl.n_levels))
         print(f"sweep case {c} ({wl.nx0}x{wl.ny0}, {wl.n_levels} levels)", flush=True)
         compare_levels(g, o, wl, TOL64, c=c)
-        fg, _ = compare_history(g, o, c=c)
+        fg, _ = compare_history(g, o, c=c, tol=TOL_MOVING_HISTORY)
         assert len(fg) == SWEEP_STEPS * 2 ** (V - 1)
 
 
