@@ -191,6 +191,22 @@ sbt_status sbt_create(const sbt_case_desc *cases, int32_t n_cases, void *device_
                       void *hip_stream, sbt_ctx **out);
 sbt_status sbt_destroy(sbt_ctx *ctx);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, hosts that forbid hipMalloc): sbt_create
+ * with the context's device memory in the library's file-scope static
+ * device array of SBT_STATIC_BYTES per GPU (each GPU the library runs on
+ * holds its own copy until the process ends) instead of a caller buffer.
+ * The current device's array is used; the cases must plan to at most
+ * SBT_STATIC_BYTES (else SBT_ERR_NOMEM, nothing created).  One such context
+ * may live per device at a time: a call while another one is alive on the
+ * same device returns SBT_ERR_STATE; sbt_destroy frees the array for the
+ * next.  Calls that overlap on one device from several threads race for
+ * the array and must be serialised by the caller.  Everything else is
+ * sbt_create's: same kernels, same results, the same calls on the context
+ * afterwards.  Makes no device allocation (no hipMalloc or hipFree). */
+#define SBT_STATIC_BYTES ((size_t)128 << 20)
+sbt_status sbt_create_static(const sbt_case_desc *cases, int32_t n_cases, void *hip_stream, sbt_ctx **out);
+
 /* Blocks of a case's level that own at least one cell, Morton order; origins
  * in level cells.  ox/oy may be NULL (then only the count is returned). */
 sbt_status sbt_level_blocks(sbt_ctx *ctx, int32_t c, int32_t level, int32_t *n_blocks,

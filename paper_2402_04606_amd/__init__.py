@@ -25,7 +25,7 @@ ERRORS = {-1: "ARG", -2: "TOPOLOGY", -3: "DEVICE", -4: "NOMEM", -5: "STATE", -6:
 
 # Every function include/sbt.h declares.
 ABI_SYMBOLS = [
-    "sbt_plan", "sbt_create", "sbt_destroy", "sbt_level_blocks", "sbt_level_info", "sbt_init_fields",
+    "sbt_plan", "sbt_create", "sbt_create_static", "sbt_destroy", "sbt_level_blocks", "sbt_level_info", "sbt_init_fields",
     "sbt_init_uniform", "sbt_set_body", "sbt_set_markers", "sbt_step", "sbt_synchronize", "sbt_read_fields",
     "sbt_read_fields_blocks", "sbt_read_marker_forces",
     "sbt_read_force_history", "sbt_diagnostics", "sbt_force_stats", "sbt_snapshot_bytes",
@@ -95,6 +95,7 @@ def lib():
         sig = {
             "sbt_plan": [C.POINTER(CaseDesc), i32, C.POINTER(C.c_size_t)],
             "sbt_create": [C.POINTER(CaseDesc), i32, vp, C.c_size_t, vp, C.POINTER(vp)],
+            "sbt_create_static": [C.POINTER(CaseDesc), i32, vp, C.POINTER(vp)],
             "sbt_destroy": [vp],
             "sbt_level_blocks": [vp, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
             "sbt_level_info": [vp, i32, i32, C.POINTER(i64)],
@@ -210,9 +211,12 @@ class Sim:
     """One context on cuda:0 holding one or more cases (a batch).
 
     Device memory is a torch uint8 buffer; the stream is torch's current
-    stream unless one is given."""
+    stream unless one is given.  static_memory=True creates the context
+    with sbt_create_static instead: its memory is the library's static
+    device array and no buffer is allocated here."""
 
-    def __init__(self, workloads, storage="f64", stream=None, history_cap=1 << 16, init=True):
+    def __init__(self, workloads, storage="f64", stream=None, history_cap=1 << 16, init=True,
+                 static_memory=False):
         import torch
         if not isinstance(workloads, (list, tuple)):
             workloads = [workloads]
@@ -223,13 +227,18 @@ class Sim:
         n = C.c_size_t()
         _check(L.sbt_plan(self._descs, len(self.workloads), C.byref(n)))
         self.device_bytes = n.value
-        self._buf = torch.empty(self.device_bytes + 256, dtype=torch.uint8, device="cuda")
-        ptr = self._buf.data_ptr()
-        ptr = (ptr + 255) // 256 * 256
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         h = C.c_void_p()
-        _check(L.sbt_create(self._descs, len(self.workloads), C.c_void_p(ptr), self.device_bytes,
-                            C.c_void_p(self._stream.cuda_stream), C.byref(h)))
+        if static_memory:
+            self._buf = None
+            _check(L.sbt_create_static(self._descs, len(self.workloads), C.c_void_p(self._stream.cuda_stream),
+                                       C.byref(h)))
+        else:
+            self._buf = torch.empty(self.device_bytes + 256, dtype=torch.uint8, device="cuda")
+            ptr = self._buf.data_ptr()
+            ptr = (ptr + 255) // 256 * 256
+            _check(L.sbt_create(self._descs, len(self.workloads), C.c_void_p(ptr), self.device_bytes,
+                                C.c_void_p(self._stream.cuda_stream), C.byref(h)))
         self._h = h
         if init:
             for c, wl in enumerate(self.workloads):

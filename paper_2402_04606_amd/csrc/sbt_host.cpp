@@ -295,6 +295,7 @@ struct sbt_ctx {
   hipEvent_t step_event = nullptr;
   bool graph_dirty = true;
   size_t bytes_used = 0;
+  int static_dev = -1;             // device whose static array holds the memory (sbt_create_static), or -1
   // profiling
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_level, ev_fast, ev_mdf;
@@ -1074,6 +1075,11 @@ sbt_status sbt_plan(const sbt_case_desc *cases, int32_t n_cases, size_t *device_
 
 sbt_status sbt_create(const sbt_case_desc *cases, int32_t n_cases, void *device_buf, size_t bytes,
                       void *hip_stream, sbt_ctx **out) {
+  return sbt_create_in(cases, n_cases, device_buf, bytes, hip_stream, -1, out);
+}
+
+sbt_status sbt_create_in(const sbt_case_desc *cases, int32_t n_cases, void *device_buf, size_t bytes,
+                         void *hip_stream, int32_t static_dev, sbt_ctx **out) {
   if (!out) return fail(SBT_ERR_ARG, "null output");
   *out = nullptr;
   if (!device_buf) return fail(SBT_ERR_ARG, "null device buffer");
@@ -1092,6 +1098,7 @@ sbt_status sbt_create(const sbt_case_desc *cases, int32_t n_cases, void *device_
   }
   X->bytes_used = cv.off;
   X->stream = (hipStream_t)hip_stream;
+  X->static_dev = static_dev;
   auto cleanup_fail = [&](sbt_status s) {
     delete X;
     return s;
@@ -1159,7 +1166,9 @@ sbt_status sbt_destroy(sbt_ctx *ctx) {
   destroy_graphs(*ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->step_event) (void)hipEventDestroy(ctx->step_event);
+  const int dev = ctx->static_dev;
   delete ctx;
+  if (dev >= 0) sbt_static_release(dev);
   return SBT_OK;
 }
 

@@ -156,6 +156,12 @@ enum : int32_t { ERR_NONFINITE = 1, ERR_MARKER = 2, ERR_CONTRIB = 4, ERR_WINDOW 
 
 // Launchers implemented in sbt_kernels.hip.
 extern "C" {
+// sbt_create on a given device region; static_dev >= 0 marks a context whose
+// region is that device's static array (sbt_destroy releases it).
+sbt_status sbt_create_in(const sbt_case_desc *cases, int32_t n_cases, void *device_buf, size_t bytes,
+                         void *hip_stream, int32_t static_dev, sbt_ctx **out);
+// Mark the static array of device dev free again (sbt_static.hip).
+void sbt_static_release(int dev);
 // Message for sbt_last_error (the thread's last failure); returns code.
 sbt_status sbt_set_error(sbt_status code, const char *msg);
 // Generic level kernel: any block (interfaces, domain edges, readout,
