@@ -247,7 +247,16 @@ def main():
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}))
+        # the practical copy bandwidth of this GPU, for context
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        gbs = 10 * 2 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 13,
+                          "copy_gbs": round(gbs, 1), "copy_frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}))
         return
 
     import paper_2402_04606_amd as P

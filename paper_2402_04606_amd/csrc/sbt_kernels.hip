@@ -374,17 +374,27 @@ struct Collide : PickT<(ST & 4) != 0, CollideMRT<ST & 3>, CollideBGK<ST & 3>>::t
 // window).  `parity` is that substep's plan buffer (negative: derived from
 // the forcing-loop counter).  The window test is per block, on wave-uniform
 // values.
+// The window and the plan counter are written by other launches, never by
+// the kernels that read them here, so they are read through the constant
+// address space (scalar loads); the force density through the global one.
+// Generic (flat) loads would make the compiler wait for every outstanding
+// direct-to-LDS copy first, since a flat access may alias LDS.
+typedef __attribute__((address_space(4))) const int32_t ci32_t;
+typedef __attribute__((address_space(4))) const int64_t ci64_t;
+typedef __attribute__((address_space(1))) const double gdbl_t;
+
 template <typename C>
 __device__ __forceinline__ void add_ibm_force(const CaseDev &cp, int parity, int ox, int oy, int x, int y, C &Fx,
                                               C &Fy) {
-  const int b = parity >= 0 ? parity : __builtin_amdgcn_readfirstlane((int)((*cp.kcount - 1) & cp.plan_mask));
-  const IbmWindow w = cp.win[b];
-  const int x0 = __builtin_amdgcn_readfirstlane(w.x0), y0 = __builtin_amdgcn_readfirstlane(w.y0);
-  const int ww = __builtin_amdgcn_readfirstlane(w.w), wh = __builtin_amdgcn_readfirstlane(w.h);
+  const int b = parity >= 0 ? parity
+                            : __builtin_amdgcn_readfirstlane((int)((*(ci64_t *)cp.kcount - 1) & cp.plan_mask));
+  ci32_t *w = (ci32_t *)cp.win + 4 * b;   // IbmWindow {x0, y0, w, h}
+  const int x0 = __builtin_amdgcn_readfirstlane(w[0]), y0 = __builtin_amdgcn_readfirstlane(w[1]);
+  const int ww = __builtin_amdgcn_readfirstlane(w[2]), wh = __builtin_amdgcn_readfirstlane(w[3]);
   if (ox + kB <= x0 || ox >= x0 + ww || oy + kB <= y0 || oy >= y0 + wh) return;
   const int wx = ox + x - x0, wy = oy + y - y0;
   if (wx >= 0 && wx < ww && wy >= 0 && wy < wh) {
-    const double *F = cp.wF + (size_t)b * 2 * cp.win_cap;
+    gdbl_t *F = (gdbl_t *)cp.wF + (size_t)b * 2 * cp.win_cap;
     const size_t wi = (size_t)wy * ww + wx;
     Fx = Fx + (C)F[wi];
     Fy = Fy + (C)F[(size_t)cp.win_cap + wi];
@@ -983,22 +993,23 @@ __device__ __forceinline__ void fetch_tile(const LevelArgs &a, const Blk &k, typ
 // Make buf complete for every lane: this lane's halo value (8-byte
 // storage), then wait for this wave's direct copies before the barrier
 // (other waves read them).  Vector memory operations complete in issue
-// order, so when at least 9 were issued after this buffer's copies (the
-// previous block's stores), vmcnt(9) covers the copies without waiting
-// for those stores.  The barrier then carries no memory fence: a fence
+// order, so when at least `after` were issued after this buffer's copies
+// (later blocks' copies, earlier blocks' 9 stores), vmcnt(after) covers the
+// copies without waiting for those.  The barrier then carries no memory fence: a fence
 // would wait for the stores too.  Only LDS is shared across it, and every
 // LDS access before it has completed (the copies by the wait, the reads
 // because their values were used); the empty asm statements keep the
 // compiler from moving memory accesses across it.
 template <int ST>
-__device__ __forceinline__ void commit_tile(typename Store<ST>::T *buf, typename Store<ST>::T h, bool after9 = false) {
+__device__ __forceinline__ void commit_tile(typename Store<ST>::T *buf, typename Store<ST>::T h, int after = 0) {
   if constexpr (!Tile<ST>::kDmaHalo) {
     if (threadIdx.x < 188) buf[Tile<ST>::DENSE + threadIdx.x] = h;
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
   } else {
-    if (after9) __builtin_amdgcn_s_waitcnt(0x0F79);  // vmcnt(9)
-    else __builtin_amdgcn_s_waitcnt(0x0F70);         // vmcnt(0)
+    // vmcnt(n) with lgkmcnt and expcnt left at their maxima
+    if (after >= 9) __builtin_amdgcn_s_waitcnt(0x0F79);        // vmcnt(9)
+    else __builtin_amdgcn_s_waitcnt(0x0F70);                   // vmcnt(0)
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
@@ -1009,7 +1020,8 @@ __device__ __forceinline__ void commit_tile(typename Store<ST>::T *buf, typename
 // explosion work only when SLOW.
 template <int ST, bool SLOW>
 __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev *__restrict__ cases, const Blk &k,
-                                              const typename Store<ST>::T *tile, uint16_t code_in = 0) {
+                                              const typename Store<ST>::T *tile, double ibm_fx, double ibm_fy,
+                                              uint16_t code_in = 0) {
 #pragma clang fp contract(off)
   using S = Store<ST>;
   using T = typename S::T;
@@ -1078,7 +1090,10 @@ __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev 
     Fx = cp.fx_f[l];
     Fy = cp.fy_f[l];
   }
-  if (k.flags & BF_IBM) add_ibm_force<C>(cp, a.ibm_parity, k.ox, k.oy, x, y, Fx, Fy);
+  if (k.flags & BF_IBM) {
+    Fx = Fx + (C)ibm_fx;
+    Fy = Fy + (C)ibm_fy;
+  }
   C rho, ux, uy;
   Collide<ST>::run(cp, l, f, Fx, Fy, rho, ux, uy);
   if (!(rho == rho) || rho > C(1e30) || rho < C(-1e30)) atomicOr(a.err, ERR_NONFINITE);
@@ -1112,12 +1127,44 @@ __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev 
   }
 }
 
+// IBM force density of this lane's cell of block k for the collision of
+// this substep (zero outside the body's window, and for blocks of levels
+// without a body).  Its loads are issued where the caller puts this call:
+// before a block's tile copies, so that waiting for them never waits for
+// the copies.
+// The window and counter reads are scalar, so a block outside the window
+// issues no vector load; the few blocks inside it load their cells' values
+// before the next block's copies are issued.
+template <int ST>
+__device__ __forceinline__ void ibm_force_of(const LevelArgs &a, const CaseDev *__restrict__ cases, const Blk &k,
+                                             double &fx, double &fy) {
+  fx = 0.0;
+  fy = 0.0;
+  if (k.flags & BF_IBM) {
+    const CaseDev &cp = cases[__builtin_amdgcn_readfirstlane(k.cid)];
+    const int b = a.ibm_parity >= 0
+                      ? a.ibm_parity
+                      : __builtin_amdgcn_readfirstlane((int)((*(ci64_t *)cp.kcount - 1) & cp.plan_mask));
+    ci32_t *w = (ci32_t *)cp.win + 4 * b;   // IbmWindow {x0, y0, w, h}
+    const int x0 = __builtin_amdgcn_readfirstlane(w[0]), y0 = __builtin_amdgcn_readfirstlane(w[1]);
+    const int ww = __builtin_amdgcn_readfirstlane(w[2]), wh = __builtin_amdgcn_readfirstlane(w[3]);
+    if (k.ox + kB <= x0 || k.ox >= x0 + ww || k.oy + kB <= y0 || k.oy >= y0 + wh) return;
+    const int wx = k.ox + (int)(threadIdx.x & 15) - x0, wy = k.oy + (int)(threadIdx.x >> 4) - y0;
+    if (wx >= 0 && wx < ww && wy >= 0 && wy < wh) {
+      gdbl_t *F = (gdbl_t *)cp.wF + (size_t)b * 2 * cp.win_cap + (size_t)wy * ww + wx;
+      fx = F[0];
+      fy = F[cp.win_cap];
+    }
+  }
+}
+
+
 // One pipelined step over a run of interior blocks: make `cur` (block j)
-// complete, start block j+1's copies into `nxt`, stream + collide block j
-// from `cur`, then issue the scalar load of block j+2's metadata (used
-// after the next barrier).  No vector load whose value the step needs is
-// issued after the copies, so nothing waits for them before the barrier of
-// the next step.
+// complete, issue the loads of block j's IBM force, start block j+1's copies
+// into `nxt`, stream + collide block j from `cur`, then issue the scalar
+// load of block j+2's metadata (used after the next barrier).  No vector
+// load whose value the step needs is issued after the copies, so nothing
+// waits for them before the barrier of the next step.
 template <int ST>
 __device__ __forceinline__ void pipe_step(const LevelArgs &a, const CaseDev *__restrict__ cases,
                                           const BlockMeta *__restrict__ meta, Blk &kc, Blk &kn, int lv, int j, int cnt,
@@ -1125,9 +1172,11 @@ __device__ __forceinline__ void pipe_step(const LevelArgs &a, const CaseDev *__r
                                           typename Store<ST>::T &h, uint32_t he) {
   // after the first block, the previous block's 9 stores were issued after
   // this buffer's copies
-  commit_tile<ST>(cur, h, j > 0);
+  commit_tile<ST>(cur, h, j > 0 ? 9 : 0);
+  double fx, fy;
+  ibm_force_of<ST>(a, cases, kc, fx, fy);
   if (j + 1 < cnt) fetch_tile<ST>(a, kn, nxt, h, he);
-  compute_block<ST, false>(a, cases, kc, cur);
+  compute_block<ST, false>(a, cases, kc, cur, fx, fy);
   kc = kn;
   if (j + 2 < cnt) kn = load_blk(meta, __builtin_amdgcn_readlane(lv, j + 2));
 }
@@ -1162,9 +1211,11 @@ __global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a, const Case
     const int cnt = min(kpw, a.n_fast - first);
     if (NBUF == 1 || cnt == 1) {
       const Blk k = load_blk(meta, list[first]);
+      double fx, fy;
+      ibm_force_of<ST>(a, cases, k, fx, fy);
       fetch_tile<ST>(a, k, bufA, h, he);
       commit_tile<ST>(bufA, h);
-      compute_block<ST, false>(a, cases, k, bufA);
+      compute_block<ST, false>(a, cases, k, bufA, fx, fy);
       return;
     }
     // the run's block ids (one per lane) and the first two blocks' metadata
@@ -1181,10 +1232,12 @@ __global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a, const Case
   }
   if (role == 1) {
     const Blk k = load_blk(meta, list[a.n_fast + w]);
+    double fx, fy;
+    ibm_force_of<ST>(a, cases, k, fx, fy);
     fetch_tile<ST>(a, k, bufA, h, he);
     const uint16_t code = (k.flags & BF_CODES) ? a.codes[(size_t)k.code * kCells + threadIdx.x] : (uint16_t)0;
     commit_tile<ST>(bufA, h);
-    compute_block<ST, true>(a, cases, k, bufA, code);
+    compute_block<ST, true>(a, cases, k, bufA, fx, fy, code);
   } else if (role == 2) {
     int idx = w * 256 + threadIdx.x;
     if (idx < a.n_band) band_cell<ST>(a, a.band[idx]);
