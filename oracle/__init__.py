@@ -114,6 +114,15 @@ def _configure(L):
     L.orc3_set_body.argtypes = [C.c_void_p, C.c_int32, d, d, d, d, C.c_int32]
     L.orc3_body_force.argtypes = [C.c_void_p, d]
     L.orc3_set_motion.argtypes = [C.c_void_p, C.c_int32, d]
+    L.orc3f_create.argtypes = [C.POINTER(_Case3F), C.POINTER(C.c_void_p)]
+    L.orc3f_destroy.argtypes = [C.c_void_p]
+    L.orc3f_destroy.restype = None
+    L.orc3f_level_size.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int32)]
+    L.orc3f_level_kinds.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_uint8)]
+    L.orc3f_init_fields.argtypes = [C.c_void_p, C.c_int, d, d, d, d]
+    L.orc3f_step.argtypes = [C.c_void_p, C.c_int32]
+    L.orc3f_read_fields.argtypes = [C.c_void_p, C.c_int, d, d, d, d]
+    L.orc3f_diagnostics.argtypes = [C.c_void_p, d]
     L.orc_num_threads.argtypes = []
     L.orc3_marker_positions.argtypes = [C.c_void_p, C.c_double, d, d, d]
     return L
@@ -423,6 +432,84 @@ def feq3(rho, ux, uy, uz, q=19):
     out = np.zeros(q)
     lib().orc3_feq(q, float(rho), float(ux), float(uy), float(uz), _dp(out))
     return out
+
+
+class _Case3F(C.Structure):
+    _fields_ = [
+        ("nx0", C.c_int32), ("ny0", C.c_int32), ("nz0", C.c_int32), ("block_n", C.c_int32),
+        ("n_levels", C.c_int32), ("q", C.c_int32), ("n_boxes", C.c_int32), ("boxes", C.POINTER(C.c_int32)),
+        ("tau0", C.c_double), ("rho0", C.c_double), ("fext", C.c_double * 3), ("cf_mode", C.c_int32),
+    ]
+
+
+class Oracle3FSim:
+    """A periodic 3D block forest (a ``workloads.Workload3F``); fields are dense
+    per-level arrays [nz, ny, nx], NaN where the level owns no cell."""
+
+    def __init__(self, wl, so=None):
+        self.wl = wl
+        self._L = so if so is not None else lib()
+        c = _Case3F()
+        c.nx0, c.ny0, c.nz0, c.block_n = wl.nx0, wl.ny0, wl.nz0, wl.block_n
+        c.n_levels, c.q = wl.n_levels, wl.lattice
+        self._boxes = np.ascontiguousarray(np.array(wl.boxes, dtype=np.int32).reshape(-1, 7))
+        c.n_boxes = self._boxes.shape[0]
+        c.boxes = self._boxes.ctypes.data_as(C.POINTER(C.c_int32))
+        c.tau0, c.rho0 = wl.tau0, wl.rho0
+        for k in range(3):
+            c.fext[k] = wl.fext[k]
+        c.cf_mode = wl.cf_mode
+        self._case = c
+        h = C.c_void_p()
+        rc = self._L.orc3f_create(C.byref(c), C.byref(h))
+        if rc:
+            raise RuntimeError(f"orc3f_create failed: {rc}")
+        self._h = h
+        self.n_levels = wl.n_levels
+        if wl.init is not None:
+            for l in range(wl.n_levels):
+                self.init_fields(l, *wl.init(l, *self.level_size(l)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None:
+            self._L.orc3f_destroy(h)
+            self._h = None
+
+    def level_size(self, l):
+        out = (C.c_int32 * 3)()
+        self._L.orc3f_level_size(self._h, l, out)
+        return out[0], out[1], out[2]
+
+    def kinds(self, l):
+        nx, ny, nz = self.level_size(l)
+        k = np.zeros((nz, ny, nx), dtype=np.uint8)
+        self._L.orc3f_level_kinds(self._h, l, k.ctypes.data_as(C.POINTER(C.c_uint8)))
+        return k
+
+    def init_fields(self, l, rho, ux, uy, uz):
+        nx, ny, nz = self.level_size(l)
+        a = [_f64(np.broadcast_to(v, (nz, ny, nx))) for v in (rho, ux, uy, uz)]
+        rc = self._L.orc3f_init_fields(self._h, l, *[_dp(v) for v in a])
+        if rc:
+            raise RuntimeError(rc)
+
+    def step(self, n=1):
+        rc = self._L.orc3f_step(self._h, int(n))
+        if rc:
+            raise RuntimeError(f"orc3f_step failed: {rc}")
+
+    def fields(self, l):
+        nx, ny, nz = self.level_size(l)
+        out = [np.empty((nz, ny, nx)) for _ in range(4)]
+        self._L.orc3f_read_fields(self._h, l, *[_dp(v) for v in out])
+        return out
+
+    def diagnostics(self):
+        """(mass, momentum x, y, z) over owned cells, each level weighted by 8^-l."""
+        out = np.zeros(4)
+        self._L.orc3f_diagnostics(self._h, _dp(out))
+        return out
 
 
 class Oracle3Sim:

@@ -1577,3 +1577,385 @@ int orc3_read_fields(const orc3_sim *s, double *rho, double *ux, double *uy, dou
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Three dimensions on a block forest: the topology-confined refinement of  */
+/* Sec. 2.3 and the coarse-fine interface of Sec. 2.4 in 3D (D3Q19 or       */
+/* D3Q27), periodic in every direction                                       */
+/* ------------------------------------------------------------------------ */
+
+/* The same construction as in 2D, one dimension up: level l is a dense grid
+ * of (nx0, ny0, nz0) 2^l cells; region_l is the union of the level's boxes
+ * (level 0: everything); own_l = region_l minus the cells covered by
+ * region_{l+1} (hidden); the halo of level l >= 1 is every cell outside
+ * region_l within Chebyshev distance 2 of own_l, whose parent must be owned
+ * on level l-1.  A coarse cell's 8 children are (2x + a, 2y + b, 2z + c),
+ * a, b, c in {0, 1}. */
+typedef struct {
+    int nx, ny, nz;
+    double tau, F[3];
+    uint8_t *kind;
+    double *f, *fs;           /* [cell][q] pre- / post-collision, cell = (z ny + y) nx + x */
+    double *rho, *u;          /* moments of the last collision: rho [cell], u [cell][3] */
+    int64_t *own, *ghost, *act;
+    int64_t n_own, n_ghost, n_act;
+} o3lev;
+
+struct orc3f_sim {
+    orc3f_case c;
+    int32_t *boxes;
+    int m, q;
+    o3lev L[MAXL];
+};
+
+static inline size_t c3(const o3lev *L, int x, int y, int z) { return ((size_t)z * L->ny + y) * L->nx + x; }
+
+static void wrap3(const o3lev *L, int *x, int *y, int *z) {
+    *x = wrapi(*x, L->nx);
+    *y = wrapi(*y, L->ny);
+    *z = wrapi(*z, L->nz);
+}
+
+static int in_region3(const orc3f_sim *s, int l, int x, int y, int z) {
+    if (l == 0) return 1;
+    const int B = s->c.block_n;
+    for (int b = 0; b < s->c.n_boxes; ++b) {
+        const int32_t *q = s->boxes + 7 * b;
+        if (q[0] != l) continue;
+        if (x >= q[1] * B && x < q[4] * B && y >= q[2] * B && y < q[5] * B && z >= q[3] * B && z < q[6] * B) return 1;
+    }
+    return 0;
+}
+
+void orc3f_destroy(orc3f_sim *s) {
+    if (!s) return;
+    for (int l = 0; l < MAXL; ++l) {
+        o3lev *L = &s->L[l];
+        free(L->kind); free(L->f); free(L->fs); free(L->rho); free(L->u);
+        free(L->own); free(L->ghost); free(L->act);
+    }
+    free(s->boxes);
+    free(s);
+}
+
+static int topology3(orc3f_sim *s) {
+    const int m = s->m;
+    for (int l = 0; l < m; ++l) {
+        o3lev *L = &s->L[l];
+        for (int z = 0; z < L->nz; ++z)
+            for (int y = 0; y < L->ny; ++y)
+                for (int x = 0; x < L->nx; ++x) {
+                    uint8_t kd = K_NONE;
+                    if (in_region3(s, l, x, y, z)) {
+                        kd = K_OWN;
+                        if (l + 1 < m && in_region3(s, l + 1, 2 * x, 2 * y, 2 * z)) kd = K_HIDDEN;
+                        if (l > 0 && !in_region3(s, l - 1, x / 2, y / 2, z / 2)) return ORC_ERR_TOPOLOGY;
+                    }
+                    L->kind[c3(L, x, y, z)] = kd;
+                }
+    }
+    for (int l = 1; l < m; ++l) {
+        o3lev *L = &s->L[l], *P = &s->L[l - 1];
+        const size_t n = (size_t)L->nx * L->ny * L->nz;
+        uint8_t *mark = calloc(n, 1);
+        for (int z = 0; z < L->nz; ++z)
+            for (int y = 0; y < L->ny; ++y)
+                for (int x = 0; x < L->nx; ++x) {
+                    if (L->kind[c3(L, x, y, z)] != K_OWN) continue;
+                    for (int dz = -2; dz <= 2; ++dz)
+                        for (int dy = -2; dy <= 2; ++dy)
+                            for (int dx = -2; dx <= 2; ++dx) {
+                                int xx = x + dx, yy = y + dy, zz = z + dz;
+                                wrap3(L, &xx, &yy, &zz);
+                                if (L->kind[c3(L, xx, yy, zz)] == K_NONE) mark[c3(L, xx, yy, zz)] = 1;
+                            }
+                }
+        for (int z = 0; z < L->nz; ++z)
+            for (int y = 0; y < L->ny; ++y)
+                for (int x = 0; x < L->nx; ++x) {
+                    if (!mark[c3(L, x, y, z)]) continue;
+                    if (P->kind[c3(P, x / 2, y / 2, z / 2)] != K_OWN) { free(mark); return ORC_ERR_TOPOLOGY; }
+                    L->kind[c3(L, x, y, z)] = K_GHOST;
+                }
+        free(mark);
+    }
+    for (int l = 0; l < m; ++l) {
+        o3lev *L = &s->L[l];
+        const size_t n = (size_t)L->nx * L->ny * L->nz;
+        int64_t no = 0, ng = 0;
+        for (size_t q = 0; q < n; ++q) { no += L->kind[q] == K_OWN; ng += L->kind[q] == K_GHOST; }
+        L->own = malloc(sizeof(int64_t) * (no + 1));
+        L->ghost = malloc(sizeof(int64_t) * (ng + 1));
+        L->act = malloc(sizeof(int64_t) * (no + ng + 1));
+        for (size_t q = 0; q < n; ++q) {
+            if (L->kind[q] == K_OWN) L->own[L->n_own++] = (int64_t)q;
+            if (L->kind[q] == K_GHOST) L->ghost[L->n_ghost++] = (int64_t)q;
+            if (L->kind[q] == K_OWN || L->kind[q] == K_GHOST) L->act[L->n_act++] = (int64_t)q;
+        }
+    }
+    return ORC_OK;
+}
+
+int orc3f_create(const orc3f_case *c, orc3f_sim **out) {
+    *out = NULL;
+    if (c->n_levels < 1 || c->n_levels > MAXL || c->nx0 <= 0 || c->ny0 <= 0 || c->nz0 <= 0 || c->block_n <= 0 ||
+        c->tau0 <= 0.5 || (c->q != 19 && c->q != 27) || c->n_boxes < 0 || (c->n_boxes > 0 && !c->boxes))
+        return ORC_ERR_ARG;
+    orc3f_sim *s = calloc(1, sizeof(orc3f_sim));
+    s->c = *c;
+    s->m = c->n_levels;
+    s->q = c->q;
+    s->boxes = malloc(sizeof(int32_t) * 7 * (c->n_boxes > 0 ? c->n_boxes : 1));
+    if (c->n_boxes > 0) memcpy(s->boxes, c->boxes, sizeof(int32_t) * 7 * c->n_boxes);
+    s->c.boxes = s->boxes;
+    for (int l = 0; l < s->m; ++l) {
+        o3lev *L = &s->L[l];
+        L->nx = c->nx0 << l;
+        L->ny = c->ny0 << l;
+        L->nz = c->nz0 << l;
+        L->tau = 0.5 + (double)(1 << l) * (c->tau0 - 0.5);
+        for (int k = 0; k < 3; ++k) L->F[k] = c->fext[k] / (double)(1 << l);
+        const size_t n = (size_t)L->nx * L->ny * L->nz;
+        L->kind = calloc(n, 1);
+        L->f = malloc(sizeof(double) * n * s->q);
+        L->fs = malloc(sizeof(double) * n * s->q);
+        L->rho = malloc(sizeof(double) * n);
+        L->u = malloc(sizeof(double) * n * 3);
+        if (!L->kind || !L->f || !L->fs || !L->rho || !L->u) { orc3f_destroy(s); return ORC_ERR_ARG; }
+        for (size_t q = 0; q < n * s->q; ++q) L->f[q] = L->fs[q] = NAN;
+        for (size_t q = 0; q < n; ++q) L->rho[q] = NAN;
+        for (size_t q = 0; q < 3 * n; ++q) L->u[q] = NAN;
+    }
+    int rc = topology3(s);
+    if (rc) { orc3f_destroy(s); return rc; }
+    if (c->cf_mode == ORC_CF_RESCALE)
+        for (int l = 0; l + 1 < s->m; ++l)
+            if (fabs(s->L[l].tau - 1.0) < 1e-6) { orc3f_destroy(s); return ORC_ERR_ARG; }
+    for (int l = 0; l < s->m; ++l) {      /* rest at rho0 */
+        o3lev *L = &s->L[l];
+        double feq[27];
+        orc3_feq(s->q, c->rho0, 0.0, 0.0, 0.0, feq);
+        for (int64_t k = 0; k < L->n_own; ++k) memcpy(L->f + (size_t)L->own[k] * s->q, feq, sizeof(double) * s->q);
+    }
+    *out = s;
+    return ORC_OK;
+}
+
+int orc3f_level_size(const orc3f_sim *s, int level, int32_t out[3]) {
+    if (level < 0 || level >= s->m) return ORC_ERR_ARG;
+    out[0] = s->L[level].nx; out[1] = s->L[level].ny; out[2] = s->L[level].nz;
+    return ORC_OK;
+}
+
+int orc3f_level_kinds(const orc3f_sim *s, int level, uint8_t *kind) {
+    if (level < 0 || level >= s->m) return ORC_ERR_ARG;
+    const o3lev *L = &s->L[level];
+    memcpy(kind, L->kind, (size_t)L->nx * L->ny * L->nz);
+    return ORC_OK;
+}
+
+/* f = f^eq(rho, u) on the owned cells of a level (dense [z][y][x] arrays). */
+int orc3f_init_fields(orc3f_sim *s, int level, const double *rho, const double *ux, const double *uy,
+                      const double *uz) {
+    if (level < 0 || level >= s->m) return ORC_ERR_ARG;
+    o3lev *L = &s->L[level];
+    for (int64_t k = 0; k < L->n_own; ++k) {
+        const size_t c = (size_t)L->own[k];
+        orc3_feq(s->q, rho[c], ux[c], uy[c], uz[c], L->f + c * s->q);
+    }
+    return ORC_OK;
+}
+
+/* Collision (Eqs. (2)-(8) in 3D, BGK with Guo's term and the half-force
+ * velocity) of the owned cells of a level. */
+static void collide3f(orc3f_sim *s, int l) {
+    o3lev *L = &s->L[l];
+    const int Q3 = s->q;
+    const double tau = L->tau, pre = 1.0 - 0.5 / tau;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < L->n_own; ++k) {
+        const size_t c = (size_t)L->own[k];
+        const double *f = L->f + c * Q3;
+        const double Fx = L->F[0], Fy = L->F[1], Fz = L->F[2];
+        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int i = 0; i < Q3; ++i) { rho += f[i]; jx += C3X[i] * f[i]; jy += C3Y[i] * f[i]; jz += C3Z[i] * f[i]; }
+        double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho, uz = (jz + 0.5 * Fz) / rho;
+        double feq[27];
+        orc3_feq(Q3, rho, ux, uy, uz, feq);
+        double uF = ux * Fx + uy * Fy + uz * Fz;
+        for (int i = 0; i < Q3; ++i) {
+            double cu = C3X[i] * ux + C3Y[i] * uy + C3Z[i] * uz;
+            double cF = C3X[i] * Fx + C3Y[i] * Fy + C3Z[i] * Fz;
+            double fi = w3(Q3, i) * pre * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
+            L->fs[c * Q3 + i] = f[i] - (f[i] - feq[i]) / tau + fi;
+        }
+        L->rho[c] = rho;
+        L->u[3 * c] = ux; L->u[3 * c + 1] = uy; L->u[3 * c + 2] = uz;
+    }
+}
+
+/* Explosion (step (2) of Sec. 2.4): every halo cell of the fine level takes
+ * the post-collision populations of its coarse parent (RESCALE: with the
+ * non-equilibrium part scaled by s_cf). */
+static void explode3f(orc3f_sim *s, int lc, int lf) {
+    o3lev *C = &s->L[lc], *F = &s->L[lf];
+    const int Q3 = s->q;
+    double fac[2];
+    orc_interface_factors(C->tau, F->tau, fac);
+    const int rescale = s->c.cf_mode == ORC_CF_RESCALE;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < F->n_ghost; ++k) {
+        const size_t g = (size_t)F->ghost[k];
+        const int x = (int)(g % F->nx), y = (int)((g / F->nx) % F->ny), z = (int)(g / ((size_t)F->nx * F->ny));
+        const size_t p = c3(C, x / 2, y / 2, z / 2);
+        const double *src = C->fs + p * Q3;
+        double *dst = F->fs + g * Q3;
+        if (!rescale) {
+            for (int i = 0; i < Q3; ++i) dst[i] = src[i];
+        } else {
+            double feq[27];
+            orc3_feq(Q3, C->rho[p], C->u[3 * p], C->u[3 * p + 1], C->u[3 * p + 2], feq);
+            for (int i = 0; i < Q3; ++i) dst[i] = feq[i] + fac[0] * (src[i] - feq[i]);
+        }
+    }
+}
+
+/* Streaming, Eq. (10), over owned and halo cells (periodic wrap); a source
+ * that is neither owned nor halo leaves NaN. */
+static void stream3f(orc3f_sim *s, int l) {
+    o3lev *L = &s->L[l];
+    const int Q3 = s->q;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < L->n_act; ++k) {
+        const size_t c = (size_t)L->act[k];
+        const int x = (int)(c % L->nx), y = (int)((c / L->nx) % L->ny), z = (int)(c / ((size_t)L->nx * L->ny));
+        for (int i = 0; i < Q3; ++i) {
+            int sx = x - C3X[i], sy = y - C3Y[i], sz = z - C3Z[i];
+            wrap3(L, &sx, &sy, &sz);
+            const size_t p = c3(L, sx, sy, sz);
+            L->f[c * Q3 + i] = (L->kind[p] == K_OWN || L->kind[p] == K_GHOST) ? L->fs[p * Q3 + i] : NAN;
+        }
+    }
+}
+
+/* Step (5) of Sec. 2.4: the halo cells' sources of the second fine stream are
+ * their own post-stream values of the first. */
+static void halo_second3f(orc3f_sim *s, int l) {
+    o3lev *L = &s->L[l];
+    for (int64_t k = 0; k < L->n_ghost; ++k) {
+        const size_t g = (size_t)L->ghost[k];
+        memcpy(L->fs + g * s->q, L->f + g * s->q, sizeof(double) * s->q);
+    }
+}
+
+/* Coalescence (step (6) of Sec. 2.4): an owned coarse cell takes, for each
+ * direction whose source is covered by the fine level, the mean of its 8
+ * children's post-stream populations (RESCALE: non-equilibrium part scaled by
+ * s_fc about the moments of the assembled set). */
+static void coalesce3f(orc3f_sim *s, int lf, int lc) {
+    o3lev *F = &s->L[lf], *C = &s->L[lc];
+    const int Q3 = s->q;
+    double fac[2];
+    orc_interface_factors(C->tau, F->tau, fac);
+    const int rescale = s->c.cf_mode == ORC_CF_RESCALE;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < C->n_own; ++k) {
+        const size_t q = (size_t)C->own[k];
+        const int x = (int)(q % C->nx), y = (int)((q / C->nx) % C->ny), z = (int)(q / ((size_t)C->nx * C->ny));
+        int hid[27], any = 0;
+        for (int i = 0; i < Q3; ++i) {
+            int sx = x - C3X[i], sy = y - C3Y[i], sz = z - C3Z[i];
+            wrap3(C, &sx, &sy, &sz);
+            hid[i] = C->kind[c3(C, sx, sy, sz)] == K_HIDDEN;
+            any |= hid[i];
+        }
+        if (!any) continue;
+        double avg[27];
+        for (int i = 0; i < Q3; ++i) {
+            if (!hid[i]) continue;
+            double sum = 0.0;
+            for (int cz = 0; cz < 2; ++cz)
+                for (int cy = 0; cy < 2; ++cy)
+                    for (int cx = 0; cx < 2; ++cx)
+                        sum += F->f[c3(F, 2 * x + cx, 2 * y + cy, 2 * z + cz) * Q3 + i];
+            avg[i] = 0.125 * sum;
+        }
+        double *dst = C->f + q * Q3;
+        if (!rescale) {
+            for (int i = 0; i < Q3; ++i) if (hid[i]) dst[i] = avg[i];
+        } else {
+            double g[27], r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+            for (int i = 0; i < Q3; ++i) g[i] = hid[i] ? avg[i] : dst[i];
+            for (int i = 0; i < Q3; ++i) { r += g[i]; jx += C3X[i] * g[i]; jy += C3Y[i] * g[i]; jz += C3Z[i] * g[i]; }
+            double feq[27];
+            orc3_feq(Q3, r, jx / r, jy / r, jz / r, feq);
+            for (int i = 0; i < Q3; ++i)
+                if (hid[i]) dst[i] = feq[i] + fac[1] * (avg[i] - feq[i]);
+        }
+    }
+}
+
+/* One coarse step: the same clock over the finest substeps as in 2D (Sec.
+ * 2.4-2.5): levels whose substep starts collide, coarse to fine; levels
+ * whose substep ends stream, fine to coarse, the fine level's halo prepared
+ * by explosion before the first of its two substeps and by its own values
+ * before the second, the coarse level coalescing after its stream. */
+int orc3f_step(orc3f_sim *s, int32_t n) {
+    const int m = s->m;
+    const int64_t nsub = (int64_t)1 << (m - 1);
+    for (int32_t step = 0; step < n; ++step)
+        for (int64_t t = 0; t < nsub; ++t) {
+            for (int l = 0; l < m; ++l)
+                if (t % (nsub >> l) == 0) collide3f(s, l);
+            for (int l = m - 1; l >= 0; --l) {
+                const int64_t span = nsub >> l;
+                if ((t + 1) % span != 0) continue;
+                if (l > 0) {
+                    if (((t / span) & 1) == 0) explode3f(s, l - 1, l);
+                    else halo_second3f(s, l);
+                }
+                stream3f(s, l);
+                if (l + 1 < m) coalesce3f(s, l + 1, l);
+            }
+        }
+    return ORC_OK;
+}
+
+/* rho and u = (sum_i c_i f_i + F/2) / rho on the owned cells of a level, NaN
+ * elsewhere (dense [z][y][x]). */
+int orc3f_read_fields(const orc3f_sim *s, int level, double *rho, double *ux, double *uy, double *uz) {
+    if (level < 0 || level >= s->m) return ORC_ERR_ARG;
+    const o3lev *L = &s->L[level];
+    const size_t n = (size_t)L->nx * L->ny * L->nz;
+    for (size_t c = 0; c < n; ++c) rho[c] = ux[c] = uy[c] = uz[c] = NAN;
+    for (int64_t k = 0; k < L->n_own; ++k) {
+        const size_t c = (size_t)L->own[k];
+        const double *f = L->f + c * s->q;
+        double r = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        for (int i = 0; i < s->q; ++i) { r += f[i]; jx += C3X[i] * f[i]; jy += C3Y[i] * f[i]; jz += C3Z[i] * f[i]; }
+        rho[c] = r;
+        ux[c] = (jx + 0.5 * L->F[0]) / r;
+        uy[c] = (jy + 0.5 * L->F[1]) / r;
+        uz[c] = (jz + 0.5 * L->F[2]) / r;
+    }
+    return ORC_OK;
+}
+
+/* out = {mass, momentum x, y, z}: sums over owned cells with volume weight
+ * 8^-l; momentum is the bare first moment. */
+int orc3f_diagnostics(const orc3f_sim *s, double out[4]) {
+    for (int k = 0; k < 4; ++k) out[k] = 0.0;
+    for (int l = 0; l < s->m; ++l) {
+        const o3lev *L = &s->L[l];
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t k = 0; k < L->n_own; ++k) {
+            const double *f = L->f + (size_t)L->own[k] * s->q;
+            for (int i = 0; i < s->q; ++i) {
+                acc[0] += f[i]; acc[1] += C3X[i] * f[i]; acc[2] += C3Y[i] * f[i]; acc[3] += C3Z[i] * f[i];
+            }
+        }
+        const double wgt = 1.0 / (double)((int64_t)1 << (3 * l));
+        for (int k = 0; k < 4; ++k) out[k] += wgt * acc[k];
+    }
+    return ORC_OK;
+}

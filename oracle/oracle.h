@@ -159,6 +159,29 @@ int  orc3_body_force(const orc3_sim *s, double out[3]);
 int  orc3_marker_positions(const orc3_sim *s, double t, double *X, double *Y, double *Z);
 int  orc3_read_fields(const orc3_sim *s, double *rho, double *ux, double *uy, double *uz);
 
+/* ---- three dimensions on a block forest (periodic, D3Q19 or D3Q27) ------ */
+typedef struct {
+    int32_t nx0, ny0, nz0;   /* level-0 cells                                     */
+    int32_t block_n;         /* cells per block edge (boxes are in block units)   */
+    int32_t n_levels, q;     /* m >= 1; 19 or 27                                  */
+    int32_t n_boxes;         /* refinement boxes, 7 ints each: level, bx0, by0,   */
+    const int32_t *boxes;    /*   bz0, bx1, by1, bz1 (half-open, level-l blocks)  */
+    double tau0, rho0;       /* level-0 relaxation time, reference density       */
+    double fext[3];          /* uniform body-force density, level-0 units         */
+    int32_t cf_mode;         /* ORC_CF_*                                          */
+} orc3f_case;
+typedef struct orc3f_sim orc3f_sim;
+int  orc3f_create(const orc3f_case *c, orc3f_sim **out);
+void orc3f_destroy(orc3f_sim *s);
+int  orc3f_level_size(const orc3f_sim *s, int level, int32_t out[3]);
+/* Kind map of a level: 0 none, 1 own, 2 halo, 3 hidden (dense [z][y][x]). */
+int  orc3f_level_kinds(const orc3f_sim *s, int level, uint8_t *kind);
+int  orc3f_init_fields(orc3f_sim *s, int level, const double *rho, const double *ux, const double *uy,
+                       const double *uz);
+int  orc3f_step(orc3f_sim *s, int32_t n);
+int  orc3f_read_fields(const orc3f_sim *s, int level, double *rho, double *ux, double *uy, double *uz);
+int  orc3f_diagnostics(const orc3f_sim *s, double out[4]);
+
 #ifdef __cplusplus
 }
 #endif

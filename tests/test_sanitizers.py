@@ -38,8 +38,10 @@ def test_oracle_pins_under_asan_ubsan(tmp_path):
     libasan = subprocess.run(["gcc", "-print-file-name=libasan.so"], capture_output=True, text=True).stdout.strip()
     driver = ("import sys, oracle, pytest; oracle.LIB_PATH = sys.argv[1]; "
               "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', '-m', 'not gpu and not slow', "
-              "'tests/test_oracle_pins.py', 'tests/test_oracle_interface_pins.py', '-k', sys.argv[2]]))")
-    out = _run([sys.executable, "-c", driver, so, ORACLE_PINS + " or chapman or outflow_at or 3d_pitch_plunge_pose"],
+              "'tests/test_oracle_pins.py', 'tests/test_oracle_interface_pins.py', "
+              "'tests/test_oracle_forest3d.py', '-k', sys.argv[2]]))")
+    out = _run([sys.executable, "-c", driver, so, ORACLE_PINS + " or chapman or outflow_at or 3d_pitch_plunge_pose or invariant_forest "
+                                           "or single_level_forest or uniform_stream_on or permutation"],
                {"LD_PRELOAD": libasan, "OMP_NUM_THREADS": "4"}, 900)
     assert " passed" in out and "failed" not in out, out[-2000:]
 

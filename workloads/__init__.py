@@ -689,3 +689,100 @@ def flapping_ellipsoid3(n=32, chord=12.0, amp_deg=30.0, T=1.0, U=0.05, tau=0.8, 
     return Workload3(name=f"flapping_ellipsoid3_{n}", nx=n, ny=n, nz=n, tau=tau, lattice=lattice,
                      body=(xb, yb, zb, dA, mdf_iters), motion=(1, params), init=init,
                      meta=dict(U=U, chord=chord, n_markers=nm))
+
+
+# ---- three dimensions on a block forest ------------------------------------------
+
+@dataclasses.dataclass
+class Workload3F:
+    """A periodic 3D case on a block forest (Sec. 2.3-2.4 in three dimensions).
+
+    Level l has (nx0, ny0, nz0) * 2**l cells; a box (level, bx0, by0, bz0,
+    bx1, by1, bz1) covers the half-open range of level-l blocks of block_n^3
+    cells.  tau_l = 1/2 + 2**l (tau0 - 1/2) and F_l = F_0 / 2**l (Eq. (9))."""
+    name: str
+    nx0: int
+    ny0: int
+    nz0: int
+    n_levels: int = 1
+    boxes: tuple = ()
+    block_n: int = 8
+    tau0: float = 0.8
+    rho0: float = 1.0
+    fext: tuple = (0.0, 0.0, 0.0)
+    lattice: int = 19
+    cf_mode: int = CF_HOMOGENEOUS
+    # init(level, nx, ny, nz) -> (rho, ux, uy, uz), each [nz, ny, nx] or a scalar
+    init: Optional[Callable] = None
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    def replace(self, **kw):
+        return dataclasses.replace(self, **kw)
+
+
+def _centres3(level, nx, ny, nz):
+    """Cell centres of level l in level-0 units, each [nz, ny, nx]."""
+    h = 1.0 / (1 << level)
+    z, y, x = np.meshgrid((np.arange(nz) + 0.5) * h, (np.arange(ny) + 0.5) * h, (np.arange(nx) + 0.5) * h,
+                          indexing="ij")
+    return x, y, z
+
+
+def uniform3f(u=(0.04, 0.02, -0.01), n0=32, m=2, boxes=((1, 1, 1, 1, 3, 3, 3),), tau0=0.8, lattice=19,
+              cf_mode=CF_HOMOGENEOUS, rho0=1.0, name="uniform3f"):
+    """A uniform stream on a refined forest: every scheme that is consistent
+    across the interface keeps it uniform exactly (up to rounding)."""
+    def init(level, nx, ny, nz):
+        return rho0, u[0], u[1], u[2]
+    return Workload3F(name, n0, n0, n0, m, tuple(boxes), 8, tau0, rho0, (0.0, 0.0, 0.0), lattice, cf_mode, init)
+
+
+def tgv3f(n0=32, m=2, boxes=((1, 2, 2, 0, 6, 6, 1),), tau0=0.8, u0=0.02, lattice=19, cf_mode=CF_HOMOGENEOUS,
+          rho0=1.0, plane="xy", n_third=None, name="tgv3f"):
+    """The Taylor-Green vortex of Sec. 3.1 in one coordinate plane ("xy",
+    "xz" or "yz"), uniform along the third axis (n_third level-0 cells,
+    default n0 / 4), on a 3D forest: the exact solution decays as
+    exp(-2 nu k^2 t) on every level."""
+    n_third = n_third or n0 // 4
+    k = 2.0 * math.pi / n0
+    a_ax, b_ax = {"xy": (0, 1), "xz": (0, 2), "yz": (1, 2)}[plane]
+    size = [n_third] * 3
+    size[a_ax] = size[b_ax] = n0
+
+    def init(level, nx, ny, nz):
+        c = _centres3(level, nx, ny, nz)
+        a, b = c[a_ax], c[b_ax]
+        u = [np.zeros_like(a) for _ in range(3)]
+        u[a_ax] = -u0 * np.cos(k * a) * np.sin(k * b)
+        u[b_ax] = u0 * np.sin(k * a) * np.cos(k * b)
+        p = -0.25 * rho0 * u0 * u0 * (np.cos(2 * k * a) + np.cos(2 * k * b))
+        return rho0 + 3.0 * p, u[0], u[1], u[2]
+    return Workload3F(name, size[0], size[1], size[2], m, tuple(boxes), 8, tau0, rho0, (0.0, 0.0, 0.0), lattice,
+                      cf_mode, init, {"u0": u0, "k": k, "nu": (tau0 - 0.5) / 3.0, "axes": (a_ax, b_ax)})
+
+
+def vortex3f(n0=32, m=2, boxes=((1, 2, 2, 2, 6, 6, 6),), tau0=0.8, u0=0.02, lattice=19, cf_mode=CF_HOMOGENEOUS,
+             rho0=1.0, seed=4606, name="vortex3f"):
+    """A genuinely 3D periodic flow: a sum of a few divergence-free Fourier
+    modes with seeded amplitudes and phases, velocities of order u0."""
+    rng = np.random.default_rng(seed)
+    modes = []
+    for _ in range(4):
+        kv = rng.integers(-2, 3, size=3)
+        while not kv.any():
+            kv = rng.integers(-2, 3, size=3)
+        a = rng.normal(size=3)
+        a -= kv * (a @ kv) / (kv @ kv)              # amplitude normal to the wave vector
+        modes.append((kv.astype(float), a * u0 / np.linalg.norm(a) / 2.0, rng.uniform(0, 2 * math.pi)))
+    k = 2.0 * math.pi / n0
+
+    def init(level, nx, ny, nz):
+        x, y, z = _centres3(level, nx, ny, nz)
+        u = [np.zeros_like(x) for _ in range(3)]
+        for kv, a, ph in modes:
+            s = np.sin(k * (kv[0] * x + kv[1] * y + kv[2] * z) + ph)
+            for d in range(3):
+                u[d] += a[d] * s
+        return np.full_like(x, rho0), u[0], u[1], u[2]
+    return Workload3F(name, n0, n0, n0, m, tuple(boxes), 8, tau0, rho0, (0.0, 0.0, 0.0), lattice, cf_mode, init,
+                      {"u0": u0})
