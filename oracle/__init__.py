@@ -468,7 +468,7 @@ class Oracle3FSim:
         self.n_levels = wl.n_levels
         if wl.init is not None:
             for l in range(wl.n_levels):
-                self.init_fields(l, *wl.init(l, *self.level_size(l)))
+                self.init_fields(l, *wl.init(l, 0, 0, 0, *self.level_size(l)))
 
     def __del__(self):
         h = getattr(self, "_h", None)

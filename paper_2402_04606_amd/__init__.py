@@ -34,6 +34,8 @@ ABI_SYMBOLS = [
     "sbt_last_error",
     "sbt3_plan", "sbt3_create", "sbt3_destroy", "sbt3_init_slab", "sbt3_step", "sbt3_synchronize",
     "sbt3_read_slab", "sbt3_body_force",
+    "sbt3f_plan", "sbt3f_create", "sbt3f_destroy", "sbt3f_level_kinds", "sbt3f_init_box", "sbt3f_step",
+    "sbt3f_synchronize", "sbt3f_read_box", "sbt3f_diagnostics",
 ]
 
 
@@ -60,6 +62,13 @@ class Desc3(C.Structure):
                 ("n_markers", C.c_int32), ("marker_xyz", C.POINTER(C.c_double)),
                 ("marker_dA", C.POINTER(C.c_double)), ("mdf_iters", C.c_int32),
                 ("ibm_box_cells", C.c_int64), ("body_motion", C.c_int32), ("motion_p", C.c_double * 10)]
+
+
+class Desc3F(C.Structure):
+    _fields_ = [("nx0", C.c_int32), ("ny0", C.c_int32), ("nz0", C.c_int32), ("n_levels", C.c_int32),
+                ("n_boxes", C.c_int32), ("boxes", C.POINTER(C.c_int32)), ("tau0", C.c_double),
+                ("rho0", C.c_double), ("fext", C.c_double * 3), ("storage", C.c_int32), ("lattice", C.c_int32),
+                ("cf_mode", C.c_int32)]
 
 
 class CaseDesc(C.Structure):
@@ -128,6 +137,15 @@ def lib():
             "sbt3_synchronize": [vp],
             "sbt3_read_slab": [vp, i32, i32, d, d, d, d],
             "sbt3_body_force": [vp, d],
+            "sbt3f_plan": [C.POINTER(Desc3F), C.POINTER(C.c_size_t)],
+            "sbt3f_create": [C.POINTER(Desc3F), vp, C.c_size_t, vp, C.POINTER(vp)],
+            "sbt3f_destroy": [vp],
+            "sbt3f_level_kinds": [C.POINTER(Desc3F), i32, C.POINTER(i32), C.POINTER(C.c_uint8), C.POINTER(i64)],
+            "sbt3f_init_box": [vp, i32, C.POINTER(i32), d, d, d, d],
+            "sbt3f_step": [vp, i32],
+            "sbt3f_synchronize": [vp],
+            "sbt3f_read_box": [vp, i32, C.POINTER(i32), d, d, d, d],
+            "sbt3f_diagnostics": [vp, d],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -506,3 +524,126 @@ class Sim3:
 
     def updates_per_step(self):
         return self.wl.nx * self.wl.ny * self.wl.nz
+
+
+def desc3f(wl, storage=F64):
+    """A ``workloads.Workload3F`` as the C descriptor; returns (desc, keepalive)."""
+    d = Desc3F()
+    d.nx0, d.ny0, d.nz0, d.n_levels = wl.nx0, wl.ny0, wl.nz0, wl.n_levels
+    boxes = np.ascontiguousarray(np.array(wl.boxes, dtype=np.int32).reshape(-1, 7))
+    d.n_boxes = boxes.shape[0]
+    d.boxes = boxes.ctypes.data_as(C.POINTER(C.c_int32))
+    d.tau0, d.rho0 = wl.tau0, wl.rho0
+    for k in range(3):
+        d.fext[k] = wl.fext[k]
+    d.storage = STORAGE[storage] if isinstance(storage, str) else storage
+    d.lattice, d.cf_mode = wl.lattice, wl.cf_mode
+    return d, boxes
+
+
+def _box(box):
+    return (C.c_int32 * 6)(*[int(v) for v in box])
+
+
+def level_info3f(wl, level):
+    """(nx, ny, nz, owned, halo, hidden) of a level of the forest (host only)."""
+    d, keep = desc3f(wl)
+    info = (C.c_int64 * 6)()
+    _check(lib().sbt3f_level_kinds(C.byref(d), level, None, None, info))
+    return tuple(info)
+
+
+def level_kinds3f(wl, level, box=None):
+    """Kinds [nz, ny, nx] (0 none, 1 owned, 2 halo, 3 hidden) of a level's cells
+    inside box (x0, y0, z0, nx, ny, nz; default: the whole level), host only."""
+    info = level_info3f(wl, level)
+    box = box or (0, 0, 0, info[0], info[1], info[2])
+    d, keep = desc3f(wl)
+    k = np.zeros((box[5], box[4], box[3]), dtype=np.uint8)
+    _check(lib().sbt3f_level_kinds(C.byref(d), level, _box(box), k.ctypes.data_as(C.POINTER(C.c_uint8)), None))
+    return k
+
+
+class Sim3F:
+    """A periodic 3D block forest (``workloads.Workload3F``) on cuda:0: torch
+    device buffer, torch's current stream.  Each level is initialised over
+    the bounding box of its region (level 0: the whole grid)."""
+
+    def __init__(self, wl, storage="f64", stream=None):
+        import torch
+        self.wl = wl
+        self.storage = STORAGE[storage] if isinstance(storage, str) else storage
+        self._desc, self._keep = desc3f(wl, self.storage)
+        n = C.c_size_t()
+        _check(lib().sbt3f_plan(C.byref(self._desc), C.byref(n)))
+        self.device_bytes = n.value
+        self._buf = torch.empty(n.value + 256, dtype=torch.uint8, device="cuda")
+        ptr = (self._buf.data_ptr() + 255) // 256 * 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        _check(lib().sbt3f_create(C.byref(self._desc), C.c_void_p(ptr), n.value,
+                                  C.c_void_p(self._stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.n_levels = wl.n_levels
+        self.info = [level_info3f(wl, l) for l in range(wl.n_levels)]
+        if wl.init is not None:
+            for l in range(wl.n_levels):
+                for box in self.init_boxes(l):
+                    self.init_box(l, box, *wl.init(l, *box))
+
+    def level_size(self, l):
+        return self.info[l][:3]
+
+    def region_box(self, l):
+        """Bounding box (x0, y0, z0, nx, ny, nz) of level l's boxes, level cells."""
+        nx, ny, nz = self.level_size(l)
+        if l == 0:
+            return (0, 0, 0, nx, ny, nz)
+        b = np.array([q for q in self.wl.boxes if q[0] == l]).reshape(-1, 7)
+        lo, hi = b[:, 1:4].min(0) * 8, b[:, 4:7].max(0) * 8
+        return (int(lo[0]), int(lo[1]), int(lo[2]), int(hi[0] - lo[0]), int(hi[1] - lo[1]), int(hi[2] - lo[2]))
+
+    def init_boxes(self, l, max_cells=1 << 24):
+        """The level's region box cut into z-slabs of at most max_cells cells."""
+        x0, y0, z0, nx, ny, nz = self.region_box(l)
+        dz = max(1, min(nz, max_cells // (nx * ny)))
+        return [(x0, y0, z, nx, ny, min(dz, z0 + nz - z)) for z in range(z0, z0 + nz, dz)]
+
+    def init_box(self, l, box, rho, ux, uy, uz):
+        shape = (box[5], box[4], box[3])
+        a = [np.ascontiguousarray(np.broadcast_to(v, shape), dtype=np.float64) for v in (rho, ux, uy, uz)]
+        _check(lib().sbt3f_init_box(self._h, l, _box(box), *[_dp(v) for v in a]))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().sbt3f_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        _check(lib().sbt3f_step(self._h, int(n)))
+
+    def synchronize(self):
+        _check(lib().sbt3f_synchronize(self._h))
+
+    def fields(self, l, box=None):
+        """(rho, ux, uy, uz) of level l inside box (default: the whole level),
+        each [nz, ny, nx] FP64, NaN where the level owns no cell."""
+        box = box or (0, 0, 0, *self.level_size(l))
+        out = [np.empty((box[5], box[4], box[3])) for _ in range(4)]
+        _check(lib().sbt3f_read_box(self._h, l, _box(box), *[_dp(a) for a in out]))
+        return out
+
+    def diagnostics(self):
+        out = np.zeros(4)
+        _check(lib().sbt3f_diagnostics(self._h, _dp(out)))
+        return out
+
+    def updates_per_step(self):
+        """Cell updates of one coarse step: owned cells of level l times 2^l."""
+        return sum(self.info[l][3] << l for l in range(self.n_levels))

@@ -24,7 +24,7 @@ def declared_symbols():
             continue
         src = open(os.path.join(ROOT, "include", h)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-        names |= set(re.findall(r"\b(sbt3?_[a-z_]+)\s*\(", src))
+        names |= set(re.findall(r"\b(sbt(?:3f?)?_[a-z_]+)\s*\(", src))
     return sorted(names)
 
 

@@ -146,11 +146,11 @@ def _permuted(wl, perm):
     boxes = tuple((b[0], *(b[1 + p] for p in perm), *(b[4 + p] for p in perm)) for b in wl.boxes)
     init0 = wl.init
 
-    def init(level, nx, ny, nz):
-        size = [0, 0, 0]
+    def init(level, x0, y0, z0, nx, ny, nz):
+        size, org = [0, 0, 0], [0, 0, 0]
         for d, p in enumerate(perm):
-            size[p] = (nx, ny, nz)[d]
-        rho, *u = (np.broadcast_to(v, (size[2], size[1], size[0])) for v in init0(level, *size))
+            size[p], org[p] = (nx, ny, nz)[d], (x0, y0, z0)[d]
+        rho, *u = (np.broadcast_to(v, (size[2], size[1], size[0])) for v in init0(level, *org, *size))
         # arrays are [z, y, x]: reverse the axis order to permute, then reverse back
         order = [2 - perm[2 - d] for d in range(3)]
         return (rho.transpose(order), *(u[p].transpose(order) for p in perm))

@@ -712,7 +712,8 @@ class Workload3F:
     fext: tuple = (0.0, 0.0, 0.0)
     lattice: int = 19
     cf_mode: int = CF_HOMOGENEOUS
-    # init(level, nx, ny, nz) -> (rho, ux, uy, uz), each [nz, ny, nx] or a scalar
+    # init(level, x0, y0, z0, nx, ny, nz) -> (rho, ux, uy, uz) on the level's
+    # cells [x0, x0 + nx) x [y0, ...) x [z0, ...), each [nz, ny, nx] or a scalar
     init: Optional[Callable] = None
     meta: dict = dataclasses.field(default_factory=dict)
 
@@ -720,11 +721,11 @@ class Workload3F:
         return dataclasses.replace(self, **kw)
 
 
-def _centres3(level, nx, ny, nz):
-    """Cell centres of level l in level-0 units, each [nz, ny, nx]."""
+def _centres3(level, nx, ny, nz, x0=0, y0=0, z0=0):
+    """Centres of level-l cells [x0, x0 + nx) x ... in level-0 units, each [nz, ny, nx]."""
     h = 1.0 / (1 << level)
-    z, y, x = np.meshgrid((np.arange(nz) + 0.5) * h, (np.arange(ny) + 0.5) * h, (np.arange(nx) + 0.5) * h,
-                          indexing="ij")
+    z, y, x = np.meshgrid((z0 + np.arange(nz) + 0.5) * h, (y0 + np.arange(ny) + 0.5) * h,
+                          (x0 + np.arange(nx) + 0.5) * h, indexing="ij")
     return x, y, z
 
 
@@ -732,7 +733,7 @@ def uniform3f(u=(0.04, 0.02, -0.01), n0=32, m=2, boxes=((1, 1, 1, 1, 3, 3, 3),),
               cf_mode=CF_HOMOGENEOUS, rho0=1.0, name="uniform3f"):
     """A uniform stream on a refined forest: every scheme that is consistent
     across the interface keeps it uniform exactly (up to rounding)."""
-    def init(level, nx, ny, nz):
+    def init(level, x0, y0, z0, nx, ny, nz):
         return rho0, u[0], u[1], u[2]
     return Workload3F(name, n0, n0, n0, m, tuple(boxes), 8, tau0, rho0, (0.0, 0.0, 0.0), lattice, cf_mode, init)
 
@@ -749,8 +750,8 @@ def tgv3f(n0=32, m=2, boxes=((1, 2, 2, 0, 6, 6, 1),), tau0=0.8, u0=0.02, lattice
     size = [n_third] * 3
     size[a_ax] = size[b_ax] = n0
 
-    def init(level, nx, ny, nz):
-        c = _centres3(level, nx, ny, nz)
+    def init(level, x0, y0, z0, nx, ny, nz):
+        c = _centres3(level, nx, ny, nz, x0, y0, z0)
         a, b = c[a_ax], c[b_ax]
         u = [np.zeros_like(a) for _ in range(3)]
         u[a_ax] = -u0 * np.cos(k * a) * np.sin(k * b)
@@ -776,8 +777,8 @@ def vortex3f(n0=32, m=2, boxes=((1, 2, 2, 2, 6, 6, 6),), tau0=0.8, u0=0.02, latt
         modes.append((kv.astype(float), a * u0 / np.linalg.norm(a) / 2.0, rng.uniform(0, 2 * math.pi)))
     k = 2.0 * math.pi / n0
 
-    def init(level, nx, ny, nz):
-        x, y, z = _centres3(level, nx, ny, nz)
+    def init(level, x0, y0, z0, nx, ny, nz):
+        x, y, z = _centres3(level, nx, ny, nz, x0, y0, z0)
         u = [np.zeros_like(x) for _ in range(3)]
         for kv, a, ph in modes:
             s = np.sin(k * (kv[0] * x + kv[1] * y + kv[2] * z) + ph)
@@ -786,3 +787,17 @@ def vortex3f(n0=32, m=2, boxes=((1, 2, 2, 2, 6, 6, 6),), tau0=0.8, u0=0.02, latt
         return np.full_like(x, rho0), u[0], u[1], u[2]
     return Workload3F(name, n0, n0, n0, m, tuple(boxes), 8, tau0, rho0, (0.0, 0.0, 0.0), lattice, cf_mode, init,
                       {"u0": u0})
+
+
+def forest3d_bench(n0=256, lattice=19, cf_mode=CF_HOMOGENEOUS, tau0=0.6, u0=0.02):
+    """The 3D forest the benchmark times: a 256^3 periodic level 0 with a
+    nested level 1 over the central half of each axis and a level 2 over the
+    central quarter (a body-centred refinement of the shape Sec. 2.3
+    describes), carrying the seeded 3D vortex of period n0 / 4."""
+    b1 = n0 // 8 * 2                      # level-1 blocks per axis
+    b2 = n0 // 8 * 4
+    boxes = ((1, b1 // 4, b1 // 4, b1 // 4, 3 * b1 // 4, 3 * b1 // 4, 3 * b1 // 4),
+             (2, 3 * b2 // 8, 3 * b2 // 8, 3 * b2 // 8, 5 * b2 // 8, 5 * b2 // 8, 5 * b2 // 8))
+    wl = vortex3f(n0=n0 // 4, m=3, boxes=boxes, tau0=tau0, u0=u0, lattice=lattice, cf_mode=cf_mode,
+                  name="forest3d_bench")
+    return wl.replace(nx0=n0, ny0=n0, nz0=n0)
