@@ -208,6 +208,69 @@ def bench3d(args, P, W):
     print(json.dumps(out), flush=True)
 
 
+def bench_forest3d(args, P, W):
+    """The 3D block forest (forest3d = 256^3 D3Q19 level 0 with nested level-1
+    and level-2 boxes over the central half and quarter of each axis;
+    forest3d_q27 the same with D3Q27): MLUPS over the cell updates of a
+    coarse step (owned cells of level l counted 2^l times) and the bandwidth
+    of the step's launches from HIP events on the stream they run on."""
+    import torch
+    q = 27 if args.workload == "forest3d_q27" else 19
+    wl = W.forest3d_bench(lattice=q)
+    sim = P.Sim3F(wl, args.storage)
+    sim.step(args.warmup)
+    sim.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ups = sim.updates_per_step()
+    s = P.STORAGE_BYTES[P.STORAGE[args.storage]]
+    step_ms = e0.elapsed_time(e1) / args.steps
+    algo = ups * 2 * q * s
+    gbs = algo / (step_ms * 1e-3) / 1e9
+    launches = 1 + sum(1 << l for l in range(1, wl.n_levels))
+    out = {
+        "metric": f"MLUPS & HBM GB/s fraction (D3Q{q} 3D block forest)",
+        "value": round(ups * args.steps / dt / 1e6, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.storage == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"d3q{q}_forest_256^3_levels3_nested_half_quarter", "storage": args.storage,
+                   "updates_per_step": ups, "levels": wl.n_levels,
+                   "owned_cells": [i[3] for i in sim.info], "halo_cells": [i[4] for i in sim.info],
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": f"forest3_kernel (D3Q{q} pull stream + coalescence + collide + explosion), "
+                               f"{launches} launches per coarse step",
+                     "bytes_per_update": 2 * q * s, "algorithmic_bytes_per_step": algo,
+                     "step_launch_ms": round(step_ms, 4)},
+    }
+    if not args.no_cpu:
+        import oracle
+        small = W.forest3d_bench(n0=32, lattice=q)
+        o = oracle.Oracle3FSim(small)
+        ups_small = sum(int((o.kinds(l) == 1).sum()) << l for l in range(small.n_levels))
+        k, t_used = 0, 0.0
+        while t_used < args.cpu_budget:
+            t1 = time.perf_counter()
+            o.step(1)
+            t_used += time.perf_counter() - t1
+            k += 1
+        out["cpu_baseline"] = dict(value=round(ups_small * k / t_used / 1e6, 3), unit="MLUPS",
+                                   cores=oracle.num_threads(), kind="oracle",
+                                   sample=f"the same forest at 32^3 level-0 cells ({ups_small} updates per "
+                                          f"coarse step), {k} coarse steps in {t_used:.1f} s, FP64, OpenMP")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +324,8 @@ def main():
 
     import paper_2402_04606_amd as P
     import workloads as W
+    if args.workload.startswith("forest3d"):
+        return bench_forest3d(args, P, W)
     if args.workload.startswith("box3d") or args.workload == "flap3d":
         return bench3d(args, P, W)
     wls, wname = workload_list(args.workload)

@@ -76,6 +76,10 @@ struct Args3 {
   const void *fprev;    // its lattice read by its last substep (coalescence)
   void *fcur;           // its lattice its next substep reads (explosion)
   const int32_t *list;  // pool blocks of the launch
+  int32_t n_blocks;     // list entries
+  int32_t n_fast;       // leading list entries taking the interior path (step launches)
+  const int32_t *band;  // halo cells gathered in the launch (block * 512 + cell), after the blocks
+  int32_t n_band;
   int32_t mode;
   int32_t xcd;
   Lev3 L;
@@ -84,13 +88,22 @@ struct Args3 {
   int32_t *err;
 };
 
-__device__ __forceinline__ int remap3(int bid, int nblk, int enable) {
-  if (!enable) return bid;
-  // Workgroups go to the 8 XCDs round-robin: give each XCD a contiguous run
-  // of (Morton-ordered) blocks so neighbour reads hit its own L2.
-  const int xcd = bid & 7, k = bid >> 3;
-  const int q = nblk >> 3, r = nblk & 7;
-  return xcd * q + (xcd < r ? xcd : r) + k;
+// Work item of workgroup bid: an entry of the launch's sequence [interior
+// blocks (n_fast) | other blocks | groups of 512 halo cells] (n entries), or
+// -1.  Workgroups go to the 8 XCDs round-robin; XCD x takes the x-th eighth
+// of the entries after the interior blocks (interface blocks and halo
+// groups: latency-bound, so they start first and are spread over all XCDs)
+// and then the x-th eighth of the interior blocks (contiguous in Morton
+// order, so neighbour reads stay in its own L2).  Without the remap the
+// entry is bid.
+__device__ __forceinline__ int remap3(int bid, int n, int n_fast, int enable) {
+  if (!enable) return bid < n ? bid : -1;
+  const int x = bid & 7, k = bid >> 3, ns = n - n_fast;
+  const int s0 = ns * x / 8, s1 = ns * (x + 1) / 8;
+  if (k < s1 - s0) return n_fast + s0 + k;
+  const int k2 = k - (s1 - s0);
+  const int r0 = n_fast * x / 8, r1 = n_fast * (x + 1) / 8;
+  return k2 < r1 - r0 ? r0 + k2 : -1;
 }
 
 __device__ __forceinline__ int nbr_slot(int sx, int sy, int sz) {
@@ -110,28 +123,31 @@ template <int ST> using Calc3 = std::conditional_t<ST == 0, double, float>;
 // post-stream value f(g, i) = f*(g - c_i, i) (coalescence, step (6) of Sec.
 // 2.4), children in z, y, x order.
 template <int ST, int Q>
-__device__ __forceinline__ Calc3<ST> coalesce3(const Args3 &a, const Blk3 &k, int x, int y, int z, int i) {
+__device__ __forceinline__ Calc3<ST> coalesce3(const Args3 &a, const Blk3 &k, const int32_t (*cnb)[27], int x, int y,
+                                               int z, int i) {
 #pragma clang fp contract(off)
   using S = Store3<ST>;
   using T = typename S::T;
   using C = Calc3<ST>;
-  const int cb = k.child[(x >> 2) + 2 * (y >> 2) + 4 * (z >> 2)];
+  const int o = (x >> 2) + 2 * (y >> 2) + 4 * (z >> 2);
+  const int cb = k.child[o];
   if (cb < 0) return C(__builtin_nan(""));
   const T *fp = static_cast<const T *>(a.fprev);
-  const Blk3 *F = a.fmeta + cb;
   const int fx0 = (2 * x) & 7, fy0 = (2 * y) & 7, fz0 = (2 * z) & 7;
+  // the 8 loads first (an absent block reads the child block; its value is
+  // replaced by NaN), then the sum in z, y, x order
+  C v[8];
+  bool miss[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int sx = fx0 + (c & 1) - E3X[i], sy = fy0 + ((c >> 1) & 1) - E3Y[i], sz = fz0 + (c >> 2) - E3Z[i];
+    const int nb = cnb[o][nbr_slot(sx, sy, sz)];
+    miss[c] = nb < 0;
+    v[c] = (C)S::ld(fp[((size_t)(nb < 0 ? cb : nb) * Q + i) * kC3 + wrap_cell(sx, sy, sz)]);
+  }
   C sum = C(0);
 #pragma unroll
-  for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-    for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-      for (int cx = 0; cx < 2; ++cx) {
-        const int sx = fx0 + cx - E3X[i], sy = fy0 + cy - E3Y[i], sz = fz0 + cz - E3Z[i];
-        const int nb = F->nbr[nbr_slot(sx, sy, sz)];
-        const C v = nb < 0 ? C(__builtin_nan("")) : (C)S::ld(fp[((size_t)nb * Q + i) * kC3 + wrap_cell(sx, sy, sz)]);
-        sum += v;
-      }
+  for (int c = 0; c < 8; ++c) sum += miss[c] ? C(__builtin_nan("")) : v[c];
   return C(0.125) * sum;
 }
 
@@ -154,7 +170,8 @@ __device__ __forceinline__ Calc3<ST> feq3(const Lev3 &L, int i, Calc3<ST> rho, C
 // One cell of a level launch; part gets its mass and first moment in a
 // readout.
 template <int ST, int Q>
-__device__ __forceinline__ void cell3(const Args3 &a, const Blk3 &k, int b, int w, int cell, double part[4]) {
+__device__ __forceinline__ void cell3(const Args3 &a, const Blk3 &k, const int32_t (*cnb)[27], int b, int w, int cell,
+                                      double part[4]) {
 #pragma clang fp contract(off)
   using S = Store3<ST>;
   using T = typename S::T;
@@ -164,19 +181,7 @@ __device__ __forceinline__ void cell3(const Args3 &a, const Blk3 &k, int b, int 
   const T *src = static_cast<const T *>(a.src);
   T *dst = static_cast<T *>(a.dst);
 
-  if (k.flags & B3_GHOST) {  // halo cells: streamed, never collided
-    if (!(code & K3_BAND)) return;
-    T g[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int sx = x - E3X[i], sy = y - E3Y[i], sz = z - E3Z[i];
-      const int nb = k.nbr[nbr_slot(sx, sy, sz)];
-      g[i] = nb < 0 ? S::st(C(__builtin_nan(""))) : src[((size_t)nb * Q + i) * kC3 + wrap_cell(sx, sy, sz)];
-    }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) dst[((size_t)b * Q + i) * kC3 + cell] = g[i];
-    return;
-  }
+  if (k.flags & B3_GHOST) return;  // halo blocks: their cells go through band3
   if (code & K3_HIDDEN) {
     if (a.mode & M3_READOUT) {
 #pragma unroll
@@ -191,14 +196,16 @@ __device__ __forceinline__ void cell3(const Args3 &a, const Blk3 &k, int b, int 
     for (int i = 0; i < Q; ++i) f[i] = (C)S::ld(src[((size_t)b * Q + i) * kC3 + cell]);
   } else {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if (code & (1u << i)) {
-        f[i] = coalesce3<ST, Q>(a, k, x, y, z, i);
-      } else {
-        const int sx = x - E3X[i], sy = y - E3Y[i], sz = z - E3Z[i];
-        const int nb = k.nbr[nbr_slot(sx, sy, sz)];
-        f[i] = nb < 0 ? C(__builtin_nan("")) : (C)S::ld(src[((size_t)nb * Q + i) * kC3 + wrap_cell(sx, sy, sz)]);
-      }
+    for (int i = 0; i < Q; ++i) {  // every source first (absent blocks as in the halo gather)
+      const int sx = x - E3X[i], sy = y - E3Y[i], sz = z - E3Z[i];
+      const int nb = k.nbr[nbr_slot(sx, sy, sz)];
+      const C v = (C)S::ld(src[((size_t)(nb < 0 ? b : nb) * Q + i) * kC3 + wrap_cell(sx, sy, sz)]);
+      f[i] = nb < 0 ? C(__builtin_nan("")) : v;
+    }
+    if (code & K3_HSRC) {  // then the coalesced populations
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        if (code & (1u << i)) f[i] = coalesce3<ST, Q>(a, k, cnb, x, y, z, i);
     }
     if ((code & K3_HSRC) && a.L.rescale) {  // RESCALE the coalesced populations
       C r = C(0), jx = C(0), jy = C(0), jz = C(0);
@@ -330,18 +337,155 @@ __device__ __forceinline__ void cell3(const Args3 &a, const Blk3 &k, int b, int 
   }
 }
 
+typedef __attribute__((address_space(4))) const int32_t ci32_3;
+
+// Interior block (no per-cell code: every cell owned, every source in the
+// pool): the straight-line gather + collide.  The neighbour indices come
+// through scalar loads; each lane picks its source block per direction with
+// selects among the (at most 8) candidates the direction can reach, so the Q
+// loads issue back to back.
 template <int ST, int Q>
+__device__ __forceinline__ void interior3(const Args3 &a, int b, int cell) {
+#pragma clang fp contract(off)
+  using S = Store3<ST>;
+  using T = typename S::T;
+  using C = Calc3<ST>;
+  ci32_3 *nbp = (ci32_3 *)(a.meta + b) + 5;   // Blk3::nbr, 27 scalar loads
+  int nb[27];
+#pragma unroll
+  for (int k = 0; k < 27; ++k) nb[k] = __builtin_amdgcn_readfirstlane(nbp[k]);
+  const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
+  const T *src = static_cast<const T *>(a.src);
+  T *dst = static_cast<T *>(a.dst);
+  C f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = E3X[i], cy = E3Y[i], cz = E3Z[i];
+    // the lane's source leaves the block along an axis only at one face
+    const bool ox = cx != 0 && x == (cx > 0 ? 0 : 7);
+    const bool oy = cy != 0 && y == (cy > 0 ? 0 : 7);
+    const bool oz = cz != 0 && z == (cz > 0 ? 0 : 7);
+    // select among the candidates of this direction (compile-time slots)
+    const int s0 = 13, sx = -cx, sy = -3 * cy, sz = -9 * cz;
+    const int p00 = ox ? nb[s0 + sx] : nb[s0];
+    const int p10 = ox ? nb[s0 + sx + sy] : nb[s0 + sy];
+    const int p01 = ox ? nb[s0 + sx + sz] : nb[s0 + sz];
+    const int p11 = ox ? nb[s0 + sx + sy + sz] : nb[s0 + sy + sz];
+    const int q0 = oy ? p10 : p00, q1 = oy ? p11 : p01;
+    const int blk = oz ? q1 : q0;
+    const uint32_t off = ((uint32_t)blk * Q + i) * kC3 + (uint32_t)wrap_cell(x - cx, y - cy, z - cz);
+    f[i] = (C)S::ld(src[off]);
+  }
+  C rho = C(0), jx = C(0), jy = C(0), jz = C(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    rho += f[i];
+    jx += E3X[i] * f[i];
+    jy += E3Y[i] * f[i];
+    jz += E3Z[i] * f[i];
+  }
+  if constexpr (ST == 0) {
+    const double Fx = a.L.F[0], Fy = a.L.F[1], Fz = a.L.F[2];
+    const double ux = (jx + 0.5 * Fx) / rho, uy = (jy + 0.5 * Fy) / rho, uz = (jz + 0.5 * Fz) / rho;
+    const double usq = ux * ux + uy * uy + uz * uz;
+    const double uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double cu = E3X[i] * ux + E3Y[i] * uy + E3Z[i] * uz;
+      const double cF = E3X[i] * Fx + E3Y[i] * Fy + E3Z[i] * Fz;
+      const double fe = w3<double, Q>(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
+      const double fi = w3<double, Q>(i) * a.L.pre * (3.0 * cF + 9.0 * cu * cF - 3.0 * uF);
+      f[i] = f[i] - (f[i] - fe) / a.L.tau + fi;
+    }
+  } else {
+    const float dr = rho;
+    rho = a.L.rho0_f + dr;
+    const float ir = __builtin_amdgcn_rcpf(rho);
+    const float Fx = a.L.F_f[0], Fy = a.L.F_f[1], Fz = a.L.F_f[2];
+    const float ux = (jx + 0.5f * Fx) * ir, uy = (jy + 0.5f * Fy) * ir, uz = (jz + 0.5f * Fz) * ir;
+    const float usq = ux * ux + uy * uy + uz * uz;
+    const float A = dr - rho * (1.5f * usq);
+    const bool forced = Fx != 0.f || Fy != 0.f || Fz != 0.f;
+    const float uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float cu = E3X[i] * ux + E3Y[i] * uy + E3Z[i] * uz;
+      const float de = w3<float, Q>(i) * fmaf(rho * cu, fmaf(4.5f, cu, 3.0f), A);
+      float v = fmaf(a.L.om_f, de - f[i], f[i]);
+      if (forced) {
+        const float cF = E3X[i] * Fx + E3Y[i] * Fy + E3Z[i] * Fz;
+        v += w3<float, Q>(i) * a.L.pre_f * (3.f * cF + 9.f * cu * cF - 3.f * uF);
+      }
+      f[i] = v;
+    }
+  }
+  if (!(rho == rho) || rho > C(1e30) || rho < C(-1e30)) atomicOr(a.err, sbt::ERR_NONFINITE);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) dst[((size_t)b * Q + i) * kC3 + cell] = S::st(f[i]);
+}
+
+// A halo cell of the level (first of a fine level's two substeps): streamed,
+// never collided; a source outside the level's blocks gives NaN.
+template <int ST, int Q>
+__device__ __forceinline__ void band3(const Args3 &a, int packed) {
+  using S = Store3<ST>;
+  using T = typename S::T;
+  using C = Calc3<ST>;
+  const int b = packed >> 9, cell = packed & (kC3 - 1);
+  const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
+  const T *src = static_cast<const T *>(a.src);
+  T *dst = static_cast<T *>(a.dst);
+  const int32_t *nbr = a.meta[b].nbr;
+  int nb[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) nb[i] = nbr[nbr_slot(x - E3X[i], y - E3Y[i], z - E3Z[i])];
+  T g[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {  // an absent block reads the cell's own block; NaN replaces the value
+    const T v = src[((size_t)(nb[i] < 0 ? b : nb[i]) * Q + i) * kC3 + wrap_cell(x - E3X[i], y - E3Y[i], z - E3Z[i])];
+    g[i] = nb[i] < 0 ? S::st(C(__builtin_nan(""))) : v;
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) dst[((size_t)b * Q + i) * kC3 + cell] = g[i];
+}
+
+// MODE: 0 step (interior blocks first, then the rest, then halo cells),
+// M3_LOCAL, M3_READOUT or both.
+template <int ST, int Q, int MODE>
 __global__ __launch_bounds__(kC3) void forest3_kernel(Args3 a) {
+  const int n_bg = (a.n_band + kC3 - 1) / kC3;
+  const int w = remap3(blockIdx.x, a.n_blocks + n_bg, a.n_fast, a.xcd);
+  if (w < 0) return;
+  if (w >= a.n_blocks) {
+    const int idx = (w - a.n_blocks) * kC3 + threadIdx.x;
+    if (idx < a.n_band) band3<ST, Q>(a, a.band[idx]);
+    return;
+  }
+  const int b = __builtin_amdgcn_readfirstlane(a.list[w]);
+  if constexpr (MODE == 0) {
+    if (w < a.n_fast) {
+      interior3<ST, Q>(a, b, threadIdx.x);
+      return;
+    }
+  }
+  // the block's table and the neighbour tables of the 8 finer blocks under
+  // its octants (coalescence), in LDS
   __shared__ Blk3 sk;
-  __shared__ double red[4][kC3];
-  const int w = remap3(blockIdx.x, gridDim.x, a.xcd);
-  const int b = a.list[w];
-  if (threadIdx.x < kBlkInts)
-    reinterpret_cast<int32_t *>(&sk)[threadIdx.x] = reinterpret_cast<const int32_t *>(a.meta + b)[threadIdx.x];
+  __shared__ int32_t cnb[8][27];
+  const int t = threadIdx.x;
+  if (t < kBlkInts) reinterpret_cast<int32_t *>(&sk)[t] = reinterpret_cast<const int32_t *>(a.meta + b)[t];
+  if (t >= 64 && t < 64 + 8 * 27) {
+    const int o = (t - 64) / 27, sl = (t - 64) % 27;
+    const int cb = a.fmeta ? a.meta[b].child[o] : -1;
+    cnb[o][sl] = cb >= 0 ? a.fmeta[cb].nbr[sl] : -1;
+  }
   __syncthreads();
   double part[4] = {0.0, 0.0, 0.0, 0.0};
-  cell3<ST, Q>(a, sk, b, w, threadIdx.x, part);
-  if (a.mode & M3_READOUT) {  // fixed-order tree over the block's cells
+  Args3 m = a;
+  m.mode = MODE;
+  cell3<ST, Q>(m, sk, cnb, b, w, t, part);
+  if constexpr ((MODE & M3_READOUT) != 0) {  // fixed-order tree over the block's cells
+    __shared__ double red[4][kC3];
 #pragma unroll
     for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = part[q];
     __syncthreads();
@@ -389,10 +533,29 @@ __global__ __launch_bounds__(kC3) void init3f_kernel(const int32_t *list, const 
   }
 }
 
+// Workgroups of a launch over n list entries: with the XCD remap, 8 times
+// the largest share of one XCD.
+int grid3(int n, int n_fast, int remap) {
+  if (!remap) return n;
+  int most = 0;
+  for (int x = 0; x < 8; ++x) {
+    const int ns = n - n_fast;
+    most = std::max(most, (ns * (x + 1) / 8 - ns * x / 8) + (n_fast * (x + 1) / 8 - n_fast * x / 8));
+  }
+  return 8 * most;
+}
+
 template <int ST, int Q>
-hipError_t launch_forest3(const Args3 &a, int n, hipStream_t s) {
+hipError_t launch_forest3(const Args3 &a, hipStream_t s) {
+  const int n = grid3(a.n_blocks + (a.n_band + kC3 - 1) / kC3, a.n_fast, a.xcd);
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((forest3_kernel<ST, Q>), dim3(n), dim3(kC3), 0, s, a);
+  switch (a.mode) {
+    case 0: hipLaunchKernelGGL((forest3_kernel<ST, Q, 0>), dim3(n), dim3(kC3), 0, s, a); break;
+    case M3_LOCAL: hipLaunchKernelGGL((forest3_kernel<ST, Q, M3_LOCAL>), dim3(n), dim3(kC3), 0, s, a); break;
+    case M3_READOUT: hipLaunchKernelGGL((forest3_kernel<ST, Q, M3_READOUT>), dim3(n), dim3(kC3), 0, s, a); break;
+    default:
+      hipLaunchKernelGGL((forest3_kernel<ST, Q, M3_LOCAL | M3_READOUT>), dim3(n), dim3(kC3), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -404,20 +567,20 @@ hipError_t launch_init3f(const int32_t *list, int n, const Blk3 *meta, const uin
   return hipGetLastError();
 }
 
-hipError_t forest3_dispatch(int st, int q, const Args3 &a, int n, hipStream_t s) {
+hipError_t forest3_dispatch(int st, int q, const Args3 &a, hipStream_t s) {
   if (q == 19) {
     switch (st) {
-      case 0: return launch_forest3<0, 19>(a, n, s);
-      case 1: return launch_forest3<1, 19>(a, n, s);
-      case 2: return launch_forest3<2, 19>(a, n, s);
-      default: return launch_forest3<3, 19>(a, n, s);
+      case 0: return launch_forest3<0, 19>(a, s);
+      case 1: return launch_forest3<1, 19>(a, s);
+      case 2: return launch_forest3<2, 19>(a, s);
+      default: return launch_forest3<3, 19>(a, s);
     }
   }
   switch (st) {
-    case 0: return launch_forest3<0, 27>(a, n, s);
-    case 1: return launch_forest3<1, 27>(a, n, s);
-    case 2: return launch_forest3<2, 27>(a, n, s);
-    default: return launch_forest3<3, 27>(a, n, s);
+    case 0: return launch_forest3<0, 27>(a, s);
+    case 1: return launch_forest3<1, 27>(a, s);
+    case 2: return launch_forest3<2, 27>(a, s);
+    default: return launch_forest3<3, 27>(a, s);
   }
 }
 
@@ -767,6 +930,9 @@ constexpr int kStageBlocks = 2048;
 
 struct Pool3 {
   int n_own = 0, n_halo = 0, code_rows = 0;
+  int n_fast = 0;            // interior blocks: the first n_fast entries of the list
+  int32_t *d_band = nullptr; // halo cells: pool block * 512 + cell
+  int n_band = 0;
   Blk3 *d_meta = nullptr;
   uint32_t *d_codes = nullptr;
   int32_t *d_list = nullptr;
@@ -827,6 +993,8 @@ size_t layout(sbt3f_ctx &X, char *base, const std::vector<std::vector<Blk3>> &me
     P.d_meta = cv.take<Blk3>(n * sizeof(Blk3));
     P.d_codes = cv.take<uint32_t>(std::max<size_t>(1, codes[l].size()) * 4);
     P.d_list = cv.take<int32_t>(n * 4);
+    P.n_band = (int)H.n_ghost;
+    P.d_band = cv.take<int32_t>(std::max<size_t>(1, (size_t)P.n_band) * 4);
   }
   const int sb = std::min(kStageBlocks, max_pool);
   X.d_stage = cv.take<double>((size_t)sb * 4 * kC3 * 8);
@@ -885,8 +1053,9 @@ void rec3(int l, int V, std::vector<std::pair<int, int>> &out) {
   out.push_back({l, 2});
 }
 
-// One launch of level l over n blocks of `list` (pool indices).
-sbt_status launch_level3(sbt3f_ctx &X, int l, const int32_t *list, int n, int mode, bool flip) {
+// One launch of level l over n blocks of `list` (pool indices) and, in a
+// step launch, n_band halo cells.
+sbt_status launch_level3(sbt3f_ctx &X, int l, const int32_t *list, int n, int mode, bool flip, int n_band = 0) {
   Pool3 &P = X.pools[l];
   Args3 a{};
   a.meta = P.d_meta;
@@ -903,23 +1072,26 @@ sbt_status launch_level3(sbt3f_ctx &X, int l, const int32_t *list, int n, int mo
     a.fcur = F.lat[F.cur];
   }
   a.list = list;
+  a.n_blocks = n;
+  a.n_fast = mode == 0 ? P.n_fast : 0;
+  a.band = P.d_band;
+  a.n_band = mode == 0 ? n_band : 0;
   a.mode = mode;
-  a.xcd = 1;
+  a.xcd = mode == 0 ? 1 : 0;
   a.L = P.L;
   a.out = X.d_stage;
   a.part = X.d_part;
   a.err = X.d_err;
-  HIPCHK3(forest3_dispatch(X.storage, X.q, a, n, X.stream));
+  HIPCHK3(forest3_dispatch(X.storage, X.q, a, X.stream));
   if (flip) P.cur ^= 1;
   return SBT_OK;
 }
 
-// Substep p (1 or 2) of level l: the owned blocks, and in the first of a
-// fine level's two substeps the halo blocks too (they gather their halo
-// cells).
+// Substep p (1 or 2) of level l: the blocks with owned cells, and in the
+// first of a fine level's two substeps its halo cells.
 sbt_status substep3(sbt3f_ctx &X, int l, int p) {
   Pool3 &P = X.pools[l];
-  return launch_level3(X, l, P.d_list, P.n_own + ((p == 1 && l > 0) ? P.n_halo : 0), 0, true);
+  return launch_level3(X, l, P.d_list, P.n_own, 0, true, (p == 1 && l > 0) ? P.n_band : 0);
 }
 
 // The first collision of every level from the initial pre-collision state,
@@ -1033,8 +1205,25 @@ sbt_status sbt3f_create(const sbt3f_desc *desc, void *device_buf, size_t bytes, 
   for (int l = 0; l < X->fo.m; ++l) {
     Pool3 &P = X->pools[l];
     const size_t n = (size_t)P.n_own + P.n_halo;
-    std::vector<int32_t> list(n);
-    for (size_t i = 0; i < n; ++i) list[i] = (int32_t)i;
+    // launch order: interior blocks, the other blocks with owned cells, halo blocks
+    std::vector<int32_t> list;
+    list.reserve(n);
+    for (int i = 0; i < P.n_own; ++i)
+      if (metas[l][i].code < 0) list.push_back(i);
+    P.n_fast = (int)list.size();
+    for (int i = 0; i < P.n_own; ++i)
+      if (metas[l][i].code >= 0) list.push_back(i);
+    for (size_t i = P.n_own; i < n; ++i) list.push_back((int32_t)i);
+    std::vector<int32_t> band;
+    band.reserve(P.n_band);
+    for (size_t i = P.n_own; i < n; ++i) {
+      const int32_t code = metas[l][i].code;
+      for (int c = 0; c < kC3; ++c)
+        if (codes[l][(size_t)code * kC3 + c] & K3_BAND) band.push_back((int32_t)(i * kC3 + c));
+    }
+    if ((int)band.size() != P.n_band) return cleanup(fail3(SBT_ERR_STATE, "halo cell count mismatch"));
+    if (!band.empty() && hipMemcpyAsync(P.d_band, band.data(), band.size() * 4, hipMemcpyHostToDevice, X->stream) != hipSuccess)
+      return cleanup(fail3(SBT_ERR_DEVICE, "upload of the halo cells failed"));
     if (hipMemcpyAsync(P.d_meta, metas[l].data(), n * sizeof(Blk3), hipMemcpyHostToDevice, X->stream) != hipSuccess ||
         (!codes[l].empty() && hipMemcpyAsync(P.d_codes, codes[l].data(), codes[l].size() * 4, hipMemcpyHostToDevice,
                                              X->stream) != hipSuccess) ||
@@ -1150,7 +1339,6 @@ sbt_status sbt3f_read_box(sbt3f_ctx *ctx, int32_t level, const int32_t box[6], d
   sbt3f_ctx &X = *ctx;
   const size_t nc = (size_t)box[3] * box[4] * box[5];
   for (size_t i = 0; i < nc; ++i) rho[i] = ux[i] = uy[i] = uz[i] = __builtin_nan("");
-  Pool3 &P = X.pools[level];
   const LevelHost &H = X.fo.L[level];
   const std::vector<int32_t> blocks = blocks_in_box(X, level, box);
   const int sb = stage_blocks(X);
