@@ -11,6 +11,7 @@ a bounded sample of the same workload.
 import argparse
 import hashlib
 import json
+import subprocess
 import math
 import os
 import sys
@@ -39,6 +40,10 @@ def workload_list(name):
         return [W.pitch_up_plate()], "pitch_up_plate_1120x640_3levels_chord64_ramp"
     if name == "pitching_airfoil":
         return [W.pitching_airfoil()], "pitching_airfoil_1120x640_3levels_chord64_tri"
+    if name == "tgv64":
+        return [W.tgv(64, tau=0.8, u0=0.02)], "tgv_64x64_single_level"
+    if name == "flap_re1000":
+        return [W.flapping_ellipse(Re=1000.0)], "flapping_ellipse_512x256_4levels_200markers_re1000"
     if name == "tgv8192":
         return [W.tgv(8192, tau=0.8, u0=0.02)], "tgv_8192x8192_single_level"
     raise SystemExit(f"unknown workload {name}")
@@ -115,32 +120,68 @@ def time_form(P, wls, storage, steps, warmup, tile=None, autotune=False):
     return sim, dt, ups
 
 
-def cpu_baseline(wls, budget_s, V):
-    """The FP64 oracle on the smallest cases of the workload, one batch step
-    (2^(V-m) coarse steps) each, until the time budget is used."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_rate(wls, budget_s, V, per_case=8):
+    """(cell updates, seconds, cases used) of the FP64 oracle on the cases of
+    the workload, smallest first, each for whole batch steps (2^(V-m) coarse
+    steps) until budget_s / per_case is used on it (at least one), until the
+    budget is used.  Only stepping is timed (the oracle's set-up of its dense
+    per-level arrays is not)."""
     import oracle
-    order = sorted(range(len(wls)), key=lambda c: wls[c].nx0 * 4 ** wls[c].n_levels)
-    done, ups, t_used = [], 0, 0.0
+    order = sorted(range(len(wls)), key=lambda c: wls[c].nx0 * wls[c].ny0 * 4 ** wls[c].n_levels)
+    ups, t_used, used = 0, 0.0, []
     for c in order:
         wl = wls[c]
         o = oracle.OracleSim(wl)
         n = 2 ** (V - wl.n_levels)
-        cells = 0
-        for l in range(wl.n_levels):
-            k = o.kinds(l)
-            cells += int((k == 1).sum()) * 2 ** l
-        t0 = time.perf_counter()
-        o.step(n)
-        t_used += time.perf_counter() - t0
-        ups += cells * n
-        done.append(c)
+        cells = sum(int((o.kinds(l) == 1).sum()) * 2 ** l for l in range(wl.n_levels))
+        t_case = 0.0
+        while t_case < budget_s / per_case or t_case == 0.0:
+            t0 = time.perf_counter()
+            o.step(n)
+            t_case += time.perf_counter() - t0
+            ups += cells * n
+        t_used += t_case
+        used.append(c)
         del o
         if t_used >= budget_s:
             break
-    return dict(value=round(ups / t_used / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"cases {done} of the same workload, one batch step each "
-                       f"({ups} cell updates in {t_used:.1f} s), FP64, OpenMP")
+    return ups, t_used, used
+
+
+def cpu_baseline(wls, budget_s, V, name, mrt=False):
+    """The FP64 oracle on every case of the workload (whole batch steps of
+    each, the budget split evenly over the cases), on all the host's threads
+    and, in a child process, on one thread."""
+    import oracle
+    ups, t_used, used = _oracle_rate(wls, budget_s, V)
+    out = dict(value=round(ups / t_used / 1e6, 3), unit="MLUPS", cores=oracle.num_threads(),
+               kind="oracle", host_cpus=os.cpu_count(), cpu_model=_cpu_model(),
+               sample=f"cases {used} of the same workload (smallest first), whole batch steps each, "
+                      f"{ups} cell updates in {t_used:.1f} s of stepping, FP64, OpenMP")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = ("import json, sys; sys.path.insert(0, %r); import bench, workloads as W; "
+            "w, _ = bench.workload_list(%r); w = [c.replace(collision=W.COLL_MRT) for c in w] if %r else w; "
+            "u, t, c = bench._oracle_rate(w, %r, %d); print(json.dumps([u, t]))") % (ROOT, name, mrt, budget_s / 2, V)
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                           timeout=60 + 4 * budget_s)
+        u1, t1 = json.loads(r.stdout.strip().splitlines()[-1])
+        out["single_thread_value"] = round(u1 / t1 / 1e6, 3)
+        out["single_thread_sample"] = f"smallest cases of the same workload, {u1} cell updates in {t1:.1f} s on 1 thread"
+    except Exception as e:  # the single-thread figure is informative only
+        out["single_thread_value"] = None
+        out["single_thread_error"] = str(e)[:200]
+    return out
 
 
 def bench3d(args, P, W):
@@ -417,7 +458,7 @@ def main():
         "forms": forms,
     }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wls, args.cpu_budget, V)
+        out["cpu_baseline"] = cpu_baseline(wls, args.cpu_budget, V, args.workload, args.collision == "mrt")
     print(json.dumps(out), flush=True)
 
 

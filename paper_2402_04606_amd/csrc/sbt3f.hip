@@ -82,6 +82,7 @@ struct Args3 {
   int32_t n_band;
   int32_t mode;
   int32_t xcd;
+  int32_t off32;        // the lattice read is under 4 GiB: 32-bit byte offsets
   Lev3 L;
   double *out;          // readout [n][4][512]: rho, ux, uy, uz
   double *part;         // readout [n][4]: mass, jx, jy, jz of the block's owned cells
@@ -344,7 +345,7 @@ typedef __attribute__((address_space(4))) const int32_t ci32_3;
 // through scalar loads; each lane picks its source block per direction with
 // selects among the (at most 8) candidates the direction can reach, so the Q
 // loads issue back to back.
-template <int ST, int Q>
+template <int ST, int Q, bool O32>
 __device__ __forceinline__ void interior3(const Args3 &a, int b, int cell) {
 #pragma clang fp contract(off)
   using S = Store3<ST>;
@@ -374,7 +375,10 @@ __device__ __forceinline__ void interior3(const Args3 &a, int b, int cell) {
     const int q0 = oy ? p10 : p00, q1 = oy ? p11 : p01;
     const int blk = oz ? q1 : q0;
     const uint32_t off = ((uint32_t)blk * Q + i) * kC3 + (uint32_t)wrap_cell(x - cx, y - cy, z - cz);
-    f[i] = (C)S::ld(src[off]);
+    if constexpr (O32)  // pool under 4 GiB: a 32-bit byte offset from the scalar base, one VGPR per load
+      f[i] = (C)S::ld(*reinterpret_cast<const T *>(reinterpret_cast<const char *>(src) + off * (uint32_t)sizeof(T)));
+    else
+      f[i] = (C)S::ld(src[off]);
   }
   C rho = C(0), jx = C(0), jy = C(0), jz = C(0);
 #pragma unroll
@@ -464,7 +468,8 @@ __global__ __launch_bounds__(kC3) void forest3_kernel(Args3 a) {
   const int b = __builtin_amdgcn_readfirstlane(a.list[w]);
   if constexpr (MODE == 0) {
     if (w < a.n_fast) {
-      interior3<ST, Q>(a, b, threadIdx.x);
+      if (a.off32) interior3<ST, Q, true>(a, b, threadIdx.x);
+      else interior3<ST, Q, false>(a, b, threadIdx.x);
       return;
     }
   }
@@ -1078,6 +1083,7 @@ sbt_status launch_level3(sbt3f_ctx &X, int l, const int32_t *list, int n, int mo
   a.n_band = mode == 0 ? n_band : 0;
   a.mode = mode;
   a.xcd = mode == 0 ? 1 : 0;
+  a.off32 = ((size_t)P.n_own + P.n_halo) * X.q * kC3 * stor_bytes3(X.storage) < ((size_t)1 << 32);
   a.L = P.L;
   a.out = X.d_stage;
   a.part = X.d_part;
