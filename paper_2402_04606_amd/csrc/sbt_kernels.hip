@@ -566,6 +566,43 @@ __device__ __forceinline__ typename Store<ST>::C coalesce(const LevelArgs &a, co
   return C(0.25) * sum;
 }
 
+// The same mean, for a block whose 4 finer blocks' neighbour tables sit in
+// LDS: cn[c * 9 + d] = neighbour d (the block table's order) of the finer
+// block under quadrant c = (x >= 8) + 2 (y >= 8), cn[c * 9 + 8] = that block
+// (-1 if none).  The 4 loads are issued together (a missing block reads
+// block 0 and is replaced by NaN after the load), so a coalesced direction
+// costs one memory round trip.
+__device__ __forceinline__ int nbr_dir(int x, int y) {
+  if (x < 0) return y < 0 ? 6 : (y > 15 ? 5 : 2);
+  if (x > 15) return y < 0 ? 7 : (y > 15 ? 4 : 0);
+  if (y < 0) return 3;
+  if (y > 15) return 1;
+  return 8;
+}
+
+template <int ST>
+__device__ __forceinline__ typename Store<ST>::C coalesce_lds(const LevelArgs &a, const int *cn, int x, int y,
+                                                               int q) {
+#pragma clang fp contract(off)
+  using C = typename Store<ST>::C;
+  const int c = (x >= 8) + 2 * (y >= 8);
+  const int fx0 = (2 * x) & 15, fy0 = (2 * y) & 15;
+  C v[4];
+  bool miss[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int sx = fx0 + (s & 1) - CX[q], sy = fy0 + (s >> 1) - CY[q];
+    const int nb = cn[c * 9 + nbr_dir(sx, sy)];
+    miss[s] = nb < 0;
+    v[s] = ldv<ST>(a.fprev, nb < 0 ? 0 : nb, q, (sy & 15) * 16 + (sx & 15));
+  }
+  C sum = miss[0] ? C(__builtin_nan("")) : v[0];
+  sum += miss[1] ? C(__builtin_nan("")) : v[1];
+  sum += miss[2] ? C(__builtin_nan("")) : v[2];
+  sum += miss[3] ? C(__builtin_nan("")) : v[3];
+  return C(0.25) * sum;
+}
+
 // Interpolated bounce-back (linear Bouzidi form, resting wall) of pulled
 // direction i at cell (x, y) of block k, whose source x - c_i is solid: the
 // population o = opposite(i) that the cell sent toward the wall, at wall
@@ -1021,7 +1058,7 @@ __device__ __forceinline__ void commit_tile(typename Store<ST>::T *buf, typename
 template <int ST, bool SLOW>
 __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev *__restrict__ cases, const Blk &k,
                                               const typename Store<ST>::T *tile, double ibm_fx, double ibm_fy,
-                                              uint16_t code_in = 0) {
+                                              uint16_t code_in = 0, const int *cn = nullptr) {
 #pragma clang fp contract(off)
   using S = Store<ST>;
   using T = typename S::T;
@@ -1059,7 +1096,7 @@ __device__ __forceinline__ void compute_block(const LevelArgs &a, const CaseDev 
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       if (code & (1u << i)) {
-        f[i] = coalesce<ST>(a, k, x, y, i);
+        f[i] = coalesce_lds<ST>(a, cn, x, y, i);
       } else if (edge) {
         int sx = gx - CX[i], sy = gy - CY[i];
         bool out = (!ep.per_x() && (sx < 0 || sx >= ep.nx)) || (!ep.per_y() && (sy < 0 || sy >= ep.ny));
@@ -1231,13 +1268,22 @@ __global__ __launch_bounds__(256) void level_tile_kernel(LevelArgs a, const Case
     return;
   }
   if (role == 1) {
+    __shared__ int cn[36];  // the finer blocks' neighbour tables (coalescence)
     const Blk k = load_blk(meta, list[a.n_fast + w]);
     double fx, fy;
     ibm_force_of<ST>(a, cases, k, fx, fy);
+    int cv = -1;
+    if ((k.flags & BF_CODES) && a.fmeta && threadIdx.x < 36) {
+      const int c = threadIdx.x / 9, d = threadIdx.x % 9;
+      const int cb = c == 0 ? k.c0 : (c == 1 ? k.c1 : (c == 2 ? k.c2 : k.c3));
+      cv = cb < 0 ? -1 : (d == 8 ? cb : a.fmeta[cb].nbr[d]);
+    }
     fetch_tile<ST>(a, k, bufA, h, he);
     const uint16_t code = (k.flags & BF_CODES) ? a.codes[(size_t)k.code * kCells + threadIdx.x] : (uint16_t)0;
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the table entry (and the copies) have landed
+    if (threadIdx.x < 36) cn[threadIdx.x] = cv;
     commit_tile<ST>(bufA, h);
-    compute_block<ST, true>(a, cases, k, bufA, fx, fy, code);
+    compute_block<ST, true>(a, cases, k, bufA, fx, fy, code, cn);
   } else if (role == 2) {
     int idx = w * 256 + threadIdx.x;
     if (idx < a.n_band) band_cell<ST>(a, a.band[idx]);
