@@ -34,6 +34,11 @@ struct Params {
   double uw[2][3];             // bottom and top wall velocities (walls across z)
   const double *ibm_F;         // immersed body: force density [3][box] over its current box, or null
   const int *ibm_box;          // [6] that box: origin x, y, z and size x, y, z
+  // the body force of the forcing loop that precedes this launch, summed by
+  // the launch's first workgroup beside the cells' work (fs_n = 0: none)
+  const double *fs_ft, *fs_dA; // [3][n] total marker force of the loop, [n] surface elements
+  double *fs_out;              // [3] F_s = -sum_j F_j dA_j, marker order
+  int fs_n;
   float om_f, pre_f, rho0_f, F_f[3];
 };
 
@@ -135,13 +140,48 @@ __device__ __forceinline__ double wall_term(const Params &p, int i) {
   return 6.0 * w3<double, Q>(i) * p.rho0 * cu;
 }
 
+// F_s = -sum_j F_j dA_j of the forcing loop that precedes the launch, in
+// marker order (Eq. (16) in 3D): the products formed in parallel 256 at a
+// time, then summed in order by one lane per component.
+__device__ __forceinline__ void body_force_sum(const Params &p) {
+#pragma clang fp contract(off)
+  __shared__ double s_prod[3][kThreads];
+  const int tid = threadIdx.x, n = p.fs_n;
+  double fsum = 0.0;
+  for (int j0 = 0; j0 < n; j0 += kThreads) {
+    const int j = j0 + tid;
+    if (j < n)
+      for (int a = 0; a < 3; ++a) s_prod[a][tid] = p.fs_ft[a * n + j] * p.fs_dA[j];
+    __syncthreads();
+    if (tid < 3) {
+      const int m = min(kThreads, n - j0);
+      int i = 0;
+      for (; i + 8 <= m; i += 8) {  // loads ahead of the (ordered) subtractions
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = s_prod[tid][i + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) fsum -= v[q];
+      }
+      for (; i < m; ++i) fsum -= s_prod[tid][i];
+    }
+    __syncthreads();
+  }
+  if (tid < 3) p.fs_out[tid] = fsum;
+}
+
 template <int ST, int kQ3>
 __global__ __launch_bounds__(kThreads) void step3_kernel(Params p, const void *src_, void *dst_, int pull,
                                                          int *err) {
 #pragma clang fp contract(off)
   using S = Store3<ST>;
   using T = typename S::T;
-  const long long c = (long long)blockIdx.x * kThreads + threadIdx.x;
+  const int fsw = p.fs_n > 0;  // workgroup 0 sums the body force (it starts first)
+  if (fsw && blockIdx.x == 0) {
+    body_force_sum(p);
+    return;
+  }
+  const long long c = (long long)(blockIdx.x - fsw) * kThreads + threadIdx.x;
   if (c >= p.n) return;
   const T *src = static_cast<const T *>(src_);
   T *dst = static_cast<T *>(dst_);
@@ -263,7 +303,7 @@ struct Ibm3 {
   double *Fbox;                // [3][K] force density the step kernel adds
   int *box;                    // [6] the box: origin and size (size 0: no force this step)
   int *lohi;                   // [6] tap bounds reduced over the markers
-  double *fs;                  // [6]: [3..5] F_s of the previous forcing loop
+  double *fs;                  // [2][3] F_s of forcing loop L in slot L & 1
   int *err;                    // bit 2: the box outgrew cap or left the lattice
 };
 
@@ -314,51 +354,15 @@ __device__ __forceinline__ void marker3(const Ibm3 &b, const Pose3 &q, int j, do
 __device__ __forceinline__ long long box_cells(const int *B) { return (long long)B[3] * B[4] * B[5]; }
 
 // Sec. 2.2 in 3D, the forcing loop before the collision of step t, as a
-// chain of launches on the stream: ibm3_fs_kernel (F_s of the previous
-// loop), ibm3_markers_kernel (markers, desired velocities, 4x4x4 taps with
-// weight phi_x (phi_y phi_z)), ibm3_box_kernel (the box they cover),
-// ibm3_moments_kernel (rho, u of the box cells from the state the step
-// collides), then N_F times ibm3_interp_kernel (U_j, rho_j over the taps,
-// z outer, y, x inner; g_j = 2 rho_j (u_d - U_j)) and ibm3_spread_kernel
-// (each box cell sums g_j phi dA_j over the markers in marker order, then
-// F += dF, u += dF / (2 rho)).
-constexpr int kPoseThreads = 1024;
-
-// F_s of the previous loop, -sum_j F_j dA_j in marker order, into fs[3..5]
-// (the step about to run is one ahead of the readouts): the products are
-// formed in parallel chunk by chunk and summed in order by one thread per
-// component.  Also resets the box bounds the marker kernel reduces into.
-__global__ __launch_bounds__(kPoseThreads) void ibm3_fs_kernel(Ibm3 b) {
-#pragma clang fp contract(off)
-  __shared__ double s_prod[3][kPoseThreads];
-  const int tid = threadIdx.x, nt = kPoseThreads, n = b.n;
-  double fsum = 0.0;
-  for (int j0 = 0; j0 < n; j0 += nt) {
-    const int j = j0 + tid;
-    if (j < n)
-      for (int a = 0; a < 3; ++a) s_prod[a][tid] = b.ft[a * n + j] * b.dA[j];
-    __syncthreads();
-    if (tid < 3) {
-      const int m = min(nt, n - j0);
-      int i = 0;
-      for (; i + 8 <= m; i += 8) {  // loads ahead of the (ordered) subtractions
-        double v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) v[q] = s_prod[tid][i + q];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) fsum -= v[q];
-      }
-      for (; i < m; ++i) fsum -= s_prod[tid][i];
-    }
-    __syncthreads();
-  }
-  if (tid < 3) {
-    b.fs[3 + tid] = fsum;
-    b.lohi[tid] = 1 << 30;
-    b.lohi[3 + tid] = -(1 << 30);
-  }
-}
-
+// chain of launches on the stream: ibm3_markers_kernel (markers, desired
+// velocities, 4x4x4 taps with weight phi_x (phi_y phi_z)), ibm3_box_kernel
+// (the box they cover; it also resets the bounds for the next loop),
+// ibm3_moments_kernel (rho, u of the box cells from
+// the state the step collides), then N_F times ibm3_interp_kernel (U_j,
+// rho_j over the taps, z outer, y, x inner; g_j = 2 rho_j (u_d - U_j)) and
+// ibm3_spread_kernel (each box cell sums g_j phi dA_j over the markers in
+// marker order, then F += dF, u += dF / (2 rho)).  The loop's body force F_s is summed by the first
+// workgroup of the step kernel that follows it.
 // Marker j at step t: position, desired velocity, taps and weights; clears
 // its force total; the workgroup's tap bounds go into lohi.
 __global__ __launch_bounds__(kThreads) void ibm3_markers_kernel(Pose3 q0, Pose3 q1, Ibm3 b) {
@@ -416,16 +420,23 @@ __global__ __launch_bounds__(64) void ibm3_box_kernel(Params p, Ibm3 b) {
     K *= hi - lo;
     bad |= lo < 0 || hi > dims[a];
   }
+  int box[6] = {0, 0, 0, 0, 0, 0};
   if (bad || K > b.cap) {
     atomicOr(b.err, 2);
+  } else {
 #pragma unroll
-    for (int a = 0; a < 6; ++a) b.box[a] = 0;
-    return;
+    for (int a = 0; a < 3; ++a) {
+      box[a] = b.lohi[a];
+      box[3 + a] = b.lohi[3 + a] - b.lohi[a];
+    }
   }
 #pragma unroll
+  for (int a = 0; a < 6; ++a) b.box[a] = box[a];
+  // the bounds start over for the next loop's marker kernel
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    b.box[a] = b.lohi[a];
-    b.box[3 + a] = b.lohi[3 + a] - b.lohi[a];
+    b.lohi[a] = 1 << 30;
+    b.lohi[3 + a] = -(1 << 30);
   }
 }
 
@@ -496,15 +507,17 @@ __global__ __launch_bounds__(kThreads) void ibm3_interp_kernel(Ibm3 b) {
 
 // One pass's spreading, markers in order.  A one-wave workgroup takes 4x4x4
 // tiles of the box (grid-stride).  For each tile it stages the taps of up to
-// kSpBlock markers in LDS at once, keeps (64 at a time, in marker order) the
-// markers whose 4x4x4 stencil reaches the tile, stages their weights, g_j
-// and dA_j, and each cell sums over that list.
+// kSpBlock markers in LDS at once and lists, in marker order, the markers
+// whose 4x4x4 stencil reaches the tile (no global load in this scan); then
+// it stages the listed markers' weights, g_j and dA_j 64 at a time (one
+// round of loads per 64 listed markers) and each cell sums over them.
 constexpr int kSpThreads = 64, kSpTx = 4, kSpTy = 4, kSpTz = kSpThreads / (kSpTx * kSpTy), kSpBlock = 1024;
 static_assert(kSpTz * kSpTx * kSpTy == kSpThreads && kSpThreads == 64, "one wave, one cell per lane");
 
 __global__ __launch_bounds__(kSpThreads) void ibm3_spread_kernel(Ibm3 b) {
 #pragma clang fp contract(off)
   __shared__ int s_tap[3][kSpBlock];
+  __shared__ int s_rel[kSpBlock];
   __shared__ int s_t[3][kSpThreads];
   __shared__ double s_phi[12][kSpThreads];
   __shared__ double s_g[3][kSpThreads];
@@ -541,27 +554,38 @@ __global__ __launch_bounds__(kSpThreads) void ibm3_spread_kernel(Ibm3 b) {
         }
       }
       __syncthreads();
+      // the markers of this block that reach the tile, in marker order
+      int cnt = 0;
       for (int c0 = 0; c0 < bn; c0 += kSpThreads) {
         const int i = c0 + lane;
         bool f = false;
-        int tx = 0, ty = 0, tz = 0;
         if (i < bn) {
-          tx = s_tap[0][i];
-          ty = s_tap[1][i];
-          tz = s_tap[2][i];
+          const int tx = s_tap[0][i], ty = s_tap[1][i], tz = s_tap[2][i];
           f = tx <= xhi && tx + 3 >= xlo && ty <= yhi && ty + 3 >= ylo && tz <= zhi && tz + 3 >= zlo;
         }
         const unsigned long long m = __ballot(f);
-        if (m == 0ull) continue;  // the whole wave
-        const int total = __popcll(m);
-        if (f) {
-          const int pos = __popcll(m & ((1ull << lane) - 1ull)), jc = b0 + i;
-          s_t[0][pos] = tx;
-          s_t[1][pos] = ty;
-          s_t[2][pos] = tz;
-          for (int q = 0; q < 12; ++q) s_phi[q][pos] = b.phi[q * n + jc];
-          for (int a = 0; a < 3; ++a) s_g[a][pos] = b.g[a * n + jc];
-          s_dA[pos] = b.dA[jc];
+        if (f) s_rel[cnt + __popcll(m & ((1ull << lane) - 1ull))] = i;
+        cnt += __popcll(m);
+      }
+      __syncthreads();
+      for (int g0 = 0; g0 < cnt; g0 += kSpThreads) {
+        const int total = min(kSpThreads, cnt - g0);
+        if (lane < total) {
+          const int i = s_rel[g0 + lane], jc = b0 + i;
+          s_t[0][lane] = s_tap[0][i];
+          s_t[1][lane] = s_tap[1][i];
+          s_t[2][lane] = s_tap[2][i];
+          double w[12], gg[3];
+#pragma unroll
+          for (int q = 0; q < 12; ++q) w[q] = b.phi[q * n + jc];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) gg[a] = b.g[a * n + jc];
+          const double dA = b.dA[jc];
+#pragma unroll
+          for (int q = 0; q < 12; ++q) s_phi[q][lane] = w[q];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) s_g[a][lane] = gg[a];
+          s_dA[lane] = dA;
         }
         __syncthreads();
         if (live) {
@@ -574,9 +598,8 @@ __global__ __launch_bounds__(kSpThreads) void ibm3_spread_kernel(Ibm3 b) {
             d2 += s_g[2][c] * w * s_dA[c];
           }
         }
-        __syncthreads();  // the list is rebuilt by the next chunk
+        __syncthreads();  // the group is restaged by the next one
       }
-      __syncthreads();  // the taps are restaged by the next block
     }
     if (!live || (d0 == 0.0 && d1 == 0.0 && d2 == 0.0)) continue;
     const long long k = ((long long)z * bwy + y) * bwx + x;
@@ -866,7 +889,6 @@ hipError_t launch_ibm(sbt3_ctx &X, int pull) {
   // smaller than cap, and workgroups that find no tile still cost dispatch
   // time, so the grid is capped at two small workgroups per CU
   const dim3 gs((unsigned)std::min<long long>(512, (B.cap + kSpThreads - 1) / kSpThreads));
-  hipLaunchKernelGGL(ibm3_fs_kernel, dim3(1), dim3(kPoseThreads), 0, X.stream, B);
   const Pose3 q0 = B.kind ? pose3(B, (double)X.ibm_t) : Pose3{}, q1 = B.kind ? pose3(B, (double)(X.ibm_t + 1)) : Pose3{};
   hipLaunchKernelGGL(ibm3_markers_kernel, gn, dim3(64), 0, X.stream, q0, q1, B);
   hipLaunchKernelGGL(ibm3_box_kernel, dim3(1), dim3(64), 0, X.stream, X.p, B);
@@ -1037,6 +1059,8 @@ sbt_status sbt3_create(const sbt3_desc *desc_in, void *device_buf, size_t bytes,
     ok &= hipMemcpy(dA, desc->marker_dA, n * 8, hipMemcpyHostToDevice) == hipSuccess;
     ok &= hipMemset(B.box, 0, 6 * 4) == hipSuccess;
     ok &= hipMemset(B.fs, 0, 6 * 8) == hipSuccess;
+    const int lohi0[6] = {1 << 30, 1 << 30, 1 << 30, -(1 << 30), -(1 << 30), -(1 << 30)};
+    ok &= hipMemcpy(B.lohi, lohi0, sizeof lohi0, hipMemcpyHostToDevice) == hipSuccess;
     ok &= hipMemset(B.ft, 0, 3 * n * 8) == hipSuccess;
     if (!ok) {
       delete X;
@@ -1079,19 +1103,33 @@ sbt_status sbt3_init_slab(sbt3_ctx *ctx, int32_t z0, int32_t nz, const double *r
   return SBT_OK;
 }
 
+// The step kernel's launch after forcing loop L (its first workgroup sums
+// that loop's F_s into slot L & 1).
+hipError_t launch_step3(sbt3_ctx &X, int pull) {
+  Params p = X.p;
+  long long wgs = (X.p.n + kThreads - 1) / kThreads;
+  if (X.ibm.n > 0) {
+    p.fs_n = X.ibm.n;
+    p.fs_ft = X.ibm.ft;
+    p.fs_dA = X.ibm.dA;
+    p.fs_out = X.ibm.fs + 3 * ((X.ibm_t - 1) & 1);
+    ++wgs;
+  }
+  return SBT3_LAUNCH(step3_kernel, X.d.storage, X.d.lattice, dim3((unsigned)wgs), X.stream, p,
+                     (const void *)X.lat[X.cur], X.lat[1 - X.cur], pull, X.err);
+}
+
 sbt_status sbt3_step(sbt3_ctx *ctx, int32_t n) {
   if (!ctx || n < 0) return sbt_set_error(SBT_ERR_ARG, "bad argument");
   sbt3_ctx &X = *ctx;
   if (n == 0) return SBT_OK;
-  const dim3 grid((unsigned)((X.p.n + kThreads - 1) / kThreads));
   if (!X.post) {  // collide the initial state in place: the lattice then holds f*
     if (X.ibm.n > 0) {
       X.ibm_t = 0;
       HIP3(launch_ibm(X, 0));
       ++X.ibm_t;
     }
-    HIP3(SBT3_LAUNCH(step3_kernel, X.d.storage, X.d.lattice, grid, X.stream, X.p, (const void *)X.lat[X.cur], X.lat[1 - X.cur], 0,
-                     X.err));
+    HIP3(launch_step3(X, 0));
     X.cur = 1 - X.cur;
     X.post = true;
   }
@@ -1100,8 +1138,7 @@ sbt_status sbt3_step(sbt3_ctx *ctx, int32_t n) {
       HIP3(launch_ibm(X, 1));
       ++X.ibm_t;
     }
-    HIP3(SBT3_LAUNCH(step3_kernel, X.d.storage, X.d.lattice, grid, X.stream, X.p, (const void *)X.lat[X.cur], X.lat[1 - X.cur], 1,
-                     X.err));
+    HIP3(launch_step3(X, 1));
     X.cur = 1 - X.cur;
   }
   return SBT_OK;
@@ -1124,8 +1161,10 @@ sbt_status sbt3_body_force(sbt3_ctx *ctx, double out[3]) {
   if (!ctx || !out) return sbt_set_error(SBT_ERR_ARG, "null argument");
   if (ctx->ibm.n == 0) return sbt_set_error(SBT_ERR_STATE, "no immersed body");
   if (!ctx->post) return sbt_set_error(SBT_ERR_STATE, "no completed step");
-  // the last launch ran the forcing loop of the step after the last completed one
-  HIP3(hipMemcpyAsync(out, ctx->ibm.fs + 3, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  // the last launch ran the forcing loop of the step after the last completed
+  // one: the completed step's loop is the one before it
+  HIP3(hipMemcpyAsync(out, ctx->ibm.fs + 3 * ((ctx->ibm_t - 2) & 1), 3 * sizeof(double), hipMemcpyDeviceToHost,
+                      ctx->stream));
   HIP3(hipStreamSynchronize(ctx->stream));
   // a step whose stencils left the box ran without the body force: its F_s
   // is not a result (the flag stays set for sbt3_synchronize)
