@@ -233,6 +233,20 @@ def bench3d(args, P, W):
                      "bytes_per_update": 2 * q * s, "algorithmic_bytes_per_launch": algo,
                      "avg_launch_us": round(launch_ms * 1e3, 2)},
     }
+    if args.storage != "f64" and not args.no_err:
+        # the same run in FP64 (same steps), compared on three sampled planes
+        total = args.warmup + args.steps
+        ref = P.Sim3(wl, "f64")
+        ref.step(total)
+        ref.synchronize()
+        num = den = 0.0
+        for z in (0, wl.nz // 2, wl.nz - 1):
+            a, b = sim.fields(z, z + 1), ref.fields(z, z + 1)
+            num += sum(float(((a[k] - b[k]) ** 2).sum()) for k in (1, 2, 3))
+            den += sum(float((b[k] ** 2).sum()) for k in (1, 2, 3))
+        ref.close()
+        out["rel_l2_u_vs_f64"] = float(f"{(num / den) ** 0.5:.3e}")
+        out["error_sample"] = f"planes z = 0, {wl.nz // 2}, {wl.nz - 1} after {total} steps, against the FP64 run"
     if not args.no_cpu and args.workload != "flap3d":
         import oracle
         m = 64
@@ -255,6 +269,7 @@ def bench_forest3d(args, P, W):
     forest3d_q27 the same with D3Q27): MLUPS over the cell updates of a
     coarse step (owned cells of level l counted 2^l times) and the bandwidth
     of the step's launches from HIP events on the stream they run on."""
+    import numpy as np
     import torch
     q = 27 if args.workload == "forest3d_q27" else 19
     wl = W.forest3d_bench(lattice=q)
@@ -294,6 +309,23 @@ def bench_forest3d(args, P, W):
                      "bytes_per_update": 2 * q * s, "algorithmic_bytes_per_step": algo,
                      "step_launch_ms": round(step_ms, 4)},
     }
+    if args.storage != "f64" and not args.no_err:
+        total = args.warmup + args.steps
+        sim_steps = total
+        ref = P.Sim3F(wl, "f64")
+        ref.step(sim_steps)
+        ref.synchronize()
+        num = den = 0.0
+        for l in range(wl.n_levels):
+            x0, y0, z0, nx, ny, nz = sim.region_box(l)
+            for z in (z0 + 1, z0 + nz // 2, z0 + nz - 2):
+                a, b = sim.fields(l, (x0, y0, z, nx, ny, 1)), ref.fields(l, (x0, y0, z, nx, ny, 1))
+                own = ~np.isnan(b[0])
+                num += sum(float(((a[k] - b[k])[own] ** 2).sum()) for k in (1, 2, 3))
+                den += sum(float((b[k][own] ** 2).sum()) for k in (1, 2, 3))
+        ref.close()
+        out["rel_l2_u_vs_f64"] = float(f"{(num / den) ** 0.5:.3e}")
+        out["error_sample"] = f"three planes of every level after {total} coarse steps, against the FP64 run"
     if not args.no_cpu:
         import oracle
         small = W.forest3d_bench(n0=32, lattice=q)
@@ -323,6 +355,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=3)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-err", action="store_true", help="3D workloads: skip the FP64 reference run")
     ap.add_argument("--tile", type=int, default=None)
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="automatic blocks per workgroup instead of the autotuner's choice")
