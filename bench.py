@@ -62,6 +62,19 @@ def measured_traffic_3d(storage):
     return rec.get("hbm_bytes_per_launch")
 
 
+def measured_traffic_forest(storage):
+    """HBM bytes per coarse step of the 3D forest's step launches from the
+    committed counter summary, or None (none, or the kernel source changed)."""
+    path = os.path.join(ROOT, "profiles", f"forest3_kernel_forest3d_{storage}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2402_04606_amd", "csrc", "sbt3f.hip")
+    if rec.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return rec.get("hbm_bytes_per_step")
+
+
 def measured_traffic(workload, storage):
     """HBM bytes per launch of the level kernel from the committed counter
     summary of this workload and storage form (rocprofv3 FETCH_SIZE and
@@ -303,7 +316,9 @@ def bench_forest3d(args, P, W):
                    "owned_cells": [i[3] for i in sim.info], "halo_cells": [i[4] for i in sim.info],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic_forest(args.storage) if q == 19 else None,
+                     "traffic_unit": "HBM bytes per coarse step (the 7 step launches)",
                      "kernel": f"forest3_kernel (D3Q{q} pull stream + coalescence + collide + explosion), "
                                f"{launches} launches per coarse step",
                      "bytes_per_update": 2 * q * s, "algorithmic_bytes_per_step": algo,
