@@ -8,7 +8,7 @@
 // blocks under its octants) and one 32-bit code per cell for the blocks
 // that need one (hidden cells, hidden sources, interface and halo cells).
 //
-// One launch per level substep, one workgroup per block, one thread per
+// One launch per level substep, two workgroups per block (one per 4 z-planes), one thread per
 // cell, pull scheme (as the 2D level kernel): a lattice holds f*; a launch
 // gathers f(x, i) = f*(x - c_i, i) through the neighbour table, replaces the
 // populations whose source is hidden by the mean over the cell's 8 children
@@ -38,6 +38,7 @@ namespace {
 constexpr int kB3 = 8;                    // block edge
 constexpr int kC3 = kB3 * kB3 * kB3;      // cells per block (one workgroup)
 constexpr int kMaxLev3 = 6;
+constexpr int kWG3 = kC3 / 2;             // lanes per workgroup: half a block (4 z-planes)
 
 // Per-cell codes.
 enum : uint32_t {
@@ -85,7 +86,7 @@ struct Args3 {
   int32_t off32;        // the lattice read is under 4 GiB: 32-bit byte offsets
   Lev3 L;
   double *out;          // readout [n][4][512]: rho, ux, uy, uz
-  double *part;         // readout [n][4]: mass, jx, jy, jz of the block's owned cells
+  double *part;         // readout [2 n][4]: mass, jx, jy, jz of the owned cells of each half block
   int32_t *err;
 };
 
@@ -456,20 +457,24 @@ __device__ __forceinline__ void band3(const Args3 &a, int packed) {
 // MODE: 0 step (interior blocks first, then the rest, then halo cells),
 // M3_LOCAL, M3_READOUT or both.
 template <int ST, int Q, int MODE>
-__global__ __launch_bounds__(kC3) void forest3_kernel(Args3 a) {
-  const int n_bg = (a.n_band + kC3 - 1) / kC3;
-  const int w = remap3(blockIdx.x, a.n_blocks + n_bg, a.n_fast, a.xcd);
-  if (w < 0) return;
-  if (w >= a.n_blocks) {
-    const int idx = (w - a.n_blocks) * kC3 + threadIdx.x;
+__global__ __launch_bounds__(kWG3) void forest3_kernel(Args3 a) {
+  // work items: the two halves (z < 4, z >= 4) of each listed block, then
+  // groups of kWG3 halo cells
+  const int n_bg = (a.n_band + kWG3 - 1) / kWG3;
+  const int w2 = remap3(blockIdx.x, 2 * a.n_blocks + n_bg, 2 * a.n_fast, a.xcd);
+  if (w2 < 0) return;
+  if (w2 >= 2 * a.n_blocks) {
+    const int idx = (w2 - 2 * a.n_blocks) * kWG3 + threadIdx.x;
     if (idx < a.n_band) band3<ST, Q>(a, a.band[idx]);
     return;
   }
+  const int w = w2 >> 1;
+  const int cell = (w2 & 1) * kWG3 + threadIdx.x;
   const int b = __builtin_amdgcn_readfirstlane(a.list[w]);
   if constexpr (MODE == 0) {
     if (w < a.n_fast) {
-      if (a.off32) interior3<ST, Q, true>(a, b, threadIdx.x);
-      else interior3<ST, Q, false>(a, b, threadIdx.x);
+      if (a.off32) interior3<ST, Q, true>(a, b, cell);
+      else interior3<ST, Q, false>(a, b, cell);
       return;
     }
   }
@@ -479,8 +484,8 @@ __global__ __launch_bounds__(kC3) void forest3_kernel(Args3 a) {
   __shared__ int32_t cnb[8][27];
   const int t = threadIdx.x;
   if (t < kBlkInts) reinterpret_cast<int32_t *>(&sk)[t] = reinterpret_cast<const int32_t *>(a.meta + b)[t];
-  if (t >= 64 && t < 64 + 8 * 27) {
-    const int o = (t - 64) / 27, sl = (t - 64) % 27;
+  if (t < 8 * 27) {
+    const int o = t / 27, sl = t % 27;
     const int cb = a.fmeta ? a.meta[b].child[o] : -1;
     cnb[o][sl] = cb >= 0 ? a.fmeta[cb].nbr[sl] : -1;
   }
@@ -488,20 +493,20 @@ __global__ __launch_bounds__(kC3) void forest3_kernel(Args3 a) {
   double part[4] = {0.0, 0.0, 0.0, 0.0};
   Args3 m = a;
   m.mode = MODE;
-  cell3<ST, Q>(m, sk, cnb, b, w, t, part);
-  if constexpr ((MODE & M3_READOUT) != 0) {  // fixed-order tree over the block's cells
-    __shared__ double red[4][kC3];
+  cell3<ST, Q>(m, sk, cnb, b, w, cell, part);
+  if constexpr ((MODE & M3_READOUT) != 0) {  // fixed-order tree over the half block's cells
+    __shared__ double red[4][kWG3];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = part[q];
+    for (int q = 0; q < 4; ++q) red[q][t] = part[q];
     __syncthreads();
-    for (int h = kC3 / 2; h > 0; h >>= 1) {
-      if ((int)threadIdx.x < h) {
+    for (int h = kWG3 / 2; h > 0; h >>= 1) {
+      if (t < h) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + h];
+        for (int q = 0; q < 4; ++q) red[q][t] += red[q][t + h];
       }
       __syncthreads();
     }
-    if (threadIdx.x < 4) a.part[(size_t)w * 4 + threadIdx.x] = red[threadIdx.x][0];
+    if (t < 4) a.part[(size_t)w2 * 4 + t] = red[t][0];
   }
 }
 
@@ -552,14 +557,14 @@ int grid3(int n, int n_fast, int remap) {
 
 template <int ST, int Q>
 hipError_t launch_forest3(const Args3 &a, hipStream_t s) {
-  const int n = grid3(a.n_blocks + (a.n_band + kC3 - 1) / kC3, a.n_fast, a.xcd);
+  const int n = grid3(2 * a.n_blocks + (a.n_band + kWG3 - 1) / kWG3, 2 * a.n_fast, a.xcd);
   if (n <= 0) return hipSuccess;
   switch (a.mode) {
-    case 0: hipLaunchKernelGGL((forest3_kernel<ST, Q, 0>), dim3(n), dim3(kC3), 0, s, a); break;
-    case M3_LOCAL: hipLaunchKernelGGL((forest3_kernel<ST, Q, M3_LOCAL>), dim3(n), dim3(kC3), 0, s, a); break;
-    case M3_READOUT: hipLaunchKernelGGL((forest3_kernel<ST, Q, M3_READOUT>), dim3(n), dim3(kC3), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((forest3_kernel<ST, Q, 0>), dim3(n), dim3(kWG3), 0, s, a); break;
+    case M3_LOCAL: hipLaunchKernelGGL((forest3_kernel<ST, Q, M3_LOCAL>), dim3(n), dim3(kWG3), 0, s, a); break;
+    case M3_READOUT: hipLaunchKernelGGL((forest3_kernel<ST, Q, M3_READOUT>), dim3(n), dim3(kWG3), 0, s, a); break;
     default:
-      hipLaunchKernelGGL((forest3_kernel<ST, Q, M3_LOCAL | M3_READOUT>), dim3(n), dim3(kC3), 0, s, a);
+      hipLaunchKernelGGL((forest3_kernel<ST, Q, M3_LOCAL | M3_READOUT>), dim3(n), dim3(kWG3), 0, s, a);
   }
   return hipGetLastError();
 }
@@ -1003,7 +1008,7 @@ size_t layout(sbt3f_ctx &X, char *base, const std::vector<std::vector<Blk3>> &me
   }
   const int sb = std::min(kStageBlocks, max_pool);
   X.d_stage = cv.take<double>((size_t)sb * 4 * kC3 * 8);
-  X.d_part = cv.take<double>((size_t)max_pool * 4 * 8);
+  X.d_part = cv.take<double>((size_t)max_pool * 2 * 4 * 8);
   X.d_stage_list = cv.take<int32_t>((size_t)sb * 4);
   X.d_err = cv.take<int32_t>(256);
   return cv.off;
@@ -1379,7 +1384,7 @@ sbt_status sbt3f_diagnostics(sbt3f_ctx *ctx, double out[4]) {
   sbt3f_ctx &X = *ctx;
   for (int k = 0; k < 4; ++k) out[k] = 0.0;
   const int sb = stage_blocks(X);
-  std::vector<double> part((size_t)sb * 4);
+  std::vector<double> part((size_t)sb * 2 * 4);
   for (int l = 0; l < X.fo.m; ++l) {
     Pool3 &P = X.pools[l];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1390,9 +1395,9 @@ sbt_status sbt3f_diagnostics(sbt3f_ctx *ctx, double out[4]) {
       HIPCHK3(hipMemcpyAsync(X.d_stage_list, list.data(), (size_t)nb * 4, hipMemcpyHostToDevice, X.stream));
       sbt_status st = launch_level3(X, l, X.d_stage_list, nb, M3_READOUT | (X.post ? 0 : M3_LOCAL), false);
       if (st) return st;
-      HIPCHK3(hipMemcpyAsync(part.data(), X.d_part, (size_t)nb * 4 * 8, hipMemcpyDeviceToHost, X.stream));
+      HIPCHK3(hipMemcpyAsync(part.data(), X.d_part, (size_t)nb * 2 * 4 * 8, hipMemcpyDeviceToHost, X.stream));
       HIPCHK3(hipStreamSynchronize(X.stream));
-      for (int w = 0; w < nb; ++w)
+      for (int w = 0; w < 2 * nb; ++w)
         for (int k = 0; k < 4; ++k) acc[k] += part[(size_t)w * 4 + k];
     }
     const double wgt = 1.0 / (double)((int64_t)1 << (3 * l));
