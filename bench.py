@@ -112,11 +112,13 @@ def rel_l2_vs(ref, sim, wls):
     return math.sqrt(num / max(den, 1e-300)), worst
 
 
-def time_form(P, wls, storage, steps, warmup, tile=None, autotune=False):
+def time_form(P, wls, storage, steps, warmup, tile=None, autotune=False, persistent=False):
     import torch
     sim = P.Sim(wls, storage)
     if tile is not None:
         sim.set_option(P.OPT_TILE, tile)
+    if persistent:
+        sim.set_option(P.OPT_PERSISTENT, 1)
     if autotune:
         # blocks per workgroup per level: the autotuner's cached choice for
         # this workload shape, or timed trials when the shape is new
@@ -372,6 +374,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-err", action="store_true", help="3D workloads: skip the FP64 reference run")
     ap.add_argument("--tile", type=int, default=None)
+    ap.add_argument("--persistent", action="store_true",
+                    help="time the one-launch-per-step form (SBT_OPT_PERSISTENT) instead of the launch chain")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="automatic blocks per workgroup instead of the autotuner's choice")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"],
@@ -424,7 +428,7 @@ def main():
     V = max(w.n_levels for w in wls)
 
     # ---- headline form, timed with graphs --------------------------------------
-    sim, dt, ups = time_form(P, wls, args.storage, args.steps, args.warmup, args.tile, args.autotune)
+    sim, dt, ups = time_form(P, wls, args.storage, args.steps, args.warmup, args.tile, args.autotune, args.persistent)
     mlups = ups * args.steps / dt / 1e6
     ms_per_step = dt * 1e3 / args.steps
 

@@ -312,8 +312,13 @@ sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes);
  * SBT_OPT_TILE: interior 16x16 blocks per workgroup of the stream+collide
  *   launch, 1..16 for every level (a workgroup loads block j+1 while it
  *   computes block j); 0 (default) = automatic per launch size.
- * SBT_OPT_XCD_REMAP (default 1): map consecutive Morton blocks to one XCD. */
-enum { SBT_OPT_GRAPH = 0, SBT_OPT_TILE = 1, SBT_OPT_XCD_REMAP = 2 };
+ * SBT_OPT_XCD_REMAP (default 1): map consecutive Morton blocks to one XCD.
+ * SBT_OPT_PERSISTENT (default 0): run each step as one persistent launch
+ *   (plan builder, forcing loops and level substeps as phases separated by
+ *   grid barriers, every level block through the generic per-cell path)
+ *   instead of the chain of launches.  Results are the same either way; a
+ *   barrier that times out makes sbt_synchronize report SBT_ERR_DEVICE. */
+enum { SBT_OPT_GRAPH = 0, SBT_OPT_TILE = 1, SBT_OPT_XCD_REMAP = 2, SBT_OPT_PERSISTENT = 3 };
 sbt_status sbt_set_option(sbt_ctx *ctx, int32_t option, int32_t value);
 /* Pick the blocks per workgroup of each level by timing `steps` steps per
  * trial (1, 2, 3, 4, 6, 8; finest level first, one level at a time) and keep the

@@ -20,7 +20,8 @@ def build(verbose=False, jobs=2):
     inc = ["-I", os.path.join(ROOT, "include"), "-I", csrc]
     objs = []
     procs = []
-    for src in ("sbt_kernels.hip", "sbt_stats.hip", "sbt3d.hip", "sbt3f.hip", "sbt_static.hip", "sbt_host.cpp"):
+    for src in ("sbt_kernels.hip", "sbt_persist.hip", "sbt_stats.hip", "sbt3d.hip", "sbt3f.hip", "sbt_static.hip",
+                "sbt_host.cpp"):
         obj = os.path.join(csrc, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = ["hipcc", *HIP_FLAGS, *inc, *lang, "-c", os.path.join(csrc, src), "-o", obj]

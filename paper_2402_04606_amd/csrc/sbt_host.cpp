@@ -283,6 +283,14 @@ struct sbt_ctx {
   hipStream_t cap_stream = nullptr;
   bool post = false;               // false: lattices hold the initial pre-collision state
   int tile = 0, xcd = 1, use_graph = 1;
+  int persistent = 0;              // one persistent launch per step instead of the launch chain
+  PPhase *d_ptab = nullptr;        // [2 * plan_bufs][ptab_cap] phase tables of the persistent step
+  int ptab_cap = 0;
+  std::vector<char> ptab_ready;
+  std::vector<int> ptab_n;
+  uint32_t *d_bar = nullptr;       // grid-barrier state of the persistent step
+  int p_groups = 0;                // its workgroups (0: not sized yet)
+  size_t p_lds = 0;
   std::vector<int> kpw_level;   // interior blocks per workgroup per virtual level (0: automatic)
   int lds_window = 0;           // IBM window cells whose plan-builder counters fit in LDS
   int cell_cap = 0;             // stencil cells per IBM plan (fits the forcing kernel's LDS)
@@ -305,6 +313,8 @@ struct sbt_ctx {
 namespace {
 
 void build_tables(sbt_ctx &X);
+std::vector<Phase> step_phases(int V);
+void advance_host(sbt_ctx &X, int steps);
 
 // Copy and validate a case's solid regions (dense per level), applying the
 // q = 1/2 rule where a short link has no fluid cell behind it.
@@ -461,6 +471,12 @@ sbt_status plan_ctx(const sbt_case_desc *cases, int32_t n_cases, sbt_ctx &X, Car
   X.d_partial = (double *)cv.take(sizeof(double) * 3 * max_blocks);
   X.d_diag = (double *)cv.take(sizeof(double) * 16);  // diagnostics [0, 4), force stats [4, 12), E [12, 16)
   X.d_err = (int32_t *)cv.take(sizeof(int32_t) * 4);
+  // persistent step: one phase table per (level-0 parity, first plan buffer)
+  X.ptab_cap = 1 + (int)step_phases(X.V).size();
+  X.d_ptab = (PPhase *)cv.take(sizeof(PPhase) * (size_t)X.ptab_cap * 2 * X.plan_bufs);
+  X.ptab_ready.assign((size_t)2 * X.plan_bufs, 0);
+  X.ptab_n.assign((size_t)2 * X.plan_bufs, 0);
+  X.d_bar = (uint32_t *)cv.take(sizeof(uint32_t) * 4);
   X.d_cases = (CaseDev *)cv.take(sizeof(CaseDev) * n_cases);
   X.d_bodies = (CaseDev *)cv.take(sizeof(CaseDev) * n_cases);
   for (int c = 0; c < n_cases; ++c) {
@@ -740,8 +756,9 @@ int blocks_per_wg(const sbt_ctx &X, int v, int n_fast) {
   return k;
 }
 
-sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
-  Pool &P = X.pools[v];
+// Arguments of a level launch of pool v in the current state.
+LevelArgs level_args(const sbt_ctx &X, int v, int mode) {
+  const Pool &P = X.pools[v];
   LevelArgs a;
   std::memset(&a, 0, sizeof(a));
   a.meta = P.d_meta;
@@ -751,7 +768,7 @@ sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
   a.src = P.lat[P.cur];
   a.dst = P.lat[1 - P.cur];
   if (v + 1 < X.V) {
-    Pool &Q = X.pools[v + 1];
+    const Pool &Q = X.pools[v + 1];
     a.fmeta = Q.d_meta;
     a.fcodes = Q.d_codes;
     a.fprev = Q.lat[1 - Q.cur];
@@ -763,6 +780,12 @@ sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
   // the finest level collides with the force of the forcing loop just run
   a.ibm_parity = (v == X.V - 1 && X.n_bodies > 0 && X.k_host > 0) ? (int)((X.k_host - 1) & (X.plan_bufs - 1)) : -1;
   a.err = X.d_err;
+  return a;
+}
+
+sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
+  Pool &P = X.pools[v];
+  LevelArgs a = level_args(X, v, mode);
   auto timed = [&](bool fast, auto &&launch) -> sbt_status {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (X.profiling) {
@@ -806,9 +829,9 @@ sbt_status launch_level(sbt_ctx &X, int v, int p, int mode, hipStream_t s) {
   return SBT_OK;
 }
 
-sbt_status launch_mdf(sbt_ctx &X, bool first, hipStream_t s) {
-  if (X.n_bodies == 0) return SBT_OK;
-  Pool &P = X.pools[X.V - 1];
+// Arguments of the forcing loop of the next finest substep.
+MdfArgs mdf_args(const sbt_ctx &X, bool first) {
+  const Pool &P = X.pools[X.V - 1];
   MdfArgs a;
   a.meta = P.d_meta;
   a.src = P.lat[P.cur];
@@ -819,6 +842,12 @@ sbt_status launch_mdf(sbt_ctx &X, bool first, hipStream_t s) {
   a.max_markers = X.max_body_markers;
   a.cell_cap = X.cell_cap;
   a.parity = (int)(X.k_host & (X.plan_bufs - 1));
+  return a;
+}
+
+sbt_status launch_mdf(sbt_ctx &X, bool first, hipStream_t s) {
+  if (X.n_bodies == 0) return SBT_OK;
+  MdfArgs a = mdf_args(X, first);
   ++X.k_host;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (X.profiling) {
@@ -844,9 +873,7 @@ int forcing_phases(const sbt_ctx &X) {
 // substeps (those of kcount .. kcount + n_plans - 1), one workgroup per body
 // and substep.  The plan of substep k goes to buffer k & (plan_bufs - 1);
 // every earlier reader of those buffers precedes this launch in stream order.
-sbt_status launch_prep(sbt_ctx &X, int n_plans, hipStream_t s) {
-  if (X.n_bodies == 0) return SBT_OK;
-  if (n_plans > X.plan_bufs) return fail(SBT_ERR_STATE, "more IBM plans than plan buffers");
+IbmArgs prep_args(const sbt_ctx &X, int n_plans) {
   IbmArgs a;
   a.cases = X.d_cases;
   a.bodies = X.d_bodies;
@@ -855,6 +882,13 @@ sbt_status launch_prep(sbt_ctx &X, int n_plans, hipStream_t s) {
   a.lds_window = X.lds_window;
   a.n_bodies = X.n_bodies;
   a.n_plans = n_plans;
+  return a;
+}
+
+sbt_status launch_prep(sbt_ctx &X, int n_plans, hipStream_t s) {
+  if (X.n_bodies == 0) return SBT_OK;
+  if (n_plans > X.plan_bufs) return fail(SBT_ERR_STATE, "more IBM plans than plan buffers");
+  IbmArgs a = prep_args(X, n_plans);
   HIPCHK(sbt_launch_ibm_prep(&a, s));
   return SBT_OK;
 }
@@ -896,6 +930,89 @@ void destroy_graphs(sbt_ctx &X) {
       g = nullptr;
     }
   X.graph_dirty = true;
+  X.ptab_ready.assign(X.ptab_ready.size(), 0);
+}
+
+// ---- the persistent step ------------------------------------------------------
+// The phase table of one step from the current state: the same plan
+// builder, forcing loops and level substeps, with the same arguments, as the
+// launch chain (run_step_eager), in the same order.
+void build_phase_table(sbt_ctx &X, std::vector<PPhase> &out) {
+  out.clear();
+  std::vector<int> saved(X.pools.size());
+  for (size_t i = 0; i < X.pools.size(); ++i) saved[i] = X.pools[i].cur;
+  const int64_t saved_k = X.k_host;
+  auto blank = [] {
+    PPhase q;
+    std::memset(&q, 0, sizeof(q));
+    return q;
+  };
+  if (X.n_bodies > 0) {
+    PPhase q = blank();
+    q.type = PP_PREP;
+    q.ibm = prep_args(X, forcing_phases(X));
+    q.n_items = X.n_bodies * q.ibm.n_plans;
+    out.push_back(q);
+  }
+  for (const Phase &ph : X.step_phases) {
+    PPhase q = blank();
+    if (ph.type == PH_MDF) {
+      if (X.n_bodies == 0) continue;
+      q.type = PP_MDF;
+      q.mdf = mdf_args(X, false);
+      q.n_items = X.n_bodies;
+      ++X.k_host;
+    } else {
+      Pool &P = X.pools[ph.v];
+      q.type = PP_LEVEL;
+      q.lv = level_args(X, ph.v, 0);
+      q.lv.list = P.d_list;
+      q.n_list = (int)(P.fast.size() + P.slow.size());
+      q.solid = P.d_solid;
+      q.n_solid = (int)P.solid.size();
+      if (ph.p == 1) {
+        q.lv.band = P.d_band;
+        q.lv.n_band = (int)P.band.size();
+      }
+      q.n_items = q.n_list + q.n_solid;
+      P.cur = 1 - P.cur;
+    }
+    out.push_back(q);
+  }
+  for (size_t i = 0; i < X.pools.size(); ++i) X.pools[i].cur = saved[i];
+  X.k_host = saved_k;
+}
+
+// One step as one persistent launch.  The table depends on the state only
+// through level 0's lattice parity and the plan buffer of the step's first
+// substep (as the captured graphs do); each of those tables is uploaded once.
+sbt_status run_step_persistent(sbt_ctx &X, hipStream_t s) {
+  if (X.p_groups == 0) {
+    int dev = 0, cus = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    X.p_lds = 0;
+    if (X.n_bodies > 0)
+      X.p_lds = std::max(sbt_mdf_lds_bytes(X.max_body_markers, X.cell_cap),
+                         sbt_prep_lds_bytes(X.max_body_markers, X.cell_cap, X.lds_window));
+    const int per_cu = sbt_step_persistent_occupancy(X.kvar, X.p_lds);
+    if (per_cu <= 0) return fail(SBT_ERR_DEVICE, "the persistent step kernel cannot launch");
+    X.p_groups = per_cu * cus;
+  }
+  const int slot = X.pools[0].cur + 2 * (int)(X.k_host & (X.plan_bufs - 1));
+  PPhase *tab = X.d_ptab + (size_t)slot * X.ptab_cap;
+  if (!X.ptab_ready[slot]) {
+    std::vector<PPhase> t;
+    build_phase_table(X, t);
+    if ((int)t.size() > X.ptab_cap) return fail(SBT_ERR_STATE, "phase table larger than planned");
+    HIPCHK(hipMemcpyAsync(tab, t.data(), sizeof(PPhase) * t.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // t is released on return
+    X.ptab_n[slot] = (int)t.size();
+    X.ptab_ready[slot] = 1;
+  }
+  HIPCHK(sbt_launch_step_persistent(X.kvar, tab, X.ptab_n[slot], X.d_bar, X.d_err, X.p_groups, X.p_lds, s));
+  advance_host(X, 1);
+  return SBT_OK;
 }
 
 // Steps per graph launch: a call of n steps replays graphs of 4, 2 and 1
@@ -1146,7 +1263,8 @@ sbt_status sbt_create_in(const sbt_case_desc *cases, int32_t n_cases, void *devi
     }
     if (upload_case(*X, c)) return cleanup_fail(SBT_ERR_DEVICE);
   }
-  if (hipMemsetAsync(X->d_err, 0, sizeof(int32_t) * 4, s) != hipSuccess)
+  if (hipMemsetAsync(X->d_err, 0, sizeof(int32_t) * 4, s) != hipSuccess ||
+      hipMemsetAsync(X->d_bar, 0, sizeof(uint32_t) * 4, s) != hipSuccess)
     return cleanup_fail(fail(SBT_ERR_DEVICE, "memset"));
   if (reset_counters(*X)) return cleanup_fail(SBT_ERR_DEVICE);
   for (auto &P : X->pools) {
@@ -1369,7 +1487,11 @@ sbt_status sbt_step(sbt_ctx *ctx, int32_t n) {
     if (st) return st;
   }
   for (int t = 0; t < n;) {
-    if (X.use_graph && !X.profiling) {
+    if (X.persistent && !X.profiling) {
+      sbt_status st = run_step_persistent(X, X.stream);
+      if (st) return st;
+      ++t;
+    } else if (X.use_graph && !X.profiling) {
       sbt_status st = ensure_capture_stream(X);
       if (st) return st;
       const int rem = n - t, si = rem >= 4 ? 2 : (rem >= 2 ? 1 : 0);
@@ -1405,6 +1527,7 @@ sbt_status sbt_synchronize(sbt_ctx *ctx) {
       return fail(SBT_ERR_MARKER_OUTSIDE, "IBM stencil cells exceed the plan capacity (" + std::to_string(ctx->cell_cap) + ")");
     if (err[0] & ERR_WINDOW) return fail(SBT_ERR_MARKER_OUTSIDE, "IBM window larger than planned");
     if (err[0] & ERR_PLAN) return fail(SBT_ERR_STATE, "IBM plan out of step with the forcing loop");
+    if (err[0] & ERR_BARRIER) return fail(SBT_ERR_DEVICE, "persistent step: a grid barrier timed out");
   }
   return SBT_OK;
 }
@@ -1699,6 +1822,7 @@ sbt_status sbt_set_option(sbt_ctx *ctx, int32_t option, int32_t value) {
       ctx->kpw_level.assign(ctx->V, value);
       break;
     case SBT_OPT_XCD_REMAP: ctx->xcd = value != 0; break;
+    case SBT_OPT_PERSISTENT: ctx->persistent = value != 0; break;
     default: return fail(SBT_ERR_ARG, "unknown option");
   }
   destroy_graphs(*ctx);

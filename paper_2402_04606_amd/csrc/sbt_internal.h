@@ -146,11 +146,25 @@ struct IbmArgs {
   int32_t n_plans;             // plans per body: substeps kcount .. kcount + n_plans - 1
 };
 
+// One phase of the persistent step (one launch per step): the plan builder
+// of the step's finest substeps, a forcing loop, or a level substep.
+enum : int32_t { PP_PREP = 0, PP_MDF = 1, PP_LEVEL = 2 };
+struct PPhase {
+  int32_t type;
+  int32_t n_items;             // PREP: plans (bodies x substeps); MDF: bodies; LEVEL: list + solid blocks
+  int32_t n_list;              // LEVEL: entries of lv.list (interior and edge / interface blocks)
+  int32_t n_solid;             // LEVEL: entries of `solid`
+  const int32_t *solid;
+  LevelArgs lv;                // LEVEL (band cells in lv.band / lv.n_band)
+  MdfArgs mdf;
+  IbmArgs ibm;
+};
+
 // Level launch modes: LOCAL = read the cell's own populations (initial
 // pre-collision state) instead of streaming; READOUT = moments only, no write.
 enum : int32_t { MODE_LOCAL = 1, MODE_READOUT = 2 };
 
-enum : int32_t { ERR_NONFINITE = 1, ERR_MARKER = 2, ERR_CONTRIB = 4, ERR_WINDOW = 8, ERR_PLAN = 16 };
+enum : int32_t { ERR_NONFINITE = 1, ERR_MARKER = 2, ERR_CONTRIB = 4, ERR_WINDOW = 8, ERR_PLAN = 16, ERR_BARRIER = 32 };
 
 }  // namespace sbt
 
@@ -173,6 +187,16 @@ hipError_t sbt_launch_level(int storage, int tile, const sbt::LevelArgs *a, hipS
 // neighbours present), kpw of them per workgroup; [n_fast, n_blocks) blocks
 // next to a finer level or a domain edge; then n_band packed halo-band cells.
 hipError_t sbt_launch_level_tile(int storage, const sbt::LevelArgs *a, hipStream_t s);
+// One step as a single persistent launch of `groups` 1024-lane workgroups
+// (all resident at once) over the phase table `ph` (n_ph entries, device
+// memory), phases separated by grid barriers on bar[3] (zero between
+// launches).  A barrier that waits too long raises ERR_BARRIER in err and
+// every workgroup skips the remaining phases.
+hipError_t sbt_launch_step_persistent(int storage, const sbt::PPhase *ph, int n_ph, uint32_t *bar, int32_t *err,
+                                      int groups, size_t lds_bytes, hipStream_t s);
+// Resident 1024-lane workgroups per CU of the persistent step kernel with
+// lds_bytes of dynamic LDS (0 if it cannot launch).
+int sbt_step_persistent_occupancy(int storage, size_t lds_bytes);
 // IBM plan of the next finest substep of every body, one workgroup each.
 hipError_t sbt_launch_ibm_prep(const sbt::IbmArgs *a, hipStream_t s);
 // Multi-direct forcing loop of the current finest substep on its plan.

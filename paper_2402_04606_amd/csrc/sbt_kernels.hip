@@ -383,14 +383,34 @@ typedef __attribute__((address_space(4))) const int32_t ci32_t;
 typedef __attribute__((address_space(4))) const int64_t ci64_t;
 typedef __attribute__((address_space(1))) const double gdbl_t;
 
-template <typename C>
+// A value another workgroup of the same launch may have written (the
+// persistent step): a vector load at agent scope, never a scalar one (the
+// scalar cache is not kept coherent with vector stores).
+template <typename T>
+__device__ __forceinline__ T ld_fresh(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// FRESH: the window may have been written earlier in the same launch.
+template <typename C, bool FRESH = false>
 __device__ __forceinline__ void add_ibm_force(const CaseDev &cp, int parity, int ox, int oy, int x, int y, C &Fx,
                                               C &Fy) {
-  const int b = parity >= 0 ? parity
-                            : __builtin_amdgcn_readfirstlane((int)((*(ci64_t *)cp.kcount - 1) & cp.plan_mask));
-  ci32_t *w = (ci32_t *)cp.win + 4 * b;   // IbmWindow {x0, y0, w, h}
-  const int x0 = __builtin_amdgcn_readfirstlane(w[0]), y0 = __builtin_amdgcn_readfirstlane(w[1]);
-  const int ww = __builtin_amdgcn_readfirstlane(w[2]), wh = __builtin_amdgcn_readfirstlane(w[3]);
+  int b, x0, y0, ww, wh;
+  if constexpr (FRESH) {
+    b = parity >= 0 ? parity : __builtin_amdgcn_readfirstlane((int)((ld_fresh(cp.kcount) - 1) & cp.plan_mask));
+    const int32_t *w = reinterpret_cast<const int32_t *>(cp.win + b);
+    x0 = __builtin_amdgcn_readfirstlane(ld_fresh(w));
+    y0 = __builtin_amdgcn_readfirstlane(ld_fresh(w + 1));
+    ww = __builtin_amdgcn_readfirstlane(ld_fresh(w + 2));
+    wh = __builtin_amdgcn_readfirstlane(ld_fresh(w + 3));
+  } else {
+    b = parity >= 0 ? parity : __builtin_amdgcn_readfirstlane((int)((*(ci64_t *)cp.kcount - 1) & cp.plan_mask));
+    ci32_t *w = (ci32_t *)cp.win + 4 * b;   // IbmWindow {x0, y0, w, h}
+    x0 = __builtin_amdgcn_readfirstlane(w[0]);
+    y0 = __builtin_amdgcn_readfirstlane(w[1]);
+    ww = __builtin_amdgcn_readfirstlane(w[2]);
+    wh = __builtin_amdgcn_readfirstlane(w[3]);
+  }
   if (ox + kB <= x0 || ox >= x0 + ww || oy + kB <= y0 || oy >= y0 + wh) return;
   const int wx = ox + x - x0, wy = oy + y - y0;
   if (wx >= 0 && wx < ww && wy >= 0 && wy < wh) {
@@ -630,7 +650,7 @@ __device__ __forceinline__ typename Store<ST>::C bouzidi(const LevelArgs &a, con
 }
 
 // ---- one cell of a level launch --------------------------------------------
-template <int ST>
+template <int ST, bool FRESH = false>
 __device__ __forceinline__ void level_cell(const LevelArgs &a, const Blk &k, int cell, const CaseDev &cp,
                                            bool slow, double *part) {
 #pragma clang fp contract(off)
@@ -733,7 +753,7 @@ __device__ __forceinline__ void level_cell(const LevelArgs &a, const Blk &k, int
     Fx = cp.fx_f[l];
     Fy = cp.fy_f[l];
   }
-  if (k.flags & BF_IBM) add_ibm_force<C>(cp, a.ibm_parity, k.ox, k.oy, x, y, Fx, Fy);
+  if (k.flags & BF_IBM) add_ibm_force<C, FRESH>(cp, a.ibm_parity, k.ox, k.oy, x, y, Fx, Fy);
 
   C rho, ux, uy;
   Collide<ST>::run(cp, l, f, Fx, Fy, rho, ux, uy);
@@ -1464,14 +1484,21 @@ __device__ __forceinline__ PlanView plan_view(const CaseDev &cp, int b) {
 // Plan builder.  LDS: window counters and compact indices (when the window
 // fits), the stencil cells' window indices and CSR starts, the contributor
 // lists while they are filled.
-__global__ __launch_bounds__(MDF_THREADS, 8) void ibm_prep_kernel(IbmArgs a) {
+// Dynamic LDS of the plan builder and the forcing loop: one symbol for every
+// kernel that runs them, so each kernel addresses it directly.
+extern __shared__ __align__(16) char sbt_ibm_lds[];
+
+// Plan `item` of the launch: substep item / n_bodies of body item % n_bodies.
+// FRESH: the substep counter may have been written earlier in the launch.
+template <bool FRESH>
+__device__ __forceinline__ void prep_item(const IbmArgs &a, unsigned item) {
 #pragma clang fp contract(off)
-  const int64_t j = blockIdx.x / a.n_bodies;  // plan of the launch's j-th substep
-  const CaseDev &cp = a.bodies[blockIdx.x % a.n_bodies];
+  const int64_t j = item / a.n_bodies;  // plan of the launch's j-th substep
+  const CaseDev &cp = a.bodies[item % a.n_bodies];
   const int n = cp.n_markers;
   const int nm = cp.nm_cap, cap = cp.cell_cap;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  extern __shared__ int lds_i[];
+  int *lds_i = reinterpret_cast<int *>(sbt_ibm_lds);
   const int NMa = a.max_markers, CCa = a.cell_cap;  // LDS table sizes
   int *s_cells = lds_i;                  // [CCa] window index of stencil cell q
   int *s_start = s_cells + CCa;          // [CCa] CSR start of stencil cell q
@@ -1485,7 +1512,12 @@ __global__ __launch_bounds__(MDF_THREADS, 8) void ibm_prep_kernel(IbmArgs a) {
   __shared__ int s_wsum[MDF_THREADS / 64];
   __shared__ Pose s_pose[2];
   // the forcing loop of substep kcount runs next, in stream order after this
-  const int64_t k = *cp.kcount + j;
+  // the counter through the constant address space (a scalar load) unless
+  // it may have been written earlier in the same launch
+  int64_t k0;
+  if constexpr (FRESH) k0 = ld_fresh(cp.kcount);
+  else k0 = *(ci64_t *)cp.kcount;
+  const int64_t k = k0 + j;
   const int b = (int)(k & cp.plan_mask);
   const PlanView P = plan_view(cp, b);
 
@@ -1704,6 +1736,10 @@ __global__ __launch_bounds__(MDF_THREADS, 8) void ibm_prep_kernel(IbmArgs a) {
   }
 }
 
+#ifndef SBT_PERSISTENT_TU
+__global__ __launch_bounds__(MDF_THREADS, 8) void ibm_prep_kernel(IbmArgs a) { prep_item<false>(a, blockIdx.x); }
+#endif
+
 __device__ __forceinline__ void mdf_fail(const CaseDev &cp, int *err, int code, int64_t k) {
   atomicOr(err, code);
   IbmWindow e = {0, 0, 0, 0};
@@ -1724,15 +1760,17 @@ __device__ __forceinline__ int corner_block(int gx, int gy, int sx, int sy, int 
   return west ? (south ? sw : nw) : (south ? se : ne);
 }
 
-template <int ST>
-__global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
+// The forcing loop of body `body` (one 1024-lane workgroup).  FRESH: the
+// plan, window and counter may have been written earlier in the launch.
+template <int ST, bool FRESH>
+__device__ __forceinline__ void mdf_body(const MdfArgs &a, int body) {
 #pragma clang fp contract(off)
-  const CaseDev &cp = a.bodies[blockIdx.x];
+  const CaseDev &cp = a.bodies[body];
   const int n = cp.n_markers;
   const int nm = cp.nm_cap;
   const int tid = threadIdx.x;
   const int NM = a.max_markers, CC = a.cell_cap;  // LDS table strides
-  extern __shared__ __align__(16) double lds[];
+  double *lds = reinterpret_cast<double *>(sbt_ibm_lds);
   double2 *s_dF = reinterpret_cast<double2 *>(lds);  // [NM] marker force of the iteration
   double2 *s_uv = s_dF + NM;        // [CC] corrected velocity of the cell
   double *s_wx = reinterpret_cast<double *>(s_uv + CC);  // [4][NM]
@@ -1748,9 +1786,19 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
   // plan loads below do not wait for the substep counter.
   const int b = a.parity;
   const PlanView P = plan_view(cp, b);
-  const int64_t k = *cp.kcount;
-  const int4 hdr = *reinterpret_cast<const int4 *>(P.hdr);
-  const IbmWindow win = cp.win[b];
+  int64_t k;
+  int4 hdr;
+  IbmWindow win;
+  if constexpr (FRESH) {
+    k = ld_fresh(cp.kcount);
+    hdr = make_int4(ld_fresh(P.hdr), ld_fresh(P.hdr + 1), ld_fresh(P.hdr + 2), ld_fresh(P.hdr + 3));
+    const int32_t *w = reinterpret_cast<const int32_t *>(cp.win + b);
+    win = {ld_fresh(w), ld_fresh(w + 1), ld_fresh(w + 2), ld_fresh(w + 3)};
+  } else {
+    k = *cp.kcount;
+    hdr = *reinterpret_cast<const int4 *>(P.hdr);
+    win = cp.win[b];
+  }
   // 1. load the plan before the header is known, all in one round: this
   //    lane's first stencil-cell record, the contributor lists (direct
   //    global->LDS copies, 16 bytes per lane) and the marker tables
@@ -2005,6 +2053,120 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) {
   if (tid == 0) *cp.kcount = k + 1;
 }
 
+#ifndef SBT_PERSISTENT_TU
+template <int ST>
+__global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) { mdf_body<ST, false>(a, blockIdx.x); }
+#endif
+
+#ifdef SBT_PERSISTENT_TU
+// ---- the persistent step ----------------------------------------------------
+// Compiled in a module of its own (sbt_persist.hip includes this file with
+// SBT_PERSISTENT_TU defined and keeps only this part and its launchers): a
+// kernel that runs the plan builder and the forcing loop next to their own
+// kernels in one module would change how those kernels address their LDS.
+// One launch runs a whole step: the phase table holds the plan builder, the
+// forcing loops and the level substeps in the order of the launch chain, and
+// a grid barrier separates consecutive phases (every workgroup resident).
+// Level substeps go through the generic per-cell path, four blocks at a
+// time per workgroup (one per 256 lanes), which needs no workgroup barrier;
+// the plan builder and the forcing loop use all 1024 lanes as in their own
+// launches.
+
+// Spins of a barrier wait before it gives up (about a second).
+constexpr uint32_t kBarrierSpins = 1u << 21;
+
+// Grid barrier number `idx` (1, 2, ...) of the launch: bar[0] counts
+// arrivals, so it is passed when bar[0] >= idx * gridDim.x.  The release
+// makes this workgroup's writes visible at agent scope and the acquire
+// invalidates what this CU cached before.  A wait past kBarrierSpins raises
+// ERR_BARRIER and sets bar[1], which ends every other wait.  Returns false
+// when the launch is aborted.
+__device__ bool grid_barrier(uint32_t *bar, uint32_t idx, int32_t *err) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t target = idx * gridDim.x;
+    uint32_t spins = 0;
+    while (__hip_atomic_load(&bar[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        ok = 0;
+        break;
+      }
+      if (++spins >= kBarrierSpins) {
+        atomicOr(err, ERR_BARRIER);
+        __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+template <int ST>
+__device__ __forceinline__ void level_phase(const PPhase &P) {
+  const LevelArgs &a = P.lv;
+  const int sub = threadIdx.x >> 8, cell = threadIdx.x & 255;
+  const int n_blk = P.n_list + P.n_solid;
+  const int n_work = n_blk + (a.n_band + 255) / 256;
+  for (int base = blockIdx.x * 4; base < n_work; base += gridDim.x * 4) {
+    const int i = base + sub;  // uniform over the 4 waves of this quarter
+    if (i < n_blk) {
+      const int b = __builtin_amdgcn_readfirstlane(i < P.n_list ? a.list[i] : P.solid[i - P.n_list]);
+      const Blk k = load_blk(a.meta, b);
+      const CaseDev &cp = a.cases[k.cid];
+      const bool slow = (k.flags & (BF_CODES | BF_EDGE | BF_SOLID)) != 0;
+      double part[3] = {0.0, 0.0, 0.0};
+      level_cell<ST, true>(a, k, cell, cp, slow, part);
+    } else if (i < n_work) {
+      const int idx = (i - n_blk) * 256 + cell;
+      if (idx < a.n_band) band_cell<ST>(a, a.band[idx]);
+    }
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(MDF_THREADS) void step_persistent_kernel(const PPhase *__restrict__ ph, int n_ph,
+                                                                      uint32_t *bar, int32_t *err) {
+  bool ok = true;
+  for (int p = 0; p < n_ph && ok; ++p) {
+    const PPhase &P = ph[p];
+    if (P.type == PP_PREP) {
+      for (unsigned it = blockIdx.x; it < (unsigned)P.n_items; it += gridDim.x) {
+        prep_item<true>(P.ibm, it);
+        __syncthreads();
+      }
+    } else if (P.type == PP_MDF) {
+      for (int it = blockIdx.x; it < P.n_items; it += gridDim.x) {
+        mdf_body<ST & 3, true>(P.mdf, it);
+        __syncthreads();
+      }
+    } else {
+      level_phase<ST>(P);
+    }
+    if (p + 1 < n_ph) ok = grid_barrier(bar, (uint32_t)(p + 1), err);
+  }
+  // the last workgroup out puts the barrier state back to zero for the next
+  // launch (every other workgroup has passed its last barrier)
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t done = __hip_atomic_fetch_add(&bar[2], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == gridDim.x - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&bar[2], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+#endif  // SBT_PERSISTENT_TU
+
+#ifndef SBT_PERSISTENT_TU
 // ---- small helpers ---------------------------------------------------------
 __global__ void reduce_kernel(const double *partial, int n, double vol, double *out, int accumulate) {
   __shared__ double red[3][256];
@@ -2079,8 +2241,11 @@ hipError_t launch_level_st(int tile, const LevelArgs *a, hipStream_t s) {
   return hipGetLastError();
 }
 
+#endif  // !SBT_PERSISTENT_TU
+
 }  // namespace
 
+#ifndef SBT_PERSISTENT_TU
 extern "C" hipError_t sbt_launch_level_tile(int storage, const LevelArgs *a, hipStream_t s) {
   if (a->kpw < 1) return hipErrorInvalidValue;
   const bool pipe = a->kpw > 1;
@@ -2203,3 +2368,38 @@ extern "C" hipError_t sbt_launch_fill_nan(void *p, size_t n, int storage, hipStr
   }
   return hipGetLastError();
 }
+#endif  // !SBT_PERSISTENT_TU
+
+#ifdef SBT_PERSISTENT_TU
+#define SBT_PERSIST_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+
+extern "C" hipError_t sbt_launch_step_persistent(int storage, const PPhase *ph, int n_ph, uint32_t *bar, int32_t *err,
+                                                 int groups, size_t lds_bytes, hipStream_t s) {
+  if (n_ph <= 0 || groups <= 0) return hipSuccess;
+  switch (storage) {
+#define SBT_P(S)                                                                                              \
+  case S:                                                                                                     \
+    hipLaunchKernelGGL((step_persistent_kernel<S>), dim3(groups), dim3(MDF_THREADS), lds_bytes, s, ph, n_ph, bar, err); \
+    break;
+    SBT_PERSIST_CASES(SBT_P)
+#undef SBT_P
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+extern "C" int sbt_step_persistent_occupancy(int storage, size_t lds_bytes) {
+  int n = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (storage) {
+#define SBT_P(S)                                                                                              \
+  case S:                                                                                                     \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, step_persistent_kernel<S>, MDF_THREADS, lds_bytes); \
+    break;
+    SBT_PERSIST_CASES(SBT_P)
+#undef SBT_P
+    default: break;
+  }
+  return e == hipSuccess ? n : 0;
+}
+#endif  // SBT_PERSISTENT_TU

@@ -470,6 +470,50 @@ def test_multi_step_graphs_match_eager(env):
                 assert np.array_equal(x, y, equal_nan=True)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f16s"])
+def test_persistent_step_matches_launch_chain(env, storage):
+    """One persistent launch per step (SBT_OPT_PERSISTENT: plan builder,
+    forcing loops and level substeps as phases behind grid barriers) against
+    the launch chain: the 64-case batch, 4 and then 3 global steps (both
+    level-0 parities of the phase tables), and a refined patch without
+    bodies (no plan or forcing phases).  FP64 bit for bit.  In the deviation
+    forms the persistent step's per-cell path rounds differently from the
+    tile kernel in FP32 arithmetic (last-bit differences on refined levels
+    after one step), so the 2-byte form is held to a relative L2 of velocity
+    of 1e-3, well inside its 5e-3 ceiling against FP64."""
+    P, _ = env
+    for wls in (W.batch_sweep(), [W.tgv_patch(m=3)]):
+        outs = []
+        for persistent in (1, 0):
+            print(f"{len(wls)} cases {storage} persistent {persistent}", flush=True)
+            g = P.Sim(wls, storage)
+            g.set_option(P.OPT_PERSISTENT, persistent)
+            g.step(4)
+            g.step(3)
+            g.synchronize()
+            outs.append([[g.fields_blocks(c, l) for l in range(wl.n_levels)]
+                         + ([g.force_history(c)[0]] if wl.body is not None else [])
+                         for c, wl in enumerate(wls)])
+            g.close()
+        if storage == "f64":
+            for c in range(len(wls)):
+                for x, y in zip(outs[0][c], outs[1][c]):
+                    assert np.array_equal(x, y, equal_nan=True), c
+            continue
+        num = den = 0.0
+        for c, wl in enumerate(wls):
+            for l in range(wl.n_levels):
+                a, b = outs[1][c][l], outs[0][c][l]
+                m = ~np.isnan(a[:, 0])
+                assert (np.isnan(b[:, 0]) == ~m).all(), (c, l)
+                for k in (1, 2):
+                    num += float(((b[:, k][m] - a[:, k][m]) ** 2).sum())
+                    den += float((a[:, k][m] ** 2).sum())
+        e = math.sqrt(num / den)
+        print(f"  persistent vs chain rel L2 u: {e:.3e}", flush=True)
+        assert e <= 1e-3
+
+
 def test_checkpoint_resume_bitwise(env):
     P, _ = env
     wl = W.small_refined_flap()
