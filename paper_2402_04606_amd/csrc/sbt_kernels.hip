@@ -383,34 +383,31 @@ typedef __attribute__((address_space(4))) const int32_t ci32_t;
 typedef __attribute__((address_space(4))) const int64_t ci64_t;
 typedef __attribute__((address_space(1))) const double gdbl_t;
 
-// A value another workgroup of the same launch may have written (the
-// persistent step): a vector load at agent scope, never a scalar one (the
-// scalar cache is not kept coherent with vector stores).
+// A value another workgroup of the same launch may have written (used in
+// the persistent step's module): a vector load at agent scope, never a
+// scalar one (the scalar cache is not kept coherent with vector stores).
 template <typename T>
 __device__ __forceinline__ T ld_fresh(const T *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// FRESH: the window may have been written earlier in the same launch.
-template <typename C, bool FRESH = false>
+// In the persistent step's module the window and counter may have been
+// written earlier in the same launch: vector loads there.
+template <typename C>
 __device__ __forceinline__ void add_ibm_force(const CaseDev &cp, int parity, int ox, int oy, int x, int y, C &Fx,
                                               C &Fy) {
-  int b, x0, y0, ww, wh;
-  if constexpr (FRESH) {
-    b = parity >= 0 ? parity : __builtin_amdgcn_readfirstlane((int)((ld_fresh(cp.kcount) - 1) & cp.plan_mask));
-    const int32_t *w = reinterpret_cast<const int32_t *>(cp.win + b);
-    x0 = __builtin_amdgcn_readfirstlane(ld_fresh(w));
-    y0 = __builtin_amdgcn_readfirstlane(ld_fresh(w + 1));
-    ww = __builtin_amdgcn_readfirstlane(ld_fresh(w + 2));
-    wh = __builtin_amdgcn_readfirstlane(ld_fresh(w + 3));
-  } else {
-    b = parity >= 0 ? parity : __builtin_amdgcn_readfirstlane((int)((*(ci64_t *)cp.kcount - 1) & cp.plan_mask));
-    ci32_t *w = (ci32_t *)cp.win + 4 * b;   // IbmWindow {x0, y0, w, h}
-    x0 = __builtin_amdgcn_readfirstlane(w[0]);
-    y0 = __builtin_amdgcn_readfirstlane(w[1]);
-    ww = __builtin_amdgcn_readfirstlane(w[2]);
-    wh = __builtin_amdgcn_readfirstlane(w[3]);
-  }
+#ifdef SBT_PERSISTENT_TU
+  const int b = parity >= 0 ? parity : __builtin_amdgcn_readfirstlane((int)((ld_fresh(cp.kcount) - 1) & cp.plan_mask));
+  const int32_t *w = reinterpret_cast<const int32_t *>(cp.win + b);
+  const int x0 = __builtin_amdgcn_readfirstlane(ld_fresh(w)), y0 = __builtin_amdgcn_readfirstlane(ld_fresh(w + 1));
+  const int ww = __builtin_amdgcn_readfirstlane(ld_fresh(w + 2)), wh = __builtin_amdgcn_readfirstlane(ld_fresh(w + 3));
+#else
+  const int b = parity >= 0 ? parity
+                            : __builtin_amdgcn_readfirstlane((int)((*(ci64_t *)cp.kcount - 1) & cp.plan_mask));
+  ci32_t *w = (ci32_t *)cp.win + 4 * b;   // IbmWindow {x0, y0, w, h}
+  const int x0 = __builtin_amdgcn_readfirstlane(w[0]), y0 = __builtin_amdgcn_readfirstlane(w[1]);
+  const int ww = __builtin_amdgcn_readfirstlane(w[2]), wh = __builtin_amdgcn_readfirstlane(w[3]);
+#endif
   if (ox + kB <= x0 || ox >= x0 + ww || oy + kB <= y0 || oy >= y0 + wh) return;
   const int wx = ox + x - x0, wy = oy + y - y0;
   if (wx >= 0 && wx < ww && wy >= 0 && wy < wh) {
@@ -650,7 +647,7 @@ __device__ __forceinline__ typename Store<ST>::C bouzidi(const LevelArgs &a, con
 }
 
 // ---- one cell of a level launch --------------------------------------------
-template <int ST, bool FRESH = false>
+template <int ST>
 __device__ __forceinline__ void level_cell(const LevelArgs &a, const Blk &k, int cell, const CaseDev &cp,
                                            bool slow, double *part) {
 #pragma clang fp contract(off)
@@ -753,7 +750,7 @@ __device__ __forceinline__ void level_cell(const LevelArgs &a, const Blk &k, int
     Fx = cp.fx_f[l];
     Fy = cp.fy_f[l];
   }
-  if (k.flags & BF_IBM) add_ibm_force<C, FRESH>(cp, a.ibm_parity, k.ox, k.oy, x, y, Fx, Fy);
+  if (k.flags & BF_IBM) add_ibm_force<C>(cp, a.ibm_parity, k.ox, k.oy, x, y, Fx, Fy);
 
   C rho, ux, uy;
   Collide<ST>::run(cp, l, f, Fx, Fy, rho, ux, uy);
@@ -1484,21 +1481,17 @@ __device__ __forceinline__ PlanView plan_view(const CaseDev &cp, int b) {
 // Plan builder.  LDS: window counters and compact indices (when the window
 // fits), the stencil cells' window indices and CSR starts, the contributor
 // lists while they are filled.
-// Dynamic LDS of the plan builder and the forcing loop: one symbol for every
-// kernel that runs them, so each kernel addresses it directly.
-extern __shared__ __align__(16) char sbt_ibm_lds[];
-
 // Plan `item` of the launch: substep item / n_bodies of body item % n_bodies.
-// FRESH: the substep counter may have been written earlier in the launch.
-template <bool FRESH>
-__device__ __forceinline__ void prep_item(const IbmArgs &a, unsigned item) {
+// The arguments come by value, as a kernel's do: taken by reference they
+// cost the plan builder 4 more VGPRs (one builder per CU instead of two).
+__device__ __forceinline__ void prep_item(const IbmArgs a, unsigned item) {
 #pragma clang fp contract(off)
   const int64_t j = item / a.n_bodies;  // plan of the launch's j-th substep
   const CaseDev &cp = a.bodies[item % a.n_bodies];
   const int n = cp.n_markers;
   const int nm = cp.nm_cap, cap = cp.cell_cap;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int *lds_i = reinterpret_cast<int *>(sbt_ibm_lds);
+  extern __shared__ int lds_i[];
   const int NMa = a.max_markers, CCa = a.cell_cap;  // LDS table sizes
   int *s_cells = lds_i;                  // [CCa] window index of stencil cell q
   int *s_start = s_cells + CCa;          // [CCa] CSR start of stencil cell q
@@ -1512,12 +1505,11 @@ __device__ __forceinline__ void prep_item(const IbmArgs &a, unsigned item) {
   __shared__ int s_wsum[MDF_THREADS / 64];
   __shared__ Pose s_pose[2];
   // the forcing loop of substep kcount runs next, in stream order after this
-  // the counter through the constant address space (a scalar load) unless
-  // it may have been written earlier in the same launch
-  int64_t k0;
-  if constexpr (FRESH) k0 = ld_fresh(cp.kcount);
-  else k0 = *(ci64_t *)cp.kcount;
-  const int64_t k = k0 + j;
+#ifdef SBT_PERSISTENT_TU
+  const int64_t k = ld_fresh(cp.kcount) + j;  // written earlier in the same launch
+#else
+  const int64_t k = *cp.kcount + j;
+#endif
   const int b = (int)(k & cp.plan_mask);
   const PlanView P = plan_view(cp, b);
 
@@ -1737,7 +1729,7 @@ __device__ __forceinline__ void prep_item(const IbmArgs &a, unsigned item) {
 }
 
 #ifndef SBT_PERSISTENT_TU
-__global__ __launch_bounds__(MDF_THREADS, 8) void ibm_prep_kernel(IbmArgs a) { prep_item<false>(a, blockIdx.x); }
+__global__ __launch_bounds__(MDF_THREADS, 8) void ibm_prep_kernel(IbmArgs a) { prep_item(a, blockIdx.x); }
 #endif
 
 __device__ __forceinline__ void mdf_fail(const CaseDev &cp, int *err, int code, int64_t k) {
@@ -1760,17 +1752,17 @@ __device__ __forceinline__ int corner_block(int gx, int gy, int sx, int sy, int 
   return west ? (south ? sw : nw) : (south ? se : ne);
 }
 
-// The forcing loop of body `body` (one 1024-lane workgroup).  FRESH: the
-// plan, window and counter may have been written earlier in the launch.
-template <int ST, bool FRESH>
-__device__ __forceinline__ void mdf_body(const MdfArgs &a, int body) {
+// The forcing loop of body `body` (one 1024-lane workgroup); arguments by
+// value for the same reason as prep_item's.
+template <int ST>
+__device__ __forceinline__ void mdf_body(const MdfArgs a, unsigned body) {
 #pragma clang fp contract(off)
   const CaseDev &cp = a.bodies[body];
   const int n = cp.n_markers;
   const int nm = cp.nm_cap;
   const int tid = threadIdx.x;
   const int NM = a.max_markers, CC = a.cell_cap;  // LDS table strides
-  double *lds = reinterpret_cast<double *>(sbt_ibm_lds);
+  extern __shared__ __align__(16) double lds[];
   double2 *s_dF = reinterpret_cast<double2 *>(lds);  // [NM] marker force of the iteration
   double2 *s_uv = s_dF + NM;        // [CC] corrected velocity of the cell
   double *s_wx = reinterpret_cast<double *>(s_uv + CC);  // [4][NM]
@@ -1786,19 +1778,17 @@ __device__ __forceinline__ void mdf_body(const MdfArgs &a, int body) {
   // plan loads below do not wait for the substep counter.
   const int b = a.parity;
   const PlanView P = plan_view(cp, b);
-  int64_t k;
-  int4 hdr;
-  IbmWindow win;
-  if constexpr (FRESH) {
-    k = ld_fresh(cp.kcount);
-    hdr = make_int4(ld_fresh(P.hdr), ld_fresh(P.hdr + 1), ld_fresh(P.hdr + 2), ld_fresh(P.hdr + 3));
-    const int32_t *w = reinterpret_cast<const int32_t *>(cp.win + b);
-    win = {ld_fresh(w), ld_fresh(w + 1), ld_fresh(w + 2), ld_fresh(w + 3)};
-  } else {
-    k = *cp.kcount;
-    hdr = *reinterpret_cast<const int4 *>(P.hdr);
-    win = cp.win[b];
-  }
+#ifdef SBT_PERSISTENT_TU
+  // written earlier in the same launch (the persistent step)
+  const int64_t k = ld_fresh(cp.kcount);
+  const int4 hdr = make_int4(ld_fresh(P.hdr), ld_fresh(P.hdr + 1), ld_fresh(P.hdr + 2), ld_fresh(P.hdr + 3));
+  const int32_t *wq = reinterpret_cast<const int32_t *>(cp.win + b);
+  const IbmWindow win = {ld_fresh(wq), ld_fresh(wq + 1), ld_fresh(wq + 2), ld_fresh(wq + 3)};
+#else
+  const int64_t k = *cp.kcount;
+  const int4 hdr = *reinterpret_cast<const int4 *>(P.hdr);
+  const IbmWindow win = cp.win[b];
+#endif
   // 1. load the plan before the header is known, all in one round: this
   //    lane's first stencil-cell record, the contributor lists (direct
   //    global->LDS copies, 16 bytes per lane) and the marker tables
@@ -2055,7 +2045,7 @@ __device__ __forceinline__ void mdf_body(const MdfArgs &a, int body) {
 
 #ifndef SBT_PERSISTENT_TU
 template <int ST>
-__global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) { mdf_body<ST, false>(a, blockIdx.x); }
+__global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) { mdf_body<ST>(a, blockIdx.x); }
 #endif
 
 #ifdef SBT_PERSISTENT_TU
@@ -2122,7 +2112,7 @@ __device__ __forceinline__ void level_phase(const PPhase &P) {
       const CaseDev &cp = a.cases[k.cid];
       const bool slow = (k.flags & (BF_CODES | BF_EDGE | BF_SOLID)) != 0;
       double part[3] = {0.0, 0.0, 0.0};
-      level_cell<ST, true>(a, k, cell, cp, slow, part);
+      level_cell<ST>(a, k, cell, cp, slow, part);
     } else if (i < n_work) {
       const int idx = (i - n_blk) * 256 + cell;
       if (idx < a.n_band) band_cell<ST>(a, a.band[idx]);
@@ -2138,12 +2128,12 @@ __global__ __launch_bounds__(MDF_THREADS) void step_persistent_kernel(const PPha
     const PPhase &P = ph[p];
     if (P.type == PP_PREP) {
       for (unsigned it = blockIdx.x; it < (unsigned)P.n_items; it += gridDim.x) {
-        prep_item<true>(P.ibm, it);
+        prep_item(P.ibm, it);
         __syncthreads();
       }
     } else if (P.type == PP_MDF) {
-      for (int it = blockIdx.x; it < P.n_items; it += gridDim.x) {
-        mdf_body<ST & 3, true>(P.mdf, it);
+      for (unsigned it = blockIdx.x; it < (unsigned)P.n_items; it += gridDim.x) {
+        mdf_body<ST & 3>(P.mdf, it);
         __syncthreads();
       }
     } else {
