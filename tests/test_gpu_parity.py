@@ -475,14 +475,16 @@ def test_persistent_step_matches_launch_chain(env, storage):
     """One persistent launch per step (SBT_OPT_PERSISTENT: plan builder,
     forcing loops and level substeps as phases behind grid barriers) against
     the launch chain: the 64-case batch, 4 and then 3 global steps (both
-    level-0 parities of the phase tables), and a refined patch without
-    bodies (no plan or forcing phases).  FP64 bit for bit.  In the deviation
+    level-0 parities of the phase tables), a refined patch without bodies
+    (no plan or forcing phases), and the walled cavity with solid cells in
+    MRT (solid blocks, domain edges, the MRT variant).  FP64 bit for bit.
+    In the deviation
     forms the persistent step's per-cell path rounds differently from the
     tile kernel in FP32 arithmetic (last-bit differences on refined levels
     after one step), so the 2-byte form is held to a relative L2 of velocity
     of 1e-3, well inside its 5e-3 ceiling against FP64."""
     P, _ = env
-    for wls in (W.batch_sweep(), [W.tgv_patch(m=3)]):
+    for wls in (W.batch_sweep(), [W.tgv_patch(m=3)], [W.cavity_ibb().replace(collision=W.COLL_MRT)]):
         outs = []
         for persistent in (1, 0):
             print(f"{len(wls)} cases {storage} persistent {persistent}", flush=True)
