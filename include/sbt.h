@@ -317,8 +317,11 @@ sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes);
  *   (plan builder, forcing loops and level substeps as phases separated by
  *   grid barriers, every level block through the generic per-cell path)
  *   instead of the chain of launches.  Results are the same either way; a
- *   barrier that times out makes sbt_synchronize report SBT_ERR_DEVICE. */
-enum { SBT_OPT_GRAPH = 0, SBT_OPT_TILE = 1, SBT_OPT_XCD_REMAP = 2, SBT_OPT_PERSISTENT = 3 };
+ *   barrier that times out makes sbt_synchronize report SBT_ERR_DEVICE.
+ * SBT_OPT_BARRIER_SPINS: polls a grid-barrier wait of the persistent step
+ *   makes before it gives up; 0 (default) = 2^21 (about a second).  A small
+ *   value forces the time-out path (for tests of it). */
+enum { SBT_OPT_GRAPH = 0, SBT_OPT_TILE = 1, SBT_OPT_XCD_REMAP = 2, SBT_OPT_PERSISTENT = 3, SBT_OPT_BARRIER_SPINS = 4 };
 sbt_status sbt_set_option(sbt_ctx *ctx, int32_t option, int32_t value);
 /* Pick the blocks per workgroup of each level by timing `steps` steps per
  * trial (1, 2, 3, 4, 6, 8; finest level first, one level at a time) and keep the

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsbt.so")
 F64, F32, F16S, BF16S = 0, 1, 2, 3
 STORAGE = {"f64": F64, "f32": F32, "f16s": F16S, "bf16s": BF16S}
 STORAGE_BYTES = {F64: 8, F32: 4, F16S: 2, BF16S: 2}
-OPT_GRAPH, OPT_TILE, OPT_XCD_REMAP, OPT_PERSISTENT = 0, 1, 2, 3
+OPT_GRAPH, OPT_TILE, OPT_XCD_REMAP, OPT_PERSISTENT, OPT_BARRIER_SPINS = 0, 1, 2, 3, 4
 
 ERRORS = {-1: "ARG", -2: "TOPOLOGY", -3: "DEVICE", -4: "NOMEM", -5: "STATE", -6: "NONFINITE",
           -7: "MARKER_OUTSIDE", -8: "BUFSIZE"}

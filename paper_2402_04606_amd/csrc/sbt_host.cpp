@@ -268,6 +268,10 @@ struct Phase {
 
 }  // namespace
 
+// Polls of a persistent-step grid-barrier wait before it gives up (with a
+// short sleep each, about a second).
+constexpr uint32_t kBarrierSpins = 1u << 21;
+
 struct sbt_ctx {
   int n_cases = 0, V = 1, storage = 0;
   int kvar = 0;  // level-launch variant: storage | (collision model << 2)
@@ -290,6 +294,7 @@ struct sbt_ctx {
   std::vector<int> ptab_n;
   uint32_t *d_bar = nullptr;       // grid-barrier state of the persistent step
   int p_groups = 0;                // its workgroups (0: not sized yet)
+  uint32_t p_spins = kBarrierSpins;  // polls of a grid-barrier wait before it gives up
   size_t p_lds = 0;
   std::vector<int> kpw_level;   // interior blocks per workgroup per virtual level (0: automatic)
   int lds_window = 0;           // IBM window cells whose plan-builder counters fit in LDS
@@ -1010,7 +1015,7 @@ sbt_status run_step_persistent(sbt_ctx &X, hipStream_t s) {
     X.ptab_n[slot] = (int)t.size();
     X.ptab_ready[slot] = 1;
   }
-  HIPCHK(sbt_launch_step_persistent(X.kvar, tab, X.ptab_n[slot], X.d_bar, X.d_err, X.p_groups, X.p_lds, s));
+  HIPCHK(sbt_launch_step_persistent(X.kvar, tab, X.ptab_n[slot], X.d_bar, X.d_err, X.p_spins, X.p_groups, X.p_lds, s));
   advance_host(X, 1);
   return SBT_OK;
 }
@@ -1823,6 +1828,10 @@ sbt_status sbt_set_option(sbt_ctx *ctx, int32_t option, int32_t value) {
       break;
     case SBT_OPT_XCD_REMAP: ctx->xcd = value != 0; break;
     case SBT_OPT_PERSISTENT: ctx->persistent = value != 0; break;
+    case SBT_OPT_BARRIER_SPINS:
+      if (value < 0) return fail(SBT_ERR_ARG, "barrier spins must be >= 0");
+      ctx->p_spins = value == 0 ? kBarrierSpins : (uint32_t)value;
+      break;
     default: return fail(SBT_ERR_ARG, "unknown option");
   }
   destroy_graphs(*ctx);

@@ -190,10 +190,10 @@ hipError_t sbt_launch_level_tile(int storage, const sbt::LevelArgs *a, hipStream
 // One step as a single persistent launch of `groups` 1024-lane workgroups
 // (all resident at once) over the phase table `ph` (n_ph entries, device
 // memory), phases separated by grid barriers on bar[3] (zero between
-// launches).  A barrier that waits too long raises ERR_BARRIER in err and
-// every workgroup skips the remaining phases.
+// launches).  A barrier wait of `spins` polls that does not pass raises
+// ERR_BARRIER in err and every workgroup skips the remaining phases.
 hipError_t sbt_launch_step_persistent(int storage, const sbt::PPhase *ph, int n_ph, uint32_t *bar, int32_t *err,
-                                      int groups, size_t lds_bytes, hipStream_t s);
+                                      uint32_t spins, int groups, size_t lds_bytes, hipStream_t s);
 // Resident 1024-lane workgroups per CU of the persistent step kernel with
 // lds_bytes of dynamic LDS (0 if it cannot launch).
 int sbt_step_persistent_occupancy(int storage, size_t lds_bytes);

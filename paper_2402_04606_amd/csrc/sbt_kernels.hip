@@ -2062,16 +2062,13 @@ __global__ __launch_bounds__(MDF_THREADS) void mdf_kernel(MdfArgs a) { mdf_body<
 // the plan builder and the forcing loop use all 1024 lanes as in their own
 // launches.
 
-// Spins of a barrier wait before it gives up (about a second).
-constexpr uint32_t kBarrierSpins = 1u << 21;
-
 // Grid barrier number `idx` (1, 2, ...) of the launch: bar[0] counts
 // arrivals, so it is passed when bar[0] >= idx * gridDim.x.  The release
 // makes this workgroup's writes visible at agent scope and the acquire
-// invalidates what this CU cached before.  A wait past kBarrierSpins raises
-// ERR_BARRIER and sets bar[1], which ends every other wait.  Returns false
-// when the launch is aborted.
-__device__ bool grid_barrier(uint32_t *bar, uint32_t idx, int32_t *err) {
+// invalidates what this CU cached before.  A wait of `spins` polls without
+// the barrier passing raises ERR_BARRIER and sets bar[1], which ends every
+// other wait.  Returns false when the launch is aborted.
+__device__ bool grid_barrier(uint32_t *bar, uint32_t idx, int32_t *err, uint32_t spins_max) {
   __shared__ int s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -2084,7 +2081,7 @@ __device__ bool grid_barrier(uint32_t *bar, uint32_t idx, int32_t *err) {
         ok = 0;
         break;
       }
-      if (++spins >= kBarrierSpins) {
+      if (++spins >= spins_max) {
         atomicOr(err, ERR_BARRIER);
         __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
@@ -2122,7 +2119,7 @@ __device__ __forceinline__ void level_phase(const PPhase &P) {
 
 template <int ST>
 __global__ __launch_bounds__(MDF_THREADS) void step_persistent_kernel(const PPhase *__restrict__ ph, int n_ph,
-                                                                      uint32_t *bar, int32_t *err) {
+                                                                      uint32_t *bar, int32_t *err, uint32_t spins) {
   bool ok = true;
   for (int p = 0; p < n_ph && ok; ++p) {
     const PPhase &P = ph[p];
@@ -2139,7 +2136,7 @@ __global__ __launch_bounds__(MDF_THREADS) void step_persistent_kernel(const PPha
     } else {
       level_phase<ST>(P);
     }
-    if (p + 1 < n_ph) ok = grid_barrier(bar, (uint32_t)(p + 1), err);
+    if (p + 1 < n_ph) ok = grid_barrier(bar, (uint32_t)(p + 1), err, spins);
   }
   // the last workgroup out puts the barrier state back to zero for the next
   // launch (every other workgroup has passed its last barrier)
@@ -2364,12 +2361,12 @@ extern "C" hipError_t sbt_launch_fill_nan(void *p, size_t n, int storage, hipStr
 #define SBT_PERSIST_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
 
 extern "C" hipError_t sbt_launch_step_persistent(int storage, const PPhase *ph, int n_ph, uint32_t *bar, int32_t *err,
-                                                 int groups, size_t lds_bytes, hipStream_t s) {
+                                                 uint32_t spins, int groups, size_t lds_bytes, hipStream_t s) {
   if (n_ph <= 0 || groups <= 0) return hipSuccess;
   switch (storage) {
 #define SBT_P(S)                                                                                              \
   case S:                                                                                                     \
-    hipLaunchKernelGGL((step_persistent_kernel<S>), dim3(groups), dim3(MDF_THREADS), lds_bytes, s, ph, n_ph, bar, err); \
+    hipLaunchKernelGGL((step_persistent_kernel<S>), dim3(groups), dim3(MDF_THREADS), lds_bytes, s, ph, n_ph, bar, err, spins); \
     break;
     SBT_PERSIST_CASES(SBT_P)
 #undef SBT_P

@@ -516,6 +516,36 @@ def test_persistent_step_matches_launch_chain(env, storage):
         assert e <= 1e-3
 
 
+def test_persistent_barrier_time_out_is_reported(env):
+    """A grid barrier of the persistent step that gives up (forced from the
+    host: one poll per wait) ends the launch normally and makes synchronize
+    report SBT_ERR_DEVICE; the launch's last workgroup resets the barrier
+    state, so after re-initialising, the same context steps exactly like a
+    fresh one."""
+    P, _ = env
+    wl = W.small_refined_flap()
+    g = P.Sim(wl, "f64")
+    g.set_option(P.OPT_PERSISTENT, 1)
+    g.step(1)
+    g.synchronize()
+    g.set_option(P.OPT_BARRIER_SPINS, 1)
+    g.step(1)
+    with pytest.raises(P.SbtError) as e:
+        g.synchronize()
+    assert e.value.code == -3
+    g.set_option(P.OPT_BARRIER_SPINS, 0)
+    ref = P.Sim(wl, "f64")
+    ref.set_option(P.OPT_PERSISTENT, 1)
+    for s in (g, ref):
+        s.init_uniform(0, 1.0, 0.05, 0.0)
+        s.step(3)
+        s.synchronize()
+    for l in range(wl.n_levels):
+        for a, b in zip(g.fields(0, l), ref.fields(0, l)):
+            assert np.array_equal(a, b, equal_nan=True), l
+    assert np.array_equal(g.force_history()[0], ref.force_history()[0])
+
+
 def test_checkpoint_resume_bitwise(env):
     P, _ = env
     wl = W.small_refined_flap()
