@@ -230,12 +230,16 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body);
  * SBT_BODY_HOST, every forcing loop that the following sbt_step calls run
  * uses positions x, y (finest-level cells) and desired velocities udx, udy
  * (finest-level lattice units), n = the body's marker count, until the next
- * call.  A step collides one finest substep ahead of what the readouts
- * show: after the readouts show finest substep s, the next forcing loop is
- * that of substep s + 1 (the first sbt_step runs substeps 0 and 1).  Host
- * arrays, copied in; waits for the context's stream. */
+ * call; ds (may be NULL: keep the current values) replaces the markers'
+ * arc-length weights ds_j of Eqs. (15)-(16) as well.  A step collides one
+ * finest substep ahead of what the readouts show: after the readouts show
+ * finest substep s, the next forcing loop is that of substep s + 1 (the
+ * first sbt_step runs substeps 0 and 1).  Host arrays, copied in; waits for
+ * the context's stream.  Errors: SBT_ERR_ARG (not a HOST body, n differs
+ * from the body's marker count, null positions or velocities, ds not
+ * positive and finite). */
 sbt_status sbt_set_markers(sbt_ctx *ctx, int32_t c, int32_t n, const double *x, const double *y,
-                           const double *udx, const double *udy);
+                           const double *udx, const double *udy, const double *ds);
 
 /* Advance every case by n virtual-level-0 steps (Algorithm 1, each level
  * sub-cycled 2^l times).  Asynchronous, stream-ordered. */

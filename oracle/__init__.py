@@ -70,7 +70,7 @@ def _configure(L):
     L.orc_read_fields.argtypes = [C.c_void_p, C.c_int, d, d, d]
     L.orc_read_populations.argtypes = [C.c_void_p, C.c_int, d]
     L.orc_marker_forces.argtypes = [C.c_void_p, d, d]
-    L.orc_set_markers.argtypes = [C.c_void_p, C.c_int32, d, d, d, d]
+    L.orc_set_markers.argtypes = [C.c_void_p, C.c_int32, d, d, d, d, d]
     L.orc_force_history.argtypes = [C.c_void_p, C.c_int32, d, d, C.POINTER(C.c_int32)]
     L.orc_diagnostics.argtypes = [C.c_void_p, d]
     L.orc_substeps.argtypes = [C.c_void_p]
@@ -251,10 +251,13 @@ class OracleSim:
         self._L.orc_marker_forces(self._h, _dp(fx), _dp(fy))
         return fx[:n], fy[:n]
 
-    def set_markers(self, X, Y, udx, udy):
-        """Caller-placed markers (body kind HOST) for the next steps."""
+    def set_markers(self, X, Y, udx, udy, ds=None):
+        """Caller-placed markers (body kind HOST) for the next steps; ds
+        (optional) replaces their arc-length weights."""
         X, Y, udx, udy = (_f64(a) for a in (X, Y, udx, udy))
-        rc = self._L.orc_set_markers(self._h, len(X), _dp(X), _dp(Y), _dp(udx), _dp(udy))
+        w = None if ds is None else _f64(ds)
+        rc = self._L.orc_set_markers(self._h, len(X), _dp(X), _dp(Y), _dp(udx), _dp(udy),
+                                     None if w is None else _dp(w))
         if rc:
             raise RuntimeError(f"orc_set_markers failed: {rc}")
 

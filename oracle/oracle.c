@@ -1077,13 +1077,14 @@ int orc_marker_forces(const orc_sim *s, double *fx, double *fy) {
 }
 
 int orc_set_markers(orc_sim *s, int32_t n, const double *X, const double *Y, const double *udx,
-                    const double *udy) {
+                    const double *udy, const double *ds) {
     if (s->c.body_kind != ORC_BODY_HOST || n != s->c.n_markers) return ORC_ERR_ARG;
     for (int j = 0; j < n; ++j) {
         s->xb[j] = X[j];
         s->yb[j] = Y[j];
         s->hud[j] = udx[j];
         s->hud[n + j] = udy[j];
+        if (ds) s->ds[j] = ds[j];
     }
     return ORC_OK;
 }

@@ -79,9 +79,10 @@ int  orc_read_populations(const orc_sim *s, int level, double *f);
 int  orc_marker_forces(const orc_sim *s, double *fx, double *fy);
 /* ORC_BODY_HOST: marker positions X, Y (finest cells) and desired velocities
  * used by every finest substep from the next orc_step on (Sec. 2.2 takes
- * both as given). */
+ * both as given); ds (NULL: unchanged) replaces the markers' arc-length
+ * weights. */
 int  orc_set_markers(orc_sim *s, int32_t n, const double *X, const double *Y, const double *udx,
-                     const double *udy);
+                     const double *udy, const double *ds);
 int  orc_force_history(const orc_sim *s, int32_t cap, double *fx, double *fy, int32_t *n_out);
 /* out = {mass, momentum x, momentum y}, each summed over owned cells with
  * volume weight 4^-l; momentum is the bare first moment sum_i c_i f_i. */

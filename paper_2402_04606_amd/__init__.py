@@ -112,7 +112,7 @@ def lib():
             "sbt_init_uniform": [vp, i32, C.c_double, C.c_double, C.c_double],
             "sbt_read_fields_blocks": [vp, i32, i32, d],
             "sbt_set_body": [vp, i32, C.POINTER(Body)],
-            "sbt_set_markers": [vp, i32, i32, d, d, d, d],
+            "sbt_set_markers": [vp, i32, i32, d, d, d, d, d],
             "sbt_step": [vp, i32],
             "sbt_synchronize": [vp],
             "sbt_read_fields": [vp, i32, i32, d, d, d],
@@ -327,11 +327,14 @@ class Sim:
             b.p[k] = v
         _check(lib().sbt_set_body(self._h, c, C.byref(b)))
 
-    def set_markers(self, c, x, y, udx, udy):
-        """Caller-placed markers (body kind HOST): positions and desired
-        velocities for every finest substep from the next step on."""
+    def set_markers(self, c, x, y, udx, udy, ds=None):
+        """Caller-placed markers (body kind HOST): positions, desired
+        velocities and (optionally) arc-length weights for every finest
+        substep from the next step on."""
         x, y, udx, udy = (np.ascontiguousarray(a, dtype=np.float64) for a in (x, y, udx, udy))
-        _check(lib().sbt_set_markers(self._h, c, len(x), _dp(x), _dp(y), _dp(udx), _dp(udy)))
+        w = None if ds is None else np.ascontiguousarray(ds, dtype=np.float64)
+        _check(lib().sbt_set_markers(self._h, c, len(x), _dp(x), _dp(y), _dp(udx), _dp(udy),
+                                     None if w is None else _dp(w)))
 
     def step(self, n=1):
         _check(lib().sbt_step(self._h, int(n)))

@@ -1465,7 +1465,7 @@ sbt_status sbt_set_body(sbt_ctx *ctx, int32_t c, const sbt_body *body) {
 }
 
 sbt_status sbt_set_markers(sbt_ctx *ctx, int32_t c, int32_t n, const double *x, const double *y,
-                           const double *udx, const double *udy) {
+                           const double *udx, const double *udy, const double *ds) {
   sbt_status st = check_case(ctx, c);
   if (st) return st;
   sbt_ctx &X = *ctx;
@@ -1473,8 +1473,12 @@ sbt_status sbt_set_markers(sbt_ctx *ctx, int32_t c, int32_t n, const double *x, 
   if (!C.has_body || C.dev.body_kind != SBT_BODY_HOST) return fail(SBT_ERR_ARG, "case has no caller-placed body");
   if (n != C.n_markers) return fail(SBT_ERR_ARG, "marker count differs from the body's");
   if (!x || !y || !udx || !udy) return fail(SBT_ERR_ARG, "null marker arrays");
+  if (ds)
+    for (int j = 0; j < n; ++j)
+      if (!(ds[j] > 0.0 && std::isfinite(ds[j]))) return fail(SBT_ERR_ARG, "ds must be positive and finite");
   HIPCHK(hipStreamSynchronize(X.stream));
   const size_t N = (size_t)n, nm = (size_t)C.d.max_markers;
+  if (ds) HIPCHK(hipMemcpy((void *)C.dev.ds, ds, sizeof(double) * N, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy((void *)C.dev.xb, x, sizeof(double) * N, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy((void *)C.dev.yb, y, sizeof(double) * N, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(C.dev.hud, udx, sizeof(double) * N, hipMemcpyHostToDevice));

@@ -752,13 +752,15 @@ def test_pitch_up_plate_first_lift_peak(env):
     assert cl[-1] > 0.6 * cl[i]
 
 
-def test_host_markers_match_oracle(env):
+@pytest.mark.parametrize("vary_ds", [False, True])
+def test_host_markers_match_oracle(env, vary_ds):
     """sbt_set_markers on the graph path against the oracle's caller-placed
     body: the markers of a flapping motion (positions r(t_k), desired
-    velocity r(t_k+1) - r(t_k)) are set before every step.  The GPU's step n
-    runs the forcing loop of substep n (it collides one substep ahead; step
-    1 also runs substep 0), so the oracle is fed substep 0 with the markers
-    of substep 1 and substep k >= 1 with those of k; both must agree bit for
+    velocity r(t_k+1) - r(t_k), and with vary_ds arc-length weights that
+    change every step) are set before every step.  The GPU's step n runs the
+    forcing loop of substep n (it collides one substep ahead; step 1 also
+    runs substep 0), so the oracle is fed substep 0 with the markers of
+    substep 1 and substep k >= 1 with those of k; both must agree bit for
     bit."""
     P, O = env
     U, chord = 0.05, 24.0
@@ -770,10 +772,11 @@ def test_host_markers_match_oracle(env):
     def markers(k):
         X, Y = O.body_positions(wl, k)
         X1, Y1 = O.body_positions(wl, k + 1)
-        return X, Y, X1 - X, Y1 - Y
+        w = np.asarray(ds) * (1.0 + 0.05 * np.sin(0.7 * k)) if vary_ds else None
+        return X, Y, X1 - X, Y1 - Y, w
 
     n = 40
-    X0, Y0, _, _ = markers(0)
+    X0, Y0 = markers(0)[:2]
     host = wl.replace(body=W.Body(W.BODY_HOST, X0, Y0, ds, [0.0] * 16))
     o = O.OracleSim(host)
     for k in range(n):

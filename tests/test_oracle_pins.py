@@ -763,6 +763,31 @@ def test_host_markers_reproduce_prescribed_motion(orc):
     assert np.array_equal(ref.force_history()[0], h.force_history()[0])
 
 
+def test_host_markers_replace_arc_lengths(orc):
+    """The arc-length weights ds_j of Eqs. (15)-(16) given with the markers
+    replace the body's: a HOST body created with twice the weights and fed
+    the prescribed body's positions and weights every step reproduces the
+    prescribed run bit for bit (and a run that keeps the doubled weights
+    does not)."""
+    wl = _flap_single_level()
+    ref = orc.OracleSim(wl)
+    ref.step(20)
+    b = wl.body
+    runs = []
+    for give_ds in (True, False):
+        host = wl.replace(body=W.Body(W.BODY_HOST, np.zeros(len(b.xb)), np.zeros(len(b.xb)), 2.0 * np.asarray(b.ds),
+                                      [0.0] * 16))
+        h = orc.OracleSim(host)
+        for k in range(20):
+            X, Y = orc.body_positions(wl, k)
+            X1, Y1 = orc.body_positions(wl, k + 1)
+            h.set_markers(X, Y, X1 - X, Y1 - Y, b.ds if give_ds else None)
+            h.step(1)
+        runs.append(h.force_history()[0])
+    assert np.array_equal(ref.force_history()[0], runs[0])
+    assert not np.allclose(ref.force_history()[0], runs[1], rtol=1e-3)
+
+
 # ---- three dimensions: D3Q19 ---------------------------------------------------
 
 @pytest.mark.parametrize("q", [19, 27])
