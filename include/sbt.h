@@ -320,8 +320,13 @@ sbt_status sbt_write_state(sbt_ctx *ctx, const void *host, size_t bytes);
  * SBT_OPT_PERSISTENT (default 0): run each step as one persistent launch
  *   (plan builder, forcing loops and level substeps as phases separated by
  *   grid barriers, every level block through the generic per-cell path)
- *   instead of the chain of launches.  Results are the same either way; a
- *   barrier that times out makes sbt_synchronize report SBT_ERR_DEVICE.
+ *   instead of the chain of launches.  FP64 results are the same bit for
+ *   bit; the deviation forms may differ in the last bits (the per-cell path
+ *   rounds some FP32 sums differently).  A barrier that times out makes
+ *   sbt_synchronize report SBT_ERR_DEVICE.  The
+ *   launch sizes its grid to fill every CU, so kernels of other streams
+ *   running at the same time can keep a workgroup from starting and make a
+ *   barrier time out.
  * SBT_OPT_BARRIER_SPINS: polls a grid-barrier wait of the persistent step
  *   makes before it gives up; 0 (default) = 2^21 (about a second).  A small
  *   value forces the time-out path (for tests of it). */
