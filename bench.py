@@ -376,6 +376,8 @@ def main():
     ap.add_argument("--tile", type=int, default=None)
     ap.add_argument("--persistent", action="store_true",
                     help="time the one-launch-per-step form (SBT_OPT_PERSISTENT) instead of the launch chain")
+    ap.add_argument("--no-persistent-form", dest="persistent_form", action="store_false",
+                    help="do not also time the one-launch-per-step form beside the launch chain")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="automatic blocks per workgroup instead of the autotuner's choice")
     ap.add_argument("--collision", default="bgk", choices=["bgk", "mrt"],
@@ -495,6 +497,13 @@ def main():
             "mlups": round(ups * args.steps / dt3 / 1e6, 1), "ms_per_step": round(dt3 * 1e3 / args.steps, 3),
             "tile_gbs": round(p3["fast_bytes"] / (p3["fast_ms"] * 1e-3) / 1e9, 1) if p3["fast_ms"] > 0 else 0.0}
         del s3
+
+    # ---- the same step as one persistent launch (SBT_OPT_PERSISTENT) -----------
+    if not args.persistent and args.persistent_form:
+        s4, dt4, _ = time_form(P, wls, args.storage, args.steps, args.warmup, args.tile, args.autotune, True)
+        forms["persistent_" + args.storage] = {"mlups": round(ups * args.steps / dt4 / 1e6, 1),
+                                               "ms_per_step": round(dt4 * 1e3 / args.steps, 3)}
+        del s4
 
     out = {
         "metric": "MLUPS & HBM GB/s fraction; FP16/FP32-storage vs FP64 at stated L2 error",
